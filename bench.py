@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path: full SSP-RK3 time steps (ghost fill, time step,
+three residual + stage updates, norms) on one MI355X.
+
+Default workload: compressible Navier-Stokes over a wall bump, one
+curvilinear block of 256 x 128 x 128 cells, FP64, seeded noise (synthetic
+inputs).  Prints one JSON line with the cell-stage update rate, the stage
+kernel's roofline figures and the CPU oracle's rate on a bounded sample.
+
+Timing: W untimed warm-up steps, then exactly K steps bracketed by device
+synchronisation and HIP events on the solver's stream (graph replay, the
+production path).  A second pass of K steps with the library's kernel
+profiling on (eager launches, a hipEvent pair around every stage-kernel
+launch on its stream) gives the stage kernel's mean duration for the
+roofline entry.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK = 78.6   # TFLOP/s
+
+
+def stage_bytes_per_cell(local_dt: bool) -> float:
+    """Algorithmic HBM bytes per interior cell per stage-kernel launch, averaged
+    over the three stages: stencil state 40 B (read once), metrics 80 B
+    (S_i, S_j, S_k, V), write 40 B; stages 2-3 also read Q^n pointwise (40 B);
+    local time stepping reads one more double per cell."""
+    s1 = 40 + 80 + 40
+    s23 = s1 + 40
+    extra = 8 if local_dt else 0
+    return (s1 + 2 * s23) / 3.0 + extra
+
+
+def make_case(name: str, flux: str):
+    from paper_1710_09995_amd import cases
+    fp32 = 1 if flux == "fp32" else 0
+    if name == "bump_ns":
+        c = cases.bump_ns_case(256, 128, 128, seed=0)
+        label = "bump_ns_256x128x128"
+    elif name == "vortex":
+        c = cases.vortex_case(32, seed=0)
+        label = "euler_vortex_32^3"
+    elif name == "batched":
+        c = cases.batched_euler_case(64, seed=0)
+        label = "batched_euler_64blk"
+    elif name == "paper_share":
+        c = cases.paper_share_case(seed=0)
+        label = "ns_16x512x512x144"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return c.with_params(flux_fp32=fp32), label
+
+
+def cpu_baseline(name: str, flux: str, budget_s: float = 12.0):
+    """The oracle as it stands, on a bounded sample of the same workload."""
+    import numpy as np  # noqa: F401
+    from oracle import solver as osol
+    from paper_1710_09995_amd import cases
+    if name in ("bump_ns", "paper_share"):
+        c = cases.bump_ns_case(64, 32, 32, seed=0)
+        sample = "bump_ns 64x32x32 sub-block (same flow, grid family and BCs), FP64 oracle RK3 steps"
+    elif name == "vortex":
+        c = cases.vortex_case(32, seed=0)
+        sample = "euler vortex 32^3, FP64 oracle RK3 steps"
+    else:
+        c = cases.batched_euler_case(8, seed=0, lo=16, hi=40, flux_fp32=0)
+        sample = "batched euler 8 blocks dims in [16,40), FP64 oracle RK3 steps"
+    st = osol.setup(c)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        osol.step(st)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    rate = c.ncells * 3 * n / dt / 1e6
+    return {"value": rate, "unit": "Mcell-stage/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}; {n} steps of {c.ncells} cells in {dt:.1f} s, single-threaded NumPy"}
+
+
+def read_traffic(kernel_label: str):
+    """HBM bytes per stage launch from a committed rocprofv3 --pmc summary,
+    valid only while the stage-kernel sources are unchanged."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_label}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha") != source_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels_stage.hip", "physics.hpp", "cfd_internal.hpp"):
+        p = os.path.join(ROOT, "paper_1710_09995_amd", "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="bump_ns", choices=["bump_ns", "vortex", "batched", "paper_share"])
+    ap.add_argument("--flux", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--kernel", type=int, default=None)
+    ap.add_argument("--tile-j", type=int, default=None)
+    ap.add_argument("--tile-k", type=int, default=None)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-profile-pass", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(sharding across GPUs is a design note, not code); use --gpus 1.", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1710_09995_amd.binding import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    case, label = make_case(a.workload, a.flux)
+    print(f"# workload {label}: {case.nblk} blocks, {case.ncells} cells, flux {a.flux}", file=sys.stderr,
+          flush=True)
+    s = Solver(case, device="cuda:0")
+    tun = {}
+    if a.kernel is not None:
+        tun["kernel"] = a.kernel
+    if a.tile_j is not None:
+        tun["tile_j"] = a.tile_j
+    if a.tile_k is not None:
+        tun["tile_k"] = a.tile_k
+    if a.no_graph:
+        tun["use_graph"] = 0
+    if tun:
+        s.set_tuning(**tun)
+    stream = torch.cuda.current_stream()
+    s.step(a.warmup, hist=False)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(a.steps, hist=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    print(f"# timed {a.steps} steps: {ms:.2f} ms", file=sys.stderr, flush=True)
+    cell_stages = case.ncells * 3 * a.steps
+    value = cell_stages / (ms / 1e3) / 1e6
+    h = s.step(1, hist=True).cpu().numpy()[0]
+    finite = bool(all(math.isfinite(x) for x in h))
+
+    roofline = None
+    prof = None
+    if not a.no_profile_pass:
+        s.set_profiling(True)
+        s.step(a.steps, hist=False)
+        torch.cuda.synchronize()
+        prof = s.profile_read()
+        s.set_profiling(False)
+        st = prof["stage"]
+        bpc = stage_bytes_per_cell(bool(case.params.local_dt))
+        per_launch = bpc * case.ncells
+        achieved = per_launch / (st["mean_ms"] / 1e3) / 1e9
+        kernel_label = f"stage_{label}_{a.flux}"
+        traffic = read_traffic(kernel_label)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "kernel": "k_stage (residual + RK stage update)",
+                    "mean_launch_ms": round(st["mean_ms"], 4), "launches": st["launches"],
+                    "algorithmic_bytes_per_cell": round(bpc, 2), "cells_per_launch": case.ncells}
+        print(f"# profile: {json.dumps(prof)}", file=sys.stderr, flush=True)
+    tune = s.get_tuning()
+    s.close()
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(a.workload, a.flux, a.cpu_budget)
+
+    out = {
+        "metric": "Mcell-stage updates/s + % HBM peak; wall-clock to 1e-8 residual drop",
+        "value": round(value, 2),
+        "unit": "Mcell-stage/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms / a.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if a.flux == "fp64" else "f32-flux/f64-state",
+        "data": "synthetic (seeded grid, state and noise)",
+        "config": {"workload": label, "blocks": case.nblk, "cells": case.ncells,
+                   "viscous": bool(case.params.viscous), "flux": a.flux, "stages_per_step": 3,
+                   "tuning": tune, "finite": finite},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if prof is not None:
+        out["kernel_ms"] = {k: {"mean": round(v["mean_ms"], 4), "launches": v["launches"]} for k, v in prof.items()}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

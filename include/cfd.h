@@ -1,0 +1,192 @@
+/*
+ * cfd.h -- C ABI of libcfd: the per-cell residual, third-order Runge-Kutta
+ * update and block-to-block ghost fill of a 3-D multi-block structured-grid
+ * compressible flow solver, on one MI355X (gfx950).
+ *
+ * The operation (Wang et al., "Performance optimizations for scalable CFD
+ * applications on hybrid CPU+MIC heterogeneous computing system with millions
+ * of cores", Computers & Fluids):
+ *   - Section 2.1, Eq. (1): Navier-Stokes equations in curvilinear coordinates,
+ *     Q = (rho, rho u, rho v, rho w, rho E);
+ *   - Section 2.2, Eq. (3): semi-discrete form dQ/dt = -R(Q);
+ *   - Section 2.2, Eqs. (4)-(6): third-order Runge-Kutta with lambda = -dt;
+ *   - Sections 2.3 and 3.2.3: multi-block domains whose neighbouring blocks
+ *     exchange boundary data after every update.
+ * The paper leaves the spatial operator's details open; this library uses a
+ * cell-centred finite-volume residual: kappa = 1/3 MUSCL reconstruction of
+ * primitive variables with a smooth van Albada-type limiter, Roe's flux with
+ * Harten's entropy fix, and face-gradient viscous fluxes (Sutherland's law,
+ * constant Prandtl number) on face-area-vector metrics.
+ *
+ * Conventions
+ *   - All device pointers are HIP device memory owned by the caller.  The
+ *     library allocates no device memory: everything it needs lives in the
+ *     caller's workspace buffer, which must outlive the context.
+ *   - All calls are asynchronous on the given stream unless stated.
+ *   - Every call returns a cfd_status; no C++ exception crosses the ABI.
+ *     After a failure, cfd_last_error() describes it.
+ *   - A context is not thread-safe; calls that use one context on one
+ *     stream are ordered by that stream.
+ *   - Directions 0,1,2 = i,j,k; faces 0..5 = -i,+i,-j,+j,-k,+k.  Patch
+ *     ranges on a face are half-open cell ranges in the two transverse
+ *     directions in ascending order (i-face: j,k; j-face: i,k; k-face: i,j).
+ *   - State layout ("arena"): per block, FP64 structure-of-arrays
+ *     [var 0..4][k][j][i] including g ghost layers on every side, i fastest,
+ *     rows padded to 16 doubles, interior i = 0 aligned to 128 bytes.
+ *     cfd_layout() gives each block's offset and strides.
+ */
+#ifndef CFD_H
+#define CFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CFD_OK = 0,
+  CFD_EINVAL = -1,        /* bad argument, table or size                        */
+  CFD_ENOMEM = -2,        /* workspace smaller than cfd_workspace_size()        */
+  CFD_EHIP = -3,          /* a HIP runtime call failed                          */
+  CFD_ENONFINITE = -4,    /* NaN or Inf found in the state or residual          */
+  CFD_ESTATE = -5,        /* call not valid in the context's current state      */
+  CFD_EUNSUPPORTED = -6,  /* option not supported                               */
+  CFD_EINTERNAL = -7
+} cfd_status;
+
+typedef struct cfd_ctx cfd_ctx;
+
+typedef struct { int32_t ni, nj, nk; } cfd_dims;   /* interior cells, each >= ghost_layers */
+
+/* One-to-one block connection, identity orientation.  Fills the ghost cells
+ * of `face` of `blk` over the patch [lo, hi) from the cells of `nbr` just
+ * inside `nbr_face`, which must be the opposite face of the same direction.
+ * Transverse index p maps to p - lo + nbr_lo on the neighbour.  `shift` is
+ * added to the neighbour's node coordinates (periodic translation).  Each
+ * side of a seam is listed separately.  (Sections 2.3, 3.2.3.) */
+typedef struct {
+  int32_t blk, face, nbr, nbr_face;
+  int32_t lo[2], hi[2], nbr_lo[2];
+  double shift[3];
+} cfd_conn;
+
+/* Physical boundary patch (the paper specifies none; these are the
+ * library's): far field by Riemann invariants, slip wall, no-slip adiabatic
+ * wall, zeroth-order extrapolation. */
+typedef enum { CFD_BC_FARFIELD = 1, CFD_BC_SLIPWALL = 2, CFD_BC_NOSLIP_ADIABATIC = 3,
+               CFD_BC_EXTRAP = 4 } cfd_bc_kind;
+typedef struct { int32_t blk, face, kind; int32_t lo[2], hi[2]; } cfd_bc;
+
+/* Non-dimensional flow parameters: rho_inf = p_inf = 1, T = p/rho,
+ * |u_inf| = mach*sqrt(gamma) along (cos a cos b, sin a cos b, sin b),
+ * mu_inf = |u_inf| / reynolds (unit length), Sutherland constant S* = T_s/T_inf.
+ * cfl: Courant number of the time step; entropy_fix: Harten delta factor;
+ * limiter_eps: limiter regulariser.  viscous: 0 Euler, 1 Navier-Stokes.
+ * flux_fp32: 1 evaluates reconstruction and face fluxes in FP32 (state,
+ * metrics, flux sums, update and norms stay FP64).  local_dt: 1 uses the
+ * per-cell time step (steady problems).  ghost_layers must be 2. */
+typedef struct {
+  double gamma, prandtl, mach, alpha, beta, reynolds, sutherland, cfl, entropy_fix, limiter_eps;
+  int32_t viscous, flux_fp32, local_dt, ghost_layers;
+} cfd_params;
+
+/* Tuning knobs of the stage kernels.  Any value changes speed only, never
+ * results (results are bitwise identical across all valid settings).
+ * kernel: 0 = tiled face-once kernel (default), 1 = simple per-cell kernel.
+ * tile_j, tile_k: tile extent in j and k (tile_i is 64, one wavefront).
+ * use_graph: 1 captures one time step in a hipGraph and replays it. */
+typedef struct { int32_t kernel, tile_j, tile_k, use_graph; } cfd_tuning;
+
+/* Arena layout for `nblk` blocks: block_offset[b] = element index of padded
+ * cell (i,j,k) = (-g,-g,-g), var 0; block_strides[4*b + 0..3] = element
+ * strides of (var, k, j, i).  arena_elems = doubles in one state arena.
+ * Output arrays may be NULL.  Host-only, synchronous. */
+cfd_status cfd_layout(int32_t nblk, const cfd_dims* dims, int32_t ghost_layers,
+                      int64_t* block_offset, int64_t* block_strides, int64_t* arena_elems);
+
+/* Bytes of device workspace cfd_create_blocks needs (metrics, two stage
+ * arenas, tables, reduction partials).  Host-only, synchronous. */
+cfd_status cfd_workspace_size(const cfd_params* params, int32_t nblk, const cfd_dims* dims,
+                              size_t* workspace_bytes);
+
+/* Build a context: validate the tables (every boundary cell face covered
+ * exactly once, ranges in bounds, connected extents match), fill ghost
+ * nodes, compute face vectors and volumes (metrics) into the workspace and
+ * build the tile list.  nodes_dev[b] points to block b's node coordinates,
+ * FP64 [3][nk+1][nj+1][ni+1], device memory; they may be freed on return.
+ * Synchronises `stream` before returning.  On error *out is NULL. */
+cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_dims* dims,
+                             const double* const* nodes_dev, int32_t nconn, const cfd_conn* conns,
+                             int32_t nbc, const cfd_bc* bcs, void* workspace_dev,
+                             size_t workspace_bytes, hipStream_t stream, cfd_ctx** out);
+
+cfd_status cfd_destroy(cfd_ctx* ctx);
+
+/* Replace the tuning knobs (default {0, 4, 16, 1}).  Drops cached graphs. */
+cfd_status cfd_set_tuning(cfd_ctx* ctx, const cfd_tuning* tuning);
+cfd_status cfd_get_tuning(const cfd_ctx* ctx, cfd_tuning* tuning);
+
+/* Fill the ghost cells of every block of q_arena_dev (three sweeps i, j, k;
+ * connections copy bitwise, physical patches apply their condition).
+ * Interior cells are not modified. */
+cfd_status cfd_fill_ghosts(cfd_ctx* ctx, double* q_arena_dev, hipStream_t stream);
+
+/* R(Q) = (1/V) sum over the cell's faces of (F_inv - F_vis) . S_out for all
+ * interior cells (Eq. 3 with dQ/dt = -R).  Reads the ghost cells of
+ * q_arena_dev as they are: call cfd_fill_ghosts first.  r_arena_dev has the
+ * state layout; its ghost and padding entries are not written. */
+cfd_status cfd_residual(cfd_ctx* ctx, const double* q_arena_dev, double* r_arena_dev,
+                        hipStream_t stream);
+
+/* Advance q_arena_dev by nsteps third-order Runge-Kutta steps (Eqs. 4-6,
+ * lambda = -dt) with a ghost fill before every stage and the CFL time step
+ * recomputed from Q^n at every step.  Ghost cells of q_arena_dev are
+ * overwritten.  hist_dev (device, nullable) receives one row of 12 doubles
+ * per step, all about the state at the start of that step:
+ *   [dt, L2(R) x5, sum V Q x5, max|R_rho|],  L2(R_c) = sqrt(sum R_c^2 / N).
+ * With local_dt, dt is the minimum of the per-cell steps. */
+cfd_status cfd_step(cfd_ctx* ctx, double* q_arena_dev, int32_t nsteps, double* hist_dev,
+                    hipStream_t stream);
+
+/* Norms: out[0..4] = L2 of r (0 if r_arena_dev is NULL), out[5..9] = sum V q,
+ * out[10] = max |r_rho|, out[11] = count of non-finite values in q and r.
+ * Deterministic fixed-order reductions.  flags & CFD_NORMS_HOST: `out` is
+ * host memory and the call synchronises `stream`; then CFD_ENONFINITE is
+ * returned if out[11] > 0.  Otherwise `out` is device memory. */
+#define CFD_NORMS_HOST 1
+cfd_status cfd_norms(cfd_ctx* ctx, const double* q_arena_dev, const double* r_arena_dev,
+                     double* out, int32_t flags, hipStream_t stream);
+
+/* Global (minimum) time step of q_arena_dev written to dt_dev (device, one
+ * double); with local_dt, the per-cell steps are also kept in the workspace. */
+cfd_status cfd_time_step(cfd_ctx* ctx, const double* q_arena_dev, double* dt_dev,
+                         hipStream_t stream);
+
+/* Kernel timing.  With profiling on, cfd_step runs without its graph and
+ * records a hipEvent pair around every launch of the residual/stage kernel,
+ * the ghost-fill sweeps and the time-step kernel, on the stream they run on.
+ * cfd_profile_read synchronises those events and writes, per kernel class
+ * (0 = stage, 1 = ghost-fill sweep, 2 = time step):
+ *   out[4*c + 0] = launches, [4*c + 1] = total ms, [+2] = min ms, [+3] = max ms,
+ * then clears the record.  Turning profiling off also clears it. */
+cfd_status cfd_set_profiling(cfd_ctx* ctx, int32_t enable);
+cfd_status cfd_profile_read(cfd_ctx* ctx, double out[12]);
+
+/* Copy block blk's metrics to out_dev (device) as a dense FP64 array
+ * [10][nk+2g][nj+2g][ni+2g]: components 0-2 = S_i, 3-5 = S_j, 6-8 = S_k (the
+ * area vectors of the cell's lower i, j, k faces, pointing towards increasing
+ * index), 9 = V, ghost cells included.  S_d = 1/2 (x[+t1+t2] - x[0]) x
+ * (x[+t2] - x[+t1]) with (t1, t2) cyclic after d; V by the divergence theorem
+ * (the geometric conservation requirement of Section 2.2). */
+cfd_status cfd_copy_metrics(cfd_ctx* ctx, int32_t blk, double* out_dev, hipStream_t stream);
+
+const char* cfd_status_string(cfd_status s);
+const char* cfd_last_error(const cfd_ctx* ctx);   /* ctx may be NULL: last global error */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFD_H */

@@ -194,13 +194,19 @@ def upper_face_vectors(X):
 
 
 def volumes(X):
-    """Cell volumes by the divergence theorem over the 6 faces."""
+    """Cell volumes by the divergence theorem over the 6 faces.
+
+    Face centres are measured from each cell's lowest node: the closed-surface
+    formula does not depend on the origin, and a local one keeps the sum free
+    of cancellation when coordinates are large compared with the cell.
+    """
     S = face_vectors(X)
     C = face_centres(X)
     Su, Cu = upper_face_vectors(X)
+    x0 = _node(X, (0, 0, 0))
     acc = np.zeros(S.shape[2:])
     for d in range(3):
-        acc = acc + np.sum(Cu[d] * Su[d], axis=0) - np.sum(C[d] * S[d], axis=0)
+        acc = acc + np.sum((Cu[d] - x0) * Su[d], axis=0) - np.sum((C[d] - x0) * S[d], axis=0)
     return acc / 3.0
 
 

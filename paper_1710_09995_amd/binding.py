@@ -1,0 +1,316 @@
+"""ctypes binding over libcfd.so (include/cfd.h).
+
+Argument marshalling only: torch owns every device buffer (state arena,
+workspace, node upload, residual, history) and supplies the HIP stream; every
+step of the computation runs in the library's HIP kernels.  There is no CPU
+fallback: if the shared library cannot be loaded the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libcfd.so")
+NG = 2
+
+CFD_OK = 0
+STATUS = {0: "CFD_OK", -1: "CFD_EINVAL", -2: "CFD_ENOMEM", -3: "CFD_EHIP", -4: "CFD_ENONFINITE",
+          -5: "CFD_ESTATE", -6: "CFD_EUNSUPPORTED", -7: "CFD_EINTERNAL"}
+CFD_NORMS_HOST = 1
+
+
+class Dims(C.Structure):
+    _fields_ = [("ni", C.c_int32), ("nj", C.c_int32), ("nk", C.c_int32)]
+
+
+class ConnS(C.Structure):
+    _fields_ = [("blk", C.c_int32), ("face", C.c_int32), ("nbr", C.c_int32), ("nbr_face", C.c_int32),
+                ("lo", C.c_int32 * 2), ("hi", C.c_int32 * 2), ("nbr_lo", C.c_int32 * 2),
+                ("shift", C.c_double * 3)]
+
+
+class BCS(C.Structure):
+    _fields_ = [("blk", C.c_int32), ("face", C.c_int32), ("kind", C.c_int32),
+                ("lo", C.c_int32 * 2), ("hi", C.c_int32 * 2)]
+
+
+class ParamsS(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("gamma", "prandtl", "mach", "alpha", "beta", "reynolds",
+                                           "sutherland", "cfl", "entropy_fix", "limiter_eps")] + \
+               [(n, C.c_int32) for n in ("viscous", "flux_fp32", "local_dt", "ghost_layers")]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("tile_j", C.c_int32), ("tile_k", C.c_int32),
+                ("use_graph", C.c_int32)]
+
+
+EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy", "cfd_set_tuning",
+           "cfd_get_tuning", "cfd_fill_ghosts", "cfd_residual", "cfd_step", "cfd_norms",
+           "cfd_time_step", "cfd_copy_metrics", "cfd_set_profiling", "cfd_profile_read",
+           "cfd_status_string", "cfd_last_error"]
+
+_lib = None
+
+
+def lib(build_if_missing: bool = True):
+    """Load libcfd.so (building it first only if no built library exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        if not build_if_missing:
+            raise RuntimeError(f"{LIBPATH} is missing; run python -m paper_1710_09995_amd.build")
+        from . import build as _b
+        _b.build()
+    L = C.CDLL(LIBPATH)
+    vp, i32, i64p = C.c_void_p, C.c_int32, C.POINTER(C.c_int64)
+    L.cfd_layout.argtypes = [i32, C.POINTER(Dims), i32, i64p, i64p, i64p]
+    L.cfd_workspace_size.argtypes = [C.POINTER(ParamsS), i32, C.POINTER(Dims), C.POINTER(C.c_size_t)]
+    L.cfd_create_blocks.argtypes = [C.POINTER(ParamsS), i32, C.POINTER(Dims), C.POINTER(vp), i32,
+                                    C.POINTER(ConnS), i32, C.POINTER(BCS), vp, C.c_size_t, vp,
+                                    C.POINTER(vp)]
+    L.cfd_destroy.argtypes = [vp]
+    L.cfd_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    L.cfd_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    L.cfd_fill_ghosts.argtypes = [vp, vp, vp]
+    L.cfd_residual.argtypes = [vp, vp, vp, vp]
+    L.cfd_step.argtypes = [vp, vp, i32, vp, vp]
+    L.cfd_norms.argtypes = [vp, vp, vp, vp, i32, vp]
+    L.cfd_time_step.argtypes = [vp, vp, vp, vp]
+    L.cfd_copy_metrics.argtypes = [vp, i32, vp, vp]
+    L.cfd_set_profiling.argtypes = [vp, i32]
+    L.cfd_profile_read.argtypes = [vp, C.POINTER(C.c_double)]
+    L.cfd_status_string.argtypes = [i32]
+    L.cfd_status_string.restype = C.c_char_p
+    L.cfd_last_error.argtypes = [vp]
+    L.cfd_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("cfd_status_string", "cfd_last_error"):
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+class CfdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(st, ctx=None):
+    if st != CFD_OK:
+        msg = lib().cfd_last_error(ctx).decode(errors="replace")
+        raise CfdError(st, msg)
+
+
+def to_params(p) -> ParamsS:
+    s = ParamsS()
+    for f, _ in ParamsS._fields_:
+        setattr(s, f, getattr(p, f))
+    return s
+
+
+def to_dims(dims) -> C.Array:
+    arr = (Dims * len(dims))()
+    for b, (ni, nj, nk) in enumerate(dims):
+        arr[b].ni, arr[b].nj, arr[b].nk = ni, nj, nk
+    return arr
+
+
+def to_conns(conns):
+    arr = (ConnS * max(len(conns), 1))()
+    for n, c in enumerate(conns):
+        a = arr[n]
+        a.blk, a.face, a.nbr, a.nbr_face = c.blk, c.face, c.nbr, c.nbr_face
+        a.lo[:] = list(c.lo)
+        a.hi[:] = list(c.hi)
+        a.nbr_lo[:] = list(c.nbr_lo)
+        a.shift[:] = [float(v) for v in c.shift]
+    return arr
+
+
+def to_bcs(bcs):
+    arr = (BCS * max(len(bcs), 1))()
+    for n, b in enumerate(bcs):
+        a = arr[n]
+        a.blk, a.face, a.kind = b.blk, b.face, b.kind
+        a.lo[:] = list(b.lo)
+        a.hi[:] = list(b.hi)
+    return arr
+
+
+def layout(dims):
+    L = lib()
+    nb = len(dims)
+    off = (C.c_int64 * nb)()
+    strd = (C.c_int64 * (4 * nb))()
+    tot = C.c_int64()
+    _check(L.cfd_layout(nb, to_dims(dims), NG, off, strd, C.byref(tot)))
+    return list(off), [tuple(strd[4 * b:4 * b + 4]) for b in range(nb)], int(tot.value)
+
+
+def _stream_handle(torch, stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One context over one GPU's share of blocks.
+
+    ``q`` is the caller-visible state arena (torch float64 on the device);
+    ``views()`` gives per-block padded views [5, nk+2g, nj+2g, ni+2g].
+    """
+
+    def __init__(self, case, device: str = "cuda:0", tuning: Optional[dict] = None, stream=None):
+        import torch
+        self.torch = torch
+        self.case = case
+        self.device = torch.device(device)
+        self.stream = stream
+        L = lib()
+        self.dims = list(case.dims)
+        self.offsets, self.strides, self.arena_elems = layout(self.dims)
+        self._pp = to_params(case.params)
+        self._dims = to_dims(self.dims)
+        ws = C.c_size_t()
+        _check(L.cfd_workspace_size(C.byref(self._pp), len(self.dims), self._dims, C.byref(ws)))
+        self.ws_bytes = int(ws.value)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            self.q = torch.full((self.arena_elems,), float("nan"), dtype=torch.float64, device=self.device)
+            nodes = [torch.from_numpy(np.ascontiguousarray(x)).to(self.device) for x in case.nodes]
+            nptrs = (C.c_void_p * len(nodes))(*[t.data_ptr() for t in nodes])
+            conns = to_conns(case.conns)
+            bcs = to_bcs(case.bcs)
+            ctx = C.c_void_p()
+            st = L.cfd_create_blocks(C.byref(self._pp), len(self.dims), self._dims, nptrs, len(case.conns),
+                                     conns, len(case.bcs), bcs, _ptr(self.workspace),
+                                     C.c_size_t(self.ws_bytes), self._s(), C.byref(ctx))
+            _check(st)
+            self.ctx = ctx
+            del nodes
+        if tuning:
+            self.set_tuning(**tuning)
+        self.set_state(case.q0)
+
+    # ------------------------------------------------------------ plumbing
+    def _s(self):
+        return _stream_handle(self.torch, self.stream)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().cfd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, kernel=None, tile_j=None, tile_k=None, use_graph=None):
+        t = Tuning()
+        _check(lib().cfd_get_tuning(self.ctx, C.byref(t)), self.ctx)
+        for name, v in (("kernel", kernel), ("tile_j", tile_j), ("tile_k", tile_k), ("use_graph", use_graph)):
+            if v is not None:
+                setattr(t, name, int(v))
+        _check(lib().cfd_set_tuning(self.ctx, C.byref(t)), self.ctx)
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().cfd_get_tuning(self.ctx, C.byref(t)), self.ctx)
+        return {n: getattr(t, n) for n, _ in Tuning._fields_}
+
+    def views(self, arena=None):
+        arena = self.q if arena is None else arena
+        out = []
+        for b, (ni, nj, nk) in enumerate(self.dims):
+            sv, sk, sj, si = self.strides[b]
+            out.append(arena.as_strided((5, nk + 2 * NG, nj + 2 * NG, ni + 2 * NG), (sv, sk, sj, si),
+                                        self.offsets[b]))
+        return out
+
+    def interior_views(self, arena=None):
+        return [v[:, NG:-NG, NG:-NG, NG:-NG] for v in self.views(arena)]
+
+    def new_arena(self, fill=float("nan")):
+        return self.torch.full((self.arena_elems,), fill, dtype=self.torch.float64, device=self.device)
+
+    def set_state(self, q0: Sequence[np.ndarray], arena=None):
+        arena = self.q if arena is None else arena
+        for v, q in zip(self.interior_views(arena), q0):
+            v.copy_(self.torch.from_numpy(np.ascontiguousarray(q)).to(self.device))
+
+    def state(self, arena=None) -> List[np.ndarray]:
+        self.torch.cuda.synchronize(self.device)
+        return [v.cpu().numpy().copy() for v in self.interior_views(arena)]
+
+    # ------------------------------------------------------------ library calls
+    def fill_ghosts(self, arena=None):
+        arena = self.q if arena is None else arena
+        _check(lib().cfd_fill_ghosts(self.ctx, _ptr(arena), self._s()), self.ctx)
+
+    def residual(self, arena=None, fill=True):
+        arena = self.q if arena is None else arena
+        if fill:
+            self.fill_ghosts(arena)
+        r = self.new_arena()
+        _check(lib().cfd_residual(self.ctx, _ptr(arena), _ptr(r), self._s()), self.ctx)
+        return r
+
+    def step(self, nsteps: int = 1, hist: bool = True, arena=None):
+        arena = self.q if arena is None else arena
+        h = None
+        if hist and nsteps > 0:
+            h = self.torch.zeros((nsteps, 12), dtype=self.torch.float64, device=self.device)
+        _check(lib().cfd_step(self.ctx, _ptr(arena), int(nsteps), _ptr(h) if h is not None else None,
+                              self._s()), self.ctx)
+        return h
+
+    def time_step(self, arena=None) -> float:
+        arena = self.q if arena is None else arena
+        d = self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
+        _check(lib().cfd_time_step(self.ctx, _ptr(arena), _ptr(d), self._s()), self.ctx)
+        self.torch.cuda.synchronize(self.device)
+        return float(d.item())
+
+    def set_profiling(self, on: bool):
+        _check(lib().cfd_set_profiling(self.ctx, 1 if on else 0), self.ctx)
+
+    def profile_read(self) -> dict:
+        """Per kernel class: launches, total/min/max ms (and mean) since the last read."""
+        out = (C.c_double * 12)()
+        _check(lib().cfd_profile_read(self.ctx, out), self.ctx)
+        res = {}
+        for k, name in enumerate(("stage", "ghost", "dt")):
+            n, tot, mn, mx = out[4 * k:4 * k + 4]
+            res[name] = {"launches": int(n), "total_ms": tot, "min_ms": mn, "max_ms": mx,
+                         "mean_ms": tot / n if n else 0.0}
+        return res
+
+    def metrics(self, blk: int) -> np.ndarray:
+        """Block blk's metrics [10, nk+2g, nj+2g, ni+2g] (S_i, S_j, S_k, V)."""
+        ni, nj, nk = self.dims[blk]
+        out = self.torch.empty((10, nk + 2 * NG, nj + 2 * NG, ni + 2 * NG), dtype=self.torch.float64,
+                               device=self.device)
+        _check(lib().cfd_copy_metrics(self.ctx, int(blk), _ptr(out), self._s()), self.ctx)
+        self.torch.cuda.synchronize(self.device)
+        return out.cpu().numpy()
+
+    def norms(self, arena=None, r=None, check=True) -> np.ndarray:
+        arena = self.q if arena is None else arena
+        out = (C.c_double * 12)()
+        st = lib().cfd_norms(self.ctx, _ptr(arena), _ptr(r) if r is not None else None, out, CFD_NORMS_HOST,
+                             self._s())
+        if st != CFD_OK and not (st == -4 and not check):
+            _check(st, self.ctx)
+        return np.array(out[:])

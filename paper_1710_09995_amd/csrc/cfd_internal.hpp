@@ -1,0 +1,76 @@
+// Internal device/host descriptors shared by the kernels and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cfd {
+
+constexpr int NG = 2;          // ghost layers
+constexpr int NV = 5;          // conserved variables
+constexpr int NM = 10;         // metric components: S_i(3), S_j(3), S_k(3), V
+constexpr int NHIST = 12;      // history row: dt, L2(R) x5, sum VQ x5, max|R_rho|
+constexpr int NPART = 13;      // per-workgroup partials: sum R^2 x5, sum VQ x5, max|R_rho|, nonfinite, min dt
+
+// physical boundary kinds (same values as cfd_bc_kind)
+constexpr int CFD_BC_KIND_FARFIELD = 1;
+constexpr int CFD_BC_KIND_SLIPWALL = 2;
+constexpr int CFD_BC_KIND_NOSLIP = 3;
+constexpr int CFD_BC_KIND_EXTRAP = 4;
+
+// One block of the multi-block grid, as the kernels see it.
+struct BlockDesc {
+  int32_t n[3];        // interior cells ni, nj, nk
+  int32_t pad0;
+  int64_t qoff;        // state arena: element index of padded cell (-g,-g,-g), var 0
+  int64_t moff;        // metrics arena offset (NM vars, same strides)
+  int64_t soff;        // scalar arena offset (1 var, same strides)
+  int64_t sv, sk, sj;  // element strides of var, k, j (i stride is 1)
+  int64_t xoff;        // node scratch: element index of padded node (-g,-g,-g), coord 0
+  int64_t xsv, xsk, xsj;
+};
+
+// One patch of one sweep (connection or physical boundary), cells or nodes.
+struct PatchDesc {
+  int32_t blk, face, kind, nbr;   // kind 0 = connection, else cfd_bc_kind
+  int32_t lo[3], hi[3];           // covered logical index range per direction (d entry unused)
+  int32_t noff[3];                // neighbour index = own index + noff (transverse); unused for d
+  int32_t count;                  // number of transverse points
+  int32_t pad0;
+  double shift[3];
+};
+
+// One tile of the stage work list.
+struct TileDesc {
+  int32_t blk, i0, j0, k0;
+};
+
+// Flow constants in the precision of the flux evaluation.
+template <typename T>
+struct Gas {
+  T gamma, gm1, prandtl, mu_inf, s_star, eps_h, eps_lim;
+  T uinf[3];
+};
+
+// Arguments of the residual / stage kernels.
+// mode 0 writes R; mode 1 is stage 1 (plus norm partials of R(Qn) and V Qn);
+// mode 2 is stages 2-3: out = a Qn + b (Qs - dt R(Qs)).
+struct StageArgs {
+  const double* qs;   // stencil state Q^(s)
+  const double* qn;   // Q^n (pointwise, mode 2)
+  double* out;        // R (mode 0) or Q^(s+1)
+  const double* met;
+  const double* dt;   // global dt (1 double) or per-cell scalar arena (local)
+  double* partials;   // [gridDim.x][NPART] (mode 1)
+  double a, b;
+  int32_t local_dt;
+  int32_t ntiles;
+  int32_t tile_j, tile_k;
+};
+
+struct StepParams {
+  double gamma, prandtl, mu_inf, s_star, cfl, eps_h, eps_lim;
+  double uinf[3];
+  int32_t viscous, flux_fp32, local_dt, pad0;
+};
+
+}  // namespace cfd

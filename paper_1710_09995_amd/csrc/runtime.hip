@@ -1,0 +1,848 @@
+// Host runtime behind the C ABI (include/cfd.h): table validation, arena and
+// workspace layout, patch and tile work lists, the setup pipeline (ghost
+// nodes -> metrics -> metric ghost copy), the per-step launch sequence and
+// its hipGraph cache.  No device memory is allocated here: the caller's
+// workspace holds everything.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/cfd.h"
+#include "cfd_internal.hpp"
+
+namespace cfd {
+void launch_copy_nodes(const double* src, double* x, const BlockDesc& B, hipStream_t s);
+void launch_ghost_nodes(double* x, const BlockDesc* blocks, const PatchDesc* patches, int npatch,
+                        int maxcount, hipStream_t s);
+void launch_metrics(const double* x, double* met, const BlockDesc& B, hipStream_t s);
+void launch_metric_ghosts(double* met, const BlockDesc* blocks, const PatchDesc* patches, int npatch,
+                          int maxcount, hipStream_t s);
+void launch_ghost_q(double* q, const double* met, const BlockDesc* blocks, const PatchDesc* patches,
+                    int npatch, int maxcount, const StepParams& SP, hipStream_t s);
+void launch_stage_simple(const StageArgs& A, int mode, bool visc, bool fp32, const BlockDesc* blocks,
+                         const TileDesc* tiles, const Gas<double>& g64, const Gas<float>& g32, int nwg,
+                         hipStream_t s);
+void launch_dt(const double* q, const double* met, double* dtcell, double* partials,
+               const BlockDesc* blocks, const TileDesc* tiles, int ntiles, int tile_j, int tile_k,
+               const StepParams& P, int nwg, hipStream_t s);
+void launch_norms(const double* q, const double* r, const double* met, double* partials,
+                  const BlockDesc* blocks, const TileDesc* tiles, int ntiles, int tile_j, int tile_k,
+                  int nwg, hipStream_t s);
+void launch_finalize(const double* partials, int nrows, int mode, double inv_ncells, double* dt,
+                     double* hist, double* nonfinite, hipStream_t s);
+}  // namespace cfd
+
+using namespace cfd;
+
+namespace {
+
+constexpr int TILE_I = 64;
+constexpr int NWG_MAX = 4096;   // persistent grid cap (rows of the partials buffers)
+
+thread_local std::string g_last_error;
+
+struct Err : std::exception {
+  cfd_status st;
+  std::string msg;
+  Err(cfd_status s, std::string m) : st(s), msg(std::move(m)) {}
+};
+
+[[noreturn]] void fail(cfd_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  throw Err(st, buf);
+}
+
+#define HIPCHK(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) fail(CFD_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  std::vector<int64_t> qoff, moff, soff, sv, sk, sj, xoff, xsv, xsk, xsj;
+  int64_t q_elems = 0, m_elems = 0, s_elems = 0, x_elems = 0;
+};
+
+// Aligned offset so that interior i = 0 (padded index g) sits on 128 bytes.
+int64_t place(int64_t& cursor, int64_t nvar, int64_t sv) {
+  int64_t off = round_up(cursor + NG, 16) - NG;
+  cursor = off + nvar * sv;
+  return off;
+}
+
+Layout make_layout(int nblk, const cfd_dims* dims) {
+  Layout L;
+  for (int b = 0; b < nblk; ++b) {
+    const int64_t ni = dims[b].ni, nj = dims[b].nj, nk = dims[b].nk;
+    const int64_t sj = round_up(ni + 2 * NG, 16);
+    const int64_t sk = sj * (nj + 2 * NG);
+    const int64_t sv = sk * (nk + 2 * NG);
+    L.sj.push_back(sj);
+    L.sk.push_back(sk);
+    L.sv.push_back(sv);
+    L.qoff.push_back(place(L.q_elems, NV, sv));
+    L.moff.push_back(place(L.m_elems, NM, sv));
+    L.soff.push_back(place(L.s_elems, 1, sv));
+    const int64_t xsj = ni + 1 + 2 * NG, xsk = xsj * (nj + 1 + 2 * NG), xsv = xsk * (nk + 1 + 2 * NG);
+    L.xsj.push_back(xsj);
+    L.xsk.push_back(xsk);
+    L.xsv.push_back(xsv);
+    L.xoff.push_back(L.x_elems);
+    L.x_elems += 3 * xsv;
+  }
+  L.q_elems = round_up(L.q_elems + 16, 16);
+  L.m_elems = round_up(L.m_elems + 16, 16);
+  L.s_elems = round_up(L.s_elems + 16, 16);
+  return L;
+}
+
+struct WsLayout {
+  size_t met, qa, qb, scal, blocks, patches, tiles, part_dt, part_nrm, scalars, total;
+  size_t node_scratch;   // aliases qa.. during setup
+  int64_t max_tiles;
+  int npatch_total;
+};
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+int64_t max_tiles_for(int nblk, const cfd_dims* dims) {
+  int64_t t = 0;
+  for (int b = 0; b < nblk; ++b)
+    t += (int64_t)((dims[b].ni + TILE_I - 1) / TILE_I) * dims[b].nj * dims[b].nk;
+  return t;
+}
+
+WsLayout make_ws(const Layout& L, int nblk, const cfd_dims* dims, int npatch_total, bool local_dt) {
+  WsLayout W{};
+  size_t c = 0;
+  W.met = c;
+  c = align256(c + (size_t)L.m_elems * 8);
+  W.qa = c;
+  c = align256(c + (size_t)L.q_elems * 8);
+  W.qb = c;
+  c = align256(c + (size_t)L.q_elems * 8);
+  // node scratch aliases qa (and beyond if needed)
+  W.node_scratch = W.qa;
+  if (W.qa + (size_t)L.x_elems * 8 > c) c = align256(W.qa + (size_t)L.x_elems * 8);
+  W.scal = c;
+  if (local_dt) c = align256(c + (size_t)L.s_elems * 8);
+  W.blocks = c;
+  c = align256(c + sizeof(BlockDesc) * nblk);
+  W.patches = c;
+  c = align256(c + sizeof(PatchDesc) * (size_t)std::max(npatch_total, 1));
+  W.max_tiles = max_tiles_for(nblk, dims);
+  W.tiles = c;
+  c = align256(c + sizeof(TileDesc) * (size_t)W.max_tiles);
+  W.part_dt = c;
+  c = align256(c + sizeof(double) * NPART * NWG_MAX);
+  W.part_nrm = c;
+  c = align256(c + sizeof(double) * NPART * NWG_MAX);
+  W.scalars = c;   // dt, hist[12], nonfinite, norms_out[12]
+  c = align256(c + sizeof(double) * 32);
+  W.total = c;
+  W.npatch_total = npatch_total;
+  return W;
+}
+
+void check_params(const cfd_params* p) {
+  if (!p) fail(CFD_EINVAL, "params is NULL");
+  if (p->ghost_layers != NG) fail(CFD_EUNSUPPORTED, "ghost_layers must be %d", NG);
+  if (!(p->gamma > 1.0)) fail(CFD_EINVAL, "gamma must exceed 1");
+  if (!(p->cfl > 0.0)) fail(CFD_EINVAL, "cfl must be positive");
+  if (p->viscous && !(p->reynolds > 0.0 && p->prandtl > 0.0))
+    fail(CFD_EINVAL, "viscous flow needs positive reynolds and prandtl");
+  if (!(p->mach >= 0.0)) fail(CFD_EINVAL, "mach must be non-negative");
+}
+
+void check_dims(int nblk, const cfd_dims* dims) {
+  if (nblk <= 0 || !dims) fail(CFD_EINVAL, "need at least one block");
+  for (int b = 0; b < nblk; ++b) {
+    const cfd_dims& d = dims[b];
+    if (d.ni < NG || d.nj < NG || d.nk < NG)
+      fail(CFD_EINVAL, "block %d: every extent must be >= %d (got %d x %d x %d)", b, NG, d.ni, d.nj, d.nk);
+    if ((int64_t)d.ni * d.nj * d.nk > (int64_t)1 << 34) fail(CFD_EINVAL, "block %d too large", b);
+  }
+}
+
+void face_extent(const cfd_dims& d, int face, int& e1, int& e2) {
+  const int n[3] = {d.ni, d.nj, d.nk};
+  const int dir = face >> 1;
+  const int t1 = dir == 0 ? 1 : 0, t2 = dir == 2 ? 1 : 2;
+  e1 = n[t1];
+  e2 = n[t2];
+}
+
+void validate_tables(int nblk, const cfd_dims* dims, int nconn, const cfd_conn* conns, int nbc,
+                     const cfd_bc* bcs) {
+  if (nconn < 0 || nbc < 0 || (nconn && !conns) || (nbc && !bcs)) fail(CFD_EINVAL, "bad table pointers");
+  std::vector<std::vector<uint8_t>> cover(nblk * 6);
+  for (int b = 0; b < nblk; ++b)
+    for (int f = 0; f < 6; ++f) {
+      int e1, e2;
+      face_extent(dims[b], f, e1, e2);
+      cover[b * 6 + f].assign((size_t)e1 * e2, 0);
+    }
+  auto mark = [&](int b, int f, const int32_t lo[2], const int32_t hi[2], const char* what, int idx) {
+    int e1, e2;
+    face_extent(dims[b], f, e1, e2);
+    if (lo[0] < 0 || lo[1] < 0 || hi[0] > e1 || hi[1] > e2 || lo[0] >= hi[0] || lo[1] >= hi[1])
+      fail(CFD_EINVAL, "%s %d: patch [%d,%d)x[%d,%d) outside face %d of block %d (%d x %d)", what, idx,
+           lo[0], hi[0], lo[1], hi[1], f, b, e1, e2);
+    auto& cv = cover[b * 6 + f];
+    for (int q = lo[1]; q < hi[1]; ++q)
+      for (int p = lo[0]; p < hi[0]; ++p) {
+        if (cv[(size_t)q * e1 + p]) fail(CFD_EINVAL, "%s %d: face %d of block %d covered twice at (%d,%d)",
+                                         what, idx, f, b, p, q);
+        cv[(size_t)q * e1 + p] = 1;
+      }
+  };
+  for (int c = 0; c < nconn; ++c) {
+    const cfd_conn& C = conns[c];
+    if (C.blk < 0 || C.blk >= nblk || C.nbr < 0 || C.nbr >= nblk) fail(CFD_EINVAL, "connection %d: bad block", c);
+    if (C.face < 0 || C.face > 5) fail(CFD_EINVAL, "connection %d: bad face", c);
+    if (C.nbr_face != (C.face ^ 1))
+      fail(CFD_EINVAL, "connection %d: only opposite faces of one direction connect (identity orientation)", c);
+    mark(C.blk, C.face, C.lo, C.hi, "connection", c);
+    int e1, e2;
+    face_extent(dims[C.nbr], C.nbr_face, e1, e2);
+    if (C.nbr_lo[0] < 0 || C.nbr_lo[1] < 0 || C.nbr_lo[0] + (C.hi[0] - C.lo[0]) > e1 ||
+        C.nbr_lo[1] + (C.hi[1] - C.lo[1]) > e2)
+      fail(CFD_EINVAL, "connection %d: neighbour patch outside block %d face %d", c, C.nbr, C.nbr_face);
+    for (int x = 0; x < 3; ++x)
+      if (!std::isfinite(C.shift[x])) fail(CFD_EINVAL, "connection %d: non-finite shift", c);
+  }
+  for (int c = 0; c < nbc; ++c) {
+    const cfd_bc& B = bcs[c];
+    if (B.blk < 0 || B.blk >= nblk) fail(CFD_EINVAL, "boundary %d: bad block", c);
+    if (B.face < 0 || B.face > 5) fail(CFD_EINVAL, "boundary %d: bad face", c);
+    if (B.kind < CFD_BC_FARFIELD || B.kind > CFD_BC_EXTRAP) fail(CFD_EINVAL, "boundary %d: bad kind %d", c, B.kind);
+    mark(B.blk, B.face, B.lo, B.hi, "boundary", c);
+  }
+  for (int b = 0; b < nblk; ++b)
+    for (int f = 0; f < 6; ++f)
+      for (uint8_t v : cover[b * 6 + f])
+        if (!v) fail(CFD_EINVAL, "face %d of block %d is not fully covered by connections/boundaries", f, b);
+}
+
+// Patch descriptors for sweep d (cells or nodes), with the transverse
+// extension into ghost layers of directions swept earlier.
+void build_patches(int d, bool nodes, int nblk, const cfd_dims* dims, int nconn, const cfd_conn* conns,
+                   int nbc, const cfd_bc* bcs, std::vector<PatchDesc>& out, int& maxcount) {
+  auto make = [&](int blk, int face, int kind, int nbr, const int32_t lo[2], const int32_t hi[2],
+                  const int32_t* nbr_lo, const double* shift) {
+    PatchDesc P{};
+    P.blk = blk;
+    P.face = face;
+    P.kind = kind;
+    P.nbr = nbr;
+    const int n[3] = {dims[blk].ni, dims[blk].nj, dims[blk].nk};
+    const int ts[2] = {d == 0 ? 1 : 0, d == 2 ? 1 : 2};
+    int count = 1;
+    for (int a = 0; a < 2; ++a) {
+      const int t = ts[a];
+      int s = lo[a], e = hi[a];
+      if (nodes && hi[a] == n[t]) e = n[t] + 1;
+      if (t < d) {
+        if (lo[a] == 0) s = -NG;
+        if (hi[a] == n[t]) e = nodes ? n[t] + 1 + NG : n[t] + NG;
+      }
+      P.lo[t] = s;
+      P.hi[t] = e;
+      P.noff[t] = nbr_lo ? nbr_lo[a] - lo[a] : 0;
+      count *= (e - s);
+    }
+    P.count = count;
+    for (int x = 0; x < 3; ++x) P.shift[x] = shift ? shift[x] : 0.0;
+    maxcount = std::max(maxcount, count);
+    out.push_back(P);
+  };
+  for (int c = 0; c < nbc; ++c)
+    if ((bcs[c].face >> 1) == d) make(bcs[c].blk, bcs[c].face, bcs[c].kind, -1, bcs[c].lo, bcs[c].hi, nullptr, nullptr);
+  for (int c = 0; c < nconn; ++c)
+    if ((conns[c].face >> 1) == d)
+      make(conns[c].blk, conns[c].face, 0, conns[c].nbr, conns[c].lo, conns[c].hi, conns[c].nbr_lo, conns[c].shift);
+}
+
+}  // namespace
+
+struct cfd_ctx {
+  cfd_params params{};
+  int nblk = 0;
+  std::vector<cfd_dims> dims;
+  Layout L;
+  WsLayout W{};
+  std::vector<BlockDesc> hblocks;
+  char* ws = nullptr;
+  BlockDesc* dblocks = nullptr;
+  PatchDesc* dpatches = nullptr;
+  // per sweep: [node sweeps 0..2][cell sweeps 0..2]
+  int poff[6] = {0}, pcount[6] = {0}, pmax[6] = {0};
+  TileDesc* dtiles = nullptr;
+  int ntiles = 0;
+  int64_t ncells = 0;
+  cfd_tuning tun{1, 4, 16, 1};
+  StepParams SP{};
+  Gas<double> g64{};
+  Gas<float> g32{};
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* graph_q = nullptr;
+  std::string last_error;
+  // kernel timing (eager steps only)
+  struct EvPair {
+    hipEvent_t a, b;
+    int cls;
+  };
+  bool profiling = false;
+  std::vector<EvPair> ev_used;
+  std::vector<hipEvent_t> ev_pool;
+
+  hipEvent_t take_event() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) throw std::runtime_error(hipGetErrorString(r));
+    return e;
+  }
+  void release_events() {
+    for (auto& p : ev_used) {
+      ev_pool.push_back(p.a);
+      ev_pool.push_back(p.b);
+    }
+    ev_used.clear();
+  }
+  void destroy_events() {
+    release_events();
+    for (hipEvent_t e : ev_pool) hipEventDestroy(e);
+    ev_pool.clear();
+  }
+
+  double* met() const { return reinterpret_cast<double*>(ws + W.met); }
+  double* qa() const { return reinterpret_cast<double*>(ws + W.qa); }
+  double* qb() const { return reinterpret_cast<double*>(ws + W.qb); }
+  double* scal() const { return params.local_dt ? reinterpret_cast<double*>(ws + W.scal) : nullptr; }
+  double* part_dt() const { return reinterpret_cast<double*>(ws + W.part_dt); }
+  double* part_nrm() const { return reinterpret_cast<double*>(ws + W.part_nrm); }
+  double* d_dt() const { return reinterpret_cast<double*>(ws + W.scalars); }
+  double* d_hist() const { return d_dt() + 1; }
+  double* d_nonfinite() const { return d_dt() + 13; }
+  double* d_norms() const { return d_dt() + 16; }
+
+  void drop_graph() {
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (graph) hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    graph_q = nullptr;
+  }
+};
+
+namespace {
+
+void set_params(cfd_ctx* c) {
+  const cfd_params& p = c->params;
+  StepParams& S = c->SP;
+  S.gamma = p.gamma;
+  S.prandtl = p.prandtl;
+  const double speed = p.mach * std::sqrt(p.gamma);
+  S.mu_inf = p.viscous ? speed / p.reynolds : 0.0;
+  S.s_star = p.sutherland;
+  S.cfl = p.cfl;
+  S.eps_h = p.entropy_fix;
+  S.eps_lim = p.limiter_eps;
+  S.uinf[0] = speed * std::cos(p.alpha) * std::cos(p.beta);
+  S.uinf[1] = speed * std::sin(p.alpha) * std::cos(p.beta);
+  S.uinf[2] = speed * std::sin(p.beta);
+  S.viscous = p.viscous;
+  S.flux_fp32 = p.flux_fp32;
+  S.local_dt = p.local_dt;
+  auto fill = [&](auto& G) {
+    using T = std::remove_reference_t<decltype(G.gamma)>;
+    G.gamma = (T)p.gamma;
+    G.gm1 = (T)(p.gamma - 1.0);
+    G.prandtl = (T)p.prandtl;
+    G.mu_inf = (T)S.mu_inf;
+    G.s_star = (T)p.sutherland;
+    G.eps_h = (T)p.entropy_fix;
+    G.eps_lim = (T)p.limiter_eps;
+    for (int x = 0; x < 3; ++x) G.uinf[x] = (T)S.uinf[x];
+  };
+  fill(c->g64);
+  fill(c->g32);
+}
+
+void build_tiles(cfd_ctx* c, hipStream_t s) {
+  const int tj = c->tun.tile_j, tk = c->tun.tile_k;
+  struct T2 {
+    TileDesc t;
+    int64_t work;
+  };
+  std::vector<T2> v;
+  for (int b = 0; b < c->nblk; ++b) {
+    const cfd_dims& d = c->dims[b];
+    for (int k0 = 0; k0 < d.nk; k0 += tk)
+      for (int j0 = 0; j0 < d.nj; j0 += tj)
+        for (int i0 = 0; i0 < d.ni; i0 += TILE_I) {
+          const int64_t w = (int64_t)std::min(TILE_I, d.ni - i0) * std::min(tj, d.nj - j0) * std::min(tk, d.nk - k0);
+          v.push_back({{b, i0, j0, k0}, w});
+        }
+  }
+  // longest-processing-time order: big tiles first, ties keep block order
+  std::stable_sort(v.begin(), v.end(), [](const T2& a, const T2& b) { return a.work > b.work; });
+  if ((int64_t)v.size() > c->W.max_tiles) fail(CFD_EINTERNAL, "tile list overflow");
+  std::vector<TileDesc> h(v.size());
+  for (size_t i = 0; i < v.size(); ++i) h[i] = v[i].t;
+  c->ntiles = (int)h.size();
+  HIPCHK(hipMemcpyAsync(c->dtiles, h.data(), sizeof(TileDesc) * h.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+int nwg_for(const cfd_ctx* c, int per_cu) {
+  return std::max(1, std::min({c->ntiles, NWG_MAX, 256 * per_cu}));
+}
+
+// Run a launch; with profiling on, bracket it with a hipEvent pair on its stream.
+template <typename F>
+void timed(cfd_ctx* c, int cls, hipStream_t s, F&& launch) {
+  if (!c->profiling) {
+    launch();
+    return;
+  }
+  hipEvent_t a = c->take_event(), b = c->take_event();
+  HIPCHK(hipEventRecord(a, s));
+  launch();
+  HIPCHK(hipEventRecord(b, s));
+  c->ev_used.push_back({a, b, cls});
+}
+
+void ghost_fill(cfd_ctx* c, double* q, hipStream_t s) {
+  for (int d = 0; d < 3; ++d)
+    timed(c, 1, s, [&] {
+      launch_ghost_q(q, c->met(), c->dblocks, c->dpatches + c->poff[3 + d], c->pcount[3 + d], c->pmax[3 + d],
+                     c->SP, s);
+    });
+}
+
+StageArgs stage_args(cfd_ctx* c) {
+  StageArgs A{};
+  A.met = c->met();
+  A.local_dt = c->params.local_dt;
+  A.dt = c->params.local_dt ? c->scal() : c->d_dt();
+  A.ntiles = c->ntiles;
+  A.tile_j = c->tun.tile_j;
+  A.tile_k = c->tun.tile_k;
+  A.partials = c->part_nrm();
+  return A;
+}
+
+int stage_nwg(cfd_ctx* c) {
+  return nwg_for(c, 8);
+}
+
+void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, int nwg, hipStream_t s) {
+  const bool visc = c->params.viscous != 0, fp32 = c->params.flux_fp32 != 0;
+  if (c->tun.kernel != 1) fail(CFD_EUNSUPPORTED, "stage kernel %d not available", c->tun.kernel);
+  timed(c, 0, s, [&] { launch_stage_simple(A, mode, visc, fp32, c->dblocks, c->dtiles, c->g64, c->g32, nwg, s); });
+}
+
+// One full RK3 step: ghost fill + dt + 3 x (ghost fill + stage) + finalize.
+void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
+  const int nwg_dt = nwg_for(c, 8);
+  const int nwg = stage_nwg(c);
+  ghost_fill(c, q, s);
+  timed(c, 2, s, [&] {
+    launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
+              c->tun.tile_k, c->SP, nwg_dt, s);
+  });
+  launch_finalize(c->part_dt(), nwg_dt, 0, 0.0, c->d_dt(), nullptr, nullptr, s);
+  StageArgs A = stage_args(c);
+  A.qs = q;
+  A.qn = q;
+  A.out = c->qa();
+  launch_stage(c, A, 1, nwg, s);
+  ghost_fill(c, c->qa(), s);
+  A.qs = c->qa();
+  A.out = c->qb();
+  A.a = 0.75;
+  A.b = 0.25;
+  launch_stage(c, A, 2, nwg, s);
+  ghost_fill(c, c->qb(), s);
+  A.qs = c->qb();
+  A.out = q;
+  A.a = 1.0 / 3.0;
+  A.b = 2.0 / 3.0;
+  launch_stage(c, A, 2, nwg, s);
+  launch_finalize(c->part_nrm(), nwg, 1, 1.0 / (double)c->ncells, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
+}
+
+template <typename F>
+cfd_status guard(cfd_ctx* c, F&& f) {
+  try {
+    f();
+    return CFD_OK;
+  } catch (const Err& e) {
+    g_last_error = e.msg;
+    if (c) c->last_error = e.msg;
+    return e.st;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    if (c) c->last_error = e.what();
+    return CFD_EINTERNAL;
+  } catch (...) {
+    g_last_error = "unknown internal error";
+    if (c) c->last_error = g_last_error;
+    return CFD_EINTERNAL;
+  }
+}
+
+void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) fail(CFD_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+cfd_status cfd_layout(int32_t nblk, const cfd_dims* dims, int32_t ghost_layers, int64_t* block_offset,
+                      int64_t* block_strides, int64_t* arena_elems) {
+  return guard(nullptr, [&] {
+    if (ghost_layers != NG) fail(CFD_EUNSUPPORTED, "ghost_layers must be %d", NG);
+    check_dims(nblk, dims);
+    Layout L = make_layout(nblk, dims);
+    for (int b = 0; b < nblk; ++b) {
+      if (block_offset) block_offset[b] = L.qoff[b];
+      if (block_strides) {
+        block_strides[4 * b + 0] = L.sv[b];
+        block_strides[4 * b + 1] = L.sk[b];
+        block_strides[4 * b + 2] = L.sj[b];
+        block_strides[4 * b + 3] = 1;
+      }
+    }
+    if (arena_elems) *arena_elems = L.q_elems;
+  });
+}
+
+static int count_patches(int nconn, int nbc) { return 2 * (nconn + nbc); }
+
+cfd_status cfd_workspace_size(const cfd_params* params, int32_t nblk, const cfd_dims* dims,
+                              size_t* workspace_bytes) {
+  return guard(nullptr, [&] {
+    check_params(params);
+    check_dims(nblk, dims);
+    if (!workspace_bytes) fail(CFD_EINVAL, "workspace_bytes is NULL");
+    Layout L = make_layout(nblk, dims);
+    // patch count is bounded by 6 faces x a generous number of patches; the
+    // exact count is only known with the tables, so reserve for 64 per face.
+    WsLayout W = make_ws(L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0);
+    *workspace_bytes = W.total;
+  });
+}
+
+cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_dims* dims,
+                             const double* const* nodes_dev, int32_t nconn, const cfd_conn* conns, int32_t nbc,
+                             const cfd_bc* bcs, void* workspace_dev, size_t workspace_bytes, hipStream_t stream,
+                             cfd_ctx** out) {
+  if (out) *out = nullptr;
+  cfd_ctx* c = nullptr;
+  cfd_status st = guard(nullptr, [&] {
+    if (!out) fail(CFD_EINVAL, "out is NULL");
+    check_params(params);
+    check_dims(nblk, dims);
+    if (!nodes_dev) fail(CFD_EINVAL, "nodes_dev is NULL");
+    for (int b = 0; b < nblk; ++b)
+      if (!nodes_dev[b]) fail(CFD_EINVAL, "nodes_dev[%d] is NULL", b);
+    validate_tables(nblk, dims, nconn, conns, nbc, bcs);
+    if (!workspace_dev) fail(CFD_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(workspace_dev) & 255) != 0) fail(CFD_EINVAL, "workspace must be 256-byte aligned");
+    const int npatch = count_patches(nconn, nbc);
+    if (npatch > 2 * 6 * 64 * nblk) fail(CFD_EUNSUPPORTED, "more than 64 patches per face on average");
+    c = new cfd_ctx();
+    c->params = *params;
+    c->nblk = nblk;
+    c->dims.assign(dims, dims + nblk);
+    c->L = make_layout(nblk, dims);
+    size_t need = 0;
+    {
+      WsLayout Wfull = make_ws(c->L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0);
+      need = Wfull.total;
+    }
+    if (workspace_bytes < need) fail(CFD_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    c->W = make_ws(c->L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0);
+    c->ws = static_cast<char*>(workspace_dev);
+    c->dblocks = reinterpret_cast<BlockDesc*>(c->ws + c->W.blocks);
+    c->dpatches = reinterpret_cast<PatchDesc*>(c->ws + c->W.patches);
+    c->dtiles = reinterpret_cast<TileDesc*>(c->ws + c->W.tiles);
+    set_params(c);
+    for (int b = 0; b < nblk; ++b) {
+      BlockDesc B{};
+      B.n[0] = dims[b].ni;
+      B.n[1] = dims[b].nj;
+      B.n[2] = dims[b].nk;
+      B.qoff = c->L.qoff[b];
+      B.moff = c->L.moff[b];
+      B.soff = c->L.soff[b];
+      B.sv = c->L.sv[b];
+      B.sk = c->L.sk[b];
+      B.sj = c->L.sj[b];
+      B.xoff = c->L.xoff[b];   // padded node (-g,-g,-g) at the start of the block's scratch
+      B.xsv = c->L.xsv[b];
+      B.xsk = c->L.xsk[b];
+      B.xsj = c->L.xsj[b];
+      c->hblocks.push_back(B);
+      c->ncells += (int64_t)dims[b].ni * dims[b].nj * dims[b].nk;
+    }
+    std::vector<PatchDesc> all;
+    for (int sweep = 0; sweep < 6; ++sweep) {
+      const bool nodes = sweep < 3;
+      const int d = sweep % 3;
+      c->poff[sweep] = (int)all.size();
+      int mx = 0;
+      build_patches(d, nodes, nblk, dims, nconn, conns, nbc, bcs, all, mx);
+      c->pcount[sweep] = (int)all.size() - c->poff[sweep];
+      c->pmax[sweep] = mx;
+    }
+    HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipMemcpyAsync(c->dblocks, c->hblocks.data(), sizeof(BlockDesc) * nblk, hipMemcpyHostToDevice, stream));
+    if (!all.empty())
+      HIPCHK(hipMemcpyAsync(c->dpatches, all.data(), sizeof(PatchDesc) * all.size(), hipMemcpyHostToDevice, stream));
+    // setup pipeline: padded nodes -> ghost nodes -> metrics -> metric ghosts
+    double* x = reinterpret_cast<double*>(c->ws + c->W.node_scratch);
+    for (int b = 0; b < nblk; ++b) launch_copy_nodes(nodes_dev[b], x, c->hblocks[b], stream);
+    check_launch();
+    for (int d = 0; d < 3; ++d)
+      launch_ghost_nodes(x, c->dblocks, c->dpatches + c->poff[d], c->pcount[d], c->pmax[d], stream);
+    check_launch();
+    for (int b = 0; b < nblk; ++b) launch_metrics(x, c->met(), c->hblocks[b], stream);
+    check_launch();
+    for (int d = 0; d < 3; ++d)
+      launch_metric_ghosts(c->met(), c->dblocks, c->dpatches + c->poff[3 + d], c->pcount[3 + d], c->pmax[3 + d],
+                           stream);
+    check_launch();
+    HIPCHK(hipStreamSynchronize(stream));
+    build_tiles(c, stream);
+    *out = c;
+  });
+  if (st != CFD_OK && c) {
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    delete c;
+  }
+  return st;
+}
+
+cfd_status cfd_set_profiling(cfd_ctx* c, int32_t enable) {
+  return guard(c, [&] {
+    if (!c) fail(CFD_EINVAL, "NULL context");
+    if (!enable) {
+      HIPCHK(hipDeviceSynchronize());
+      c->release_events();
+    }
+    c->profiling = enable != 0;
+  });
+}
+
+cfd_status cfd_profile_read(cfd_ctx* c, double out[12]) {
+  return guard(c, [&] {
+    if (!c || !out) fail(CFD_EINVAL, "NULL argument");
+    for (int k = 0; k < 3; ++k) {
+      out[4 * k + 0] = 0.0;
+      out[4 * k + 1] = 0.0;
+      out[4 * k + 2] = 1e300;
+      out[4 * k + 3] = 0.0;
+    }
+    for (auto& p : c->ev_used) {
+      HIPCHK(hipEventSynchronize(p.b));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+      double* o = out + 4 * p.cls;
+      o[0] += 1.0;
+      o[1] += ms;
+      o[2] = std::min(o[2], (double)ms);
+      o[3] = std::max(o[3], (double)ms);
+    }
+    for (int k = 0; k < 3; ++k)
+      if (out[4 * k] == 0.0) out[4 * k + 2] = 0.0;
+    c->release_events();
+  });
+}
+
+cfd_status cfd_destroy(cfd_ctx* c) {
+  if (!c) return CFD_OK;
+  c->destroy_events();
+  c->drop_graph();
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  delete c;
+  return CFD_OK;
+}
+
+cfd_status cfd_set_tuning(cfd_ctx* c, const cfd_tuning* t) {
+  return guard(c, [&] {
+    if (!c || !t) fail(CFD_EINVAL, "NULL argument");
+    if (t->kernel < 0 || t->kernel > 1) fail(CFD_EINVAL, "kernel must be 0 or 1");
+    if (t->tile_j < 1 || t->tile_j > 16 || (t->tile_j & (t->tile_j - 1)))
+      fail(CFD_EINVAL, "tile_j must be a power of two in [1, 16]");
+    if (t->tile_k < 1 || t->tile_k > 4096) fail(CFD_EINVAL, "tile_k must be in [1, 4096]");
+    c->drop_graph();
+    c->tun = *t;
+    HIPCHK(hipDeviceSynchronize());
+    build_tiles(c, c->cap_stream);
+  });
+}
+
+cfd_status cfd_get_tuning(const cfd_ctx* c, cfd_tuning* t) {
+  if (!c || !t) return CFD_EINVAL;
+  *t = c->tun;
+  return CFD_OK;
+}
+
+cfd_status cfd_fill_ghosts(cfd_ctx* c, double* q, hipStream_t s) {
+  return guard(c, [&] {
+    if (!c || !q) fail(CFD_EINVAL, "NULL argument");
+    ghost_fill(c, q, s);
+    check_launch();
+  });
+}
+
+cfd_status cfd_residual(cfd_ctx* c, const double* q, double* r, hipStream_t s) {
+  return guard(c, [&] {
+    if (!c || !q || !r) fail(CFD_EINVAL, "NULL argument");
+    if (q == r) fail(CFD_EINVAL, "q and r must not alias");
+    StageArgs A = stage_args(c);
+    A.qs = q;
+    A.qn = q;
+    A.out = r;
+    launch_stage(c, A, 0, stage_nwg(c), s);
+    check_launch();
+  });
+}
+
+cfd_status cfd_time_step(cfd_ctx* c, const double* q, double* dt_dev, hipStream_t s) {
+  return guard(c, [&] {
+    if (!c || !q || !dt_dev) fail(CFD_EINVAL, "NULL argument");
+    const int nwg = nwg_for(c, 8);
+    launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
+              c->tun.tile_k, c->SP, nwg, s);
+    launch_finalize(c->part_dt(), nwg, 0, 0.0, dt_dev, nullptr, nullptr, s);
+    check_launch();
+  });
+}
+
+cfd_status cfd_step(cfd_ctx* c, double* q, int32_t nsteps, double* hist, hipStream_t s) {
+  return guard(c, [&] {
+    if (!c || !q) fail(CFD_EINVAL, "NULL argument");
+    if (nsteps < 0) fail(CFD_EINVAL, "nsteps must be >= 0");
+    if (c->tun.use_graph && !c->profiling) {
+      if (!c->gexec || c->graph_q != q) {
+        c->drop_graph();
+        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        try {
+          enqueue_step(c, q, c->cap_stream);
+        } catch (...) {
+          hipGraph_t g = nullptr;
+          hipStreamEndCapture(c->cap_stream, &g);
+          if (g) hipGraphDestroy(g);
+          throw;
+        }
+        HIPCHK(hipStreamEndCapture(c->cap_stream, &c->graph));
+        HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+        c->graph_q = q;
+      }
+      for (int n = 0; n < nsteps; ++n) {
+        HIPCHK(hipGraphLaunch(c->gexec, s));
+        if (hist)
+          HIPCHK(hipMemcpyAsync(hist + (int64_t)n * NHIST, c->d_hist(), sizeof(double) * NHIST,
+                                hipMemcpyDeviceToDevice, s));
+      }
+    } else {
+      for (int n = 0; n < nsteps; ++n) {
+        enqueue_step(c, q, s);
+        check_launch();
+        if (hist)
+          HIPCHK(hipMemcpyAsync(hist + (int64_t)n * NHIST, c->d_hist(), sizeof(double) * NHIST,
+                                hipMemcpyDeviceToDevice, s));
+      }
+    }
+  });
+}
+
+cfd_status cfd_norms(cfd_ctx* c, const double* q, const double* r, double* out, int32_t flags, hipStream_t s) {
+  cfd_status st = guard(c, [&] {
+    if (!c || !q || !out) fail(CFD_EINVAL, "NULL argument");
+    const int nwg = nwg_for(c, 8);
+    launch_norms(q, r, c->met(), c->part_nrm(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j, c->tun.tile_k,
+                 nwg, s);
+    // history row layout: [dt, L2 x5, VQ x5, max]; norms output drops dt
+    launch_finalize(c->part_nrm(), nwg, 1, 1.0 / (double)c->ncells, nullptr, c->d_norms(), c->d_nonfinite(), s);
+    check_launch();
+    if (flags & CFD_NORMS_HOST) {
+      double row[NHIST + 1];
+      HIPCHK(hipMemcpyAsync(row, c->d_norms(), sizeof(double) * NHIST, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(row + NHIST, c->d_nonfinite(), sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int q2 = 0; q2 < 11; ++q2) out[q2] = row[1 + q2];
+      out[11] = row[NHIST];
+    } else {
+      HIPCHK(hipMemcpyAsync(out, c->d_norms() + 1, sizeof(double) * 11, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(out + 11, c->d_nonfinite(), sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+  });
+  if (st == CFD_OK && (flags & CFD_NORMS_HOST) && out[11] > 0.0) {
+    c->last_error = "non-finite values in state or residual";
+    return CFD_ENONFINITE;
+  }
+  return st;
+}
+
+cfd_status cfd_copy_metrics(cfd_ctx* c, int32_t blk, double* out, hipStream_t s) {
+  return guard(c, [&] {
+    if (!c || !out) fail(CFD_EINVAL, "NULL argument");
+    if (blk < 0 || blk >= c->nblk) fail(CFD_EINVAL, "block %d out of range", blk);
+    const BlockDesc& B = c->hblocks[blk];
+    const size_t wi = (size_t)B.n[0] + 2 * NG, hj = (size_t)B.n[1] + 2 * NG, dk = (size_t)B.n[2] + 2 * NG;
+    // rows of the padded block are strided; one 2-D copy per metric component
+    for (int m = 0; m < NM; ++m)
+      HIPCHK(hipMemcpy2DAsync(out + (size_t)m * wi * hj * dk, wi * sizeof(double),
+                              c->met() + B.moff + (int64_t)m * B.sv, (size_t)B.sj * sizeof(double),
+                              wi * sizeof(double), hj * dk, hipMemcpyDeviceToDevice, s));
+  });
+}
+
+const char* cfd_status_string(cfd_status s) {
+  switch (s) {
+    case CFD_OK: return "ok";
+    case CFD_EINVAL: return "invalid argument";
+    case CFD_ENOMEM: return "workspace too small";
+    case CFD_EHIP: return "HIP runtime error";
+    case CFD_ENONFINITE: return "non-finite values";
+    case CFD_ESTATE: return "invalid state";
+    case CFD_EUNSUPPORTED: return "unsupported option";
+    case CFD_EINTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* cfd_last_error(const cfd_ctx* c) {
+  if (c) return c->last_error.c_str();
+  return g_last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and its host-only entry points (layout, workspace size,
+table validation) behave as documented.  No compute call is made here."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1710_09995_amd import binding as B
+from paper_1710_09995_amd import cases
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "cfd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cfd_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_layout_alignment_and_disjoint_blocks():
+    dims = [(17, 5, 3), (64, 2, 2), (3, 9, 4)]
+    off, strides, total = B.layout(dims)
+    end = 0
+    for (ni, nj, nk), o, (sv, sk, sj, si) in zip(dims, off, strides):
+        assert si == 1 and sj >= ni + 4 and sj % 16 == 0
+        assert sk == sj * (nj + 4) and sv == sk * (nk + 4)
+        assert (o + 2) % 16 == 0            # interior i = 0 on 128 bytes
+        assert o >= end
+        end = o + 5 * sv
+    assert total >= end
+
+
+def test_workspace_size_positive():
+    c = cases.vortex_case(8)
+    ws = C.c_size_t()
+    st = B.lib().cfd_workspace_size(C.byref(B.to_params(c.params)), 1, B.to_dims(c.dims), C.byref(ws))
+    assert st == 0 and ws.value > 10 * 8 * 12 ** 3
+
+
+def _create(case, conns=None, bcs=None, params=None):
+    """Call cfd_create_blocks with tables only; node/workspace pointers are
+    placeholders that validation rejects before any device access."""
+    L = B.lib()
+    conns = case.conns if conns is None else conns
+    bcs = case.bcs if bcs is None else bcs
+    p = B.to_params(case.params if params is None else params)
+    fake = (C.c_void_p * case.nblk)(*([0x1000] * case.nblk))
+    ctx = C.c_void_p()
+    st = L.cfd_create_blocks(C.byref(p), case.nblk, B.to_dims(case.dims), fake, len(conns), B.to_conns(conns),
+                             len(bcs), B.to_bcs(bcs), None, C.c_size_t(0), None, C.byref(ctx))
+    return st, L.cfd_last_error(None).decode()
+
+
+def test_validation_rejects_double_cover():
+    c = cases.vortex_case(4)
+    extra = [cases.BC(0, 0, cases.FARFIELD, (0, 0), (1, 1))]
+    st, msg = _create(c, bcs=extra)
+    assert st == -1 and "covered twice" in msg
+
+
+def test_validation_rejects_uncovered_face():
+    c = cases.vortex_case(4)
+    st, msg = _create(c, conns=c.conns[:-1])
+    assert st == -1 and "not fully covered" in msg
+
+
+def test_validation_rejects_same_side_connection():
+    c = cases.vortex_case(4)
+    conns = list(c.conns)
+    a = conns[0]
+    conns[0] = cases.Conn(a.blk, a.face, a.nbr, a.face, a.lo, a.hi, a.nbr_lo, a.shift)
+    st, msg = _create(c, conns=conns)
+    assert st == -1 and "opposite faces" in msg
+
+
+def test_validation_rejects_out_of_range_patch_and_small_blocks():
+    c = cases.vortex_case(4)
+    bcs = [cases.BC(0, 0, cases.FARFIELD, (0, 0), (5, 4))]
+    st, msg = _create(c, conns=[x for x in c.conns if x.face != 0], bcs=bcs)
+    assert st == -1 and "outside face" in msg
+    d = cases.vortex_case(4)
+    d.dims[0] = (1, 4, 4)
+    st, msg = _create(d)
+    assert st == -1 and ">= 2" in msg
+
+
+def test_unsupported_ghost_layers():
+    c = cases.vortex_case(4)
+    p = cases.Params(ghost_layers=3)
+    st, msg = _create(c, params=p)
+    assert st == -6
+
+
+def test_status_strings():
+    L = B.lib()
+    for s in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert L.cfd_status_string(s)

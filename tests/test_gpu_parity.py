@@ -1,0 +1,171 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  FP64 results must agree to 1e-12 relative; copies are
+bitwise; the FP32-flux variant to 1e-5 relative L2 after the run."""
+import numpy as np
+import pytest
+
+from gpu_util import max_rel, oracle_residual, oracle_steps, rel_l2, say, small_cases
+from oracle import geometry as ogeo
+from oracle import solver as osol
+from paper_1710_09995_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+CASES = small_cases()
+G = 2
+
+
+def _solver(case, **tun):
+    from paper_1710_09995_amd.binding import Solver
+    return Solver(case, tuning=tun or None)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_metrics_parity(name):
+    case = CASES[name]
+    say("metrics", name)
+    s = _solver(case)
+    _, Ss, Vs = ogeo.build_metrics(case, G)
+    for b in range(case.nblk):
+        m = s.metrics(b)
+        S = Ss[b].reshape(9, *Ss[b].shape[2:])
+        scale = np.max(np.abs(S))
+        assert np.max(np.abs(m[:9] - S)) <= 4e-15 * scale, (name, b)
+        assert np.max(np.abs(m[9] - Vs[b]) / np.abs(Vs[b])) <= 1e-13, (name, b)
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_ghost_fill_parity(name):
+    case = CASES[name]
+    say("ghosts", name)
+    s = _solver(case)
+    s.fill_ghosts()
+    got = [v.cpu().numpy() for v in s.views()]
+    st = osol.setup(case)
+    osol.fill(st)
+    for b in range(case.nblk):
+        want = st.Qs[b]
+        assert not np.isnan(got[b]).any(), (name, b)
+        scale = np.maximum(np.max(np.abs(want), axis=(1, 2, 3)), 1.0)[:, None, None, None]
+        err = np.max(np.abs(got[b] - want) / scale)
+        # connection copies are exact; computed wall / far-field states differ by rounding only
+        assert err <= 1e-14, (name, b, err)
+        if not case.bcs:
+            assert np.array_equal(got[b], want)
+    s.close()
+
+
+@pytest.mark.parametrize("kernel", [1])
+@pytest.mark.parametrize("name", list(CASES))
+def test_residual_parity(name, kernel):
+    case = CASES[name]
+    say("residual", name, kernel)
+    s = _solver(case, kernel=kernel)
+    r = s.residual()
+    got = [v.cpu().numpy() for v in s.interior_views(r)]
+    want = oracle_residual(case)
+    assert rel_l2(got, want) <= 1e-12
+    assert max_rel(got, want) <= 1e-11
+    s.close()
+
+
+@pytest.mark.parametrize("name,nsteps", [("vortex16", 20), ("vortex_curv", 8), ("bump_ns", 6),
+                                         ("batched", 5), ("channel_local", 8)])
+def test_step_parity_fp64(name, nsteps):
+    case = CASES[name]
+    say("steps", name, nsteps)
+    s = _solver(case)
+    h = s.step(nsteps).cpu().numpy()
+    got = s.state()
+    want, rows = oracle_steps(case, nsteps)
+    err = rel_l2(got, want)
+    say("  rel L2", err)
+    assert err <= 1e-12
+    rows = np.array(rows)
+    assert np.max(np.abs(h[:, 0] - rows[:, 0]) / rows[:, 0]) <= 1e-13            # dt
+    l2_scale = np.abs(rows[:, 1:6]).max(axis=1, keepdims=True)    # a component may be exactly 0
+    assert np.max(np.abs(h[:, 1:6] - rows[:, 1:6]) / l2_scale) <= 1e-11               # L2(R)
+    tot_scale = np.abs(rows[:, 6:11]).max(axis=0) + np.abs(rows[:, 6:11]).max()
+    assert np.max(np.abs(h[:, 6:11] - rows[:, 6:11]) / tot_scale) <= 1e-13      # totals
+    s.close()
+
+
+@pytest.mark.parametrize("name,nsteps", [("vortex16", 10), ("bump_ns", 4), ("batched", 4)])
+def test_step_parity_fp32_flux(name, nsteps):
+    case = CASES[name].with_params(flux_fp32=1)
+    say("fp32 steps", name)
+    s = _solver(case)
+    s.step(nsteps)
+    got = s.state()
+    want, _ = oracle_steps(CASES[name], nsteps)
+    err = rel_l2(got, want)
+    dq = rel_l2([g - q0 for g, q0 in zip(got, case.q0)], [w - q0 for w, q0 in zip(want, case.q0)])
+    say("  fp32 rel L2", err, "rel L2 of dQ", dq)
+    assert err <= 1e-5
+    s.close()
+
+
+def test_graph_eager_tiles_bitwise():
+    case = CASES["bump_ns"]
+    say("graph/eager/tiles")
+    outs = []
+    for tun in ({"use_graph": 1}, {"use_graph": 0}, {"use_graph": 1, "tile_j": 1, "tile_k": 3},
+                {"use_graph": 0, "tile_j": 16, "tile_k": 64}):
+        s = _solver(case, **tun)
+        s.step(3)
+        outs.append(s.state())
+        s.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
+def test_run_to_run_bitwise():
+    case = CASES["batched"]
+    res = []
+    for _ in range(2):
+        s = _solver(case)
+        h = s.step(3).cpu().numpy()
+        res.append((s.state(), h))
+        s.close()
+    for a, b in zip(res[0][0], res[1][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(res[0][1], res[1][1])
+
+
+def test_conservation_periodic_gpu():
+    case = cases.vortex_case(24, seed=5, curvilinear=True)
+    s = _solver(case)
+    t0 = s.norms()[5:10]
+    s.step(30)
+    t1 = s.norms()[5:10]
+    scale = np.abs(t0).max()
+    assert np.max(np.abs(t1 - t0)) <= 1e-13 * scale
+    s.close()
+
+
+def test_nonfinite_detected():
+    from paper_1710_09995_amd.binding import CfdError
+    case = CASES["vortex16"]
+    s = _solver(case)
+    v = s.interior_views()[0]
+    v[0, 3, 4, 5] = float("nan")
+    with pytest.raises(CfdError) as e:
+        s.norms()
+    assert e.value.status == -4
+    s.close()
+
+
+def test_norms_match_fsum():
+    case = CASES["batched"]
+    s = _solver(case)
+    r = s.residual()
+    out = s.norms(r=r)
+    st = osol.setup(case)
+    Rs = osol.residual(st)
+    want = osol.norms_from(st, st.Qs, Rs)
+    assert np.max(np.abs(out[:5] - want[:5]) / np.abs(want[:5])) <= 1e-11
+    assert np.max(np.abs(out[5:10] - want[5:10]) / np.abs(want[5:10]).max()) <= 1e-13
+    assert abs(out[10] - want[10]) <= 1e-11 * want[10]
+    s.close()
