@@ -19,10 +19,12 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcfd.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["runtime.hip", "kernels_grid.hip", "kernels_stage.hip"]
+SOURCES = ["runtime.hip", "kernels_grid.hip", "kernels_stage.hip", "kernels_tiled.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+# -ffp-contract=on: a*b+c is fused only within one source expression, so a face
+# flux evaluated by different kernels / tile shapes gets the same bits.
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
          "-Wno-unused-command-line-argument"]

@@ -12,143 +12,18 @@
 // launch covers all blocks of uneven sizes.  Reductions go wave64 butterfly
 // -> LDS in fixed order -> one partial row per workgroup -> a single-workgroup
 // finalize in fixed order, so results are bitwise reproducible.
+//
+// This file holds the simple per-cell kernel (every face read from global
+// memory and computed by both of its cells); the tiled face-once kernel is in
+// kernels_tiled.hip.
 #include <hip/hip_runtime.h>
 #include "cfd_internal.hpp"
 #include "physics.hpp"
+#include "stage_common.hpp"
 
 namespace cfd {
 
-// ------------------------------------------------------------------ helpers
-
-template <typename T>
-__device__ __forceinline__ Prim<T> ld_prim(const double* __restrict__ qb, int64_t o, int64_t sv,
-                                           T gm1) {
-  return to_prim<T>(qb[o], qb[o + sv], qb[o + 2 * sv], qb[o + 3 * sv], qb[o + 4 * sv], gm1);
-}
-
-template <typename T>
-__device__ __forceinline__ void ld_phi(const double* __restrict__ qb, int64_t o, int64_t sv, T gm1,
-                                       T phi[4]) {
-  Prim<T> W = ld_prim<T>(qb, o, sv, gm1);
-  phi[0] = W.u;
-  phi[1] = W.v;
-  phi[2] = W.w;
-  phi[3] = W.p / W.r;
-}
-
-__device__ __forceinline__ int64_t dstride(int d, int64_t sj, int64_t sk) {
-  return d == 0 ? 1 : (d == 1 ? sj : sk);
-}
-
-// (F_inv - F_vis) . S on the lower d-face of the cell at offset c (relative to
-// the block's padded origin), read straight from global memory.
-template <typename T, bool VISC>
-__device__ __forceinline__ void face_flux_global(const double* __restrict__ qb,
-                                                 const double* __restrict__ mb, const BlockDesc& B,
-                                                 int64_t c, int d, const Gas<T>& gas,
-                                                 double F[5]) {
-  const int64_t sd = dstride(d, B.sj, B.sk);
-  const int64_t sv = B.sv;
-  Prim<T> wm2 = ld_prim<T>(qb, c - 2 * sd, sv, gas.gm1);
-  Prim<T> wm1 = ld_prim<T>(qb, c - sd, sv, gas.gm1);
-  Prim<T> w0 = ld_prim<T>(qb, c, sv, gas.gm1);
-  Prim<T> wp1 = ld_prim<T>(qb, c + sd, sv, gas.gm1);
-  Prim<T> L, R;
-  muscl(wm2, wm1, w0, wp1, gas.eps_lim, L, R);
-  const double sx = mb[(3 * d) * sv + c], sy = mb[(3 * d + 1) * sv + c], sz = mb[(3 * d + 2) * sv + c];
-  const double area = sqrt(sx * sx + sy * sy + sz * sz);
-  const double ia = 1.0 / area;
-  const T nx = (T)(sx * ia), ny = (T)(sy * ia), nz = (T)(sz * ia);
-  T f[5];
-  roe<T>(L, R, nx, ny, nz, gas.gamma, gas.eps_h, f);
-  if (VISC) {
-    const int64_t cl = c - sd;
-    T pl[4], pr[4];
-    pl[0] = wm1.u; pl[1] = wm1.v; pl[2] = wm1.w; pl[3] = wm1.p / wm1.r;
-    pr[0] = w0.u; pr[1] = w0.v; pr[2] = w0.w; pr[3] = w0.p / w0.r;
-    T dd[2][4];
-    double St[2][3];
-    int tt = 0;
-    for (int t = 0; t < 3; ++t) {
-      if (t == d) continue;
-      const int64_t st = dstride(t, B.sj, B.sk);
-      T a[4], b[4], e[4], f4[4];
-      ld_phi<T>(qb, cl + st, sv, gas.gm1, a);
-      ld_phi<T>(qb, c + st, sv, gas.gm1, b);
-      ld_phi<T>(qb, cl - st, sv, gas.gm1, e);
-      ld_phi<T>(qb, c - st, sv, gas.gm1, f4);
-      for (int q = 0; q < 4; ++q) dd[tt][q] = T(0.25) * (a[q] + b[q] - e[q] - f4[q]);
-      for (int x = 0; x < 3; ++x) {
-        const int64_t mo = (int64_t)(3 * t + x) * sv;
-        St[tt][x] = 0.25 * (mb[mo + cl] + mb[mo + cl + st] + mb[mo + c] + mb[mo + c + st]);
-      }
-      ++tt;
-    }
-    const double vf = 0.5 * (mb[9 * sv + cl] + mb[9 * sv + c]);
-    const double iv = 1.0 / vf;
-    const T sdx = (T)(sx * iv), sdy = (T)(sy * iv), sdz = (T)(sz * iv);
-    const T s1x = (T)(St[0][0] * iv), s1y = (T)(St[0][1] * iv), s1z = (T)(St[0][2] * iv);
-    const T s2x = (T)(St[1][0] * iv), s2y = (T)(St[1][1] * iv), s2z = (T)(St[1][2] * iv);
-    T g[4][3];
-    for (int q = 0; q < 4; ++q) {
-      const T dq = pr[q] - pl[q];
-      g[q][0] = dq * sdx + dd[0][q] * s1x + dd[1][q] * s2x;
-      g[q][1] = dq * sdy + dd[0][q] * s1y + dd[1][q] * s2y;
-      g[q][2] = dq * sdz + dd[0][q] * s1z + dd[1][q] * s2z;
-    }
-    T uf[3] = {T(0.5) * (pl[0] + pr[0]), T(0.5) * (pl[1] + pr[1]), T(0.5) * (pl[2] + pr[2])};
-    const T tf = T(0.5) * (pl[3] + pr[3]);
-    T fv[5];
-    viscous_n<T>(g, uf, tf, nx, ny, nz, gas, fv);
-    for (int q = 0; q < 5; ++q) f[q] -= fv[q];
-  }
-  for (int q = 0; q < 5; ++q) F[q] = (double)f[q] * area;
-}
-
-// Fixed-order workgroup reduction of NPART partials; thread 0 writes the row.
-// op: sums for [0,10), max for 10, sum for 11 (count), min for 12.
-__device__ __forceinline__ void wg_reduce_partials(double acc[NPART], double* __restrict__ out_row) {
-  __shared__ double red[NPART][16];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int nwave = (blockDim.x + 63) >> 6;
-#pragma unroll
-  for (int q = 0; q < NPART; ++q) {
-    double v = acc[q];
-    for (int off = 32; off > 0; off >>= 1) {
-      double o = __shfl_xor(v, off, 64);
-      if (q == 10) v = fmax(v, o);
-      else if (q == 12) v = fmin(v, o);
-      else v = v + o;
-    }
-    if (lane == 0) red[q][wave] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 0; q < NPART; ++q) {
-      double v = red[q][0];
-      for (int w = 1; w < nwave; ++w) {
-        if (q == 10) v = fmax(v, red[q][w]);
-        else if (q == 12) v = fmin(v, red[q][w]);
-        else v = v + red[q][w];
-      }
-      out_row[q] = v;
-    }
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ void init_partials(double acc[NPART]) {
-#pragma unroll
-  for (int q = 0; q < NPART; ++q) acc[q] = 0.0;
-  acc[12] = __builtin_inf();
-}
-
-__device__ __forceinline__ bool finite(double x) { return !(isnan(x) || isinf(x)); }
-
 // ------------------------------------------------- simple per-cell stage kernel
-// MODE 0: write R; MODE 1: stage 1 (+ norm partials of R(Qn), V Qn);
-// MODE 2: stages 2-3 with coefficients (a, b).
 template <typename T, bool VISC, int MODE>
 __global__ void __launch_bounds__(256) k_stage_simple(StageArgs A, const BlockDesc* __restrict__ blocks,
                                                       const TileDesc* __restrict__ tiles, Gas<T> gas) {
@@ -173,30 +48,7 @@ __global__ void __launch_bounds__(256) k_stage_simple(StageArgs A, const BlockDe
           face_flux_global<T, VISC>(qb, mb, B, c + dstride(d, B.sj, B.sk), d, gas, Fu);
           for (int q = 0; q < 5; ++q) D[d][q] = Fu[q] - Fl[q];
         }
-        const double vol = mb[9 * B.sv + c];
-        double R[5];
-        for (int q = 0; q < 5; ++q) R[q] = ((D[0][q] + D[1][q]) + D[2][q]) / vol;
-        if (MODE == 0) {
-          for (int q = 0; q < 5; ++q) A.out[B.qoff + q * B.sv + c] = R[q];
-          continue;
-        }
-        const double dt = A.local_dt ? A.dt[B.soff + c] : A.dt[0];
-        if (MODE == 1) {
-          for (int q = 0; q < 5; ++q) {
-            const double qv = qb[q * B.sv + c];
-            A.out[B.qoff + q * B.sv + c] = qv - dt * R[q];
-            acc[q] += R[q] * R[q];
-            acc[5 + q] += vol * qv;
-            if (!finite(qv) || !finite(R[q])) acc[11] += 1.0;
-          }
-          acc[10] = fmax(acc[10], fabs(R[0]));
-        } else {
-          const double* qnb = A.qn + B.qoff;
-          for (int q = 0; q < 5; ++q) {
-            const double qv = qb[q * B.sv + c];
-            A.out[B.qoff + q * B.sv + c] = A.a * qnb[q * B.sv + c] + A.b * (qv - dt * R[q]);
-          }
-        }
+        finish_cell<MODE>(A, B, c, D[0], D[1], D[2], mb[9 * B.sv + c], acc);
       }
     }
   }

@@ -13,6 +13,7 @@
 #include <exception>
 #include <stdexcept>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/cfd.h"
@@ -27,6 +28,9 @@ void launch_metric_ghosts(double* met, const BlockDesc* blocks, const PatchDesc*
                           int maxcount, hipStream_t s);
 void launch_ghost_q(double* q, const double* met, const BlockDesc* blocks, const PatchDesc* patches,
                     int npatch, int maxcount, const StepParams& SP, hipStream_t s);
+bool stage_tiled(const StageArgs& A, int mode, bool visc, bool fp32, const BlockDesc* blocks,
+                 const TileDesc* tiles, const Gas<double>& g64, const Gas<float>& g32, int nwg,
+                 hipStream_t s, int* occ);
 void launch_stage_simple(const StageArgs& A, int mode, bool visc, bool fp32, const BlockDesc* blocks,
                          const TileDesc* tiles, const Gas<double>& g64, const Gas<float>& g32, int nwg,
                          hipStream_t s);
@@ -294,7 +298,7 @@ struct cfd_ctx {
   TileDesc* dtiles = nullptr;
   int ntiles = 0;
   int64_t ncells = 0;
-  cfd_tuning tun{1, 4, 16, 1};
+  cfd_tuning tun{0, 4, 32, 1};
   StepParams SP{};
   Gas<double> g64{};
   Gas<float> g32{};
@@ -302,6 +306,8 @@ struct cfd_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   const void* graph_q = nullptr;
+  int num_cu = 256;
+  std::map<int, int> occ_cache;
   std::string last_error;
   // kernel timing (eager steps only)
   struct EvPair {
@@ -454,20 +460,44 @@ StageArgs stage_args(cfd_ctx* c) {
   return A;
 }
 
-int stage_nwg(cfd_ctx* c) {
-  return nwg_for(c, 8);
+// Persistent grid of the stage kernel: resident workgroups per CU (occupancy
+// query, cached per variant) times the CU count, capped by the tile count.
+int stage_nwg(cfd_ctx* c, int mode) {
+  if (c->tun.kernel != 0) return nwg_for(c, 8);
+  const int key = (c->params.viscous ? 1 : 0) | (c->params.flux_fp32 ? 2 : 0) | (mode << 2) |
+                  ((c->tun.tile_j == 2 ? 0 : c->tun.tile_j == 4 ? 1 : 2) << 4);
+  auto it = c->occ_cache.find(key);
+  int occ;
+  if (it != c->occ_cache.end()) {
+    occ = it->second;
+  } else {
+    StageArgs A{};
+    A.tile_j = c->tun.tile_j;
+    if (!stage_tiled(A, mode, c->params.viscous != 0, c->params.flux_fp32 != 0, nullptr, nullptr, c->g64,
+                     c->g32, 0, nullptr, &occ))
+      fail(CFD_EINVAL, "tiled kernel has no variant for tile_j = %d", c->tun.tile_j);
+    c->occ_cache[key] = occ;
+  }
+  return std::max(1, std::min({c->ntiles, NWG_MAX, occ * c->num_cu}));
 }
 
-void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, int nwg, hipStream_t s) {
+void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, hipStream_t s) {
   const bool visc = c->params.viscous != 0, fp32 = c->params.flux_fp32 != 0;
-  if (c->tun.kernel != 1) fail(CFD_EUNSUPPORTED, "stage kernel %d not available", c->tun.kernel);
-  timed(c, 0, s, [&] { launch_stage_simple(A, mode, visc, fp32, c->dblocks, c->dtiles, c->g64, c->g32, nwg, s); });
+  const int nwg = stage_nwg(c, mode);
+  if (c->tun.kernel == 0) {
+    timed(c, 0, s, [&] {
+      if (!stage_tiled(A, mode, visc, fp32, c->dblocks, c->dtiles, c->g64, c->g32, nwg, s, nullptr))
+        fail(CFD_EINVAL, "tiled kernel has no variant for tile_j = %d", c->tun.tile_j);
+    });
+  } else {
+    timed(c, 0, s, [&] { launch_stage_simple(A, mode, visc, fp32, c->dblocks, c->dtiles, c->g64, c->g32, nwg, s); });
+  }
 }
 
 // One full RK3 step: ghost fill + dt + 3 x (ghost fill + stage) + finalize.
 void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
   const int nwg_dt = nwg_for(c, 8);
-  const int nwg = stage_nwg(c);
+  const int nwg1 = stage_nwg(c, 1);   // rows of the stage-1 norm partials
   ghost_fill(c, q, s);
   timed(c, 2, s, [&] {
     launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
@@ -478,20 +508,20 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
   A.qs = q;
   A.qn = q;
   A.out = c->qa();
-  launch_stage(c, A, 1, nwg, s);
+  launch_stage(c, A, 1, s);
   ghost_fill(c, c->qa(), s);
   A.qs = c->qa();
   A.out = c->qb();
   A.a = 0.75;
   A.b = 0.25;
-  launch_stage(c, A, 2, nwg, s);
+  launch_stage(c, A, 2, s);
   ghost_fill(c, c->qb(), s);
   A.qs = c->qb();
   A.out = q;
   A.a = 1.0 / 3.0;
   A.b = 2.0 / 3.0;
-  launch_stage(c, A, 2, nwg, s);
-  launch_finalize(c->part_nrm(), nwg, 1, 1.0 / (double)c->ncells, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
+  launch_stage(c, A, 2, s);
+  launch_finalize(c->part_nrm(), nwg1, 1, 1.0 / (double)c->ncells, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
 }
 
 template <typename F>
@@ -622,6 +652,11 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
       c->pmax[sweep] = mx;
     }
     HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    {
+      int dev = 0;
+      HIPCHK(hipGetDevice(&dev));
+      HIPCHK(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    }
     HIPCHK(hipMemcpyAsync(c->dblocks, c->hblocks.data(), sizeof(BlockDesc) * nblk, hipMemcpyHostToDevice, stream));
     if (!all.empty())
       HIPCHK(hipMemcpyAsync(c->dpatches, all.data(), sizeof(PatchDesc) * all.size(), hipMemcpyHostToDevice, stream));
@@ -701,6 +736,8 @@ cfd_status cfd_set_tuning(cfd_ctx* c, const cfd_tuning* t) {
     if (t->tile_j < 1 || t->tile_j > 16 || (t->tile_j & (t->tile_j - 1)))
       fail(CFD_EINVAL, "tile_j must be a power of two in [1, 16]");
     if (t->tile_k < 1 || t->tile_k > 4096) fail(CFD_EINVAL, "tile_k must be in [1, 4096]");
+    if (t->kernel == 0 && t->tile_j != 2 && t->tile_j != 4 && t->tile_j != 8)
+      fail(CFD_EINVAL, "the tiled kernel takes tile_j = 2, 4 or 8");
     c->drop_graph();
     c->tun = *t;
     HIPCHK(hipDeviceSynchronize());
@@ -730,7 +767,7 @@ cfd_status cfd_residual(cfd_ctx* c, const double* q, double* r, hipStream_t s) {
     A.qs = q;
     A.qn = q;
     A.out = r;
-    launch_stage(c, A, 0, stage_nwg(c), s);
+    launch_stage(c, A, 0, s);
     check_launch();
   });
 }

@@ -1,0 +1,230 @@
+// Device code shared by the stage kernels: one face-flux function fed by
+// different gathers (straight from global memory, or from LDS planes), the
+// cell update of Eqs. (4)-(6) and the norm partials.
+//
+// Both stage kernels call face_core with bitwise identical inputs (the same
+// primitives from the same Q, the same metric loads, the same averaging
+// expressions), and the sources are built with -ffp-contract=on so the
+// contraction of each expression is fixed by the source: every face flux is
+// the same bits whichever kernel, tile shape or launch computed it.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "cfd_internal.hpp"
+#include "physics.hpp"
+
+namespace cfd {
+
+template <typename T>
+__device__ __forceinline__ Prim<T> ld_prim(const double* __restrict__ qb, int64_t o, int64_t sv, T gm1) {
+  return to_prim<T>(qb[o], qb[o + sv], qb[o + 2 * sv], qb[o + 3 * sv], qb[o + 4 * sv], gm1);
+}
+
+__device__ __forceinline__ int64_t dstride(int d, int64_t sj, int64_t sk) {
+  return d == 0 ? 1 : (d == 1 ? sj : sk);
+}
+
+// phi = (u, v, w, T) of a cell
+template <typename T>
+__device__ __forceinline__ void phi_of(const Prim<T>& W, T tc, T phi[4]) {
+  phi[0] = W.u;
+  phi[1] = W.v;
+  phi[2] = W.w;
+  phi[3] = tc;
+}
+
+template <typename T>
+__device__ __forceinline__ T temp_of(const Prim<T>& W) {
+  return W.p / W.r;
+}
+
+// transverse difference 1/4 (phi(L+e) + phi(R+e) - phi(L-e) - phi(R-e))
+template <typename T>
+__device__ __forceinline__ void tdiff(const T a[4], const T b[4], const T e[4], const T f[4], T out[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = T(0.25) * (a[q] + b[q] - e[q] - f[q]);
+}
+
+// Metric terms of the viscous face between cells cl (L) and c (R) in
+// direction d: averaged transverse face vectors (ascending transverse order)
+// and the auxiliary volume.
+__device__ __forceinline__ void visc_metrics(const double* __restrict__ mb, int64_t sv, int64_t cl, int64_t c,
+                                             int d, int64_t sj, int64_t sk, double St[2][3], double& vf) {
+  int tt = 0;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (t == d) continue;
+    const int64_t st = dstride(t, sj, sk);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      const int64_t mo = (int64_t)(3 * t + x) * sv;
+      St[tt][x] = 0.25 * (mb[mo + cl] + mb[mo + cl + st] + mb[mo + c] + mb[mo + c + st]);
+    }
+    ++tt;
+  }
+  vf = 0.5 * (mb[9 * sv + cl] + mb[9 * sv + c]);
+}
+
+// (F_inv - F_vis) . S through one face from gathered inputs.
+//  a, b, c, d: primitives of cells c-2, c-1 (L), c (R), c+1 along the face direction
+//  sx, sy, sz: the face vector; tl, tr: temperatures of L and R
+//  dt1, dt2: transverse differences of phi; St, vf: viscous metric terms
+template <typename T, bool VISC>
+__device__ __forceinline__ void face_core(const Prim<T>& a, const Prim<T>& b, const Prim<T>& c, const Prim<T>& d,
+                                          double sx, double sy, double sz, T tl, T tr, const T dt1[4],
+                                          const T dt2[4], const double St[2][3], double vf, const Gas<T>& gas,
+                                          double F[5]) {
+  Prim<T> L, R;
+  muscl(a, b, c, d, gas.eps_lim, L, R);
+  const double area = sqrt(sx * sx + sy * sy + sz * sz);
+  const double ia = 1.0 / area;
+  const T nx = (T)(sx * ia), ny = (T)(sy * ia), nz = (T)(sz * ia);
+  T f[5];
+  roe<T>(L, R, nx, ny, nz, gas.gamma, gas.eps_h, f);
+  if (VISC) {
+    T pl[4], pr[4];
+    phi_of(b, tl, pl);
+    phi_of(c, tr, pr);
+    const double iv = 1.0 / vf;
+    const T sdx = (T)(sx * iv), sdy = (T)(sy * iv), sdz = (T)(sz * iv);
+    const T s1x = (T)(St[0][0] * iv), s1y = (T)(St[0][1] * iv), s1z = (T)(St[0][2] * iv);
+    const T s2x = (T)(St[1][0] * iv), s2y = (T)(St[1][1] * iv), s2z = (T)(St[1][2] * iv);
+    T g[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T dq = pr[q] - pl[q];
+      g[q][0] = dq * sdx + dt1[q] * s1x + dt2[q] * s2x;
+      g[q][1] = dq * sdy + dt1[q] * s1y + dt2[q] * s2y;
+      g[q][2] = dq * sdz + dt1[q] * s1z + dt2[q] * s2z;
+    }
+    const T uf[3] = {T(0.5) * (pl[0] + pr[0]), T(0.5) * (pl[1] + pr[1]), T(0.5) * (pl[2] + pr[2])};
+    const T tf = T(0.5) * (pl[3] + pr[3]);
+    T fv[5];
+    viscous_n<T>(g, uf, tf, nx, ny, nz, gas, fv);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) f[q] -= fv[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) F[q] = (double)f[q] * area;
+}
+
+// Face flux on the lower d-face of cell c, every input read from global memory.
+template <typename T, bool VISC>
+__device__ __forceinline__ void face_flux_global(const double* __restrict__ qb, const double* __restrict__ mb,
+                                                 const BlockDesc& B, int64_t c, int d, const Gas<T>& gas,
+                                                 double F[5]) {
+  const int64_t sd = dstride(d, B.sj, B.sk);
+  const int64_t sv = B.sv;
+  const Prim<T> wm2 = ld_prim<T>(qb, c - 2 * sd, sv, gas.gm1);
+  const Prim<T> wm1 = ld_prim<T>(qb, c - sd, sv, gas.gm1);
+  const Prim<T> w0 = ld_prim<T>(qb, c, sv, gas.gm1);
+  const Prim<T> wp1 = ld_prim<T>(qb, c + sd, sv, gas.gm1);
+  const double sx = mb[(3 * d) * sv + c], sy = mb[(3 * d + 1) * sv + c], sz = mb[(3 * d + 2) * sv + c];
+  T dd[2][4] = {};
+  double St[2][3] = {};
+  double vf = 1.0;
+  T tl = T(0), tr = T(0);
+  if (VISC) {
+    const int64_t cl = c - sd;
+    tl = temp_of(wm1);
+    tr = temp_of(w0);
+    int tt = 0;
+    for (int t = 0; t < 3; ++t) {
+      if (t == d) continue;
+      const int64_t st = dstride(t, B.sj, B.sk);
+      T a[4], b[4], e[4], f[4];
+      Prim<T> W;
+      W = ld_prim<T>(qb, cl + st, sv, gas.gm1);
+      phi_of(W, temp_of(W), a);
+      W = ld_prim<T>(qb, c + st, sv, gas.gm1);
+      phi_of(W, temp_of(W), b);
+      W = ld_prim<T>(qb, cl - st, sv, gas.gm1);
+      phi_of(W, temp_of(W), e);
+      W = ld_prim<T>(qb, c - st, sv, gas.gm1);
+      phi_of(W, temp_of(W), f);
+      tdiff(a, b, e, f, dd[tt]);
+      ++tt;
+    }
+    visc_metrics(mb, sv, cl, c, d, B.sj, B.sk, St, vf);
+  }
+  face_core<T, VISC>(wm2, wm1, w0, wp1, sx, sy, sz, tl, tr, dd[0], dd[1], St, vf, gas, F);
+}
+
+__device__ __forceinline__ void init_partials(double acc[NPART]) {
+#pragma unroll
+  for (int q = 0; q < NPART; ++q) acc[q] = 0.0;
+  acc[12] = __builtin_inf();
+}
+
+__device__ __forceinline__ bool finite(double x) { return !(isnan(x) || isinf(x)); }
+
+// Finish one interior cell: R = ((Di + Dj) + Dk) / V, then write R (mode 0)
+// or the stage update (modes 1, 2) and accumulate norm partials (mode 1).
+template <int MODE>
+__device__ __forceinline__ void finish_cell(const StageArgs& A, const BlockDesc& B, int64_t c,
+                                            const double Di[5], const double Dj[5], const double Dk[5],
+                                            double vol, double acc[NPART]) {
+  double R[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) R[q] = ((Di[q] + Dj[q]) + Dk[q]) / vol;
+  if (MODE == 0) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) A.out[B.qoff + q * B.sv + c] = R[q];
+    return;
+  }
+  const double dt = A.local_dt ? A.dt[B.soff + c] : A.dt[0];
+  const double* qb = A.qs + B.qoff;
+  if (MODE == 1) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const double qv = qb[q * B.sv + c];
+      A.out[B.qoff + q * B.sv + c] = qv - dt * R[q];
+      acc[q] += R[q] * R[q];
+      acc[5 + q] += vol * qv;
+      if (!finite(qv) || !finite(R[q])) acc[11] += 1.0;
+    }
+    acc[10] = fmax(acc[10], fabs(R[0]));
+  } else {
+    const double* qnb = A.qn + B.qoff;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const double qv = qb[q * B.sv + c];
+      A.out[B.qoff + q * B.sv + c] = A.a * qnb[q * B.sv + c] + A.b * (qv - dt * R[q]);
+    }
+  }
+}
+
+// Fixed-order workgroup reduction of NPART partials; thread 0 writes the row.
+// Slots: sums for [0,10) and 11, max for 10, min for 12.
+__device__ __forceinline__ void wg_reduce_partials(double acc[NPART], double* __restrict__ out_row) {
+  __shared__ double red[NPART][16];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nwave = (blockDim.x + 63) >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NPART; ++q) {
+    double v = acc[q];
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v, off, 64);
+      if (q == 10) v = fmax(v, o);
+      else if (q == 12) v = fmin(v, o);
+      else v = v + o;
+    }
+    if (lane == 0) red[q][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < NPART; ++q) {
+      double v = red[q][0];
+      for (int w = 1; w < nwave; ++w) {
+        if (q == 10) v = fmax(v, red[q][w]);
+        else if (q == 12) v = fmin(v, red[q][w]);
+        else v = v + red[q][w];
+      }
+      out_row[q] = v;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace cfd

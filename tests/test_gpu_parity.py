@@ -56,7 +56,7 @@ def test_ghost_fill_parity(name):
     s.close()
 
 
-@pytest.mark.parametrize("kernel", [1])
+@pytest.mark.parametrize("kernel", [0, 1])
 @pytest.mark.parametrize("name", list(CASES))
 def test_residual_parity(name, kernel):
     case = CASES[name]
@@ -106,19 +106,26 @@ def test_step_parity_fp32_flux(name, nsteps):
     s.close()
 
 
-def test_graph_eager_tiles_bitwise():
-    case = CASES["bump_ns"]
-    say("graph/eager/tiles")
+TUNINGS = ({"kernel": 0, "use_graph": 1}, {"kernel": 0, "use_graph": 0},
+           {"kernel": 0, "tile_j": 2, "tile_k": 3}, {"kernel": 0, "tile_j": 8, "tile_k": 64},
+           {"kernel": 1, "tile_j": 1, "tile_k": 3}, {"kernel": 1, "tile_j": 16, "tile_k": 64})
+
+
+@pytest.mark.parametrize("name", ["bump_ns", "batched", "vortex_curv"])
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_graph_eager_tiles_kernels_bitwise(name, fp32):
+    """Graph vs eager, every tile shape and both stage kernels give the same bits."""
+    case = CASES[name].with_params(flux_fp32=fp32)
+    say("graph/eager/tiles/kernels", name, fp32)
     outs = []
-    for tun in ({"use_graph": 1}, {"use_graph": 0}, {"use_graph": 1, "tile_j": 1, "tile_k": 3},
-                {"use_graph": 0, "tile_j": 16, "tile_k": 64}):
+    for tun in TUNINGS:
         s = _solver(case, **tun)
         s.step(3)
         outs.append(s.state())
         s.close()
-    for o in outs[1:]:
+    for t, o in zip(TUNINGS[1:], outs[1:]):
         for a, b in zip(outs[0], o):
-            assert np.array_equal(a, b)
+            assert np.array_equal(a, b), t
 
 
 def test_run_to_run_bitwise():
