@@ -129,10 +129,24 @@ def main(argv=None):
     ap.add_argument("--tile-j", type=int, default=None)
     ap.add_argument("--tile-k", type=int, default=None)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--order", type=int, default=None, choices=[0, 1], help="tile order (1 = XCD-aware)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the tile autotuner (library defaults)")
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (HBM counter calibration) and exit")
     a = ap.parse_args(argv)
+    if a.calibrate_copy:
+        import torch
+        n = a.calibrate_copy * (1 << 20) // 8
+        src = torch.rand(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 8, "copies": 5}), flush=True)
+        return 0
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(sharding across GPUs is a design note, not code); use --gpus 1.", file=sys.stderr)
@@ -155,8 +169,17 @@ def main(argv=None):
         tun["tile_k"] = a.tile_k
     if a.no_graph:
         tun["use_graph"] = 0
+    if a.order is not None:
+        tun["order"] = a.order
+    tune_info = None
     if tun:
         s.set_tuning(**tun)
+    elif not a.no_tune:
+        from paper_1710_09995_amd.autotune import autotune
+        res = autotune(s, log=lambda m: print(m, file=sys.stderr, flush=True))
+        tune_info = {"cached": res["cached"], "ms_per_step_tuning": round(res["ms_per_step"], 4),
+                     "candidates": len(res["table"])}
+        print(f"# tuned: {res['tuning']} ({res['ms_per_step']:.3f} ms/step)", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
     s.step(a.warmup, hist=False)
     torch.cuda.synchronize()
@@ -216,7 +239,7 @@ def main(argv=None):
         "data": "synthetic (seeded grid, state and noise)",
         "config": {"workload": label, "blocks": case.nblk, "cells": case.ncells,
                    "viscous": bool(case.params.viscous), "flux": a.flux, "stages_per_step": 3,
-                   "tuning": tune, "finite": finite},
+                   "tuning": tune, "autotune": tune_info, "finite": finite},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -96,9 +96,15 @@ typedef struct {
 /* Tuning knobs of the stage kernels.  Any value changes speed only, never
  * results (results are bitwise identical across all valid settings).
  * kernel: 0 = tiled face-once kernel (default), 1 = simple per-cell kernel.
- * tile_j, tile_k: tile extent in j and k (tile_i is 64, one wavefront).
- * use_graph: 1 captures one time step in a hipGraph and replays it. */
-typedef struct { int32_t kernel, tile_j, tile_k, use_graph; } cfd_tuning;
+ * tile_j, tile_k: tile extent in j and k (tile_i is 64, one wavefront);
+ *   the tiled kernel takes tile_j = 2, 4 or 8.
+ * use_graph: 1 captures one time step in a hipGraph and replays it.
+ * order: tile work-list order.  0 = largest tiles first (balances uneven
+ *   blocks); 1 = XCD-aware: the tiles are cut into 8 spatially contiguous
+ *   chunks and interleaved so that every workgroup of the persistent grid on
+ *   one XCD (workgroup id mod 8) works inside one chunk, keeping halo reuse in
+ *   that XCD's L2. */
+typedef struct { int32_t kernel, tile_j, tile_k, use_graph, order; } cfd_tuning;
 
 /* Arena layout for `nblk` blocks: block_offset[b] = element index of padded
  * cell (i,j,k) = (-g,-g,-g), var 0; block_strides[4*b + 0..3] = element
@@ -125,7 +131,7 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
 
 cfd_status cfd_destroy(cfd_ctx* ctx);
 
-/* Replace the tuning knobs (default {0, 4, 16, 1}).  Drops cached graphs. */
+/* Replace the tuning knobs (default {0, 4, 32, 1, 1}).  Drops cached graphs. */
 cfd_status cfd_set_tuning(cfd_ctx* ctx, const cfd_tuning* tuning);
 cfd_status cfd_get_tuning(const cfd_ctx* ctx, cfd_tuning* tuning);
 

@@ -14,7 +14,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(HERE, "libcfd.so")
+LIBPATH = os.environ.get("CFD_LIB", os.path.join(HERE, "libcfd.so"))
 NG = 2
 
 CFD_OK = 0
@@ -46,7 +46,7 @@ class ParamsS(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("tile_j", C.c_int32), ("tile_k", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("order", C.c_int32)]
 
 
 EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy", "cfd_set_tuning",
@@ -217,10 +217,11 @@ class Solver:
         except Exception:
             pass
 
-    def set_tuning(self, kernel=None, tile_j=None, tile_k=None, use_graph=None):
+    def set_tuning(self, kernel=None, tile_j=None, tile_k=None, use_graph=None, order=None):
         t = Tuning()
         _check(lib().cfd_get_tuning(self.ctx, C.byref(t)), self.ctx)
-        for name, v in (("kernel", kernel), ("tile_j", tile_j), ("tile_k", tile_k), ("use_graph", use_graph)):
+        for name, v in (("kernel", kernel), ("tile_j", tile_j), ("tile_k", tile_k), ("use_graph", use_graph),
+                        ("order", order)):
             if v is not None:
                 setattr(t, name, int(v))
         _check(lib().cfd_set_tuning(self.ctx, C.byref(t)), self.ctx)

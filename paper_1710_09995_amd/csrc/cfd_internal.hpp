@@ -48,7 +48,14 @@ struct TileDesc {
 template <typename T>
 struct Gas {
   T gamma, gm1, prandtl, mu_inf, s_star, eps_h, eps_lim;
+  T kfac;   // gamma / ((gamma - 1) Pr): conductivity over viscosity
   T uinf[3];
+};
+
+struct StepParams {
+  double gamma, prandtl, mu_inf, s_star, cfl, eps_h, eps_lim;
+  double uinf[3];
+  int32_t viscous, flux_fp32, local_dt, pad0;
 };
 
 // Arguments of the residual / stage kernels.
@@ -67,10 +74,5 @@ struct StageArgs {
   int32_t tile_j, tile_k;
 };
 
-struct StepParams {
-  double gamma, prandtl, mu_inf, s_star, cfl, eps_h, eps_lim;
-  double uinf[3];
-  int32_t viscous, flux_fp32, local_dt, pad0;
-};
 
 }  // namespace cfd

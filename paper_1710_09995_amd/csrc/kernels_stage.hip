@@ -67,8 +67,6 @@ __global__ void __launch_bounds__(256) k_dt(const double* __restrict__ q, const 
   init_partials(acc);
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int nty = blockDim.x >> 6;
-  const double gm1 = P.gamma - 1.0;
-  const double coefv = fmax(4.0 / 3.0, P.gamma / P.prandtl);
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const TileDesc td = tiles[tile];
     const BlockDesc B = blocks[td.blk];
@@ -79,28 +77,8 @@ __global__ void __launch_bounds__(256) k_dt(const double* __restrict__ q, const 
     for (int j = td.j0 + ty; j < min(td.j0 + tile_j, B.n[1]); j += nty) {
       for (int k = td.k0; k < min(td.k0 + tile_k, B.n[2]); ++k) {
         const int64_t c = (int64_t)(k + NG) * B.sk + (int64_t)(j + NG) * B.sj + (i + NG);
-        const double r = qb[c];
-        const double inv = 1.0 / r;
-        const double u = qb[B.sv + c] * inv, v = qb[2 * B.sv + c] * inv, w = qb[3 * B.sv + c] * inv;
-        const double p = gm1 * (qb[4 * B.sv + c] - 0.5 * r * (u * u + v * v + w * w));
-        const double cs = sqrt(P.gamma * p / r);
-        const double vol = mb[9 * B.sv + c];
-        double lam = 0.0, lamv = 0.0;
-        double mu_r = 0.0;
-        if (P.viscous) {
-          const double t = p / r;
-          mu_r = P.mu_inf * t * sqrt(t) * (1.0 + P.s_star) / (t + P.s_star) / r;
-        }
-        for (int d = 0; d < 3; ++d) {
-          const int64_t sd = dstride(d, B.sj, B.sk);
-          const double bx = 0.5 * (mb[(3 * d) * B.sv + c] + mb[(3 * d) * B.sv + c + sd]);
-          const double by = 0.5 * (mb[(3 * d + 1) * B.sv + c] + mb[(3 * d + 1) * B.sv + c + sd]);
-          const double bz = 0.5 * (mb[(3 * d + 2) * B.sv + c] + mb[(3 * d + 2) * B.sv + c + sd]);
-          const double mag = sqrt(bx * bx + by * by + bz * bz);
-          lam += fabs(u * bx + v * by + w * bz) + cs * mag;
-          if (P.viscous) lamv += coefv * mu_r * mag * mag / vol;
-        }
-        const double dtc = P.cfl * vol / (lam + 4.0 * lamv);
+        const double qc[5] = {qb[c], qb[B.sv + c], qb[2 * B.sv + c], qb[3 * B.sv + c], qb[4 * B.sv + c]};
+        const double dtc = cell_dt(qc, mb, c, B.sv, B.sj, B.sk, P);
         if (P.local_dt) dtcell[B.soff + c] = dtc;
         acc[12] = fmin(acc[12], dtc);
       }

@@ -8,17 +8,37 @@
 //   2. each thread computes the lower i-face and lower j-face of its column
 //      from LDS and the upper k-face from a register queue of its own column
 //      (W at k-1 .. k+2); the faces on the tile's high i and j edges are
-//      spread over two waves; every face is computed exactly once per tile;
-//   3. fluxes are exchanged through LDS (aliasing the primitive plane) and
-//      every interior cell forms R = ((Di + Dj) + Dk) / V and its stage update.
+//      spread over the first waves; every face is computed once per tile and
+//      its flux goes straight to an LDS exchange buffer;
+//   3. every interior cell forms R = ((Di + Dj) + Dk) / V and its stage update.
 // Metrics are read from global memory (cached; each is used by several faces).
 // The first k-face of a tile comes from the global-memory gather, which feeds
-// the same face_core with the same bits, so results do not depend on the tile
-// shape or on which kernel computed them.
+// face_inviscid / face_viscous the same bits in the same order, so results do
+// not depend on the tile shape or on which kernel computed them.
 #include <hip/hip_runtime.h>
 #include "cfd_internal.hpp"
 #include "physics.hpp"
 #include "stage_common.hpp"
+
+// Scheduling fence between face computations: keeps the compiler from
+// hoisting one face's loads into another's live range (register pressure).
+#ifndef CFD_SCHED_FENCE
+#define CFD_SCHED_FENCE 1
+#endif
+#if CFD_SCHED_FENCE
+#define CFD_FACE_FENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define CFD_FACE_FENCE() ((void)0)
+#endif
+// Minimum waves per SIMD requested from the register allocator (0 = none).
+#ifndef CFD_MIN_WAVES
+#define CFD_MIN_WAVES 0
+#endif
+#if CFD_MIN_WAVES > 0
+#define CFD_TILED_BOUNDS(n) __launch_bounds__(n, CFD_MIN_WAVES)
+#else
+#define CFD_TILED_BOUNDS(n) __launch_bounds__(n)
+#endif
 
 namespace cfd {
 
@@ -27,28 +47,27 @@ struct TiledLds {
   static constexpr int WI = 68, WJ = TJ + 4;   // primitive plane, halo 2
   static constexpr int PI = 66, PJ = TJ + 2;   // phi planes, halo 1
   static constexpr int NW = VISC ? 6 : 5;
-  static constexpr int W_BYTES = NW * WJ * WI * (int)sizeof(T);
+  static constexpr int W_BYTES = (NW * WJ * WI * (int)sizeof(T) + 15) / 16 * 16;
   static constexpr int FI = 5 * TJ * 65;        // doubles: lower i-faces, 65 per row
   static constexpr int FJ = 5 * (TJ + 1) * 64;  // doubles: lower j-faces, TJ+1 rows
   static constexpr int F_BYTES = (FI + FJ) * 8;
-  static constexpr int A_BYTES = ((W_BYTES > F_BYTES ? W_BYTES : F_BYTES) + 15) / 16 * 16;
   static constexpr int P_ELEMS = 4 * PJ * PI;
   static constexpr int P_BYTES = VISC ? 2 * P_ELEMS * (int)sizeof(T) : 0;
-  static constexpr int TOTAL = A_BYTES + P_BYTES;
+  static constexpr int TOTAL = F_BYTES + W_BYTES + P_BYTES;
 };
 
 template <typename T, bool VISC, int MODE, int TJ>
-__global__ void __launch_bounds__(64 * TJ) k_stage_tiled(StageArgs A, const BlockDesc* __restrict__ blocks,
+__global__ void CFD_TILED_BOUNDS(64 * TJ) k_stage_tiled(StageArgs A, const BlockDesc* __restrict__ blocks,
                                                         const TileDesc* __restrict__ tiles, Gas<T> gas) {
   using LD = TiledLds<T, VISC, TJ>;
   constexpr int NT = 64 * TJ;
   constexpr int WI = LD::WI, WJ = LD::WJ, PI = LD::PI, PJ = LD::PJ;
   __shared__ __attribute__((aligned(16))) char smem[LD::TOTAL];
-  T* sW = reinterpret_cast<T*>(smem);                   // [NW][WJ][WI]
-  double* sFi = reinterpret_cast<double*>(smem);        // [5][TJ][65]    (aliases sW)
-  double* sFj = sFi + LD::FI;                            // [5][TJ+1][64]
-  T* sPm = reinterpret_cast<T*>(smem + LD::A_BYTES);     // phi(k-1) [4][PJ][PI]
-  T* sPp = sPm + LD::P_ELEMS;                            // phi(k+1)
+  double* sFi = reinterpret_cast<double*>(smem);                 // [5][TJ][65]
+  double* sFj = sFi + LD::FI;                                     // [5][TJ+1][64]
+  T* sW = reinterpret_cast<T*>(smem + LD::F_BYTES);               // [NW][WJ][WI]
+  T* sPm = reinterpret_cast<T*>(smem + LD::F_BYTES + LD::W_BYTES);   // phi(k-1) [4][PJ][PI]
+  T* sPp = sPm + LD::P_ELEMS;                                     // phi(k+1)
 
   auto W = [&](int v, int pj, int pi) -> T& { return sW[(v * WJ + pj) * WI + pi]; };
   auto P = [&](T* buf, int v, int pj, int pi) -> T& { return buf[(v * PJ + pj) * PI + pi]; };
@@ -89,7 +108,7 @@ __global__ void __launch_bounds__(64 * TJ) k_stage_tiled(StageArgs A, const Bloc
     const bool fi_ok = i <= ni && j < nj;   // this thread's lower i-face is needed
     const bool fj_ok = j <= nj && i < ni;   // this thread's lower j-face is needed
     // faces on the tile's high edges, spread over the first waves
-    const bool xj = tid < 64 && j0 + TJ <= nj && i0 + tid < ni;                       // j-face at row j0+TJ
+    const bool xj = tid < 64 && j0 + TJ <= nj && i0 + tid < ni;                           // j-face at row j0+TJ
     const bool xi = tid >= 64 && tid < 64 + TJ && i0 + 64 <= ni && j0 + (tid - 64) < nj;  // i-face at col i0+64
     const double* qb = A.qs + B.qoff;
     const double* mb = A.met + B.moff;
@@ -109,8 +128,7 @@ __global__ void __launch_bounds__(64 * TJ) k_stage_tiled(StageArgs A, const Bloc
       q2 = ld_prim<T>(qb, c0 + sk, sv, gas.gm1);
       q3 = ld_prim<T>(qb, c0 + 2 * sk, sv, gas.gm1);
     }
-    // phi(k0 - 1) plane, halo 1
-    auto fill_phi = [&](T* buf, int kk) {
+    auto fill_phi = [&](T* buf, int kk) {   // phi plane kk with halo 1
       for (int s = tid; s < PJ * PI; s += NT) {
         const int pj = s / PI, pi = s - (s / PI) * PI;
         const int gi = i0 - 1 + pi, gj = j0 - 1 + pj;
@@ -122,7 +140,7 @@ __global__ void __launch_bounds__(64 * TJ) k_stage_tiled(StageArgs A, const Bloc
         for (int v = 0; v < 4; ++v) P(buf, v, pj, pi) = o[v];
       }
     };
-    __syncthreads();   // previous tile's LDS users are done
+    __syncthreads();   // the previous tile's LDS users are done
     if (VISC) fill_phi(sPm, k0 - 1);
 
     for (int k = k0; k < kend; ++k) {
@@ -143,80 +161,84 @@ __global__ void __launch_bounds__(64 * TJ) k_stage_tiled(StageArgs A, const Bloc
       if (VISC) fill_phi(sPp, k + 1);
       __syncthreads();
 
-      // ---- 2. faces
-      double Fi[5], Fj[5], Fku[5], Fx[5];
-      const T zero4[4] = {T(0), T(0), T(0), T(0)};
-      auto face_i = [&](int ci, int rj, double F[5]) {   // lower i-face of cell (i0+ci, j0+rj)
+      // ---- 2. faces, each flux stored to LDS as soon as it is known
+      auto face_i = [&](int ci, int rj) {   // lower i-face of cell (i0+ci, j0+rj)
         const int pi = ci + 2, pj = rj + 2, qi = ci + 1, qj = rj + 1;
         const int64_t c = off(i0 + ci, j0 + rj, k);
-        T tl = T(0), tr = T(0), d1[4], d2[4];
-        double St[2][3] = {{0, 0, 0}, {0, 0, 0}};
-        double vf = 1.0;
+        const double sx = mb[c], sy = mb[sv + c], sz = mb[2 * sv + c];
+        T f[5], n[3];
+        const double area = face_inviscid<T>(wprim(pj, pi - 2), wprim(pj, pi - 1), wprim(pj, pi),
+                                             wprim(pj, pi + 1), sx, sy, sz, gas, f, n);
         if (VISC) {
-          tl = W(5, pj, pi - 1);
-          tr = W(5, pj, pi);
-          T a[4], b[4], e[4], f[4];
-          wphi(pj + 1, pi - 1, a); wphi(pj + 1, pi, b); wphi(pj - 1, pi - 1, e); wphi(pj - 1, pi, f);
-          tdiff(a, b, e, f, d1);
-          pphi(sPp, qj, qi - 1, a); pphi(sPp, qj, qi, b); pphi(sPm, qj, qi - 1, e); pphi(sPm, qj, qi, f);
-          tdiff(a, b, e, f, d2);
+          T pl[4], pr[4], d1[4], d2[4], a[4], b[4], e[4], g[4];
+          wphi(pj, pi - 1, pl);
+          wphi(pj, pi, pr);
+          wphi(pj + 1, pi - 1, a); wphi(pj + 1, pi, b); wphi(pj - 1, pi - 1, e); wphi(pj - 1, pi, g);
+          tdiff(a, b, e, g, d1);
+          pphi(sPp, qj, qi - 1, a); pphi(sPp, qj, qi, b); pphi(sPm, qj, qi - 1, e); pphi(sPm, qj, qi, g);
+          tdiff(a, b, e, g, d2);
+          double St[2][3], vf;
           visc_metrics(mb, sv, c - 1, c, 0, sj, sk, St, vf);
-        } else {
-          for (int q = 0; q < 4; ++q) { d1[q] = zero4[q]; d2[q] = zero4[q]; }
+          face_viscous<T>(pl, pr, sx, sy, sz, n, d1, d2, St, vf, gas, f);
         }
-        face_core<T, VISC>(wprim(pj, pi - 2), wprim(pj, pi - 1), wprim(pj, pi), wprim(pj, pi + 1),
-                           mb[c], mb[sv + c], mb[2 * sv + c], tl, tr, d1, d2, St, vf, gas, F);
+        double F[5];
+        scale_flux_f64(f, area, F);
+        for (int q = 0; q < 5; ++q) sFi[(q * TJ + rj) * 65 + ci] = F[q];
       };
-      auto face_j = [&](int ci, int rj, double F[5]) {   // lower j-face of cell (i0+ci, j0+rj)
+      auto face_j = [&](int ci, int rj) {   // lower j-face of cell (i0+ci, j0+rj)
         const int pi = ci + 2, pj = rj + 2, qi = ci + 1, qj = rj + 1;
         const int64_t c = off(i0 + ci, j0 + rj, k);
-        T tl = T(0), tr = T(0), d1[4], d2[4];
-        double St[2][3] = {{0, 0, 0}, {0, 0, 0}};
-        double vf = 1.0;
+        const double sx = mb[3 * sv + c], sy = mb[4 * sv + c], sz = mb[5 * sv + c];
+        T f[5], n[3];
+        const double area = face_inviscid<T>(wprim(pj - 2, pi), wprim(pj - 1, pi), wprim(pj, pi),
+                                             wprim(pj + 1, pi), sx, sy, sz, gas, f, n);
         if (VISC) {
-          tl = W(5, pj - 1, pi);
-          tr = W(5, pj, pi);
-          T a[4], b[4], e[4], f[4];
-          wphi(pj - 1, pi + 1, a); wphi(pj, pi + 1, b); wphi(pj - 1, pi - 1, e); wphi(pj, pi - 1, f);
-          tdiff(a, b, e, f, d1);
-          pphi(sPp, qj - 1, qi, a); pphi(sPp, qj, qi, b); pphi(sPm, qj - 1, qi, e); pphi(sPm, qj, qi, f);
-          tdiff(a, b, e, f, d2);
+          T pl[4], pr[4], d1[4], d2[4], a[4], b[4], e[4], g[4];
+          wphi(pj - 1, pi, pl);
+          wphi(pj, pi, pr);
+          wphi(pj - 1, pi + 1, a); wphi(pj, pi + 1, b); wphi(pj - 1, pi - 1, e); wphi(pj, pi - 1, g);
+          tdiff(a, b, e, g, d1);
+          pphi(sPp, qj - 1, qi, a); pphi(sPp, qj, qi, b); pphi(sPm, qj - 1, qi, e); pphi(sPm, qj, qi, g);
+          tdiff(a, b, e, g, d2);
+          double St[2][3], vf;
           visc_metrics(mb, sv, c - sj, c, 1, sj, sk, St, vf);
-        } else {
-          for (int q = 0; q < 4; ++q) { d1[q] = zero4[q]; d2[q] = zero4[q]; }
+          face_viscous<T>(pl, pr, sx, sy, sz, n, d1, d2, St, vf, gas, f);
         }
-        face_core<T, VISC>(wprim(pj - 2, pi), wprim(pj - 1, pi), wprim(pj, pi), wprim(pj + 1, pi),
-                           mb[3 * sv + c], mb[4 * sv + c], mb[5 * sv + c], tl, tr, d1, d2, St, vf, gas, F);
+        double F[5];
+        scale_flux_f64(f, area, F);
+        for (int q = 0; q < 5; ++q) sFj[(q * (TJ + 1) + rj) * 64 + ci] = F[q];
       };
-      if (fi_ok) face_i(tx, ty, Fi);
-      if (fj_ok) face_j(tx, ty, Fj);
-      if (xj) face_j(tid, TJ, Fx);
-      if (xi) face_i(64, tid - 64, Fx);
+      if (fi_ok) face_i(tx, ty);
+      CFD_FACE_FENCE();
+      if (fj_ok) face_j(tx, ty);
+      CFD_FACE_FENCE();
+      if (xj) face_j(tid, TJ);
+      if (xi) face_i(64, tid - 64);
+      CFD_FACE_FENCE();
+      double Fku[5] = {0, 0, 0, 0, 0};
       if (act) {   // upper k-face between (i, j, k) and (i, j, k+1)
         const int pi = tx + 2, pj = ty + 2, qi = tx + 1, qj = ty + 1;
-        const int64_t c = off(i, j, k);
-        const int64_t cu = c + sk;
-        T tl = T(0), tr = T(0), d1[4], d2[4];
-        double St[2][3] = {{0, 0, 0}, {0, 0, 0}};
-        double vf = 1.0;
+        const int64_t cu = off(i, j, k) + sk;
+        const double sx = mb[6 * sv + cu], sy = mb[7 * sv + cu], sz = mb[8 * sv + cu];
+        T f[5], n[3];
+        const double area = face_inviscid<T>(q0, q1, q2, q3, sx, sy, sz, gas, f, n);
         if (VISC) {
-          tl = temp_of(q1);
-          tr = temp_of(q2);
-          T a[4], b[4], e[4], f[4];
-          wphi(pj, pi + 1, a); pphi(sPp, qj, qi + 1, b); wphi(pj, pi - 1, e); pphi(sPp, qj, qi - 1, f);
-          tdiff(a, b, e, f, d1);
-          wphi(pj + 1, pi, a); pphi(sPp, qj + 1, qi, b); wphi(pj - 1, pi, e); pphi(sPp, qj - 1, qi, f);
-          tdiff(a, b, e, f, d2);
-          visc_metrics(mb, sv, c, cu, 2, sj, sk, St, vf);
-        } else {
-          for (int q = 0; q < 4; ++q) { d1[q] = zero4[q]; d2[q] = zero4[q]; }
+          T pl[4], pr[4], d1[4], d2[4], a[4], b[4], e[4], g[4];
+          phi_of(q1, temp_of(q1), pl);
+          phi_of(q2, temp_of(q2), pr);
+          wphi(pj, pi + 1, a); pphi(sPp, qj, qi + 1, b); wphi(pj, pi - 1, e); pphi(sPp, qj, qi - 1, g);
+          tdiff(a, b, e, g, d1);
+          wphi(pj + 1, pi, a); pphi(sPp, qj + 1, qi, b); wphi(pj - 1, pi, e); pphi(sPp, qj - 1, qi, g);
+          tdiff(a, b, e, g, d2);
+          double St[2][3], vf;
+          visc_metrics(mb, sv, cu - sk, cu, 2, sj, sk, St, vf);
+          face_viscous<T>(pl, pr, sx, sy, sz, n, d1, d2, St, vf, gas, f);
         }
-        face_core<T, VISC>(q0, q1, q2, q3, mb[6 * sv + cu], mb[7 * sv + cu], mb[8 * sv + cu], tl, tr, d1, d2,
-                           St, vf, gas, Fku);
+        scale_flux_f64(f, area, Fku);
       }
-      __syncthreads();   // every read of sW / sPm / sPp for this plane is done
+      __syncthreads();   // fluxes stored; every read of sW / sPm / sPp for this plane done
 
-      // ---- 3. keep phi(k) as the next plane's phi(k-1); then exchange fluxes
+      // ---- 3. keep phi(k) as the next plane's phi(k-1); finish the cells
       if (VISC) {
         for (int s = tid; s < PJ * PI; s += NT) {
           const int pj = s / PI, pi = s - (s / PI) * PI;
@@ -224,18 +246,7 @@ __global__ void __launch_bounds__(64 * TJ) k_stage_tiled(StageArgs A, const Bloc
           wphi(pj + 1, pi + 1, o);
           for (int v = 0; v < 4; ++v) P(sPm, v, pj, pi) = o[v];
         }
-        __syncthreads();
       }
-      if (fi_ok)
-        for (int q = 0; q < 5; ++q) sFi[(q * TJ + ty) * 65 + tx] = Fi[q];
-      if (fj_ok)
-        for (int q = 0; q < 5; ++q) sFj[(q * (TJ + 1) + ty) * 64 + tx] = Fj[q];
-      if (xj)
-        for (int q = 0; q < 5; ++q) sFj[(q * (TJ + 1) + TJ) * 64 + tid] = Fx[q];
-      if (xi)
-        for (int q = 0; q < 5; ++q) sFi[(q * TJ + (tid - 64)) * 65 + 64] = Fx[q];
-      __syncthreads();
-
       if (act) {
         double Di[5], Dj[5], Dk[5];
         for (int q = 0; q < 5; ++q) {
@@ -251,7 +262,7 @@ __global__ void __launch_bounds__(64 * TJ) k_stage_tiled(StageArgs A, const Bloc
         q2 = q3;
         if (k + 1 < kend) q3 = ld_prim<T>(qb, c + 3 * sk, sv, gas.gm1);
       }
-      __syncthreads();   // flux reads done before the next plane overwrites sW
+      __syncthreads();   // flux reads and the phi copy done before the next plane
     }
   }
   if (MODE == 1) wg_reduce_partials(acc, A.partials + (int64_t)blockIdx.x * NPART);

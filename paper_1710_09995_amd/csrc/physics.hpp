@@ -18,12 +18,22 @@ struct Prim {
   T r, u, v, w, p;
 };
 
+// Reciprocal, quotient and square root in the flux precision: IEEE FP64
+// operations for double; the single-instruction hardware reciprocal and
+// square root (1 ulp) for the FP32 flux variant, whose error budget is 1e-5.
+__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double div_t(double a, double b) { return a / b; }
+__device__ __forceinline__ float div_t(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 template <typename T>
 __device__ __forceinline__ Prim<T> to_prim(double q0, double q1, double q2, double q3, double q4,
                                            T gm1) {
   Prim<T> W;
   W.r = (T)q0;
-  T inv = T(1) / W.r;
+  T inv = rcp_t(W.r);
   W.u = (T)q1 * inv;
   W.v = (T)q2 * inv;
   W.w = (T)q3 * inv;
@@ -31,32 +41,79 @@ __device__ __forceinline__ Prim<T> to_prim(double q0, double q1, double q2, doub
   return W;
 }
 
-template <typename T>
-__device__ __forceinline__ T limiter(T a, T b, T eps) {
-  return (T(2) * a * b + eps) / (a * a + b * b + eps);
+// Reciprocals of n positive values.  FP64: one division and prefix products
+// (Montgomery's batch inversion); denominators here lie in [eps, O(1e6)], so
+// the products stay far inside the FP64 range.  FP32: hardware reciprocal.
+template <int N>
+__device__ __forceinline__ void batch_rcp(const double* den, double* inv) {
+  double p[N];
+  p[0] = den[0];
+#pragma unroll
+  for (int k = 1; k < N; ++k) p[k] = p[k - 1] * den[k];
+  double r = 1.0 / p[N - 1];
+#pragma unroll
+  for (int k = N - 1; k > 0; --k) {
+    inv[k] = r * p[k - 1];
+    r = r * den[k];
+  }
+  inv[0] = r;
+}
+template <int N>
+__device__ __forceinline__ void batch_rcp(const float* den, float* inv) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) inv[k] = __builtin_amdgcn_rcpf(den[k]);
 }
 
-// Left and right states of one component at the face between cells c-1, c.
-template <typename T>
-__device__ __forceinline__ void muscl1(T wm2, T wm1, T w0, T wp1, T eps, T& wl, T& wr) {
-  const T kap = T(1.0 / 3.0);
-  T dm = wm1 - wm2;
-  T dp = w0 - wm1;
-  T s = limiter(dm, dp, eps);
-  wl = wm1 + T(0.25) * s * ((T(1) - kap * s) * dm + (T(1) + kap * s) * dp);
-  T dp2 = wp1 - w0;
-  T s2 = limiter(dp, dp2, eps);
-  wr = w0 - T(0.25) * s2 * ((T(1) - kap * s2) * dp2 + (T(1) + kap * s2) * dp);
-}
+// 1: Roe's flux divides through reciprocals (fewer FP64 divisions);
+// 0: plain quotients.
+#ifndef CFD_ROE_RCP
+#define CFD_ROE_RCP 1
+#endif
+
+// How many limiter denominators share one reciprocal: 10 (one division per
+// face), 5 (one per side) or 1 (a division each).
+#ifndef CFD_LIMITER_BATCH
+#define CFD_LIMITER_BATCH 5
+#endif
 
 template <typename T>
 __device__ __forceinline__ void muscl(const Prim<T>& a, const Prim<T>& b, const Prim<T>& c,
                                       const Prim<T>& d, T eps, Prim<T>& L, Prim<T>& R) {
-  muscl1(a.r, b.r, c.r, d.r, eps, L.r, R.r);
-  muscl1(a.u, b.u, c.u, d.u, eps, L.u, R.u);
-  muscl1(a.v, b.v, c.v, d.v, eps, L.v, R.v);
-  muscl1(a.w, b.w, c.w, d.w, eps, L.w, R.w);
-  muscl1(a.p, b.p, c.p, d.p, eps, L.p, R.p);
+  const T A[5] = {a.r, a.u, a.v, a.w, a.p};
+  const T Bv[5] = {b.r, b.u, b.v, b.w, b.p};
+  const T Cv[5] = {c.r, c.u, c.v, c.w, c.p};
+  const T D[5] = {d.r, d.u, d.v, d.w, d.p};
+  T dm[5], dp[5], dp2[5], num[10], den[10], inv[10];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    dm[q] = Bv[q] - A[q];
+    dp[q] = Cv[q] - Bv[q];
+    dp2[q] = D[q] - Cv[q];
+    num[q] = T(2) * dm[q] * dp[q] + eps;
+    den[q] = dm[q] * dm[q] + dp[q] * dp[q] + eps;
+    num[5 + q] = T(2) * dp[q] * dp2[q] + eps;
+    den[5 + q] = dp[q] * dp[q] + dp2[q] * dp2[q] + eps;
+  }
+#if CFD_LIMITER_BATCH == 10
+  batch_rcp<10>(den, inv);
+#elif CFD_LIMITER_BATCH == 5
+  batch_rcp<5>(den, inv);
+  batch_rcp<5>(den + 5, inv + 5);
+#else
+#pragma unroll
+  for (int k = 0; k < 10; ++k) inv[k] = rcp_t(den[k]);
+#endif
+  const T kap = T(1.0 / 3.0);
+  T l[5], r[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const T s = num[q] * inv[q];
+    l[q] = Bv[q] + T(0.25) * s * ((T(1) - kap * s) * dm[q] + (T(1) + kap * s) * dp[q]);
+    const T s2 = num[5 + q] * inv[5 + q];
+    r[q] = Cv[q] - T(0.25) * s2 * ((T(1) - kap * s2) * dp2[q] + (T(1) + kap * s2) * dp[q]);
+  }
+  L.r = l[0]; L.u = l[1]; L.v = l[2]; L.w = l[3]; L.p = l[4];
+  R.r = r[0]; R.u = r[1]; R.v = r[2]; R.w = r[3]; R.p = r[4];
   // positivity fallback: first order on this face
   if (!(L.r > T(0)) || !(L.p > T(0)) || !(R.r > T(0)) || !(R.p > T(0))) {
     L = b;
@@ -69,19 +126,26 @@ template <typename T>
 __device__ __forceinline__ void roe(const Prim<T>& L, const Prim<T>& R, T nx, T ny, T nz,
                                     T gamma, T eps_h, T F[5]) {
   const T gm1 = gamma - T(1);
-  const T gg = gamma / gm1;
-  T Hl = gg * L.p / L.r + T(0.5) * (L.u * L.u + L.v * L.v + L.w * L.w);
-  T Hr = gg * R.p / R.r + T(0.5) * (R.u * R.u + R.v * R.v + R.w * R.w);
-  T r = sqrt(R.r / L.r);
+  const T gg = div_t(gamma, gm1);
+#if CFD_ROE_RCP
+  const T iLr = rcp_t(L.r), iRr = rcp_t(R.r);
+  T Hl = gg * L.p * iLr + T(0.5) * (L.u * L.u + L.v * L.v + L.w * L.w);
+  T Hr = gg * R.p * iRr + T(0.5) * (R.u * R.u + R.v * R.v + R.w * R.w);
+  T r = sqrt_t(R.r * iLr);
+#else
+  T Hl = div_t(gg * L.p, L.r) + T(0.5) * (L.u * L.u + L.v * L.v + L.w * L.w);
+  T Hr = div_t(gg * R.p, R.r) + T(0.5) * (R.u * R.u + R.v * R.v + R.w * R.w);
+  T r = sqrt_t(div_t(R.r, L.r));
+#endif
   T rhat = r * L.r;
-  T i1r = T(1) / (T(1) + r);
+  T i1r = rcp_t(T(1) + r);
   T uh = (L.u + r * R.u) * i1r;
   T vh = (L.v + r * R.v) * i1r;
   T wh = (L.w + r * R.w) * i1r;
   T Hh = (Hl + r * Hr) * i1r;
   T q2 = uh * uh + vh * vh + wh * wh;
   T c2 = gm1 * (Hh - T(0.5) * q2);
-  T ch = sqrt(c2);
+  T ch = sqrt_t(c2);
   T Uh = uh * nx + vh * ny + wh * nz;
   T dr = R.r - L.r;
   T du = R.u - L.u, dv = R.v - L.v, dw = R.w - L.w;
@@ -91,12 +155,18 @@ __device__ __forceinline__ void roe(const Prim<T>& L, const Prim<T>& R, T nx, T 
   T l2 = fabs(Uh);
   T l3 = fabs(Uh + ch);
   T delta = eps_h * (fabs(Uh) + ch);
-  if (l1 < delta) l1 = (l1 * l1 + delta * delta) / (T(2) * delta);
-  if (l3 < delta) l3 = (l3 * l3 + delta * delta) / (T(2) * delta);
-  T i2c2 = T(1) / (T(2) * c2);
+#if CFD_ROE_RCP
+  const T i2d = rcp_t(T(2) * delta);
+  if (l1 < delta) l1 = (l1 * l1 + delta * delta) * i2d;
+  if (l3 < delta) l3 = (l3 * l3 + delta * delta) * i2d;
+#else
+  if (l1 < delta) l1 = div_t(l1 * l1 + delta * delta, T(2) * delta);
+  if (l3 < delta) l3 = div_t(l3 * l3 + delta * delta, T(2) * delta);
+#endif
+  T i2c2 = rcp_t(T(2) * c2);
   T a1 = (dp - rhat * ch * dU) * i2c2;
   T a5 = (dp + rhat * ch * dU) * i2c2;
-  T a2 = dr - dp / c2;
+  T a2 = dr - dp * (T(2) * i2c2);
   T w1 = l1 * a1, w5 = l3 * a5, w2 = l2 * a2, ws = l2 * rhat;
   T D0 = w1 + w2 + w5;
   T D1 = w1 * (uh - ch * nx) + w2 * uh + ws * (du - dU * nx) + w5 * (uh + ch * nx);
@@ -116,7 +186,7 @@ __device__ __forceinline__ void roe(const Prim<T>& L, const Prim<T>& R, T nx, T 
 
 template <typename T>
 __device__ __forceinline__ T sutherland(T t, T mu_inf, T s_star) {
-  return mu_inf * t * sqrt(t) * (T(1) + s_star) / (t + s_star);
+  return div_t(mu_inf * t * sqrt_t(t) * (T(1) + s_star), t + s_star);
 }
 
 // Viscous flux F_v . n per unit area through a face of unit normal n.
@@ -126,7 +196,7 @@ template <typename T>
 __device__ __forceinline__ void viscous_n(const T g[4][3], const T uf[3], T tf, T nx, T ny, T nz,
                                           const Gas<T>& gas, T F[5]) {
   T mu = sutherland(tf, gas.mu_inf, gas.s_star);
-  T kc = mu * gas.gamma / (gas.gm1 * gas.prandtl);
+  T kc = mu * gas.kfac;   // k = mu gamma / ((gamma - 1) Pr)
   T div = g[0][0] + g[1][1] + g[2][2];
   T lam = T(2.0 / 3.0) * div;
   T txx = mu * (g[0][0] + g[0][0] - lam);

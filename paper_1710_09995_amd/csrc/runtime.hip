@@ -298,12 +298,12 @@ struct cfd_ctx {
   TileDesc* dtiles = nullptr;
   int ntiles = 0;
   int64_t ncells = 0;
-  cfd_tuning tun{0, 4, 32, 1};
+  cfd_tuning tun{0, 4, 32, 1, 1};
   StepParams SP{};
   Gas<double> g64{};
   Gas<float> g32{};
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;          // one time step, captured once per state pointer
   hipGraphExec_t gexec = nullptr;
   const void* graph_q = nullptr;
   int num_cu = 256;
@@ -390,6 +390,7 @@ void set_params(cfd_ctx* c) {
     G.s_star = (T)p.sutherland;
     G.eps_h = (T)p.entropy_fix;
     G.eps_lim = (T)p.limiter_eps;
+    G.kfac = (T)(p.gamma / ((p.gamma - 1.0) * p.prandtl));
     for (int x = 0; x < 3; ++x) G.uinf[x] = (T)S.uinf[x];
   };
   fill(c->g64);
@@ -412,11 +413,26 @@ void build_tiles(cfd_ctx* c, hipStream_t s) {
           v.push_back({{b, i0, j0, k0}, w});
         }
   }
-  // longest-processing-time order: big tiles first, ties keep block order
-  std::stable_sort(v.begin(), v.end(), [](const T2& a, const T2& b) { return a.work > b.work; });
   if ((int64_t)v.size() > c->W.max_tiles) fail(CFD_EINTERNAL, "tile list overflow");
-  std::vector<TileDesc> h(v.size());
-  for (size_t i = 0; i < v.size(); ++i) h[i] = v[i].t;
+  std::vector<TileDesc> h;
+  h.reserve(v.size());
+  if (c->tun.order == 1) {
+    // XCD-aware: 8 spatially contiguous chunks (natural block, k, j, i order),
+    // interleaved so list position p belongs to chunk p mod 8.  The persistent
+    // grid has a multiple of 8 workgroups and workgroup w runs on XCD w mod 8,
+    // so each XCD sweeps one chunk and its L2 keeps the shared halos.
+    const size_t n = v.size();
+    size_t bounds[9];
+    for (int x = 0; x <= 8; ++x) bounds[x] = n * x / 8;
+    const size_t rounds = (n + 7) / 8 + 1;
+    for (size_t l = 0; l < rounds; ++l)
+      for (int x = 0; x < 8; ++x)
+        if (bounds[x] + l < bounds[x + 1]) h.push_back(v[bounds[x] + l].t);
+  } else {
+    // longest-processing-time order: big tiles first, ties keep block order
+    std::stable_sort(v.begin(), v.end(), [](const T2& a, const T2& b) { return a.work > b.work; });
+    for (size_t i = 0; i < v.size(); ++i) h.push_back(v[i].t);
+  }
   c->ntiles = (int)h.size();
   HIPCHK(hipMemcpyAsync(c->dtiles, h.data(), sizeof(TileDesc) * h.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -495,9 +511,12 @@ void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, hipStream_t s) {
 }
 
 // One full RK3 step: ghost fill + dt + 3 x (ghost fill + stage) + finalize.
+// (Taking dt of the new state inside the third stage instead of a separate
+// kernel was measured slower: the stage kernel's extra metric loads cost more
+// than the separate pass.)
 void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
-  const int nwg_dt = nwg_for(c, 8);
   const int nwg1 = stage_nwg(c, 1);   // rows of the stage-1 norm partials
+  const int nwg_dt = nwg_for(c, 8);
   ghost_fill(c, q, s);
   timed(c, 2, s, [&] {
     launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
@@ -736,6 +755,7 @@ cfd_status cfd_set_tuning(cfd_ctx* c, const cfd_tuning* t) {
     if (t->tile_j < 1 || t->tile_j > 16 || (t->tile_j & (t->tile_j - 1)))
       fail(CFD_EINVAL, "tile_j must be a power of two in [1, 16]");
     if (t->tile_k < 1 || t->tile_k > 4096) fail(CFD_EINVAL, "tile_k must be in [1, 4096]");
+    if (t->order < 0 || t->order > 1) fail(CFD_EINVAL, "order must be 0 or 1");
     if (t->kernel == 0 && t->tile_j != 2 && t->tile_j != 4 && t->tile_j != 8)
       fail(CFD_EINVAL, "the tiled kernel takes tile_j = 2, 4 or 8");
     c->drop_graph();
@@ -794,9 +814,9 @@ cfd_status cfd_step(cfd_ctx* c, double* q, int32_t nsteps, double* hist, hipStre
         try {
           enqueue_step(c, q, c->cap_stream);
         } catch (...) {
-          hipGraph_t g = nullptr;
-          hipStreamEndCapture(c->cap_stream, &g);
-          if (g) hipGraphDestroy(g);
+          hipGraph_t gg = nullptr;
+          hipStreamEndCapture(c->cap_stream, &gg);
+          if (gg) hipGraphDestroy(gg);
           throw;
         }
         HIPCHK(hipStreamEndCapture(c->cap_stream, &c->graph));

@@ -2,7 +2,8 @@
 // different gathers (straight from global memory, or from LDS planes), the
 // cell update of Eqs. (4)-(6) and the norm partials.
 //
-// Both stage kernels call face_core with bitwise identical inputs (the same
+// Both stage kernels call face_inviscid / face_viscous with bitwise identical
+// inputs in the same order (the same
 // primitives from the same Q, the same metric loads, the same averaging
 // expressions), and the sources are built with -ffp-contract=on so the
 // contraction of each expression is fixed by the source: every face flux is
@@ -64,74 +65,91 @@ __device__ __forceinline__ void visc_metrics(const double* __restrict__ mb, int6
   vf = 0.5 * (mb[9 * sv + cl] + mb[9 * sv + c]);
 }
 
-// (F_inv - F_vis) . S through one face from gathered inputs.
-//  a, b, c, d: primitives of cells c-2, c-1 (L), c (R), c+1 along the face direction
-//  sx, sy, sz: the face vector; tl, tr: temperatures of L and R
-//  dt1, dt2: transverse differences of phi; St, vf: viscous metric terms
-template <typename T, bool VISC>
-__device__ __forceinline__ void face_core(const Prim<T>& a, const Prim<T>& b, const Prim<T>& c, const Prim<T>& d,
-                                          double sx, double sy, double sz, T tl, T tr, const T dt1[4],
-                                          const T dt2[4], const double St[2][3], double vf, const Gas<T>& gas,
-                                          double F[5]) {
+// Inviscid part of one face: MUSCL states from cells c-2, c-1 (L), c (R),
+// c+1 along the face direction, then Roe's flux per unit area f through the
+// face vector (sx, sy, sz).  Returns |S|; n receives the unit normal.
+template <typename T>
+__device__ __forceinline__ double face_inviscid(const Prim<T>& a, const Prim<T>& b, const Prim<T>& c,
+                                                const Prim<T>& d, double sx, double sy, double sz,
+                                                const Gas<T>& gas, T f[5], T n[3]) {
   Prim<T> L, R;
   muscl(a, b, c, d, gas.eps_lim, L, R);
   const double area = sqrt(sx * sx + sy * sy + sz * sz);
   const double ia = 1.0 / area;
-  const T nx = (T)(sx * ia), ny = (T)(sy * ia), nz = (T)(sz * ia);
-  T f[5];
-  roe<T>(L, R, nx, ny, nz, gas.gamma, gas.eps_h, f);
-  if (VISC) {
-    T pl[4], pr[4];
-    phi_of(b, tl, pl);
-    phi_of(c, tr, pr);
-    const double iv = 1.0 / vf;
-    const T sdx = (T)(sx * iv), sdy = (T)(sy * iv), sdz = (T)(sz * iv);
-    const T s1x = (T)(St[0][0] * iv), s1y = (T)(St[0][1] * iv), s1z = (T)(St[0][2] * iv);
-    const T s2x = (T)(St[1][0] * iv), s2y = (T)(St[1][1] * iv), s2z = (T)(St[1][2] * iv);
-    T g[4][3];
+  n[0] = (T)(sx * ia);
+  n[1] = (T)(sy * ia);
+  n[2] = (T)(sz * ia);
+  roe<T>(L, R, n[0], n[1], n[2], gas.gamma, gas.eps_h, f);
+  return area;
+}
+
+// Viscous part: subtract F_v . n from f.  pl, pr: phi of L and R;
+// dt1, dt2: transverse differences of phi (ascending transverse order);
+// St, vf: averaged transverse face vectors and the auxiliary volume.
+template <typename T>
+__device__ __forceinline__ void face_viscous(const T pl[4], const T pr[4], double sx, double sy, double sz,
+                                             const T n[3], const T dt1[4], const T dt2[4], const double St[2][3],
+                                             double vf, const Gas<T>& gas, T f[5]) {
+  const double iv = 1.0 / vf;
+  const T sdx = (T)(sx * iv), sdy = (T)(sy * iv), sdz = (T)(sz * iv);
+  const T s1x = (T)(St[0][0] * iv), s1y = (T)(St[0][1] * iv), s1z = (T)(St[0][2] * iv);
+  const T s2x = (T)(St[1][0] * iv), s2y = (T)(St[1][1] * iv), s2z = (T)(St[1][2] * iv);
+  T g[4][3];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T dq = pr[q] - pl[q];
-      g[q][0] = dq * sdx + dt1[q] * s1x + dt2[q] * s2x;
-      g[q][1] = dq * sdy + dt1[q] * s1y + dt2[q] * s2y;
-      g[q][2] = dq * sdz + dt1[q] * s1z + dt2[q] * s2z;
-    }
-    const T uf[3] = {T(0.5) * (pl[0] + pr[0]), T(0.5) * (pl[1] + pr[1]), T(0.5) * (pl[2] + pr[2])};
-    const T tf = T(0.5) * (pl[3] + pr[3]);
-    T fv[5];
-    viscous_n<T>(g, uf, tf, nx, ny, nz, gas, fv);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) f[q] -= fv[q];
+  for (int q = 0; q < 4; ++q) {
+    const T dq = pr[q] - pl[q];
+    g[q][0] = dq * sdx + dt1[q] * s1x + dt2[q] * s2x;
+    g[q][1] = dq * sdy + dt1[q] * s1y + dt2[q] * s2y;
+    g[q][2] = dq * sdz + dt1[q] * s1z + dt2[q] * s2z;
   }
+  const T uf[3] = {T(0.5) * (pl[0] + pr[0]), T(0.5) * (pl[1] + pr[1]), T(0.5) * (pl[2] + pr[2])};
+  const T tf = T(0.5) * (pl[3] + pr[3]);
+  T fv[5];
+  viscous_n<T>(g, uf, tf, n[0], n[1], n[2], gas, fv);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) f[q] -= fv[q];
+}
+
+__device__ __forceinline__ void scale_flux_f64(const double f[5], double area, double F[5]) {
+#pragma unroll
+  for (int q = 0; q < 5; ++q) F[q] = f[q] * area;
+}
+__device__ __forceinline__ void scale_flux_f64(const float f[5], double area, double F[5]) {
 #pragma unroll
   for (int q = 0; q < 5; ++q) F[q] = (double)f[q] * area;
 }
 
-// Face flux on the lower d-face of cell c, every input read from global memory.
+// Face flux (F_inv - F_vis) . S on the lower d-face of cell c, every input
+// read from global memory.
 template <typename T, bool VISC>
 __device__ __forceinline__ void face_flux_global(const double* __restrict__ qb, const double* __restrict__ mb,
                                                  const BlockDesc& B, int64_t c, int d, const Gas<T>& gas,
                                                  double F[5]) {
   const int64_t sd = dstride(d, B.sj, B.sk);
   const int64_t sv = B.sv;
-  const Prim<T> wm2 = ld_prim<T>(qb, c - 2 * sd, sv, gas.gm1);
-  const Prim<T> wm1 = ld_prim<T>(qb, c - sd, sv, gas.gm1);
-  const Prim<T> w0 = ld_prim<T>(qb, c, sv, gas.gm1);
-  const Prim<T> wp1 = ld_prim<T>(qb, c + sd, sv, gas.gm1);
   const double sx = mb[(3 * d) * sv + c], sy = mb[(3 * d + 1) * sv + c], sz = mb[(3 * d + 2) * sv + c];
-  T dd[2][4] = {};
-  double St[2][3] = {};
-  double vf = 1.0;
-  T tl = T(0), tr = T(0);
+  T f[5], n[3];
+  T pl[4], pr[4];
+  double area;
+  {
+    const Prim<T> wm2 = ld_prim<T>(qb, c - 2 * sd, sv, gas.gm1);
+    const Prim<T> wm1 = ld_prim<T>(qb, c - sd, sv, gas.gm1);
+    const Prim<T> w0 = ld_prim<T>(qb, c, sv, gas.gm1);
+    const Prim<T> wp1 = ld_prim<T>(qb, c + sd, sv, gas.gm1);
+    area = face_inviscid<T>(wm2, wm1, w0, wp1, sx, sy, sz, gas, f, n);
+    if (VISC) {
+      phi_of(wm1, temp_of(wm1), pl);
+      phi_of(w0, temp_of(w0), pr);
+    }
+  }
   if (VISC) {
     const int64_t cl = c - sd;
-    tl = temp_of(wm1);
-    tr = temp_of(w0);
+    T dd[2][4];
     int tt = 0;
     for (int t = 0; t < 3; ++t) {
       if (t == d) continue;
       const int64_t st = dstride(t, B.sj, B.sk);
-      T a[4], b[4], e[4], f[4];
+      T a[4], b[4], e[4], ff[4];
       Prim<T> W;
       W = ld_prim<T>(qb, cl + st, sv, gas.gm1);
       phi_of(W, temp_of(W), a);
@@ -140,13 +158,15 @@ __device__ __forceinline__ void face_flux_global(const double* __restrict__ qb, 
       W = ld_prim<T>(qb, cl - st, sv, gas.gm1);
       phi_of(W, temp_of(W), e);
       W = ld_prim<T>(qb, c - st, sv, gas.gm1);
-      phi_of(W, temp_of(W), f);
-      tdiff(a, b, e, f, dd[tt]);
+      phi_of(W, temp_of(W), ff);
+      tdiff(a, b, e, ff, dd[tt]);
       ++tt;
     }
+    double St[2][3], vf;
     visc_metrics(mb, sv, cl, c, d, B.sj, B.sk, St, vf);
+    face_viscous<T>(pl, pr, sx, sy, sz, n, dd[0], dd[1], St, vf, gas, f);
   }
-  face_core<T, VISC>(wm2, wm1, w0, wp1, sx, sy, sz, tl, tr, dd[0], dd[1], St, vf, gas, F);
+  scale_flux_f64(f, area, F);
 }
 
 __device__ __forceinline__ void init_partials(double acc[NPART]) {
@@ -156,6 +176,38 @@ __device__ __forceinline__ void init_partials(double acc[NPART]) {
 }
 
 __device__ __forceinline__ bool finite(double x) { return !(isnan(x) || isinf(x)); }
+
+// Admissible time step of one cell with conserved state q (FP64):
+// dt_c = CFL V / (sum_d L_d + 4 sum_d Lv_d), S_d averaged over the cell's two
+// d-faces, L_d = |u . S_d| + c |S_d|, Lv_d = max(4/3, gamma/Pr)(mu/rho)|S_d|^2/V.
+__device__ __forceinline__ double cell_dt(const double q[5], const double* __restrict__ mb, int64_t c,
+                                          int64_t sv, int64_t sj, int64_t sk, const StepParams& P) {
+  const double gm1 = P.gamma - 1.0;
+  const double r = q[0];
+  const double inv = 1.0 / r;
+  const double u = q[1] * inv, v = q[2] * inv, w = q[3] * inv;
+  const double p = gm1 * (q[4] - 0.5 * r * (u * u + v * v + w * w));
+  const double cs = sqrt(P.gamma * p / r);
+  const double vol = mb[9 * sv + c];
+  const double coefv = fmax(4.0 / 3.0, P.gamma / P.prandtl);
+  double mu_r = 0.0;
+  if (P.viscous) {
+    const double t = p / r;
+    mu_r = P.mu_inf * t * sqrt(t) * (1.0 + P.s_star) / (t + P.s_star) / r;
+  }
+  double lam = 0.0, lamv = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int64_t sd = dstride(d, sj, sk);
+    const double bx = 0.5 * (mb[(3 * d) * sv + c] + mb[(3 * d) * sv + c + sd]);
+    const double by = 0.5 * (mb[(3 * d + 1) * sv + c] + mb[(3 * d + 1) * sv + c + sd]);
+    const double bz = 0.5 * (mb[(3 * d + 2) * sv + c] + mb[(3 * d + 2) * sv + c + sd]);
+    const double mag = sqrt(bx * bx + by * by + bz * bz);
+    lam += fabs(u * bx + v * by + w * bz) + cs * mag;
+    if (P.viscous) lamv += coefv * mu_r * mag * mag / vol;
+  }
+  return P.cfl * vol / (lam + 4.0 * lamv);
+}
 
 // Finish one interior cell: R = ((Di + Dj) + Dk) / V, then write R (mode 0)
 // or the stage update (modes 1, 2) and accumulate norm partials (mode 1).

@@ -108,6 +108,7 @@ def test_step_parity_fp32_flux(name, nsteps):
 
 TUNINGS = ({"kernel": 0, "use_graph": 1}, {"kernel": 0, "use_graph": 0},
            {"kernel": 0, "tile_j": 2, "tile_k": 3}, {"kernel": 0, "tile_j": 8, "tile_k": 64},
+           {"kernel": 0, "tile_j": 4, "tile_k": 5, "order": 1},
            {"kernel": 1, "tile_j": 1, "tile_k": 3}, {"kernel": 1, "tile_j": 16, "tile_k": 64})
 
 
