@@ -75,10 +75,13 @@ typedef struct {
 
 /* Physical boundary patch (the paper specifies none; these are the
  * library's): far field by Riemann invariants, slip wall, no-slip adiabatic
- * wall, zeroth-order extrapolation. */
+ * wall, zeroth-order extrapolation.  mach > 0 gives a far-field patch its own
+ * freestream Mach number (flow angles from cfd_params), so blocks of one
+ * context can carry different inflow conditions; mach <= 0 uses
+ * cfd_params.mach. */
 typedef enum { CFD_BC_FARFIELD = 1, CFD_BC_SLIPWALL = 2, CFD_BC_NOSLIP_ADIABATIC = 3,
                CFD_BC_EXTRAP = 4 } cfd_bc_kind;
-typedef struct { int32_t blk, face, kind; int32_t lo[2], hi[2]; } cfd_bc;
+typedef struct { int32_t blk, face, kind; int32_t lo[2], hi[2]; int32_t pad; double mach; } cfd_bc;
 
 /* Non-dimensional flow parameters: rho_inf = p_inf = 1, T = p/rho,
  * |u_inf| = mach*sqrt(gamma) along (cos a cos b, sin a cos b, sin b),

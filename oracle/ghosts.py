@@ -32,16 +32,17 @@ from .geometry import index_grid, patch_ranges, transverse
 FARFIELD, SLIPWALL, NOSLIP_ADIABATIC, EXTRAP = 1, 2, 3, 4
 
 
-def freestream_primitives(params):
+def freestream_primitives(params, mach=0.0):
+    """rho, velocity, p of the freestream; mach > 0 overrides the case's Mach number."""
     g = params.gamma
-    speed = params.mach * math.sqrt(g)
+    speed = (mach if mach > 0.0 else params.mach) * math.sqrt(g)
     u = speed * np.array([math.cos(params.alpha) * math.cos(params.beta),
                           math.sin(params.alpha) * math.cos(params.beta),
                           math.sin(params.beta)])
     return 1.0, u, 1.0
 
 
-def _farfield_state(Qi, n_out, params):
+def _farfield_state(Qi, n_out, params, mach=0.0):
     """Characteristic far-field state for interior states Qi [5,...], outward normals n [3,...]."""
     g = params.gamma
     rho = Qi[0]
@@ -49,7 +50,7 @@ def _farfield_state(Qi, n_out, params):
     p = (g - 1.0) * (Qi[4] - 0.5 * rho * np.sum(u * u, axis=0))
     ci = np.sqrt(g * p / rho)
     Ui = np.sum(u * n_out, axis=0)
-    rinf, uinf, pinf = freestream_primitives(params)
+    rinf, uinf, pinf = freestream_primitives(params, mach)
     uinf = uinf.reshape(3, *([1] * (Qi.ndim - 1)))
     cinf = math.sqrt(g * pinf / rinf)
     Uinf = np.sum(uinf * n_out, axis=0)
@@ -150,7 +151,7 @@ def _fill_bc(Q, S, dims, bc, params, g):
             r0[d] = (i0, i0 + 1)
             Q0 = Q[(slice(None),) + index_grid(r0, g)]
             n_out = -nhat if side == 0 else nhat
-            Qg = _farfield_state(Q0, n_out, params)
+            Qg = _farfield_state(Q0, n_out, params, getattr(bc, "mach", 0.0))
         else:
             raise ValueError(f"unknown boundary kind {bc.kind}")
         Q[(slice(None),) + index_grid(rd, g)] = Qg

@@ -35,7 +35,7 @@ class ConnS(C.Structure):
 
 class BCS(C.Structure):
     _fields_ = [("blk", C.c_int32), ("face", C.c_int32), ("kind", C.c_int32),
-                ("lo", C.c_int32 * 2), ("hi", C.c_int32 * 2)]
+                ("lo", C.c_int32 * 2), ("hi", C.c_int32 * 2), ("pad", C.c_int32), ("mach", C.c_double)]
 
 
 class ParamsS(C.Structure):
@@ -141,6 +141,7 @@ def to_bcs(bcs):
         a.blk, a.face, a.kind = b.blk, b.face, b.kind
         a.lo[:] = list(b.lo)
         a.hi[:] = list(b.hi)
+        a.mach = float(getattr(b, "mach", 0.0))
     return arr
 
 

@@ -77,6 +77,7 @@ class BC:
     kind: int
     lo: Tuple[int, int]
     hi: Tuple[int, int]
+    mach: float = 0.0   # far field: this patch's freestream Mach (<= 0: the case's)
 
 
 @dataclass
@@ -390,6 +391,51 @@ def channel_case(ni: int, nj: int, nk: int, mach: float, hb: float, cfl: float =
     bcs = [full_bc(0, dims, 0, FARFIELD), full_bc(0, dims, 1, FARFIELD),
            full_bc(0, dims, 2, SLIPWALL), full_bc(0, dims, 3, SLIPWALL)]
     return Case("channel", par, [dims], [X], conns, bcs, [q], info={"mach": mach, "hb": hb})
+
+
+def channel_batch_case(conds, ni: int = 48, nj: int = 24, nk: int = 24, cfl: float = 1.0,
+                       local_dt: int = 1) -> Case:
+    """Independent channel-bump cases side by side, one block each.
+
+    ``conds[b] = (inflow Mach, bump height)``.  Each block is its own channel
+    (periodic in z onto itself, far field on the i faces carrying that block's
+    Mach number, slip walls on the j faces) starting from its own uniform
+    stream, so one context advances all cases at once.
+    """
+    dims_b = (ni, nj, nk)
+    par = Params(mach=float(conds[0][0]), viscous=0, cfl=cfl, local_dt=local_dt)
+    dims, nodes, q0, conns, bcs = [], [], [], [], []
+    for b, (m, hb) in enumerate(conds):
+        dims.append(dims_b)
+        nodes.append(channel_nodes(ni, nj, nk, float(hb)))
+        q0.append(uniform_state(dims_b, replace(par, mach=float(m))))
+        conns += periodic_pair(b, dims_b, 2, 1.0)
+        for face, kind in ((0, FARFIELD), (1, FARFIELD), (2, SLIPWALL), (3, SLIPWALL)):
+            bc = full_bc(b, dims_b, face, kind)
+            bc.mach = float(m) if kind == FARFIELD else 0.0
+            bcs.append(bc)
+    return Case("channel_batch", par, dims, nodes, conns, bcs, q0,
+                info={"conds": [(float(m), float(h)) for m, h in conds]})
+
+
+def mlp_init(d_in: int = 5, d_hidden: int = 128, n_hidden: int = 4, d_out: int = 5, seed: int = 0,
+             out_scale: float = 0.1):
+    """Seeded initial weights of the warm-start network: list of (W [out, in], b [out]).
+
+    Glorot-uniform weights, zero biases; the output layer is scaled by
+    ``out_scale`` so the initial prediction is close to the inflow stream.
+    """
+    rng = np.random.default_rng(seed)
+    sizes = [d_in] + [d_hidden] * n_hidden + [d_out]
+    out = []
+    for l in range(len(sizes) - 1):
+        fi, fo = sizes[l], sizes[l + 1]
+        a = math.sqrt(6.0 / (fi + fo))
+        W = rng.uniform(-a, a, (fo, fi))
+        if l == len(sizes) - 2:
+            W = W * out_scale
+        out.append((W, np.zeros(fo)))
+    return out
 
 
 def channel_conditions(n: int, seed: int) -> np.ndarray:

@@ -36,7 +36,8 @@ struct PatchDesc {
   int32_t noff[3];                // neighbour index = own index + noff (transverse); unused for d
   int32_t count;                  // number of transverse points
   int32_t pad0;
-  double shift[3];
+  double shift[3];                // connections: added to neighbour node coordinates
+  double uinf[3];                 // far field: freestream velocity of this patch
 };
 
 // One tile of the stage work list.

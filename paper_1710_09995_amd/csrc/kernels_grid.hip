@@ -202,7 +202,7 @@ __global__ void k_ghost_q(double* __restrict__ q, const double* __restrict__ met
     for (int v = 0; v < NV; ++v) qi[v] = qb[v * B.sv + o0];
     if (P.kind == CFD_BC_KIND_FARFIELD) {
       const double s = side == 0 ? -1.0 : 1.0;
-      farfield_state(qi, s * nx, s * ny, s * nz, SP, qg);
+      farfield_state(qi, s * nx, s * ny, s * nz, SP.gamma, P.uinf, qg);
     } else {
       for (int v = 0; v < NV; ++v) qg[v] = qi[v];
     }

@@ -216,15 +216,15 @@ __device__ __forceinline__ void viscous_n(const T g[4][3], const T uf[3], T tf, 
 // Characteristic far-field boundary state (FP64): interior conserved state q,
 // outward unit normal n; writes the boundary conserved state.
 __device__ __forceinline__ void farfield_state(const double q[5], double nx, double ny, double nz,
-                                               const StepParams& P, double out[5]) {
-  const double g = P.gamma, gm1 = g - 1.0;
+                                               double g, const double uinf[3], double out[5]) {
+  const double gm1 = g - 1.0;
   double rho = q[0];
   double inv = 1.0 / rho;
   double u = q[1] * inv, v = q[2] * inv, w = q[3] * inv;
   double p = gm1 * (q[4] - 0.5 * rho * (u * u + v * v + w * w));
   double ci = sqrt(g * p / rho);
   double Ui = u * nx + v * ny + w * nz;
-  double ux = P.uinf[0], uy = P.uinf[1], uz = P.uinf[2];
+  double ux = uinf[0], uy = uinf[1], uz = uinf[2];
   double cinf = sqrt(g);
   double Uinf = ux * nx + uy * ny + uz * nz;
   double rb, pb, ub, vb, wb;

@@ -234,6 +234,7 @@ void validate_tables(int nblk, const cfd_dims* dims, int nconn, const cfd_conn* 
     if (B.blk < 0 || B.blk >= nblk) fail(CFD_EINVAL, "boundary %d: bad block", c);
     if (B.face < 0 || B.face > 5) fail(CFD_EINVAL, "boundary %d: bad face", c);
     if (B.kind < CFD_BC_FARFIELD || B.kind > CFD_BC_EXTRAP) fail(CFD_EINVAL, "boundary %d: bad kind %d", c, B.kind);
+    if (!std::isfinite(B.mach)) fail(CFD_EINVAL, "boundary %d: non-finite mach", c);
     mark(B.blk, B.face, B.lo, B.hi, "boundary", c);
   }
   for (int b = 0; b < nblk; ++b)
@@ -244,11 +245,18 @@ void validate_tables(int nblk, const cfd_dims* dims, int nconn, const cfd_conn* 
 
 // Patch descriptors for sweep d (cells or nodes), with the transverse
 // extension into ghost layers of directions swept earlier.
-void build_patches(int d, bool nodes, int nblk, const cfd_dims* dims, int nconn, const cfd_conn* conns,
-                   int nbc, const cfd_bc* bcs, std::vector<PatchDesc>& out, int& maxcount) {
+void build_patches(int d, bool nodes, const cfd_params* params, const cfd_dims* dims, int nconn,
+                   const cfd_conn* conns, int nbc, const cfd_bc* bcs, std::vector<PatchDesc>& out, int& maxcount) {
   auto make = [&](int blk, int face, int kind, int nbr, const int32_t lo[2], const int32_t hi[2],
-                  const int32_t* nbr_lo, const double* shift) {
+                  const int32_t* nbr_lo, const double* shift, double mach) {
     PatchDesc P{};
+    if (params) {   // freestream velocity of this patch (far field)
+      const double m = mach > 0.0 ? mach : params->mach;
+      const double speed = m * std::sqrt(params->gamma);
+      P.uinf[0] = speed * std::cos(params->alpha) * std::cos(params->beta);
+      P.uinf[1] = speed * std::sin(params->alpha) * std::cos(params->beta);
+      P.uinf[2] = speed * std::sin(params->beta);
+    }
     P.blk = blk;
     P.face = face;
     P.kind = kind;
@@ -275,10 +283,12 @@ void build_patches(int d, bool nodes, int nblk, const cfd_dims* dims, int nconn,
     out.push_back(P);
   };
   for (int c = 0; c < nbc; ++c)
-    if ((bcs[c].face >> 1) == d) make(bcs[c].blk, bcs[c].face, bcs[c].kind, -1, bcs[c].lo, bcs[c].hi, nullptr, nullptr);
+    if ((bcs[c].face >> 1) == d)
+      make(bcs[c].blk, bcs[c].face, bcs[c].kind, -1, bcs[c].lo, bcs[c].hi, nullptr, nullptr, bcs[c].mach);
   for (int c = 0; c < nconn; ++c)
     if ((conns[c].face >> 1) == d)
-      make(conns[c].blk, conns[c].face, 0, conns[c].nbr, conns[c].lo, conns[c].hi, conns[c].nbr_lo, conns[c].shift);
+      make(conns[c].blk, conns[c].face, 0, conns[c].nbr, conns[c].lo, conns[c].hi, conns[c].nbr_lo, conns[c].shift,
+           0.0);
 }
 
 }  // namespace
@@ -666,7 +676,7 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
       const int d = sweep % 3;
       c->poff[sweep] = (int)all.size();
       int mx = 0;
-      build_patches(d, nodes, nblk, dims, nconn, conns, nbc, bcs, all, mx);
+      build_patches(d, nodes, params, dims, nconn, conns, nbc, bcs, all, mx);
       c->pcount[sweep] = (int)all.size() - c->poff[sweep];
       c->pmax[sweep] = mx;
     }

@@ -284,3 +284,19 @@ def test_norms_definitions():
     assert out[10] == 3.0
     V = (10.0 / 8) ** 3
     assert abs(out[5] - V * float(np.sum(c.q0[0][0]))) < 1e-12
+
+
+def test_batched_channels_match_single_cases():
+    """Blocks of a batched context with per-patch inflow Mach behave exactly like
+    the corresponding single-case runs (independent blocks, own freestream)."""
+    conds = [(0.55, 0.03), (0.8, 0.09)]
+    bc = cases.channel_batch_case(conds, 12, 6, 4)
+    sb = solver.setup(bc)
+    for _ in range(2):
+        solver.step(sb)
+    for b, (m, h) in enumerate(conds):
+        c = cases.channel_case(12, 6, 4, mach=m, hb=h)
+        s1 = solver.setup(c)
+        for _ in range(2):
+            solver.step(s1)
+        assert np.array_equal(solver.interior_state(sb, b), solver.interior_state(s1, 0))
