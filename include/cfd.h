@@ -192,6 +192,57 @@ cfd_status cfd_profile_read(cfd_ctx* ctx, double out[12]);
  * (the geometric conservation requirement of Section 2.2). */
 cfd_status cfd_copy_metrics(cfd_ctx* ctx, int32_t blk, double* out_dev, hipStream_t stream);
 
+/* ---------------------------------------------------------------- warm start
+ * A multilayer perceptron predicts the steady flow of a channel-bump case
+ * from its condition and a cell position, giving the time march a warm start
+ * instead of the uniform stream.  (The paper's solver starts from an
+ * initialised flow field, Section 2.3, and iterates to convergence; the
+ * learned initial field is this library's addition.)
+ *   features (5): [(M - 0.675)/0.175, (h - 0.06)/0.04, 2 xi - 1, 2 eta - 1,
+ *                  2 zeta - 1], xi = (i + 1/2)/ni etc. over a block's cells;
+ *   network: n_hidden SiLU layers of width d_hidden, linear output;
+ *   outputs (5): (rho - 1, u - M sqrt(gamma), v, w, p - 1).
+ * Inference runs on BF16 matrix cores (MFMA) with FP32 accumulation; training
+ * uses FP32 backward kernels with fixed-order reductions and Adam on FP32
+ * master weights.  Parameter layout (padded): for each layer W [N][K]
+ * (output-major) then b [N]; K of the input layer is 16 (inputs zero
+ * padded), N of the output layer is 16 (outputs zero padded).  BF16 values
+ * are raw uint16 bit patterns.  Cells are ordered block, k, j, i (i fastest). */
+typedef struct { int32_t d_in, d_hidden, n_hidden, d_out, activation; } cfd_mlp_desc;  /* activation 1 = SiLU */
+
+/* Parameter count (padded layout), cache floats per point for training, and
+ * the workspace bytes cfd_mlp_mse / cfd_mlp_backward need for n points. */
+cfd_status cfd_mlp_sizes(const cfd_mlp_desc* desc, int64_t n, int64_t* n_params, int64_t* cache_per_point,
+                         size_t* work_bytes);
+/* y[n][d_out] = MLP(x[idx[p]] or x[p]); with cache != NULL also stores each
+ * layer's input and pre-activation for cfd_mlp_backward. */
+cfd_status cfd_mlp_forward(const cfd_mlp_desc* desc, const uint16_t* params_bf16, const float* x,
+                           const int32_t* idx, int64_t n, float* y, float* cache, hipStream_t stream);
+/* Mean squared error against t[idx[p]] (or t[p]); dy = d loss / d y;
+ * loss_dev (device, 1 double). */
+cfd_status cfd_mlp_mse(const cfd_mlp_desc* desc, const float* y, const float* t, const int32_t* idx, int64_t n,
+                       float* dy, double* loss_dev, void* work, size_t work_bytes, hipStream_t stream);
+/* Gradient of the loss w.r.t. all parameters (padded layout, FP32). */
+cfd_status cfd_mlp_backward(const cfd_mlp_desc* desc, const uint16_t* params_bf16, const float* cache,
+                            const float* dy, int64_t n, float* grad, void* work, size_t work_bytes,
+                            hipStream_t stream);
+/* Adam step t (1-based) on the FP32 master weights; refreshes the BF16 copy. */
+cfd_status cfd_mlp_adam(const cfd_mlp_desc* desc, float* master, float* m, float* v, const float* grad,
+                        uint16_t* params_bf16, float lr, float beta1, float beta2, float eps, int32_t t,
+                        hipStream_t stream);
+/* BF16 copy of FP32 master weights (round to nearest even). */
+cfd_status cfd_mlp_to_bf16(const cfd_mlp_desc* desc, const float* master, uint16_t* params_bf16,
+                           hipStream_t stream);
+/* Features of every interior cell of every block: x[ncells][5]; cond_dev is
+ * [nblk][2] = (inflow Mach, bump height) per block, FP64 device memory. */
+cfd_status cfd_mlp_features(cfd_ctx* ctx, const double* cond_dev, float* x, hipStream_t stream);
+/* Training targets from a state arena: t[ncells][5] primitive deviations. */
+cfd_status cfd_mlp_targets(cfd_ctx* ctx, const double* q_arena_dev, const double* cond_dev, float* t,
+                           hipStream_t stream);
+/* Write the interior state from network outputs y[ncells][5] (warm start). */
+cfd_status cfd_mlp_to_state(cfd_ctx* ctx, const float* y, const double* cond_dev, double* q_arena_dev,
+                            hipStream_t stream);
+
 const char* cfd_status_string(cfd_status s);
 const char* cfd_last_error(const cfd_ctx* ctx);   /* ctx may be NULL: last global error */
 

@@ -49,9 +49,16 @@ class Tuning(C.Structure):
                 ("use_graph", C.c_int32), ("order", C.c_int32)]
 
 
+class MlpDesc(C.Structure):
+    _fields_ = [("d_in", C.c_int32), ("d_hidden", C.c_int32), ("n_hidden", C.c_int32), ("d_out", C.c_int32),
+                ("activation", C.c_int32)]
+
+
 EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy", "cfd_set_tuning",
            "cfd_get_tuning", "cfd_fill_ghosts", "cfd_residual", "cfd_step", "cfd_norms",
            "cfd_time_step", "cfd_copy_metrics", "cfd_set_profiling", "cfd_profile_read",
+           "cfd_mlp_sizes", "cfd_mlp_forward", "cfd_mlp_mse", "cfd_mlp_backward", "cfd_mlp_adam",
+           "cfd_mlp_to_bf16", "cfd_mlp_features", "cfd_mlp_targets", "cfd_mlp_to_state",
            "cfd_status_string", "cfd_last_error"]
 
 _lib = None
@@ -85,6 +92,16 @@ def lib(build_if_missing: bool = True):
     L.cfd_copy_metrics.argtypes = [vp, i32, vp, vp]
     L.cfd_set_profiling.argtypes = [vp, i32]
     L.cfd_profile_read.argtypes = [vp, C.POINTER(C.c_double)]
+    dp = C.POINTER(MlpDesc)
+    L.cfd_mlp_sizes.argtypes = [dp, C.c_int64, i64p, i64p, C.POINTER(C.c_size_t)]
+    L.cfd_mlp_forward.argtypes = [dp, vp, vp, vp, C.c_int64, vp, vp, vp]
+    L.cfd_mlp_mse.argtypes = [dp, vp, vp, vp, C.c_int64, vp, vp, vp, C.c_size_t, vp]
+    L.cfd_mlp_backward.argtypes = [dp, vp, vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]
+    L.cfd_mlp_adam.argtypes = [dp, vp, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]
+    L.cfd_mlp_to_bf16.argtypes = [dp, vp, vp, vp]
+    L.cfd_mlp_features.argtypes = [vp, vp, vp, vp]
+    L.cfd_mlp_targets.argtypes = [vp, vp, vp, vp, vp]
+    L.cfd_mlp_to_state.argtypes = [vp, vp, vp, vp, vp]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]
@@ -316,3 +333,148 @@ class Solver:
         if st != CFD_OK and not (st == -4 and not check):
             _check(st, self.ctx)
         return np.array(out[:])
+
+    # ------------------------------------------------------------ warm start
+    def mlp_features(self, cond):
+        """Features x[ncells][5] of every interior cell; cond [nblk][2] (Mach, bump height)."""
+        torch = self.torch
+        c = torch.as_tensor(np.asarray(cond, dtype=np.float64).reshape(-1, 2), device=self.device)
+        x = torch.empty((self.case.ncells, 5), dtype=torch.float32, device=self.device)
+        _check(lib().cfd_mlp_features(self.ctx, _ptr(c), _ptr(x), self._s()), self.ctx)
+        return x
+
+    def mlp_targets(self, cond, arena=None):
+        arena = self.q if arena is None else arena
+        torch = self.torch
+        c = torch.as_tensor(np.asarray(cond, dtype=np.float64).reshape(-1, 2), device=self.device)
+        t = torch.empty((self.case.ncells, 5), dtype=torch.float32, device=self.device)
+        _check(lib().cfd_mlp_targets(self.ctx, _ptr(arena), _ptr(c), _ptr(t), self._s()), self.ctx)
+        return t
+
+    def mlp_to_state(self, y, cond, arena=None):
+        arena = self.q if arena is None else arena
+        c = self.torch.as_tensor(np.asarray(cond, dtype=np.float64).reshape(-1, 2), device=self.device)
+        _check(lib().cfd_mlp_to_state(self.ctx, _ptr(y), _ptr(c), _ptr(arena), self._s()), self.ctx)
+
+
+# ---------------------------------------------------------------------- MLP
+
+def mlp_layout(d_in, d_hidden, n_hidden, d_out):
+    """[(woff, N, K, boff)] of the padded parameter layout (see include/cfd.h)."""
+    out, off = [], 0
+    for l in range(n_hidden + 1):
+        K = 16 if l == 0 else d_hidden
+        N = 16 if l == n_hidden else d_hidden
+        out.append((off, N, K, off + N * K))
+        off += N * K + N
+    return out, off
+
+
+def pack_params(params, d_in, d_hidden, n_hidden, d_out):
+    """Unpadded [(W [out, in], b)] -> padded flat float32 vector."""
+    lay, total = mlp_layout(d_in, d_hidden, n_hidden, d_out)
+    flat = np.zeros(total, dtype=np.float32)
+    for (woff, N, K, boff), (W, b) in zip(lay, params):
+        Wp = np.zeros((N, K), dtype=np.float32)
+        Wp[:W.shape[0], :W.shape[1]] = W
+        flat[woff:woff + N * K] = Wp.ravel()
+        bp = np.zeros(N, dtype=np.float32)
+        bp[:b.shape[0]] = b
+        flat[boff:boff + N] = bp
+    return flat
+
+
+def unpack_params(flat, d_in, d_hidden, n_hidden, d_out):
+    lay, _ = mlp_layout(d_in, d_hidden, n_hidden, d_out)
+    sizes = [d_in] + [d_hidden] * n_hidden + [d_out]
+    out = []
+    for l, (woff, N, K, boff) in enumerate(lay):
+        W = np.asarray(flat[woff:woff + N * K], dtype=np.float64).reshape(N, K)[:sizes[l + 1], :sizes[l]]
+        b = np.asarray(flat[boff:boff + N], dtype=np.float64)[:sizes[l + 1]]
+        out.append((W.copy(), b.copy()))
+    return out
+
+
+class Mlp:
+    """Device-resident warm-start network: BF16 weights for inference, FP32
+    master weights, Adam moments and gradients for training."""
+
+    def __init__(self, params, d_in=5, d_hidden=128, n_hidden=4, d_out=5, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream
+        self.desc = MlpDesc(d_in, d_hidden, n_hidden, d_out, 1)
+        self.dims = (d_in, d_hidden, n_hidden, d_out)
+        npar = C.c_int64()
+        cpp = C.c_int64()
+        _check(lib().cfd_mlp_sizes(C.byref(self.desc), 0, C.byref(npar), C.byref(cpp), None))
+        self.nparam, self.cache_per_point = int(npar.value), int(cpp.value)
+        flat = pack_params(params, *self.dims)
+        assert flat.size == self.nparam
+        self.master = torch.from_numpy(flat).to(self.device)
+        self.bf16 = torch.empty(self.nparam, dtype=torch.int16, device=self.device)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.grad = torch.zeros_like(self.master)
+        self.t = 0
+        self._work = None
+        _check(lib().cfd_mlp_to_bf16(C.byref(self.desc), _ptr(self.master), _ptr(self.bf16), self._s()))
+
+    def _s(self):
+        return _stream_handle(self.torch, self.stream)
+
+    def params(self):
+        return unpack_params(self.master.cpu().numpy(), *self.dims)
+
+    def bf16_params(self):
+        """The BF16 weights as float64 (unpadded)."""
+        raw = self.bf16.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+        return unpack_params(raw.view(np.float32), *self.dims)
+
+    def workspace(self, n):
+        ws = C.c_size_t()
+        _check(lib().cfd_mlp_sizes(C.byref(self.desc), int(n), None, None, C.byref(ws)))
+        if self._work is None or self._work.numel() < ws.value:
+            self._work = self.torch.empty(int(ws.value), dtype=self.torch.uint8, device=self.device)
+        return self._work, int(ws.value)
+
+    def forward(self, x, idx=None, n=None, cache=False):
+        torch = self.torch
+        n = int(x.shape[0] if idx is None else idx.shape[0]) if n is None else n
+        y = torch.empty((n, self.dims[3]), dtype=torch.float32, device=self.device)
+        cb = torch.empty((n, self.cache_per_point), dtype=torch.float32, device=self.device) if cache else None
+        _check(lib().cfd_mlp_forward(C.byref(self.desc), _ptr(self.bf16), _ptr(x),
+                                     _ptr(idx) if idx is not None else None, n, _ptr(y),
+                                     _ptr(cb) if cb is not None else None, self._s()))
+        return (y, cb) if cache else y
+
+    def mse(self, y, t, idx=None):
+        torch = self.torch
+        n = y.shape[0]
+        dy = torch.empty_like(y)
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        w, wb = self.workspace(n)
+        _check(lib().cfd_mlp_mse(C.byref(self.desc), _ptr(y), _ptr(t), _ptr(idx) if idx is not None else None, n,
+                                 _ptr(dy), _ptr(loss), _ptr(w), wb, self._s()))
+        return loss, dy
+
+    def backward(self, cache, dy):
+        n = dy.shape[0]
+        w, wb = self.workspace(n)
+        _check(lib().cfd_mlp_backward(C.byref(self.desc), _ptr(self.bf16), _ptr(cache), _ptr(dy), n,
+                                      _ptr(self.grad), _ptr(w), wb, self._s()))
+        return self.grad
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.t += 1
+        _check(lib().cfd_mlp_adam(C.byref(self.desc), _ptr(self.master), _ptr(self.m), _ptr(self.v),
+                                  _ptr(self.grad), _ptr(self.bf16), lr, b1, b2, eps, self.t, self._s()))
+
+    def train_step(self, x, t, idx, lr=1e-3):
+        """One minibatch: forward (with cache), MSE, backward, Adam; returns the loss tensor."""
+        y, cache = self.forward(x, idx=idx, cache=True)
+        loss, dy = self.mse(y, t, idx)
+        self.backward(cache, dy)
+        self.adam(lr)
+        return loss

@@ -53,6 +53,28 @@ struct Gas {
   T uinf[3];
 };
 
+// Warm-start network geometry (padded parameter layout, training cache).
+constexpr int MLP_KIN = 16;          // input features padded to one MFMA k-step
+constexpr int MLP_NOUT = 16;         // outputs padded to one MFMA tile
+constexpr int MLP_MAX_LAYERS = 9;
+struct MlpDims {
+  int d_in, d_hidden, n_hidden, d_out;
+  int nlayer;                        // n_hidden + 1 weight matrices
+  int K[MLP_MAX_LAYERS], N[MLP_MAX_LAYERS];
+  int64_t woff[MLP_MAX_LAYERS];      // offset of W_l (elements)
+  int64_t boff[MLP_MAX_LAYERS];      // offset of b_l
+  int64_t hoff[MLP_MAX_LAYERS];      // cache: layer input h_l, per-point offset (floats)
+  int64_t zoff[MLP_MAX_LAYERS];      // cache: pre-activation z_l, per-point offset
+  int64_t nparam, cache_per_point;
+};
+
+// Interior cells of all blocks, numbered block by block (k, j, i; i fastest).
+struct CellMap {
+  const BlockDesc* blocks;
+  const int64_t* cell_start;         // [nblk + 1] prefix sums of interior cell counts
+  int nblk;
+};
+
 struct StepParams {
   double gamma, prandtl, mu_inf, s_star, cfl, eps_h, eps_lim;
   double uinf[3];

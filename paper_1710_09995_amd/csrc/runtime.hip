@@ -40,6 +40,20 @@ void launch_dt(const double* q, const double* met, double* dtcell, double* parti
 void launch_norms(const double* q, const double* r, const double* met, double* partials,
                   const BlockDesc* blocks, const TileDesc* tiles, int ntiles, int tile_j, int tile_k,
                   int nwg, hipStream_t s);
+void mlp_forward(const MlpDims& D, const uint16_t* P, const float* x, const int32_t* idx, int64_t n, float* y,
+                 float* cache, hipStream_t s);
+int mlp_mse(const float* y, const float* t, const int32_t* idx, int64_t n, int d_out, float* dy, double* partials,
+            int max_rows, double* loss, hipStream_t s);
+void mlp_backward(const MlpDims& D, const uint16_t* P, const float* cache, const float* dy, int64_t n, float* grad,
+                  float* dz, float* da, float* part, int nchunk, hipStream_t s);
+void mlp_adam(int64_t np, float* master, float* m, float* v, const float* g, uint16_t* pbf, float lr, float b1,
+              float b2, float eps, int t, hipStream_t s);
+void mlp_to_bf16(int64_t np, const float* master, uint16_t* pbf, hipStream_t s);
+void mlp_features(const CellMap& M, int64_t ncells, const double* cond, float* x, hipStream_t s);
+void mlp_targets(const CellMap& M, int64_t ncells, const double* q, const double* cond, double gamma, float* t,
+                 hipStream_t s);
+void mlp_to_state(const CellMap& M, int64_t ncells, const float* y, const double* cond, double gamma, double* q,
+                  hipStream_t s);
 void launch_finalize(const double* partials, int nrows, int mode, double inv_ncells, double* dt,
                      double* hist, double* nonfinite, hipStream_t s);
 }  // namespace cfd
@@ -115,7 +129,7 @@ Layout make_layout(int nblk, const cfd_dims* dims) {
 }
 
 struct WsLayout {
-  size_t met, qa, qb, scal, blocks, patches, tiles, part_dt, part_nrm, scalars, total;
+  size_t met, qa, qb, scal, blocks, patches, tiles, part_dt, part_nrm, scalars, cell_start, total;
   size_t node_scratch;   // aliases qa.. during setup
   int64_t max_tiles;
   int npatch_total;
@@ -157,6 +171,8 @@ WsLayout make_ws(const Layout& L, int nblk, const cfd_dims* dims, int npatch_tot
   c = align256(c + sizeof(double) * NPART * NWG_MAX);
   W.scalars = c;   // dt, hist[12], nonfinite, norms_out[12]
   c = align256(c + sizeof(double) * 32);
+  W.cell_start = c;   // interior-cell prefix sums per block (warm-start kernels)
+  c = align256(c + sizeof(int64_t) * (nblk + 1));
   W.total = c;
   W.npatch_total = npatch_total;
   return W;
@@ -362,6 +378,8 @@ struct cfd_ctx {
   double* d_hist() const { return d_dt() + 1; }
   double* d_nonfinite() const { return d_dt() + 13; }
   double* d_norms() const { return d_dt() + 16; }
+  int64_t* d_cell_start() const { return reinterpret_cast<int64_t*>(ws + W.cell_start); }
+  CellMap cell_map() const { return CellMap{dblocks, d_cell_start(), nblk}; }
 
   void drop_graph() {
     if (gexec) hipGraphExecDestroy(gexec);
@@ -703,6 +721,12 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
                            stream);
     check_launch();
     HIPCHK(hipStreamSynchronize(stream));
+    {
+      std::vector<int64_t> cs(nblk + 1, 0);
+      for (int b = 0; b < nblk; ++b) cs[b + 1] = cs[b] + (int64_t)dims[b].ni * dims[b].nj * dims[b].nk;
+      HIPCHK(hipMemcpyAsync(c->d_cell_start(), cs.data(), sizeof(int64_t) * cs.size(), hipMemcpyHostToDevice,
+                            stream));
+    }
     build_tiles(c, stream);
     *out = c;
   });
@@ -890,6 +914,151 @@ cfd_status cfd_copy_metrics(cfd_ctx* c, int32_t blk, double* out, hipStream_t s)
       HIPCHK(hipMemcpy2DAsync(out + (size_t)m * wi * hj * dk, wi * sizeof(double),
                               c->met() + B.moff + (int64_t)m * B.sv, (size_t)B.sj * sizeof(double),
                               wi * sizeof(double), hj * dk, hipMemcpyDeviceToDevice, s));
+  });
+}
+
+// ------------------------------------------------------------------ warm start
+
+namespace {
+
+constexpr int MLP_CHUNKS = 32;       // point chunks of the weight-gradient reduction
+constexpr int MLP_MSE_ROWS = 1024;   // loss partial rows
+
+MlpDims mlp_dims(const cfd_mlp_desc* d) {
+  if (!d) fail(CFD_EINVAL, "mlp desc is NULL");
+  if (d->activation != 1) fail(CFD_EUNSUPPORTED, "only SiLU (activation 1) is implemented");
+  if (d->d_in < 1 || d->d_in > MLP_KIN) fail(CFD_EINVAL, "d_in must be in [1, %d]", MLP_KIN);
+  if (d->d_out < 1 || d->d_out > MLP_NOUT) fail(CFD_EINVAL, "d_out must be in [1, %d]", MLP_NOUT);
+  if (d->d_hidden < 16 || d->d_hidden > 128 || d->d_hidden % 16)
+    fail(CFD_EINVAL, "d_hidden must be a multiple of 16 in [16, 128]");
+  if (d->n_hidden < 1 || d->n_hidden > MLP_MAX_LAYERS - 1) fail(CFD_EINVAL, "n_hidden must be in [1, 8]");
+  MlpDims D{};
+  D.d_in = d->d_in;
+  D.d_hidden = d->d_hidden;
+  D.n_hidden = d->n_hidden;
+  D.d_out = d->d_out;
+  D.nlayer = d->n_hidden + 1;
+  int64_t po = 0, co = 0;
+  for (int l = 0; l < D.nlayer; ++l) {
+    D.K[l] = l == 0 ? MLP_KIN : d->d_hidden;
+    D.N[l] = l == D.nlayer - 1 ? MLP_NOUT : d->d_hidden;
+    D.woff[l] = po;
+    po += (int64_t)D.N[l] * D.K[l];
+    D.boff[l] = po;
+    po += D.N[l];
+    D.hoff[l] = co;
+    co += D.K[l];
+    D.zoff[l] = co;
+    co += D.N[l];
+  }
+  D.nparam = po;
+  D.cache_per_point = co;
+  return D;
+}
+
+size_t mlp_work_bytes(const MlpDims& D, int64_t n) {
+  const size_t act = align256((size_t)n * D.d_hidden * sizeof(float));
+  int64_t maxw = 0;
+  for (int l = 0; l < D.nlayer; ++l) maxw = std::max<int64_t>(maxw, (int64_t)D.N[l] * D.K[l] + D.N[l]);
+  return 2 * act + align256((size_t)MLP_CHUNKS * maxw * sizeof(float)) + align256(MLP_MSE_ROWS * sizeof(double));
+}
+
+}  // namespace
+
+cfd_status cfd_mlp_sizes(const cfd_mlp_desc* desc, int64_t n, int64_t* n_params, int64_t* cache_per_point,
+                         size_t* work_bytes) {
+  return guard(nullptr, [&] {
+    const MlpDims D = mlp_dims(desc);
+    if (n < 0) fail(CFD_EINVAL, "n must be >= 0");
+    if (n_params) *n_params = D.nparam;
+    if (cache_per_point) *cache_per_point = D.cache_per_point;
+    if (work_bytes) *work_bytes = mlp_work_bytes(D, n);
+  });
+}
+
+cfd_status cfd_mlp_forward(const cfd_mlp_desc* desc, const uint16_t* params, const float* x, const int32_t* idx,
+                           int64_t n, float* y, float* cache, hipStream_t s) {
+  return guard(nullptr, [&] {
+    const MlpDims D = mlp_dims(desc);
+    if (!params || !x || !y || n < 0) fail(CFD_EINVAL, "bad forward arguments");
+    if (n == 0) return;
+    mlp_forward(D, params, x, idx, n, y, cache, s);
+    check_launch();
+  });
+}
+
+cfd_status cfd_mlp_mse(const cfd_mlp_desc* desc, const float* y, const float* t, const int32_t* idx, int64_t n,
+                       float* dy, double* loss, void* work, size_t work_bytes, hipStream_t s) {
+  return guard(nullptr, [&] {
+    const MlpDims D = mlp_dims(desc);
+    if (!y || !t || !dy || !loss || n <= 0 || !work) fail(CFD_EINVAL, "bad mse arguments");
+    if (work_bytes < mlp_work_bytes(D, n)) fail(CFD_ENOMEM, "mlp workspace too small");
+    const size_t act = align256((size_t)n * D.d_hidden * sizeof(float));
+    int64_t maxw = 0;
+    for (int l = 0; l < D.nlayer; ++l) maxw = std::max<int64_t>(maxw, (int64_t)D.N[l] * D.K[l] + D.N[l]);
+    double* part = reinterpret_cast<double*>(static_cast<char*>(work) + 2 * act +
+                                             align256((size_t)MLP_CHUNKS * maxw * sizeof(float)));
+    mlp_mse(y, t, idx, n, D.d_out, dy, part, MLP_MSE_ROWS, loss, s);
+    check_launch();
+  });
+}
+
+cfd_status cfd_mlp_backward(const cfd_mlp_desc* desc, const uint16_t* params, const float* cache, const float* dy,
+                            int64_t n, float* grad, void* work, size_t work_bytes, hipStream_t s) {
+  return guard(nullptr, [&] {
+    const MlpDims D = mlp_dims(desc);
+    if (!params || !cache || !dy || !grad || n <= 0 || !work) fail(CFD_EINVAL, "bad backward arguments");
+    if (work_bytes < mlp_work_bytes(D, n)) fail(CFD_ENOMEM, "mlp workspace too small");
+    const size_t act = align256((size_t)n * D.d_hidden * sizeof(float));
+    char* w = static_cast<char*>(work);
+    float* dz = reinterpret_cast<float*>(w);
+    float* da = reinterpret_cast<float*>(w + act);
+    float* part = reinterpret_cast<float*>(w + 2 * act);
+    mlp_backward(D, params, cache, dy, n, grad, dz, da, part, MLP_CHUNKS, s);
+    check_launch();
+  });
+}
+
+cfd_status cfd_mlp_adam(const cfd_mlp_desc* desc, float* master, float* m, float* v, const float* grad,
+                        uint16_t* params, float lr, float b1, float b2, float eps, int32_t t, hipStream_t s) {
+  return guard(nullptr, [&] {
+    const MlpDims D = mlp_dims(desc);
+    if (!master || !m || !v || !grad || !params || t < 1) fail(CFD_EINVAL, "bad adam arguments");
+    mlp_adam(D.nparam, master, m, v, grad, params, lr, b1, b2, eps, t, s);
+    check_launch();
+  });
+}
+
+cfd_status cfd_mlp_to_bf16(const cfd_mlp_desc* desc, const float* master, uint16_t* params, hipStream_t s) {
+  return guard(nullptr, [&] {
+    const MlpDims D = mlp_dims(desc);
+    if (!master || !params) fail(CFD_EINVAL, "NULL argument");
+    mlp_to_bf16(D.nparam, master, params, s);
+    check_launch();
+  });
+}
+
+cfd_status cfd_mlp_features(cfd_ctx* c, const double* cond, float* x, hipStream_t s) {
+  return guard(c, [&] {
+    if (!c || !cond || !x) fail(CFD_EINVAL, "NULL argument");
+    mlp_features(c->cell_map(), c->ncells, cond, x, s);
+    check_launch();
+  });
+}
+
+cfd_status cfd_mlp_targets(cfd_ctx* c, const double* q, const double* cond, float* t, hipStream_t s) {
+  return guard(c, [&] {
+    if (!c || !q || !cond || !t) fail(CFD_EINVAL, "NULL argument");
+    mlp_targets(c->cell_map(), c->ncells, q, cond, c->params.gamma, t, s);
+    check_launch();
+  });
+}
+
+cfd_status cfd_mlp_to_state(cfd_ctx* c, const float* y, const double* cond, double* q, hipStream_t s) {
+  return guard(c, [&] {
+    if (!c || !y || !cond || !q) fail(CFD_EINVAL, "NULL argument");
+    mlp_to_state(c->cell_map(), c->ncells, y, cond, c->params.gamma, q, s);
+    check_launch();
   });
 }
 
