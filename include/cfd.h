@@ -176,13 +176,14 @@ cfd_status cfd_time_step(cfd_ctx* ctx, const double* q_arena_dev, double* dt_dev
 
 /* Kernel timing.  With profiling on, cfd_step runs without its graph and
  * records a hipEvent pair around every launch of the residual/stage kernel,
- * the ghost-fill sweeps and the time-step kernel, on the stream they run on.
- * cfd_profile_read synchronises those events and writes, per kernel class
- * (0 = stage, 1 = ghost-fill sweep, 2 = time step):
+ * the ghost-fill sweeps, the time-step kernel and the norms kernel, on the
+ * stream they run on.  cfd_profile_read synchronises those events and writes,
+ * per kernel class (0 = stage, 1 = ghost-fill sweep, 2 = time step,
+ * 3 = norms):
  *   out[4*c + 0] = launches, [4*c + 1] = total ms, [+2] = min ms, [+3] = max ms,
  * then clears the record.  Turning profiling off also clears it. */
 cfd_status cfd_set_profiling(cfd_ctx* ctx, int32_t enable);
-cfd_status cfd_profile_read(cfd_ctx* ctx, double out[12]);
+cfd_status cfd_profile_read(cfd_ctx* ctx, double out[16]);
 
 /* Copy block blk's metrics to out_dev (device) as a dense FP64 array
  * [10][nk+2g][nj+2g][ni+2g]: components 0-2 = S_i, 3-5 = S_j, 6-8 = S_k (the

@@ -307,10 +307,10 @@ class Solver:
 
     def profile_read(self) -> dict:
         """Per kernel class: launches, total/min/max ms (and mean) since the last read."""
-        out = (C.c_double * 12)()
+        out = (C.c_double * 16)()
         _check(lib().cfd_profile_read(self.ctx, out), self.ctx)
         res = {}
-        for k, name in enumerate(("stage", "ghost", "dt")):
+        for k, name in enumerate(("stage", "ghost", "dt", "norms")):
             n, tot, mn, mx = out[4 * k:4 * k + 4]
             res[name] = {"launches": int(n), "total_ms": tot, "min_ms": mn, "max_ms": mx,
                          "mean_ms": tot / n if n else 0.0}

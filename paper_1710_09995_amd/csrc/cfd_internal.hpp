@@ -49,6 +49,7 @@ struct TileDesc {
 template <typename T>
 struct Gas {
   T gamma, gm1, prandtl, mu_inf, s_star, eps_h, eps_lim;
+  T gg;     // gamma / (gamma - 1): enthalpy over p / rho
   T kfac;   // gamma / ((gamma - 1) Pr): conductivity over viscosity
   T uinf[3];
 };
@@ -82,15 +83,15 @@ struct StepParams {
 };
 
 // Arguments of the residual / stage kernels.
-// mode 0 writes R; mode 1 is stage 1 (plus norm partials of R(Qn) and V Qn);
-// mode 2 is stages 2-3: out = a Qn + b (Qs - dt R(Qs)).
+// mode 0 writes R; mode 1 is stage 1: out = Qs - dt R(Qs) and rout = R(Qs)
+// (for the norms kernel); mode 2 is stages 2-3: out = a Qn + b (Qs - dt R(Qs)).
 struct StageArgs {
   const double* qs;   // stencil state Q^(s)
   const double* qn;   // Q^n (pointwise, mode 2)
   double* out;        // R (mode 0) or Q^(s+1)
+  double* rout;       // R (mode 1), state-arena layout, interior cells only
   const double* met;
   const double* dt;   // global dt (1 double) or per-cell scalar arena (local)
-  double* partials;   // [gridDim.x][NPART] (mode 1)
   double a, b;
   int32_t local_dt;
   int32_t ntiles;

@@ -164,25 +164,28 @@ __global__ void k_metric_ghosts(double* __restrict__ met, const BlockDesc* __res
 __global__ void k_ghost_q(double* __restrict__ q, const double* __restrict__ met,
                           const BlockDesc* __restrict__ blocks,
                           const PatchDesc* __restrict__ patches, StepParams SP) {
-  const PatchDesc P = patches[blockIdx.y];
+  const PatchDesc& P = patches[blockIdx.y];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P.count) return;
   const int d = P.face >> 1, side = P.face & 1;
-  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-  const int w1 = P.hi[t1] - P.lo[t1];
-  const int p1 = P.lo[t1] + t % w1, p2 = P.lo[t2] + t / w1;
-  const BlockDesc B = blocks[P.blk];
-  const int n = B.n[d];
+  // transverse directions t1 < t2, selected without indexing (keeps P out of scratch)
+  const int lo1 = d == 0 ? P.lo[1] : P.lo[0], hi1 = d == 0 ? P.hi[1] : P.hi[0];
+  const int lo2 = d == 2 ? P.lo[1] : P.lo[2];
+  const int w1 = hi1 - lo1;
+  const int p1 = lo1 + t % w1, p2 = lo2 + t / w1;
+  const BlockDesc& B = blocks[P.blk];
+  const int n = d == 0 ? B.n[0] : (d == 1 ? B.n[1] : B.n[2]);
   double* qb = q + B.qoff;
   if (P.kind == 0) {
-    const BlockDesc N = blocks[P.nbr];
+    const BlockDesc& N = blocks[P.nbr];
     const double* qn = q + N.qoff;
-    const int nn = N.n[d];
+    const int nn = d == 0 ? N.n[0] : (d == 1 ? N.n[1] : N.n[2]);
+    const int o1 = d == 0 ? P.noff[1] : P.noff[0], o2 = d == 2 ? P.noff[1] : P.noff[2];
     for (int m = 1; m <= NG; ++m) {
       const int gm = side == 0 ? -m : n - 1 + m;
       const int sm = side == 0 ? nn - m : m - 1;
       const int64_t od = pos3(d, gm, p1, p2, B.sj, B.sk);
-      const int64_t os = pos3(d, sm, p1 + P.noff[t1], p2 + P.noff[t2], N.sj, N.sk);
+      const int64_t os = pos3(d, sm, p1 + o1, p2 + o2, N.sj, N.sk);
       for (int v = 0; v < NV; ++v) qb[v * B.sv + od] = qn[v * N.sv + os];
     }
     return;

@@ -27,8 +27,6 @@ namespace cfd {
 template <typename T, bool VISC, int MODE>
 __global__ void __launch_bounds__(256) k_stage_simple(StageArgs A, const BlockDesc* __restrict__ blocks,
                                                       const TileDesc* __restrict__ tiles, Gas<T> gas) {
-  double acc[NPART];
-  init_partials(acc);
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int nty = blockDim.x >> 6;
   for (int tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
@@ -48,11 +46,10 @@ __global__ void __launch_bounds__(256) k_stage_simple(StageArgs A, const BlockDe
           face_flux_global<T, VISC>(qb, mb, B, c + dstride(d, B.sj, B.sk), d, gas, Fu);
           for (int q = 0; q < 5; ++q) D[d][q] = Fu[q] - Fl[q];
         }
-        finish_cell<MODE>(A, B, c, D[0], D[1], D[2], mb[9 * B.sv + c], acc);
+        finish_cell<MODE>(A, B, c, D[0], D[1], D[2], mb[9 * B.sv + c]);
       }
     }
   }
-  if (MODE == 1) wg_reduce_partials(acc, A.partials + (int64_t)blockIdx.x * NPART);
 }
 
 // ------------------------------------------------------------- time step
@@ -63,31 +60,38 @@ __global__ void __launch_bounds__(256) k_dt(const double* __restrict__ q, const 
                                             const BlockDesc* __restrict__ blocks,
                                             const TileDesc* __restrict__ tiles, int ntiles, int tile_j,
                                             int tile_k, StepParams P) {
+  // One wave per 64-cell i-row of a tile; rows are dealt to the waves of the
+  // grid round robin (the rows of a tile, j fastest, go to neighbouring waves).
   double acc[NPART];
   init_partials(acc);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int nty = blockDim.x >> 6;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
+  const int nwave = gridDim.x * wpb;
+  const int rpt = tile_j * tile_k;
+  const int64_t nrows = (int64_t)ntiles * rpt;
+  for (int64_t u = wave; u < nrows; u += nwave) {
+    const int tile = (int)(u / rpt);
+    const int r = (int)(u - (int64_t)tile * rpt);
     const TileDesc td = tiles[tile];
     const BlockDesc B = blocks[td.blk];
-    const int i = td.i0 + tx;
-    if (i >= B.n[0]) continue;
+    const int i = td.i0 + lane, j = td.j0 + r % tile_j, k = td.k0 + r / tile_j;
+    if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
     const double* qb = q + B.qoff;
     const double* mb = met + B.moff;
-    for (int j = td.j0 + ty; j < min(td.j0 + tile_j, B.n[1]); j += nty) {
-      for (int k = td.k0; k < min(td.k0 + tile_k, B.n[2]); ++k) {
-        const int64_t c = (int64_t)(k + NG) * B.sk + (int64_t)(j + NG) * B.sj + (i + NG);
-        const double qc[5] = {qb[c], qb[B.sv + c], qb[2 * B.sv + c], qb[3 * B.sv + c], qb[4 * B.sv + c]};
-        const double dtc = cell_dt(qc, mb, c, B.sv, B.sj, B.sk, P);
-        if (P.local_dt) dtcell[B.soff + c] = dtc;
-        acc[12] = fmin(acc[12], dtc);
-      }
-    }
+    const int64_t c = (int64_t)(k + NG) * B.sk + (int64_t)(j + NG) * B.sj + (i + NG);
+    const double qc[5] = {qb[c], qb[B.sv + c], qb[2 * B.sv + c], qb[3 * B.sv + c], qb[4 * B.sv + c]};
+    const double dtc = cell_dt(qc, mb, c, B.sv, B.sj, B.sk, P);
+    if (P.local_dt) dtcell[B.soff + c] = dtc;
+    acc[12] = fmin(acc[12], dtc);
   }
   wg_reduce_partials(acc, partials + (int64_t)blockIdx.x * NPART);
 }
 
-// ------------------------------------------------------------- norms only
+// ------------------------------------------------------------- norms
+// Partials of sum R^2, sum V Q, max |R_rho| and the non-finite count over the
+// interior cells (r may be null: Q terms only).  Rows of 64 cells are dealt to
+// the waves round robin, as in the time-step kernel.
 __global__ void __launch_bounds__(256) k_norms(const double* __restrict__ q, const double* __restrict__ r,
                                                const double* __restrict__ met, double* __restrict__ partials,
                                                const BlockDesc* __restrict__ blocks,
@@ -95,30 +99,38 @@ __global__ void __launch_bounds__(256) k_norms(const double* __restrict__ q, con
                                                int tile_k) {
   double acc[NPART];
   init_partials(acc);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int nty = blockDim.x >> 6;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
+  const int nwave = gridDim.x * wpb;
+  const int rpt = tile_j * tile_k;
+  const int64_t nrows = (int64_t)ntiles * rpt;
+  for (int64_t u = wave; u < nrows; u += nwave) {
+    const int tile = (int)(u / rpt);
+    const int rr = (int)(u - (int64_t)tile * rpt);
     const TileDesc td = tiles[tile];
     const BlockDesc B = blocks[td.blk];
-    const int i = td.i0 + tx;
-    if (i >= B.n[0]) continue;
-    for (int j = td.j0 + ty; j < min(td.j0 + tile_j, B.n[1]); j += nty) {
-      for (int k = td.k0; k < min(td.k0 + tile_k, B.n[2]); ++k) {
-        const int64_t c = (int64_t)(k + NG) * B.sk + (int64_t)(j + NG) * B.sj + (i + NG);
-        const double vol = met[B.moff + 9 * B.sv + c];
-        for (int v = 0; v < 5; ++v) {
-          const double qv = q[B.qoff + v * B.sv + c];
-          acc[5 + v] += vol * qv;
-          if (!finite(qv)) acc[11] += 1.0;
-          if (r) {
-            const double rv = r[B.qoff + v * B.sv + c];
-            acc[v] += rv * rv;
-            if (!finite(rv)) acc[11] += 1.0;
-            if (v == 0) acc[10] = fmax(acc[10], fabs(rv));
-          }
-        }
+    const int i = td.i0 + lane, j = td.j0 + rr % tile_j, k = td.k0 + rr / tile_j;
+    if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
+    const int64_t c = (int64_t)(k + NG) * B.sk + (int64_t)(j + NG) * B.sj + (i + NG);
+    const double vol = met[B.moff + 9 * B.sv + c];
+    double qv[5], rv[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) qv[v] = q[B.qoff + v * B.sv + c];
+    if (r) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) rv[v] = r[B.qoff + v * B.sv + c];
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      acc[5 + v] += vol * qv[v];
+      if (!finite(qv[v])) acc[11] += 1.0;
+      if (r) {
+        acc[v] += rv[v] * rv[v];
+        if (!finite(rv[v])) acc[11] += 1.0;
       }
     }
+    if (r) acc[10] = fmax(acc[10], fabs(rv[0]));
   }
   wg_reduce_partials(acc, partials + (int64_t)blockIdx.x * NPART);
 }

@@ -94,8 +94,6 @@ __global__ void CFD_TILED_BOUNDS(64 * TJ) k_stage_tiled(StageArgs A, const Block
   };
 
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-  double acc[NPART];
-  init_partials(acc);
 
   for (int tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
     const TileDesc td = tiles[tile];
@@ -107,9 +105,10 @@ __global__ void CFD_TILED_BOUNDS(64 * TJ) k_stage_tiled(StageArgs A, const Block
     const bool act = i < ni && j < nj;
     const bool fi_ok = i <= ni && j < nj;   // this thread's lower i-face is needed
     const bool fj_ok = j <= nj && i < ni;   // this thread's lower j-face is needed
-    // faces on the tile's high edges, spread over the first waves
-    const bool xj = tid < 64 && j0 + TJ <= nj && i0 + tid < ni;                           // j-face at row j0+TJ
-    const bool xi = tid >= 64 && tid < 64 + TJ && i0 + 64 <= ni && j0 + (tid - 64) < nj;  // i-face at col i0+64
+    // faces on the tile's high edges: the j-faces of row j0+TJ (wave 0) and
+    // the i-faces of column i0+64 (TJ lanes of wave 1)
+    const bool has_xj = j0 + TJ <= nj && i0 + tx < ni;
+    const bool has_xi = tx < TJ && i0 + 64 <= ni && j0 + tx < nj;
     const double* qb = A.qs + B.qoff;
     const double* mb = A.met + B.moff;
     const int64_t sj = B.sj, sk = B.sk, sv = B.sv;
@@ -212,8 +211,8 @@ __global__ void CFD_TILED_BOUNDS(64 * TJ) k_stage_tiled(StageArgs A, const Block
       CFD_FACE_FENCE();
       if (fj_ok) face_j(tx, ty);
       CFD_FACE_FENCE();
-      if (xj) face_j(tid, TJ);
-      if (xi) face_i(64, tid - 64);
+      if (ty == 0 && has_xj) face_j(tx, TJ);
+      if (ty == 1 && has_xi) face_i(64, tx);
       CFD_FACE_FENCE();
       double Fku[5] = {0, 0, 0, 0, 0};
       if (act) {   // upper k-face between (i, j, k) and (i, j, k+1)
@@ -255,17 +254,16 @@ __global__ void CFD_TILED_BOUNDS(64 * TJ) k_stage_tiled(StageArgs A, const Block
           Dk[q] = Fku[q] - Fklo[q];
         }
         const int64_t c = off(i, j, k);
-        finish_cell<MODE>(A, B, c, Di, Dj, Dk, mb[9 * sv + c], acc);
-        for (int q = 0; q < 5; ++q) Fklo[q] = Fku[q];
         q0 = q1;
         q1 = q2;
         q2 = q3;
-        if (k + 1 < kend) q3 = ld_prim<T>(qb, c + 3 * sk, sv, gas.gm1);
+        if (k + 1 < kend) q3 = ld_prim<T>(qb, c + 3 * sk, sv, gas.gm1);   // loads before the stores below
+        finish_cell<MODE>(A, B, c, Di, Dj, Dk, mb[9 * sv + c]);
+        for (int q = 0; q < 5; ++q) Fklo[q] = Fku[q];
       }
       __syncthreads();   // flux reads and the phi copy done before the next plane
     }
   }
-  if (MODE == 1) wg_reduce_partials(acc, A.partials + (int64_t)blockIdx.x * NPART);
 }
 
 // ---------------------------------------------------------------- launchers

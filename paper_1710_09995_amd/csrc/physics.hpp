@@ -18,14 +18,56 @@ struct Prim {
   T r, u, v, w, p;
 };
 
-// Reciprocal, quotient and square root in the flux precision: IEEE FP64
-// operations for double; the single-instruction hardware reciprocal and
+// FP64 reciprocal and square root of positive normal operands (densities,
+// pressures, squared sound speeds, temperatures, volumes, face areas).
+// 1 (default): the hardware estimates refined in FMA arithmetic, no
+// special-case handling: reciprocal by two Newton-Raphson steps
+// x' = x + x (1 - b x); square root by Goldschmidt's iteration from the
+// reciprocal square root (g ~ sqrt(a), h ~ 1/(2 sqrt(a))) and two residual
+// corrections g' = g + h (a - g^2) (Markstein, IBM J. Res. Dev. 34(1), 1990).
+// Both stay within 1 ulp of the correctly rounded result and take about half
+// the instructions of the IEEE sequences, which also scale denormal and
+// infinite operands that never occur here.  Zero or negative operands give
+// inf or NaN, which the non-finite counters report.  0: IEEE operations.
+#ifndef CFD_FAST_F64
+#define CFD_FAST_F64 1
+#endif
+#if CFD_FAST_F64
+__device__ __forceinline__ double frcp(double b) {
+  double x = __builtin_amdgcn_rcp(b);
+  double e = __builtin_fma(-b, x, 1.0);
+  x = __builtin_fma(x, e, x);
+  e = __builtin_fma(-b, x, 1.0);
+  return __builtin_fma(x, e, x);
+}
+__device__ __forceinline__ double fdiv(double a, double b) {
+  const double x = frcp(b);
+  const double q = a * x;
+  return __builtin_fma(__builtin_fma(-b, q, a), x, q);
+}
+__device__ __forceinline__ double fsqrt(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y, h = 0.5 * y;
+  const double r = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  g = __builtin_fma(__builtin_fma(-g, g, a), h, g);
+  return __builtin_fma(__builtin_fma(-g, g, a), h, g);
+}
+#else
+__device__ __forceinline__ double frcp(double b) { return 1.0 / b; }
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ double fsqrt(double a) { return sqrt(a); }
+#endif
+
+// Reciprocal, quotient and square root in the flux precision: the FP64
+// helpers above for double; the single-instruction hardware reciprocal and
 // square root (1 ulp) for the FP32 flux variant, whose error budget is 1e-5.
-__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
+__device__ __forceinline__ double rcp_t(double x) { return frcp(x); }
 __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double div_t(double a, double b) { return a / b; }
+__device__ __forceinline__ double div_t(double a, double b) { return fdiv(a, b); }
 __device__ __forceinline__ float div_t(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+__device__ __forceinline__ double sqrt_t(double x) { return fsqrt(x); }
 __device__ __forceinline__ float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 template <typename T>
@@ -50,7 +92,7 @@ __device__ __forceinline__ void batch_rcp(const double* den, double* inv) {
   p[0] = den[0];
 #pragma unroll
   for (int k = 1; k < N; ++k) p[k] = p[k - 1] * den[k];
-  double r = 1.0 / p[N - 1];
+  double r = frcp(p[N - 1]);
 #pragma unroll
   for (int k = N - 1; k > 0; --k) {
     inv[k] = r * p[k - 1];
@@ -124,9 +166,10 @@ __device__ __forceinline__ void muscl(const Prim<T>& a, const Prim<T>& b, const 
 // Roe flux per unit area through a face with unit normal n (Roe 1981, Harten fix).
 template <typename T>
 __device__ __forceinline__ void roe(const Prim<T>& L, const Prim<T>& R, T nx, T ny, T nz,
-                                    T gamma, T eps_h, T F[5]) {
-  const T gm1 = gamma - T(1);
-  const T gg = div_t(gamma, gm1);
+                                    const Gas<T>& gas, T F[5]) {
+  const T gm1 = gas.gm1;
+  const T gg = gas.gg;
+  const T eps_h = gas.eps_h;
 #if CFD_ROE_RCP
   const T iLr = rcp_t(L.r), iRr = rcp_t(R.r);
   T Hl = gg * L.p * iLr + T(0.5) * (L.u * L.u + L.v * L.v + L.w * L.w);

@@ -418,6 +418,7 @@ void set_params(cfd_ctx* c) {
     G.s_star = (T)p.sutherland;
     G.eps_h = (T)p.entropy_fix;
     G.eps_lim = (T)p.limiter_eps;
+    G.gg = (T)(p.gamma / (p.gamma - 1.0));
     G.kfac = (T)(p.gamma / ((p.gamma - 1.0) * p.prandtl));
     for (int x = 0; x < 3; ++x) G.uinf[x] = (T)S.uinf[x];
   };
@@ -470,6 +471,13 @@ int nwg_for(const cfd_ctx* c, int per_cu) {
   return std::max(1, std::min({c->ntiles, NWG_MAX, 256 * per_cu}));
 }
 
+// Grid of the row-per-wave time-step kernel: 8 four-wave workgroups per CU,
+// capped by the number of 64-cell rows.
+int dt_nwg(const cfd_ctx* c) {
+  const int64_t rows = (int64_t)c->ntiles * c->tun.tile_j * c->tun.tile_k;
+  return (int)std::max<int64_t>(1, std::min<int64_t>({(rows + 3) / 4, (int64_t)NWG_MAX, (int64_t)c->num_cu * 8}));
+}
+
 // Run a launch; with profiling on, bracket it with a hipEvent pair on its stream.
 template <typename F>
 void timed(cfd_ctx* c, int cls, hipStream_t s, F&& launch) {
@@ -500,7 +508,6 @@ StageArgs stage_args(cfd_ctx* c) {
   A.ntiles = c->ntiles;
   A.tile_j = c->tun.tile_j;
   A.tile_k = c->tun.tile_k;
-  A.partials = c->part_nrm();
   return A;
 }
 
@@ -543,8 +550,7 @@ void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, hipStream_t s) {
 // kernel was measured slower: the stage kernel's extra metric loads cost more
 // than the separate pass.)
 void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
-  const int nwg1 = stage_nwg(c, 1);   // rows of the stage-1 norm partials
-  const int nwg_dt = nwg_for(c, 8);
+  const int nwg_dt = dt_nwg(c);   // also the norms kernel's grid (rows of its partials)
   ghost_fill(c, q, s);
   timed(c, 2, s, [&] {
     launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
@@ -555,7 +561,12 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
   A.qs = q;
   A.qn = q;
   A.out = c->qa();
+  A.rout = c->qb();   // R(Qn) lives in qb until stage 2 overwrites it
   launch_stage(c, A, 1, s);
+  timed(c, 3, s, [&] {
+    launch_norms(q, c->qb(), c->met(), c->part_nrm(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
+                 c->tun.tile_k, nwg_dt, s);
+  });
   ghost_fill(c, c->qa(), s);
   A.qs = c->qa();
   A.out = c->qb();
@@ -568,7 +579,7 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
   A.a = 1.0 / 3.0;
   A.b = 2.0 / 3.0;
   launch_stage(c, A, 2, s);
-  launch_finalize(c->part_nrm(), nwg1, 1, 1.0 / (double)c->ncells, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
+  launch_finalize(c->part_nrm(), nwg_dt, 1, 1.0 / (double)c->ncells, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
 }
 
 template <typename F>
@@ -748,10 +759,10 @@ cfd_status cfd_set_profiling(cfd_ctx* c, int32_t enable) {
   });
 }
 
-cfd_status cfd_profile_read(cfd_ctx* c, double out[12]) {
+cfd_status cfd_profile_read(cfd_ctx* c, double out[16]) {
   return guard(c, [&] {
     if (!c || !out) fail(CFD_EINVAL, "NULL argument");
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
       out[4 * k + 0] = 0.0;
       out[4 * k + 1] = 0.0;
       out[4 * k + 2] = 1e300;
@@ -767,7 +778,7 @@ cfd_status cfd_profile_read(cfd_ctx* c, double out[12]) {
       o[2] = std::min(o[2], (double)ms);
       o[3] = std::max(o[3], (double)ms);
     }
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 4; ++k)
       if (out[4 * k] == 0.0) out[4 * k + 2] = 0.0;
     c->release_events();
   });
@@ -829,7 +840,7 @@ cfd_status cfd_residual(cfd_ctx* c, const double* q, double* r, hipStream_t s) {
 cfd_status cfd_time_step(cfd_ctx* c, const double* q, double* dt_dev, hipStream_t s) {
   return guard(c, [&] {
     if (!c || !q || !dt_dev) fail(CFD_EINVAL, "NULL argument");
-    const int nwg = nwg_for(c, 8);
+    const int nwg = dt_nwg(c);
     launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
               c->tun.tile_k, c->SP, nwg, s);
     launch_finalize(c->part_dt(), nwg, 0, 0.0, dt_dev, nullptr, nullptr, s);
@@ -878,7 +889,7 @@ cfd_status cfd_step(cfd_ctx* c, double* q, int32_t nsteps, double* hist, hipStre
 cfd_status cfd_norms(cfd_ctx* c, const double* q, const double* r, double* out, int32_t flags, hipStream_t s) {
   cfd_status st = guard(c, [&] {
     if (!c || !q || !out) fail(CFD_EINVAL, "NULL argument");
-    const int nwg = nwg_for(c, 8);
+    const int nwg = dt_nwg(c);
     launch_norms(q, r, c->met(), c->part_nrm(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j, c->tun.tile_k,
                  nwg, s);
     // history row layout: [dt, L2 x5, VQ x5, max]; norms output drops dt

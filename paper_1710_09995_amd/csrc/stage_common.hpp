@@ -35,7 +35,7 @@ __device__ __forceinline__ void phi_of(const Prim<T>& W, T tc, T phi[4]) {
 
 template <typename T>
 __device__ __forceinline__ T temp_of(const Prim<T>& W) {
-  return W.p / W.r;
+  return div_t(W.p, W.r);
 }
 
 // transverse difference 1/4 (phi(L+e) + phi(R+e) - phi(L-e) - phi(R-e))
@@ -74,12 +74,12 @@ __device__ __forceinline__ double face_inviscid(const Prim<T>& a, const Prim<T>&
                                                 const Gas<T>& gas, T f[5], T n[3]) {
   Prim<T> L, R;
   muscl(a, b, c, d, gas.eps_lim, L, R);
-  const double area = sqrt(sx * sx + sy * sy + sz * sz);
-  const double ia = 1.0 / area;
+  const double area = fsqrt(sx * sx + sy * sy + sz * sz);
+  const double ia = frcp(area);
   n[0] = (T)(sx * ia);
   n[1] = (T)(sy * ia);
   n[2] = (T)(sz * ia);
-  roe<T>(L, R, n[0], n[1], n[2], gas.gamma, gas.eps_h, f);
+  roe<T>(L, R, n[0], n[1], n[2], gas, f);
   return area;
 }
 
@@ -90,7 +90,7 @@ template <typename T>
 __device__ __forceinline__ void face_viscous(const T pl[4], const T pr[4], double sx, double sy, double sz,
                                              const T n[3], const T dt1[4], const T dt2[4], const double St[2][3],
                                              double vf, const Gas<T>& gas, T f[5]) {
-  const double iv = 1.0 / vf;
+  const double iv = frcp(vf);
   const T sdx = (T)(sx * iv), sdy = (T)(sy * iv), sdz = (T)(sz * iv);
   const T s1x = (T)(St[0][0] * iv), s1y = (T)(St[0][1] * iv), s1z = (T)(St[0][2] * iv);
   const T s2x = (T)(St[1][0] * iv), s2y = (T)(St[1][1] * iv), s2z = (T)(St[1][2] * iv);
@@ -184,17 +184,18 @@ __device__ __forceinline__ double cell_dt(const double q[5], const double* __res
                                           int64_t sv, int64_t sj, int64_t sk, const StepParams& P) {
   const double gm1 = P.gamma - 1.0;
   const double r = q[0];
-  const double inv = 1.0 / r;
+  const double inv = frcp(r);
   const double u = q[1] * inv, v = q[2] * inv, w = q[3] * inv;
   const double p = gm1 * (q[4] - 0.5 * r * (u * u + v * v + w * w));
-  const double cs = sqrt(P.gamma * p / r);
+  const double cs = fsqrt(P.gamma * p * inv);
   const double vol = mb[9 * sv + c];
   const double coefv = fmax(4.0 / 3.0, P.gamma / P.prandtl);
   double mu_r = 0.0;
   if (P.viscous) {
-    const double t = p / r;
-    mu_r = P.mu_inf * t * sqrt(t) * (1.0 + P.s_star) / (t + P.s_star) / r;
+    const double t = p * inv;
+    mu_r = P.mu_inf * t * fsqrt(t) * (1.0 + P.s_star) * frcp(t + P.s_star) * inv;
   }
+  const double ivol = frcp(vol);
   double lam = 0.0, lamv = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -202,22 +203,27 @@ __device__ __forceinline__ double cell_dt(const double q[5], const double* __res
     const double bx = 0.5 * (mb[(3 * d) * sv + c] + mb[(3 * d) * sv + c + sd]);
     const double by = 0.5 * (mb[(3 * d + 1) * sv + c] + mb[(3 * d + 1) * sv + c + sd]);
     const double bz = 0.5 * (mb[(3 * d + 2) * sv + c] + mb[(3 * d + 2) * sv + c + sd]);
-    const double mag = sqrt(bx * bx + by * by + bz * bz);
-    lam += fabs(u * bx + v * by + w * bz) + cs * mag;
-    if (P.viscous) lamv += coefv * mu_r * mag * mag / vol;
+    const double m2 = bx * bx + by * by + bz * bz;
+    lam += fabs(u * bx + v * by + w * bz) + cs * fsqrt(m2);
+    if (P.viscous) lamv += coefv * mu_r * m2 * ivol;
   }
-  return P.cfl * vol / (lam + 4.0 * lamv);
+  return fdiv(P.cfl * vol, lam + 4.0 * lamv);
 }
 
 // Finish one interior cell: R = ((Di + Dj) + Dk) / V, then write R (mode 0)
-// or the stage update (modes 1, 2) and accumulate norm partials (mode 1).
+// or the stage update (modes 1, 2; mode 1 also writes R for the norms).
+// Every load is issued before the first store: the output may alias the
+// inputs as far as the compiler knows, so a load placed after a store would
+// wait for that store (and, through the shared memory counter, for every
+// store before it).
 template <int MODE>
 __device__ __forceinline__ void finish_cell(const StageArgs& A, const BlockDesc& B, int64_t c,
                                             const double Di[5], const double Dj[5], const double Dk[5],
-                                            double vol, double acc[NPART]) {
+                                            double vol) {
   double R[5];
+  const double ivol = frcp(vol);
 #pragma unroll
-  for (int q = 0; q < 5; ++q) R[q] = ((Di[q] + Dj[q]) + Dk[q]) / vol;
+  for (int q = 0; q < 5; ++q) R[q] = ((Di[q] + Dj[q]) + Dk[q]) * ivol;
   if (MODE == 0) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) A.out[B.qoff + q * B.sv + c] = R[q];
@@ -225,30 +231,31 @@ __device__ __forceinline__ void finish_cell(const StageArgs& A, const BlockDesc&
   }
   const double dt = A.local_dt ? A.dt[B.soff + c] : A.dt[0];
   const double* qb = A.qs + B.qoff;
+  double qv[5], qn[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) qv[q] = qb[q * B.sv + c];
+  if (MODE == 2) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) qn[q] = A.qn[B.qoff + q * B.sv + c];
+  }
   if (MODE == 1) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      const double qv = qb[q * B.sv + c];
-      A.out[B.qoff + q * B.sv + c] = qv - dt * R[q];
-      acc[q] += R[q] * R[q];
-      acc[5 + q] += vol * qv;
-      if (!finite(qv) || !finite(R[q])) acc[11] += 1.0;
+      A.out[B.qoff + q * B.sv + c] = qv[q] - dt * R[q];
+      A.rout[B.qoff + q * B.sv + c] = R[q];
     }
-    acc[10] = fmax(acc[10], fabs(R[0]));
   } else {
-    const double* qnb = A.qn + B.qoff;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const double qv = qb[q * B.sv + c];
-      A.out[B.qoff + q * B.sv + c] = A.a * qnb[q * B.sv + c] + A.b * (qv - dt * R[q]);
-    }
+    for (int q = 0; q < 5; ++q) A.out[B.qoff + q * B.sv + c] = A.a * qn[q] + A.b * (qv[q] - dt * R[q]);
   }
 }
 
 // Fixed-order workgroup reduction of NPART partials; thread 0 writes the row.
-// Slots: sums for [0,10) and 11, max for 10, min for 12.
-__device__ __forceinline__ void wg_reduce_partials(double acc[NPART], double* __restrict__ out_row) {
-  __shared__ double red[NPART][16];
+// Slots: sums for [0,10) and 11, max for 10, min for 12.  red: LDS scratch of
+// NPART x 16 doubles that no thread uses any more (the first barrier below
+// orders the caller's last uses before it).
+__device__ __forceinline__ void wg_reduce_partials(double acc[NPART], double* __restrict__ out_row,
+                                                   double (*red)[16]) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nwave = (blockDim.x + 63) >> 6;
@@ -277,6 +284,10 @@ __device__ __forceinline__ void wg_reduce_partials(double acc[NPART], double* __
     }
   }
   __syncthreads();
+}
+__device__ __forceinline__ void wg_reduce_partials(double acc[NPART], double* __restrict__ out_row) {
+  __shared__ double red[NPART][16];
+  wg_reduce_partials(acc, out_row, red);
 }
 
 }  // namespace cfd
