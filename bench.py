@@ -111,7 +111,7 @@ def read_traffic(kernel_label: str):
 
 def source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("kernels_stage.hip", "physics.hpp", "cfd_internal.hpp"):
+    for f in ("kernels_tiled.hip", "kernels_stage.hip", "stage_common.hpp", "physics.hpp", "cfd_internal.hpp"):
         p = os.path.join(ROOT, "paper_1710_09995_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
@@ -130,7 +130,9 @@ def main(argv=None):
     ap.add_argument("--tile-k", type=int, default=None)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--order", type=int, default=None, choices=[0, 1], help="tile order (1 = XCD-aware)")
-    ap.add_argument("--no-tune", action="store_true", help="skip the tile autotuner (library defaults)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the tile autotuner first (default: the library's default tiles)")
+    ap.add_argument("--no-tune", action="store_true", help="accepted for compatibility; the default")
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -174,7 +176,7 @@ def main(argv=None):
     tune_info = None
     if tun:
         s.set_tuning(**tun)
-    elif not a.no_tune:
+    elif a.tune:
         from paper_1710_09995_amd.autotune import autotune
         res = autotune(s, log=lambda m: print(m, file=sys.stderr, flush=True))
         tune_info = {"cached": res["cached"], "ms_per_step_tuning": round(res["ms_per_step"], 4),

@@ -100,7 +100,8 @@ typedef struct {
  * results (results are bitwise identical across all valid settings).
  * kernel: 0 = tiled face-once kernel (default), 1 = simple per-cell kernel.
  * tile_j, tile_k: tile extent in j and k (tile_i is 64, one wavefront);
- *   the tiled kernel takes tile_j = 2, 4 or 8.
+ *   the tiled kernel takes tile_j = 2, 4 or 8.  Defaults: kernel 0,
+ *   tile_j 8, tile_k 32, use_graph 1, order 1.
  * use_graph: 1 captures one time step in a hipGraph and replays it.
  * order: tile work-list order.  0 = largest tiles first (balances uneven
  *   blocks); 1 = XCD-aware: the tiles are cut into 8 spatially contiguous

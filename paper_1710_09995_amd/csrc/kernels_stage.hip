@@ -53,25 +53,39 @@ __global__ void __launch_bounds__(256) k_stage_simple(StageArgs A, const BlockDe
   }
 }
 
+// ------------------------------------------------- row-per-wave reductions
+// The time-step and norms kernels give every wave a contiguous run of 64-cell
+// i-rows of the tile list (rows of a tile: j fastest, then k).  With a grid
+// that is a multiple of 8, workgroup b runs on XCD b % 8 and the runs of one
+// XCD's workgroups are adjacent, so a row's k+1 neighbour is mostly read
+// through the same L2.
+__device__ __forceinline__ void wave_rows(int64_t nrows, int64_t& r0, int64_t& r1) {
+  const int wpb = blockDim.x >> 6;
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int slot = (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+  const int64_t w = __builtin_amdgcn_readfirstlane((int)slot * wpb + (int)(threadIdx.x >> 6));
+  const int64_t nw = (int64_t)nb * wpb;
+  r0 = nrows * w / nw;
+  r1 = nrows * (w + 1) / nw;
+}
+
 // ------------------------------------------------------------- time step
 // dt_c = CFL V / (sum_d L_d + 4 sum_d Lv_d) with S_d averaged over the cell's
-// two d-faces; per-workgroup minimum partial (slot 12); local steps stored.
+// two d-faces; per-workgroup partials: minimum dt (slot 12), sum V Q
+// (slots 5-9) and the count of non-finite Q values (slot 11); local steps
+// stored.
 __global__ void __launch_bounds__(256) k_dt(const double* __restrict__ q, const double* __restrict__ met,
                                             double* __restrict__ dtcell, double* __restrict__ partials,
                                             const BlockDesc* __restrict__ blocks,
                                             const TileDesc* __restrict__ tiles, int ntiles, int tile_j,
                                             int tile_k, StepParams P) {
-  // One wave per 64-cell i-row of a tile; rows are dealt to the waves of the
-  // grid round robin (the rows of a tile, j fastest, go to neighbouring waves).
   double acc[NPART];
   init_partials(acc);
   const int lane = threadIdx.x & 63;
-  const int wpb = blockDim.x >> 6;
-  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-  const int nwave = gridDim.x * wpb;
   const int rpt = tile_j * tile_k;
-  const int64_t nrows = (int64_t)ntiles * rpt;
-  for (int64_t u = wave; u < nrows; u += nwave) {
+  int64_t r0, r1;
+  wave_rows((int64_t)ntiles * rpt, r0, r1);
+  for (int64_t u = r0; u < r1; ++u) {
     const int tile = (int)(u / rpt);
     const int r = (int)(u - (int64_t)tile * rpt);
     const TileDesc td = tiles[tile];
@@ -82,17 +96,23 @@ __global__ void __launch_bounds__(256) k_dt(const double* __restrict__ q, const 
     const double* mb = met + B.moff;
     const int64_t c = (int64_t)(k + NG) * B.sk + (int64_t)(j + NG) * B.sj + (i + NG);
     const double qc[5] = {qb[c], qb[B.sv + c], qb[2 * B.sv + c], qb[3 * B.sv + c], qb[4 * B.sv + c]};
+    const double vol = mb[9 * B.sv + c];
     const double dtc = cell_dt(qc, mb, c, B.sv, B.sj, B.sk, P);
     if (P.local_dt) dtcell[B.soff + c] = dtc;
     acc[12] = fmin(acc[12], dtc);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      acc[5 + v] += vol * qc[v];
+      if (!finite(qc[v])) acc[11] += 1.0;
+    }
   }
   wg_reduce_partials(acc, partials + (int64_t)blockIdx.x * NPART);
 }
 
 // ------------------------------------------------------------- norms
-// Partials of sum R^2, sum V Q, max |R_rho| and the non-finite count over the
-// interior cells (r may be null: Q terms only).  Rows of 64 cells are dealt to
-// the waves round robin, as in the time-step kernel.
+// Partials of sum R^2 (slots 0-4), max |R_rho| (10) and the non-finite count
+// (11) of r, and of sum V Q (5-9) and the non-finite count of q; either of q
+// (then met too) and r may be null.
 __global__ void __launch_bounds__(256) k_norms(const double* __restrict__ q, const double* __restrict__ r,
                                                const double* __restrict__ met, double* __restrict__ partials,
                                                const BlockDesc* __restrict__ blocks,
@@ -101,12 +121,10 @@ __global__ void __launch_bounds__(256) k_norms(const double* __restrict__ q, con
   double acc[NPART];
   init_partials(acc);
   const int lane = threadIdx.x & 63;
-  const int wpb = blockDim.x >> 6;
-  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-  const int nwave = gridDim.x * wpb;
   const int rpt = tile_j * tile_k;
-  const int64_t nrows = (int64_t)ntiles * rpt;
-  for (int64_t u = wave; u < nrows; u += nwave) {
+  int64_t r0, r1;
+  wave_rows((int64_t)ntiles * rpt, r0, r1);
+  for (int64_t u = r0; u < r1; ++u) {
     const int tile = (int)(u / rpt);
     const int rr = (int)(u - (int64_t)tile * rpt);
     const TileDesc td = tiles[tile];
@@ -114,24 +132,28 @@ __global__ void __launch_bounds__(256) k_norms(const double* __restrict__ q, con
     const int i = td.i0 + lane, j = td.j0 + rr % tile_j, k = td.k0 + rr / tile_j;
     if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
     const int64_t c = (int64_t)(k + NG) * B.sk + (int64_t)(j + NG) * B.sj + (i + NG);
-    const double vol = met[B.moff + 9 * B.sv + c];
-    double qv[5], rv[5];
+    if (q) {
+      const double vol = met[B.moff + 9 * B.sv + c];
+      double qv[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) qv[v] = q[B.qoff + v * B.sv + c];
+      for (int v = 0; v < 5; ++v) qv[v] = q[B.qoff + v * B.sv + c];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        acc[5 + v] += vol * qv[v];
+        if (!finite(qv[v])) acc[11] += 1.0;
+      }
+    }
     if (r) {
+      double rv[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) rv[v] = r[B.qoff + v * B.sv + c];
-    }
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      acc[5 + v] += vol * qv[v];
-      if (!finite(qv[v])) acc[11] += 1.0;
-      if (r) {
+      for (int v = 0; v < 5; ++v) {
         acc[v] += rv[v] * rv[v];
         if (!finite(rv[v])) acc[11] += 1.0;
       }
+      acc[10] = fmax(acc[10], fabs(rv[0]));
     }
-    if (r) acc[10] = fmax(acc[10], fabs(rv[0]));
   }
   wg_reduce_partials(acc, partials + (int64_t)blockIdx.x * NPART);
 }

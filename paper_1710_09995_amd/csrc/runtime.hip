@@ -329,7 +329,7 @@ struct cfd_ctx {
   TileDesc* dtiles = nullptr;
   int ntiles = 0;
   int64_t ncells = 0;
-  cfd_tuning tun{0, 4, 32, 1, 1};
+  cfd_tuning tun{0, 8, 32, 1, 1};   // tiled kernel, 64 x 8 x 32 tiles, graph, XCD-aware order
   StepParams SP{};
   Gas<double> g64{};
   Gas<float> g32{};
@@ -477,11 +477,14 @@ int nwg_for(const cfd_ctx* c, int per_cu) {
   return std::max(1, std::min({c->ntiles, NWG_MAX, 256 * per_cu}));
 }
 
-// Grid of the row-per-wave time-step kernel: 8 four-wave workgroups per CU,
-// capped by the number of 64-cell rows.
+// Grid of the row-per-wave time-step and norms kernels: 8 four-wave
+// workgroups per CU, capped by the number of 64-cell rows and by half the
+// partials buffer (a step stores both kernels' rows in it, one after the
+// other).
 int dt_nwg(const cfd_ctx* c) {
   const int64_t rows = (int64_t)c->ntiles * c->tun.tile_j * c->tun.tile_k;
-  return (int)std::max<int64_t>(1, std::min<int64_t>({(rows + 3) / 4, (int64_t)NWG_MAX, (int64_t)c->num_cu * 8}));
+  return (int)std::max<int64_t>(
+      1, std::min<int64_t>({(rows + 3) / 4, (int64_t)NWG_MAX / 2, (int64_t)c->num_cu * 8}));
 }
 
 // Run a launch; with profiling on, bracket it with a hipEvent pair on its stream.
@@ -557,7 +560,9 @@ void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, hipStream_t s) {
 // kernel was measured slower: the stage kernel's extra metric loads cost more
 // than the separate pass.)
 void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
-  const int nwg_dt = dt_nwg(c);   // also the norms kernel's grid (rows of its partials)
+  // k_dt writes partial rows [0, nwg) of part_dt (min dt, sum V Qn), the norms
+  // kernel rows [nwg, 2 nwg) (R terms); the history finalize reads all 2 nwg.
+  const int nwg_dt = dt_nwg(c);
   ghost_fill(c, q, s);
   timed(c, 2, s, [&] {
     launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
@@ -571,8 +576,8 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
   A.rout = c->qb();   // R(Qn) lives in qb until stage 2 overwrites it
   launch_stage(c, A, 1, s);
   timed(c, 3, s, [&] {
-    launch_norms(q, c->qb(), c->met(), c->part_nrm(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
-                 c->tun.tile_k, nwg_dt, s);
+    launch_norms(nullptr, c->qb(), nullptr, c->part_dt() + (int64_t)nwg_dt * NPART, c->dblocks, c->dtiles,
+                 c->ntiles, c->tun.tile_j, c->tun.tile_k, nwg_dt, s);
   });
   ghost_fill(c, c->qa(), s);
   A.qs = c->qa();
@@ -586,7 +591,8 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
   A.a = 1.0 / 3.0;
   A.b = 2.0 / 3.0;
   launch_stage(c, A, 2, s);
-  launch_finalize(c->part_nrm(), nwg_dt, 1, 1.0 / (double)c->ncells, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
+  launch_finalize(c->part_dt(), 2 * nwg_dt, 1, 1.0 / (double)c->ncells, c->d_dt(), c->d_hist(), c->d_nonfinite(),
+                  s);
 }
 
 template <typename F>
