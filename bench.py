@@ -111,7 +111,8 @@ def read_traffic(kernel_label: str):
 
 def source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("kernels_tiled.hip", "kernels_stage.hip", "stage_common.hpp", "physics.hpp", "cfd_internal.hpp"):
+    for f in ("kernels_ring.hip", "kernels_tiled.hip", "kernels_stage.hip", "stage_common.hpp", "physics.hpp",
+              "cfd_internal.hpp"):
         p = os.path.join(ROOT, "paper_1710_09995_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
@@ -214,7 +215,8 @@ def main(argv=None):
         traffic = read_traffic(kernel_label)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": "k_stage (residual + RK stage update)",
+                    "kernel": {0: "k_stage_tiled", 1: "k_stage_simple", 2: "k_stage_ring"}.get(
+                        s.get_tuning()["kernel"], "k_stage") + " (residual + RK stage update)",
                     "mean_launch_ms": round(st["mean_ms"], 4), "launches": st["launches"],
                     "algorithmic_bytes_per_cell": round(bpc, 2), "cells_per_launch": case.ncells}
         print(f"# profile: {json.dumps(prof)}", file=sys.stderr, flush=True)

@@ -98,10 +98,15 @@ typedef struct {
 
 /* Tuning knobs of the stage kernels.  Any value changes speed only, never
  * results (results are bitwise identical across all valid settings).
- * kernel: 0 = tiled face-once kernel (default), 1 = simple per-cell kernel.
+ * kernel: 0 = tiled face-once kernel, 1 = simple per-cell kernel,
+ *   2 = plane-ring face-once kernel (a ring of three primitive planes in LDS,
+ *   two barriers per plane; tile_j = 8 only).
  * tile_j, tile_k: tile extent in j and k (tile_i is 64, one wavefront);
- *   the tiled kernel takes tile_j = 2, 4 or 8.  Defaults: kernel 0,
- *   tile_j 8, tile_k 32, use_graph 1, order 1.
+ *   the tiled kernel takes tile_j = 2, 4 or 8.  Defaults (set by
+ *   cfd_create_blocks): kernel 2, tile_j 8, tile_k 32, use_graph 1, order 1;
+ *   tile_k is halved (down to 4) while the grid gives fewer tiles than CUs,
+ *   and a grid with fewer tiles than CUs even then gets the tiled kernel
+ *   with tile_j halved (down to 2) until it has one tile per CU.
  * use_graph: 1 captures one time step in a hipGraph and replays it.
  * order: tile work-list order.  0 = largest tiles first (balances uneven
  *   blocks); 1 = XCD-aware: the tiles are cut into 8 spatially contiguous

@@ -17,7 +17,8 @@ import os
 from typing import Dict, Iterable, Optional, Tuple
 
 DEFAULT_CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = tuple(
-    (0, tj, tk, order) for order in (0, 1) for tj in (2, 4, 8) for tk in (4, 8, 16, 32, 64))
+    (0, tj, tk, order) for order in (0, 1) for tj in (2, 4, 8) for tk in (4, 8, 16, 32, 64)) + tuple(
+    (2, 8, tk, order) for order in (0, 1) for tk in (4, 8, 16, 32, 64))
 
 
 def cache_path() -> str:

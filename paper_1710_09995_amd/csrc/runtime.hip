@@ -29,6 +29,8 @@ void launch_metric_ghosts(double* met, const BlockDesc* blocks, const PatchDesc*
                           int maxcount, hipStream_t s);
 void launch_ghost_q(double* q, const double* met, const BlockDesc* blocks, const PatchDesc* patches,
                     int npatch, int maxcount, const StepParams& SP, hipStream_t s);
+bool stage_ring(const StageArgs& A, int mode, bool visc, bool fp32, const BlockDesc* blocks, const TileDesc* tiles,
+                const Gas<double>& g64, const Gas<float>& g32, int nwg, hipStream_t s, int* occ);
 bool stage_tiled(const StageArgs& A, int mode, bool visc, bool fp32, const BlockDesc* blocks,
                  const TileDesc* tiles, const Gas<double>& g64, const Gas<float>& g32, int nwg,
                  hipStream_t s, int* occ);
@@ -329,7 +331,7 @@ struct cfd_ctx {
   TileDesc* dtiles = nullptr;
   int ntiles = 0;
   int64_t ncells = 0;
-  cfd_tuning tun{0, 8, 32, 1, 1};   // tiled kernel, 64 x 8 x 32 tiles, graph, XCD-aware order
+  cfd_tuning tun{2, 8, 32, 1, 1};   // replaced by default_tuning() when the blocks are created
   StepParams SP{};
   Gas<double> g64{};
   Gas<float> g32{};
@@ -432,6 +434,26 @@ void set_params(cfd_ctx* c) {
   fill(c->g32);
 }
 
+int64_t count_tiles(const std::vector<cfd_dims>& dims, int tj, int tk) {
+  int64_t t = 0;
+  for (const auto& d : dims)
+    t += (int64_t)((d.ni + TILE_I - 1) / TILE_I) * ((d.nj + tj - 1) / tj) * ((d.nk + tk - 1) / tk);
+  return t;
+}
+
+// Default tuning for the grid: the plane-ring kernel with 64 x 8 x 32 tiles,
+// tile_k halved (down to 4) while there are fewer tiles than CUs, and the
+// tiled kernel with narrower tiles for grids that still leave CUs idle.
+cfd_tuning default_tuning(const std::vector<cfd_dims>& dims, int num_cu) {
+  cfd_tuning t{2, 8, 32, 1, 1};
+  while (t.tile_k > 4 && count_tiles(dims, t.tile_j, t.tile_k) < (int64_t)num_cu) t.tile_k /= 2;
+  if (count_tiles(dims, t.tile_j, t.tile_k) < num_cu) {
+    t.kernel = 0;
+    while (t.tile_j > 2 && count_tiles(dims, t.tile_j, t.tile_k) < num_cu) t.tile_j /= 2;
+  }
+  return t;
+}
+
 void build_tiles(cfd_ctx* c, hipStream_t s) {
   const int tj = c->tun.tile_j, tk = c->tun.tile_k;
   struct T2 {
@@ -524,9 +546,9 @@ StageArgs stage_args(cfd_ctx* c) {
 // Persistent grid of the stage kernel: resident workgroups per CU (occupancy
 // query, cached per variant) times the CU count, capped by the tile count.
 int stage_nwg(cfd_ctx* c, int mode) {
-  if (c->tun.kernel != 0) return nwg_for(c, 8);
+  if (c->tun.kernel == 1) return nwg_for(c, 8);
   const int key = (c->params.viscous ? 1 : 0) | (c->params.flux_fp32 ? 2 : 0) | (mode << 2) |
-                  ((c->tun.tile_j == 2 ? 0 : c->tun.tile_j == 4 ? 1 : 2) << 4);
+                  ((c->tun.tile_j == 2 ? 0 : c->tun.tile_j == 4 ? 1 : 2) << 4) | (c->tun.kernel << 6);
   auto it = c->occ_cache.find(key);
   int occ;
   if (it != c->occ_cache.end()) {
@@ -534,9 +556,12 @@ int stage_nwg(cfd_ctx* c, int mode) {
   } else {
     StageArgs A{};
     A.tile_j = c->tun.tile_j;
-    if (!stage_tiled(A, mode, c->params.viscous != 0, c->params.flux_fp32 != 0, nullptr, nullptr, c->g64,
-                     c->g32, 0, nullptr, &occ))
-      fail(CFD_EINVAL, "tiled kernel has no variant for tile_j = %d", c->tun.tile_j);
+    const bool ok = c->tun.kernel == 2
+                        ? stage_ring(A, mode, c->params.viscous != 0, c->params.flux_fp32 != 0, nullptr, nullptr,
+                                     c->g64, c->g32, 0, nullptr, &occ)
+                        : stage_tiled(A, mode, c->params.viscous != 0, c->params.flux_fp32 != 0, nullptr, nullptr,
+                                      c->g64, c->g32, 0, nullptr, &occ);
+    if (!ok) fail(CFD_EINVAL, "stage kernel %d has no variant for tile_j = %d", c->tun.kernel, c->tun.tile_j);
     c->occ_cache[key] = occ;
   }
   return std::max(1, std::min({c->ntiles, NWG_MAX, occ * c->num_cu}));
@@ -549,6 +574,11 @@ void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, hipStream_t s) {
     timed(c, 0, s, [&] {
       if (!stage_tiled(A, mode, visc, fp32, c->dblocks, c->dtiles, c->g64, c->g32, nwg, s, nullptr))
         fail(CFD_EINVAL, "tiled kernel has no variant for tile_j = %d", c->tun.tile_j);
+    });
+  } else if (c->tun.kernel == 2) {
+    timed(c, 0, s, [&] {
+      if (!stage_ring(A, mode, visc, fp32, c->dblocks, c->dtiles, c->g64, c->g32, nwg, s, nullptr))
+        fail(CFD_EINVAL, "plane-ring kernel needs tile_j = 8, got %d", c->tun.tile_j);
     });
   } else {
     timed(c, 0, s, [&] { launch_stage_simple(A, mode, visc, fp32, c->dblocks, c->dtiles, c->g64, c->g32, nwg, s); });
@@ -757,6 +787,7 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
       HIPCHK(hipMemcpyAsync(c->d_cell_start(), cs.data(), sizeof(int64_t) * cs.size(), hipMemcpyHostToDevice,
                             stream));
     }
+    c->tun = default_tuning(c->dims, c->num_cu);
     build_tiles(c, stream);
     *out = c;
   });
@@ -815,13 +846,14 @@ cfd_status cfd_destroy(cfd_ctx* c) {
 cfd_status cfd_set_tuning(cfd_ctx* c, const cfd_tuning* t) {
   return guard(c, [&] {
     if (!c || !t) fail(CFD_EINVAL, "NULL argument");
-    if (t->kernel < 0 || t->kernel > 1) fail(CFD_EINVAL, "kernel must be 0 or 1");
+    if (t->kernel < 0 || t->kernel > 2) fail(CFD_EINVAL, "kernel must be 0, 1 or 2");
     if (t->tile_j < 1 || t->tile_j > 16 || (t->tile_j & (t->tile_j - 1)))
       fail(CFD_EINVAL, "tile_j must be a power of two in [1, 16]");
     if (t->tile_k < 1 || t->tile_k > 4096) fail(CFD_EINVAL, "tile_k must be in [1, 4096]");
     if (t->order < 0 || t->order > 1) fail(CFD_EINVAL, "order must be 0 or 1");
     if (t->kernel == 0 && t->tile_j != 2 && t->tile_j != 4 && t->tile_j != 8)
       fail(CFD_EINVAL, "the tiled kernel takes tile_j = 2, 4 or 8");
+    if (t->kernel == 2 && t->tile_j != 8) fail(CFD_EINVAL, "the plane-ring kernel takes tile_j = 8");
     c->drop_graph();
     c->tun = *t;
     HIPCHK(hipDeviceSynchronize());

@@ -56,7 +56,7 @@ def test_ghost_fill_parity(name):
     s.close()
 
 
-@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("kernel", [0, 1, 2])
 @pytest.mark.parametrize("name", list(CASES))
 def test_residual_parity(name, kernel):
     case = CASES[name]
@@ -109,13 +109,15 @@ def test_step_parity_fp32_flux(name, nsteps):
 TUNINGS = ({"kernel": 0, "use_graph": 1}, {"kernel": 0, "use_graph": 0},
            {"kernel": 0, "tile_j": 2, "tile_k": 3}, {"kernel": 0, "tile_j": 8, "tile_k": 64},
            {"kernel": 0, "tile_j": 4, "tile_k": 5, "order": 1},
+           {"kernel": 2, "tile_j": 8, "tile_k": 32}, {"kernel": 2, "tile_j": 8, "tile_k": 3, "order": 0},
+           {"kernel": 2, "tile_j": 8, "tile_k": 7, "use_graph": 0},
            {"kernel": 1, "tile_j": 1, "tile_k": 3}, {"kernel": 1, "tile_j": 16, "tile_k": 64})
 
 
 @pytest.mark.parametrize("name", ["bump_ns", "batched", "vortex_curv"])
 @pytest.mark.parametrize("fp32", [0, 1])
 def test_graph_eager_tiles_kernels_bitwise(name, fp32):
-    """Graph vs eager, every tile shape and both stage kernels give the same bits."""
+    """Graph vs eager, every tile shape and all three stage kernels give the same bits."""
     case = CASES[name].with_params(flux_fp32=fp32)
     say("graph/eager/tiles/kernels", name, fp32)
     outs = []
