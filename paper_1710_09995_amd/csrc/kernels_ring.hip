@@ -11,9 +11,9 @@
 //   A. faces of plane k (W(k-1..k+1) ready): the lower i-face and lower
 //      j-face of every column, the tile-edge faces, the upper k-face (cells
 //      k-1..k+1 from the ring, k+2 from a one-cell register queue);
-//   B. after the barrier: the cell update of plane k (global loads and
-//      stores) together with the fill of W(k+2) into the slot of W(k-1) and
-//      the queue load of W(k+3), so their memory latencies overlap.
+//   B. after the barrier: the cell update of plane k (its inputs were loaded
+//      before the faces) together with the fill of W(k+2) into the slot of
+//      W(k-1) and the queue load of W(k+3), so their memory latencies overlap.
 // The i-face fluxes are exchanged between neighbouring lanes of the wave
 // (shuffle) instead of through LDS; only the tile's edge i-faces and the
 // j-faces go through LDS.  Every face flux gets the same bits as in the
@@ -93,9 +93,14 @@ __global__ void __launch_bounds__(64 * RING_TJ) k_stage_ring(StageArgs A, const 
     auto off = [&](int ii, int jj, int kk) -> int64_t {
       return (int64_t)(kk + NG) * sk + (int64_t)(jj + NG) * sj + (ii + NG);
     };
-    // W(kk) with halo 2 into ring slot `slot`
+    // W(kk) with halo 2 into ring slot `slot`; a fixed trip count, unrolled,
+    // so that all of a thread's loads are in flight together
     auto fill = [&](int slot, int kk) {
-      for (int s = tid; s < WJ * WI; s += NT) {
+      constexpr int NS = (WJ * WI + NT - 1) / NT;
+#pragma unroll
+      for (int it = 0; it < NS; ++it) {
+        const int s = tid + it * NT;
+        if (s >= WJ * WI) break;
         const int pj = s / WI, pi = s - (s / WI) * WI;
         const int gi = i0 - 2 + pi, gj = j0 - 2 + pj;
         Prim<T> w;
@@ -126,6 +131,9 @@ __global__ void __launch_bounds__(64 * RING_TJ) k_stage_ring(StageArgs A, const 
     __syncthreads();
 
     for (int k = k0; k < kend; ++k) {
+      // inputs of this plane's cell update, loaded before the face work
+      CellIn cin;
+      if (act) load_cell<MODE>(A, B, off(i, j, k), cin);
       // ---- A. faces of plane k
       auto face_i = [&](int ci, int rj, double F[5]) {   // lower i-face of cell (i0+ci, j0+rj)
         const int pi = ci + 2, pj = rj + 2;
@@ -223,8 +231,7 @@ __global__ void __launch_bounds__(64 * RING_TJ) k_stage_ring(StageArgs A, const 
           Dj[q] = sFj[(q * (TJ + 1) + ty + 1) * 64 + tx] - sFj[(q * (TJ + 1) + ty) * 64 + tx];
           Dk[q] = Fku[q] - Fklo[q];
         }
-        const int64_t c = off(i, j, k);
-        finish_cell<MODE>(A, B, c, Di, Dj, Dk, mb[9 * sv + c]);
+        update_cell<MODE>(A, B, off(i, j, k), Di, Dj, Dk, cin);
         for (int q = 0; q < 5; ++q) Fklo[q] = Fku[q];
       }
       q3 = q3n;

@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) k_stage_simple(StageArgs A, const BlockDe
           face_flux_global<T, VISC>(qb, mb, vb, B, c + dstride(d, B.sj, B.sk), d, gas, Fu);
           for (int q = 0; q < 5; ++q) D[d][q] = Fu[q] - Fl[q];
         }
-        finish_cell<MODE>(A, B, c, D[0], D[1], D[2], mb[9 * B.sv + c]);
+        finish_cell<MODE>(A, B, c, D[0], D[1], D[2]);
       }
     }
   }

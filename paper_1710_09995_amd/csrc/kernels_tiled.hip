@@ -260,7 +260,7 @@ __global__ void CFD_TILED_BOUNDS(64 * TJ) k_stage_tiled(StageArgs A, const Block
         q1 = q2;
         q2 = q3;
         if (k + 1 < kend) q3 = ld_prim<T>(qb, c + 3 * sk, sv, gas.gm1);   // loads before the stores below
-        finish_cell<MODE>(A, B, c, Di, Dj, Dk, mb[9 * sv + c]);
+        finish_cell<MODE>(A, B, c, Di, Dj, Dk);
         for (int q = 0; q < 5; ++q) Fklo[q] = Fku[q];
       }
       __syncthreads();   // flux reads and the phi copy done before the next plane

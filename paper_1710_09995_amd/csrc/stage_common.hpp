@@ -222,44 +222,61 @@ __device__ __forceinline__ double cell_dt(const double q[5], const double* __res
   return fdiv(P.cfl * vol, lam + 4.0 * lamv);
 }
 
-// Finish one interior cell: R = ((Di + Dj) + Dk) / V, then write R (mode 0)
-// or the stage update (modes 1, 2; mode 1 also writes R for the norms).
-// Every load is issued before the first store: the output may alias the
-// inputs as far as the compiler knows, so a load placed after a store would
-// wait for that store (and, through the shared memory counter, for every
-// store before it).
+// Inputs of one cell's update besides its flux differences.
+struct CellIn {
+  double qv[5], qn[5], dt, vol;
+};
+
+// Load them (qn only in mode 2, dt only in modes 1-2).  Every load of the
+// update is issued before its first store: the output may alias the inputs
+// as far as the compiler knows, so a load placed after a store would wait for
+// that store (and, through the shared memory counter, for every store before
+// it).  A kernel may load them early, before its face work, to hide latency.
 template <int MODE>
-__device__ __forceinline__ void finish_cell(const StageArgs& A, const BlockDesc& B, int64_t c,
-                                            const double Di[5], const double Dj[5], const double Dk[5],
-                                            double vol) {
+__device__ __forceinline__ void load_cell(const StageArgs& A, const BlockDesc& B, int64_t c, CellIn& in) {
+  in.vol = A.met[B.moff + 9 * B.sv + c];
+  if (MODE == 0) return;
+  in.dt = A.local_dt ? A.dt[B.soff + c] : A.dt[0];
+  const double* qb = A.qs + B.qoff;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) in.qv[q] = qb[q * B.sv + c];
+  if (MODE == 2) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) in.qn[q] = A.qn[B.qoff + q * B.sv + c];
+  }
+}
+
+// R = ((Di + Dj) + Dk) / V, then write R (mode 0) or the stage update
+// (modes 1, 2; mode 1 also writes R for the norms).
+template <int MODE>
+__device__ __forceinline__ void update_cell(const StageArgs& A, const BlockDesc& B, int64_t c, const double Di[5],
+                                            const double Dj[5], const double Dk[5], const CellIn& in) {
   double R[5];
-  const double ivol = frcp(vol);
+  const double ivol = frcp(in.vol);
 #pragma unroll
   for (int q = 0; q < 5; ++q) R[q] = ((Di[q] + Dj[q]) + Dk[q]) * ivol;
   if (MODE == 0) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) A.out[B.qoff + q * B.sv + c] = R[q];
-    return;
-  }
-  const double dt = A.local_dt ? A.dt[B.soff + c] : A.dt[0];
-  const double* qb = A.qs + B.qoff;
-  double qv[5], qn[5];
-#pragma unroll
-  for (int q = 0; q < 5; ++q) qv[q] = qb[q * B.sv + c];
-  if (MODE == 2) {
-#pragma unroll
-    for (int q = 0; q < 5; ++q) qn[q] = A.qn[B.qoff + q * B.sv + c];
-  }
-  if (MODE == 1) {
+  } else if (MODE == 1) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      A.out[B.qoff + q * B.sv + c] = qv[q] - dt * R[q];
+      A.out[B.qoff + q * B.sv + c] = in.qv[q] - in.dt * R[q];
       A.rout[B.qoff + q * B.sv + c] = R[q];
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) A.out[B.qoff + q * B.sv + c] = A.a * qn[q] + A.b * (qv[q] - dt * R[q]);
+    for (int q = 0; q < 5; ++q)
+      A.out[B.qoff + q * B.sv + c] = A.a * in.qn[q] + A.b * (in.qv[q] - in.dt * R[q]);
   }
+}
+
+template <int MODE>
+__device__ __forceinline__ void finish_cell(const StageArgs& A, const BlockDesc& B, int64_t c, const double Di[5],
+                                            const double Dj[5], const double Dk[5]) {
+  CellIn in;
+  load_cell<MODE>(A, B, c, in);
+  update_cell<MODE>(A, B, c, Di, Dj, Dk, in);
 }
 
 // Fixed-order workgroup reduction of NPART partials; thread 0 writes the row.
