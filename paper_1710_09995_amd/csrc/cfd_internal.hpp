@@ -87,13 +87,16 @@ struct StepParams {
 };
 
 // Arguments of the residual / stage kernels.
-// mode 0 writes R; mode 1 is stage 1: out = Qs - dt R(Qs) and rout = R(Qs)
-// (for the norms kernel); mode 2 is stages 2-3: out = a Qn + b (Qs - dt R(Qs)).
+// mode 0 writes R; mode 1 is stage 1: out = Qs - dt R(Qs), and either
+// rout = R(Qs) (for the norms kernel) or, in the plane-ring kernel, the norm
+// partials of R(Qs) per workgroup; mode 2 is stages 2-3:
+// out = a Qn + b (Qs - dt R(Qs)).
 struct StageArgs {
   const double* qs;   // stencil state Q^(s)
   const double* qn;   // Q^n (pointwise, mode 2)
   double* out;        // R (mode 0) or Q^(s+1)
-  double* rout;       // R (mode 1), state-arena layout, interior cells only
+  double* rout;       // R (mode 1, if not null), state-arena layout, interior cells only
+  double* partials;   // [gridDim.x][NPART] norm partials of R (mode 1, plane-ring kernel)
   const double* met;
   const double* vmet; // viscous face metrics (viscous flow only)
   const double* dt;   // global dt (1 double) or per-cell scalar arena (local)

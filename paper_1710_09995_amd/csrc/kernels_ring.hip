@@ -14,6 +14,8 @@
 //   B. after the barrier: the cell update of plane k (its inputs were loaded
 //      before the faces) together with the fill of W(k+2) into the slot of
 //      W(k-1) and the queue load of W(k+3), so their memory latencies overlap.
+// Stage 1 accumulates the norm partials of R(Qn) in registers (this kernel
+// has the register room) instead of writing R for a separate norms kernel.
 // The i-face fluxes are exchanged between neighbouring lanes of the wave
 // (shuffle) instead of through LDS; only the tile's edge i-faces and the
 // j-faces go through LDS.  Every face flux gets the same bits as in the
@@ -73,6 +75,8 @@ __global__ void __launch_bounds__(64 * RING_TJ) k_stage_ring(StageArgs A, const 
   };
 
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  double acc[NPART];   // stage 1: norm partials of R (sum R^2, max |R_rho|, non-finite count)
+  init_partials(acc);
 
   for (int tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
     const TileDesc td = tiles[tile];
@@ -231,7 +235,16 @@ __global__ void __launch_bounds__(64 * RING_TJ) k_stage_ring(StageArgs A, const 
           Dj[q] = sFj[(q * (TJ + 1) + ty + 1) * 64 + tx] - sFj[(q * (TJ + 1) + ty) * 64 + tx];
           Dk[q] = Fku[q] - Fklo[q];
         }
-        update_cell<MODE>(A, B, off(i, j, k), Di, Dj, Dk, cin);
+        double Rc[5];
+        update_cell<MODE>(A, B, off(i, j, k), Di, Dj, Dk, cin, Rc);
+        if (MODE == 1) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            acc[q] += Rc[q] * Rc[q];
+            if (!finite(Rc[q])) acc[11] += 1.0;
+          }
+          acc[10] = fmax(acc[10], fabs(Rc[0]));
+        }
         for (int q = 0; q < 5; ++q) Fklo[q] = Fku[q];
       }
       q3 = q3n;
@@ -242,6 +255,8 @@ __global__ void __launch_bounds__(64 * RING_TJ) k_stage_ring(StageArgs A, const 
       __syncthreads();   // W(k+2) filled; j-face and edge flux reads done
     }
   }
+  // the j-face buffer is free once the tiles are done
+  if (MODE == 1) wg_reduce_partials(acc, A.partials + (int64_t)blockIdx.x * NPART, reinterpret_cast<double(*)[16]>(sFj));
 }
 
 // ---------------------------------------------------------------- launchers

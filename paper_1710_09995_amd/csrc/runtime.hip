@@ -564,7 +564,7 @@ int stage_nwg(cfd_ctx* c, int mode) {
     if (!ok) fail(CFD_EINVAL, "stage kernel %d has no variant for tile_j = %d", c->tun.kernel, c->tun.tile_j);
     c->occ_cache[key] = occ;
   }
-  return std::max(1, std::min({c->ntiles, NWG_MAX, occ * c->num_cu}));
+  return std::max(1, std::min({c->ntiles, NWG_MAX / 2, occ * c->num_cu}));   // room for the k_dt rows too
 }
 
 void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, hipStream_t s) {
@@ -590,8 +590,9 @@ void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, hipStream_t s) {
 // kernel was measured slower: the stage kernel's extra metric loads cost more
 // than the separate pass.)
 void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
-  // k_dt writes partial rows [0, nwg) of part_dt (min dt, sum V Qn), the norms
-  // kernel rows [nwg, 2 nwg) (R terms); the history finalize reads all 2 nwg.
+  // k_dt writes partial rows [0, nwg) of part_dt (min dt, sum V Qn), the R
+  // terms follow (stage 1 or the norms kernel); the history finalize reads
+  // them all.
   const int nwg_dt = dt_nwg(c);
   ghost_fill(c, q, s);
   timed(c, 2, s, [&] {
@@ -603,12 +604,26 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
   A.qs = q;
   A.qn = q;
   A.out = c->qa();
-  A.rout = c->qb();   // R(Qn) lives in qb until stage 2 overwrites it
-  launch_stage(c, A, 1, s);
-  timed(c, 3, s, [&] {
-    launch_norms(nullptr, c->qb(), nullptr, c->part_dt() + (int64_t)nwg_dt * NPART, c->dblocks, c->dtiles,
-                 c->ntiles, c->tun.tile_j, c->tun.tile_k, nwg_dt, s);
-  });
+  // norm partials of R(Qn): the plane-ring kernel reduces them itself (rows
+  // after k_dt's); the other kernels write R to qb (free until stage 2
+  // overwrites it) for the norms kernel
+  int nrows_hist = nwg_dt;
+  if (c->tun.kernel == 2) {
+    A.rout = nullptr;
+    A.partials = c->part_dt() + (int64_t)nwg_dt * NPART;
+    nrows_hist += stage_nwg(c, 1);
+    launch_stage(c, A, 1, s);
+  } else {
+    A.rout = c->qb();
+    launch_stage(c, A, 1, s);
+    timed(c, 3, s, [&] {
+      launch_norms(nullptr, c->qb(), nullptr, c->part_dt() + (int64_t)nwg_dt * NPART, c->dblocks, c->dtiles,
+                   c->ntiles, c->tun.tile_j, c->tun.tile_k, nwg_dt, s);
+    });
+    nrows_hist += nwg_dt;
+  }
+  A.rout = nullptr;
+  A.partials = nullptr;
   ghost_fill(c, c->qa(), s);
   A.qs = c->qa();
   A.out = c->qb();
@@ -621,7 +636,7 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
   A.a = 1.0 / 3.0;
   A.b = 2.0 / 3.0;
   launch_stage(c, A, 2, s);
-  launch_finalize(c->part_dt(), 2 * nwg_dt, 1, 1.0 / (double)c->ncells, c->d_dt(), c->d_hist(), c->d_nonfinite(),
+  launch_finalize(c->part_dt(), nrows_hist, 1, 1.0 / (double)c->ncells, c->d_dt(), c->d_hist(), c->d_nonfinite(),
                   s);
 }
 

@@ -247,10 +247,12 @@ __device__ __forceinline__ void load_cell(const StageArgs& A, const BlockDesc& B
 }
 
 // R = ((Di + Dj) + Dk) / V, then write R (mode 0) or the stage update
-// (modes 1, 2; mode 1 also writes R for the norms).
+// (modes 1, 2; mode 1 also writes R for the norms if A.rout is set).  R is
+// returned in Rc.
 template <int MODE>
 __device__ __forceinline__ void update_cell(const StageArgs& A, const BlockDesc& B, int64_t c, const double Di[5],
-                                            const double Dj[5], const double Dk[5], const CellIn& in) {
+                                            const double Dj[5], const double Dk[5], const CellIn& in,
+                                            double Rc[5] = nullptr) {
   double R[5];
   const double ivol = frcp(in.vol);
 #pragma unroll
@@ -262,12 +264,16 @@ __device__ __forceinline__ void update_cell(const StageArgs& A, const BlockDesc&
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       A.out[B.qoff + q * B.sv + c] = in.qv[q] - in.dt * R[q];
-      A.rout[B.qoff + q * B.sv + c] = R[q];
+      if (A.rout) A.rout[B.qoff + q * B.sv + c] = R[q];
     }
   } else {
 #pragma unroll
     for (int q = 0; q < 5; ++q)
       A.out[B.qoff + q * B.sv + c] = A.a * in.qn[q] + A.b * (in.qv[q] - in.dt * R[q]);
+  }
+  if (Rc) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Rc[q] = R[q];
   }
 }
 
