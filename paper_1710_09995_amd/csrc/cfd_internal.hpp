@@ -89,14 +89,17 @@ struct StepParams {
 // Arguments of the residual / stage kernels.
 // mode 0 writes R; mode 1 is stage 1: out = Qs - dt R(Qs), and either
 // rout = R(Qs) (for the norms kernel) or, in the plane-ring kernel, the norm
-// partials of R(Qs) per workgroup; mode 2 is stages 2-3:
-// out = a Qn + b (Qs - dt R(Qs)).
+// partials of R(Qs) and of V Qs per workgroup; mode 2 is stages 2-3:
+// out = a Qn + b (Qs - dt R(Qs)); mode 3 (plane-ring kernel only) is stage 3
+// plus the CFL time step of the new state (per-workgroup minimum into
+// partials, per-cell steps into dt_out with local stepping).
 struct StageArgs {
   const double* qs;   // stencil state Q^(s)
   const double* qn;   // Q^n (pointwise, mode 2)
   double* out;        // R (mode 0) or Q^(s+1)
   double* rout;       // R (mode 1, if not null), state-arena layout, interior cells only
-  double* partials;   // [gridDim.x][NPART] norm partials of R (mode 1, plane-ring kernel)
+  double* partials;   // [gridDim.x][NPART] partials (modes 1 and 3, plane-ring kernel)
+  double* dt_out;     // per-cell steps of the new state (mode 3, local stepping)
   const double* met;
   const double* vmet; // viscous face metrics (viscous flow only)
   const double* dt;   // global dt (1 double) or per-cell scalar arena (local)
@@ -104,6 +107,7 @@ struct StageArgs {
   int32_t local_dt;
   int32_t ntiles;
   int32_t tile_j, tile_k;
+  StepParams sp;      // flow and CFL parameters (mode 3)
 };
 
 

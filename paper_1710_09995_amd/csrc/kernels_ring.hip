@@ -14,8 +14,10 @@
 //   B. after the barrier: the cell update of plane k (its inputs were loaded
 //      before the faces) together with the fill of W(k+2) into the slot of
 //      W(k-1) and the queue load of W(k+3), so their memory latencies overlap.
-// Stage 1 accumulates the norm partials of R(Qn) in registers (this kernel
-// has the register room) instead of writing R for a separate norms kernel.
+// Stage 1 accumulates the norm partials of R(Qn) and V Qn in registers (this
+// kernel has the register room) instead of writing R for a separate norms
+// kernel, and stage 3 (mode 3) evaluates the CFL time step of the state it
+// writes (the next step's), instead of a separate time-step kernel.
 // The i-face fluxes are exchanged between neighbouring lanes of the wave
 // (shuffle) instead of through LDS; only the tile's edge i-faces and the
 // j-faces go through LDS.  Every face flux gets the same bits as in the
@@ -75,7 +77,9 @@ __global__ void __launch_bounds__(64 * RING_TJ) k_stage_ring(StageArgs A, const 
   };
 
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-  double acc[NPART];   // stage 1: norm partials of R (sum R^2, max |R_rho|, non-finite count)
+  // partials: stage 1 (mode 1) sum R^2, sum V Qs, max |R_rho|, non-finite
+  // count; stage 3 (mode 3) minimum time step of the new state
+  double acc[NPART];
   init_partials(acc);
 
   for (int tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
@@ -226,6 +230,8 @@ __global__ void __launch_bounds__(64 * RING_TJ) k_stage_ring(StageArgs A, const 
       const bool more = k + 1 < kend;
       Prim<T> q3n = q3;
       if (act && more) q3n = ld_prim<T>(qb, off(i, j, k) + 3 * sk, sv, gas.gm1);
+      double bdt[3][3];   // mode 3: face-averaged area vectors of the cell
+      if (MODE == 3 && act) dt_vectors(mb, off(i, j, k), sv, sj, sk, bdt);
       if (more) fill(sm, k + 2);
       if (act) {
         double Di[5], Dj[5], Dk[5];
@@ -235,15 +241,22 @@ __global__ void __launch_bounds__(64 * RING_TJ) k_stage_ring(StageArgs A, const 
           Dj[q] = sFj[(q * (TJ + 1) + ty + 1) * 64 + tx] - sFj[(q * (TJ + 1) + ty) * 64 + tx];
           Dk[q] = Fku[q] - Fklo[q];
         }
-        double Rc[5];
-        update_cell<MODE>(A, B, off(i, j, k), Di, Dj, Dk, cin, Rc);
+        double Rc[5], Qo[5];
+        update_cell<MODE>(A, B, off(i, j, k), Di, Dj, Dk, cin, Rc, Qo);
         if (MODE == 1) {
 #pragma unroll
           for (int q = 0; q < 5; ++q) {
             acc[q] += Rc[q] * Rc[q];
+            acc[5 + q] += cin.vol * cin.qv[q];
             if (!finite(Rc[q])) acc[11] += 1.0;
+            if (!finite(cin.qv[q])) acc[11] += 1.0;
           }
           acc[10] = fmax(acc[10], fabs(Rc[0]));
+        }
+        if (MODE == 3) {
+          const double dtc = cell_dt_b(Qo, bdt, cin.vol, A.sp);
+          if (A.sp.local_dt) A.dt_out[B.soff + off(i, j, k)] = dtc;
+          acc[12] = fmin(acc[12], dtc);
         }
         for (int q = 0; q < 5; ++q) Fklo[q] = Fku[q];
       }
@@ -256,7 +269,8 @@ __global__ void __launch_bounds__(64 * RING_TJ) k_stage_ring(StageArgs A, const 
     }
   }
   // the j-face buffer is free once the tiles are done
-  if (MODE == 1) wg_reduce_partials(acc, A.partials + (int64_t)blockIdx.x * NPART, reinterpret_cast<double(*)[16]>(sFj));
+  if (MODE == 1 || MODE == 3)
+    wg_reduce_partials(acc, A.partials + (int64_t)blockIdx.x * NPART, reinterpret_cast<double(*)[16]>(sFj));
 }
 
 // ---------------------------------------------------------------- launchers
@@ -279,12 +293,14 @@ template <typename T, bool VISC>
 static void ring_mode(const StageArgs& A, int mode, const BlockDesc* blocks, const TileDesc* tiles,
                       const Gas<T>& gas, int nwg, hipStream_t s, int* occ) {
   if (occ) {
-    *occ = mode == 0 ? occ_ring_t<T, VISC, 0>() : (mode == 1 ? occ_ring_t<T, VISC, 1>() : occ_ring_t<T, VISC, 2>());
+    *occ = mode == 0 ? occ_ring_t<T, VISC, 0>()
+                     : (mode == 1 ? occ_ring_t<T, VISC, 1>() : (mode == 2 ? occ_ring_t<T, VISC, 2>() : occ_ring_t<T, VISC, 3>()));
     return;
   }
   if (mode == 0) launch_ring_t<T, VISC, 0>(A, blocks, tiles, gas, nwg, s);
   else if (mode == 1) launch_ring_t<T, VISC, 1>(A, blocks, tiles, gas, nwg, s);
-  else launch_ring_t<T, VISC, 2>(A, blocks, tiles, gas, nwg, s);
+  else if (mode == 2) launch_ring_t<T, VISC, 2>(A, blocks, tiles, gas, nwg, s);
+  else launch_ring_t<T, VISC, 3>(A, blocks, tiles, gas, nwg, s);
 }
 
 // Launch (occ == nullptr) or query the resident workgroups per CU.  Needs

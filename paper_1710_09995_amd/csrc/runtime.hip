@@ -540,6 +540,7 @@ StageArgs stage_args(cfd_ctx* c) {
   A.ntiles = c->ntiles;
   A.tile_j = c->tun.tile_j;
   A.tile_k = c->tun.tile_k;
+  A.sp = c->SP;
   return A;
 }
 
@@ -585,42 +586,54 @@ void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, hipStream_t s) {
   }
 }
 
-// One full RK3 step: ghost fill + dt + 3 x (ghost fill + stage) + finalize.
-// (Taking dt of the new state inside the third stage instead of a separate
-// kernel was measured slower: the stage kernel's extra metric loads cost more
-// than the separate pass.)
-void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
-  // k_dt writes partial rows [0, nwg) of part_dt (min dt, sum V Qn), the R
-  // terms follow (stage 1 or the norms kernel); the history finalize reads
-  // them all.
-  const int nwg_dt = dt_nwg(c);
-  ghost_fill(c, q, s);
+// CFL time step of q: per-cell steps (local stepping) and the minimum into d_dt.
+void time_step_pass(cfd_ctx* c, const double* q, hipStream_t s) {
+  const int nwg = dt_nwg(c);
   timed(c, 2, s, [&] {
     launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
-              c->tun.tile_k, c->SP, nwg_dt, s);
+              c->tun.tile_k, c->SP, nwg, s);
   });
-  launch_finalize(c->part_dt(), nwg_dt, 0, 0.0, c->d_dt(), nullptr, nullptr, s);
+  launch_finalize(c->part_dt(), nwg, 0, 0.0, c->d_dt(), nullptr, nullptr, s);
+}
+
+// One full RK3 step: 3 x (ghost fill + stage), the time step of Q^n and the
+// history row (dt, L2(R(Q^n)), sum V Q^n, max |R_rho|).
+//  - plane-ring kernel: the time step of Q^n was left in d_dt (and the
+//    per-cell arena) by the previous step's stage 3, or by the time-step pass
+//    cfd_step runs before its first step; stage 1 reduces the history's norm
+//    partials itself and stage 3 those of the next time step.
+//  - other kernels: a time-step pass first (k_dt writes partial rows
+//    [0, nwg) of part_dt: min dt, sum V Q^n), stage 1 writes R(Q^n) to qb
+//    (free until stage 2 overwrites it) and the norms kernel adds the R rows.
+// (Taking dt of the new state inside the tiled kernel's third stage was
+// measured slower: its extra metric loads cost more than the separate pass.
+// The plane-ring kernel has the register room for it.)
+void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
+  const bool ring = c->tun.kernel == 2;
+  const double inv_n = 1.0 / (double)c->ncells;
+  ghost_fill(c, q, s);
   StageArgs A = stage_args(c);
   A.qs = q;
   A.qn = q;
   A.out = c->qa();
-  // norm partials of R(Qn): the plane-ring kernel reduces them itself (rows
-  // after k_dt's); the other kernels write R to qb (free until stage 2
-  // overwrites it) for the norms kernel
-  int nrows_hist = nwg_dt;
-  if (c->tun.kernel == 2) {
-    A.rout = nullptr;
-    A.partials = c->part_dt() + (int64_t)nwg_dt * NPART;
-    nrows_hist += stage_nwg(c, 1);
+  if (ring) {
+    A.partials = c->part_nrm();
     launch_stage(c, A, 1, s);
+    launch_finalize(c->part_nrm(), stage_nwg(c, 1), 1, inv_n, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
   } else {
+    const int nwg_dt = dt_nwg(c);
+    timed(c, 2, s, [&] {
+      launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
+                c->tun.tile_k, c->SP, nwg_dt, s);
+    });
+    launch_finalize(c->part_dt(), nwg_dt, 0, 0.0, c->d_dt(), nullptr, nullptr, s);
     A.rout = c->qb();
     launch_stage(c, A, 1, s);
     timed(c, 3, s, [&] {
       launch_norms(nullptr, c->qb(), nullptr, c->part_dt() + (int64_t)nwg_dt * NPART, c->dblocks, c->dtiles,
                    c->ntiles, c->tun.tile_j, c->tun.tile_k, nwg_dt, s);
     });
-    nrows_hist += nwg_dt;
+    launch_finalize(c->part_dt(), 2 * nwg_dt, 1, inv_n, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
   }
   A.rout = nullptr;
   A.partials = nullptr;
@@ -635,9 +648,14 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
   A.out = q;
   A.a = 1.0 / 3.0;
   A.b = 2.0 / 3.0;
-  launch_stage(c, A, 2, s);
-  launch_finalize(c->part_dt(), nrows_hist, 1, 1.0 / (double)c->ncells, c->d_dt(), c->d_hist(), c->d_nonfinite(),
-                  s);
+  if (ring) {
+    A.partials = c->part_dt();
+    A.dt_out = c->params.local_dt ? c->scal() : nullptr;
+    launch_stage(c, A, 3, s);
+    launch_finalize(c->part_dt(), stage_nwg(c, 3), 0, 0.0, c->d_dt(), nullptr, nullptr, s);
+  } else {
+    launch_stage(c, A, 2, s);
+  }
 }
 
 template <typename F>
@@ -918,6 +936,9 @@ cfd_status cfd_step(cfd_ctx* c, double* q, int32_t nsteps, double* hist, hipStre
   return guard(c, [&] {
     if (!c || !q) fail(CFD_EINVAL, "NULL argument");
     if (nsteps < 0) fail(CFD_EINVAL, "nsteps must be >= 0");
+    // the plane-ring step takes the time step of Q^n from the step before;
+    // the state may have changed since, so the first one is computed here
+    if (nsteps > 0 && c->tun.kernel == 2) time_step_pass(c, q, s);
     if (c->tun.use_graph && !c->profiling) {
       if (!c->gexec || c->graph_q != q) {
         c->drop_graph();

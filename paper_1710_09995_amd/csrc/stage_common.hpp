@@ -191,16 +191,16 @@ __device__ __forceinline__ bool finite(double x) { return !(isnan(x) || isinf(x)
 
 // Admissible time step of one cell with conserved state q (FP64):
 // dt_c = CFL V / (sum_d L_d + 4 sum_d Lv_d), S_d averaged over the cell's two
-// d-faces, L_d = |u . S_d| + c |S_d|, Lv_d = max(4/3, gamma/Pr)(mu/rho)|S_d|^2/V.
-__device__ __forceinline__ double cell_dt(const double q[5], const double* __restrict__ mb, int64_t c,
-                                          int64_t sv, int64_t sj, int64_t sk, const StepParams& P) {
+// d-faces (b[d]), L_d = |u . S_d| + c |S_d|,
+// Lv_d = max(4/3, gamma/Pr)(mu/rho)|S_d|^2/V.
+__device__ __forceinline__ double cell_dt_b(const double q[5], const double b[3][3], double vol,
+                                            const StepParams& P) {
   const double gm1 = P.gamma - 1.0;
   const double r = q[0];
   const double inv = frcp(r);
   const double u = q[1] * inv, v = q[2] * inv, w = q[3] * inv;
   const double p = gm1 * (q[4] - 0.5 * r * (u * u + v * v + w * w));
   const double cs = fsqrt(P.gamma * p * inv);
-  const double vol = mb[9 * sv + c];
   const double coefv = fmax(4.0 / 3.0, P.gamma / P.prandtl);
   double mu_r = 0.0;
   if (P.viscous) {
@@ -211,15 +211,30 @@ __device__ __forceinline__ double cell_dt(const double q[5], const double* __res
   double lam = 0.0, lamv = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const int64_t sd = dstride(d, sj, sk);
-    const double bx = 0.5 * (mb[(3 * d) * sv + c] + mb[(3 * d) * sv + c + sd]);
-    const double by = 0.5 * (mb[(3 * d + 1) * sv + c] + mb[(3 * d + 1) * sv + c + sd]);
-    const double bz = 0.5 * (mb[(3 * d + 2) * sv + c] + mb[(3 * d + 2) * sv + c + sd]);
+    const double bx = b[d][0], by = b[d][1], bz = b[d][2];
     const double m2 = bx * bx + by * by + bz * bz;
     lam += fabs(u * bx + v * by + w * bz) + cs * fsqrt(m2);
     if (P.viscous) lamv += coefv * mu_r * m2 * ivol;
   }
   return fdiv(P.cfl * vol, lam + 4.0 * lamv);
+}
+
+// The face-averaged area vectors of cell c: b[d] = (S_d(c) + S_d(c + e_d)) / 2.
+__device__ __forceinline__ void dt_vectors(const double* __restrict__ mb, int64_t c, int64_t sv, int64_t sj,
+                                           int64_t sk, double b[3][3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int64_t sd = dstride(d, sj, sk);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) b[d][x] = 0.5 * (mb[(3 * d + x) * sv + c] + mb[(3 * d + x) * sv + c + sd]);
+  }
+}
+
+__device__ __forceinline__ double cell_dt(const double q[5], const double* __restrict__ mb, int64_t c,
+                                          int64_t sv, int64_t sj, int64_t sk, const StepParams& P) {
+  double b[3][3];
+  dt_vectors(mb, c, sv, sj, sk, b);
+  return cell_dt_b(q, b, mb[9 * sv + c], P);
 }
 
 // Inputs of one cell's update besides its flux differences.
@@ -240,19 +255,19 @@ __device__ __forceinline__ void load_cell(const StageArgs& A, const BlockDesc& B
   const double* qb = A.qs + B.qoff;
 #pragma unroll
   for (int q = 0; q < 5; ++q) in.qv[q] = qb[q * B.sv + c];
-  if (MODE == 2) {
+  if (MODE >= 2) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) in.qn[q] = A.qn[B.qoff + q * B.sv + c];
   }
 }
 
 // R = ((Di + Dj) + Dk) / V, then write R (mode 0) or the stage update
-// (modes 1, 2; mode 1 also writes R for the norms if A.rout is set).  R is
-// returned in Rc.
+// (modes 1-3; mode 1 also writes R for the norms if A.rout is set).  R is
+// returned in Rc, the written state in Qo (modes 1-3).
 template <int MODE>
 __device__ __forceinline__ void update_cell(const StageArgs& A, const BlockDesc& B, int64_t c, const double Di[5],
                                             const double Dj[5], const double Dk[5], const CellIn& in,
-                                            double Rc[5] = nullptr) {
+                                            double Rc[5] = nullptr, double Qo[5] = nullptr) {
   double R[5];
   const double ivol = frcp(in.vol);
 #pragma unroll
@@ -263,13 +278,18 @@ __device__ __forceinline__ void update_cell(const StageArgs& A, const BlockDesc&
   } else if (MODE == 1) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      A.out[B.qoff + q * B.sv + c] = in.qv[q] - in.dt * R[q];
+      const double o = in.qv[q] - in.dt * R[q];
+      A.out[B.qoff + q * B.sv + c] = o;
       if (A.rout) A.rout[B.qoff + q * B.sv + c] = R[q];
+      if (Qo) Qo[q] = o;
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < 5; ++q)
-      A.out[B.qoff + q * B.sv + c] = A.a * in.qn[q] + A.b * (in.qv[q] - in.dt * R[q]);
+    for (int q = 0; q < 5; ++q) {
+      const double o = A.a * in.qn[q] + A.b * (in.qv[q] - in.dt * R[q]);
+      A.out[B.qoff + q * B.sv + c] = o;
+      if (Qo) Qo[q] = o;
+    }
   }
   if (Rc) {
 #pragma unroll
