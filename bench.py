@@ -55,7 +55,7 @@ def make_case(name: str, flux: str):
         c = cases.batched_euler_case(64, seed=0)
         label = "batched_euler_64blk"
     elif name == "paper_share":
-        c = cases.paper_share_case(seed=0)
+        c = cases.paper_share_case(seed=0, log=lambda m: print(m, file=sys.stderr, flush=True))
         label = "ns_16x512x512x144"
     else:
         raise SystemExit(f"unknown workload {name}")

@@ -447,7 +447,7 @@ def channel_conditions(n: int, seed: int) -> np.ndarray:
 def paper_share_case(nbx: int = 4, nbz: int = 4, ni: int = 512, nj: int = 512, nk: int = 144,
                      seed: int = 0, mach: float = 0.8, reynolds: float = 1.0e6,
                      flux_fp32: int = 1, viscous: int = 1, amp: float = 0.05,
-                     stretch: float = 2.0, pulses: bool = True, cfl: float = 0.5) -> Case:
+                     stretch: float = 2.0, pulses: bool = True, cfl: float = 0.5, log=None) -> Case:
     """One GPU's share of a large multi-block wall-bounded flow.
 
     nbx x nbz blocks tile x in [0, nbx] and z in [0, nbz], each block one
@@ -455,7 +455,8 @@ def paper_share_case(nbx: int = 4, nbz: int = 4, ni: int = 512, nj: int = 512, n
     (a right-handed frame).  The lower k face is a no-slip adiabatic wall
     with a sinusoidal bump, the upper k face is far field at y = 1, and the
     outer x and z faces are periodic.  Eight seeded isentropic Gaussian
-    pressure pulses (amplitude 1e-2, sigma 0.1) ride on the stream.
+    pressure pulses (amplitude 1e-2, sigma 0.1) ride on the stream.  log, if
+    given, is called with a progress line after every block.
     """
     rng = np.random.default_rng(seed)
     par = Params(mach=mach, reynolds=reynolds, viscous=viscous, flux_fp32=flux_fp32, cfl=cfl)
@@ -481,6 +482,8 @@ def paper_share_case(nbx: int = 4, nbz: int = 4, ni: int = 512, nj: int = 512, n
                 q0.append(pressure_pulses(centroids(X), centres, 1e-2, 0.1, par))
             else:
                 q0.append(uniform_state((ni, nj, nk), par))
+            if log:
+                log(f"# block {len(dims)}/{nbx * nbz} generated")
     conns, bcs = [], []
     for bx in range(nbx):
         for bz in range(nbz):
