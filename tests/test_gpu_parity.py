@@ -70,12 +70,19 @@ def test_residual_parity(name, kernel):
     s.close()
 
 
+# The small parity grids get the tiled kernel by default (too few 64x8 tiles);
+# RING forces the plane-ring kernel, whose stage 1 reduces the history's norms
+# and whose stage 3 computes the next time step (global and local) itself.
+RING = {"kernel": 2, "tile_j": 8, "tile_k": 5}
+
+
+@pytest.mark.parametrize("tun", [None, RING], ids=["default", "ring"])
 @pytest.mark.parametrize("name,nsteps", [("vortex16", 20), ("vortex_curv", 8), ("bump_ns", 6),
                                          ("batched", 5), ("channel_local", 8)])
-def test_step_parity_fp64(name, nsteps):
+def test_step_parity_fp64(name, nsteps, tun):
     case = CASES[name]
-    say("steps", name, nsteps)
-    s = _solver(case)
+    say("steps", name, nsteps, tun)
+    s = _solver(case, **(tun or {}))
     h = s.step(nsteps).cpu().numpy()
     got = s.state()
     want, rows = oracle_steps(case, nsteps)
@@ -91,11 +98,12 @@ def test_step_parity_fp64(name, nsteps):
     s.close()
 
 
+@pytest.mark.parametrize("tun", [None, RING], ids=["default", "ring"])
 @pytest.mark.parametrize("name,nsteps", [("vortex16", 10), ("bump_ns", 4), ("batched", 4)])
-def test_step_parity_fp32_flux(name, nsteps):
+def test_step_parity_fp32_flux(name, nsteps, tun):
     case = CASES[name].with_params(flux_fp32=1)
-    say("fp32 steps", name)
-    s = _solver(case)
+    say("fp32 steps", name, tun)
+    s = _solver(case, **(tun or {}))
     s.step(nsteps)
     got = s.state()
     want, _ = oracle_steps(CASES[name], nsteps)
@@ -131,11 +139,12 @@ def test_graph_eager_tiles_kernels_bitwise(name, fp32):
             assert np.array_equal(a, b), t
 
 
-def test_run_to_run_bitwise():
+@pytest.mark.parametrize("tun", [None, RING], ids=["default", "ring"])
+def test_run_to_run_bitwise(tun):
     case = CASES["batched"]
     res = []
     for _ in range(2):
-        s = _solver(case)
+        s = _solver(case, **(tun or {}))
         h = s.step(3).cpu().numpy()
         res.append((s.state(), h))
         s.close()
