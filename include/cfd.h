@@ -96,11 +96,13 @@ typedef struct {
   int32_t viscous, flux_fp32, local_dt, ghost_layers;
 } cfd_params;
 
-/* Tuning knobs of the stage kernels.  Any value changes speed only, never
- * results (results are bitwise identical across all valid settings).
+/* Tuning knobs of the stage kernels.  Any value changes speed only: the
+ * state is bitwise identical across all valid settings; the history's norms
+ * and totals are sums in a fixed order that depends on the kernel and tiles,
+ * so across settings they agree to rounding (and bitwise run to run).
  * kernel: 0 = tiled face-once kernel, 1 = simple per-cell kernel,
  *   2 = plane-ring face-once kernel (a ring of three primitive planes in LDS,
- *   two barriers per plane; tile_j = 8 only).
+ *   two barriers per plane; tile_j = 4 or 8).
  * tile_j, tile_k: tile extent in j and k (tile_i is 64, one wavefront);
  *   the tiled kernel takes tile_j = 2, 4 or 8.  Defaults (set by
  *   cfd_create_blocks): kernel 2, tile_j 8, tile_k 32, use_graph 1, order 1;

@@ -1,4 +1,4 @@
-// Plane-ring face-once residual / stage kernel (64 x 8 tiles).
+// Plane-ring face-once residual / stage kernel (64 x 8 or 64 x 4 tiles).
 //
 // Same tile decomposition and per-face arithmetic as the tiled kernel, with a
 // different plane pipeline.  LDS holds a ring of three primitive planes
@@ -33,11 +33,9 @@
 
 namespace cfd {
 
-constexpr int RING_TJ = 8;
-
-template <typename T, bool VISC>
+template <typename T, bool VISC, int TJ_>
 struct RingLds {
-  static constexpr int TJ = RING_TJ;
+  static constexpr int TJ = TJ_;
   static constexpr int WI = 68, WJ = TJ + 4;   // halo 2
   static constexpr int NW = VISC ? 6 : 5;
   static constexpr int PLANE = NW * WJ * WI;   // elements of one plane
@@ -47,11 +45,10 @@ struct RingLds {
   static constexpr int TOTAL = W_BYTES + (FJ + FE) * 8;
 };
 
-template <typename T, bool VISC, int MODE>
-__global__ void __launch_bounds__(64 * RING_TJ) k_stage_ring(StageArgs A, const BlockDesc* __restrict__ blocks,
-                                                             const TileDesc* __restrict__ tiles, Gas<T> gas) {
-  using LD = RingLds<T, VISC>;
-  constexpr int TJ = RING_TJ;
+template <typename T, bool VISC, int MODE, int TJ>
+__global__ void __launch_bounds__(64 * TJ) k_stage_ring(StageArgs A, const BlockDesc* __restrict__ blocks,
+                                                        const TileDesc* __restrict__ tiles, Gas<T> gas) {
+  using LD = RingLds<T, VISC, TJ>;
   constexpr int NT = 64 * TJ;
   constexpr int WI = LD::WI, WJ = LD::WJ;
   __shared__ __attribute__((aligned(16))) char smem[LD::TOTAL];
@@ -275,47 +272,54 @@ __global__ void __launch_bounds__(64 * RING_TJ) k_stage_ring(StageArgs A, const 
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T, bool VISC, int MODE>
+template <typename T, bool VISC, int MODE, int TJ>
 static void launch_ring_t(const StageArgs& A, const BlockDesc* blocks, const TileDesc* tiles, const Gas<T>& gas,
                           int nwg, hipStream_t s) {
-  hipLaunchKernelGGL((k_stage_ring<T, VISC, MODE>), dim3(nwg), dim3(64 * RING_TJ), 0, s, A, blocks, tiles, gas);
+  hipLaunchKernelGGL((k_stage_ring<T, VISC, MODE, TJ>), dim3(nwg), dim3(64 * TJ), 0, s, A, blocks, tiles, gas);
 }
 
-template <typename T, bool VISC, int MODE>
+template <typename T, bool VISC, int MODE, int TJ>
 static int occ_ring_t() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stage_ring<T, VISC, MODE>, 64 * RING_TJ, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stage_ring<T, VISC, MODE, TJ>, 64 * TJ, 0) != hipSuccess)
     return 1;
   return n > 0 ? n : 1;
 }
 
-template <typename T, bool VISC>
+template <typename T, bool VISC, int TJ>
 static void ring_mode(const StageArgs& A, int mode, const BlockDesc* blocks, const TileDesc* tiles,
                       const Gas<T>& gas, int nwg, hipStream_t s, int* occ) {
   if (occ) {
-    *occ = mode == 0 ? occ_ring_t<T, VISC, 0>()
-                     : (mode == 1 ? occ_ring_t<T, VISC, 1>() : (mode == 2 ? occ_ring_t<T, VISC, 2>() : occ_ring_t<T, VISC, 3>()));
+    *occ = mode == 0 ? occ_ring_t<T, VISC, 0, TJ>()
+                     : (mode == 1 ? occ_ring_t<T, VISC, 1, TJ>()
+                                  : (mode == 2 ? occ_ring_t<T, VISC, 2, TJ>() : occ_ring_t<T, VISC, 3, TJ>()));
     return;
   }
-  if (mode == 0) launch_ring_t<T, VISC, 0>(A, blocks, tiles, gas, nwg, s);
-  else if (mode == 1) launch_ring_t<T, VISC, 1>(A, blocks, tiles, gas, nwg, s);
-  else if (mode == 2) launch_ring_t<T, VISC, 2>(A, blocks, tiles, gas, nwg, s);
-  else launch_ring_t<T, VISC, 3>(A, blocks, tiles, gas, nwg, s);
+  if (mode == 0) launch_ring_t<T, VISC, 0, TJ>(A, blocks, tiles, gas, nwg, s);
+  else if (mode == 1) launch_ring_t<T, VISC, 1, TJ>(A, blocks, tiles, gas, nwg, s);
+  else if (mode == 2) launch_ring_t<T, VISC, 2, TJ>(A, blocks, tiles, gas, nwg, s);
+  else launch_ring_t<T, VISC, 3, TJ>(A, blocks, tiles, gas, nwg, s);
 }
 
-// Launch (occ == nullptr) or query the resident workgroups per CU.  Needs
-// A.tile_j == 8.
+template <typename T, bool VISC>
+static bool ring_tj(const StageArgs& A, int mode, const BlockDesc* blocks, const TileDesc* tiles, const Gas<T>& gas,
+                    int nwg, hipStream_t s, int* occ) {
+  if (A.tile_j == 8) ring_mode<T, VISC, 8>(A, mode, blocks, tiles, gas, nwg, s, occ);
+  else if (A.tile_j == 4) ring_mode<T, VISC, 4>(A, mode, blocks, tiles, gas, nwg, s, occ);
+  else return false;
+  return true;
+}
+
+// Launch (occ == nullptr) or query the resident workgroups per CU.  Takes
+// A.tile_j = 4 or 8.
 bool stage_ring(const StageArgs& A, int mode, bool visc, bool fp32, const BlockDesc* blocks, const TileDesc* tiles,
                 const Gas<double>& g64, const Gas<float>& g32, int nwg, hipStream_t s, int* occ) {
-  if (A.tile_j != RING_TJ) return false;
   if (fp32) {
-    if (visc) ring_mode<float, true>(A, mode, blocks, tiles, g32, nwg, s, occ);
-    else ring_mode<float, false>(A, mode, blocks, tiles, g32, nwg, s, occ);
-  } else {
-    if (visc) ring_mode<double, true>(A, mode, blocks, tiles, g64, nwg, s, occ);
-    else ring_mode<double, false>(A, mode, blocks, tiles, g64, nwg, s, occ);
+    return visc ? ring_tj<float, true>(A, mode, blocks, tiles, g32, nwg, s, occ)
+                : ring_tj<float, false>(A, mode, blocks, tiles, g32, nwg, s, occ);
   }
-  return true;
+  return visc ? ring_tj<double, true>(A, mode, blocks, tiles, g64, nwg, s, occ)
+              : ring_tj<double, false>(A, mode, blocks, tiles, g64, nwg, s, occ);
 }
 
 }  // namespace cfd

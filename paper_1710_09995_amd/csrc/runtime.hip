@@ -441,9 +441,13 @@ int64_t count_tiles(const std::vector<cfd_dims>& dims, int tj, int tk) {
   return t;
 }
 
-// Default tuning for the grid: the plane-ring kernel with 64 x 8 x 32 tiles,
-// tile_k halved (down to 4) while there are fewer tiles than CUs, and the
-// tiled kernel with narrower tiles for grids that still leave CUs idle.
+// Default tuning for the grid: the plane-ring kernel with 64 x 8 x 32 tiles
+// (deep tiles amortise each tile's three plane fills; measured better than
+// 64 x 8 x 16 even where nk = 144 leaves a half-empty last tile), tile_k
+// halved (down to 4) while there are fewer tiles than CUs, and the tiled
+// kernel with narrower tiles for grids that still leave CUs idle.  Grids of
+// many small uneven blocks run faster with smaller tiles: the autotuner
+// finds them.
 cfd_tuning default_tuning(const std::vector<cfd_dims>& dims, int num_cu) {
   cfd_tuning t{2, 8, 32, 1, 1};
   while (t.tile_k > 4 && count_tiles(dims, t.tile_j, t.tile_k) < (int64_t)num_cu) t.tile_k /= 2;
@@ -579,7 +583,7 @@ void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, hipStream_t s) {
   } else if (c->tun.kernel == 2) {
     timed(c, 0, s, [&] {
       if (!stage_ring(A, mode, visc, fp32, c->dblocks, c->dtiles, c->g64, c->g32, nwg, s, nullptr))
-        fail(CFD_EINVAL, "plane-ring kernel needs tile_j = 8, got %d", c->tun.tile_j);
+        fail(CFD_EINVAL, "plane-ring kernel takes tile_j = 4 or 8, got %d", c->tun.tile_j);
     });
   } else {
     timed(c, 0, s, [&] { launch_stage_simple(A, mode, visc, fp32, c->dblocks, c->dtiles, c->g64, c->g32, nwg, s); });
@@ -596,22 +600,29 @@ void time_step_pass(cfd_ctx* c, const double* q, hipStream_t s) {
   launch_finalize(c->part_dt(), nwg, 0, 0.0, c->d_dt(), nullptr, nullptr, s);
 }
 
+// Whether stage 3 evaluates the next step's time step: the plane-ring kernel
+// on viscous flow (measured faster than the separate time-step kernel there;
+// slower on inviscid flow, whose stage kernel is cheap next to it).
+bool fused_dt(const cfd_ctx* c) { return c->tun.kernel == 2 && c->params.viscous; }
+
 // One full RK3 step: 3 x (ghost fill + stage), the time step of Q^n and the
 // history row (dt, L2(R(Q^n)), sum V Q^n, max |R_rho|).
-//  - plane-ring kernel: the time step of Q^n was left in d_dt (and the
-//    per-cell arena) by the previous step's stage 3, or by the time-step pass
-//    cfd_step runs before its first step; stage 1 reduces the history's norm
-//    partials itself and stage 3 those of the next time step.
-//  - other kernels: a time-step pass first (k_dt writes partial rows
-//    [0, nwg) of part_dt: min dt, sum V Q^n), stage 1 writes R(Q^n) to qb
-//    (free until stage 2 overwrites it) and the norms kernel adds the R rows.
+//  - Time step: with fused_dt, left in d_dt (and the per-cell arena) by the
+//    previous step's stage 3, or by the time-step pass cfd_step runs before
+//    its first step; otherwise a time-step pass first (k_dt writes partial
+//    rows [0, nwg) of part_dt: min dt, sum V Q^n).
+//  - History: the plane-ring kernel's stage 1 reduces the norm partials of
+//    R(Q^n) and V Q^n itself; the other kernels write R(Q^n) to qb (free until
+//    stage 2 overwrites it) and the norms kernel adds the R rows after k_dt's.
 // (Taking dt of the new state inside the tiled kernel's third stage was
-// measured slower: its extra metric loads cost more than the separate pass.
-// The plane-ring kernel has the register room for it.)
+// measured slower: its extra metric loads cost more than the separate pass.)
 void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
   const bool ring = c->tun.kernel == 2;
+  const bool fuse = fused_dt(c);
   const double inv_n = 1.0 / (double)c->ncells;
+  const int nwg_dt = dt_nwg(c);
   ghost_fill(c, q, s);
+  if (!fuse) time_step_pass(c, q, s);
   StageArgs A = stage_args(c);
   A.qs = q;
   A.qn = q;
@@ -621,12 +632,6 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
     launch_stage(c, A, 1, s);
     launch_finalize(c->part_nrm(), stage_nwg(c, 1), 1, inv_n, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
   } else {
-    const int nwg_dt = dt_nwg(c);
-    timed(c, 2, s, [&] {
-      launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
-                c->tun.tile_k, c->SP, nwg_dt, s);
-    });
-    launch_finalize(c->part_dt(), nwg_dt, 0, 0.0, c->d_dt(), nullptr, nullptr, s);
     A.rout = c->qb();
     launch_stage(c, A, 1, s);
     timed(c, 3, s, [&] {
@@ -648,7 +653,7 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
   A.out = q;
   A.a = 1.0 / 3.0;
   A.b = 2.0 / 3.0;
-  if (ring) {
+  if (fuse) {
     A.partials = c->part_dt();
     A.dt_out = c->params.local_dt ? c->scal() : nullptr;
     launch_stage(c, A, 3, s);
@@ -886,7 +891,8 @@ cfd_status cfd_set_tuning(cfd_ctx* c, const cfd_tuning* t) {
     if (t->order < 0 || t->order > 1) fail(CFD_EINVAL, "order must be 0 or 1");
     if (t->kernel == 0 && t->tile_j != 2 && t->tile_j != 4 && t->tile_j != 8)
       fail(CFD_EINVAL, "the tiled kernel takes tile_j = 2, 4 or 8");
-    if (t->kernel == 2 && t->tile_j != 8) fail(CFD_EINVAL, "the plane-ring kernel takes tile_j = 8");
+    if (t->kernel == 2 && t->tile_j != 4 && t->tile_j != 8)
+      fail(CFD_EINVAL, "the plane-ring kernel takes tile_j = 4 or 8");
     c->drop_graph();
     c->tun = *t;
     HIPCHK(hipDeviceSynchronize());
@@ -936,9 +942,9 @@ cfd_status cfd_step(cfd_ctx* c, double* q, int32_t nsteps, double* hist, hipStre
   return guard(c, [&] {
     if (!c || !q) fail(CFD_EINVAL, "NULL argument");
     if (nsteps < 0) fail(CFD_EINVAL, "nsteps must be >= 0");
-    // the plane-ring step takes the time step of Q^n from the step before;
+    // with fused_dt a step takes the time step of Q^n from the step before;
     // the state may have changed since, so the first one is computed here
-    if (nsteps > 0 && c->tun.kernel == 2) time_step_pass(c, q, s);
+    if (nsteps > 0 && fused_dt(c)) time_step_pass(c, q, s);
     if (c->tun.use_graph && !c->profiling) {
       if (!c->gexec || c->graph_q != q) {
         c->drop_graph();
