@@ -45,9 +45,17 @@ struct RingLds {
   static constexpr int TOTAL = W_BYTES + (FJ + FE) * 8;
 };
 
+// Minimum waves per SIMD asked of the register allocator: the FP32 Euler
+// variants fit 128 VGPRs (4 waves per SIMD; LDS allows two 64x8 or three
+// 64x4 workgroups per CU), the others take what they need.
+template <typename T, bool VISC>
+constexpr int ring_min_waves() {
+  return (sizeof(T) == 4 && !VISC) ? 4 : 1;
+}
+
 template <typename T, bool VISC, int MODE, int TJ>
-__global__ void __launch_bounds__(64 * TJ) k_stage_ring(StageArgs A, const BlockDesc* __restrict__ blocks,
-                                                        const TileDesc* __restrict__ tiles, Gas<T> gas) {
+__global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_ring(
+    StageArgs A, const BlockDesc* __restrict__ blocks, const TileDesc* __restrict__ tiles, Gas<T> gas) {
   using LD = RingLds<T, VISC, TJ>;
   constexpr int NT = 64 * TJ;
   constexpr int WI = LD::WI, WJ = LD::WJ;
