@@ -151,7 +151,7 @@ def main(argv=None):
         print(json.dumps({"calibrate_copy_bytes": n * 8, "copies": 5}), flush=True)
         return 0
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: this library has no multi-GPU path "
               "(sharding across GPUs is a design note, not code); use --gpus 1.", file=sys.stderr)
         return 2
 

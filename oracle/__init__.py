@@ -17,6 +17,6 @@ mlp        FP64 multilayer perceptron forward/backward (warm start)
 Parity status: every function is pinned by the CPU tests (closed forms,
 invariants, textbook special cases, brute force) except the trained
 warm-start network's output, which has no closed form ("parity unpinned";
-it is judged by residual history only).
+it is assessed by residual history only).
 """
 from . import geometry, ghosts, flux, solver  # noqa: F401

@@ -8,7 +8,7 @@ sequences the calls and moves tensors):
   2. train:  minibatch Adam on the MLP (BF16 MFMA forward, FP32 backward);
   3. start:  on a new (finer) case, the network's prediction at every cell
              becomes the initial state instead of the uniform stream;
-  4. judge:  steps and wall seconds until the density residual L2(R_rho)
+  4. compare: steps and wall seconds until the density residual L2(R_rho)
              falls below 1e-8 of the cold start's initial residual (one
              absolute threshold for both starts).
 """

@@ -5,7 +5,7 @@ two held-out cases of 48 x 24 x 24): the network is trained by the library's
 own forward/backward/Adam kernels on solutions the solver produced, and the
 warm start must begin below the cold start's residual and reach the deepest
 residual decade both starts reach in fewer steps.  The network's output has
-no closed form (parity unpinned); the residual history is the judge.
+no closed form (parity unpinned); the residual history decides.
 """
 import numpy as np
 import pytest
