@@ -1,0 +1,138 @@
+"""Pins for the oracle's block split and regroup (Section 3.2.1), CPU only.
+
+* The split plan tiles every block exactly once (brute-force occupancy), keeps
+  every piece within max_cells unless no direction may be cut, and gives the
+  hand-derived plans of a cube and of a thin column.
+* Longest-processing-time regroup: a hand-worked assignment, Graham's bound
+  against the brute-force optimum (reached exactly on his tight instance),
+  and capacity-proportional loads.
+* Split tables: every face cell of every piece is covered exactly once, every
+  seam is listed from both sides, and the oracle solver gives bitwise the
+  same states and history on the split case as on its parent (viscous walls,
+  far field, periodic seams, partial patches).
+"""
+import numpy as np
+import pytest
+
+from gpu_util import oracle_steps
+from oracle import partition as opart
+from paper_1710_09995_amd import cases
+
+
+def test_split_plan_cube_closed_form():
+    p = opart.split_plan([(64, 64, 64)], 32 ** 3)
+    # cut k first (equal extents: the higher direction), then j, then i; lower part first
+    want = [(i, j, k) for k in (0, 32) for j in (0, 32) for i in (0, 32)]
+    assert [q.lo for q in p] == want
+    assert all(q.n == (32, 32, 32) and q.parent == 0 for q in p)
+
+
+def test_split_plan_thin_column():
+    """3 x 3 x 100 with max_cells 10: only k may be cut (3 < 2 * 2).  By hand,
+    100 -> 50 + 50 -> 25 + 25 each; 25 -> 12 + 13; 12 -> 6 + 6 -> 3 + 3 each;
+    13 -> 6 + 7; 7 -> 3 + 4; 4 -> 2 + 2."""
+    p = opart.split_plan([(3, 3, 100)], 10, min_width=2)
+    quarter = [3, 3, 3, 3, 3, 3, 3, 2, 2]
+    assert [q.n[2] for q in p] == quarter * 4
+    assert all(q.n[:2] == (3, 3) for q in p)
+    assert [q.lo[2] for q in p] == list(np.cumsum([0] + quarter * 4)[:-1])
+
+
+def test_split_plan_tiles_blocks_exactly():
+    rng = np.random.default_rng(11)
+    dims = [tuple(int(v) for v in rng.integers(2, 41, 3)) for _ in range(12)]
+    for max_cells, wmin in ((500, 2), (64, 3), (10 ** 9, 2)):
+        pieces = opart.split_plan(dims, max_cells, wmin)
+        occ = [np.zeros((nk, nj, ni), np.int32) for ni, nj, nk in dims]
+        for q in pieces:
+            (i0, j0, k0), (ni, nj, nk) = q.lo, q.n
+            occ[q.parent][k0:k0 + nk, j0:j0 + nj, i0:i0 + ni] += 1
+            if q.cells > max_cells:
+                assert max(q.n) < 2 * wmin
+            assert min(q.n) >= min(wmin, min(dims[q.parent]))
+        for o in occ:
+            assert np.all(o == 1)
+        assert [q.parent for q in pieces] == sorted(q.parent for q in pieces)
+
+
+def test_regroup_worked_example():
+    """loads 5,1,4,2,3 on two groups, by hand: 5 -> g0 (5); 4 -> g1 (4);
+    3 -> g1 (7 < 8); 2 -> g0 (7 < 9); 1 -> g0 (8 = 8, lower group)."""
+    group, tot = opart.regroup([5, 1, 4, 2, 3], 2)
+    assert group == [0, 0, 1, 0, 1]
+    assert tot == [8, 7]
+
+
+def test_regroup_graham_bound_and_tight_instance():
+    group, tot = opart.regroup([3, 3, 2, 2, 2], 2)
+    assert max(tot) == 7 and opart.optimal_max_load([3, 3, 2, 2, 2], 2) == 6   # 7/6 = 4/3 - 1/6
+    rng = np.random.default_rng(5)
+    for _ in range(60):
+        m = int(rng.integers(2, 4))
+        loads = [int(v) for v in rng.integers(1, 20, int(rng.integers(m, 8)))]
+        group, tot = opart.regroup(loads, m)
+        assert set(group) <= set(range(m))
+        assert [sum(w for w, g in zip(loads, group) if g == h) for h in range(m)] == tot
+        opt = opart.optimal_max_load(loads, m)
+        assert 3 * m * max(tot) <= (4 * m - 1) * opt
+
+
+def test_regroup_special_cases():
+    assert opart.regroup([7, 3, 9], 1) == ([0, 0, 0], [19])
+    group, tot = opart.regroup([4] * 12, 4)
+    assert tot == [12, 12, 12, 12]
+    group, tot = opart.regroup([1] * 30, 2, capacity=[2.0, 1.0])
+    assert tot == [20, 10]
+
+
+def _split_cases():
+    bump = cases.bump_ns_case(24, 12, 8, seed=3, noise=1e-3, reynolds=5e3)
+    batched = cases.batched_euler_case(nblk=4, seed=4, lo=6, hi=23, flux_fp32=0)
+    vortex = cases.vortex_case(12, nz=8, seed=2, curvilinear=True)
+    return {"bump_ns": (bump, 300), "batched": (batched, 700), "vortex": (vortex, 200)}
+
+
+def _coverage(case):
+    cov = []
+    for b, (ni, nj, nk) in enumerate(case.dims):
+        cov.append({f: np.zeros(cases.face_extent((ni, nj, nk), f)[::-1], np.int32) for f in range(6)})
+    for t in list(case.conns) + list(case.bcs):
+        cov[t.blk][t.face][t.lo[1]:t.hi[1], t.lo[0]:t.hi[0]] += 1
+    return cov
+
+
+@pytest.mark.parametrize("name", ["bump_ns", "batched", "vortex"])
+def test_split_tables_cover_faces_once(name):
+    case, max_cells = _split_cases()[name]
+    for f in _coverage(case):
+        for a in f.values():
+            assert np.all(a == 1)
+    split, pieces = opart.split_case(case, max_cells)
+    assert len(pieces) > case.nblk
+    for f in _coverage(split):
+        for a in f.values():
+            assert np.all(a == 1)
+    keys = {(c.blk, c.face, c.nbr, c.lo, c.hi, c.nbr_lo) for c in split.conns}
+    for c in split.conns:
+        assert (c.nbr, c.nbr_face, c.blk, c.nbr_lo,
+                (c.nbr_lo[0] + c.hi[0] - c.lo[0], c.nbr_lo[1] + c.hi[1] - c.lo[1]), c.lo) in keys
+
+
+def _assemble(case, pieces, states):
+    out = [np.full((5, nk, nj, ni), np.nan) for ni, nj, nk in case.dims]
+    for q, s in zip(pieces, states):
+        (i0, j0, k0), (ni, nj, nk) = q.lo, q.n
+        out[q.parent][:, k0:k0 + nk, j0:j0 + nj, i0:i0 + ni] = s
+    return out
+
+
+@pytest.mark.parametrize("name,nsteps", [("bump_ns", 3), ("batched", 3), ("vortex", 3)])
+def test_split_case_is_the_same_problem(name, nsteps):
+    case, max_cells = _split_cases()[name]
+    split, pieces = opart.split_case(case, max_cells)
+    want, rows = oracle_steps(case, nsteps)
+    got, rows_s = oracle_steps(split, nsteps)
+    got = _assemble(case, pieces, got)
+    for a, b in zip(got, want):
+        assert np.array_equal(a, b)
+    assert np.array_equal(np.array(rows_s), np.array(rows))     # fsum norms: exact, order-free
