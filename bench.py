@@ -137,6 +137,10 @@ def main(argv=None):
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--split", type=int, default=0, metavar="MAX_CELLS",
+                    help="cut the blocks into pieces of at most MAX_CELLS cells first (Section 3.2.1)")
+    ap.add_argument("--groups", type=int, default=8,
+                    help="with --split: groups (devices) the pieces are regrouped into for the balance report")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (HBM counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -162,6 +166,20 @@ def main(argv=None):
     case, label = make_case(a.workload, a.flux)
     print(f"# workload {label}: {case.nblk} blocks, {case.ncells} cells, flux {a.flux}", file=sys.stderr,
           flush=True)
+    split_info = None
+    if a.split:
+        from paper_1710_09995_amd import partition as part
+
+        def balance(loads):
+            _, tot = part.regroup(loads, a.groups)
+            return round(max(tot) / (sum(tot) / a.groups), 4)
+
+        blocks_loads = [ni * nj * nk for ni, nj, nk in case.dims]
+        case, pieces = part.split_case(case, a.split)
+        split_info = {"max_cells": a.split, "blocks": len(blocks_loads), "pieces": len(pieces),
+                      "groups": a.groups, "max_over_mean_blocks": balance(blocks_loads),
+                      "max_over_mean_pieces": balance([p.cells for p in pieces])}
+        print(f"# split: {json.dumps(split_info)}", file=sys.stderr, flush=True)
     s = Solver(case, device="cuda:0")
     tun = {}
     if a.kernel is not None:
@@ -211,7 +229,7 @@ def main(argv=None):
         bpc = stage_bytes_per_cell(bool(case.params.local_dt))
         per_launch = bpc * case.ncells
         achieved = per_launch / (st["mean_ms"] / 1e3) / 1e9
-        kernel_label = f"stage_{label}_{a.flux}"
+        kernel_label = f"stage_{label}_{a.flux}" + (f"_split{a.split}" if a.split else "")
         traffic = read_traffic(kernel_label)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -243,7 +261,7 @@ def main(argv=None):
         "data": "synthetic (seeded grid, state and noise)",
         "config": {"workload": label, "blocks": case.nblk, "cells": case.ncells,
                    "viscous": bool(case.params.viscous), "flux": a.flux, "stages_per_step": 3,
-                   "tuning": tune, "autotune": tune_info, "finite": finite},
+                   "tuning": tune, "autotune": tune_info, "finite": finite, "split": split_info},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

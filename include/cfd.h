@@ -49,7 +49,7 @@ extern "C" {
 typedef enum {
   CFD_OK = 0,
   CFD_EINVAL = -1,        /* bad argument, table or size                        */
-  CFD_ENOMEM = -2,        /* workspace smaller than cfd_workspace_size()        */
+  CFD_ENOMEM = -2,        /* workspace or output array too small                */
   CFD_EHIP = -3,          /* a HIP runtime call failed                          */
   CFD_ENONFINITE = -4,    /* NaN or Inf found in the state or residual          */
   CFD_ESTATE = -5,        /* call not valid in the context's current state      */
@@ -202,6 +202,50 @@ cfd_status cfd_profile_read(cfd_ctx* ctx, double out[16]);
  * (x[+t2] - x[+t1]) with (t1, t2) cyclic after d; V by the divergence theorem
  * (the geometric conservation requirement of Section 2.2). */
 cfd_status cfd_copy_metrics(cfd_ctx* ctx, int32_t blk, double* out_dev, hipStream_t stream);
+
+/* ------------------------------------------------------ split and regroup
+ * Load balance by re-partitioning (Section 3.2.1): the blocks of the grid are
+ * cut into smaller pieces, and the pieces are dealt into balanced groups, one
+ * per device.  The paper leaves the algorithm to a pre-processing tool that it
+ * does not print; these are the library's rules.  All three calls are
+ * host-only and synchronous and touch no device; output arrays are the
+ * caller's.  An output array may be NULL: the call then only stores the
+ * count.  An array too small for the count gives CFD_ENOMEM and is left
+ * unwritten (the count is stored; call again with a larger array). */
+typedef struct { int32_t parent; int32_t lo[3]; int32_t n[3]; } cfd_piece;   /* cells lo .. lo+n-1 of parent */
+
+/* Split plan.  A block of more than max_cells cells is cut in two across its
+ * longest index direction (equal extents: the higher direction, k before j
+ * before i), the lower part taking floor(n/2) cells; both parts are split
+ * again by the same rule.  A part whose every extent is below 2*min_width is
+ * kept whole, however large.  Pieces are listed block by block, depth first,
+ * lower part first.  max_cells >= 1; min_width >= 2 (the ghost depth). */
+cfd_status cfd_split_plan(int32_t nblk, const cfd_dims* dims, int64_t max_cells, int32_t min_width,
+                          cfd_piece* pieces, int32_t capacity, int32_t* npieces);
+
+/* Connection and boundary tables of a set of pieces that tiles every block
+ * (checked: every cell exactly once).  A piece face inside its parent becomes
+ * a connection to each sibling piece across it (zero shift, both sides
+ * listed); a piece face on its parent's face takes the parent's boundary
+ * patches and connections there, cut to the piece, and each connection is
+ * cut again to every piece of the neighbour block that it reaches (shift
+ * kept).  The parent tables are checked as cfd_create_blocks checks them.
+ * With the pieces' nodes and states sliced from their parents, the solver
+ * gives the pieces bitwise the same state as the parent blocks. */
+cfd_status cfd_split_tables(int32_t nblk, const cfd_dims* dims, const cfd_conn* conns, int32_t nconn,
+                            const cfd_bc* bcs, int32_t nbc, const cfd_piece* pieces, int32_t npieces,
+                            cfd_conn* out_conns, int32_t conn_capacity, int32_t* nconn_out, cfd_bc* out_bcs,
+                            int32_t bc_capacity, int32_t* nbc_out);
+
+/* Regroup by longest processing time first (Graham, 1969): items in
+ * decreasing load (equal loads: lower index first) each go to the group g
+ * whose (load after taking the item) / capacity[g] is least (equal: lower g;
+ * computed in FP64).  capacity (may be NULL: all 1) carries the paper's load
+ * ratio between unlike devices; with equal capacities the largest group load
+ * is at most (4/3 - 1/(3 ngroups)) times the optimum.  group[i] in
+ * [0, ngroups); group_load (may be NULL) receives each group's total. */
+cfd_status cfd_regroup(int32_t n, const int64_t* load, int32_t ngroups, const double* capacity,
+                       int32_t* group, int64_t* group_load);
 
 /* ---------------------------------------------------------------- warm start
  * A multilayer perceptron predicts the steady flow of a channel-bump case

@@ -38,6 +38,10 @@ class BCS(C.Structure):
                 ("lo", C.c_int32 * 2), ("hi", C.c_int32 * 2), ("pad", C.c_int32), ("mach", C.c_double)]
 
 
+class PieceS(C.Structure):
+    _fields_ = [("parent", C.c_int32), ("lo", C.c_int32 * 3), ("n", C.c_int32 * 3)]
+
+
 class ParamsS(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("gamma", "prandtl", "mach", "alpha", "beta", "reynolds",
                                            "sutherland", "cfl", "entropy_fix", "limiter_eps")] + \
@@ -59,6 +63,7 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_time_step", "cfd_copy_metrics", "cfd_set_profiling", "cfd_profile_read",
            "cfd_mlp_sizes", "cfd_mlp_forward", "cfd_mlp_mse", "cfd_mlp_backward", "cfd_mlp_adam",
            "cfd_mlp_to_bf16", "cfd_mlp_features", "cfd_mlp_targets", "cfd_mlp_to_state",
+           "cfd_split_plan", "cfd_split_tables", "cfd_regroup",
            "cfd_status_string", "cfd_last_error"]
 
 _lib = None
@@ -102,6 +107,11 @@ def lib(build_if_missing: bool = True):
     L.cfd_mlp_features.argtypes = [vp, vp, vp, vp]
     L.cfd_mlp_targets.argtypes = [vp, vp, vp, vp, vp]
     L.cfd_mlp_to_state.argtypes = [vp, vp, vp, vp, vp]
+    i32p = C.POINTER(C.c_int32)
+    L.cfd_split_plan.argtypes = [i32, C.POINTER(Dims), C.c_int64, i32, C.POINTER(PieceS), i32, i32p]
+    L.cfd_split_tables.argtypes = [i32, C.POINTER(Dims), C.POINTER(ConnS), i32, C.POINTER(BCS), i32,
+                                   C.POINTER(PieceS), i32, C.POINTER(ConnS), i32, i32p, C.POINTER(BCS), i32, i32p]
+    L.cfd_regroup.argtypes = [i32, i64p, i32, C.POINTER(C.c_double), i32p, i64p]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]

@@ -18,6 +18,7 @@
 
 #include "../../include/cfd.h"
 #include "cfd_internal.hpp"
+#include "host_services.hpp"
 
 namespace cfd {
 void launch_copy_nodes(const double* src, double* x, const BlockDesc& B, hipStream_t s);
@@ -689,6 +690,22 @@ void check_launch() {
 }
 
 }  // namespace
+
+namespace cfd {
+
+cfd_status host_guarded(const std::function<void()>& f) { return guard(nullptr, f); }
+
+void host_fail(cfd_status st, const std::string& msg) { throw Err(st, msg); }
+
+void host_check_dims(int nblk, const cfd_dims* dims) { check_dims(nblk, dims); }
+
+void host_check_case(int nblk, const cfd_dims* dims, int nconn, const cfd_conn* conns, int nbc,
+                     const cfd_bc* bcs) {
+  check_dims(nblk, dims);
+  validate_tables(nblk, dims, nconn, conns, nbc, bcs);
+}
+
+}  // namespace cfd
 
 extern "C" {
 

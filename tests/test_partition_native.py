@@ -1,0 +1,106 @@
+"""The library's split and regroup calls (host-only, no GPU) against the
+oracle's, exactly: these are integer and index results.  Error paths of the
+calls as include/cfd.h documents them."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle import partition as opart
+from paper_1710_09995_amd import binding as B
+from paper_1710_09995_amd import cases
+from paper_1710_09995_amd import partition as part
+
+
+def _plan_tuple(pieces):
+    return [(p.parent, tuple(p.lo), tuple(p.n)) for p in pieces]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_split_plan_matches_oracle(seed):
+    rng = np.random.default_rng(seed)
+    dims = [tuple(int(v) for v in rng.integers(2, 120, 3)) for _ in range(20)]
+    for max_cells in (300, 5000, 37_000, 10 ** 12):
+        for wmin in (2, 3, 8):
+            assert _plan_tuple(part.split_plan(dims, max_cells, wmin)) == \
+                _plan_tuple(opart.split_plan(dims, max_cells, wmin))
+
+
+def _conn_key(c):
+    return (c.blk, c.face, c.nbr, c.nbr_face, tuple(c.lo), tuple(c.hi), tuple(c.nbr_lo),
+            tuple(float(v) for v in c.shift))
+
+
+def _bc_key(b):
+    return (b.blk, b.face, b.kind, tuple(b.lo), tuple(b.hi), float(b.mach))
+
+
+def _table_cases():
+    return [(cases.bump_ns_case(24, 12, 8, seed=3), 300),
+            (cases.batched_euler_case(nblk=4, seed=4, lo=6, hi=23, flux_fp32=0), 700),
+            (cases.vortex_case(12, nz=8, seed=2, curvilinear=True), 200),
+            (cases.batched_euler_case(nblk=64, seed=0, lo=4, hi=41), 3_000),
+            (cases.channel_case(40, 12, 6, mach=0.7, hb=0.08), 500)]
+
+
+@pytest.mark.parametrize("k", range(5))
+def test_split_tables_match_oracle(k):
+    case, max_cells = _table_cases()[k]
+    pieces = opart.split_plan(case.dims, max_cells)
+    assert len(pieces) > case.nblk
+    want_c, want_b = opart.split_tables(case.dims, case.conns, case.bcs, pieces)
+    got_c, got_b = part.split_tables(case, [part.Piece(p.parent, p.lo, p.n) for p in pieces])
+    assert sorted(map(_conn_key, got_c)) == sorted(map(_conn_key, want_c))
+    assert sorted(map(_bc_key, got_b)) == sorted(map(_bc_key, want_b))
+
+
+def test_split_case_tables_accepted_by_create_validation():
+    """The split tables pass the same checks cfd_create_blocks applies."""
+    case, max_cells = _table_cases()[3]
+    split, pieces = part.split_case(case, max_cells)
+    assert sum(p.cells for p in pieces) == case.ncells
+    L = B.lib()
+    nc, nb = C.c_int32(), C.c_int32()
+    st = L.cfd_split_tables(split.nblk, B.to_dims(split.dims), B.to_conns(split.conns), len(split.conns),
+                            B.to_bcs(split.bcs), len(split.bcs),
+                            part._to_pieces([part.Piece(b, (0, 0, 0), d) for b, d in enumerate(split.dims)]),
+                            split.nblk, None, 0, C.byref(nc), None, 0, C.byref(nb))
+    assert st == 0 and nc.value == len(split.conns) and nb.value == len(split.bcs)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_regroup_matches_oracle(seed):
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(25):
+        n = int(rng.integers(0, 300))
+        m = int(rng.integers(1, 17))
+        loads = [int(v) for v in rng.integers(0, 10 ** int(rng.integers(1, 12)), n)]
+        cap = None if seed % 2 == 0 else [float(v) for v in rng.uniform(0.25, 4.0, m)]
+        assert part.regroup(loads, m, cap) == opart.regroup(loads, m, cap)
+
+
+def test_error_paths():
+    with pytest.raises(B.CfdError) as e:
+        part.split_plan([(8, 8, 8)], 0)
+    assert e.value.status == -1
+    with pytest.raises(B.CfdError) as e:
+        part.split_plan([(8, 8, 8)], 10, min_width=1)
+    assert e.value.status == -1
+    case = cases.vortex_case(8)
+    with pytest.raises(B.CfdError) as e:      # pieces that leave a gap
+        part.split_tables(case, [part.Piece(0, (0, 0, 0), (8, 8, 4))])
+    assert e.value.status == -1 and "tile" in str(e.value)
+    with pytest.raises(B.CfdError) as e:      # overlapping pieces with the right total
+        part.split_tables(case, [part.Piece(0, (0, 0, 0), (8, 8, 4)), part.Piece(0, (0, 0, 2), (8, 8, 4))])
+    assert e.value.status == -1 and "overlap" in str(e.value)
+    L = B.lib()
+    arr = (B.PieceS * 3)()
+    n = C.c_int32()
+    st = L.cfd_split_plan(1, B.to_dims([(8, 8, 8)]), 64, 2, arr, 3, C.byref(n))
+    assert st == -2 and n.value == 8            # too small: count stored, nothing written
+    with pytest.raises(B.CfdError):
+        part.regroup([1, -1], 2)
+    with pytest.raises(B.CfdError):
+        part.regroup([1, 2], 2, capacity=[1.0, 0.0])
+    with pytest.raises(B.CfdError):
+        part.regroup([1, 2], 0)
