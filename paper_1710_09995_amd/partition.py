@@ -99,3 +99,22 @@ def assemble(case: cases.Case, pieces: Sequence[Piece], states) -> list:
         (i0, j0, k0), (ni, nj, nk) = p.lo, p.n
         out[p.parent][:, k0:k0 + nk, j0:j0 + nj, i0:i0 + ni] = s
     return out
+
+
+def balance_report(dims: Sequence[Sequence[int]], groups: Sequence[int] = (8, 16, 32, 64, 128),
+                   pieces_per_group: int = 4, min_width: int = 2) -> list:
+    """For each group count G: the largest group load over the mean when the
+    blocks are regrouped as they are, and when they are first split to at most
+    total / (pieces_per_group * G) cells (loads in cells)."""
+    loads = [int(a) * int(b) * int(c) for a, b, c in dims]
+    total = sum(loads)
+    rows = []
+    for G in groups:
+        _, t_blocks = regroup(loads, G)
+        max_cells = max(1, total // (pieces_per_group * G))
+        pieces = split_plan(dims, max_cells, min_width)
+        _, t_pieces = regroup([p.cells for p in pieces], G)
+        rows.append({"groups": G, "blocks": len(loads), "max_over_mean_blocks": max(t_blocks) * G / total,
+                     "max_cells": max_cells, "pieces": len(pieces),
+                     "max_over_mean_pieces": max(t_pieces) * G / total})
+    return rows
