@@ -162,18 +162,24 @@ __global__ void k_metric_ghosts(double* __restrict__ met, const BlockDesc* __res
 }
 
 // Ghost fill of the conserved state (one sweep, all patches of all blocks).
+// One thread per transverse point, except on i-face connections: there the
+// NG ghost cells of a row are adjacent in memory while neighbouring points
+// are a row apart, so a thread per (point, layer) puts a row's layers on
+// adjacent lanes and halves the memory segments each access touches.
 __global__ void k_ghost_q(double* __restrict__ q, const double* __restrict__ met,
                           const BlockDesc* __restrict__ blocks,
                           const PatchDesc* __restrict__ patches, StepParams SP) {
   const PatchDesc& P = patches[blockIdx.y];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= P.count) return;
   const int d = P.face >> 1, side = P.face & 1;
+  const int per = ghost_threads_per_point(P.kind, d);
+  if (t >= P.count * per) return;
+  const int pt = t / per;
   // transverse directions t1 < t2, selected without indexing (keeps P out of scratch)
   const int lo1 = d == 0 ? P.lo[1] : P.lo[0], hi1 = d == 0 ? P.hi[1] : P.hi[0];
   const int lo2 = d == 2 ? P.lo[1] : P.lo[2];
   const int w1 = hi1 - lo1;
-  const int p1 = lo1 + t % w1, p2 = lo2 + t / w1;
+  const int p1 = lo1 + pt % w1, p2 = lo2 + pt / w1;
   const BlockDesc& B = blocks[P.blk];
   const int n = d == 0 ? B.n[0] : (d == 1 ? B.n[1] : B.n[2]);
   double* qb = q + B.qoff;
@@ -182,13 +188,28 @@ __global__ void k_ghost_q(double* __restrict__ q, const double* __restrict__ met
     const double* qn = q + N.qoff;
     const int nn = d == 0 ? N.n[0] : (d == 1 ? N.n[1] : N.n[2]);
     const int o1 = d == 0 ? P.noff[1] : P.noff[0], o2 = d == 2 ? P.noff[1] : P.noff[2];
+    // Every load before the first store: source and destination share one
+    // arena, so a load issued after a store would wait for it.
+    if (per != 1) {     // this thread's layer only
+      const int m = 1 + t % per;
+      const int64_t od = pos3(d, side == 0 ? -m : n - 1 + m, p1, p2, B.sj, B.sk);
+      const int64_t os = pos3(d, side == 0 ? nn - m : m - 1, p1 + o1, p2 + o2, N.sj, N.sk);
+      double val[NV];
+      for (int v = 0; v < NV; ++v) val[v] = qn[v * N.sv + os];
+      for (int v = 0; v < NV; ++v) qb[v * B.sv + od] = val[v];
+      return;
+    }
+    double val[NG][NV];
+    int64_t od[NG];
     for (int m = 1; m <= NG; ++m) {
       const int gm = side == 0 ? -m : n - 1 + m;
       const int sm = side == 0 ? nn - m : m - 1;
-      const int64_t od = pos3(d, gm, p1, p2, B.sj, B.sk);
+      od[m - 1] = pos3(d, gm, p1, p2, B.sj, B.sk);
       const int64_t os = pos3(d, sm, p1 + o1, p2 + o2, N.sj, N.sk);
-      for (int v = 0; v < NV; ++v) qb[v * B.sv + od] = qn[v * N.sv + os];
+      for (int v = 0; v < NV; ++v) val[m - 1][v] = qn[v * N.sv + os];
     }
+    for (int m = 0; m < NG; ++m)
+      for (int v = 0; v < NV; ++v) qb[v * B.sv + od[m]] = val[m][v];
     return;
   }
   // boundary face vector at this transverse position
@@ -217,13 +238,17 @@ __global__ void k_ghost_q(double* __restrict__ q, const double* __restrict__ met
     }
     return;
   }
+  double wv[NG][NV];       // the mirrored interior cells, all loaded before any store
+  for (int m = 1; m <= NG; ++m) {
+    const int im = side == 0 ? m - 1 : n - m;
+    const int64_t oi = pos3(d, im, p1, p2, B.sj, B.sk);
+    for (int v = 0; v < NV; ++v) wv[m - 1][v] = qb[v * B.sv + oi];
+  }
   for (int m = 1; m <= NG; ++m) {
     const int gm = side == 0 ? -m : n - 1 + m;
-    const int im = side == 0 ? m - 1 : n - m;
     const int64_t od = pos3(d, gm, p1, p2, B.sj, B.sk);
-    const int64_t oi = pos3(d, im, p1, p2, B.sj, B.sk);
-    const double r = qb[oi], mx = qb[B.sv + oi], my = qb[2 * B.sv + oi], mz = qb[3 * B.sv + oi],
-                 e = qb[4 * B.sv + oi];
+    const double r = wv[m - 1][0], mx = wv[m - 1][1], my = wv[m - 1][2], mz = wv[m - 1][3],
+                 e = wv[m - 1][4];
     double gx, gy, gz;
     if (P.kind == CFD_BC_KIND_SLIPWALL) {
       const double mn = mx * nx + my * ny + mz * nz;
@@ -300,10 +325,10 @@ void launch_metric_ghosts(double* met, const BlockDesc* blocks, const PatchDesc*
 }
 
 void launch_ghost_q(double* q, const double* met, const BlockDesc* blocks,
-                    const PatchDesc* patches, int npatch, int maxcount, const StepParams& SP,
+                    const PatchDesc* patches, int npatch, int nthreads, const StepParams& SP,
                     hipStream_t s) {
   if (npatch == 0) return;
-  hipLaunchKernelGGL(k_ghost_q, dim3((maxcount + 127) / 128, npatch), dim3(128), 0, s, q, met,
+  hipLaunchKernelGGL(k_ghost_q, dim3((nthreads + 127) / 128, npatch), dim3(128), 0, s, q, met,
                      blocks, patches, SP);
 }
 

@@ -29,7 +29,7 @@ void launch_visc_metrics(const double* met, double* vmet, const BlockDesc& B, hi
 void launch_metric_ghosts(double* met, const BlockDesc* blocks, const PatchDesc* patches, int npatch,
                           int maxcount, hipStream_t s);
 void launch_ghost_q(double* q, const double* met, const BlockDesc* blocks, const PatchDesc* patches,
-                    int npatch, int maxcount, const StepParams& SP, hipStream_t s);
+                    int npatch, int nthreads, const StepParams& SP, hipStream_t s);
 bool stage_ring(const StageArgs& A, int mode, bool visc, bool fp32, const BlockDesc* blocks, const TileDesc* tiles,
                 const Gas<double>& g64, const Gas<float>& g32, int nwg, hipStream_t s, int* occ);
 bool stage_tiled(const StageArgs& A, int mode, bool visc, bool fp32, const BlockDesc* blocks,
@@ -329,6 +329,7 @@ struct cfd_ctx {
   PatchDesc* dpatches = nullptr;
   // per sweep: [node sweeps 0..2][cell sweeps 0..2]
   int poff[6] = {0}, pcount[6] = {0}, pmax[6] = {0};
+  int qthreads[3] = {0};   // threads of each state ghost sweep (k_ghost_q)
   TileDesc* dtiles = nullptr;
   int ntiles = 0;
   int64_t ncells = 0;
@@ -531,7 +532,7 @@ void timed(cfd_ctx* c, int cls, hipStream_t s, F&& launch) {
 void ghost_fill(cfd_ctx* c, double* q, hipStream_t s) {
   for (int d = 0; d < 3; ++d)
     timed(c, 1, s, [&] {
-      launch_ghost_q(q, c->met(), c->dblocks, c->dpatches + c->poff[3 + d], c->pcount[3 + d], c->pmax[3 + d],
+      launch_ghost_q(q, c->met(), c->dblocks, c->dpatches + c->poff[3 + d], c->pcount[3 + d], c->qthreads[d],
                      c->SP, s);
     });
 }
@@ -807,6 +808,9 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
       build_patches(d, nodes, params, dims, nconn, conns, nbc, bcs, all, mx);
       c->pcount[sweep] = (int)all.size() - c->poff[sweep];
       c->pmax[sweep] = mx;
+      if (!nodes)
+        for (int p = c->poff[sweep]; p < (int)all.size(); ++p)
+          c->qthreads[d] = std::max(c->qthreads[d], all[p].count * ghost_threads_per_point(all[p].kind, d));
     }
     HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     {
