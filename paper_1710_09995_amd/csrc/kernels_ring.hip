@@ -43,6 +43,10 @@ struct RingLds {
   static constexpr int FJ = 5 * (TJ + 1) * 64;  // doubles: lower j-faces, TJ+1 rows
   static constexpr int FE = 5 * TJ;             // doubles: i-faces at i0+64
   static constexpr int TOTAL = W_BYTES + (FJ + FE) * 8;
+  // stage 3 also keeps the area vectors of those faces for the time step
+  static constexpr int SJ = 3 * (TJ + 1) * 64;  // doubles: S_j of the lower j-faces
+  static constexpr int SE = 3 * TJ;             // doubles: S_i at i0+64
+  static constexpr int TOTAL_DT = TOTAL + (SJ + SE) * 8;
 };
 
 // Minimum waves per SIMD asked of the register allocator: the FP32 Euler
@@ -59,10 +63,12 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
   using LD = RingLds<T, VISC, TJ>;
   constexpr int NT = 64 * TJ;
   constexpr int WI = LD::WI, WJ = LD::WJ;
-  __shared__ __attribute__((aligned(16))) char smem[LD::TOTAL];
+  __shared__ __attribute__((aligned(16))) char smem[MODE == 3 ? LD::TOTAL_DT : LD::TOTAL];
   T* sW = reinterpret_cast<T*>(smem);                                   // [3][NW][WJ][WI]
   double* sFj = reinterpret_cast<double*>(smem + LD::W_BYTES);          // [5][TJ+1][64]
   double* sFe = sFj + LD::FJ;                                           // [5][TJ]
+  double* sSj = sFe + LD::FE;                                           // mode 3: [3][TJ+1][64]
+  double* sSe = sSj + LD::SJ;                                           // mode 3: [3][TJ]
 
   auto W = [&](int slot, int v, int pj, int pi) -> T& { return sW[slot * LD::PLANE + (v * WJ + pj) * WI + pi]; };
   auto wprim = [&](int slot, int pj, int pi) {
@@ -148,10 +154,14 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
       CellIn cin;
       if (act) load_cell<MODE>(A, B, off(i, j, k), cin);
       // ---- A. faces of plane k
-      auto face_i = [&](int ci, int rj, double F[5]) {   // lower i-face of cell (i0+ci, j0+rj)
+      // lower i-face of cell (i0+ci, j0+rj): flux F, area vector S
+      auto face_i = [&](int ci, int rj, double F[5], double S[3]) {
         const int pi = ci + 2, pj = rj + 2;
         const int64_t c = off(i0 + ci, j0 + rj, k);
         const double sx = mb[c], sy = mb[sv + c], sz = mb[2 * sv + c];
+        S[0] = sx;
+        S[1] = sy;
+        S[2] = sz;
         T f[5], n[3];
         const double area = face_inviscid<T>(wprim(s0, pj, pi - 2), wprim(s0, pj, pi - 1), wprim(s0, pj, pi),
                                              wprim(s0, pj, pi + 1), sx, sy, sz, gas, f, n);
@@ -173,6 +183,11 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
         const int pi = ci + 2, pj = rj + 2;
         const int64_t c = off(i0 + ci, j0 + rj, k);
         const double sx = mb[3 * sv + c], sy = mb[4 * sv + c], sz = mb[5 * sv + c];
+        if (MODE == 3) {
+          sSj[(0 * (TJ + 1) + rj) * 64 + ci] = sx;
+          sSj[(1 * (TJ + 1) + rj) * 64 + ci] = sy;
+          sSj[(2 * (TJ + 1) + rj) * 64 + ci] = sz;
+        }
         T f[5], n[3];
         const double area = face_inviscid<T>(wprim(s0, pj - 2, pi), wprim(s0, pj - 1, pi), wprim(s0, pj, pi),
                                              wprim(s0, pj + 1, pi), sx, sy, sz, gas, f, n);
@@ -193,15 +208,20 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
         for (int q = 0; q < 5; ++q) sFj[(q * (TJ + 1) + rj) * 64 + ci] = F[q];
       };
       double Fi[5] = {0, 0, 0, 0, 0};
-      if (fi_ok) face_i(tx, ty, Fi);
+      if (fi_ok) {
+        double Si[3];
+        face_i(tx, ty, Fi, Si);
+      }
       CFD_FACE_FENCE_RING();
       if (fj_ok) face_j(tx, ty);
       CFD_FACE_FENCE_RING();
       if (ty == 0 && has_xj) face_j(tx, TJ);
       if (ty == 1 && has_xi) {
-        double Fe[5];
-        face_i(64, tx, Fe);
+        double Fe[5], Se[3];
+        face_i(64, tx, Fe, Se);
         for (int q = 0; q < 5; ++q) sFe[q * TJ + tx] = Fe[q];
+        if (MODE == 3)
+          for (int x = 0; x < 3; ++x) sSe[x * TJ + tx] = Se[x];
       }
       CFD_FACE_FENCE_RING();
       double Fku[5] = {0, 0, 0, 0, 0};
@@ -235,8 +255,33 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
       const bool more = k + 1 < kend;
       Prim<T> q3n = q3;
       if (act && more) q3n = ld_prim<T>(qb, off(i, j, k) + 3 * sk, sv, gas.gm1);
-      double bdt[3][3];   // mode 3: face-averaged area vectors of the cell
-      if (MODE == 3 && act) dt_vectors(mb, off(i, j, k), sv, sj, sk, bdt);
+      // mode 3: the cell's face-averaged area vectors b[d] = (S_d(c) + S_d(c + e_d)) / 2.
+      // Upper faces from this plane's face work: S_i of the next lane
+      // (shuffle; the tile-edge face from LDS for lane 63), S_j of the next
+      // row (LDS), S_k from the k-face (registers).  The lower i- and k-faces
+      // are loaded again (cheaper than keeping them live through the faces).
+      double bdt[3][3];
+      if (MODE == 3) {
+        double Si[3] = {0, 0, 0}, Sk[3] = {0, 0, 0}, Sku[3] = {0, 0, 0};
+        if (fi_ok) {
+          const int64_t c = off(i, j, k);
+          for (int x = 0; x < 3; ++x) Si[x] = mb[x * sv + c];
+        }
+        if (act) {
+          const int64_t c = off(i, j, k);
+          for (int x = 0; x < 3; ++x) Sk[x] = mb[(6 + x) * sv + c];
+          for (int x = 0; x < 3; ++x) Sku[x] = mb[(6 + x) * sv + c + sk];
+        }
+        double Siu[3];
+        for (int x = 0; x < 3; ++x) Siu[x] = __shfl_down(Si[x], 1, 64);
+        if (act)
+          for (int x = 0; x < 3; ++x) {
+            const double su = tx == 63 ? sSe[x * TJ + ty] : Siu[x];
+            bdt[0][x] = 0.5 * (Si[x] + su);
+            bdt[1][x] = 0.5 * (sSj[(x * (TJ + 1) + ty) * 64 + tx] + sSj[(x * (TJ + 1) + ty + 1) * 64 + tx]);
+            bdt[2][x] = 0.5 * (Sk[x] + Sku[x]);
+          }
+      }
       if (more) fill(sm, k + 2);
       if (act) {
         double Di[5], Dj[5], Dk[5];
