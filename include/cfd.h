@@ -105,7 +105,8 @@ typedef struct {
  *   two barriers per plane; tile_j = 4 or 8).
  * tile_j, tile_k: tile extent in j and k (tile_i is 64, one wavefront);
  *   the tiled kernel takes tile_j = 2, 4 or 8.  Defaults (set by
- *   cfd_create_blocks): kernel 2, tile_j 8, tile_k 32, use_graph 1, order 1;
+ *   cfd_create_blocks): kernel 2, tile_j 8, tile_k 32 (16 for FP32-flux
+ *   Euler, whose kernels hold two workgroups per CU), use_graph 1, order 1;
  *   tile_k is halved (down to 4) while the grid gives fewer tiles than CUs,
  *   and a grid with fewer tiles than CUs even then gets the tiled kernel
  *   with tile_j halved (down to 2) until it has one tile per CU.

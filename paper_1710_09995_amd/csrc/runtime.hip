@@ -450,8 +450,10 @@ int64_t count_tiles(const std::vector<cfd_dims>& dims, int tj, int tk) {
 // kernel with narrower tiles for grids that still leave CUs idle.  Grids of
 // many small uneven blocks run faster with smaller tiles: the autotuner
 // finds them.
-cfd_tuning default_tuning(const std::vector<cfd_dims>& dims, int num_cu) {
-  cfd_tuning t{2, 8, 32, 1, 1};
+// The FP32-flux Euler plane-ring kernels hold two workgroups per CU; tiles of
+// half the depth fill both and shorten the tail of the persistent grid.
+cfd_tuning default_tuning(const std::vector<cfd_dims>& dims, int num_cu, const cfd_params& p) {
+  cfd_tuning t{2, 8, (p.flux_fp32 && !p.viscous) ? 16 : 32, 1, 1};
   while (t.tile_k > 4 && count_tiles(dims, t.tile_j, t.tile_k) < (int64_t)num_cu) t.tile_k /= 2;
   if (count_tiles(dims, t.tile_j, t.tile_k) < num_cu) {
     t.kernel = 0;
@@ -846,7 +848,7 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
       HIPCHK(hipMemcpyAsync(c->d_cell_start(), cs.data(), sizeof(int64_t) * cs.size(), hipMemcpyHostToDevice,
                             stream));
     }
-    c->tun = default_tuning(c->dims, c->num_cu);
+    c->tun = default_tuning(c->dims, c->num_cu, c->params);
     build_tiles(c, stream);
     *out = c;
   });
