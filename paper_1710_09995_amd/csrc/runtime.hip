@@ -338,9 +338,15 @@ struct cfd_ctx {
   Gas<double> g64{};
   Gas<float> g32{};
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;          // one time step, captured once per state pointer
-  hipGraphExec_t gexec = nullptr;
+  // Captured time steps, for the state pointer graph_q: one step, and
+  // STEPS_PER_GRAPH steps for runs without a history (one graph launch, and
+  // its start-up gap, per STEPS_PER_GRAPH steps).
+  static constexpr int STEPS_PER_GRAPH = 8;
   const void* graph_q = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph_n = nullptr;
+  hipGraphExec_t gexec_n = nullptr;
   int num_cu = 256;
   std::map<int, int> occ_cache;
   std::string last_error;
@@ -394,9 +400,13 @@ struct cfd_ctx {
   void drop_graph() {
     if (gexec) hipGraphExecDestroy(gexec);
     if (graph) hipGraphDestroy(graph);
+    if (gexec_n) hipGraphExecDestroy(gexec_n);
+    if (graph_n) hipGraphDestroy(graph_n);
     gexec = nullptr;
     graph = nullptr;
     graph_q = nullptr;
+    gexec_n = nullptr;
+    graph_n = nullptr;
   }
 };
 
@@ -969,22 +979,31 @@ cfd_status cfd_step(cfd_ctx* c, double* q, int32_t nsteps, double* hist, hipStre
     // the state may have changed since, so the first one is computed here
     if (nsteps > 0 && fused_dt(c)) time_step_pass(c, q, s);
     if (c->tun.use_graph && !c->profiling) {
-      if (!c->gexec || c->graph_q != q) {
+      if (c->graph_q != q) {
         c->drop_graph();
+        c->graph_q = q;
+      }
+      auto capture = [&](int steps, hipGraph_t& g, hipGraphExec_t& ge) {
         HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         try {
-          enqueue_step(c, q, c->cap_stream);
+          for (int n = 0; n < steps; ++n) enqueue_step(c, q, c->cap_stream);
         } catch (...) {
           hipGraph_t gg = nullptr;
           hipStreamEndCapture(c->cap_stream, &gg);
           if (gg) hipGraphDestroy(gg);
           throw;
         }
-        HIPCHK(hipStreamEndCapture(c->cap_stream, &c->graph));
-        HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
-        c->graph_q = q;
+        HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
+        HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+      };
+      int n0 = 0;
+      if (!hist && nsteps >= cfd_ctx::STEPS_PER_GRAPH) {
+        if (!c->gexec_n) capture(cfd_ctx::STEPS_PER_GRAPH, c->graph_n, c->gexec_n);
+        for (; n0 + cfd_ctx::STEPS_PER_GRAPH <= nsteps; n0 += cfd_ctx::STEPS_PER_GRAPH)
+          HIPCHK(hipGraphLaunch(c->gexec_n, s));
       }
-      for (int n = 0; n < nsteps; ++n) {
+      if (n0 < nsteps && !c->gexec) capture(1, c->graph, c->gexec);
+      for (int n = n0; n < nsteps; ++n) {
         HIPCHK(hipGraphLaunch(c->gexec, s));
         if (hist)
           HIPCHK(hipMemcpyAsync(hist + (int64_t)n * NHIST, c->d_hist(), sizeof(double) * NHIST,

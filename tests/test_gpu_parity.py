@@ -139,6 +139,29 @@ def test_graph_eager_tiles_kernels_bitwise(name, fp32):
             assert np.array_equal(a, b), t
 
 
+@pytest.mark.parametrize("name", ["bump_ns", "batched"])
+def test_multi_step_graph_bitwise(name):
+    """Runs without a history replay one graph of several steps; the states
+    after 13 steps (one multi-step graph and single-step graphs), 8 more (the
+    multi-step graph replayed) and 2 steps with a history equal eager runs."""
+    case = CASES[name]
+    say("multi-step graph", name)
+    out = []
+    for g in (1, 0):
+        s = _solver(case, use_graph=g)
+        s.step(13, hist=False)
+        a = s.state()
+        s.step(8, hist=False)
+        b = s.state()
+        h = s.step(2).cpu().numpy()
+        out.append((a, b, s.state(), h))
+        s.close()
+    for x, y in zip(out[0][:3], out[1][:3]):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v)
+    assert np.array_equal(out[0][3], out[1][3])
+
+
 @pytest.mark.parametrize("tun", [None, RING], ids=["default", "ring"])
 def test_run_to_run_bitwise(tun):
     case = CASES["batched"]
