@@ -139,6 +139,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--split", type=int, default=0, metavar="MAX_CELLS",
                     help="cut the blocks into pieces of at most MAX_CELLS cells first (Section 3.2.1)")
+    ap.add_argument("--split-align", default="64,8,1", metavar="I,J,K",
+                    help="with --split: cut positions snap to multiples of these (1,1,1 = plain bisection)")
     ap.add_argument("--groups", type=int, default=8,
                     help="with --split: groups (devices) the pieces are regrouped into for the balance report")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -175,8 +177,9 @@ def main(argv=None):
             return round(max(tot) / (sum(tot) / a.groups), 4)
 
         blocks_loads = [ni * nj * nk for ni, nj, nk in case.dims]
-        case, pieces = part.split_case(case, a.split)
-        split_info = {"max_cells": a.split, "blocks": len(blocks_loads), "pieces": len(pieces),
+        align = tuple(int(v) for v in a.split_align.split(","))
+        case, pieces = part.split_case(case, a.split, align=align)
+        split_info = {"max_cells": a.split, "align": list(align), "blocks": len(blocks_loads), "pieces": len(pieces),
                       "groups": a.groups, "max_over_mean_blocks": balance(blocks_loads),
                       "max_over_mean_pieces": balance([p.cells for p in pieces])}
         print(f"# split: {json.dumps(split_info)}", file=sys.stderr, flush=True)

@@ -217,12 +217,16 @@ typedef struct { int32_t parent; int32_t lo[3]; int32_t n[3]; } cfd_piece;   /* 
 
 /* Split plan.  A block of more than max_cells cells is cut in two across its
  * longest index direction (equal extents: the higher direction, k before j
- * before i), the lower part taking floor(n/2) cells; both parts are split
- * again by the same rule.  A part whose every extent is below 2*min_width is
- * kept whole, however large.  Pieces are listed block by block, depth first,
- * lower part first.  max_cells >= 1; min_width >= 2 (the ghost depth). */
+ * before i); both parts are split again by the same rule.  A part whose every
+ * extent is below 2*min_width is kept whole, however large.  The lower part
+ * takes the multiple of align[d] nearest n/2 (equal distance: the lower) when
+ * that lies in [n/4, 3n/4] and leaves both parts min_width cells, else
+ * floor(n/2): align = {64, 8, 1} keeps cuts on the stage kernels' tile grid.
+ * Pieces are listed block by block, depth first, lower part first.
+ * max_cells >= 1; min_width >= 2 (the ghost depth); align may be NULL (all 1),
+ * else each entry in [1, 2^20]. */
 cfd_status cfd_split_plan(int32_t nblk, const cfd_dims* dims, int64_t max_cells, int32_t min_width,
-                          cfd_piece* pieces, int32_t capacity, int32_t* npieces);
+                          const int32_t align[3], cfd_piece* pieces, int32_t capacity, int32_t* npieces);
 
 /* Connection and boundary tables of a set of pieces that tiles every block
  * (checked: every cell exactly once).  A piece face inside its parent becomes

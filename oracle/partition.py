@@ -9,10 +9,13 @@ of it; these are the readings this solver takes:
 
 * split plan: a block of more than ``max_cells`` cells is cut in two across
   its longest index direction (equal extents: the higher direction, k before
-  j before i), the lower part taking floor(n/2) cells; both parts are split
-  again by the same rule.  A part whose every extent is below
-  2 * ``min_width`` is kept whole, however large.  Pieces are listed block by
-  block, depth first, lower part first.
+  j before i); both parts are split again by the same rule.  A part whose
+  every extent is below 2 * ``min_width`` is kept whole, however large.  The
+  lower part takes the multiple of ``align[d]`` nearest n/2 (equal distance:
+  the lower one) when that lies in [n/4, 3n/4] and leaves both parts at
+  least ``min_width`` cells, else floor(n/2); with align 1 always floor(n/2).
+  Aligned cuts keep the pieces on the kernels' tile grid (64 cells in i, 8 in
+  j).  Pieces are listed block by block, depth first, lower part first.
 * split tables: a piece face inside its parent becomes a connection to every
   sibling piece across it (no shift); a piece face on its parent's face takes
   the parent's boundary patches and connections on that face, cut to the
@@ -75,7 +78,18 @@ def _transverse(d):
     return tuple(t for t in range(3) if t != d)
 
 
-def split_plan(dims: Sequence[Sequence[int]], max_cells: int, min_width: int = 2) -> List[Piece]:
+def cut_position(n: int, align: int, min_width: int) -> int:
+    """Cells of the lower part when n cells are cut in two (the reading above)."""
+    below = (n // (2 * align)) * align          # the multiple of align at or below n/2
+    above = below + align
+    c = below if n - 2 * below <= 2 * above - n else above
+    if c > 0 and n <= 4 * c <= 3 * n and min_width <= c <= n - min_width:
+        return c
+    return n // 2
+
+
+def split_plan(dims: Sequence[Sequence[int]], max_cells: int, min_width: int = 2,
+               align: Sequence[int] = (1, 1, 1)) -> List[Piece]:
     """Recursive bisection of every block (the reading above)."""
     out: List[Piece] = []
 
@@ -83,7 +97,7 @@ def split_plan(dims: Sequence[Sequence[int]], max_cells: int, min_width: int = 2
         if n[0] * n[1] * n[2] > max_cells:
             d = max(range(3), key=lambda t: (n[t], t))
             if n[d] >= 2 * min_width:
-                h = n[d] // 2
+                h = cut_position(n[d], align[d], min_width)
                 n_lo = list(n)
                 n_lo[d] = h
                 n_hi = list(n)
@@ -185,9 +199,9 @@ def split_tables(dims, conns, bcs, pieces: Sequence[Piece]):
     return out_c, out_b
 
 
-def split_case(case, max_cells: int, min_width: int = 2):
+def split_case(case, max_cells: int, min_width: int = 2, align: Sequence[int] = (1, 1, 1)):
     """The case cut into pieces: same object type, sliced nodes and states."""
-    pieces = split_plan(case.dims, max_cells, min_width)
+    pieces = split_plan(case.dims, max_cells, min_width, align)
     conns, bcs = split_tables(case.dims, case.conns, case.bcs, pieces)
     nodes, q0, dims = [], [], []
     for p in pieces:

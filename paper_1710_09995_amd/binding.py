@@ -108,7 +108,7 @@ def lib(build_if_missing: bool = True):
     L.cfd_mlp_targets.argtypes = [vp, vp, vp, vp, vp]
     L.cfd_mlp_to_state.argtypes = [vp, vp, vp, vp, vp]
     i32p = C.POINTER(C.c_int32)
-    L.cfd_split_plan.argtypes = [i32, C.POINTER(Dims), C.c_int64, i32, C.POINTER(PieceS), i32, i32p]
+    L.cfd_split_plan.argtypes = [i32, C.POINTER(Dims), C.c_int64, i32, i32p, C.POINTER(PieceS), i32, i32p]
     L.cfd_split_tables.argtypes = [i32, C.POINTER(Dims), C.POINTER(ConnS), i32, C.POINTER(BCS), i32,
                                    C.POINTER(PieceS), i32, C.POINTER(ConnS), i32, i32p, C.POINTER(BCS), i32, i32p]
     L.cfd_regroup.argtypes = [i32, i64p, i32, C.POINTER(C.c_double), i32p, i64p]

@@ -67,7 +67,19 @@ Rect moved(const Rect& r, const int32_t off[2]) {
   return Rect{{r.lo[0] + off[0], r.lo[1] + off[1]}, {r.hi[0] + off[0], r.hi[1] + off[1]}};
 }
 
-std::vector<Box> make_plan(int nblk, const cfd_dims* dims, int64_t max_cells, int min_width) {
+// Cells of the lower part when n cells are cut: the multiple of `align`
+// nearest n/2 (equal distance: the lower), if it lies in [n/4, 3n/4] and leaves
+// both parts min_width cells; else floor(n/2).
+int cut_at(int n, int align, int min_width) {
+  const int below = n / (2 * align) * align;
+  const int above = below + align;
+  const int c = (n - 2 * below <= 2 * above - n) ? below : above;
+  const int64_t c4 = 4 * (int64_t)c;
+  if (c > 0 && c4 >= n && c4 <= 3 * (int64_t)n && c >= min_width && n - c >= min_width) return c;
+  return n / 2;
+}
+
+std::vector<Box> make_plan(int nblk, const cfd_dims* dims, int64_t max_cells, int min_width, const int align[3]) {
   std::vector<Box> out, todo;
   for (int b = 0; b < nblk; ++b) {
     todo.push_back(Box{b, {0, 0, 0}, {dims[b].ni, dims[b].nj, dims[b].nk}});
@@ -77,7 +89,7 @@ std::vector<Box> make_plan(int nblk, const cfd_dims* dims, int64_t max_cells, in
       const int d = cut_direction(x);
       if (volume(x) > max_cells && x.n[d] >= 2 * min_width) {
         Box lower = x, upper = x;
-        lower.n[d] = x.n[d] / 2;
+        lower.n[d] = cut_at(x.n[d], align[d], min_width);
         upper.n[d] = x.n[d] - lower.n[d];
         upper.lo[d] = x.lo[d] + lower.n[d];
         todo.push_back(upper);
@@ -229,12 +241,17 @@ void deliver(const std::vector<T>& v, T* out, int32_t cap, int32_t* count, const
 extern "C" {
 
 cfd_status cfd_split_plan(int32_t nblk, const cfd_dims* dims, int64_t max_cells, int32_t min_width,
-                          cfd_piece* pieces, int32_t capacity, int32_t* npieces) {
+                          const int32_t align[3], cfd_piece* pieces, int32_t capacity, int32_t* npieces) {
   return cfd::host_guarded([&] {
     cfd::host_check_dims(nblk, dims);
     if (max_cells < 1) host_fail(CFD_EINVAL, "max_cells must be positive");
     if (min_width < 2) host_fail(CFD_EINVAL, "min_width must be at least the ghost depth (2)");
-    const std::vector<Box> P = make_plan(nblk, dims, max_cells, min_width);
+    int al[3] = {1, 1, 1};
+    for (int a = 0; a < 3 && align; ++a) {
+      if (align[a] < 1 || align[a] > (1 << 20)) host_fail(CFD_EINVAL, "align must be in [1, 2^20]");
+      al[a] = align[a];
+    }
+    const std::vector<Box> P = make_plan(nblk, dims, max_cells, min_width, al);
     std::vector<cfd_piece> out(P.size());
     for (size_t q = 0; q < P.size(); ++q) {
       out[q].parent = P[q].parent;

@@ -30,13 +30,20 @@ class Piece:
         return self.n[0] * self.n[1] * self.n[2]
 
 
-def split_plan(dims: Sequence[Sequence[int]], max_cells: int, min_width: int = 2) -> List[Piece]:
+# cuts on the stage kernels' tile grid: 64 cells in i (one wavefront), 8 rows in j
+TILE_ALIGN = (64, 8, 1)
+
+
+def split_plan(dims: Sequence[Sequence[int]], max_cells: int, min_width: int = 2,
+               align: Sequence[int] = TILE_ALIGN) -> List[Piece]:
     L = B.lib()
     d = B.to_dims(dims)
+    al = (C.c_int32 * 3)(*[int(v) for v in align])
     count = C.c_int32()
-    B._check(L.cfd_split_plan(len(dims), d, int(max_cells), int(min_width), None, 0, C.byref(count)))
+    B._check(L.cfd_split_plan(len(dims), d, int(max_cells), int(min_width), al, None, 0, C.byref(count)))
     arr = (B.PieceS * max(count.value, 1))()
-    B._check(L.cfd_split_plan(len(dims), d, int(max_cells), int(min_width), arr, count.value, C.byref(count)))
+    B._check(L.cfd_split_plan(len(dims), d, int(max_cells), int(min_width), al, arr, count.value,
+                              C.byref(count)))
     return [Piece(a.parent, tuple(a.lo), tuple(a.n)) for a in arr[:count.value]]
 
 
@@ -65,9 +72,9 @@ def split_tables(case: cases.Case, pieces: Sequence[Piece]):
     return conns, bcs
 
 
-def split_case(case: cases.Case, max_cells: int, min_width: int = 2):
+def split_case(case: cases.Case, max_cells: int, min_width: int = 2, align: Sequence[int] = TILE_ALIGN):
     """(the case cut into pieces, the pieces): same parameters, sliced nodes and states."""
-    pieces = split_plan(case.dims, max_cells, min_width)
+    pieces = split_plan(case.dims, max_cells, min_width, align)
     conns, bcs = split_tables(case, pieces)
     dims, nodes, q0 = [], [], []
     for p in pieces:
@@ -102,7 +109,7 @@ def assemble(case: cases.Case, pieces: Sequence[Piece], states) -> list:
 
 
 def balance_report(dims: Sequence[Sequence[int]], groups: Sequence[int] = (8, 16, 32, 64, 128),
-                   pieces_per_group: int = 4, min_width: int = 2) -> list:
+                   pieces_per_group: int = 4, min_width: int = 2, align: Sequence[int] = TILE_ALIGN) -> list:
     """For each group count G: the largest group load over the mean when the
     blocks are regrouped as they are, and when they are first split to at most
     total / (pieces_per_group * G) cells (loads in cells)."""
@@ -112,7 +119,7 @@ def balance_report(dims: Sequence[Sequence[int]], groups: Sequence[int] = (8, 16
     for G in groups:
         _, t_blocks = regroup(loads, G)
         max_cells = max(1, total // (pieces_per_group * G))
-        pieces = split_plan(dims, max_cells, min_width)
+        pieces = split_plan(dims, max_cells, min_width, align)
         _, t_pieces = regroup([p.cells for p in pieces], G)
         rows.append({"groups": G, "blocks": len(loads), "max_over_mean_blocks": max(t_blocks) * G / total,
                      "max_cells": max_cells, "pieces": len(pieces),

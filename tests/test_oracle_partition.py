@@ -38,11 +38,29 @@ def test_split_plan_thin_column():
     assert [q.lo[2] for q in p] == list(np.cumsum([0] + quarter * 4)[:-1])
 
 
+def test_split_plan_aligned_cuts():
+    """150 x 100 x 10 (150,000 cells), max_cells 75,000, align (64, 8, 1), by hand:
+    i = 150 is cut at 64 (the multiple of 64 nearest 75, inside [37.5, 112.5]):
+    64 x 100 x 10 = 64,000 stays; 86 x 100 x 10 = 86,000 is cut across j = 100
+    at 48 (48 and 56 are 2 and 6 from 50): 86 x 48 x 10 and 86 x 52 x 10."""
+    p = opart.split_plan([(150, 100, 10)], 75_000, align=(64, 8, 1))
+    assert [(q.lo, q.n) for q in p] == [((0, 0, 0), (64, 100, 10)), ((64, 0, 0), (86, 48, 10)),
+                                        ((64, 48, 0), (86, 52, 10))]
+    # no aligned cut in [n/4, 3n/4] or one leaving a part below min_width: floor(n/2)
+    assert opart.cut_position(10, 8, 2) == 5
+    assert opart.cut_position(20, 8, 2) == 8          # 8 and 16 are 2 and 6 from 10
+    assert opart.cut_position(24, 8, 2) == 8          # 8 and 16 both 4 from 12: the lower
+    assert opart.cut_position(9, 8, 4) == 4           # 8 leaves 1 < min_width
+    for n in range(4, 300):                           # align 1 is plain bisection
+        assert opart.cut_position(n, 1, 2) == n // 2
+
+
 def test_split_plan_tiles_blocks_exactly():
     rng = np.random.default_rng(11)
     dims = [tuple(int(v) for v in rng.integers(2, 41, 3)) for _ in range(12)]
-    for max_cells, wmin in ((500, 2), (64, 3), (10 ** 9, 2)):
-        pieces = opart.split_plan(dims, max_cells, wmin)
+    for max_cells, wmin, align in ((500, 2, (1, 1, 1)), (64, 3, (1, 1, 1)), (10 ** 9, 2, (1, 1, 1)),
+                                   (500, 2, (64, 8, 1)), (300, 3, (8, 4, 2))):
+        pieces = opart.split_plan(dims, max_cells, wmin, align)
         occ = [np.zeros((nk, nj, ni), np.int32) for ni, nj, nk in dims]
         for q in pieces:
             (i0, j0, k0), (ni, nj, nk) = q.lo, q.n

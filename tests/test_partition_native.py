@@ -22,8 +22,9 @@ def test_split_plan_matches_oracle(seed):
     dims = [tuple(int(v) for v in rng.integers(2, 120, 3)) for _ in range(20)]
     for max_cells in (300, 5000, 37_000, 10 ** 12):
         for wmin in (2, 3, 8):
-            assert _plan_tuple(part.split_plan(dims, max_cells, wmin)) == \
-                _plan_tuple(opart.split_plan(dims, max_cells, wmin))
+            for align in ((1, 1, 1), (64, 8, 1), (8, 4, 2), (3, 5, 7)):
+                assert _plan_tuple(part.split_plan(dims, max_cells, wmin, align)) == \
+                    _plan_tuple(opart.split_plan(dims, max_cells, wmin, align))
 
 
 def _conn_key(c):
@@ -46,7 +47,7 @@ def _table_cases():
 @pytest.mark.parametrize("k", range(5))
 def test_split_tables_match_oracle(k):
     case, max_cells = _table_cases()[k]
-    pieces = opart.split_plan(case.dims, max_cells)
+    pieces = opart.split_plan(case.dims, max_cells, align=(64, 8, 1) if k % 2 else (1, 1, 1))
     assert len(pieces) > case.nblk
     want_c, want_b = opart.split_tables(case.dims, case.conns, case.bcs, pieces)
     got_c, got_b = part.split_tables(case, [part.Piece(p.parent, p.lo, p.n) for p in pieces])
@@ -86,6 +87,9 @@ def test_error_paths():
     with pytest.raises(B.CfdError) as e:
         part.split_plan([(8, 8, 8)], 10, min_width=1)
     assert e.value.status == -1
+    with pytest.raises(B.CfdError) as e:
+        part.split_plan([(8, 8, 8)], 10, align=(0, 1, 1))
+    assert e.value.status == -1
     case = cases.vortex_case(8)
     with pytest.raises(B.CfdError) as e:      # pieces that leave a gap
         part.split_tables(case, [part.Piece(0, (0, 0, 0), (8, 8, 4))])
@@ -96,7 +100,7 @@ def test_error_paths():
     L = B.lib()
     arr = (B.PieceS * 3)()
     n = C.c_int32()
-    st = L.cfd_split_plan(1, B.to_dims([(8, 8, 8)]), 64, 2, arr, 3, C.byref(n))
+    st = L.cfd_split_plan(1, B.to_dims([(8, 8, 8)]), 64, 2, None, arr, 3, C.byref(n))
     assert st == -2 and n.value == 8            # too small: count stored, nothing written
     with pytest.raises(B.CfdError):
         part.regroup([1, -1], 2)
