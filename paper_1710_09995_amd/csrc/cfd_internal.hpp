@@ -45,8 +45,8 @@ struct PatchDesc {
 };
 
 // Threads per transverse point of a state ghost sweep (k_ghost_q): one per
-// ghost layer on i-face connections, else one.
-__host__ __device__ inline int ghost_threads_per_point(int kind, int d) { return kind == 0 && d == 0 ? NG : 1; }
+// ghost layer on i-faces, else one.
+__host__ __device__ inline int ghost_threads_per_point(int /*kind*/, int d) { return d == 0 ? NG : 1; }
 
 // One tile of the stage work list.
 struct TileDesc {

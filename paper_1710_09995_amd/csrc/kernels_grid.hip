@@ -162,10 +162,10 @@ __global__ void k_metric_ghosts(double* __restrict__ met, const BlockDesc* __res
 }
 
 // Ghost fill of the conserved state (one sweep, all patches of all blocks).
-// One thread per transverse point, except on i-face connections: there the
-// NG ghost cells of a row are adjacent in memory while neighbouring points
-// are a row apart, so a thread per (point, layer) puts a row's layers on
-// adjacent lanes and halves the memory segments each access touches.
+// One thread per transverse point, except on i-faces: there the NG ghost
+// cells of a row are adjacent in memory while neighbouring points are a row
+// apart, so a thread per (point, layer) puts a row's layers on adjacent lanes
+// and halves the memory segments each access touches.
 __global__ void k_ghost_q(double* __restrict__ q, const double* __restrict__ met,
                           const BlockDesc* __restrict__ blocks,
                           const PatchDesc* __restrict__ patches, StepParams SP) {
@@ -231,6 +231,12 @@ __global__ void k_ghost_q(double* __restrict__ q, const double* __restrict__ met
     } else {
       for (int v = 0; v < NV; ++v) qg[v] = qi[v];
     }
+    if (per != 1) {     // this thread's layer only
+      const int m = 1 + t % per;
+      const int64_t od = pos3(d, side == 0 ? -m : n - 1 + m, p1, p2, B.sj, B.sk);
+      for (int v = 0; v < NV; ++v) qb[v * B.sv + od] = qg[v];
+      return;
+    }
     for (int m = 1; m <= NG; ++m) {
       const int gm = side == 0 ? -m : n - 1 + m;
       const int64_t od = pos3(d, gm, p1, p2, B.sj, B.sk);
@@ -238,17 +244,9 @@ __global__ void k_ghost_q(double* __restrict__ q, const double* __restrict__ met
     }
     return;
   }
-  double wv[NG][NV];       // the mirrored interior cells, all loaded before any store
-  for (int m = 1; m <= NG; ++m) {
-    const int im = side == 0 ? m - 1 : n - m;
-    const int64_t oi = pos3(d, im, p1, p2, B.sj, B.sk);
-    for (int v = 0; v < NV; ++v) wv[m - 1][v] = qb[v * B.sv + oi];
-  }
-  for (int m = 1; m <= NG; ++m) {
-    const int gm = side == 0 ? -m : n - 1 + m;
-    const int64_t od = pos3(d, gm, p1, p2, B.sj, B.sk);
-    const double r = wv[m - 1][0], mx = wv[m - 1][1], my = wv[m - 1][2], mz = wv[m - 1][3],
-                 e = wv[m - 1][4];
+  // walls: ghost layer m mirrors interior cell m - 1
+  auto wall = [&](const double w[NV], int64_t od) {
+    const double mx = w[1], my = w[2], mz = w[3];
     double gx, gy, gz;
     if (P.kind == CFD_BC_KIND_SLIPWALL) {
       const double mn = mx * nx + my * ny + mz * nz;
@@ -260,12 +258,27 @@ __global__ void k_ghost_q(double* __restrict__ q, const double* __restrict__ met
       gy = -my;
       gz = -mz;
     }
-    qb[od] = r;
+    qb[od] = w[0];
     qb[B.sv + od] = gx;
     qb[2 * B.sv + od] = gy;
     qb[3 * B.sv + od] = gz;
-    qb[4 * B.sv + od] = e;
+    qb[4 * B.sv + od] = w[4];
+  };
+  if (per != 1) {       // this thread's layer only
+    const int m = 1 + t % per;
+    const int64_t oi = pos3(d, side == 0 ? m - 1 : n - m, p1, p2, B.sj, B.sk);
+    double w[NV];
+    for (int v = 0; v < NV; ++v) w[v] = qb[v * B.sv + oi];
+    wall(w, pos3(d, side == 0 ? -m : n - 1 + m, p1, p2, B.sj, B.sk));
+    return;
   }
+  double wv[NG][NV];       // the mirrored interior cells, all loaded before any store
+  for (int m = 1; m <= NG; ++m) {
+    const int im = side == 0 ? m - 1 : n - m;
+    const int64_t oi = pos3(d, im, p1, p2, B.sj, B.sk);
+    for (int v = 0; v < NV; ++v) wv[m - 1][v] = qb[v * B.sv + oi];
+  }
+  for (int m = 1; m <= NG; ++m) wall(wv[m - 1], pos3(d, side == 0 ? -m : n - 1 + m, p1, p2, B.sj, B.sk));
 }
 
 // Viscous face metrics of one block: for every cell position (i, j, k) in

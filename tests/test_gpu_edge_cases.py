@@ -7,7 +7,10 @@
   characteristic boundary state (inflow takes the freestream, outflow the
   interior);
 - a strong shock tube (pressure and density ratios 1e3) along j, which
-  drives the limiter far from smooth data.
+  drives the limiter far from smooth data;
+- a walled box: slip walls on the i-faces and no-slip walls on the j-faces of
+  a curvilinear grid, periodic in k, with a pressure pulse (wall ghosts on
+  the i-faces, where each ghost layer has its own lane).
 
 Every case runs on the default kernel, on the tiled kernel with two-row tiles
 and on the plane-ring kernel, at the FP64 parity bar of the other step tests.
@@ -48,11 +51,25 @@ def shock_tube():
     return cases.Case("shock_tube", par, [dims], [X], conns, bcs, [q])
 
 
-CASES = {"thin_blocks": thin_blocks, "supersonic": supersonic, "shock_tube": shock_tube}
+def walled_box():
+    dims = (20, 14, 6)
+    X = cases.cartesian_nodes(dims, h=(1.0 / 20, 1.0 / 14, 1.0 / 6))
+    X[0] = X[0] + 0.01 * np.sin(2 * np.pi * X[1]) * np.sin(2 * np.pi * X[2])
+    X[1] = X[1] + 0.01 * np.sin(2 * np.pi * X[0]) * np.sin(2 * np.pi * X[2])
+    par = cases.Params(cfl=0.5, mach=0.3, viscous=1, reynolds=2e3, alpha=0.3)
+    q = cases.pressure_pulses(cases.centroids(X), [(0.4, 0.5, 0.5)], 0.05, 0.12, par)
+    conns = cases.periodic_pair(0, dims, 2, 1.0)
+    bcs = [cases.full_bc(0, dims, 0, cases.SLIPWALL), cases.full_bc(0, dims, 1, cases.SLIPWALL),
+           cases.full_bc(0, dims, 2, cases.NOSLIP_ADIABATIC), cases.full_bc(0, dims, 3, cases.NOSLIP_ADIABATIC)]
+    return cases.Case("walled_box", par, [dims], [X], conns, bcs, [q])
+
+
+CASES = {"thin_blocks": thin_blocks, "supersonic": supersonic, "shock_tube": shock_tube, "walled_box": walled_box}
 
 
 @pytest.mark.parametrize("tun", list(TUNINGS))
-@pytest.mark.parametrize("name,nsteps", [("thin_blocks", 6), ("supersonic", 5), ("shock_tube", 12)])
+@pytest.mark.parametrize("name,nsteps", [("thin_blocks", 6), ("supersonic", 5), ("shock_tube", 12),
+                                         ("walled_box", 8)])
 def test_edge_case_step_parity(name, nsteps, tun):
     from paper_1710_09995_amd.binding import Solver
     case = CASES[name]()
