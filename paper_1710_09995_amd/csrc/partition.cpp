@@ -70,13 +70,13 @@ Rect moved(const Rect& r, const int32_t off[2]) {
 // Cells of the lower part when n cells are cut: the multiple of `align`
 // nearest n/2 (equal distance: the lower), if it lies in [n/4, 3n/4] and leaves
 // both parts min_width cells; else floor(n/2).
-int cut_at(int n, int align, int min_width) {
-  const int below = n / (2 * align) * align;
-  const int above = below + align;
-  const int c = (n - 2 * below <= 2 * above - n) ? below : above;
-  const int64_t c4 = 4 * (int64_t)c;
-  if (c > 0 && c4 >= n && c4 <= 3 * (int64_t)n && c >= min_width && n - c >= min_width) return c;
-  return n / 2;
+int cut_at(int n32, int align32, int min_width32) {
+  const int64_t n = n32, align = align32, min_width = min_width32;   // 64-bit: no overflow near 2^31
+  const int64_t below = n / (2 * align) * align;
+  const int64_t above = below + align;
+  const int64_t c = (n - 2 * below <= 2 * above - n) ? below : above;
+  if (c > 0 && 4 * c >= n && 4 * c <= 3 * n && c >= min_width && n - c >= min_width) return (int)c;
+  return n32 / 2;
 }
 
 std::vector<Box> make_plan(int nblk, const cfd_dims* dims, int64_t max_cells, int min_width, const int align[3]) {
@@ -87,7 +87,7 @@ std::vector<Box> make_plan(int nblk, const cfd_dims* dims, int64_t max_cells, in
       const Box x = todo.back();
       todo.pop_back();
       const int d = cut_direction(x);
-      if (volume(x) > max_cells && x.n[d] >= 2 * min_width) {
+      if (volume(x) > max_cells && x.n[d] >= 2 * (int64_t)min_width) {
         Box lower = x, upper = x;
         lower.n[d] = cut_at(x.n[d], align[d], min_width);
         upper.n[d] = x.n[d] - lower.n[d];
@@ -113,7 +113,8 @@ void check_pieces(int nblk, const cfd_dims* dims, const cfd_piece* pieces, int n
         host_fail(CFD_EINVAL, "piece " + std::to_string(p) + " lies outside its parent");
     covered[q.parent] += (int64_t)q.n[0] * q.n[1] * q.n[2];
   }
-  // Every cell once: the volumes add up and no two pieces of a parent overlap.
+  // Every cell once: the volumes add up and no two pieces of a parent overlap
+  // (pairwise, so O(pieces^2) per block: meant for up to some thousands).
   for (int b = 0; b < nblk; ++b)
     if (covered[b] != (int64_t)dims[b].ni * dims[b].nj * dims[b].nk)
       host_fail(CFD_EINVAL, "the pieces of block " + std::to_string(b) + " do not tile it");

@@ -27,6 +27,15 @@ def test_split_plan_matches_oracle(seed):
                     _plan_tuple(opart.split_plan(dims, max_cells, wmin, align))
 
 
+def test_split_plan_large_extents_match_oracle():
+    """Extents near 2^30 (blocks up to 2^34 cells are accepted): the cut rule's
+    arithmetic must not overflow."""
+    for dims in ([(1 << 30, 4, 4)], [(3, (1 << 30) + 7, 2)], [(2, 3, (1 << 31) - 1)]):
+        for align in ((1, 1, 1), (64, 8, 1)):
+            assert _plan_tuple(part.split_plan(dims, 1 << 31, 2, align)) == \
+                _plan_tuple(opart.split_plan(dims, 1 << 31, 2, align))
+
+
 def _conn_key(c):
     return (c.blk, c.face, c.nbr, c.nbr_face, tuple(c.lo), tuple(c.hi), tuple(c.nbr_lo),
             tuple(float(v) for v in c.shift))
