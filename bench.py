@@ -90,10 +90,11 @@ def cpu_baseline(name: str, flux: str, budget_s: float = 12.0):
             "sample": f"{sample}; {n} steps of {c.ncells} cells in {dt:.1f} s, single-threaded NumPy"}
 
 
-def read_traffic(kernel_label: str):
-    """HBM bytes per stage launch from a committed rocprofv3 --pmc summary,
-    valid only while the stage-kernel sources are unchanged."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_label}_pmc.txt")
+def read_profile_value(kernel_label: str, kind: str, key: str):
+    """A per-launch figure from a committed rocprofv3 --pmc summary
+    (profiles/<label>_<kind>.txt), valid only while the stage-kernel sources
+    are unchanged."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_label}_{kind}.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -104,9 +105,14 @@ def read_traffic(kernel_label: str):
     if vals.get("source_sha") != source_sha():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def read_traffic(kernel_label: str):
+    """HBM bytes per stage launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    return read_profile_value(kernel_label, "pmc", "hbm_bytes_per_launch")
 
 
 def source_sha() -> str:
@@ -221,6 +227,7 @@ def main(argv=None):
     finite = bool(all(math.isfinite(x) for x in h))
 
     roofline = None
+    fp64 = None
     prof = None
     if not a.no_profile_pass:
         s.set_profiling(True)
@@ -240,6 +247,14 @@ def main(argv=None):
                         s.get_tuning()["kernel"], "k_stage") + " (residual + RK stage update)",
                     "mean_launch_ms": round(st["mean_ms"], 4), "launches": st["launches"],
                     "algorithmic_bytes_per_cell": round(bpc, 2), "cells_per_launch": case.ncells}
+        flops = read_profile_value(kernel_label, "valu", "fp64_flops_per_launch")
+        if flops is not None:
+            tf = flops / (st["mean_ms"] / 1e3) / 1e12
+            fp64 = {"achieved": round(tf, 2), "peak": FP64_VECTOR_PEAK, "unit": "TFLOP/s",
+                    "frac": round(tf / FP64_VECTOR_PEAK, 4), "flops_per_launch": flops,
+                    "flops_per_cell": round(flops / case.ncells, 1),
+                    "note": "executed FP64 flops from SQ_INSTS_VALU_*_F64 counters (profiles/*_valu.txt), "
+                            "incl. reciprocal/sqrt refinement"}
         print(f"# profile: {json.dumps(prof)}", file=sys.stderr, flush=True)
     tune = s.get_tuning()
     s.close()
@@ -266,6 +281,7 @@ def main(argv=None):
                    "viscous": bool(case.params.viscous), "flux": a.flux, "stages_per_step": 3,
                    "tuning": tune, "autotune": tune_info, "finite": finite, "split": split_info},
         "roofline": roofline,
+        "fp64_valu": fp64,
         "cpu_baseline": cpu,
     }
     if prof is not None:
