@@ -13,6 +13,8 @@ ghosts     ghost-cell fill of the conserved state (connections and BCs)
 flux       primitives, MUSCL reconstruction, Roe flux, viscous flux
 solver     residual, time step, third-order Runge-Kutta, norms
 mlp        FP64 multilayer perceptron forward/backward (warm start)
+partition  block split plan, split tables, LPT regroup (Section 3.2.1)
+highorder  sixth-order staggered flux difference (Section 2.2, Eq. 2)
 
 Parity status: every function is pinned by the CPU tests (closed forms,
 invariants, textbook special cases, brute force) except the trained
