@@ -252,6 +252,24 @@ cfd_status cfd_split_tables(int32_t nblk, const cfd_dims* dims, const cfd_conn* 
 cfd_status cfd_regroup(int32_t n, const int64_t* load, int32_t ngroups, const double* capacity,
                        int32_t* group, int64_t* group_load);
 
+/* ---------------------------------------------------------- high order
+ * Sixth-order staggered flux difference, Section 2.2, Eq. (2): the
+ * cell-centred derivative along index direction d (0, 1, 2 = i, j, k) of a
+ * face-centred field, for the n[0] x n[1] x n[2] cells of one block,
+ *   out_i = [75/64 (F_{i+1/2} - F_{i-1/2}) - 25/384 (F_{i+3/2} - F_{i-3/2})
+ *            + 3/640 (F_{i+5/2} - F_{i-5/2})] / h.
+ * f_dev: nvar dense arrays [k][j][i] (i fastest) with n[d] + 5 entries along
+ *   d (the faces i - 1/2 for i = -2 .. n[d] + 2) and n[t] along the other
+ *   directions t.  The two faces beyond the block on each side are the
+ *   caller's to supply: the paper's block closures are in references it does
+ *   not reproduce, so the residual kernels above do not use this operator.
+ * out_dev: nvar dense arrays [k][j][i] of n[0] x n[1] x n[2] cells.
+ * Both are the caller's device memory and must not overlap.  n[t] >= 1,
+ * 1 <= nvar <= 64, h > 0 and finite, else CFD_EINVAL.  Asynchronous on
+ * stream. */
+cfd_status cfd_staggered_diff6(const double* f_dev, double* out_dev, const int32_t n[3], int32_t d, int32_t nvar,
+                               double h, hipStream_t stream);
+
 /* ---------------------------------------------------------------- warm start
  * A multilayer perceptron predicts the steady flow of a channel-bump case
  * from its condition and a cell position, giving the time march a warm start

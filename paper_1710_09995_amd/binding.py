@@ -63,7 +63,7 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_time_step", "cfd_copy_metrics", "cfd_set_profiling", "cfd_profile_read",
            "cfd_mlp_sizes", "cfd_mlp_forward", "cfd_mlp_mse", "cfd_mlp_backward", "cfd_mlp_adam",
            "cfd_mlp_to_bf16", "cfd_mlp_features", "cfd_mlp_targets", "cfd_mlp_to_state",
-           "cfd_split_plan", "cfd_split_tables", "cfd_regroup",
+           "cfd_split_plan", "cfd_split_tables", "cfd_regroup", "cfd_staggered_diff6",
            "cfd_status_string", "cfd_last_error"]
 
 _lib = None
@@ -112,6 +112,7 @@ def lib(build_if_missing: bool = True):
     L.cfd_split_tables.argtypes = [i32, C.POINTER(Dims), C.POINTER(ConnS), i32, C.POINTER(BCS), i32,
                                    C.POINTER(PieceS), i32, C.POINTER(ConnS), i32, i32p, C.POINTER(BCS), i32, i32p]
     L.cfd_regroup.argtypes = [i32, i64p, i32, C.POINTER(C.c_double), i32p, i64p]
+    L.cfd_staggered_diff6.argtypes = [vp, vp, i32p, i32, i32, C.c_double, vp]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]
@@ -189,6 +190,27 @@ def _stream_handle(torch, stream):
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr())
+
+
+def staggered_diff6(f, n, d: int, h: float, out=None, stream=None):
+    """Eq. (2) of Section 2.2 on the device (cfd_staggered_diff6): f is a
+    contiguous FP64 CUDA tensor [nvar, Nk, Nj, Ni] of face values with
+    n[d] + 5 entries along direction d; returns [nvar, nk, nj, ni]."""
+    import torch
+    ni, nj, nk = (int(v) for v in n)
+    if f.dtype != torch.float64 or not f.is_cuda or not f.is_contiguous():
+        raise ValueError("f must be a contiguous float64 CUDA tensor")
+    want = [f.shape[0], nk + 5 * (d == 2), nj + 5 * (d == 1), ni + 5 * (d == 0)]
+    if list(f.shape) != want:
+        raise ValueError(f"f has shape {tuple(f.shape)}, expected {tuple(want)}")
+    if out is None:
+        out = torch.empty((f.shape[0], nk, nj, ni), dtype=torch.float64, device=f.device)
+    elif list(out.shape) != [f.shape[0], nk, nj, ni] or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor [nvar, nk, nj, ni]")
+    nn = (C.c_int32 * 3)(ni, nj, nk)
+    _check(lib().cfd_staggered_diff6(_ptr(f), _ptr(out), nn, int(d), int(f.shape[0]), float(h),
+                                     _stream_handle(torch, stream)))
+    return out
 
 
 class Solver:

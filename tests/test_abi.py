@@ -106,3 +106,18 @@ def test_status_strings():
     L = B.lib()
     for s in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.cfd_status_string(s)
+
+
+def test_staggered_diff6_rejects_bad_arguments():
+    """Argument checks of cfd_staggered_diff6 (each fails before any device
+    access; the pointers are placeholders)."""
+    L = B.lib()
+    f, o = C.c_void_p(0x100000), C.c_void_p(0x900000)
+    n = (C.c_int32 * 3)(8, 4, 2)
+    ok = dict(f=f, o=o, n=n, d=0, nvar=5, h=0.1)
+    bad = [dict(d=3), dict(d=-1), dict(nvar=0), dict(nvar=65), dict(h=0.0), dict(h=float("nan")),
+           dict(n=(C.c_int32 * 3)(8, 0, 2)), dict(f=None), dict(o=C.c_void_p(0x100000 + 8 * 100))]
+    for b in bad:
+        a = dict(ok, **b)
+        st = L.cfd_staggered_diff6(a["f"], a["o"], a["n"], a["d"], a["nvar"], a["h"], None)
+        assert st == -1, b
