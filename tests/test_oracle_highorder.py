@@ -84,3 +84,91 @@ def test_sixth_order_convergence():
         errs.append(np.max(np.abs(got - np.cos(0.3 + np.arange(n) * h))))
     orders = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(orders) > 5.8
+
+
+# ------------------------------------------------------------- WCNS-E-5 edges
+
+def _cells_along(d, m, other, x0, h, fn, nvar=2):
+    """Cell values fn(x) at x0 + q h, q = 0 .. m + 4, along axis d."""
+    xc = x0 + np.arange(m + 5) * h
+    shape = [nvar, other[2], other[1], other[0]]
+    shape[3 - d] = m + 5
+    sh = [1, 1, 1, 1]
+    sh[3 - d] = m + 5
+    scale = np.arange(1, nvar + 1, dtype=float).reshape(nvar, 1, 1, 1)
+    return np.ascontiguousarray(np.broadcast_to(fn(xc).reshape(sh), shape) * scale), scale
+
+
+def test_linear_weights_are_the_five_cell_interpolation():
+    """With the linear weights the left state is (3, -20, 90, 60, -5) / 128 of
+    cells i-2 .. i+2 (the interpolating quartic at the face), by hand."""
+    rng = np.random.default_rng(3)
+    u = rng.uniform(-1, 1, (1, 1, 1, 11))
+    uL, uR = ho.wcns5_edge(u, 0, linear=True)
+    c = u[0, 0, 0]
+    want_l = (3 * c[0:6] - 20 * c[1:7] + 90 * c[2:8] + 60 * c[3:9] - 5 * c[4:10]) / 128
+    want_r = (3 * c[5:11] - 20 * c[4:10] + 90 * c[3:9] + 60 * c[2:8] - 5 * c[1:7]) / 128
+    assert np.allclose(uL[0, 0, 0], want_l, rtol=0, atol=1e-15)
+    assert np.allclose(uR[0, 0, 0], want_r, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4])
+def test_linear_edges_exact_on_quartics(d, p):
+    h, x0, m = 0.13, -0.4, 9
+    u, scale = _cells_along(d, m, (3, 2, 2), x0, h, lambda x: x ** p)
+    uL, uR = ho.wcns5_edge(u, d, linear=True)
+    xf = x0 + (np.arange(m) + 2.5) * h          # face p lies between cells p+2 and p+3
+    sh = [1, 1, 1, 1]
+    sh[3 - d] = m
+    want = (xf ** p).reshape(sh) * scale
+    assert np.max(np.abs(uL - want)) <= 1e-13
+    assert np.max(np.abs(uR - want)) <= 1e-13
+
+
+def test_nonlinear_edges_smooth_data_and_mirror():
+    """Smooth, monotone data: the nonlinear edges converge at fifth order; and
+    the right state of reflected data is the reflected left state."""
+    errs = []
+    for m in (20, 40, 80):
+        h = 1.0 / m
+        u, _ = _cells_along(0, m, (1, 1, 1), 0.1, h, lambda x: np.exp(x), nvar=1)
+        uL, uR = ho.wcns5_edge(u, 0)
+        xf = 0.1 + (np.arange(m) + 2.5) * h
+        errs.append(max(np.max(np.abs(uL[0, 0, 0] - np.exp(xf))), np.max(np.abs(uR[0, 0, 0] - np.exp(xf)))))
+    orders = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) > 4.5
+    rng = np.random.default_rng(4)
+    u = rng.uniform(0, 1, (1, 1, 1, 30))
+    uL, uR = ho.wcns5_edge(u, 0)
+    uL2, uR2 = ho.wcns5_edge(u[..., ::-1].copy(), 0)
+    assert np.allclose(uR[..., ::-1], uL2, rtol=0, atol=1e-14)
+
+
+def test_nonlinear_edges_do_not_overshoot_a_jump():
+    """A unit step: the weights move to the smooth side, so every edge value
+    stays within the data range up to a small fraction of the jump, while the
+    linear interpolation overshoots by several per cent."""
+    u = np.where(np.arange(40) < 20, 0.0, 1.0).reshape(1, 1, 1, 40)
+    uL, uR = ho.wcns5_edge(u, 0)
+    for v in (uL, uR):
+        assert v.min() >= -2e-3 and v.max() <= 1 + 2e-3
+    lL, _ = ho.wcns5_edge(u, 0, linear=True)
+    assert lL.max() > 1.02 or lL.min() < -0.02
+
+
+def test_wcns5_with_eq2_is_fifth_order_for_advection():
+    """The scheme's two pieces together: upwind flux F = u_L of the WCNS-E-5
+    edges, then Eq. (2), for u_t + u_x = 0 on exp(sin x): the derivative error
+    falls at fifth order or better."""
+    errs = []
+    for m in (32, 64, 128):                       # past the coarse-grid regime (16 -> 32 gives 3.4)
+        h = 2 * np.pi / m
+        q = np.arange(-5, m + 5)                  # cells -5 .. m+4 (periodic data)
+        u = np.exp(np.sin(q * h)).reshape(1, 1, 1, -1)
+        uL, _ = ho.wcns5_edge(u, 0)               # m + 5 faces: i - 1/2 for i = -2 .. m + 2
+        dudx = ho.staggered_diff6(uL, 0, h)[0, 0, 0]
+        x = np.arange(m) * h
+        errs.append(np.max(np.abs(dudx - np.cos(x) * np.exp(np.sin(x)))))
+    orders = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) > 4.5
