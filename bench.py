@@ -125,33 +125,40 @@ def source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def bench_diff6(a) -> int:
-    """Eq. (2) operator alone: K launches per direction after W warm-up
-    launches, hipEvents on the launch stream; algorithmic bytes = the face
-    field read once + the derivative written once."""
+def bench_op(a) -> int:
+    """One high-order operator alone: K launches per direction after W
+    warm-up launches, hipEvents on the launch stream; algorithmic bytes = the
+    input field read once + the outputs written once."""
     import torch
-    from paper_1710_09995_amd.binding import staggered_diff6
+    from paper_1710_09995_amd.binding import staggered_diff6, wcns5_edges
     n, nvar, h = (256, 128, 128), 5, 1.0 / 256
     cells = n[0] * n[1] * n[2]
+    pad = 5 if a.op == "diff6" else 10
     stream = torch.cuda.current_stream()
     per_dir = {}
     for d in range(3):
         shape = [nvar, n[2], n[1], n[0]]
-        shape[3 - d] += 5
+        shape[3 - d] += pad
         g = torch.Generator(device="cuda").manual_seed(d)
         f = torch.rand(shape, dtype=torch.float64, device="cuda", generator=g)
-        out = torch.empty((nvar, n[2], n[1], n[0]), dtype=torch.float64, device="cuda")
+        if a.op == "diff6":
+            out = torch.empty((nvar, n[2], n[1], n[0]), dtype=torch.float64, device="cuda")
+            run = lambda: staggered_diff6(f, n, d, h, out=out)   # noqa: E731
+            out_elems = out.numel()
+        else:
+            run = lambda: wcns5_edges(f, n, d)                   # noqa: E731
+            out_elems = 2 * run()[0].numel()
         for _ in range(a.warmup):
-            staggered_diff6(f, n, d, h, out=out)
+            run()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(a.steps):
-            staggered_diff6(f, n, d, h, out=out)
+            run()
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / a.steps
-        nbytes = 8 * (f.numel() + out.numel())
+        nbytes = 8 * (f.numel() + out_elems)
         per_dir["ijk"[d]] = {"ms": round(ms, 5), "bytes": nbytes, "GB_s": round(nbytes / (ms / 1e3) / 1e9, 1)}
     # a plain device copy of the same bytes, for the achievable-bandwidth context
     src = torch.rand(int(per_dir["k"]["bytes"] // 16), dtype=torch.float64, device="cuda")
@@ -170,15 +177,19 @@ def bench_diff6(a) -> int:
     nbytes = sum(v["bytes"] for v in per_dir.values()) / 3
     achieved = nbytes / (ms / 1e3) / 1e9
     print(json.dumps({
-        "metric": "Mcell/s of the Eq. (2) sixth-order staggered difference (5 variables, mean over i, j, k)",
+        "metric": ("Mcell/s of the Eq. (2) sixth-order staggered difference" if a.op == "diff6" else
+                   "Mcell/s of the WCNS-E-5 cell-edge interpolation (left and right states)") +
+                  " (5 variables, mean over i, j, k)",
         "value": round(cells / (ms / 1e3) / 1e6, 1), "unit": "Mcell/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded uniform face fields)",
-        "config": {"workload": "staggered_diff6_256x128x128x5", "per_direction": per_dir,
+        "config": {"workload": ("staggered_diff6" if a.op == "diff6" else "wcns5_edges") + "_256x128x128x5",
+                   "per_direction": per_dir,
                    "plain_copy_GB_s": round(copy_gbs, 1), "frac_of_plain_copy": round(achieved / copy_gbs, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_staggered_diff6", "mean_launch_ms": round(ms, 5),
+                     "kernel": "k_window6_i / k_window6_march<" + ("Eq2Op" if a.op == "diff6" else "Wcns5Op") + ">",
+                     "mean_launch_ms": round(ms, 5),
                      "algorithmic_bytes_per_launch": nbytes},
         "cpu_baseline": None}), flush=True)
     return 0
@@ -208,9 +219,10 @@ def main(argv=None):
                     help="with --split: cut positions snap to multiples of these (1,1,1 = plain bisection)")
     ap.add_argument("--groups", type=int, default=8,
                     help="with --split: groups (devices) the pieces are regrouped into for the balance report")
-    ap.add_argument("--op", default=None, choices=["diff6"],
-                    help="time one operator instead of the solver: diff6 = the sixth-order staggered flux "
-                         "difference (Section 2.2, Eq. 2) on a 256x128x128 block, 5 variables, each direction")
+    ap.add_argument("--op", default=None, choices=["diff6", "wcns5"],
+                    help="time one operator instead of the solver, on a 256x128x128 block, 5 variables, each "
+                         "direction: diff6 = the sixth-order staggered flux difference (Section 2.2, Eq. 2); "
+                         "wcns5 = the WCNS-E-5 weighted cell-edge interpolation")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (HBM counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -224,8 +236,8 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n * 8, "copies": 5}), flush=True)
         return 0
-    if a.op == "diff6" and a.gpus == 1:
-        return bench_diff6(a)
+    if a.op is not None and a.gpus == 1:
+        return bench_op(a)
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path "
               "(sharding across GPUs is a design note, not code); use --gpus 1.", file=sys.stderr)

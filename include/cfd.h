@@ -270,6 +270,28 @@ cfd_status cfd_regroup(int32_t n, const int64_t* load, int32_t ngroups, const do
 cfd_status cfd_staggered_diff6(const double* f_dev, double* out_dev, const int32_t n[3], int32_t d, int32_t nvar,
                                double h, hipStream_t stream);
 
+/* Fifth-order weighted cell-edge interpolation of WCNS-E-5, the scheme
+ * Section 2.2 names for the face states (its reference gives the
+ * construction; this is that published construction, not a formula the paper
+ * prints): left and right states at the n[d] + 5 faces i - 1/2,
+ * i = -2 .. n[d] + 2, of the n[0] x n[1] x n[2] cells of one block, the input
+ * of cfd_staggered_diff6 after a flux function.  The left state at the face
+ * between cells c and c + 1 combines three 3-cell candidates
+ * u_c + g/2 + s/8 (one-sided and central first and second differences g, s of
+ * the stencils ending, centred and starting at c) with weights
+ * d_k / (eps + g_k^2 + s_k^2)^2, d = (1/16, 10/16, 5/16), normalised; the
+ * right state is the mirror image about the face.  With smooth data the
+ * weights tend to d: the 5-cell interpolation, fifth order.
+ * u_dev: nvar dense arrays [k][j][i] with n[d] + 10 cells along d (cells
+ *   -5 .. n[d] + 4: five beyond the block on each side, the caller's) and
+ *   n[t] along the other directions.
+ * left_dev, right_dev: nvar dense arrays with n[d] + 5 faces along d.
+ * All the caller's device memory, pairwise disjoint.  n[t] >= 1,
+ * 1 <= nvar <= 64, eps > 0 and finite (1e-6 is usual), else CFD_EINVAL.
+ * Asynchronous on stream. */
+cfd_status cfd_wcns5_edges(const double* u_dev, double* left_dev, double* right_dev, const int32_t n[3], int32_t d,
+                           int32_t nvar, double eps, hipStream_t stream);
+
 /* ---------------------------------------------------------------- warm start
  * A multilayer perceptron predicts the steady flow of a channel-bump case
  * from its condition and a cell position, giving the time march a warm start

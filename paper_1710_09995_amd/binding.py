@@ -63,7 +63,7 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_time_step", "cfd_copy_metrics", "cfd_set_profiling", "cfd_profile_read",
            "cfd_mlp_sizes", "cfd_mlp_forward", "cfd_mlp_mse", "cfd_mlp_backward", "cfd_mlp_adam",
            "cfd_mlp_to_bf16", "cfd_mlp_features", "cfd_mlp_targets", "cfd_mlp_to_state",
-           "cfd_split_plan", "cfd_split_tables", "cfd_regroup", "cfd_staggered_diff6",
+           "cfd_split_plan", "cfd_split_tables", "cfd_regroup", "cfd_staggered_diff6", "cfd_wcns5_edges",
            "cfd_status_string", "cfd_last_error"]
 
 _lib = None
@@ -113,6 +113,7 @@ def lib(build_if_missing: bool = True):
                                    C.POINTER(PieceS), i32, C.POINTER(ConnS), i32, i32p, C.POINTER(BCS), i32, i32p]
     L.cfd_regroup.argtypes = [i32, i64p, i32, C.POINTER(C.c_double), i32p, i64p]
     L.cfd_staggered_diff6.argtypes = [vp, vp, i32p, i32, i32, C.c_double, vp]
+    L.cfd_wcns5_edges.argtypes = [vp, vp, vp, i32p, i32, i32, C.c_double, vp]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]
@@ -211,6 +212,26 @@ def staggered_diff6(f, n, d: int, h: float, out=None, stream=None):
     _check(lib().cfd_staggered_diff6(_ptr(f), _ptr(out), nn, int(d), int(f.shape[0]), float(h),
                                      _stream_handle(torch, stream)))
     return out
+
+
+def wcns5_edges(u, n, d: int, eps: float = 1e-6, stream=None):
+    """WCNS-E-5 face states on the device (cfd_wcns5_edges): u is a contiguous
+    FP64 CUDA tensor [nvar, Nk, Nj, Ni] of cell values with n[d] + 10 entries
+    along direction d; returns (left, right), each with n[d] + 5 faces along d."""
+    import torch
+    ni, nj, nk = (int(v) for v in n)
+    if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous():
+        raise ValueError("u must be a contiguous float64 CUDA tensor")
+    want = [u.shape[0], nk + 10 * (d == 2), nj + 10 * (d == 1), ni + 10 * (d == 0)]
+    if list(u.shape) != want:
+        raise ValueError(f"u has shape {tuple(u.shape)}, expected {tuple(want)}")
+    fshape = [u.shape[0], nk + 5 * (d == 2), nj + 5 * (d == 1), ni + 5 * (d == 0)]
+    left = torch.empty(fshape, dtype=torch.float64, device=u.device)
+    right = torch.empty(fshape, dtype=torch.float64, device=u.device)
+    nn = (C.c_int32 * 3)(ni, nj, nk)
+    _check(lib().cfd_wcns5_edges(_ptr(u), _ptr(left), _ptr(right), nn, int(d), int(u.shape[0]), float(eps),
+                                 _stream_handle(torch, stream)))
+    return left, right
 
 
 class Solver:

@@ -1,94 +1,198 @@
-// Sixth-order staggered flux difference of Section 2.2, Eq. (2): the
-// cell-centred derivative of a face-centred field along one index direction,
-//   out_i = [75/64 (F_{i+1/2} - F_{i-1/2}) - 25/384 (F_{i+3/2} - F_{i-3/2})
-//            + 3/640 (F_{i+5/2} - F_{i-5/2})] / h.
-// One thread per (variable, cell); the six faces of a cell are adjacent along
-// the direction, so neighbouring cells share them through L1/L2.  Each XCD
-// (workgroup id mod 8, the grid being a multiple of 8) streams one contiguous
-// eighth of the rows: the faces a stencil re-reads stay in that XCD's L2.
+// High-order pieces of the paper's WCNS-E-5 scheme (Section 2.2), as operators
+// on one block's fields along one index direction d:
+//   - Eq. (2), the sixth-order staggered flux difference: the derivative at
+//     the n cells from n + 5 face values,
+//       out_i = [75/64 (F_{i+1/2} - F_{i-1/2}) - 25/384 (F_{i+3/2} - F_{i-3/2})
+//                + 3/640 (F_{i+5/2} - F_{i-5/2})] / h;
+//   - the fifth-order weighted cell-edge interpolation of WCNS-E-5: left and
+//     right states at m faces from m + 5 cell values (the published
+//     construction of the scheme; the paper names it without printing it).
+// Both read a window of six consecutive entries along d per output entry p
+// (entries p .. p + 5), so they share two kernel skeletons: along i a
+// workgroup stages 4 rows of 261 entries in LDS (coalesced, all loads in
+// flight before one barrier); along j and k each lane marches 16 outputs of
+// its i-column with a register window of 21 entries.  Each input entry is thus
+// loaded about once instead of six times.  With a grid that is a multiple of
+// 8, each XCD (workgroup id mod 8) streams one contiguous eighth of the work.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <string>
 
 #include "../../include/cfd.h"
 #include "host_services.hpp"
+#include "physics.hpp"
 
 namespace cfd {
 
-__device__ __forceinline__ int xcd_slot(int nb, int b) {   // XCD-contiguous order for grids that are multiples of 8
+__device__ __forceinline__ int xcd_slot(int nb, int b) {
   return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
 }
 
-__device__ __forceinline__ double eq2(double c1, double c2, double c3, double f0, double f1, double f2, double f3,
-                                      double f4, double f5) {
-  return c1 * (f3 - f2) + c2 * (f4 - f1) + c3 * (f5 - f0);
+// Eq. (2): one output per window.
+struct Eq2Op {
+  static constexpr int NOUT = 1;
+  double c1, c2, c3;
+  __device__ __forceinline__ void operator()(const double* w, double* o) const {
+    o[0] = c1 * (w[3] - w[2]) + c2 * (w[4] - w[1]) + c3 * (w[5] - w[0]);
+  }
+};
+
+// WCNS-E-5 left state at the face between u0 and up1: three 3-cell Taylor
+// candidates u0 + (h/2) g + (h^2/8) s, smoothness (h g)^2 + (h^2 s)^2, linear
+// weights 1/16, 10/16, 5/16 made nonlinear by d_k / (eps + beta_k)^2.  Four
+// refined hardware reciprocals (frcp, within 1 ulp) instead of six divisions.
+__device__ __forceinline__ double wcns5_left(double um2, double um1, double u0, double up1, double up2, double eps) {
+  const double g0 = (um2 - 4.0 * um1 + 3.0 * u0) / 2.0, g1 = (up1 - um1) / 2.0,
+               g2 = (-3.0 * u0 + 4.0 * up1 - up2) / 2.0;
+  const double s0 = um2 - 2.0 * um1 + u0, s1 = um1 - 2.0 * u0 + up1, s2 = u0 - 2.0 * up1 + up2;
+  const double c0 = u0 + 0.5 * g0 + 0.125 * s0, c1 = u0 + 0.5 * g1 + 0.125 * s1, c2 = u0 + 0.5 * g2 + 0.125 * s2;
+  const double b0 = eps + g0 * g0 + s0 * s0, b1 = eps + g1 * g1 + s1 * s1, b2 = eps + g2 * g2 + s2 * s2;
+  const double a0 = (1.0 / 16.0) * frcp(b0 * b0), a1 = (10.0 / 16.0) * frcp(b1 * b1),
+               a2 = (5.0 / 16.0) * frcp(b2 * b2);
+  const double it = frcp(a0 + a1 + a2);
+  return (a0 * it) * c0 + (a1 * it) * c1 + (a2 * it) * c2;
 }
 
-// Along i: workgroup w takes a 256-cell segment of RI consecutive i-rows
-// (row = (v, k, j)) and stages the rows' 261 faces each in LDS (coalesced,
-// all rows' loads in flight before the one barrier); each lane then reads its
-// six faces per row from LDS.
+// The window of face p spans cells p .. p + 5; the face lies between the
+// third and fourth.  Left state from cells p .. p + 4, right from p + 5 .. p + 1.
+struct Wcns5Op {
+  static constexpr int NOUT = 2;
+  double eps;
+  __device__ __forceinline__ void operator()(const double* w, double* o) const {
+    o[0] = wcns5_left(w[0], w[1], w[2], w[3], w[4], eps);
+    o[1] = wcns5_left(w[5], w[4], w[3], w[2], w[1], eps);
+  }
+};
+
+// Along i.  Output extents mi x mj x mk per variable (row = (v, k, j)); the
+// input has mi + 5 entries along i.  Workgroup w takes a SEG-entry segment of
+// RI consecutive rows; SEG = 264 lets one workgroup cover rows of up to 264
+// outputs (256 cells plus the 5 extra faces of the edge interpolation),
+// lanes 0..7 taking a second output.
 constexpr int RI = 4;
-__global__ void __launch_bounds__(256) k_staggered_diff6_i(const double* __restrict__ f, double* __restrict__ out,
-                                                           int ni, int nj, int nk, int nseg, int nrows, double c1,
-                                                           double c2, double c3) {
-  __shared__ double sf[RI][256 + 5];
+constexpr int SEG = 264;
+template <class Op>
+__global__ void __launch_bounds__(256) k_window6_i(const double* __restrict__ in, double* __restrict__ out0,
+                                                   double* __restrict__ out1, int mi, int nseg, int nrows, Op op) {
+  __shared__ double sw[RI][SEG + 5];
   const int w = xcd_slot(gridDim.x, blockIdx.x);
   const int rg = w / nseg, seg = w - rg * nseg;
-  const int i0 = seg * 256, t = (int)threadIdx.x;
-  const int64_t ei = ni + 5;
-#pragma unroll
-  for (int q = 0; q < RI; ++q) {
-    const int row = rg * RI + q;             // row = (v * nk + k) * nj + j
-    const double* fr = f + (int64_t)row * ei;
-    for (int s = t; s < 256 + 5; s += 256) sf[q][s] = row < nrows && i0 + s < ni + 5 ? fr[i0 + s] : 0.0;
-  }
-  __syncthreads();
-  const int i = i0 + t;
-  if (i >= ni) return;
+  const int i0 = seg * SEG, t = (int)threadIdx.x;
+  const int64_t ei = mi + 5;
 #pragma unroll
   for (int q = 0; q < RI; ++q) {
     const int row = rg * RI + q;
-    if (row < nrows)
-      out[(int64_t)row * ni + i] =
-          eq2(c1, c2, c3, sf[q][t], sf[q][t + 1], sf[q][t + 2], sf[q][t + 3], sf[q][t + 4], sf[q][t + 5]);
+    const double* r = in + (int64_t)row * ei;
+    for (int s = t; s < SEG + 5; s += 256) sw[q][s] = row < nrows && i0 + s < mi + 5 ? r[i0 + s] : 0.0;
+  }
+  __syncthreads();
+  for (int tt = t; tt < SEG; tt += 256) {
+    const int i = i0 + tt;
+    if (i >= mi) break;
+#pragma unroll
+    for (int q = 0; q < RI; ++q) {
+      const int row = rg * RI + q;
+      if (row >= nrows) continue;
+      double o[Op::NOUT];
+      op(&sw[q][tt], o);
+      const int64_t at = (int64_t)row * mi + i;
+      out0[at] = o[0];
+      if (Op::NOUT > 1) out1[at] = o[Op::NOUT - 1];
+    }
   }
 }
 
-// Along j or k: each lane marches CH cells of its i-column along the
-// direction with a register window of CH + 5 faces (all loaded up front), so
-// a face is loaded (CH + 5) / CH times instead of six.  Workgroup w takes a
-// 256-cell i-segment of one chunk of one line (v, the other transverse index).
-template <int CH>
-__global__ void __launch_bounds__(256) k_staggered_diff6_march(const double* __restrict__ f, double* __restrict__ out,
-                                                               int ni, int nj, int nk, int d, int nseg, int nchunk,
-                                                               double c1, double c2, double c3) {
+// Along j (d = 1) or k (d = 2).  Output extents mi x mj x mk per variable; the
+// input has 5 more entries along d.  Workgroup w takes a 256-entry i-segment
+// of one chunk of CH outputs of one line (v, the other transverse index).
+template <class Op, int CH>
+__global__ void __launch_bounds__(256) k_window6_march(const double* __restrict__ in, double* __restrict__ out0,
+                                                       double* __restrict__ out1, int mi, int mj, int mk, int d,
+                                                       int nseg, int nchunk, Op op) {
   const int w = xcd_slot(gridDim.x, blockIdx.x);
   const int seg = w % nseg;
   int r = w / nseg;
   const int chunk = r % nchunk;
   r /= nchunk;
   const int i = seg * 256 + (int)threadIdx.x;
-  if (i >= ni) return;
-  const int nd = d == 1 ? nj : nk;                 // cells along the direction
-  const int no = d == 1 ? nk : nj;                 // the other transverse extent
-  const int o = r % no, v = r / no;
-  const int j = d == 1 ? 0 : o, k = d == 1 ? o : 0;
-  const int64_t ej = nj + (d == 1 ? 5 : 0), ek = nk + (d == 2 ? 5 : 0);
-  const int64_t sd = d == 1 ? ni : (int64_t)ni * ej;                 // face stride along d
-  const int64_t so = d == 1 ? (int64_t)ni : (int64_t)nj * ni;          // cell stride along d in out
-  const double* fp = f + (((int64_t)v * ek + k) * ej + j) * ni + i;    // face position 0 of this line
-  double* op = out + (((int64_t)v * nk + k) * nj + j) * ni + i;        // cell 0 of this line
+  if (i >= mi) return;
+  const int md = d == 1 ? mj : mk;                  // outputs along the direction
+  const int mo = d == 1 ? mk : mj;                  // the other transverse extent
+  const int o2 = r % mo, v = r / mo;
+  const int j = d == 1 ? 0 : o2, k = d == 1 ? o2 : 0;
+  const int64_t ej = mj + (d == 1 ? 5 : 0), ek = mk + (d == 2 ? 5 : 0);
+  const int64_t sin_ = d == 1 ? (int64_t)mi : (int64_t)mi * ej;       // input stride along d
+  const int64_t sout = d == 1 ? (int64_t)mi : (int64_t)mi * mj;       // output stride along d
+  const double* ip = in + (((int64_t)v * ek + k) * ej + j) * mi + i;  // input entry 0 of this line
+  const int64_t ob = (((int64_t)v * mk + k) * mj + j) * mi + i;      // output entry 0 of this line
   const int c0 = chunk * CH;
   double win[CH + 5];
 #pragma unroll
-  for (int s = 0; s < CH + 5; ++s) win[s] = c0 + s < nd + 5 ? fp[(c0 + s) * sd] : 0.0;
+  for (int s = 0; s < CH + 5; ++s) win[s] = c0 + s < md + 5 ? ip[(c0 + s) * sin_] : 0.0;
 #pragma unroll
-  for (int s = 0; s < CH; ++s)
-    if (c0 + s < nd)
-      op[(c0 + s) * so] = eq2(c1, c2, c3, win[s], win[s + 1], win[s + 2], win[s + 3], win[s + 4], win[s + 5]);
+  for (int s = 0; s < CH; ++s) {
+    if (c0 + s >= md) break;
+    double o[Op::NOUT];
+    op(&win[s], o);
+    const int64_t at = ob + (int64_t)(c0 + s) * sout;
+    out0[at] = o[0];
+    if (Op::NOUT > 1) out1[at] = o[Op::NOUT - 1];
+  }
+}
+
+// Launch an operator over output extents m (per variable) along direction d.
+template <class Op>
+void launch_window6(const double* in, double* out0, double* out1, const int64_t m[3], int d, int nvar, const Op& op,
+                    hipStream_t stream) {
+  if (d == 0) {
+    const int64_t nseg = (m[0] + SEG - 1) / SEG;
+    const int64_t nrows = (int64_t)nvar * m[1] * m[2];
+    const int64_t nwork = nseg * ((nrows + RI - 1) / RI);
+    if (nwork > INT32_MAX || nrows > INT32_MAX) host_fail(CFD_EINVAL, "field too large");
+    hipLaunchKernelGGL(k_window6_i<Op>, dim3((unsigned)nwork), dim3(256), 0, stream, in, out0, out1, (int)m[0],
+                       (int)nseg, (int)nrows, op);
+  } else {
+    const int64_t nseg = (m[0] + 255) / 256;
+    constexpr int CH = 16;
+    const int64_t nchunk = (m[d] + CH - 1) / CH;
+    const int64_t nwork = nseg * nchunk * nvar * (d == 1 ? m[2] : m[1]);
+    if (nwork > INT32_MAX) host_fail(CFD_EINVAL, "field too large");
+    hipLaunchKernelGGL((k_window6_march<Op, CH>), dim3((unsigned)nwork), dim3(256), 0, stream, in, out0, out1,
+                       (int)m[0], (int)m[1], (int)m[2], d, (int)nseg, (int)nchunk, op);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+}
+
+// Shared argument checks: direction, extents, variables, and that the input
+// range (in_elems doubles) and the output ranges (out_elems each) are disjoint.
+void check_window6(const void* in, int64_t in_elems, const void* const* outs, int nout, int64_t out_elems,
+                   const int32_t n[3], int32_t d, int32_t nvar) {
+  if (!in) host_fail(CFD_EINVAL, "NULL argument");
+  for (int q = 0; q < nout; ++q)
+    if (!outs[q]) host_fail(CFD_EINVAL, "NULL argument");
+  if (n[0] < 1 || n[1] < 1 || n[2] < 1) host_fail(CFD_EINVAL, "every extent must be >= 1");
+  if (nvar < 1 || nvar > 64) host_fail(CFD_EINVAL, "nvar must be in [1, 64]");
+  if (in_elems > ((int64_t)1 << 40)) host_fail(CFD_EINVAL, "field too large");
+  auto overlap = [](const void* a, int64_t na, const void* b, int64_t nb) {
+    const char *a0 = static_cast<const char*>(a), *b0 = static_cast<const char*>(b);
+    return a0 < b0 + nb * 8 && b0 < a0 + na * 8;
+  };
+  for (int q = 0; q < nout; ++q) {
+    if (overlap(in, in_elems, outs[q], out_elems)) host_fail(CFD_EINVAL, "input and output overlap");
+    for (int r = q + 1; r < nout; ++r)
+      if (overlap(outs[q], out_elems, outs[r], out_elems)) host_fail(CFD_EINVAL, "outputs overlap");
+  }
+}
+
+// Entries of a field with extents m per variable and 5 more along d.
+int64_t padded_elems(const int64_t m[3], int d, int nvar) {
+  int64_t e[3] = {m[0], m[1], m[2]};
+  e[d] += 5;
+  return e[0] * e[1] * e[2] * nvar;
 }
 
 }  // namespace cfd
@@ -96,36 +200,27 @@ __global__ void __launch_bounds__(256) k_staggered_diff6_march(const double* __r
 extern "C" cfd_status cfd_staggered_diff6(const double* f_dev, double* out_dev, const int32_t n[3], int32_t d,
                                           int32_t nvar, double h, hipStream_t stream) {
   return cfd::host_guarded([&] {
-    if (!f_dev || !out_dev || !n) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (!n) cfd::host_fail(CFD_EINVAL, "NULL argument");
     if (d < 0 || d > 2) cfd::host_fail(CFD_EINVAL, "direction must be 0, 1 or 2");
-    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
-    if (nvar < 1 || nvar > 64) cfd::host_fail(CFD_EINVAL, "nvar must be in [1, 64]");
     if (!(h > 0.0) || !std::isfinite(h)) cfd::host_fail(CFD_EINVAL, "h must be positive and finite");
-    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-    const int64_t total = cells * nvar;
-    const int64_t faces = total + (int64_t)5 * nvar * (cells / n[d]);
-    if (total > ((int64_t)1 << 40)) cfd::host_fail(CFD_EINVAL, "field too large");
-    // the input and output ranges must not overlap
-    const char *fa = reinterpret_cast<const char*>(f_dev), *fe = fa + faces * 8;
-    const char *oa = reinterpret_cast<const char*>(out_dev), *oe = oa + total * 8;
-    if (fa < oe && oa < fe) cfd::host_fail(CFD_EINVAL, "f and out overlap");
-    const double c1 = 75.0 / (64.0 * h), c2 = -25.0 / (384.0 * h), c3 = 3.0 / (640.0 * h);
-    const int64_t nseg = (n[0] + 255) / 256;
-    if (d == 0) {
-      const int64_t nrows = (int64_t)nvar * n[1] * n[2];
-      const int64_t nwork = nseg * ((nrows + cfd::RI - 1) / cfd::RI);
-      if (nwork > INT32_MAX || nrows > INT32_MAX) cfd::host_fail(CFD_EINVAL, "field too large");
-      hipLaunchKernelGGL(cfd::k_staggered_diff6_i, dim3((unsigned)nwork), dim3(256), 0, stream, f_dev, out_dev, n[0],
-                         n[1], n[2], (int)nseg, (int)nrows, c1, c2, c3);
-    } else {
-      constexpr int CH = 16;
-      const int64_t nchunk = (n[d] + CH - 1) / CH;
-      const int64_t nwork = nseg * nchunk * nvar * (d == 1 ? n[2] : n[1]);
-      if (nwork > INT32_MAX) cfd::host_fail(CFD_EINVAL, "field too large");
-      hipLaunchKernelGGL(cfd::k_staggered_diff6_march<CH>, dim3((unsigned)nwork), dim3(256), 0, stream, f_dev,
-                         out_dev, n[0], n[1], n[2], d, (int)nseg, (int)nchunk, c1, c2, c3);
-    }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    const int64_t m[3] = {n[0], n[1], n[2]};          // the cells
+    const void* outs[1] = {out_dev};
+    cfd::check_window6(f_dev, cfd::padded_elems(m, d, nvar), outs, 1, m[0] * m[1] * m[2] * nvar, n, d, nvar);
+    const cfd::Eq2Op op{75.0 / (64.0 * h), -25.0 / (384.0 * h), 3.0 / (640.0 * h)};
+    cfd::launch_window6(f_dev, out_dev, nullptr, m, d, nvar, op, stream);
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_edges(const double* u_dev, double* left_dev, double* right_dev, const int32_t n[3],
+                                      int32_t d, int32_t nvar, double eps, hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!n) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (d < 0 || d > 2) cfd::host_fail(CFD_EINVAL, "direction must be 0, 1 or 2");
+    if (!(eps > 0.0) || !std::isfinite(eps)) cfd::host_fail(CFD_EINVAL, "eps must be positive and finite");
+    int64_t m[3] = {n[0], n[1], n[2]};
+    m[d] += 5;                                        // the faces i - 1/2, i = -2 .. n[d] + 2
+    const void* outs[2] = {left_dev, right_dev};
+    cfd::check_window6(u_dev, cfd::padded_elems(m, d, nvar), outs, 2, m[0] * m[1] * m[2] * nvar, n, d, nvar);
+    cfd::launch_window6(u_dev, left_dev, right_dev, m, d, nvar, cfd::Wcns5Op{eps}, stream);
   });
 }

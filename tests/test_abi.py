@@ -121,3 +121,18 @@ def test_staggered_diff6_rejects_bad_arguments():
         a = dict(ok, **b)
         st = L.cfd_staggered_diff6(a["f"], a["o"], a["n"], a["d"], a["nvar"], a["h"], None)
         assert st == -1, b
+
+
+def test_wcns5_edges_rejects_bad_arguments():
+    """Argument checks of cfd_wcns5_edges (each fails before any device
+    access; the pointers are placeholders)."""
+    L = B.lib()
+    u, lft, rgt = C.c_void_p(0x100000), C.c_void_p(0x900000), C.c_void_p(0x1100000)
+    n = (C.c_int32 * 3)(8, 4, 2)
+    ok = dict(u=u, l=lft, r=rgt, n=n, d=0, nvar=5, eps=1e-6)
+    bad = [dict(d=3), dict(nvar=0), dict(eps=0.0), dict(eps=float("inf")), dict(n=(C.c_int32 * 3)(0, 4, 2)),
+           dict(r=None), dict(r=lft), dict(l=C.c_void_p(0x100000 + 8 * 10))]
+    for b in bad:
+        a = dict(ok, **b)
+        st = L.cfd_wcns5_edges(a["u"], a["l"], a["r"], a["n"], a["d"], a["nvar"], a["eps"], None)
+        assert st == -1, b

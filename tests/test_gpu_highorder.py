@@ -88,3 +88,59 @@ def test_exact_on_polynomials_gpu(d):
         want = (p * xc ** (p - 1) if p else 0 * xc)
         sh[3 - d] = n[d]
         assert np.max(np.abs(got - want.reshape(sh))) <= 1e-12 * max(1.0, p * np.max(np.abs(xc)) ** max(p - 1, 0))
+
+
+# ------------------------------------------------------------- WCNS-E-5 edges
+# The left/right states involve divisions by the smoothness indicators; the
+# kernel and the oracle evaluate the same expressions, with FMA contraction on
+# the GPU, so they agree to a few ulps of the state (1e-13 relative bar).
+
+def _cells(n, d, nvar, seed, kind):
+    rng = np.random.default_rng(seed)
+    shape = [nvar, n[2], n[1], n[0]]
+    shape[3 - d] += 10
+    if kind == "random":
+        return rng.uniform(0.5, 1.5, shape)
+    ax = 3 - d
+    x = np.arange(shape[ax]) * 0.07
+    sh = [1, 1, 1, 1]
+    sh[ax] = shape[ax]
+    base = np.sin(x).reshape(sh) + np.where(x > x[shape[ax] // 2], 1.0, 0.0).reshape(sh)   # smooth + a jump
+    return np.ascontiguousarray(base + 0.01 * rng.uniform(-1, 1, shape))
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+@pytest.mark.parametrize("n,nvar,kind", [((37, 11, 9), 5, "random"), ((64, 8, 4), 5, "jump"), ((1, 1, 1), 2, "random"),
+                                         ((130, 3, 2), 1, "jump")])
+def test_wcns5_parity_with_oracle(n, nvar, kind, d):
+    import torch
+    from paper_1710_09995_amd.binding import wcns5_edges
+    u = _cells(n, d, nvar, seed=d + 3 * nvar, kind=kind)
+    say("wcns5", n, d, nvar, kind)
+    left, right = wcns5_edges(torch.from_numpy(u).cuda(), n, d)
+    want_l, want_r = ho.wcns5_edge(u, d)
+    for got, want in ((left.cpu().numpy(), want_l), (right.cpu().numpy(), want_r)):
+        assert got.shape == want.shape
+        assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(u))
+
+
+def test_wcns5_then_eq2_on_the_device():
+    """The two operators in sequence on the GPU (upwind flux = left state) for
+    u = exp(sin x) along k equal the oracle's pipeline, and the derivative is
+    fifth-order accurate."""
+    import torch
+    from paper_1710_09995_amd.binding import staggered_diff6, wcns5_edges
+    errs = []
+    for m in (32, 64, 128):
+        h = 2 * np.pi / m
+        q = np.arange(-5, m + 5)
+        col = np.exp(np.sin(q * h))
+        u = np.ascontiguousarray(np.broadcast_to(col.reshape(1, -1, 1, 1), (1, m + 10, 3, 70)))
+        left, _ = wcns5_edges(torch.from_numpy(u).cuda(), (70, 3, m), 2)
+        dudx = staggered_diff6(left, (70, 3, m), 2, h).cpu().numpy()
+        wl, _ = ho.wcns5_edge(u, 2)
+        want = ho.staggered_diff6(wl, 2, h)
+        assert np.max(np.abs(dudx - want)) <= 1e-12
+        x = np.arange(m) * h
+        errs.append(np.max(np.abs(dudx[0, :, 1, 5] - np.cos(x) * np.exp(np.sin(x)))))
+    assert min(np.log2(errs[i] / errs[i + 1]) for i in range(2)) > 4.5
