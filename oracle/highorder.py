@@ -6,7 +6,12 @@ Test infrastructure, like the rest of this package.  Two operators:
 2. the fifth-order weighted cell-edge interpolation of WCNS-E-5 (wcns5_edge),
    which Section 2.2 names and leaves to its reference; it is written here
    from the published construction of that scheme (Deng and Zhang), so its
-   nonlinear weights are "parity unpinned" with respect to the paper.
+   nonlinear weights are "parity unpinned" with respect to the paper;
+3. their composition into the inviscid residual of a periodic Cartesian block
+   (wcns5_euler_residual_periodic): primitive face states by (2), Roe's flux
+   through each face (the flux splitting of the finite-volume path), Eq. (2)
+   along each direction, summed.  Curvilinear metrics and block closures of
+   the scheme are in references the paper does not reproduce.
 
 Section 2.2, Eq. (2): the cell-centred derivative of a face-centred flux F
 along one index direction with grid size h,
@@ -86,3 +91,22 @@ def wcns5_edge(u: np.ndarray, d: int, eps: float = 1e-6, linear: bool = False):
     uL = _edge_left(c[0], c[1], c[2], c[3], c[4], eps, linear)
     uR = _edge_left(c[5], c[4], c[3], c[2], c[1], eps, linear)
     return uL, uR
+
+
+def wcns5_euler_residual_periodic(Q: np.ndarray, h, gamma: float, eps_h: float, eps: float = 1e-6) -> np.ndarray:
+    """Q: [5, nk, nj, ni] conserved point values of a block periodic in every
+    direction, uniform spacings h = (hx, hy, hz) along i, j, k.  Returns
+    R = sum_d dF_d/dx_d at the cells (dQ/dt = -R)."""
+    from .flux import primitives, roe_flux
+    W = primitives(Q, gamma)
+    R = np.zeros_like(Q)
+    for d in range(3):
+        ax = 1 + (2 - d)                            # array axis of direction d in [5, k, j, i]
+        n = W.shape[ax]
+        Wp = np.take(W, np.arange(-5, n + 5) % n, axis=ax)   # five periodic cells beyond each side
+        WL, WR = wcns5_edge(Wp, d, eps)             # faces i - 1/2, i = -2 .. n + 2
+        S = np.zeros((3,) + WL.shape[1:])
+        S[d] = 1.0                                  # unit area along +d: flux per unit area
+        F = roe_flux(WL, WR, S, gamma, eps_h)
+        R = R + staggered_diff6(F, d, h[d])
+    return R
