@@ -195,6 +195,65 @@ def bench_op(a) -> int:
     return 0
 
 
+def bench_wcns5_euler(a) -> int:
+    """The periodic inviscid WCNS-E-5 residual of a 256x128x128 block (a
+    smooth seeded flow): K residuals after W warm-up ones, hipEvents on the
+    launch stream.  The roofline counts each kernel of the pipeline reading
+    its inputs once and writing its outputs once (padding, edge states, Roe
+    faces, Eq. 2 with the running sum), i.e. the intermediates' HBM traffic."""
+    import numpy as np
+    import torch
+    from paper_1710_09995_amd.binding import wcns5_euler_residual_periodic
+    n = (256, 128, 128)
+    ni, nj, nk = n
+    cells = ni * nj * nk
+    rng = np.random.default_rng(0)
+    ph = rng.uniform(0, 2 * np.pi, 4)
+    z, y, x = np.meshgrid(np.arange(nk) / nk, np.arange(nj) / nj, np.arange(ni) / ni, indexing="ij")
+    s2 = 2 * np.pi
+    rho = 1 + 0.2 * np.sin(s2 * x + ph[0]) * np.cos(s2 * y + ph[1]) + 0.1 * np.sin(s2 * z + ph[2])
+    u, v, w = 0.5 + 0.1 * np.sin(s2 * y + ph[3]), 0.1 * np.sin(s2 * z), 0.1 * np.sin(s2 * x)
+    p = 1 + 0.1 * np.cos(s2 * (x + y + z))
+    q = torch.from_numpy(np.stack([rho, rho * u, rho * v, rho * w, p / 0.4 + 0.5 * rho * (u * u + v * v + w * w)])).cuda()
+    h = (1.0 / ni, 1.0 / nj, 1.0 / nk)
+    out = torch.empty_like(q)
+    work = None
+    from paper_1710_09995_amd import binding as B
+    import ctypes as C
+    nb = C.c_size_t()
+    B._check(B.lib().cfd_wcns5_euler_work_bytes((C.c_int32 * 3)(ni, nj, nk), C.byref(nb)))
+    work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(a.warmup):
+        wcns5_euler_residual_periodic(q, h, out=out, work=work)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(a.steps):
+        wcns5_euler_residual_periodic(q, h, out=out, work=work)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    nbytes = 0
+    for d in range(3):
+        P = cells // n[d] * (n[d] + 10)
+        F = cells // n[d] * (n[d] + 5)
+        nbytes += 8 * 5 * ((cells + P) + (P + 2 * F) + (2 * F + F) + (F + cells * (1 if d == 0 else 2)))
+    achieved = nbytes / (ms / 1e3) / 1e9
+    print(json.dumps({
+        "metric": "Mcell/s of the periodic inviscid WCNS-E-5 residual (three directions)",
+        "value": round(cells / (ms / 1e3) / 1e6, 1), "unit": "Mcell/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded smooth periodic flow)",
+        "config": {"workload": "wcns5_euler_periodic_256x128x128"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "pipeline: k_pad_prim_periodic, k_window6_*<Wcns5Op>, k_roe_faces, "
+                               "k_window6_*<Eq2OpT>", "mean_ms": round(ms, 4), "pipeline_bytes": nbytes},
+        "cpu_baseline": None}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,10 +278,11 @@ def main(argv=None):
                     help="with --split: cut positions snap to multiples of these (1,1,1 = plain bisection)")
     ap.add_argument("--groups", type=int, default=8,
                     help="with --split: groups (devices) the pieces are regrouped into for the balance report")
-    ap.add_argument("--op", default=None, choices=["diff6", "wcns5"],
+    ap.add_argument("--op", default=None, choices=["diff6", "wcns5", "wcns5_euler"],
                     help="time one operator instead of the solver, on a 256x128x128 block, 5 variables, each "
                          "direction: diff6 = the sixth-order staggered flux difference (Section 2.2, Eq. 2); "
-                         "wcns5 = the WCNS-E-5 weighted cell-edge interpolation")
+                         "wcns5 = the WCNS-E-5 weighted cell-edge interpolation; wcns5_euler = the periodic "
+                         "inviscid WCNS-E-5 residual (all three directions)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (HBM counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -236,6 +296,8 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n * 8, "copies": 5}), flush=True)
         return 0
+    if a.op == "wcns5_euler" and a.gpus == 1:
+        return bench_wcns5_euler(a)
     if a.op is not None and a.gpus == 1:
         return bench_op(a)
     if a.gpus != 1:

@@ -292,6 +292,25 @@ cfd_status cfd_staggered_diff6(const double* f_dev, double* out_dev, const int32
 cfd_status cfd_wcns5_edges(const double* u_dev, double* left_dev, double* right_dev, const int32_t n[3], int32_t d,
                            int32_t nvar, double eps, hipStream_t stream);
 
+/* Inviscid WCNS-E-5 residual of one block periodic in all three directions on
+ * a uniform Cartesian grid (spacings h[0..2] along i, j, k): for each
+ * direction, the primitive variables padded periodically, their WCNS-E-5 face
+ * states (cfd_wcns5_edges), Roe's flux per unit area through each face (the
+ * flux splitting of the residual kernels, Harten factor entropy_fix), and
+ * Eq. (2) (cfd_staggered_diff6); R = the sum over directions, so that
+ * dQ/dt = -R (Section 2.2, Eq. 3 with the paper's spatial operator).
+ * Curvilinear metrics and block closures of the scheme are in references the
+ * paper does not reproduce, so this covers periodic Cartesian blocks only.
+ * q_dev, r_dev: [5][nk][nj][ni] dense FP64 (conserved variables, residual);
+ * work_dev: cfd_wcns5_euler_work_bytes() bytes of device memory.  All the
+ * caller's, pairwise disjoint.  n[t] >= 1, h > 0, gamma > 1, entropy_fix >= 0,
+ * eps > 0, else CFD_EINVAL; a short workspace gives CFD_ENOMEM.
+ * Asynchronous on stream. */
+cfd_status cfd_wcns5_euler_work_bytes(const int32_t n[3], size_t* bytes);
+cfd_status cfd_wcns5_euler_residual_periodic(const double* q_dev, double* r_dev, void* work_dev, size_t work_bytes,
+                                            const int32_t n[3], const double h[3], double gamma, double entropy_fix,
+                                            double eps, hipStream_t stream);
+
 /* ---------------------------------------------------------------- warm start
  * A multilayer perceptron predicts the steady flow of a channel-bump case
  * from its condition and a cell position, giving the time march a warm start

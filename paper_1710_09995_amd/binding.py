@@ -64,6 +64,7 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_mlp_sizes", "cfd_mlp_forward", "cfd_mlp_mse", "cfd_mlp_backward", "cfd_mlp_adam",
            "cfd_mlp_to_bf16", "cfd_mlp_features", "cfd_mlp_targets", "cfd_mlp_to_state",
            "cfd_split_plan", "cfd_split_tables", "cfd_regroup", "cfd_staggered_diff6", "cfd_wcns5_edges",
+           "cfd_wcns5_euler_work_bytes", "cfd_wcns5_euler_residual_periodic",
            "cfd_status_string", "cfd_last_error"]
 
 _lib = None
@@ -114,6 +115,9 @@ def lib(build_if_missing: bool = True):
     L.cfd_regroup.argtypes = [i32, i64p, i32, C.POINTER(C.c_double), i32p, i64p]
     L.cfd_staggered_diff6.argtypes = [vp, vp, i32p, i32, i32, C.c_double, vp]
     L.cfd_wcns5_edges.argtypes = [vp, vp, vp, i32p, i32, i32, C.c_double, vp]
+    L.cfd_wcns5_euler_work_bytes.argtypes = [i32p, C.POINTER(C.c_size_t)]
+    L.cfd_wcns5_euler_residual_periodic.argtypes = [vp, vp, vp, C.c_size_t, i32p, C.POINTER(C.c_double), C.c_double,
+                                                    C.c_double, C.c_double, vp]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]
@@ -232,6 +236,29 @@ def wcns5_edges(u, n, d: int, eps: float = 1e-6, stream=None):
     _check(lib().cfd_wcns5_edges(_ptr(u), _ptr(left), _ptr(right), nn, int(d), int(u.shape[0]), float(eps),
                                  _stream_handle(torch, stream)))
     return left, right
+
+
+def wcns5_euler_residual_periodic(q, h, gamma: float = 1.4, entropy_fix: float = 0.1, eps: float = 1e-6,
+                                  out=None, work=None, stream=None):
+    """Inviscid WCNS-E-5 residual of a periodic Cartesian block on the device
+    (cfd_wcns5_euler_residual_periodic): q is a contiguous FP64 CUDA tensor
+    [5, nk, nj, ni]; returns R of the same shape (dQ/dt = -R)."""
+    import torch
+    if q.dtype != torch.float64 or not q.is_cuda or not q.is_contiguous() or q.dim() != 4 or q.shape[0] != 5:
+        raise ValueError("q must be a contiguous float64 CUDA tensor [5, nk, nj, ni]")
+    nk, nj, ni = (int(v) for v in q.shape[1:])
+    nn = (C.c_int32 * 3)(ni, nj, nk)
+    nbytes = C.c_size_t()
+    _check(lib().cfd_wcns5_euler_work_bytes(nn, C.byref(nbytes)))
+    if work is None or work.numel() * work.element_size() < nbytes.value:
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+    if out is None:
+        out = torch.empty_like(q)
+    hh = (C.c_double * 3)(*[float(v) for v in h])
+    _check(lib().cfd_wcns5_euler_residual_periodic(_ptr(q), _ptr(out), _ptr(work), nbytes.value, nn, hh,
+                                                   float(gamma), float(entropy_fix), float(eps),
+                                                   _stream_handle(torch, stream)))
+    return out
 
 
 class Solver:

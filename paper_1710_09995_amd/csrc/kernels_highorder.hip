@@ -31,9 +31,12 @@ __device__ __forceinline__ int xcd_slot(int nb, int b) {
   return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
 }
 
-// Eq. (2): one output per window.
-struct Eq2Op {
+// Eq. (2): one output per window; ACC adds it to the output (sums over
+// directions) instead of storing it.
+template <bool ACC_>
+struct Eq2OpT {
   static constexpr int NOUT = 1;
+  static constexpr bool ACC = ACC_;
   double c1, c2, c3;
   __device__ __forceinline__ void operator()(const double* w, double* o) const {
     o[0] = c1 * (w[3] - w[2]) + c2 * (w[4] - w[1]) + c3 * (w[5] - w[0]);
@@ -60,6 +63,7 @@ __device__ __forceinline__ double wcns5_left(double um2, double um1, double u0, 
 // third and fourth.  Left state from cells p .. p + 4, right from p + 5 .. p + 1.
 struct Wcns5Op {
   static constexpr int NOUT = 2;
+  static constexpr bool ACC = false;
   double eps;
   __device__ __forceinline__ void operator()(const double* w, double* o) const {
     o[0] = wcns5_left(w[0], w[1], w[2], w[3], w[4], eps);
@@ -99,8 +103,8 @@ __global__ void __launch_bounds__(256) k_window6_i(const double* __restrict__ in
       double o[Op::NOUT];
       op(&sw[q][tt], o);
       const int64_t at = (int64_t)row * mi + i;
-      out0[at] = o[0];
-      if (Op::NOUT > 1) out1[at] = o[Op::NOUT - 1];
+      if constexpr (Op::ACC) out0[at] += o[0]; else out0[at] = o[0];
+      if constexpr (Op::NOUT > 1) out1[at] = o[Op::NOUT - 1];
     }
   }
 }
@@ -138,8 +142,8 @@ __global__ void __launch_bounds__(256) k_window6_march(const double* __restrict_
     double o[Op::NOUT];
     op(&win[s], o);
     const int64_t at = ob + (int64_t)(c0 + s) * sout;
-    out0[at] = o[0];
-    if (Op::NOUT > 1) out1[at] = o[Op::NOUT - 1];
+    if constexpr (Op::ACC) out0[at] += o[0]; else out0[at] = o[0];
+    if constexpr (Op::NOUT > 1) out1[at] = o[Op::NOUT - 1];
   }
 }
 
@@ -165,6 +169,55 @@ void launch_window6(const double* in, double* out0, double* out1, const int64_t 
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+}
+
+// Primitive variables of a periodic block, padded by five cells on each side
+// along d: W[v][...p...] = prim(Q at cell (p - 5) mod n_d), p = 0 .. n_d + 9.
+__global__ void __launch_bounds__(256) k_pad_prim_periodic(const double* __restrict__ q, double* __restrict__ w,
+                                                           int ni, int nj, int nk, int d, double gm1) {
+  const int64_t ei = ni + (d == 0 ? 10 : 0), ej = nj + (d == 1 ? 10 : 0), ek = nk + (d == 2 ? 10 : 0);
+  const int64_t total = ei * ej * ek, cells = (int64_t)ni * nj * nk;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t a = t % ei, r = t / ei;
+    int64_t b = r % ej, c = r / ej;
+    if (d == 0) a = (a - 5 + 5 * (int64_t)ni) % ni;
+    if (d == 1) b = (b - 5 + 5 * (int64_t)nj) % nj;
+    if (d == 2) c = (c - 5 + 5 * (int64_t)nk) % nk;
+    const int64_t src = (c * nj + b) * ni + a;
+    const Prim<double> p = to_prim<double>(q[src], q[cells + src], q[2 * cells + src], q[3 * cells + src],
+                                           q[4 * cells + src], gm1);
+    w[t] = p.r;
+    w[total + t] = p.u;
+    w[2 * total + t] = p.v;
+    w[3 * total + t] = p.w;
+    w[4 * total + t] = p.p;
+  }
+}
+
+// Roe's flux per unit area through faces of unit normal e_d, from the left
+// and right primitive states (each [5][nf]).
+__global__ void __launch_bounds__(256) k_roe_faces(const double* __restrict__ wl, const double* __restrict__ wr,
+                                                   double* __restrict__ f, int64_t nf, int d, Gas<double> gas) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nf; t += (int64_t)gridDim.x * blockDim.x) {
+    const Prim<double> L{wl[t], wl[nf + t], wl[2 * nf + t], wl[3 * nf + t], wl[4 * nf + t]};
+    const Prim<double> R{wr[t], wr[nf + t], wr[2 * nf + t], wr[3 * nf + t], wr[4 * nf + t]};
+    double fl[5];
+    roe<double>(L, R, d == 0 ? 1.0 : 0.0, d == 1 ? 1.0 : 0.0, d == 2 ? 1.0 : 0.0, gas, fl);
+    for (int v = 0; v < 5; ++v) f[v * nf + t] = fl[v];
+  }
+}
+
+int grid_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 8192); }
+
+// Workspace of the periodic WCNS-E-5 residual (doubles): the padded primitives
+// and the two face states and the face flux of the largest direction.
+void wcns5_work(const int32_t n[3], int64_t& pmax, int64_t& fmax) {
+  const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+  pmax = fmax = 0;
+  for (int d = 0; d < 3; ++d) {
+    pmax = std::max(pmax, 5 * (cells / n[d]) * (n[d] + 10));
+    fmax = std::max(fmax, 5 * (cells / n[d]) * (n[d] + 5));
+  }
 }
 
 // Shared argument checks: direction, extents, variables, and that the input
@@ -206,7 +259,7 @@ extern "C" cfd_status cfd_staggered_diff6(const double* f_dev, double* out_dev, 
     const int64_t m[3] = {n[0], n[1], n[2]};          // the cells
     const void* outs[1] = {out_dev};
     cfd::check_window6(f_dev, cfd::padded_elems(m, d, nvar), outs, 1, m[0] * m[1] * m[2] * nvar, n, d, nvar);
-    const cfd::Eq2Op op{75.0 / (64.0 * h), -25.0 / (384.0 * h), 3.0 / (640.0 * h)};
+    const cfd::Eq2OpT<false> op{75.0 / (64.0 * h), -25.0 / (384.0 * h), 3.0 / (640.0 * h)};
     cfd::launch_window6(f_dev, out_dev, nullptr, m, d, nvar, op, stream);
   });
 }
@@ -222,5 +275,67 @@ extern "C" cfd_status cfd_wcns5_edges(const double* u_dev, double* left_dev, dou
     const void* outs[2] = {left_dev, right_dev};
     cfd::check_window6(u_dev, cfd::padded_elems(m, d, nvar), outs, 2, m[0] * m[1] * m[2] * nvar, n, d, nvar);
     cfd::launch_window6(u_dev, left_dev, right_dev, m, d, nvar, cfd::Wcns5Op{eps}, stream);
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_euler_work_bytes(const int32_t n[3], size_t* bytes) {
+  return cfd::host_guarded([&] {
+    if (!n || !bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    int64_t pmax, fmax;
+    cfd::wcns5_work(n, pmax, fmax);
+    *bytes = (size_t)(8 * (pmax + 3 * fmax));
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_euler_residual_periodic(const double* q_dev, double* r_dev, void* work_dev,
+                                                        size_t work_bytes, const int32_t n[3], const double h[3],
+                                                        double gamma, double entropy_fix, double eps,
+                                                        hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!q_dev || !r_dev || !work_dev || !n || !h) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    for (int d = 0; d < 3; ++d)
+      if (!(h[d] > 0.0) || !std::isfinite(h[d])) cfd::host_fail(CFD_EINVAL, "spacings must be positive and finite");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) cfd::host_fail(CFD_EINVAL, "gamma must exceed 1");
+    if (!(entropy_fix >= 0.0) || !std::isfinite(entropy_fix)) cfd::host_fail(CFD_EINVAL, "bad entropy_fix");
+    if (!(eps > 0.0) || !std::isfinite(eps)) cfd::host_fail(CFD_EINVAL, "eps must be positive and finite");
+    int64_t pmax, fmax;
+    cfd::wcns5_work(n, pmax, fmax);
+    const size_t need = (size_t)(8 * (pmax + 3 * fmax));
+    if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_euler_work_bytes()");
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    auto apart = [](const void* a, int64_t na, const void* b, int64_t nb) {
+      const char *a0 = static_cast<const char*>(a), *b0 = static_cast<const char*>(b);
+      return a0 + na <= b0 || b0 + nb <= a0;
+    };
+    if (!apart(q_dev, 40 * cells, r_dev, 40 * cells) || !apart(q_dev, 40 * cells, work_dev, (int64_t)need) ||
+        !apart(r_dev, 40 * cells, work_dev, (int64_t)need))
+      cfd::host_fail(CFD_EINVAL, "q, r and the workspace must not overlap");
+    double* W = static_cast<double*>(work_dev);
+    double* WL = W + pmax;
+    double* WR = WL + fmax;
+    double* F = WR + fmax;
+    cfd::Gas<double> gas{};
+    gas.gamma = gamma;
+    gas.gm1 = gamma - 1.0;
+    gas.gg = gamma / (gamma - 1.0);
+    gas.eps_h = entropy_fix;
+    for (int d = 0; d < 3; ++d) {
+      int64_t mp[3] = {n[0], n[1], n[2]}, mf[3] = {n[0], n[1], n[2]};
+      mp[d] += 10;
+      mf[d] += 5;
+      const int64_t nf = mf[0] * mf[1] * mf[2];
+      hipLaunchKernelGGL(cfd::k_pad_prim_periodic, dim3(cfd::grid_for(mp[0] * mp[1] * mp[2])), dim3(256), 0, stream,
+                         q_dev, W, n[0], n[1], n[2], d, gamma - 1.0);
+      cfd::launch_window6(W, WL, WR, mf, d, 5, cfd::Wcns5Op{eps}, stream);
+      hipLaunchKernelGGL(cfd::k_roe_faces, dim3(cfd::grid_for(nf)), dim3(256), 0, stream, WL, WR, F, nf, d, gas);
+      const int64_t m[3] = {n[0], n[1], n[2]};
+      const double c1 = 75.0 / (64.0 * h[d]), c2 = -25.0 / (384.0 * h[d]), c3 = 3.0 / (640.0 * h[d]);
+      if (d == 0)
+        cfd::launch_window6(F, r_dev, nullptr, m, d, 5, cfd::Eq2OpT<false>{c1, c2, c3}, stream);
+      else
+        cfd::launch_window6(F, r_dev, nullptr, m, d, 5, cfd::Eq2OpT<true>{c1, c2, c3}, stream);
+    }
   });
 }

@@ -136,3 +136,25 @@ def test_wcns5_edges_rejects_bad_arguments():
         a = dict(ok, **b)
         st = L.cfd_wcns5_edges(a["u"], a["l"], a["r"], a["n"], a["d"], a["nvar"], a["eps"], None)
         assert st == -1, b
+
+
+def test_wcns5_residual_work_bytes_and_bad_arguments():
+    L = B.lib()
+    n = (C.c_int32 * 3)(8, 4, 2)
+    nb = C.c_size_t()
+    assert L.cfd_wcns5_euler_work_bytes(n, C.byref(nb)) == 0
+    # the largest padded direction is k (2 cells: 32 lines of 2 + 10 padded cells, 2 + 5 faces):
+    # 5 * 32 * 12 padded primitives + 3 arrays of 5 * 32 * 7 face values
+    assert nb.value == 8 * (5 * 32 * 12 + 3 * 5 * 32 * 7)
+    q, r, w = C.c_void_p(0x100000), C.c_void_p(0x900000), C.c_void_p(0x1100000)
+    h = (C.c_double * 3)(0.1, 0.1, 0.1)
+    ok = dict(q=q, r=r, w=w, wb=nb.value, n=n, h=h, g=1.4, ef=0.1, eps=1e-6)
+    bad = {-2: [dict(wb=nb.value - 8)],
+           -1: [dict(g=1.0), dict(ef=-0.1), dict(eps=0.0), dict(h=(C.c_double * 3)(0.1, 0.0, 0.1)),
+                dict(n=(C.c_int32 * 3)(8, 0, 2)), dict(r=q), dict(w=None)]}
+    for st_want, cases_ in bad.items():
+        for b in cases_:
+            a = dict(ok, **b)
+            st = L.cfd_wcns5_euler_residual_periodic(a["q"], a["r"], a["w"], a["wb"], a["n"], a["h"], a["g"],
+                                                     a["ef"], a["eps"], None)
+            assert st == st_want, b
