@@ -158,3 +158,18 @@ def test_wcns5_residual_work_bytes_and_bad_arguments():
             st = L.cfd_wcns5_euler_residual_periodic(a["q"], a["r"], a["w"], a["wb"], a["n"], a["h"], a["g"],
                                                      a["ef"], a["eps"], None)
             assert st == st_want, b
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/cfd.h compiles as C99 (a C ABI: no C++ in the declarations)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None or not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"):
+        pytest.skip("gcc or the ROCm headers are not available")
+    src = tmp_path / "t.c"
+    src.write_text('#include "cfd.h"\nint main(void) { cfd_ctx* c = 0; return (int)cfd_destroy(c); }\n')
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                        "-I" + os.path.join(ROOT, "include"), "-I/opt/rocm/include", "-fsyntax-only", str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
