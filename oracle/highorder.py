@@ -11,7 +11,9 @@ Test infrastructure, like the rest of this package.  Two operators:
    (wcns5_euler_residual_periodic): primitive face states by (2), Roe's flux
    through each face (the flux splitting of the finite-volume path), Eq. (2)
    along each direction, summed.  Curvilinear metrics and block closures of
-   the scheme are in references the paper does not reproduce.
+   the scheme are in references the paper does not reproduce;
+4. the third-order Runge-Kutta steps of Eqs. (4)-(6) on that residual
+   (wcns5_euler_steps_periodic), with the oracle solver's ssp_rk3.
 
 Section 2.2, Eq. (2): the cell-centred derivative of a face-centred flux F
 along one index direction with grid size h,
@@ -110,3 +112,14 @@ def wcns5_euler_residual_periodic(Q: np.ndarray, h, gamma: float, eps_h: float, 
         F = roe_flux(WL, WR, S, gamma, eps_h)
         R = R + staggered_diff6(F, d, h[d])
     return R
+
+
+def wcns5_euler_steps_periodic(Q: np.ndarray, h, gamma: float, eps_h: float, dt: float, nsteps: int,
+                               eps: float = 1e-6) -> np.ndarray:
+    """nsteps SSP-RK3 steps (Eqs. 4-6, lambda = -dt) of dQ/dt = -R(Q) with the
+    periodic WCNS-E-5 residual and a fixed dt."""
+    from .solver import ssp_rk3
+    q = Q
+    for _ in range(nsteps):
+        q = ssp_rk3(q, dt, lambda x: wcns5_euler_residual_periodic(x, h, gamma, eps_h, eps))
+    return q
