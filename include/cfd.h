@@ -311,6 +311,17 @@ cfd_status cfd_wcns5_euler_residual_periodic(const double* q_dev, double* r_dev,
                                             const int32_t n[3], const double h[3], double gamma, double entropy_fix,
                                             double eps, hipStream_t stream);
 
+/* nsteps third-order Runge-Kutta steps (Section 2.2, Eqs. 4-6, lambda = -dt,
+ * fixed dt) of dQ/dt = -R(Q) with the periodic WCNS-E-5 residual above, in
+ * place on q_dev ([5][nk][nj][ni]).  work_dev: cfd_wcns5_euler_step_work_bytes()
+ * bytes (the residual's workspace, the step's start state and R).  dt > 0,
+ * nsteps >= 0, the other arguments as for the residual; a short workspace
+ * gives CFD_ENOMEM.  Asynchronous on stream. */
+cfd_status cfd_wcns5_euler_step_work_bytes(const int32_t n[3], size_t* bytes);
+cfd_status cfd_wcns5_euler_steps_periodic(double* q_dev, void* work_dev, size_t work_bytes, const int32_t n[3],
+                                          const double h[3], double gamma, double entropy_fix, double eps, double dt,
+                                          int32_t nsteps, hipStream_t stream);
+
 /* ---------------------------------------------------------------- warm start
  * A multilayer perceptron predicts the steady flow of a channel-bump case
  * from its condition and a cell position, giving the time march a warm start

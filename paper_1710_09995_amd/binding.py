@@ -64,7 +64,8 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_mlp_sizes", "cfd_mlp_forward", "cfd_mlp_mse", "cfd_mlp_backward", "cfd_mlp_adam",
            "cfd_mlp_to_bf16", "cfd_mlp_features", "cfd_mlp_targets", "cfd_mlp_to_state",
            "cfd_split_plan", "cfd_split_tables", "cfd_regroup", "cfd_staggered_diff6", "cfd_wcns5_edges",
-           "cfd_wcns5_euler_work_bytes", "cfd_wcns5_euler_residual_periodic",
+           "cfd_wcns5_euler_work_bytes", "cfd_wcns5_euler_residual_periodic", "cfd_wcns5_euler_step_work_bytes",
+           "cfd_wcns5_euler_steps_periodic",
            "cfd_status_string", "cfd_last_error"]
 
 _lib = None
@@ -118,6 +119,9 @@ def lib(build_if_missing: bool = True):
     L.cfd_wcns5_euler_work_bytes.argtypes = [i32p, C.POINTER(C.c_size_t)]
     L.cfd_wcns5_euler_residual_periodic.argtypes = [vp, vp, vp, C.c_size_t, i32p, C.POINTER(C.c_double), C.c_double,
                                                     C.c_double, C.c_double, vp]
+    L.cfd_wcns5_euler_step_work_bytes.argtypes = [i32p, C.POINTER(C.c_size_t)]
+    L.cfd_wcns5_euler_steps_periodic.argtypes = [vp, vp, C.c_size_t, i32p, C.POINTER(C.c_double), C.c_double,
+                                                 C.c_double, C.c_double, C.c_double, i32, vp]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]
@@ -259,6 +263,26 @@ def wcns5_euler_residual_periodic(q, h, gamma: float = 1.4, entropy_fix: float =
                                                    float(gamma), float(entropy_fix), float(eps),
                                                    _stream_handle(torch, stream)))
     return out
+
+
+def wcns5_euler_steps_periodic(q, h, dt: float, nsteps: int, gamma: float = 1.4, entropy_fix: float = 0.1,
+                               eps: float = 1e-6, work=None, stream=None):
+    """nsteps RK3 steps of the periodic WCNS-E-5 Euler residual on the device,
+    in place on q (contiguous FP64 CUDA tensor [5, nk, nj, ni]); returns q."""
+    import torch
+    if q.dtype != torch.float64 or not q.is_cuda or not q.is_contiguous() or q.dim() != 4 or q.shape[0] != 5:
+        raise ValueError("q must be a contiguous float64 CUDA tensor [5, nk, nj, ni]")
+    nk, nj, ni = (int(v) for v in q.shape[1:])
+    nn = (C.c_int32 * 3)(ni, nj, nk)
+    nbytes = C.c_size_t()
+    _check(lib().cfd_wcns5_euler_step_work_bytes(nn, C.byref(nbytes)))
+    if work is None or work.numel() * work.element_size() < nbytes.value:
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+    hh = (C.c_double * 3)(*[float(v) for v in h])
+    _check(lib().cfd_wcns5_euler_steps_periodic(_ptr(q), _ptr(work), nbytes.value, nn, hh, float(gamma),
+                                                float(entropy_fix), float(eps), float(dt), int(nsteps),
+                                                _stream_handle(torch, stream)))
+    return q
 
 
 class Solver:

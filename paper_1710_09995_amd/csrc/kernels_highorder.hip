@@ -209,6 +209,24 @@ __global__ void __launch_bounds__(256) k_roe_faces(const double* __restrict__ wl
 
 int grid_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 8192); }
 
+// One Runge-Kutta stage of Eqs. (4)-(6) with lambda = -dt, in place:
+// q <- a qn + b (q - dt r) (a = 0, b = 1: the first stage; then 3/4, 1/4 and
+// 1/3, 2/3).  keep_qn also stores q into qn first (the step's start state).
+__global__ void __launch_bounds__(256) k_rk3_stage(double* __restrict__ q, double* __restrict__ qn,
+                                                   const double* __restrict__ r, int64_t n, double dt, double a,
+                                                   double b, int keep_qn) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const double x = q[t], y = r[t];
+    const double s = x - dt * y;
+    if (keep_qn) {
+      qn[t] = x;
+      q[t] = s;
+    } else {
+      q[t] = a * qn[t] + b * s;
+    }
+  }
+}
+
 // Workspace of the periodic WCNS-E-5 residual (doubles): the padded primitives
 // and the two face states and the face flux of the largest direction.
 void wcns5_work(const int32_t n[3], int64_t& pmax, int64_t& fmax) {
@@ -337,5 +355,56 @@ extern "C" cfd_status cfd_wcns5_euler_residual_periodic(const double* q_dev, dou
       else
         cfd::launch_window6(F, r_dev, nullptr, m, d, 5, cfd::Eq2OpT<true>{c1, c2, c3}, stream);
     }
+  });
+}
+
+namespace {
+
+size_t wcns5_residual_work(const int32_t n[3]) {
+  int64_t pmax, fmax;
+  cfd::wcns5_work(n, pmax, fmax);
+  return (size_t)(8 * (pmax + 3 * fmax));
+}
+
+}  // namespace
+
+extern "C" cfd_status cfd_wcns5_euler_step_work_bytes(const int32_t n[3], size_t* bytes) {
+  return cfd::host_guarded([&] {
+    if (!n || !bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    *bytes = wcns5_residual_work(n) + (size_t)2 * 40 * ((size_t)n[0] * n[1] * n[2]);
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_euler_steps_periodic(double* q_dev, void* work_dev, size_t work_bytes,
+                                                     const int32_t n[3], const double h[3], double gamma,
+                                                     double entropy_fix, double eps, double dt, int32_t nsteps,
+                                                     hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!q_dev || !work_dev || !n || !h) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    if (!(dt > 0.0) || !std::isfinite(dt)) cfd::host_fail(CFD_EINVAL, "dt must be positive and finite");
+    if (nsteps < 0) cfd::host_fail(CFD_EINVAL, "nsteps must be >= 0");
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    const size_t rw = wcns5_residual_work(n);
+    if (work_bytes < rw + (size_t)2 * 40 * cells)
+      cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_euler_step_work_bytes()");
+    const char *qa = reinterpret_cast<const char*>(q_dev), *wa = static_cast<const char*>(work_dev);
+    if (qa < wa + work_bytes && wa < qa + 40 * cells) cfd::host_fail(CFD_EINVAL, "q and the workspace overlap");
+    double* qn = reinterpret_cast<double*>(static_cast<char*>(work_dev) + rw);
+    double* r = qn + 5 * cells;
+    const int64_t nv = 5 * cells;
+    const int g = cfd::grid_for(nv);
+    const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int it = 0; it < nsteps; ++it)
+      for (int st = 0; st < 3; ++st) {
+        const cfd_status s = cfd_wcns5_euler_residual_periodic(q_dev, r, work_dev, rw, n, h, gamma, entropy_fix,
+                                                               eps, stream);
+        if (s != CFD_OK) cfd::host_fail(s, cfd_last_error(nullptr));
+        hipLaunchKernelGGL(cfd::k_rk3_stage, dim3(g), dim3(256), 0, stream, q_dev, qn, r, nv, dt, a[st], b[st],
+                           st == 0 ? 1 : 0);
+      }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   });
 }

@@ -173,3 +173,19 @@ def test_header_is_plain_c(tmp_path):
                         "-I" + os.path.join(ROOT, "include"), "-I/opt/rocm/include", "-fsyntax-only", str(src)],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_wcns5_steps_bad_arguments():
+    L = B.lib()
+    n = (C.c_int32 * 3)(8, 4, 2)
+    nb, nr = C.c_size_t(), C.c_size_t()
+    assert L.cfd_wcns5_euler_step_work_bytes(n, C.byref(nb)) == 0
+    assert L.cfd_wcns5_euler_work_bytes(n, C.byref(nr)) == 0
+    assert nb.value == nr.value + 2 * 40 * 64          # + start state and R: 5 doubles per cell each
+    q, w = C.c_void_p(0x100000), C.c_void_p(0x900000)
+    h = (C.c_double * 3)(0.1, 0.1, 0.1)
+    for st_want, kw in ((-1, dict(dt=0.0)), (-1, dict(ns=-1)), (-2, dict(wb=nb.value - 8)), (-1, dict(w=None))):
+        a = dict(q=q, w=w, wb=nb.value, dt=0.01, ns=1)
+        a.update(kw)
+        st = L.cfd_wcns5_euler_steps_periodic(a["q"], a["w"], a["wb"], n, h, 1.4, 0.1, 1e-6, a["dt"], a["ns"], None)
+        assert st == st_want, kw

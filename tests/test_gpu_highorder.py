@@ -195,3 +195,22 @@ def test_wcns5_residual_freestream_and_vortex_order_gpu():
         near = ((np.abs(X - xc) < 3) & (np.abs(Y - yc) < 3))[None, None]
         errs.append(np.max(np.abs(-R - rate) * near))
     assert min(np.log2(errs[i] / errs[i + 1]) for i in range(2)) >= 4.0
+
+
+def test_wcns5_steps_parity_and_freestream():
+    """RK3 steps on the device against the oracle's steps (5 steps, the smooth
+    periodic flow), and a uniform stream kept uniform."""
+    import torch
+    from paper_1710_09995_amd import cases
+    from paper_1710_09995_amd.binding import wcns5_euler_steps_periodic
+    n = (20, 12, 6)
+    q = _smooth_state(n, seed=1)
+    h = (1.0 / n[0], 1.0 / n[1], 1.0 / n[2])
+    dt = 0.2 * min(h) / 2.0
+    got = wcns5_euler_steps_periodic(torch.from_numpy(q.copy()).cuda(), h, dt, 5).cpu().numpy()
+    want = ho.wcns5_euler_steps_periodic(q, h, 1.4, 0.1, dt, 5)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    c = cases.vortex_case(12, nz=6, seed=0)
+    qu = np.ascontiguousarray(cases.uniform_state((12, 12, 6), c.params))
+    got = wcns5_euler_steps_periodic(torch.from_numpy(qu.copy()).cuda(), (0.3, 0.3, 0.5), 0.05, 4).cpu().numpy()
+    assert np.max(np.abs(got - qu)) <= 1e-12
