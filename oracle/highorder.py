@@ -13,7 +13,13 @@ Test infrastructure, like the rest of this package.  Two operators:
    along each direction, summed.  Curvilinear metrics and block closures of
    the scheme are in references the paper does not reproduce;
 4. the third-order Runge-Kutta steps of Eqs. (4)-(6) on that residual
-   (wcns5_euler_steps_periodic), with the oracle solver's ssp_rk3.
+   (wcns5_euler_steps_periodic), with the oracle solver's ssp_rk3;
+5. the viscous terms by fourth-order central differencing, which the paper
+   chooses for the viscous flux derivatives without printing the formulas
+   (viscous_residual_periodic): the textbook fourth-order cell derivative,
+   face value, face derivative and staggered flux difference on a periodic
+   Cartesian block, with the stress tensor, Sutherland viscosity and
+   conduction of the finite-volume path.
 
 Section 2.2, Eq. (2): the cell-centred derivative of a face-centred flux F
 along one index direction with grid size h,
@@ -123,3 +129,58 @@ def wcns5_euler_steps_periodic(Q: np.ndarray, h, gamma: float, eps_h: float, dt:
     for _ in range(nsteps):
         q = ssp_rk3(q, dt, lambda x: wcns5_euler_residual_periodic(x, h, gamma, eps_h, eps))
     return q
+
+
+# ----------------------------------------- fourth-order central viscous terms
+# On a uniform periodic grid (f[i + s] by np.roll), all exact for cubics:
+#   cell derivative   (f_{i-2} - 8 f_{i-1} + 8 f_{i+1} - f_{i+2}) / (12 h)
+#   face value        (-f_{i-1} + 9 f_i + 9 f_{i+1} - f_{i+2}) / 16             at i + 1/2
+#   face derivative   (f_{i-1} - 27 f_i + 27 f_{i+1} - f_{i+2}) / (24 h)        at i + 1/2
+#   flux difference   (F_{i-3/2} - 27 F_{i-1/2} + 27 F_{i+1/2} - F_{i+3/2}) / (24 h)   at i
+# (a face array holds face i + 1/2 at index i).
+
+def _at(f, ax, s):
+    """f[i + s] along axis ax, periodic."""
+    return np.roll(f, -s, axis=ax)
+
+
+def c4_cell_deriv(f, ax, h):
+    return (_at(f, ax, -2) - 8.0 * _at(f, ax, -1) + 8.0 * _at(f, ax, 1) - _at(f, ax, 2)) / (12.0 * h)
+
+
+def c4_face_value(f, ax):
+    return (-_at(f, ax, -1) + 9.0 * f + 9.0 * _at(f, ax, 1) - _at(f, ax, 2)) / 16.0
+
+
+def c4_face_deriv(f, ax, h):
+    return (_at(f, ax, -1) - 27.0 * f + 27.0 * _at(f, ax, 1) - _at(f, ax, 2)) / (24.0 * h)
+
+
+def c4_flux_diff(F, ax, h):
+    return (_at(F, ax, -2) - 27.0 * _at(F, ax, -1) + 27.0 * F - _at(F, ax, 1)) / (24.0 * h)
+
+
+def viscous_residual_periodic(Q: np.ndarray, h, gamma: float, prandtl: float, mu_inf: float,
+                              s_star: float) -> np.ndarray:
+    """-div F_v on a periodic Cartesian block (Q: [5, nk, nj, ni]); add it to
+    the inviscid residual for the Navier-Stokes residual (dQ/dt = -R)."""
+    from .flux import primitives, sutherland
+    W = primitives(Q, gamma)
+    phi = [W[1], W[2], W[3], W[4] / W[0]]                     # u, v, w, T
+    axis = [3, 2, 1]                                          # array axis of x, y, z in [k, j, i]
+    G = [[c4_cell_deriv(phi[a], axis[t] - 1, h[t]) for t in range(3)] for a in range(4)]
+    Rv = np.zeros_like(Q)
+    for d in range(3):
+        ax = axis[d] - 1                                      # axis within a [k, j, i] field
+        pf = [c4_face_value(phi[a], ax) for a in range(4)]
+        grad = [[c4_face_deriv(phi[a], ax, h[d]) if t == d else c4_face_value(G[a][t], ax) for t in range(3)]
+                for a in range(4)]
+        mu = sutherland(pf[3], mu_inf, s_star)
+        kc = mu * gamma / ((gamma - 1.0) * prandtl)
+        div = grad[0][0] + grad[1][1] + grad[2][2]
+        tau = [mu * (grad[d][b] + grad[b][d]) for b in range(3)]
+        tau[d] = tau[d] - (2.0 / 3.0) * mu * div
+        Fv = [tau[0], tau[1], tau[2], pf[0] * tau[0] + pf[1] * tau[1] + pf[2] * tau[2] + kc * grad[3][d]]
+        for c in range(4):
+            Rv[1 + c] = Rv[1 + c] - c4_flux_diff(Fv[c], ax, h[d])
+    return Rv

@@ -261,3 +261,76 @@ def test_wcns5_steps_freestream_and_advected_vortex():
         near = ((np.abs(X - cx) < 3) & (np.abs(Y - cy) < 3))[None, None]
         errs.append(np.max(np.abs(q - Qf(X, Y, cx, cy)) * near))
     assert np.log2(errs[0] / errs[1]) >= 3.0, errs
+
+
+# ------------------------------------------ fourth-order central viscous terms
+
+def test_c4_operators_exact_on_cubics():
+    n, h, x0 = 16, 0.17, -0.6
+    x = x0 + np.arange(n) * h
+    inner = slice(2, n - 3)
+    for p in range(4):
+        f = x ** p
+        xf = x + 0.5 * h
+        assert np.allclose(ho.c4_cell_deriv(f, 0, h)[inner], (p * x ** (p - 1) if p else 0 * x)[inner], atol=1e-12)
+        assert np.allclose(ho.c4_face_value(f, 0)[inner], (xf ** p)[inner], atol=1e-12)
+        assert np.allclose(ho.c4_face_deriv(f, 0, h)[inner], (p * xf ** (p - 1) if p else 0 * x)[inner], atol=1e-12)
+        # flux difference of face values F(x_{i+1/2}) -> derivative at x_i
+        assert np.allclose(ho.c4_flux_diff(xf ** p, 0, h)[inner], (p * x ** (p - 1) if p else 0 * x)[inner],
+                           atol=1e-12)
+
+
+def _shear_field(n, gamma=1.4):
+    """rho = p = 1 (T = 1, constant viscosity), u = sin y, v = sin z, w = sin x on
+    [0, 2 pi)^3, and its -div F_v in closed form: momentum mu (sin y, sin z,
+    sin x), energy -mu (cos 2x + cos 2y + cos 2z) (worked by hand from the
+    stress tensor; the field is divergence-free)."""
+    h = 2 * np.pi / n
+    c = (np.arange(n) + 0.5) * h
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    u, v, w = np.sin(Y), np.sin(Z), np.sin(X)
+    one = np.ones_like(X)
+    Q = np.stack([one, u, v, w, 1.0 / (gamma - 1.0) + 0.5 * (u * u + v * v + w * w)])
+    mu = 0.01
+    exact = np.stack([0 * X, mu * np.sin(Y), mu * np.sin(Z), mu * np.sin(X),
+                      -mu * (np.cos(2 * X) + np.cos(2 * Y) + np.cos(2 * Z))])
+    return Q, exact, (h, h, h), mu
+
+
+def test_viscous_residual_fourth_order_and_freestream():
+    errs = []
+    for n in (16, 32, 64):
+        Q, exact, h, mu = _shear_field(n)
+        Rv = ho.viscous_residual_periodic(Q, h, 1.4, 0.72, mu, 0.38)     # T = 1: mu(T) = mu_inf
+        errs.append(np.max(np.abs(Rv - exact)))
+    orders = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) > 3.8, (errs, orders)
+    from paper_1710_09995_amd import cases
+    q = cases.uniform_state((8, 6, 5), cases.Params(mach=0.6))
+    assert np.max(np.abs(ho.viscous_residual_periodic(q, (0.1, 0.2, 0.3), 1.4, 0.72, 0.01, 0.38))) <= 1e-14
+
+
+def test_viscous_residual_conduction_fourth_order():
+    """rho = 1, u = 0, T = p = 1 + 0.1 sin x: only conduction, with Sutherland's
+    mu(T): the energy entry of -div F_v is -(k(T) T')' with
+    k = mu(T) gamma / ((gamma - 1) Pr); the exact value by central differences
+    of the closed-form k(T(x)) T'(x) (step 1e-5)."""
+    g, pr, mu0, s = 1.4, 0.72, 0.01, 0.38
+
+    def flux(x):
+        T = 1 + 0.1 * np.sin(x)
+        mu = mu0 * T * np.sqrt(T) * (1 + s) / (T + s)
+        return mu * g / ((g - 1) * pr) * 0.1 * np.cos(x)
+    errs = []
+    for n in (16, 32, 64):
+        h = 2 * np.pi / n
+        c = (np.arange(n) + 0.5) * h
+        Z, Y, X = np.meshgrid(c[:4], c[:4], c, indexing="ij")
+        T = 1 + 0.1 * np.sin(X)
+        Q = np.stack([np.ones_like(X), 0 * X, 0 * X, 0 * X, T / (g - 1)])
+        Rv = ho.viscous_residual_periodic(Q, (h, 2 * np.pi / 4, 2 * np.pi / 4), g, pr, mu0, s)
+        e = 1e-5
+        exact = -(flux(X + e) - flux(X - e)) / (2 * e)
+        errs.append(max(np.max(np.abs(Rv[4] - exact)), np.max(np.abs(Rv[:4]))))
+    orders = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) > 3.8, (errs, orders)
