@@ -203,7 +203,8 @@ def bench_wcns5_euler(a) -> int:
     faces, Eq. 2 with the running sum), i.e. the intermediates' HBM traffic."""
     import numpy as np
     import torch
-    from paper_1710_09995_amd.binding import wcns5_euler_residual_periodic
+    from paper_1710_09995_amd.binding import c4_viscous_add_periodic, wcns5_euler_residual_periodic
+    viscous = a.op == "ns_periodic"
     n = (256, 128, 128)
     ni, nj, nk = n
     cells = ni * nj * nk
@@ -223,14 +224,20 @@ def bench_wcns5_euler(a) -> int:
     nb = C.c_size_t()
     B._check(B.lib().cfd_wcns5_euler_work_bytes((C.c_int32 * 3)(ni, nj, nk), C.byref(nb)))
     work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    vwork = torch.empty(8 * 20 * cells, dtype=torch.uint8, device="cuda") if viscous else None
+
+    def residual():
+        wcns5_euler_residual_periodic(q, h, out=out, work=work)
+        if viscous:
+            c4_viscous_add_periodic(q, out, h, 1.4, 0.72, 1e-3, 110.4 / 288.15, work=vwork)
     stream = torch.cuda.current_stream()
     for _ in range(a.warmup):
-        wcns5_euler_residual_periodic(q, h, out=out, work=work)
+        residual()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(a.steps):
-        wcns5_euler_residual_periodic(q, h, out=out, work=work)
+        residual()
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / a.steps
@@ -239,17 +246,22 @@ def bench_wcns5_euler(a) -> int:
         P = cells // n[d] * (n[d] + 10)
         F = cells // n[d] * (n[d] + 5)
         nbytes += 8 * 5 * ((cells + P) + (P + 2 * F) + (2 * F + F) + (F + cells * (1 if d == 0 else 2)))
+    if viscous:   # phi (Q in, 4 out), gradients (4 in, 12 out), per direction faces (16 in, 4 out) and the sum
+        nbytes += 8 * cells * ((5 + 4) + (4 + 12) + 3 * ((4 + 8) + 4) + 3 * (4 + 8))
     achieved = nbytes / (ms / 1e3) / 1e9
     print(json.dumps({
-        "metric": "Mcell/s of the periodic inviscid WCNS-E-5 residual (three directions)",
+        "metric": "Mcell/s of the periodic " + ("Navier-Stokes (WCNS-E-5 inviscid + fourth-order viscous)"
+                                                if viscous else "inviscid WCNS-E-5") + " residual (three directions)",
         "value": round(cells / (ms / 1e3) / 1e6, 1), "unit": "Mcell/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded smooth periodic flow)",
-        "config": {"workload": "wcns5_euler_periodic_256x128x128"},
+        "config": {"workload": ("ns_wcns5_c4_periodic" if viscous else "wcns5_euler_periodic") + "_256x128x128"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "pipeline: k_pad_prim_periodic, k_window6_*<Wcns5Op>, k_roe_faces, "
-                               "k_window6_*<Eq2OpT>", "mean_ms": round(ms, 4), "pipeline_bytes": nbytes},
+                               "k_window6_*<Eq2OpT>" + (", k_c4_phi, k_c4_grads, k_c4_visc_faces, k_c4_flux_sub"
+                                                        if viscous else ""),
+                     "mean_ms": round(ms, 4), "pipeline_bytes": nbytes},
         "cpu_baseline": None}), flush=True)
     return 0
 
@@ -278,11 +290,12 @@ def main(argv=None):
                     help="with --split: cut positions snap to multiples of these (1,1,1 = plain bisection)")
     ap.add_argument("--groups", type=int, default=8,
                     help="with --split: groups (devices) the pieces are regrouped into for the balance report")
-    ap.add_argument("--op", default=None, choices=["diff6", "wcns5", "wcns5_euler"],
+    ap.add_argument("--op", default=None, choices=["diff6", "wcns5", "wcns5_euler", "ns_periodic"],
                     help="time one operator instead of the solver, on a 256x128x128 block, 5 variables, each "
                          "direction: diff6 = the sixth-order staggered flux difference (Section 2.2, Eq. 2); "
                          "wcns5 = the WCNS-E-5 weighted cell-edge interpolation; wcns5_euler = the periodic "
-                         "inviscid WCNS-E-5 residual (all three directions)")
+                         "inviscid WCNS-E-5 residual (all three directions); ns_periodic = that residual plus the "
+                         "fourth-order central viscous terms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (HBM counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -296,7 +309,7 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n * 8, "copies": 5}), flush=True)
         return 0
-    if a.op == "wcns5_euler" and a.gpus == 1:
+    if a.op in ("wcns5_euler", "ns_periodic") and a.gpus == 1:
         return bench_wcns5_euler(a)
     if a.op is not None and a.gpus == 1:
         return bench_op(a)

@@ -318,6 +318,27 @@ cfd_status cfd_wcns5_euler_residual_periodic(const double* q_dev, double* r_dev,
  * nsteps >= 0, the other arguments as for the residual; a short workspace
  * gives CFD_ENOMEM.  Asynchronous on stream. */
 cfd_status cfd_wcns5_euler_step_work_bytes(const int32_t n[3], size_t* bytes);
+
+/* Viscous terms by fourth-order central differencing, which Section 2.2
+ * chooses for the viscous flux derivatives (the paper prints no formulas;
+ * these are the textbook fourth-order forms on a uniform grid, exact for
+ * cubics): on one block periodic in all three directions, adds -div F_v to
+ * r_dev (so that after cfd_wcns5_euler_residual_periodic, r is the
+ * Navier-Stokes residual, dQ/dt = -R).  (u, v, w, T) and their cell
+ * gradients by the central derivative (f_{-2} - 8 f_{-1} + 8 f_1 - f_2) / 12h;
+ * at each face the values by (-f_{-1} + 9 f_0 + 9 f_1 - f_2) / 16 (transverse
+ * gradients likewise), the normal derivative by
+ * (f_{-1} - 27 f_0 + 27 f_1 - f_2) / 24h; the stress with Stokes' hypothesis,
+ * Sutherland's viscosity mu_inf T^1.5 (1 + s_star) / (T + s_star), conduction
+ * mu gamma / ((gamma - 1) prandtl); -div by the staggered difference
+ * (F_{-3/2} - 27 F_{-1/2} + 27 F_{1/2} - F_{3/2}) / 24h.
+ * q_dev, r_dev: [5][nk][nj][ni] dense FP64; work_dev:
+ * cfd_c4_viscous_work_bytes() bytes.  All the caller's, pairwise disjoint.
+ * Asynchronous on stream. */
+cfd_status cfd_c4_viscous_work_bytes(const int32_t n[3], size_t* bytes);
+cfd_status cfd_c4_viscous_add_periodic(const double* q_dev, double* r_dev, void* work_dev, size_t work_bytes,
+                                       const int32_t n[3], const double h[3], double gamma, double prandtl,
+                                       double mu_inf, double s_star, hipStream_t stream);
 cfd_status cfd_wcns5_euler_steps_periodic(double* q_dev, void* work_dev, size_t work_bytes, const int32_t n[3],
                                           const double h[3], double gamma, double entropy_fix, double eps, double dt,
                                           int32_t nsteps, hipStream_t stream);

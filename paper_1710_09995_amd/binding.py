@@ -65,7 +65,7 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_mlp_to_bf16", "cfd_mlp_features", "cfd_mlp_targets", "cfd_mlp_to_state",
            "cfd_split_plan", "cfd_split_tables", "cfd_regroup", "cfd_staggered_diff6", "cfd_wcns5_edges",
            "cfd_wcns5_euler_work_bytes", "cfd_wcns5_euler_residual_periodic", "cfd_wcns5_euler_step_work_bytes",
-           "cfd_wcns5_euler_steps_periodic",
+           "cfd_wcns5_euler_steps_periodic", "cfd_c4_viscous_work_bytes", "cfd_c4_viscous_add_periodic",
            "cfd_status_string", "cfd_last_error"]
 
 _lib = None
@@ -120,6 +120,9 @@ def lib(build_if_missing: bool = True):
     L.cfd_wcns5_euler_residual_periodic.argtypes = [vp, vp, vp, C.c_size_t, i32p, C.POINTER(C.c_double), C.c_double,
                                                     C.c_double, C.c_double, vp]
     L.cfd_wcns5_euler_step_work_bytes.argtypes = [i32p, C.POINTER(C.c_size_t)]
+    L.cfd_c4_viscous_work_bytes.argtypes = [i32p, C.POINTER(C.c_size_t)]
+    L.cfd_c4_viscous_add_periodic.argtypes = [vp, vp, vp, C.c_size_t, i32p, C.POINTER(C.c_double), C.c_double,
+                                              C.c_double, C.c_double, C.c_double, vp]
     L.cfd_wcns5_euler_steps_periodic.argtypes = [vp, vp, C.c_size_t, i32p, C.POINTER(C.c_double), C.c_double,
                                                  C.c_double, C.c_double, C.c_double, i32, vp]
     L.cfd_status_string.argtypes = [i32]
@@ -283,6 +286,28 @@ def wcns5_euler_steps_periodic(q, h, dt: float, nsteps: int, gamma: float = 1.4,
                                                 float(entropy_fix), float(eps), float(dt), int(nsteps),
                                                 _stream_handle(torch, stream)))
     return q
+
+
+def c4_viscous_add_periodic(q, r, h, gamma: float = 1.4, prandtl: float = 0.72, mu_inf: float = 1e-3,
+                            s_star: float = 110.4 / 288.15, work=None, stream=None):
+    """Adds -div F_v (fourth-order central, periodic Cartesian block) to r on
+    the device (cfd_c4_viscous_add_periodic); q, r: contiguous FP64 CUDA
+    tensors [5, nk, nj, ni].  Returns r."""
+    import torch
+    for t in (q, r):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 4 or t.shape[0] != 5:
+            raise ValueError("q and r must be contiguous float64 CUDA tensors [5, nk, nj, ni]")
+    nk, nj, ni = (int(v) for v in q.shape[1:])
+    nn = (C.c_int32 * 3)(ni, nj, nk)
+    nbytes = C.c_size_t()
+    _check(lib().cfd_c4_viscous_work_bytes(nn, C.byref(nbytes)))
+    if work is None or work.numel() * work.element_size() < nbytes.value:
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+    hh = (C.c_double * 3)(*[float(v) for v in h])
+    _check(lib().cfd_c4_viscous_add_periodic(_ptr(q), _ptr(r), _ptr(work), nbytes.value, nn, hh, float(gamma),
+                                             float(prandtl), float(mu_inf), float(s_star),
+                                             _stream_handle(torch, stream)))
+    return r
 
 
 class Solver:

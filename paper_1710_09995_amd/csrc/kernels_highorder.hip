@@ -408,3 +408,161 @@ extern "C" cfd_status cfd_wcns5_euler_steps_periodic(double* q_dev, void* work_d
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   });
 }
+
+// ------------------------------------------- fourth-order central viscous terms
+// The paper takes the viscous flux derivatives by fourth-order central
+// differencing; on a uniform periodic grid the textbook forms, all exact for
+// cubics: cell derivative (f_{i-2} - 8 f_{i-1} + 8 f_{i+1} - f_{i+2}) / 12h,
+// face value (-f_{i-1} + 9 f_i + 9 f_{i+1} - f_{i+2}) / 16, face derivative
+// (f_{i-1} - 27 f_i + 27 f_{i+1} - f_{i+2}) / 24h, and the flux difference
+// (F_{i-3/2} - 27 F_{i-1/2} + 27 F_{i+1/2} - F_{i+3/2}) / 24h, a face array
+// holding face i + 1/2 at index i.  Stress, Sutherland viscosity and
+// conduction as in the finite-volume path.
+namespace cfd {
+
+struct Cells3 {
+  int n[3];
+  __device__ __forceinline__ int64_t at(int i, int j, int k) const {
+    return ((int64_t)k * n[1] + j) * n[0] + i;
+  }
+  // index of the cell s steps from (i, j, k) along d, periodic
+  __device__ __forceinline__ int64_t step(int i, int j, int k, int d, int s) const {
+    int c[3] = {i, j, k};
+    c[d] = ((c[d] + s) % n[d] + n[d]) % n[d];
+    return at(c[0], c[1], c[2]);
+  }
+};
+
+__global__ void __launch_bounds__(256) k_c4_phi(const double* __restrict__ q, double* __restrict__ phi, int64_t cells,
+                                                double gm1) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += (int64_t)gridDim.x * blockDim.x) {
+    const Prim<double> p = to_prim<double>(q[t], q[cells + t], q[2 * cells + t], q[3 * cells + t], q[4 * cells + t],
+                                           gm1);
+    phi[t] = p.u;
+    phi[cells + t] = p.v;
+    phi[2 * cells + t] = p.w;
+    phi[3 * cells + t] = p.p / p.r;
+  }
+}
+
+// g[(a * 3 + t) * cells + c] = d phi_a / d x_t at cell c.
+__global__ void __launch_bounds__(256) k_c4_grads(const double* __restrict__ phi, double* __restrict__ g, Cells3 C,
+                                                  double ih0, double ih1, double ih2) {
+  const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
+  const double ih[3] = {ih0, ih1, ih2};
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
+    for (int t = 0; t < 3; ++t) {
+      const int64_t m2 = C.step(i, j, k, t, -2), m1 = C.step(i, j, k, t, -1), p1 = C.step(i, j, k, t, 1),
+                    p2 = C.step(i, j, k, t, 2);
+      for (int a = 0; a < 4; ++a) {
+        const double* f = phi + a * cells;
+        g[(a * 3 + t) * cells + c] = (f[m2] - 8.0 * f[m1] + 8.0 * f[p1] - f[p2]) * (ih[t] / 12.0);
+      }
+    }
+  }
+}
+
+// Viscous flux (momentum x, y, z and energy) through face i + 1/2 along d,
+// stored at the index of cell i.
+__global__ void __launch_bounds__(256) k_c4_visc_faces(const double* __restrict__ phi, const double* __restrict__ g,
+                                                       double* __restrict__ fv, Cells3 C, int d, double ihd,
+                                                       Gas<double> gas) {
+  const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
+    const int64_t m1 = C.step(i, j, k, d, -1), p1 = C.step(i, j, k, d, 1), p2 = C.step(i, j, k, d, 2);
+    double pf[4], grad[4][3];
+    for (int a = 0; a < 4; ++a) {
+      const double* f = phi + a * cells;
+      pf[a] = (-f[m1] + 9.0 * f[c] + 9.0 * f[p1] - f[p2]) / 16.0;
+      for (int t = 0; t < 3; ++t) {
+        if (t == d) {
+          grad[a][t] = (f[m1] - 27.0 * f[c] + 27.0 * f[p1] - f[p2]) * (ihd / 24.0);
+        } else {
+          const double* gt = g + (a * 3 + t) * cells;
+          grad[a][t] = (-gt[m1] + 9.0 * gt[c] + 9.0 * gt[p1] - gt[p2]) / 16.0;
+        }
+      }
+    }
+    const double T = pf[3];
+    const double mu = gas.mu_inf * T * sqrt(T) * (1.0 + gas.s_star) / (T + gas.s_star);
+    const double kc = mu * gas.kfac;
+    const double div = grad[0][0] + grad[1][1] + grad[2][2];
+    double tau[3];
+    for (int b = 0; b < 3; ++b) tau[b] = mu * (grad[d][b] + grad[b][d]);
+    tau[d] = tau[d] - (2.0 / 3.0) * mu * div;
+    fv[c] = tau[0];
+    fv[cells + c] = tau[1];
+    fv[2 * cells + c] = tau[2];
+    fv[3 * cells + c] = pf[0] * tau[0] + pf[1] * tau[1] + pf[2] * tau[2] + kc * grad[3][d];
+  }
+}
+
+// r[1 + v] -= (F_{i-3/2} - 27 F_{i-1/2} + 27 F_{i+1/2} - F_{i+3/2}) / 24h, v = 0..3.
+__global__ void __launch_bounds__(256) k_c4_flux_sub(const double* __restrict__ fv, double* __restrict__ r, Cells3 C,
+                                                     int d, double ihd) {
+  const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
+    const int64_t m2 = C.step(i, j, k, d, -2), m1 = C.step(i, j, k, d, -1), p1 = C.step(i, j, k, d, 1);
+    for (int v = 0; v < 4; ++v) {
+      const double* F = fv + v * cells;
+      r[(1 + v) * cells + c] -= (F[m2] - 27.0 * F[m1] + 27.0 * F[c] - F[p1]) * (ihd / 24.0);
+    }
+  }
+}
+
+}  // namespace cfd
+
+extern "C" cfd_status cfd_c4_viscous_work_bytes(const int32_t n[3], size_t* bytes) {
+  return cfd::host_guarded([&] {
+    if (!n || !bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    *bytes = (size_t)8 * 20 * ((size_t)n[0] * n[1] * n[2]);      // phi (4), gradients (12), face flux (4)
+  });
+}
+
+extern "C" cfd_status cfd_c4_viscous_add_periodic(const double* q_dev, double* r_dev, void* work_dev,
+                                                  size_t work_bytes, const int32_t n[3], const double h[3],
+                                                  double gamma, double prandtl, double mu_inf, double s_star,
+                                                  hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!q_dev || !r_dev || !work_dev || !n || !h) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    for (int d = 0; d < 3; ++d)
+      if (!(h[d] > 0.0) || !std::isfinite(h[d])) cfd::host_fail(CFD_EINVAL, "spacings must be positive and finite");
+    if (!(gamma > 1.0) || !(prandtl > 0.0) || !(mu_inf >= 0.0) || !(s_star > 0.0) || !std::isfinite(mu_inf))
+      cfd::host_fail(CFD_EINVAL, "bad gas parameters");
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    const size_t need = (size_t)8 * 20 * cells;
+    if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_c4_viscous_work_bytes()");
+    auto apart = [](const void* a, int64_t na, const void* b, int64_t nb) {
+      const char *a0 = static_cast<const char*>(a), *b0 = static_cast<const char*>(b);
+      return a0 + na <= b0 || b0 + nb <= a0;
+    };
+    if (!apart(q_dev, 40 * cells, r_dev, 40 * cells) || !apart(q_dev, 40 * cells, work_dev, (int64_t)need) ||
+        !apart(r_dev, 40 * cells, work_dev, (int64_t)need))
+      cfd::host_fail(CFD_EINVAL, "q, r and the workspace must not overlap");
+    double* phi = static_cast<double*>(work_dev);
+    double* g = phi + 4 * cells;
+    double* fv = g + 12 * cells;
+    cfd::Cells3 C{{n[0], n[1], n[2]}};
+    cfd::Gas<double> gas{};
+    gas.gamma = gamma;
+    gas.gm1 = gamma - 1.0;
+    gas.mu_inf = mu_inf;
+    gas.s_star = s_star;
+    gas.prandtl = prandtl;
+    gas.kfac = gamma / ((gamma - 1.0) * prandtl);
+    const int gr = cfd::grid_for(cells);
+    hipLaunchKernelGGL(cfd::k_c4_phi, dim3(gr), dim3(256), 0, stream, q_dev, phi, cells, gamma - 1.0);
+    hipLaunchKernelGGL(cfd::k_c4_grads, dim3(gr), dim3(256), 0, stream, phi, g, C, 1.0 / h[0], 1.0 / h[1], 1.0 / h[2]);
+    for (int d = 0; d < 3; ++d) {
+      hipLaunchKernelGGL(cfd::k_c4_visc_faces, dim3(gr), dim3(256), 0, stream, phi, g, fv, C, d, 1.0 / h[d], gas);
+      hipLaunchKernelGGL(cfd::k_c4_flux_sub, dim3(gr), dim3(256), 0, stream, fv, r_dev, C, d, 1.0 / h[d]);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  });
+}

@@ -189,3 +189,19 @@ def test_wcns5_steps_bad_arguments():
         a.update(kw)
         st = L.cfd_wcns5_euler_steps_periodic(a["q"], a["w"], a["wb"], n, h, 1.4, 0.1, 1e-6, a["dt"], a["ns"], None)
         assert st == st_want, kw
+
+
+def test_c4_viscous_bad_arguments():
+    L = B.lib()
+    n = (C.c_int32 * 3)(8, 4, 2)
+    nb = C.c_size_t()
+    assert L.cfd_c4_viscous_work_bytes(n, C.byref(nb)) == 0 and nb.value == 8 * 20 * 64
+    q, r, w = C.c_void_p(0x100000), C.c_void_p(0x900000), C.c_void_p(0x1100000)
+    h = (C.c_double * 3)(0.1, 0.1, 0.1)
+    for st_want, kw in ((-2, dict(wb=nb.value - 8)), (-1, dict(pr=0.0)), (-1, dict(mu=-1.0)), (-1, dict(r=q)),
+                        (-1, dict(g=1.0))):
+        a = dict(q=q, r=r, w=w, wb=nb.value, g=1.4, pr=0.72, mu=1e-3)
+        a.update(kw)
+        st = L.cfd_c4_viscous_add_periodic(a["q"], a["r"], a["w"], a["wb"], n, h, a["g"], a["pr"], a["mu"], 0.38,
+                                           None)
+        assert st == st_want, kw

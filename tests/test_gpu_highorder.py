@@ -214,3 +214,40 @@ def test_wcns5_steps_parity_and_freestream():
     qu = np.ascontiguousarray(cases.uniform_state((12, 12, 6), c.params))
     got = wcns5_euler_steps_periodic(torch.from_numpy(qu.copy()).cuda(), (0.3, 0.3, 0.5), 0.05, 4).cpu().numpy()
     assert np.max(np.abs(got - qu)) <= 1e-12
+
+
+# ------------------------------------------ fourth-order central viscous terms
+
+@pytest.mark.parametrize("n", [(20, 12, 6), (9, 7, 11)])
+def test_c4_viscous_parity(n):
+    """-div F_v added to a residual on the device against the oracle (a smooth
+    periodic flow with varying temperature), and the full Navier-Stokes
+    residual = inviscid WCNS-E-5 + viscous."""
+    import torch
+    from paper_1710_09995_amd.binding import c4_viscous_add_periodic, wcns5_euler_residual_periodic
+    q = _smooth_state(n, seed=2 + n[0])
+    h = (1.0 / n[0], 1.0 / n[1], 1.0 / n[2])
+    mu0, s = 0.02, 0.38
+    qd = torch.from_numpy(q).cuda()
+    r = torch.zeros_like(qd)
+    got = c4_viscous_add_periodic(qd, r, h, 1.4, 0.72, mu0, s).cpu().numpy()
+    want = ho.viscous_residual_periodic(q, h, 1.4, 0.72, mu0, s)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    rn = wcns5_euler_residual_periodic(qd, h)
+    got = c4_viscous_add_periodic(qd, rn, h, 1.4, 0.72, mu0, s).cpu().numpy()
+    want = ho.wcns5_euler_residual_periodic(q, h, 1.4, 0.1) + ho.viscous_residual_periodic(q, h, 1.4, 0.72, mu0, s)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_c4_viscous_fourth_order_gpu():
+    """The closed-form shear field of the oracle's pins, on the device."""
+    import torch
+    from paper_1710_09995_amd.binding import c4_viscous_add_periodic
+    from test_oracle_highorder import _shear_field
+    errs = []
+    for n in (16, 32, 64):
+        Q, exact, h, mu = _shear_field(n)
+        qd = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+        Rv = c4_viscous_add_periodic(qd, torch.zeros_like(qd), h, 1.4, 0.72, mu, 0.38).cpu().numpy()
+        errs.append(np.max(np.abs(Rv - exact)))
+    assert min(np.log2(errs[i] / errs[i + 1]) for i in range(2)) > 3.8
