@@ -19,7 +19,13 @@ Test infrastructure, like the rest of this package.  Two operators:
    (viscous_residual_periodic): the textbook fourth-order cell derivative,
    face value, face derivative and staggered flux difference on a periodic
    Cartesian block, with the stress tensor, Sutherland viscosity and
-   conduction of the finite-volume path.
+   conduction of the finite-volume path;
+6. curvilinear periodic blocks (metrics6, wcns5_euler_residual_curv_periodic):
+   face metrics in the symmetric conservative form built from Eq. (2) and a
+   sixth-order mid-point interpolation, so that the discrete metric
+   identities hold and a uniform stream is preserved (the geometric
+   conservation law the paper requires, whose formulas are in its reference;
+   the reading is stated at the section below).
 
 Section 2.2, Eq. (2): the cell-centred derivative of a face-centred flux F
 along one index direction with grid size h,
@@ -184,3 +190,109 @@ def viscous_residual_periodic(Q: np.ndarray, h, gamma: float, prandtl: float, mu
         for c in range(4):
             Rv[1 + c] = Rv[1 + c] - c4_flux_diff(Fv[c], ax, h[d])
     return Rv
+
+
+# ------------------------------------------------------- curvilinear blocks
+# Section 2.2 requires, for curvilinear multi-block grids, the geometric
+# conservation law of the scheme's reference, without printing its metrics.
+# The reading taken here.  Vertex v along a direction sits at index position
+# v + 1/2 (the upper corner of cell v); cell centres and solution points sit
+# at integer positions.  Every derivative is Eq. (2) with h = 1 (index units)
+# and every mid-point value the sixth-order interpolation
+#     I f = [150 (f_{+1/2} + f_{-1/2}) - 25 (f_{+3/2} + f_{-3/2})
+#            + 3 (f_{+5/2} + f_{-5/2})] / 256,
+# both taken from vertex positions to the centre position along one axis.
+# The face metrics (grad xi_d / J at the faces of direction d, one area vector
+# per face) take the symmetric conservative form
+#     S_d = 1/2 [ D_b (D_a X x I_a X) - D_a (D_b X x I_b X) ],
+# (a, b) = (d + 1, d + 2) mod 3, which is X_a x X_b of the continuous map.
+# Because D and I along different axes commute, sum_d D_d S_d = 0 holds at
+# every cell to rounding, so a uniform stream stays uniform on any grid.  The
+# cell Jacobian J^{-1} is det[X_xi, X_eta, X_zeta] at the centre, each column
+# D along its axis of the coordinates interpolated (I) along the other two; it
+# plays no part in freestream preservation.  The residual is
+#     R = J sum_d D_d( Roe(W_L, W_R; S_d) ),
+# Roe's flux through the face's area vector (flux times |S_d|) from the
+# WCNS-E-5 edge states, dQ/dt = -R.  On a uniform Cartesian grid S_d and
+# J^{-1} reduce to the face areas and the cell volume, and R to the
+# Cartesian residual above.
+
+I1, I2, I3 = 150.0 / 256.0, -25.0 / 256.0, 3.0 / 256.0
+
+
+def _win(f, ax, s, m):
+    sl = [slice(None)] * f.ndim
+    sl[ax] = slice(s, s + m)
+    return f[tuple(sl)]
+
+
+def d6(f, ax):
+    """Eq. (2) with h = 1 along array axis ax: m + 5 vertex values -> m centres."""
+    m = f.shape[ax] - 5
+    w = [_win(f, ax, s, m) for s in range(6)]
+    return C1 * (w[3] - w[2]) + C2 * (w[4] - w[1]) + C3 * (w[5] - w[0])
+
+
+def i6(f, ax):
+    """Sixth-order mid-point interpolation along axis ax: m + 5 vertex values -> m centres."""
+    m = f.shape[ax] - 5
+    w = [_win(f, ax, s, m) for s in range(6)]
+    return I1 * (w[3] + w[2]) + I2 * (w[4] + w[1]) + I3 * (w[5] + w[0])
+
+
+def _ax(d):
+    return 3 - d                       # array axis of direction d in [3, k, j, i]
+
+
+def metrics6(Xe: np.ndarray):
+    """Xe: [3, nk + 5, nj + 5, ni + 5] vertex coordinates, vertices -3 .. n + 1
+    along each direction.  Returns (S, Jinv): S [3 (direction d), 3 (x, y, z),
+    nk, nj, ni], the area vector of face v + 1/2 of direction d at index v
+    along d; Jinv [nk, nj, ni] at the cell centres."""
+    n = [Xe.shape[3] - 5, Xe.shape[2] - 5, Xe.shape[1] - 5]
+    A = [np.cross(d6(Xe, _ax(a)), i6(Xe, _ax(a)), axis=0) for a in range(3)]
+    S = []
+    for d in range(3):
+        a, b = (d + 1) % 3, (d + 2) % 3
+        s = 0.5 * (d6(A[a], _ax(b)) - d6(A[b], _ax(a)))
+        S.append(_win(s, _ax(d), 3, n[d]))                # vertices 0 .. n - 1 along d
+    cols = []
+    for d in range(3):
+        a, b = (d + 1) % 3, (d + 2) % 3
+        cols.append(d6(i6(i6(Xe, _ax(a)), _ax(b)), _ax(d)))
+    Jinv = np.sum(cols[0] * np.cross(cols[1], cols[2], axis=0), axis=0)
+    return np.stack(S), Jinv
+
+
+def periodic_vertices(Xv: np.ndarray, P: np.ndarray) -> np.ndarray:
+    """Xv: [3, nk, nj, ni] vertex coordinates of a block periodic along every
+    direction (vertex (i, j, k) is the upper corner of cell (i, j, k)); P[d]:
+    the displacement of the grid over one period along direction d.  Returns
+    the vertices -3 .. n + 1 along each direction (metrics6's input)."""
+    nk, nj, ni = Xv.shape[1:]
+    idx = [np.arange(-3, m + 2) for m in (ni, nj, nk)]
+    wi, wj, wk = (idx[0] % ni, idx[1] % nj, idx[2] % nk)
+    qi, qj, qk = (idx[0] // ni, idx[1] // nj, idx[2] // nk)
+    X = Xv[:, wk][:, :, wj][:, :, :, wi]
+    P = np.asarray(P, dtype=np.float64)
+    return (X + qi[None, None, None, :] * P[0][:, None, None, None]
+            + qj[None, None, :, None] * P[1][:, None, None, None]
+            + qk[None, :, None, None] * P[2][:, None, None, None])
+
+
+def wcns5_euler_residual_curv_periodic(Q: np.ndarray, S: np.ndarray, Jinv: np.ndarray, gamma: float,
+                                       eps_h: float, eps: float = 1e-6) -> np.ndarray:
+    """Q: [5, nk, nj, ni] conserved point values of a periodic curvilinear
+    block; S, Jinv from metrics6.  Returns R (dQ/dt = -R)."""
+    from .flux import primitives, roe_flux
+    W = primitives(Q, gamma)
+    R = np.zeros_like(Q)
+    for d in range(3):
+        ax = _ax(d)
+        n = W.shape[ax]
+        Wp = np.take(W, np.arange(-5, n + 5) % n, axis=ax)
+        WL, WR = wcns5_edge(Wp, d, eps)                      # faces of vertices -3 .. n + 1
+        Sd = np.take(S[d], np.arange(-3, n + 2) % n, axis=ax)
+        F = roe_flux(WL, WR, Sd, gamma, eps_h)
+        R = R + staggered_diff6(F, d, 1.0)
+    return R / Jinv

@@ -8,6 +8,11 @@ Eq. (2), on the CPU.
   rounding), along each axis, for any grid size and origin.
 * On xi^7 the error at xi = 0 is the closed form 2 h^6 / 2^7 * 225 = 225/64 h^6.
 * On a sine the error falls as h^6.
+
+Curvilinear metrics and residual: exact cofactors and determinant for a cubic
+map; a uniform stream preserved to rounding on a wavy grid (and not with
+non-conservative metrics); exact reduction to the Cartesian residual;
+rotation equivariance; fourth-order convergence of the vortex on a wavy grid.
 """
 import os
 from fractions import Fraction
@@ -334,3 +339,172 @@ def test_viscous_residual_conduction_fourth_order():
         errs.append(max(np.max(np.abs(Rv[4] - exact)), np.max(np.abs(Rv[:4]))))
     orders = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(orders) > 3.8, (errs, orders)
+
+
+# -------------------------------------- curvilinear metrics and residual
+
+def _cubic_map(s):
+    """A non-affine map of total degree 3 from index positions s = (xi, eta,
+    zeta) to (x, y, z), and its Jacobian columns written out by hand."""
+    a, b, c = s
+    x = 1.0 * a + 0.1 * b + 0.05 * a * b + 0.02 * c * c + 0.003 * a * b * c + 0.001 * a ** 3
+    y = 0.2 * a + 1.1 * b - 0.04 * c * a + 0.002 * b ** 3 + 0.01 * b * b
+    z = 0.05 * a * a + 0.9 * c + 0.03 * a * b + 0.002 * c ** 3 - 0.004 * a * a * b
+    Xa = np.stack([1.0 + 0.05 * b + 0.003 * b * c + 0.003 * a * a, 0.2 - 0.04 * c + 0 * a,
+                   0.1 * a + 0.03 * b - 0.008 * a * b])
+    Xb = np.stack([0.1 + 0.05 * a + 0.003 * a * c, 1.1 + 0.006 * b * b + 0.02 * b + 0 * a,
+                   0.03 * a - 0.004 * a * a])
+    Xc = np.stack([0.04 * c + 0.003 * a * b, -0.04 * a + 0 * b, 0.9 + 0.006 * c * c + 0 * a])
+    return np.stack([x, y, z]), (Xa, Xb, Xc)
+
+
+def _positions(n, shift):
+    """Index positions (xi, eta, zeta) of an [nk, nj, ni] lattice: entry v
+    along direction d sits at v + shift[d]."""
+    K, J, I = np.meshgrid(np.arange(n[2]) + shift[2], np.arange(n[1]) + shift[1], np.arange(n[0]) + shift[0],
+                          indexing="ij")
+    return (I.astype(float), J.astype(float), K.astype(float))
+
+
+def test_metrics_exact_for_a_cubic_map():
+    """Every operator in the metrics is exact on the polynomials a cubic map
+    produces, so the face area vectors equal the cofactors X_a x X_b of the
+    map at the face centres and J^{-1} its determinant at the cell centres."""
+    n = (7, 6, 5)
+    Xe, _ = _cubic_map(_positions((n[0] + 5, n[1] + 5, n[2] + 5), (-2.5, -2.5, -2.5)))
+    S, Jinv = ho.metrics6(Xe)
+    for d in range(3):
+        shift = [0.0, 0.0, 0.0]
+        shift[d] = 0.5
+        _, cols = _cubic_map(_positions(n, shift))
+        want = np.cross(cols[(d + 1) % 3], cols[(d + 2) % 3], axis=0)
+        assert np.max(np.abs(S[d] - want)) <= 1e-12
+    _, cols = _cubic_map(_positions(n, (0.0, 0.0, 0.0)))
+    det = np.sum(cols[0] * np.cross(cols[1], cols[2], axis=0), axis=0)
+    assert np.max(np.abs(Jinv - det)) <= 1e-12
+
+
+def _wavy_grid(n, L, a, planar=False):
+    """Vertices of a periodic block on the box L (edge lengths along x, y, z)
+    with every coordinate displaced by a sine of the other two (a smooth,
+    non-orthogonal, non-affine grid), and the map itself.  planar: the waves
+    depend on x and y only (for blocks thin along z)."""
+    def fmap(s):
+        xb = [L[d] * s[d] / n[d] for d in range(3)]
+        w = [2 * np.pi * xb[d] / L[d] for d in range(3)]
+        if planar:
+            return np.stack([xb[0] + a * L[0] * np.sin(w[1]), xb[1] + a * L[1] * np.sin(w[0]),
+                             xb[2] + a * L[2] * np.sin(w[0]) * np.sin(w[1])])
+        return np.stack([xb[0] + a * L[0] * np.sin(w[1]) * np.sin(w[2]),
+                         xb[1] + a * L[1] * np.sin(w[2]) * np.sin(w[0]),
+                         xb[2] + a * L[2] * np.sin(w[0]) * np.sin(w[1])])
+    return fmap(_positions(n, (0.5, 0.5, 0.5))), np.diag(L), fmap
+
+
+def _naive_metrics(Xe):
+    """Face area vectors as the plain cross product X_a x X_b at the face,
+    each column differentiated along its axis after interpolating to the face:
+    the non-conservative form, for contrast."""
+    n = [Xe.shape[3] - 5, Xe.shape[2] - 5, Xe.shape[1] - 5]
+    S = []
+    for d in range(3):
+        a, b = (d + 1) % 3, (d + 2) % 3
+        Xa = ho.d6(ho.i6(Xe, ho._ax(b)), ho._ax(a))
+        Xb = ho.d6(ho.i6(Xe, ho._ax(a)), ho._ax(b))
+        S.append(ho._win(np.cross(Xa, Xb, axis=0), ho._ax(d), 3, n[d]))
+    return np.stack(S)
+
+
+def test_curvilinear_freestream_is_preserved():
+    """The geometric conservation law: a uniform stream on a strongly wavy
+    grid has R = 0 to rounding, while the same scheme with non-conservative
+    metrics does not."""
+    from paper_1710_09995_amd import cases
+    n = (12, 10, 8)
+    Xv, P, _ = _wavy_grid(n, (3.0, 2.0, 1.5), 0.08)
+    S, Jinv = ho.metrics6(ho.periodic_vertices(Xv, P))
+    assert np.min(Jinv) > 0
+    q = cases.conserved_from(np.full((n[2], n[1], n[0]), 1.2), 0.5, -0.3, 0.2, 1.0 / 1.4, 1.4)
+    R = ho.wcns5_euler_residual_curv_periodic(q, S, Jinv, 1.4, 0.1)
+    assert np.max(np.abs(R)) <= 1e-12
+    Rn = ho.wcns5_euler_residual_curv_periodic(q, _naive_metrics(ho.periodic_vertices(Xv, P)), Jinv, 1.4, 0.1)
+    assert np.max(np.abs(Rn)) >= 1e-6
+
+
+def _smooth_state(n, seed):
+    from paper_1710_09995_amd import cases
+    rng = np.random.default_rng(seed)
+    s = _positions(n, (0.0, 0.0, 0.0))
+    ph = rng.uniform(0, 2 * np.pi, 5)
+    wv = [2 * np.pi * s[d] / n[d] for d in range(3)]
+    rho = 1.0 + 0.2 * np.sin(wv[0] + ph[0]) * np.cos(wv[1] + ph[1])
+    u = 0.4 + 0.1 * np.sin(wv[1] + wv[2] + ph[2])
+    v = -0.2 + 0.1 * np.cos(wv[0] - wv[2] + ph[3])
+    w = 0.1 + 0.1 * np.sin(wv[0] + wv[1] + ph[4])
+    p = 1.0 / 1.4 + 0.05 * np.cos(wv[2] + ph[1])
+    return cases.conserved_from(rho, u, v, w, p, 1.4), (rho, u, v, w, p)
+
+
+def test_curvilinear_residual_reduces_to_cartesian():
+    n, h = (10, 9, 7), (0.3, 0.5, 0.7)
+    Xv = np.stack([(x + 0.5) * h[d] for d, x in enumerate(_positions(n, (0.5, 0.5, 0.5)))])
+    S, Jinv = ho.metrics6(ho.periodic_vertices(Xv, np.diag([n[d] * h[d] for d in range(3)])))
+    q, _ = _smooth_state(n, 1)
+    R = ho.wcns5_euler_residual_curv_periodic(q, S, Jinv, 1.4, 0.1)
+    want = ho.wcns5_euler_residual_periodic(q, h, 1.4, 0.1)
+    assert np.max(np.abs(R - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_curvilinear_residual_is_rotation_equivariant():
+    """A rotated and translated copy of a Cartesian grid, with the velocity
+    rotated alike, gives the rotated Cartesian residual: exercises every
+    component of the metric cross products and of the face normals.  The
+    nonlinear weights act on each velocity component on its own and so do not
+    commute with a rotation; eps = 1e12 makes them the linear weights (to
+    1e-14), which do."""
+    from paper_1710_09995_amd import cases
+    n, h = (9, 8, 6), (0.4, 0.3, 0.5)
+    th, ph = 0.7, -0.4
+    Rz = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+    Rx = np.array([[1, 0, 0], [0, np.cos(ph), -np.sin(ph)], [0, np.sin(ph), np.cos(ph)]])
+    Rot = Rz @ Rx
+    base = np.stack([(x + 0.5) * h[d] for d, x in enumerate(_positions(n, (0.5, 0.5, 0.5)))])
+    Xv = np.einsum("ab,bkji->akji", Rot, base) + np.array([1.0, -2.0, 0.5])[:, None, None, None]
+    P = (Rot @ np.diag([n[d] * h[d] for d in range(3)])).T          # rows: the periods, rotated
+    S, Jinv = ho.metrics6(ho.periodic_vertices(Xv, P))
+    q, (rho, u, v, w, p) = _smooth_state(n, 2)
+    vel = np.einsum("ab,bkji->akji", Rot, np.stack([u, v, w]))
+    qr = cases.conserved_from(rho, vel[0], vel[1], vel[2], p, 1.4)
+    R = ho.wcns5_euler_residual_curv_periodic(qr, S, Jinv, 1.4, 0.1, eps=1e12)
+    Rc = ho.wcns5_euler_residual_periodic(q, h, 1.4, 0.1, eps=1e12)
+    want = np.concatenate([Rc[:1], np.einsum("ab,bkji->akji", Rot, Rc[1:4]), Rc[4:]])
+    assert np.max(np.abs(R - want)) <= 1e-11 * np.max(np.abs(want))
+
+
+def test_curvilinear_residual_vortex_order_on_a_wavy_grid():
+    """The isentropic vortex sampled at the solution points of a wavy grid:
+    -R approaches the exact dQ/dt = -(u_inf . grad) Q at fourth order or
+    better (error within 3 of the vortex centre, as on the Cartesian grid)."""
+    from paper_1710_09995_amd import cases
+    par = cases.Params(mach=0.5)
+    xc, yc = 0.3, -0.4
+    uinf = cases.freestream_velocity(par)
+    errs = []
+    for m in (32, 64, 128):
+        n = (m, m, 4)
+        Xv, P, fmap = _wavy_grid(n, (10.0, 10.0, 1.0), 0.03, planar=True)
+        Xv = Xv - 5.0 * np.array([1.0, 1.0, 0.0])[:, None, None, None]
+        S, Jinv = ho.metrics6(ho.periodic_vertices(Xv, P))
+        X = fmap(_positions(n, (0.0, 0.0, 0.0))) - 5.0 * np.array([1.0, 1.0, 0.0])[:, None, None, None]
+
+        def Q(xx, yy):
+            return cases.conserved_from(*cases.isentropic_vortex_primitives(xx, yy, xc, yc, par, period=10.0),
+                                        par.gamma)
+        e = 1e-5
+        rate = -(uinf[0] * (Q(X[0] + e, X[1]) - Q(X[0] - e, X[1])) +
+                 uinf[1] * (Q(X[0], X[1] + e) - Q(X[0], X[1] - e))) / (2 * e)
+        R = ho.wcns5_euler_residual_curv_periodic(Q(X[0], X[1]), S, Jinv, 1.4, 0.1)
+        near = ((np.abs(X[0] - xc) < 3) & (np.abs(X[1] - yc) < 3))[None]
+        errs.append(np.max(np.abs(-R - rate) * near))
+    orders = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) >= 4.0, (errs, orders)
