@@ -25,7 +25,8 @@ Test infrastructure, like the rest of this package.  Two operators:
    sixth-order mid-point interpolation, so that the discrete metric
    identities hold and a uniform stream is preserved (the geometric
    conservation law the paper requires, whose formulas are in its reference;
-   the reading is stated at the section below).
+   the reading is stated at the section below), and RK3 steps on that
+   residual (wcns5_euler_steps_curv_periodic).
 
 Section 2.2, Eq. (2): the cell-centred derivative of a face-centred flux F
 along one index direction with grid size h,
@@ -296,3 +297,14 @@ def wcns5_euler_residual_curv_periodic(Q: np.ndarray, S: np.ndarray, Jinv: np.nd
         F = roe_flux(WL, WR, Sd, gamma, eps_h)
         R = R + staggered_diff6(F, d, 1.0)
     return R / Jinv
+
+
+def wcns5_euler_steps_curv_periodic(Q: np.ndarray, S: np.ndarray, Jinv: np.ndarray, gamma: float, eps_h: float,
+                                    dt: float, nsteps: int, eps: float = 1e-6) -> np.ndarray:
+    """nsteps SSP-RK3 steps (Eqs. 4-6, lambda = -dt) of dQ/dt = -R(Q) with the
+    curvilinear periodic residual and a fixed dt."""
+    from .solver import ssp_rk3
+    q = Q
+    for _ in range(nsteps):
+        q = ssp_rk3(q, dt, lambda x: wcns5_euler_residual_curv_periodic(x, S, Jinv, gamma, eps_h, eps))
+    return q

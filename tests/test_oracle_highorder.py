@@ -12,7 +12,8 @@ Eq. (2), on the CPU.
 Curvilinear metrics and residual: exact cofactors and determinant for a cubic
 map; a uniform stream preserved to rounding on a wavy grid (and not with
 non-conservative metrics); exact reduction to the Cartesian residual;
-rotation equivariance; fourth-order convergence of the vortex on a wavy grid.
+rotation equivariance; fourth-order convergence of the vortex on a wavy grid;
+RK3 steps keep a uniform stream and advect the vortex at third order.
 """
 import os
 from fractions import Fraction
@@ -508,3 +509,37 @@ def test_curvilinear_residual_vortex_order_on_a_wavy_grid():
         errs.append(np.max(np.abs(-R - rate) * near))
     orders = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(orders) >= 4.0, (errs, orders)
+
+
+def test_curvilinear_steps_freestream_and_advected_vortex():
+    """RK3 on the curvilinear residual: a uniform stream on a wavy grid stays
+    uniform to rounding, and the isentropic vortex advected to t = 0.4 on a
+    wavy grid approaches the exactly translated vortex at third order or
+    better (dt proportional to the grid size: the time scheme's order)."""
+    from paper_1710_09995_amd import cases
+    n = (12, 10, 8)
+    Xv, P, _ = _wavy_grid(n, (3.0, 2.0, 1.5), 0.08)
+    S, Jinv = ho.metrics6(ho.periodic_vertices(Xv, P))
+    q = cases.conserved_from(np.full((n[2], n[1], n[0]), 1.2), 0.5, -0.3, 0.2, 1.0 / 1.4, 1.4)
+    q1 = ho.wcns5_euler_steps_curv_periodic(q, S, Jinv, 1.4, 0.1, 0.02, 3)
+    assert np.max(np.abs(q1 - q)) <= 1e-12
+    par = cases.Params(mach=0.5)
+    uinf = cases.freestream_velocity(par)
+    xc, yc = 0.3, -0.4
+    errs = []
+    for m in (32, 64):
+        n = (m, m, 4)
+        Xv, P, fmap = _wavy_grid(n, (10.0, 10.0, 1.0), 0.03, planar=True)
+        sh = 5.0 * np.array([1.0, 1.0, 0.0])[:, None, None, None]
+        S, Jinv = ho.metrics6(ho.periodic_vertices(Xv - sh, P))
+        X = fmap(_positions(n, (0.0, 0.0, 0.0))) - sh
+
+        def Qf(cx, cy):
+            return cases.conserved_from(*cases.isentropic_vortex_primitives(X[0], X[1], cx, cy, par, period=10.0),
+                                        1.4)
+        T, steps = 0.4, m // 4
+        q = ho.wcns5_euler_steps_curv_periodic(Qf(xc, yc), S, Jinv, 1.4, 0.1, T / steps, steps)
+        cx, cy = xc + uinf[0] * T, yc + uinf[1] * T
+        near = ((np.abs(X[0] - cx) < 3) & (np.abs(X[1] - cy) < 3))[None]
+        errs.append(np.max(np.abs(q - Qf(cx, cy)) * near))
+    assert np.log2(errs[0] / errs[1]) >= 3.0, errs
