@@ -26,7 +26,10 @@ Test infrastructure, like the rest of this package.  Two operators:
    identities hold and a uniform stream is preserved (the geometric
    conservation law the paper requires, whose formulas are in its reference;
    the reading is stated at the section below), and RK3 steps on that
-   residual (wcns5_euler_steps_curv_periodic).
+   residual (wcns5_euler_steps_curv_periodic);
+7. the fourth-order viscous terms on such blocks
+   (viscous_residual_curv_periodic): the chain rule with those metrics, the
+   viscous flux through each face's area vector (reading stated below).
 
 Section 2.2, Eq. (2): the cell-centred derivative of a face-centred flux F
 along one index direction with grid size h,
@@ -308,3 +311,59 @@ def wcns5_euler_steps_curv_periodic(Q: np.ndarray, S: np.ndarray, Jinv: np.ndarr
     for _ in range(nsteps):
         q = ssp_rk3(q, dt, lambda x: wcns5_euler_residual_curv_periodic(x, S, Jinv, gamma, eps_h, eps))
     return q
+
+
+# ------------------------------- fourth-order viscous terms, curvilinear
+# The viscous terms of the fourth-order central scheme above on a periodic
+# curvilinear block with the metrics of metrics6 (reading of the paper's
+# choice of fourth-order central differencing on curvilinear grids):
+#   - index derivatives of u, v, w, T at the cells (cell derivative, h = 1);
+#   - metrics at the cells: each S_t interpolated from its faces along t
+#     (the four-point mid-point formula, from faces to the centre);
+#   - at a face of direction d: the face value of u, v, w, T; the index
+#     derivative along d by the compact face derivative, along t != d the
+#     face value of the cell derivative; S_t (t != d) the face value of the
+#     cell metrics; J^{-1} the face value of the cell J^{-1}; the physical
+#     gradient J sum_t S_t d/dxi_t (the chain rule with grad xi_t = J S_t);
+#   - the stress tensor, Sutherland viscosity and conduction as in the
+#     Cartesian terms, the viscous flux through the face's area vector S_d;
+#   - -J times the staggered flux difference, summed over directions.
+# On a uniform Cartesian grid this is the Cartesian viscous residual.
+
+def c4_face_to_cell(f, ax):
+    """Value at cell i from faces i -/+ 1/2, i -/+ 3/2 (face i + 1/2 at index i)."""
+    return (-_at(f, ax, -2) + 9.0 * _at(f, ax, -1) + 9.0 * f - _at(f, ax, 1)) / 16.0
+
+
+def viscous_residual_curv_periodic(Q: np.ndarray, S: np.ndarray, Jinv: np.ndarray, gamma: float, prandtl: float,
+                                   mu_inf: float, s_star: float) -> np.ndarray:
+    """-div F_v on a periodic curvilinear block (Q: [5, nk, nj, ni]; S, Jinv
+    from metrics6); add it to the inviscid residual (dQ/dt = -R)."""
+    from .flux import primitives, sutherland
+    W = primitives(Q, gamma)
+    phi = [W[1], W[2], W[3], W[4] / W[0]]                     # u, v, w, T
+    axis = [2, 1, 0]                                          # axis of direction d within a [k, j, i] field
+    G = [[c4_cell_deriv(phi[a], axis[t], 1.0) for t in range(3)] for a in range(4)]
+    Sc = [c4_face_to_cell(S[t], 1 + axis[t]) for t in range(3)]          # [3, k, j, i] each
+    Rv = np.zeros_like(Q)
+    for d in range(3):
+        ax = axis[d]
+        pf = [c4_face_value(phi[a], ax) for a in range(4)]
+        dxi = [[c4_face_deriv(phi[a], ax, 1.0) if t == d else c4_face_value(G[a][t], ax) for t in range(3)]
+               for a in range(4)]
+        Sf = [S[d] if t == d else c4_face_value(Sc[t], 1 + ax) for t in range(3)]
+        Jf = 1.0 / c4_face_value(Jinv, ax)
+        grad = [[Jf * (Sf[0][x] * dxi[a][0] + Sf[1][x] * dxi[a][1] + Sf[2][x] * dxi[a][2]) for x in range(3)]
+                for a in range(4)]                            # grad[a][x] = d phi_a / d x
+        mu = sutherland(pf[3], mu_inf, s_star)
+        kc = mu * gamma / ((gamma - 1.0) * prandtl)
+        div = grad[0][0] + grad[1][1] + grad[2][2]
+        tau = [[mu * (grad[x][y] + grad[y][x]) for y in range(3)] for x in range(3)]
+        for x in range(3):
+            tau[x][x] = tau[x][x] - (2.0 / 3.0) * mu * div
+        e = [pf[0] * tau[x][0] + pf[1] * tau[x][1] + pf[2] * tau[x][2] + kc * grad[3][x] for x in range(3)]
+        Fv = [S[d][0] * tau[0][m] + S[d][1] * tau[1][m] + S[d][2] * tau[2][m] for m in range(3)]
+        Fv.append(S[d][0] * e[0] + S[d][1] * e[1] + S[d][2] * e[2])
+        for c in range(4):
+            Rv[1 + c] = Rv[1 + c] - c4_flux_diff(Fv[c], ax, 1.0) / Jinv
+    return Rv

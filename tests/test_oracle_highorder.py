@@ -14,6 +14,9 @@ map; a uniform stream preserved to rounding on a wavy grid (and not with
 non-conservative metrics); exact reduction to the Cartesian residual;
 rotation equivariance; fourth-order convergence of the vortex on a wavy grid;
 RK3 steps keep a uniform stream and advect the vortex at third order.
+Curvilinear viscous terms: exact reduction to the Cartesian ones, rotation
+equivariance, fourth-order convergence of closed-form shear and conduction
+fields sampled on a wavy grid.
 """
 import os
 from fractions import Fraction
@@ -543,3 +546,68 @@ def test_curvilinear_steps_freestream_and_advected_vortex():
         near = ((np.abs(X[0] - cx) < 3) & (np.abs(X[1] - cy) < 3))[None]
         errs.append(np.max(np.abs(q - Qf(cx, cy)) * near))
     assert np.log2(errs[0] / errs[1]) >= 3.0, errs
+
+
+# ------------------------- fourth-order viscous terms on curvilinear grids
+
+def test_curvilinear_viscous_reduces_to_cartesian_and_rotates():
+    """On a uniform grid the curvilinear viscous terms equal the Cartesian
+    ones; on a rotated copy with rotated velocities they give the rotated
+    Cartesian terms (the viscous terms are linear in the gradients, so this
+    holds with any state)."""
+    from paper_1710_09995_amd import cases
+    n, h = (10, 9, 8), (0.3, 0.5, 0.7)
+    q, (rho, u, v, w, p) = _smooth_state(n, 3)
+    want = ho.viscous_residual_periodic(q, h, 1.4, 0.72, 0.02, 0.38)
+    base = np.stack([(x + 0.5) * h[d] for d, x in enumerate(_positions(n, (0.5, 0.5, 0.5)))])
+    S, Jinv = ho.metrics6(ho.periodic_vertices(base, np.diag([n[d] * h[d] for d in range(3)])))
+    got = ho.viscous_residual_curv_periodic(q, S, Jinv, 1.4, 0.72, 0.02, 0.38)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    th, ph = 0.9, 0.35
+    Rz = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+    Ry = np.array([[np.cos(ph), 0, np.sin(ph)], [0, 1, 0], [-np.sin(ph), 0, np.cos(ph)]])
+    Rot = Ry @ Rz
+    Xv = np.einsum("ab,bkji->akji", Rot, base)
+    P = (Rot @ np.diag([n[d] * h[d] for d in range(3)])).T
+    S, Jinv = ho.metrics6(ho.periodic_vertices(Xv, P))
+    vel = np.einsum("ab,bkji->akji", Rot, np.stack([u, v, w]))
+    got = ho.viscous_residual_curv_periodic(cases.conserved_from(rho, vel[0], vel[1], vel[2], p, 1.4), S, Jinv,
+                                            1.4, 0.72, 0.02, 0.38)
+    rot = np.concatenate([want[:1], np.einsum("ab,bkji->akji", Rot, want[1:4]), want[4:]])
+    assert np.max(np.abs(got - rot)) <= 1e-11 * np.max(np.abs(want))
+
+
+def test_curvilinear_viscous_fourth_order_on_a_wavy_grid():
+    """The closed-form fields of the Cartesian pins, sampled at the solution
+    points of a wavy grid of the same periodic box: -div F_v of the shear
+    field (constant viscosity) and the conduction field (Sutherland's law)
+    converge at fourth order."""
+    g, pr, mu0, s = 1.4, 0.72, 0.01, 0.38
+    L = 2 * np.pi
+
+    def kflux(x):
+        T = 1 + 0.1 * np.sin(x)
+        mu = mu0 * T * np.sqrt(T) * (1 + s) / (T + s)
+        return mu * g / ((g - 1) * pr) * 0.1 * np.cos(x)
+    err_s, err_c = [], []
+    for m in (16, 32, 64):
+        n = (m, m, m)
+        Xv, P, fmap = _wavy_grid(n, (L, L, L), 0.02)
+        S, Jinv = ho.metrics6(ho.periodic_vertices(Xv, P))
+        X, Y, Z = fmap(_positions(n, (0.0, 0.0, 0.0)))
+        u, v, w = np.sin(Y), np.sin(Z), np.sin(X)
+        one = np.ones_like(X)
+        Q = np.stack([one, u, v, w, 1.0 / (g - 1.0) + 0.5 * (u * u + v * v + w * w)])
+        exact = np.stack([0 * X, mu0 * np.sin(Y), mu0 * np.sin(Z), mu0 * np.sin(X),
+                          -mu0 * (np.cos(2 * X) + np.cos(2 * Y) + np.cos(2 * Z))])
+        Rv = ho.viscous_residual_curv_periodic(Q, S, Jinv, g, pr, mu0, 0.38)    # T = 1: mu(T) = mu_inf
+        err_s.append(np.max(np.abs(Rv - exact)))
+        T = 1 + 0.1 * np.sin(X)
+        Q = np.stack([one, 0 * X, 0 * X, 0 * X, T / (g - 1)])
+        Rv = ho.viscous_residual_curv_periodic(Q, S, Jinv, g, pr, mu0, s)
+        e = 1e-5
+        ex = -(kflux(X + e) - kflux(X - e)) / (2 * e)
+        err_c.append(max(np.max(np.abs(Rv[4] - ex)), np.max(np.abs(Rv[:4]))))
+    for errs in (err_s, err_c):
+        orders = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+        assert min(orders) > 3.7, (err_s, err_c)
