@@ -367,3 +367,30 @@ def viscous_residual_curv_periodic(Q: np.ndarray, S: np.ndarray, Jinv: np.ndarra
         for c in range(4):
             Rv[1 + c] = Rv[1 + c] - c4_flux_diff(Fv[c], ax, 1.0) / Jinv
     return Rv
+
+
+# ------------------------------------------------------------ time step
+# The paper leaves the step size of Eqs. (4)-(6) open; the reading of the
+# finite-volume path applied to these blocks: per cell
+#   dt_c = CFL J^{-1} / (sum_d L_d + 4 sum_d Lv_d),  L_d = |u . Sb_d| + c |Sb_d|,
+#   Lv_d = max(4/3, gamma/Pr) (mu/rho) |Sb_d|^2 / J^{-1} (viscous flow only),
+# Sb_d the mean of the cell's two d-face area vectors; the step is the least
+# dt_c over the block.
+
+def cfl_time_step_curv_periodic(Q: np.ndarray, S: np.ndarray, Jinv: np.ndarray, gamma: float, cfl: float,
+                                viscous: bool = False, prandtl: float = 0.72, mu_inf: float = 0.0,
+                                s_star: float = 110.4 / 288.15) -> float:
+    from .flux import primitives, sutherland
+    W = primitives(Q, gamma)
+    c = np.sqrt(gamma * W[4] / W[0])
+    lam = np.zeros_like(Jinv)
+    lamv = np.zeros_like(Jinv)
+    axis = [2, 1, 0]
+    for d in range(3):
+        Sb = 0.5 * (_at(S[d], 1 + axis[d], -1) + S[d])
+        mag = np.sqrt(np.sum(Sb * Sb, axis=0))
+        lam = lam + (np.abs(np.sum(W[1:4] * Sb, axis=0)) + c * mag)
+        if viscous:
+            mu = sutherland(W[4] / W[0], mu_inf, s_star)
+            lamv = lamv + max(4.0 / 3.0, gamma / prandtl) * (mu / W[0]) * mag * mag / Jinv
+    return float(np.min(cfl * Jinv / (lam + 4.0 * lamv)))

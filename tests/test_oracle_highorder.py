@@ -611,3 +611,34 @@ def test_curvilinear_viscous_fourth_order_on_a_wavy_grid():
     for errs in (err_s, err_c):
         orders = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
         assert min(orders) > 3.7, (err_s, err_c)
+
+
+# ------------------------------------------------------------ time step
+
+def test_cfl_time_step_closed_form_and_rotation():
+    """A uniform state on a uniform grid: dt = CFL / sum_d ((|u_d| + c)/h_d
+    + 4 max(4/3, gamma/Pr)(mu/rho)/h_d^2) (worked from the definition with
+    S_d = the face area, J^{-1} = the volume); on a rotated copy with the
+    velocity rotated alike the step is the same."""
+    from paper_1710_09995_amd import cases
+    n, h = (8, 6, 5), (0.3, 0.5, 0.7)
+    rho, vel, p, g, pr, mu0, s = 1.3, np.array([0.4, -0.7, 0.2]), 0.9, 1.4, 0.72, 0.05, 0.38
+    one = np.ones((n[2], n[1], n[0]))
+    q = cases.conserved_from(rho * one, vel[0], vel[1], vel[2], p, g)
+    base = np.stack([(x + 0.5) * h[d] for d, x in enumerate(_positions(n, (0.5, 0.5, 0.5)))])
+    S, Jinv = ho.metrics6(ho.periodic_vertices(base, np.diag([n[d] * h[d] for d in range(3)])))
+    c = np.sqrt(g * p / rho)
+    T = p / rho
+    mu = mu0 * T * np.sqrt(T) * (1 + s) / (T + s)
+    want_inv = sum((abs(vel[d]) + c) / h[d] for d in range(3))
+    want_vis = want_inv + 4 * max(4 / 3, g / pr) * (mu / rho) * sum(1 / h[d] ** 2 for d in range(3))
+    assert np.isclose(ho.cfl_time_step_curv_periodic(q, S, Jinv, g, 0.8), 0.8 / want_inv, rtol=1e-13)
+    dtv = ho.cfl_time_step_curv_periodic(q, S, Jinv, g, 0.8, True, pr, mu0, s)
+    assert np.isclose(dtv, 0.8 / want_vis, rtol=1e-13)
+    th = 0.6
+    Rot = np.array([[np.cos(th), 0, -np.sin(th)], [0, 1, 0], [np.sin(th), 0, np.cos(th)]])
+    Xv = np.einsum("ab,bkji->akji", Rot, base)
+    Sr, Jr = ho.metrics6(ho.periodic_vertices(Xv, (Rot @ np.diag([n[d] * h[d] for d in range(3)])).T))
+    vr = Rot @ vel
+    qr = cases.conserved_from(rho * one, vr[0], vr[1], vr[2], p, g)
+    assert np.isclose(ho.cfl_time_step_curv_periodic(qr, Sr, Jr, g, 0.8, True, pr, mu0, s), dtv, rtol=1e-13)
