@@ -29,7 +29,10 @@ Test infrastructure, like the rest of this package.  Two operators:
    residual (wcns5_euler_steps_curv_periodic);
 7. the fourth-order viscous terms on such blocks
    (viscous_residual_curv_periodic): the chain rule with those metrics, the
-   viscous flux through each face's area vector (reading stated below).
+   viscous flux through each face's area vector (reading stated below);
+8. the CFL time step on such blocks (cfl_time_step_curv_periodic), and
+   blocks joined face to face (wcns5_euler_residual_blocks, block_vertices):
+   the stencils run across seams with a five-cell exchange.
 
 Section 2.2, Eq. (2): the cell-centred derivative of a face-centred flux F
 along one index direction with grid size h,
@@ -394,3 +397,53 @@ def cfl_time_step_curv_periodic(Q: np.ndarray, S: np.ndarray, Jinv: np.ndarray, 
             mu = sutherland(W[4] / W[0], mu_inf, s_star)
             lamv = lamv + max(4.0 / 3.0, gamma / prandtl) * (mu / W[0]) * mag * mag / Jinv
     return float(np.min(cfl * Jinv / (lam + 4.0 * lamv)))
+
+
+# ------------------------------------------------------------ block seams
+# Section 2.2 asks that the points adjacent blocks share be treated with care
+# on multi-block grids.  The reading taken here for blocks that meet face to
+# face (a whole face against a whole face, same transverse extents, same index
+# orientation): the scheme's stencils run across the seam unchanged.  Each
+# direction's padded cells (five beyond each side) come from the neighbour
+# across that face, as do the area vectors of the three faces below and two
+# above the block; the metrics of every block come from its own vertices
+# -3 .. n + 1, taken from the global grid, so the two sides of a seam compute
+# the seam's metrics from the same coordinates.  A periodic block is its own
+# neighbour.  Closures at physical boundaries are not covered.
+
+def block_vertices(Xv: np.ndarray, P: np.ndarray, lo, m) -> np.ndarray:
+    """Vertices -3 .. m + 1 (metrics6's input) of the sub-block at index
+    origin lo with extents m of a periodic grid (Xv, P as periodic_vertices)."""
+    nk, nj, ni = Xv.shape[1:]
+    idx = [np.arange(lo[d] - 3, lo[d] + m[d] + 2) for d in range(3)]
+    n = (ni, nj, nk)
+    w = [idx[d] % n[d] for d in range(3)]
+    q = [idx[d] // n[d] for d in range(3)]
+    X = Xv[:, w[2]][:, :, w[1]][:, :, :, w[0]]
+    P = np.asarray(P, dtype=np.float64)
+    return (X + q[0][None, None, None, :] * P[0][:, None, None, None]
+            + q[1][None, None, :, None] * P[1][:, None, None, None]
+            + q[2][None, :, None, None] * P[2][:, None, None, None])
+
+
+def wcns5_euler_residual_blocks(Qs, Ss, Jinvs, nbr, gamma: float, eps_h: float, eps: float = 1e-6):
+    """Qs, Ss, Jinvs: per block as for the periodic residual; nbr[b][2d + side]
+    = the block across face (d, side) of block b (side 0: the low face).
+    Returns the residual of every block (dQ/dt = -R)."""
+    from .flux import primitives, roe_flux
+    Ws = [primitives(Q, gamma) for Q in Qs]
+    out = []
+    for b, (W, S, Jinv) in enumerate(zip(Ws, Ss, Jinvs)):
+        R = np.zeros_like(W)
+        for d in range(3):
+            ax = _ax(d)
+            lo, hi = nbr[b][2 * d], nbr[b][2 * d + 1]
+            nlo, nhi = Ws[lo].shape[ax], Ws[hi].shape[ax]
+            assert nlo >= 5 and nhi >= 5, "a neighbour must be at least 5 cells deep across the seam"
+            Wp = np.concatenate([_win(Ws[lo], ax, nlo - 5, 5), W, _win(Ws[hi], ax, 0, 5)], axis=ax)
+            WL, WR = wcns5_edge(Wp, d, eps)
+            Sd = np.concatenate([_win(Ss[lo][d], ax, nlo - 3, 3), S[d], _win(Ss[hi][d], ax, 0, 2)], axis=ax)
+            F = roe_flux(WL, WR, Sd, gamma, eps_h)
+            R = R + staggered_diff6(F, d, 1.0)
+        out.append(R / Jinv)
+    return out

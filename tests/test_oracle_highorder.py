@@ -16,7 +16,9 @@ rotation equivariance; fourth-order convergence of the vortex on a wavy grid;
 RK3 steps keep a uniform stream and advect the vortex at third order.
 Curvilinear viscous terms: exact reduction to the Cartesian ones, rotation
 equivariance, fourth-order convergence of closed-form shear and conduction
-fields sampled on a wavy grid.
+fields sampled on a wavy grid.  Time step: closed form and rotation
+invariance.  Block seams: a periodic block cut into blocks joined face to face
+gives bitwise its own metrics and residual.
 """
 import os
 from fractions import Fraction
@@ -642,3 +644,55 @@ def test_cfl_time_step_closed_form_and_rotation():
     vr = Rot @ vel
     qr = cases.conserved_from(rho * one, vr[0], vr[1], vr[2], p, g)
     assert np.isclose(ho.cfl_time_step_curv_periodic(qr, Sr, Jr, g, 0.8, True, pr, mu0, s), dtv, rtol=1e-13)
+
+
+# ------------------------------------------------------------ block seams
+
+def _split_box(n, cuts):
+    """Blocks of an n-cell periodic box cut at the given index lists along i, j,
+    k: (origins, extents, neighbour table), blocks ordered i fastest."""
+    edges = [[0] + list(c) + [n[d]] for d, c in enumerate(cuts)]
+    nb = [len(e) - 1 for e in edges]
+    lo, m, ids = [], [], {}
+    for c in range(nb[2]):
+        for b in range(nb[1]):
+            for a in range(nb[0]):
+                ids[(a, b, c)] = len(lo)
+                lo.append((edges[0][a], edges[1][b], edges[2][c]))
+                m.append((edges[0][a + 1] - edges[0][a], edges[1][b + 1] - edges[1][b],
+                          edges[2][c + 1] - edges[2][c]))
+    nbr = []
+    for (a, b, c), k in sorted(ids.items(), key=lambda t: t[1]):
+        row = []
+        for d in range(3):
+            for side in (-1, 1):
+                p = [a, b, c]
+                p[d] = (p[d] + side) % nb[d]
+                row.append(ids[tuple(p)])
+        nbr.append(row)
+    return lo, m, nbr
+
+
+def test_split_periodic_block_gives_the_same_metrics_and_residual():
+    """A periodic wavy block cut into 2 x 3 x 2 blocks joined face to face
+    (five-cell exchange, the neighbours' seam metrics): every block's metrics
+    and residual are bitwise the slices of the unsplit block's."""
+    n = (16, 18, 12)
+    Xv, P, _ = _wavy_grid(n, (3.0, 2.0, 1.5), 0.08)
+    S, Jinv = ho.metrics6(ho.periodic_vertices(Xv, P))
+    q, _ = _smooth_state(n, 7)
+    R = ho.wcns5_euler_residual_curv_periodic(q, S, Jinv, 1.4, 0.1)
+    lo, m, nbr = _split_box(n, ([7], [5, 11], [6]))
+    Qs, Ss, Js = [], [], []
+    for o, e in zip(lo, m):
+        sl = (slice(o[2], o[2] + e[2]), slice(o[1], o[1] + e[1]), slice(o[0], o[0] + e[0]))
+        Sb, Jb = ho.metrics6(ho.block_vertices(Xv, P, o, e))
+        assert np.array_equal(Sb, S[(slice(None), slice(None)) + sl]) and np.array_equal(Jb, Jinv[sl])
+        Qs.append(np.ascontiguousarray(q[(slice(None),) + sl]))
+        Ss.append(Sb)
+        Js.append(Jb)
+    Rs = ho.wcns5_euler_residual_blocks(Qs, Ss, Js, nbr, 1.4, 0.1)
+    for o, e, Rb in zip(lo, m, Rs):
+        assert np.array_equal(Rb, R[:, o[2]:o[2] + e[2], o[1]:o[1] + e[1], o[0]:o[0] + e[0]])
+    # one block that is its own neighbour on every face is the periodic block
+    assert np.array_equal(ho.wcns5_euler_residual_blocks([q], [S], [Jinv], [[0] * 6], 1.4, 0.1)[0], R)
