@@ -203,8 +203,11 @@ def bench_wcns5_euler(a) -> int:
     faces, Eq. 2 with the running sum), i.e. the intermediates' HBM traffic."""
     import numpy as np
     import torch
-    from paper_1710_09995_amd.binding import c4_viscous_add_periodic, wcns5_euler_residual_periodic
-    viscous = a.op == "ns_periodic"
+    from paper_1710_09995_amd.binding import (c4_viscous_add_curv_periodic, c4_viscous_add_periodic,
+                                              wcns5_euler_residual_curv_periodic, wcns5_euler_residual_periodic,
+                                              wcns5_metrics_periodic)
+    viscous = a.op in ("ns_periodic", "ns_curv")
+    curv = a.op in ("wcns5_curv", "ns_curv")
     n = (256, 128, 128)
     ni, nj, nk = n
     cells = ni * nj * nk
@@ -224,11 +227,34 @@ def bench_wcns5_euler(a) -> int:
     nb = C.c_size_t()
     B._check(B.lib().cfd_wcns5_euler_work_bytes((C.c_int32 * 3)(ni, nj, nk), C.byref(nb)))
     work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
-    vwork = torch.empty(8 * 20 * cells, dtype=torch.uint8, device="cuda") if viscous else None
+    vwork = torch.empty(8 * (29 if curv else 20) * cells, dtype=torch.uint8, device="cuda") if viscous else None
+    setup_ms = None
+    if curv:   # a wavy periodic grid on the box 1 x 1/2 x 1/2: each coordinate displaced by sines of the others
+        L, amp = (1.0, 0.5, 0.5), 0.05
+        zb, yb, xb = np.meshgrid((np.arange(nk) + 0.5) * L[2] / nk, (np.arange(nj) + 0.5) * L[1] / nj,
+                                 (np.arange(ni) + 0.5) * L[0] / ni, indexing="ij")
+        wx, wy, wz = s2 * xb / L[0], s2 * yb / L[1], s2 * zb / L[2]
+        xv = torch.from_numpy(np.stack([xb + amp * L[0] * np.sin(wy) * np.sin(wz),
+                                        yb + amp * L[1] * np.sin(wz) * np.sin(wx),
+                                        zb + amp * L[2] * np.sin(wx) * np.sin(wy)])).cuda()
+        del xb, yb, zb, wx, wy, wz
+        S, jinv = wcns5_metrics_periodic(xv, np.diag(L))
+        torch.cuda.synchronize()
+        m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        m0.record(torch.cuda.current_stream())
+        S, jinv = wcns5_metrics_periodic(xv, np.diag(L))
+        m1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        setup_ms = m0.elapsed_time(m1)
 
     def residual():
-        wcns5_euler_residual_periodic(q, h, out=out, work=work)
-        if viscous:
+        if curv:
+            wcns5_euler_residual_curv_periodic(q, S, jinv, out=out, work=work)
+        else:
+            wcns5_euler_residual_periodic(q, h, out=out, work=work)
+        if viscous and curv:
+            c4_viscous_add_curv_periodic(q, out, S, jinv, 1.4, 0.72, 1e-3, 110.4 / 288.15, work=vwork)
+        elif viscous:
             c4_viscous_add_periodic(q, out, h, 1.4, 0.72, 1e-3, 110.4 / 288.15, work=vwork)
     stream = torch.cuda.current_stream()
     for _ in range(a.warmup):
@@ -246,21 +272,33 @@ def bench_wcns5_euler(a) -> int:
         P = cells // n[d] * (n[d] + 10)
         F = cells // n[d] * (n[d] + 5)
         nbytes += 8 * 5 * ((cells + P) + (P + 2 * F) + (2 * F + F) + (F + cells * (1 if d == 0 else 2)))
-    if viscous:   # phi (Q in, 4 out), gradients (4 in, 12 out), per direction faces (16 in, 4 out) and the sum
+        if curv:
+            nbytes += 8 * 3 * F                # the faces' area vectors
+    if curv:                                   # R divided by J^{-1}
+        nbytes += 8 * cells * (5 + 5 + 1)
+    if viscous and curv:   # as below, plus the cell metrics (9 in, 9 out), per face S_d, S_t across, J^{-1}
+        nbytes += 8 * cells * ((5 + 4) + (4 + 12) + (9 + 9) + 3 * ((4 + 8 + 3 + 6 + 1) + 4) + 3 * (4 + 1 + 8))
+    elif viscous:   # phi (Q in, 4 out), gradients (4 in, 12 out), per direction faces (16 in, 4 out) and the sum
         nbytes += 8 * cells * ((5 + 4) + (4 + 12) + 3 * ((4 + 8) + 4) + 3 * (4 + 8))
     achieved = nbytes / (ms / 1e3) / 1e9
     print(json.dumps({
-        "metric": "Mcell/s of the periodic " + ("Navier-Stokes (WCNS-E-5 inviscid + fourth-order viscous)"
-                                                if viscous else "inviscid WCNS-E-5") + " residual (three directions)",
+        "metric": "Mcell/s of the periodic " + ("curvilinear " if curv else "") +
+                  ("Navier-Stokes (WCNS-E-5 inviscid + fourth-order viscous)" if viscous else "inviscid WCNS-E-5") +
+                  " residual (three directions)",
         "value": round(cells / (ms / 1e3) / 1e6, 1), "unit": "Mcell/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded smooth periodic flow)",
-        "config": {"workload": ("ns_wcns5_c4_periodic" if viscous else "wcns5_euler_periodic") + "_256x128x128"},
+        "config": {"workload": ("ns_wcns5_c4" if viscous else "wcns5_euler") + ("_curv" if curv else "") +
+                               "_periodic_256x128x128",
+                   "metrics_setup_ms": None if setup_ms is None else round(setup_ms, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "pipeline: k_pad_prim_periodic, k_window6_*<Wcns5Op>, k_roe_faces, "
-                               "k_window6_*<Eq2OpT>" + (", k_c4_phi, k_c4_grads, k_c4_visc_faces, k_c4_flux_sub"
-                                                        if viscous else ""),
+                     "kernel": "pipeline: k_pad_prim_periodic, k_window6_*<Wcns5Op>, "
+                               + ("k_roe_faces_curv" if curv else "k_roe_faces") + ", k_window6_*<Eq2OpT>"
+                               + (", k_div_jinv" if curv else "")
+                               + (", k_c4_phi, k_c4_grads, k_c4_cell_metrics, k_c4_visc_faces_curv, k_c4_flux_sub"
+                                  if viscous and curv else
+                                  ", k_c4_phi, k_c4_grads, k_c4_visc_faces, k_c4_flux_sub" if viscous else ""),
                      "mean_ms": round(ms, 4), "pipeline_bytes": nbytes},
         "cpu_baseline": None}), flush=True)
     return 0
@@ -290,12 +328,14 @@ def main(argv=None):
                     help="with --split: cut positions snap to multiples of these (1,1,1 = plain bisection)")
     ap.add_argument("--groups", type=int, default=8,
                     help="with --split: groups (devices) the pieces are regrouped into for the balance report")
-    ap.add_argument("--op", default=None, choices=["diff6", "wcns5", "wcns5_euler", "ns_periodic"],
+    ap.add_argument("--op", default=None, choices=["diff6", "wcns5", "wcns5_euler", "ns_periodic", "wcns5_curv", "ns_curv"],
                     help="time one operator instead of the solver, on a 256x128x128 block, 5 variables, each "
                          "direction: diff6 = the sixth-order staggered flux difference (Section 2.2, Eq. 2); "
                          "wcns5 = the WCNS-E-5 weighted cell-edge interpolation; wcns5_euler = the periodic "
                          "inviscid WCNS-E-5 residual (all three directions); ns_periodic = that residual plus the "
-                         "fourth-order central viscous terms")
+                         "fourth-order central viscous terms; wcns5_curv = the inviscid residual on a wavy "
+                         "curvilinear periodic grid (metrics computed once, their time reported); ns_curv = that "
+                         "residual plus the curvilinear fourth-order viscous terms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (HBM counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -309,7 +349,7 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n * 8, "copies": 5}), flush=True)
         return 0
-    if a.op in ("wcns5_euler", "ns_periodic") and a.gpus == 1:
+    if a.op in ("wcns5_euler", "ns_periodic", "wcns5_curv", "ns_curv") and a.gpus == 1:
         return bench_wcns5_euler(a)
     if a.op is not None and a.gpus == 1:
         return bench_op(a)

@@ -299,8 +299,7 @@ cfd_status cfd_wcns5_edges(const double* u_dev, double* left_dev, double* right_
  * flux splitting of the residual kernels, Harten factor entropy_fix), and
  * Eq. (2) (cfd_staggered_diff6); R = the sum over directions, so that
  * dQ/dt = -R (Section 2.2, Eq. 3 with the paper's spatial operator).
- * Curvilinear metrics and block closures of the scheme are in references the
- * paper does not reproduce, so this covers periodic Cartesian blocks only.
+ * Curvilinear blocks: cfd_wcns5_euler_residual_curv_periodic below.
  * q_dev, r_dev: [5][nk][nj][ni] dense FP64 (conserved variables, residual);
  * work_dev: cfd_wcns5_euler_work_bytes() bytes of device memory.  All the
  * caller's, pairwise disjoint.  n[t] >= 1, h > 0, gamma > 1, entropy_fix >= 0,
@@ -311,6 +310,44 @@ cfd_status cfd_wcns5_euler_residual_periodic(const double* q_dev, double* r_dev,
                                             const int32_t n[3], const double h[3], double gamma, double entropy_fix,
                                             double eps, hipStream_t stream);
 
+/* Metrics of one curvilinear block periodic in all three directions, for the
+ * geometric conservation law that Section 2.2 requires of the scheme on
+ * curvilinear grids (the paper defers the formulas to its reference; this is
+ * the symmetric conservative form).  Vertex v along a direction sits at index
+ * position v + 1/2, cell centres at integer positions; D is Eq. (2) with
+ * h = 1 and I the sixth-order mid-point interpolation
+ * (150 (f_{+1/2} + f_{-1/2}) - 25 (f_{+3/2} + f_{-3/2}) + 3 (f_{+5/2} + f_{-5/2})) / 256.
+ * The area vector of face v + 1/2 of direction d is
+ *   S_d = 1/2 [D_b (D_a X x I_a X) - D_a (D_b X x I_b X)],  (a, b) = (d+1, d+2) mod 3,
+ * so sum_d D_d S_d = 0 at every cell to rounding (a uniform stream stays
+ * uniform); J^{-1} = det[X_xi, X_eta, X_zeta] at the cell centre, each column
+ * D along its direction of the coordinates interpolated (I) along the other
+ * two.  Both are exact for maps of total degree 3.
+ * xv_dev: [3][nk][nj][ni] vertex coordinates (x, y, z); vertex (i, j, k) is
+ *   the upper corner of cell (i, j, k).  period: host, 9 doubles, period[3d + c]
+ *   = component c of the grid's displacement over one period along direction
+ *   d (vertex v + n_d along d = vertex v + that displacement).
+ * s_dev: [3 (d)][3 (x, y, z)][nk][nj][ni] out: S_d of face v + 1/2 at index v
+ *   along d.  jinv_dev: [nk][nj][ni] out.
+ * All the caller's device memory, pairwise disjoint.  n[t] >= 1, at most 2^34
+ * cells, finite periods, else CFD_EINVAL.  Asynchronous on stream. */
+cfd_status cfd_wcns5_metrics_periodic(const double* xv_dev, const double period[9], const int32_t n[3], double* s_dev,
+                                      double* jinv_dev, hipStream_t stream);
+
+/* The inviscid WCNS-E-5 residual of a periodic curvilinear block: as
+ * cfd_wcns5_euler_residual_periodic, with Roe's flux through each face's
+ * area vector S_d (flux times |S_d|), Eq. (2) in index units, and the sum over
+ * directions divided by J^{-1}: R = J sum_d D_d F_d, dQ/dt = -R.  On a uniform
+ * Cartesian grid it reduces to the Cartesian residual.  s_dev, jinv_dev from
+ * cfd_wcns5_metrics_periodic (J^{-1} must not vanish); the workspace is
+ * cfd_wcns5_euler_work_bytes() bytes; the other arguments and errors as for
+ * the Cartesian residual, and r and the workspace must not overlap the
+ * metrics.  Asynchronous on stream. */
+cfd_status cfd_wcns5_euler_residual_curv_periodic(const double* q_dev, const double* s_dev, const double* jinv_dev,
+                                                  double* r_dev, void* work_dev, size_t work_bytes,
+                                                  const int32_t n[3], double gamma, double entropy_fix, double eps,
+                                                  hipStream_t stream);
+
 /* nsteps third-order Runge-Kutta steps (Section 2.2, Eqs. 4-6, lambda = -dt,
  * fixed dt) of dQ/dt = -R(Q) with the periodic WCNS-E-5 residual above, in
  * place on q_dev ([5][nk][nj][ni]).  work_dev: cfd_wcns5_euler_step_work_bytes()
@@ -318,6 +355,16 @@ cfd_status cfd_wcns5_euler_residual_periodic(const double* q_dev, double* r_dev,
  * nsteps >= 0, the other arguments as for the residual; a short workspace
  * gives CFD_ENOMEM.  Asynchronous on stream. */
 cfd_status cfd_wcns5_euler_step_work_bytes(const int32_t n[3], size_t* bytes);
+
+/* nsteps RK3 steps as cfd_wcns5_euler_steps_periodic, with the curvilinear
+ * residual cfd_wcns5_euler_residual_curv_periodic (s_dev, jinv_dev from
+ * cfd_wcns5_metrics_periodic; q must not overlap them or the workspace).
+ * work_dev: cfd_wcns5_euler_step_work_bytes() bytes.  Errors as for the
+ * Cartesian steps and the curvilinear residual.  Asynchronous on stream. */
+cfd_status cfd_wcns5_euler_steps_curv_periodic(double* q_dev, const double* s_dev, const double* jinv_dev,
+                                               void* work_dev, size_t work_bytes, const int32_t n[3], double gamma,
+                                               double entropy_fix, double eps, double dt, int32_t nsteps,
+                                               hipStream_t stream);
 
 /* Viscous terms by fourth-order central differencing, which Section 2.2
  * chooses for the viscous flux derivatives (the paper prints no formulas;
@@ -342,6 +389,75 @@ cfd_status cfd_c4_viscous_add_periodic(const double* q_dev, double* r_dev, void*
 cfd_status cfd_wcns5_euler_steps_periodic(double* q_dev, void* work_dev, size_t work_bytes, const int32_t n[3],
                                           const double h[3], double gamma, double entropy_fix, double eps, double dt,
                                           int32_t nsteps, hipStream_t stream);
+
+/* The fourth-order central viscous terms on a periodic curvilinear block
+ * (Section 2.2's choice for the viscous flux derivatives, on the metrics of
+ * cfd_wcns5_metrics_periodic): index derivatives of u, v, w, T at the cells;
+ * the metrics S_t at the cells from their faces along t,
+ * (-S_{i-3/2} + 9 S_{i-1/2} + 9 S_{i+1/2} - S_{i+3/2}) / 16; at each face of
+ * direction d the physical gradient J sum_t S_t d/dxi_t (compact derivative
+ * along d, face values of the cell derivatives, of S_t (t != d) and of J^{-1});
+ * stress, Sutherland viscosity and conduction as above, the viscous flux
+ * through S_d; r -= J times the staggered difference, summed over d.  On a
+ * uniform Cartesian grid this equals cfd_c4_viscous_add_periodic.
+ * q_dev, r_dev: [5][nk][nj][ni]; s_dev, jinv_dev from the metrics call;
+ * work_dev: cfd_c4_viscous_curv_work_bytes() bytes.  r and the workspace must
+ * not overlap each other, q or the metrics.  Errors as for the Cartesian terms.
+ * Asynchronous on stream. */
+cfd_status cfd_c4_viscous_curv_work_bytes(const int32_t n[3], size_t* bytes);
+cfd_status cfd_c4_viscous_add_curv_periodic(const double* q_dev, const double* s_dev, const double* jinv_dev,
+                                            double* r_dev, void* work_dev, size_t work_bytes, const int32_t n[3],
+                                            double gamma, double prandtl, double mu_inf, double s_star,
+                                            hipStream_t stream);
+
+/* Curvilinear blocks joined face to face (Section 2.2 asks for care with the
+ * points that adjacent blocks share; this covers whole faces joined with the
+ * same index orientation, not physical boundaries).  The scheme's stencils
+ * run across every seam unchanged: along each direction the five cells beyond
+ * a block come from the neighbour across that face, as do the area vectors of
+ * the three faces below and the two above the block.  A periodic block is its
+ * own neighbour.
+ *
+ * cfd_wcns5_metrics_ext: the metrics of cfd_wcns5_metrics_periodic from an
+ * explicit array of the block's vertices -3 .. n + 1 along each direction,
+ * xe_dev [3][nk + 5][nj + 5][ni + 5] (vertex v at index v + 3), taken by the
+ * caller from the whole grid, so the two sides of a seam compute its metrics
+ * from the same coordinates.  Outputs and errors as for the periodic call.
+ *
+ * cfd_wcns5_euler_residual_blocks: the curvilinear residual of nblk blocks.
+ * dims: host [nblk][3] (ni, nj, nk); nbr: host [nblk][6], nbr[6b + 2d + side]
+ * = the block across face (d, side) of block b (side 0: the low face); the
+ * link must be mutual (face f of b <-> face f ^ 1 of the neighbour), the
+ * joined faces of equal extents, and every neighbour at least 5 cells across
+ * the seam, else CFD_EINVAL.  q_dev, s_dev, jinv_dev, r_dev: host arrays of
+ * nblk device pointers ([5][nk][nj][ni], the metrics of each block, its
+ * residual out); work_dev: cfd_wcns5_euler_blocks_work_bytes() bytes.  No
+ * residual may overlap an input, another residual or the workspace.  gamma,
+ * entropy_fix, eps as for the periodic residual.  Asynchronous on stream. */
+cfd_status cfd_wcns5_metrics_ext(const double* xe_dev, const int32_t n[3], double* s_dev, double* jinv_dev,
+                                 hipStream_t stream);
+cfd_status cfd_wcns5_euler_blocks_work_bytes(int32_t nblk, const int32_t* dims, const int32_t* nbr, size_t* bytes);
+cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_t* dims, const int32_t* nbr,
+                                           const double* const* q_dev, const double* const* s_dev,
+                                           const double* const* jinv_dev, double* const* r_dev, void* work_dev,
+                                           size_t work_bytes, double gamma, double entropy_fix, double eps,
+                                           hipStream_t stream);
+
+/* The global time step of a periodic curvilinear block for the RK3 steps
+ * above (the paper leaves the step size of Eqs. 4-6 open; the finite-volume
+ * path's reading): per cell dt_c = cfl J^{-1} / (sum_d L_d + 4 sum_d Lv_d),
+ * L_d = |u . Sb_d| + c |Sb_d|, Lv_d = max(4/3, gamma/Pr)(mu/rho)|Sb_d|^2 / J^{-1}
+ * when viscous != 0 (Sutherland's mu from mu_inf, s_star), Sb_d the mean of the
+ * cell's two d-face area vectors; *dt_dev = the least dt_c (0 if a cell is
+ * non-physical or has J^{-1} <= 0).  q_dev [5][nk][nj][ni]; s_dev, jinv_dev
+ * from cfd_wcns5_metrics_periodic; dt_dev: one 8-byte aligned device double,
+ * the caller's, not overlapping the inputs.  gamma > 1, cfl > 0, and for
+ * viscous flow Pr > 0, mu_inf >= 0, s_star > 0, else CFD_EINVAL.
+ * Asynchronous on stream: read *dt_dev after the stream has run it. */
+cfd_status cfd_wcns5_time_step_curv_periodic(const double* q_dev, const double* s_dev, const double* jinv_dev,
+                                             const int32_t n[3], double gamma, double cfl, int32_t viscous,
+                                             double prandtl, double mu_inf, double s_star, double* dt_dev,
+                                             hipStream_t stream);
 
 /* ---------------------------------------------------------------- warm start
  * A multilayer perceptron predicts the steady flow of a channel-bump case

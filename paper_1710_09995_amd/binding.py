@@ -66,6 +66,10 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_split_plan", "cfd_split_tables", "cfd_regroup", "cfd_staggered_diff6", "cfd_wcns5_edges",
            "cfd_wcns5_euler_work_bytes", "cfd_wcns5_euler_residual_periodic", "cfd_wcns5_euler_step_work_bytes",
            "cfd_wcns5_euler_steps_periodic", "cfd_c4_viscous_work_bytes", "cfd_c4_viscous_add_periodic",
+           "cfd_wcns5_metrics_periodic", "cfd_wcns5_euler_residual_curv_periodic",
+           "cfd_wcns5_euler_steps_curv_periodic", "cfd_c4_viscous_curv_work_bytes",
+           "cfd_c4_viscous_add_curv_periodic", "cfd_wcns5_time_step_curv_periodic", "cfd_wcns5_metrics_ext",
+           "cfd_wcns5_euler_blocks_work_bytes", "cfd_wcns5_euler_residual_blocks",
            "cfd_status_string", "cfd_last_error"]
 
 _lib = None
@@ -125,6 +129,21 @@ def lib(build_if_missing: bool = True):
                                               C.c_double, C.c_double, C.c_double, vp]
     L.cfd_wcns5_euler_steps_periodic.argtypes = [vp, vp, C.c_size_t, i32p, C.POINTER(C.c_double), C.c_double,
                                                  C.c_double, C.c_double, C.c_double, i32, vp]
+    L.cfd_wcns5_metrics_periodic.argtypes = [vp, C.POINTER(C.c_double), i32p, vp, vp, vp]
+    L.cfd_wcns5_euler_residual_curv_periodic.argtypes = [vp, vp, vp, vp, vp, C.c_size_t, i32p, C.c_double,
+                                                         C.c_double, C.c_double, vp]
+    L.cfd_wcns5_euler_steps_curv_periodic.argtypes = [vp, vp, vp, vp, C.c_size_t, i32p, C.c_double, C.c_double,
+                                                      C.c_double, C.c_double, i32, vp]
+    L.cfd_c4_viscous_curv_work_bytes.argtypes = [i32p, C.POINTER(C.c_size_t)]
+    L.cfd_c4_viscous_add_curv_periodic.argtypes = [vp, vp, vp, vp, vp, C.c_size_t, i32p, C.c_double, C.c_double,
+                                                   C.c_double, C.c_double, vp]
+    L.cfd_wcns5_time_step_curv_periodic.argtypes = [vp, vp, vp, i32p, C.c_double, C.c_double, i32, C.c_double,
+                                                    C.c_double, C.c_double, vp, vp]
+    L.cfd_wcns5_metrics_ext.argtypes = [vp, i32p, vp, vp, vp]
+    L.cfd_wcns5_euler_blocks_work_bytes.argtypes = [i32, i32p, i32p, C.POINTER(C.c_size_t)]
+    L.cfd_wcns5_euler_residual_blocks.argtypes = [i32, i32p, i32p, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                                  C.POINTER(vp), vp, C.c_size_t, C.c_double, C.c_double, C.c_double,
+                                                  vp]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]
@@ -308,6 +327,170 @@ def c4_viscous_add_periodic(q, r, h, gamma: float = 1.4, prandtl: float = 0.72, 
                                              float(prandtl), float(mu_inf), float(s_star),
                                              _stream_handle(torch, stream)))
     return r
+
+
+def wcns5_metrics_periodic(xv, period, stream=None):
+    """Metrics of a periodic curvilinear block on the device
+    (cfd_wcns5_metrics_periodic): xv is a contiguous FP64 CUDA tensor
+    [3, nk, nj, ni] of vertex coordinates (vertex (i, j, k) = the upper corner
+    of cell (i, j, k)); period[d] the grid's displacement over one period
+    along direction d (3 x 3).  Returns (S [3, 3, nk, nj, ni], Jinv [nk, nj, ni])."""
+    import torch
+    if xv.dtype != torch.float64 or not xv.is_cuda or not xv.is_contiguous() or xv.dim() != 4 or xv.shape[0] != 3:
+        raise ValueError("xv must be a contiguous float64 CUDA tensor [3, nk, nj, ni]")
+    nk, nj, ni = (int(v) for v in xv.shape[1:])
+    per = [float(v) for row in period for v in row]
+    if len(per) != 9:
+        raise ValueError("period must be 3 x 3")
+    S = torch.empty((3, 3, nk, nj, ni), dtype=torch.float64, device=xv.device)
+    jinv = torch.empty((nk, nj, ni), dtype=torch.float64, device=xv.device)
+    _check(lib().cfd_wcns5_metrics_periodic(_ptr(xv), (C.c_double * 9)(*per), (C.c_int32 * 3)(ni, nj, nk), _ptr(S),
+                                            _ptr(jinv), _stream_handle(torch, stream)))
+    return S, jinv
+
+
+def wcns5_euler_residual_curv_periodic(q, S, jinv, gamma: float = 1.4, entropy_fix: float = 0.1, eps: float = 1e-6,
+                                       out=None, work=None, stream=None):
+    """Inviscid WCNS-E-5 residual of a periodic curvilinear block on the device
+    (cfd_wcns5_euler_residual_curv_periodic): q [5, nk, nj, ni], S and jinv
+    from wcns5_metrics_periodic, all contiguous FP64 CUDA tensors; returns R
+    (dQ/dt = -R)."""
+    import torch
+    if q.dtype != torch.float64 or not q.is_cuda or not q.is_contiguous() or q.dim() != 4 or q.shape[0] != 5:
+        raise ValueError("q must be a contiguous float64 CUDA tensor [5, nk, nj, ni]")
+    nk, nj, ni = (int(v) for v in q.shape[1:])
+    for t, shp in ((S, (3, 3, nk, nj, ni)), (jinv, (nk, nj, ni))):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp:
+            raise ValueError("S and jinv must be contiguous float64 CUDA tensors of the block's shape")
+    nn = (C.c_int32 * 3)(ni, nj, nk)
+    nbytes = C.c_size_t()
+    _check(lib().cfd_wcns5_euler_work_bytes(nn, C.byref(nbytes)))
+    if work is None or work.numel() * work.element_size() < nbytes.value:
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+    if out is None:
+        out = torch.empty_like(q)
+    _check(lib().cfd_wcns5_euler_residual_curv_periodic(_ptr(q), _ptr(S), _ptr(jinv), _ptr(out), _ptr(work),
+                                                        nbytes.value, nn, float(gamma), float(entropy_fix),
+                                                        float(eps), _stream_handle(torch, stream)))
+    return out
+
+
+def wcns5_euler_steps_curv_periodic(q, S, jinv, dt: float, nsteps: int, gamma: float = 1.4,
+                                    entropy_fix: float = 0.1, eps: float = 1e-6, work=None, stream=None):
+    """nsteps RK3 steps of the curvilinear periodic WCNS-E-5 Euler residual on
+    the device, in place on q (contiguous FP64 CUDA tensor [5, nk, nj, ni]);
+    S, jinv from wcns5_metrics_periodic.  Returns q."""
+    import torch
+    if q.dtype != torch.float64 or not q.is_cuda or not q.is_contiguous() or q.dim() != 4 or q.shape[0] != 5:
+        raise ValueError("q must be a contiguous float64 CUDA tensor [5, nk, nj, ni]")
+    nk, nj, ni = (int(v) for v in q.shape[1:])
+    for t, shp in ((S, (3, 3, nk, nj, ni)), (jinv, (nk, nj, ni))):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp:
+            raise ValueError("S and jinv must be contiguous float64 CUDA tensors of the block's shape")
+    nn = (C.c_int32 * 3)(ni, nj, nk)
+    nbytes = C.c_size_t()
+    _check(lib().cfd_wcns5_euler_step_work_bytes(nn, C.byref(nbytes)))
+    if work is None or work.numel() * work.element_size() < nbytes.value:
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+    _check(lib().cfd_wcns5_euler_steps_curv_periodic(_ptr(q), _ptr(S), _ptr(jinv), _ptr(work), nbytes.value, nn,
+                                                     float(gamma), float(entropy_fix), float(eps), float(dt),
+                                                     int(nsteps), _stream_handle(torch, stream)))
+    return q
+
+
+def c4_viscous_add_curv_periodic(q, r, S, jinv, gamma: float = 1.4, prandtl: float = 0.72, mu_inf: float = 1e-3,
+                                 s_star: float = 110.4 / 288.15, work=None, stream=None):
+    """Adds -div F_v (fourth-order central, periodic curvilinear block) to r on
+    the device (cfd_c4_viscous_add_curv_periodic); q, r [5, nk, nj, ni], S and
+    jinv from wcns5_metrics_periodic, all contiguous FP64 CUDA tensors.
+    Returns r."""
+    import torch
+    for t in (q, r):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 4 or t.shape[0] != 5:
+            raise ValueError("q and r must be contiguous float64 CUDA tensors [5, nk, nj, ni]")
+    nk, nj, ni = (int(v) for v in q.shape[1:])
+    for t, shp in ((S, (3, 3, nk, nj, ni)), (jinv, (nk, nj, ni))):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp:
+            raise ValueError("S and jinv must be contiguous float64 CUDA tensors of the block's shape")
+    nn = (C.c_int32 * 3)(ni, nj, nk)
+    nbytes = C.c_size_t()
+    _check(lib().cfd_c4_viscous_curv_work_bytes(nn, C.byref(nbytes)))
+    if work is None or work.numel() * work.element_size() < nbytes.value:
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+    _check(lib().cfd_c4_viscous_add_curv_periodic(_ptr(q), _ptr(S), _ptr(jinv), _ptr(r), _ptr(work), nbytes.value,
+                                                  nn, float(gamma), float(prandtl), float(mu_inf), float(s_star),
+                                                  _stream_handle(torch, stream)))
+    return r
+
+
+def wcns5_time_step_curv_periodic(q, S, jinv, cfl: float, gamma: float = 1.4, viscous: bool = False,
+                                   prandtl: float = 0.72, mu_inf: float = 1e-3, s_star: float = 110.4 / 288.15,
+                                   out=None, stream=None):
+    """The global CFL time step of a periodic curvilinear block on the device
+    (cfd_wcns5_time_step_curv_periodic).  Returns a one-element FP64 CUDA
+    tensor (out, if given), filled asynchronously on the stream."""
+    import torch
+    if q.dtype != torch.float64 or not q.is_cuda or not q.is_contiguous() or q.dim() != 4 or q.shape[0] != 5:
+        raise ValueError("q must be a contiguous float64 CUDA tensor [5, nk, nj, ni]")
+    nk, nj, ni = (int(v) for v in q.shape[1:])
+    for t, shp in ((S, (3, 3, nk, nj, ni)), (jinv, (nk, nj, ni))):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp:
+            raise ValueError("S and jinv must be contiguous float64 CUDA tensors of the block's shape")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=q.device)
+    _check(lib().cfd_wcns5_time_step_curv_periodic(_ptr(q), _ptr(S), _ptr(jinv), (C.c_int32 * 3)(ni, nj, nk),
+                                                   float(gamma), float(cfl), 1 if viscous else 0, float(prandtl),
+                                                   float(mu_inf), float(s_star), _ptr(out),
+                                                   _stream_handle(torch, stream)))
+    return out
+
+
+def wcns5_metrics_ext(xe, stream=None):
+    """Metrics of a block from its vertices -3 .. n + 1 along each direction
+    (cfd_wcns5_metrics_ext): xe a contiguous FP64 CUDA tensor
+    [3, nk + 5, nj + 5, ni + 5].  Returns (S [3, 3, nk, nj, ni], Jinv)."""
+    import torch
+    if xe.dtype != torch.float64 or not xe.is_cuda or not xe.is_contiguous() or xe.dim() != 4 or xe.shape[0] != 3:
+        raise ValueError("xe must be a contiguous float64 CUDA tensor [3, nk + 5, nj + 5, ni + 5]")
+    nk, nj, ni = (int(v) - 5 for v in xe.shape[1:])
+    if min(nk, nj, ni) < 1:
+        raise ValueError("xe must hold at least one cell along each direction")
+    S = torch.empty((3, 3, nk, nj, ni), dtype=torch.float64, device=xe.device)
+    jinv = torch.empty((nk, nj, ni), dtype=torch.float64, device=xe.device)
+    _check(lib().cfd_wcns5_metrics_ext(_ptr(xe), (C.c_int32 * 3)(ni, nj, nk), _ptr(S), _ptr(jinv),
+                                       _stream_handle(torch, stream)))
+    return S, jinv
+
+
+def wcns5_euler_residual_blocks(qs, Ss, jinvs, nbr, gamma: float = 1.4, entropy_fix: float = 0.1, eps: float = 1e-6,
+                                outs=None, work=None, stream=None):
+    """The curvilinear WCNS-E-5 residual of blocks joined face to face
+    (cfd_wcns5_euler_residual_blocks): per block q [5, nk, nj, ni], S, jinv
+    (contiguous FP64 CUDA tensors); nbr[b][2d + side] the block across face
+    (d, side).  Returns the residuals."""
+    import torch
+    nblk = len(qs)
+    dims = (C.c_int32 * (3 * nblk))()
+    for b, q in enumerate(qs):
+        if q.dtype != torch.float64 or not q.is_cuda or not q.is_contiguous() or q.dim() != 4 or q.shape[0] != 5:
+            raise ValueError("every q must be a contiguous float64 CUDA tensor [5, nk, nj, ni]")
+        nk, nj, ni = (int(v) for v in q.shape[1:])
+        dims[3 * b:3 * b + 3] = [ni, nj, nk]
+        for t, shp in ((Ss[b], (3, 3, nk, nj, ni)), (jinvs[b], (nk, nj, ni))):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp:
+                raise ValueError("S and jinv must be contiguous float64 CUDA tensors of each block's shape")
+    nb = (C.c_int32 * (6 * nblk))(*[int(v) for row in nbr for v in row])
+    nbytes = C.c_size_t()
+    _check(lib().cfd_wcns5_euler_blocks_work_bytes(nblk, dims, nb, C.byref(nbytes)))
+    if work is None or work.numel() * work.element_size() < nbytes.value:
+        work = torch.empty(max(nbytes.value, 8), dtype=torch.uint8, device=qs[0].device)
+    if outs is None:
+        outs = [torch.empty_like(q) for q in qs]
+    ptrs = lambda ts: (C.c_void_p * nblk)(*[_ptr(t) for t in ts])   # noqa: E731
+    _check(lib().cfd_wcns5_euler_residual_blocks(nblk, dims, nb, ptrs(qs), ptrs(Ss), ptrs(jinvs), ptrs(outs),
+                                                 _ptr(work), nbytes.value, float(gamma), float(entropy_fix),
+                                                 float(eps), _stream_handle(torch, stream)))
+    return outs
 
 
 class Solver:

@@ -209,6 +209,274 @@ __global__ void __launch_bounds__(256) k_roe_faces(const double* __restrict__ wl
 
 int grid_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 8192); }
 
+// ------------------------------------------------------- curvilinear blocks
+// Metrics of a periodic curvilinear block for the geometric conservation law
+// the paper requires (Section 2.2).  Vertex v along a direction sits at index
+// position v + 1/2, cells at integer positions.  D is Eq. (2) with h = 1 and
+// I the sixth-order mid-point interpolation (150, -25, 3) / 256, both from six
+// vertex positions to the centre position along one axis.  Face metrics in
+// the symmetric conservative form
+//   S_d = 1/2 [D_b (D_a X x I_a X) - D_a (D_b X x I_b X)], (a, b) = (d+1, d+2) mod 3,
+// so that sum_d D_d S_d = 0 at every cell (D and I along different axes
+// commute) and a uniform stream stays uniform; J^{-1} = det[X_xi X_eta X_zeta]
+// at the cell, each column D along its axis of I along the other two.
+constexpr double I1 = 150.0 / 256.0, I2 = -25.0 / 256.0, I3 = 3.0 / 256.0;
+constexpr double E1 = 75.0 / 64.0, E2 = -25.0 / 384.0, E3 = 3.0 / 640.0;
+
+struct PeriodicGrid {
+  const double* xv;  // [3][nk][nj][ni]: vertex (i, j, k) is the upper corner of cell (i, j, k)
+  int n[3];
+  double P[3][3];    // P[d]: the displacement of the grid over one period along d
+  // Coordinates of vertex (v0, v1, v2), any integers: the stored vertex of
+  // the wrapped index plus the periods crossed.
+  __device__ __forceinline__ void vertex(int v0, int v1, int v2, double X[3]) const {
+    const int v[3] = {v0, v1, v2};
+    int w[3];
+    double q[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int qd = v[d] >= 0 ? v[d] / n[d] : -((-v[d] + n[d] - 1) / n[d]);
+      w[d] = v[d] - qd * n[d];
+      q[d] = (double)qd;
+    }
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    const int64_t idx = ((int64_t)w[2] * n[1] + w[1]) * n[0] + w[0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) X[c] = xv[c * cells + idx] + q[0] * P[0][c] + q[1] * P[1][c] + q[2] * P[2][c];
+  }
+};
+
+// Coordinates from an explicit array of the vertices -3 .. n + 1 along each
+// direction (a block of a larger grid: the caller supplies the vertices
+// beyond its faces).  Every index the metric kernels ask for lies in that range.
+struct ExtGrid {
+  const double* xe;  // [3][nk + 5][nj + 5][ni + 5], vertex v at index v + 3
+  int n[3];
+  __device__ __forceinline__ void vertex(int v0, int v1, int v2, double X[3]) const {
+    const int64_t e0 = n[0] + 5, e1 = n[1] + 5, ecells = e0 * e1 * (n[2] + 5);
+    const int64_t idx = ((int64_t)(v2 + 3) * e1 + (v1 + 3)) * e0 + (v0 + 3);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) X[c] = xe[c * ecells + idx];
+  }
+};
+
+// D_a X x I_a X at position p (a centre along a, vertices along the others).
+template <int A, class Grid>
+__device__ __forceinline__ void metric_cross(const Grid& g, int p0, int p1, int p2, double out[3]) {
+  double f[6][3];
+#pragma unroll
+  for (int m = 0; m < 6; ++m)
+    g.vertex(p0 + (A == 0 ? m - 3 : 0), p1 + (A == 1 ? m - 3 : 0), p2 + (A == 2 ? m - 3 : 0), f[m]);
+  double D[3], I[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    D[c] = E1 * (f[3][c] - f[2][c]) + E2 * (f[4][c] - f[1][c]) + E3 * (f[5][c] - f[0][c]);
+    I[c] = I1 * (f[3][c] + f[2][c]) + I2 * (f[4][c] + f[1][c]) + I3 * (f[5][c] + f[0][c]);
+  }
+  out[0] = D[1] * I[2] - D[2] * I[1];
+  out[1] = D[2] * I[0] - D[0] * I[2];
+  out[2] = D[0] * I[1] - D[1] * I[0];
+}
+
+// S_d at the faces of direction d: s[(d * 3 + c) * cells + cell] holds
+// component c of the face v + 1/2 with v the cell's index along d.
+template <int DIR, class Grid>
+__global__ void __launch_bounds__(256) k_metric_faces(Grid g, double* __restrict__ s) {
+  constexpr int A = (DIR + 1) % 3, B = (DIR + 2) % 3;
+  const int64_t cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += (int64_t)gridDim.x * blockDim.x) {
+    const int p[3] = {(int)(t % g.n[0]), (int)((t / g.n[0]) % g.n[1]), (int)(t / ((int64_t)g.n[0] * g.n[1]))};
+    const double wd[6] = {-E3, -E2, -E1, E1, E2, E3};
+    double t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int k = 0; k < 6; ++k) {                   // D_b of (D_a X x I_a X)
+      double m[3];
+      metric_cross<A, Grid>(g, p[0] + (B == 0 ? k - 3 : 0), p[1] + (B == 1 ? k - 3 : 0), p[2] + (B == 2 ? k - 3 : 0),
+                            m);
+      const double w = k == 0 ? wd[0] : k == 1 ? wd[1] : k == 2 ? wd[2] : k == 3 ? wd[3] : k == 4 ? wd[4] : wd[5];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t1[c] += w * m[c];
+    }
+#pragma unroll 1
+    for (int k = 0; k < 6; ++k) {                   // D_a of (D_b X x I_b X)
+      double m[3];
+      metric_cross<B, Grid>(g, p[0] + (A == 0 ? k - 3 : 0), p[1] + (A == 1 ? k - 3 : 0), p[2] + (A == 2 ? k - 3 : 0),
+                            m);
+      const double w = k == 0 ? wd[0] : k == 1 ? wd[1] : k == 2 ? wd[2] : k == 3 ? wd[3] : k == 4 ? wd[4] : wd[5];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t2[c] += w * m[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[(DIR * 3 + c) * cells + t] = 0.5 * (t1[c] - t2[c]);
+  }
+}
+
+// J^{-1} at the cells: one pass over the 6 x 6 x 6 vertices around the cell,
+// column d weighted by D along d and I along the other two.
+template <class Grid>
+__global__ void __launch_bounds__(256) k_metric_jinv(Grid g, double* __restrict__ jinv) {
+  const double wd[6] = {-E3, -E2, -E1, E1, E2, E3};
+  const double wi[6] = {I3, I2, I1, I1, I2, I3};
+  const int64_t cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % g.n[0]), j = (int)((t / g.n[0]) % g.n[1]), k = (int)(t / ((int64_t)g.n[0] * g.n[1]));
+    double col[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int r2 = 0; r2 < 6; ++r2)
+      for (int r1 = 0; r1 < 6; ++r1) {
+#pragma unroll
+        for (int r0 = 0; r0 < 6; ++r0) {
+          double X[3];
+          g.vertex(i - 3 + r0, j - 3 + r1, k - 3 + r2, X);
+          const double w0 = wd[r0] * wi[r1] * wi[r2], w1 = wi[r0] * wd[r1] * wi[r2], w2 = wi[r0] * wi[r1] * wd[r2];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            col[0][c] += w0 * X[c];
+            col[1][c] += w1 * X[c];
+            col[2][c] += w2 * X[c];
+          }
+        }
+      }
+    const double cx = col[1][1] * col[2][2] - col[1][2] * col[2][1];
+    const double cy = col[1][2] * col[2][0] - col[1][0] * col[2][2];
+    const double cz = col[1][0] * col[2][1] - col[1][1] * col[2][0];
+    jinv[t] = col[0][0] * cx + col[0][1] * cy + col[0][2] * cz;
+  }
+}
+
+// Roe's flux through the area vector of each face along d (flux times |S|):
+// face p of the m0 x m1 x m2 face grid (m_d = n_d + 5) is face v + 1/2 with
+// v = (p - 3) mod n_d, whose area vector sits at index v of the metric field.
+__global__ void __launch_bounds__(256) k_roe_faces_curv(const double* __restrict__ wl, const double* __restrict__ wr,
+                                                        const double* __restrict__ sd, double* __restrict__ f,
+                                                        int m0, int m1, int m2, int d, int n0, int n1, int n2,
+                                                        Gas<double> gas) {
+  const int64_t nf = (int64_t)m0 * m1 * m2;
+  const int64_t cells = (int64_t)n0 * n1 * n2;
+  const int nd = d == 0 ? n0 : (d == 1 ? n1 : n2);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nf; t += (int64_t)gridDim.x * blockDim.x) {
+    int a = (int)(t % m0), b = (int)((t / m0) % m1), c = (int)(t / ((int64_t)m0 * m1));
+    const int p = d == 0 ? a : (d == 1 ? b : c);
+    const int v = ((p - 3) % nd + nd) % nd;
+    if (d == 0) a = v;
+    if (d == 1) b = v;
+    if (d == 2) c = v;
+    const int64_t ci = ((int64_t)c * n1 + b) * n0 + a;
+    const double sx = sd[ci], sy = sd[cells + ci], sz = sd[2 * cells + ci];
+    const double area = fsqrt(sx * sx + sy * sy + sz * sz);
+    const double ia = frcp(area);
+    const Prim<double> L{wl[t], wl[nf + t], wl[2 * nf + t], wl[3 * nf + t], wl[4 * nf + t]};
+    const Prim<double> R{wr[t], wr[nf + t], wr[2 * nf + t], wr[3 * nf + t], wr[4 * nf + t]};
+    double fl[5];
+    roe<double>(L, R, sx * ia, sy * ia, sz * ia, gas, fl);
+    for (int q = 0; q < 5; ++q) f[q * nf + t] = fl[q] * area;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_div_jinv(double* __restrict__ r, const double* __restrict__ jinv,
+                                                  int64_t cells) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += (int64_t)gridDim.x * blockDim.x) {
+    const double j = jinv[t];
+    for (int q = 0; q < 5; ++q) r[q * cells + t] = r[q * cells + t] / j;
+  }
+}
+
+template <class Grid>
+void launch_metrics(const Grid& g, double* s_dev, double* jinv_dev, int64_t cells, hipStream_t stream) {
+  const dim3 grid(grid_for(cells));
+  hipLaunchKernelGGL((k_metric_faces<0, Grid>), grid, dim3(256), 0, stream, g, s_dev);
+  hipLaunchKernelGGL((k_metric_faces<1, Grid>), grid, dim3(256), 0, stream, g, s_dev);
+  hipLaunchKernelGGL((k_metric_faces<2, Grid>), grid, dim3(256), 0, stream, g, s_dev);
+  hipLaunchKernelGGL(k_metric_jinv<Grid>, grid, dim3(256), 0, stream, g, jinv_dev);
+}
+
+// Blocks joined face to face.  Index of cell (a, b, c) of a block whose
+// extent along d is nd and whose other extents are the caller's.
+__device__ __forceinline__ int64_t seam_index(int a, int b, int c, int d, int nd, int n0, int n1) {
+  const int64_t e0 = d == 0 ? nd : n0, e1 = d == 1 ? nd : n1;
+  return ((int64_t)c * e1 + b) * e0 + a;
+}
+
+// Primitives padded by five cells on each side along d, those beyond the
+// block taken from the neighbours across its two d-faces (qlo: its last five
+// cells along d, qhi: its first five).
+__global__ void __launch_bounds__(256) k_pad_prim_blocks(const double* __restrict__ q, const double* __restrict__ qlo,
+                                                         const double* __restrict__ qhi, double* __restrict__ w,
+                                                         int n0, int n1, int n2, int d, int nlo, int nhi,
+                                                         double gm1) {
+  const int nd = d == 0 ? n0 : (d == 1 ? n1 : n2);
+  const int64_t e0 = n0 + (d == 0 ? 10 : 0), e1 = n1 + (d == 1 ? 10 : 0), e2 = n2 + (d == 2 ? 10 : 0);
+  const int64_t total = e0 * e1 * e2;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    int a = (int)(t % e0), b = (int)((t / e0) % e1), c = (int)(t / (e0 * e1));
+    int x = (d == 0 ? a : (d == 1 ? b : c)) - 5;
+    const double* src = q;
+    int sd = nd;
+    if (x < 0) {
+      src = qlo;
+      sd = nlo;
+      x += nlo;
+    } else if (x >= nd) {
+      src = qhi;
+      sd = nhi;
+      x -= nd;
+    }
+    if (d == 0) a = x;
+    if (d == 1) b = x;
+    if (d == 2) c = x;
+    const int64_t scells = (int64_t)(d == 0 ? sd : n0) * (d == 1 ? sd : n1) * (d == 2 ? sd : n2);
+    const int64_t i = seam_index(a, b, c, d, sd, n0, n1);
+    const Prim<double> p = to_prim<double>(src[i], src[scells + i], src[2 * scells + i], src[3 * scells + i],
+                                           src[4 * scells + i], gm1);
+    w[t] = p.r;
+    w[total + t] = p.u;
+    w[2 * total + t] = p.v;
+    w[3 * total + t] = p.w;
+    w[4 * total + t] = p.p;
+  }
+}
+
+// Roe's flux through the area vector of face p (m_d = n_d + 5 faces along
+// d): face v + 1/2, v = p - 3; the three faces below the block and the two
+// above come from the neighbours' metrics (slo: its last faces, shi: its first).
+__global__ void __launch_bounds__(256) k_roe_faces_blocks(const double* __restrict__ wl,
+                                                          const double* __restrict__ wr,
+                                                          const double* __restrict__ s, const double* __restrict__ slo,
+                                                          const double* __restrict__ shi, double* __restrict__ f,
+                                                          int m0, int m1, int m2, int d, int n0, int n1, int n2,
+                                                          int nlo, int nhi, Gas<double> gas) {
+  const int64_t nf = (int64_t)m0 * m1 * m2;
+  const int nd = d == 0 ? n0 : (d == 1 ? n1 : n2);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nf; t += (int64_t)gridDim.x * blockDim.x) {
+    int a = (int)(t % m0), b = (int)((t / m0) % m1), c = (int)(t / ((int64_t)m0 * m1));
+    int v = (d == 0 ? a : (d == 1 ? b : c)) - 3;
+    const double* src = s;
+    int sd = nd;
+    if (v < 0) {
+      src = slo;
+      sd = nlo;
+      v += nlo;
+    } else if (v >= nd) {
+      src = shi;
+      sd = nhi;
+      v -= nd;
+    }
+    if (d == 0) a = v;
+    if (d == 1) b = v;
+    if (d == 2) c = v;
+    const int64_t scells = (int64_t)(d == 0 ? sd : n0) * (d == 1 ? sd : n1) * (d == 2 ? sd : n2);
+    const int64_t ci = seam_index(a, b, c, d, sd, n0, n1);
+    const double* sdv = src + 3 * d * scells;
+    const double sx = sdv[ci], sy = sdv[scells + ci], sz = sdv[2 * scells + ci];
+    const double area = fsqrt(sx * sx + sy * sy + sz * sz);
+    const double ia = frcp(area);
+    const Prim<double> L{wl[t], wl[nf + t], wl[2 * nf + t], wl[3 * nf + t], wl[4 * nf + t]};
+    const Prim<double> R{wr[t], wr[nf + t], wr[2 * nf + t], wr[3 * nf + t], wr[4 * nf + t]};
+    double fl[5];
+    roe<double>(L, R, sx * ia, sy * ia, sz * ia, gas, fl);
+    for (int qv = 0; qv < 5; ++qv) f[qv * nf + t] = fl[qv] * area;
+  }
+}
+
 // One Runge-Kutta stage of Eqs. (4)-(6) with lambda = -dt, in place:
 // q <- a qn + b (q - dt r) (a = 0, b = 1: the first stage; then 3/4, 1/4 and
 // 1/3, 2/3).  keep_qn also stores q into qn first (the step's start state).
@@ -306,6 +574,72 @@ extern "C" cfd_status cfd_wcns5_euler_work_bytes(const int32_t n[3], size_t* byt
   });
 }
 
+namespace cfd {
+
+bool apart(const void* a, int64_t na, const void* b, int64_t nb) {
+  const char *a0 = static_cast<const char*>(a), *b0 = static_cast<const char*>(b);
+  return a0 + na <= b0 || b0 + nb <= a0;
+}
+
+// The periodic WCNS-E-5 residual along the three directions.  Cartesian when
+// s is NULL (face normals e_d, Eq. (2) with the spacings h); else curvilinear:
+// Roe's flux through the face area vectors s, Eq. (2) in index units and a
+// final division by jinv.  Arguments checked by the callers.
+void wcns5_residual_core(const double* q_dev, const double* s_dev, const double* jinv_dev, double* r_dev,
+                         void* work_dev, size_t work_bytes, const int32_t n[3], const double* h, double gamma,
+                         double entropy_fix, double eps, hipStream_t stream) {
+  if (!(gamma > 1.0) || !std::isfinite(gamma)) host_fail(CFD_EINVAL, "gamma must exceed 1");
+  if (!(entropy_fix >= 0.0) || !std::isfinite(entropy_fix)) host_fail(CFD_EINVAL, "bad entropy_fix");
+  if (!(eps > 0.0) || !std::isfinite(eps)) host_fail(CFD_EINVAL, "eps must be positive and finite");
+  int64_t pmax, fmax;
+  wcns5_work(n, pmax, fmax);
+  const size_t need = (size_t)(8 * (pmax + 3 * fmax));
+  if (work_bytes < need) host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_euler_work_bytes()");
+  const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+  if (!apart(q_dev, 40 * cells, r_dev, 40 * cells) || !apart(q_dev, 40 * cells, work_dev, (int64_t)need) ||
+      !apart(r_dev, 40 * cells, work_dev, (int64_t)need))
+    host_fail(CFD_EINVAL, "q, r and the workspace must not overlap");
+  if (s_dev && (!apart(r_dev, 40 * cells, s_dev, 72 * cells) || !apart(r_dev, 40 * cells, jinv_dev, 8 * cells) ||
+                !apart(work_dev, (int64_t)need, s_dev, 72 * cells) ||
+                !apart(work_dev, (int64_t)need, jinv_dev, 8 * cells)))
+    host_fail(CFD_EINVAL, "r and the workspace must not overlap the metrics");
+  double* W = static_cast<double*>(work_dev);
+  double* WL = W + pmax;
+  double* WR = WL + fmax;
+  double* F = WR + fmax;
+  Gas<double> gas{};
+  gas.gamma = gamma;
+  gas.gm1 = gamma - 1.0;
+  gas.gg = gamma / (gamma - 1.0);
+  gas.eps_h = entropy_fix;
+  for (int d = 0; d < 3; ++d) {
+    int64_t mp[3] = {n[0], n[1], n[2]}, mf[3] = {n[0], n[1], n[2]};
+    mp[d] += 10;
+    mf[d] += 5;
+    const int64_t nf = mf[0] * mf[1] * mf[2];
+    hipLaunchKernelGGL(k_pad_prim_periodic, dim3(grid_for(mp[0] * mp[1] * mp[2])), dim3(256), 0, stream, q_dev, W,
+                       n[0], n[1], n[2], d, gamma - 1.0);
+    launch_window6(W, WL, WR, mf, d, 5, Wcns5Op{eps}, stream);
+    if (s_dev)
+      hipLaunchKernelGGL(k_roe_faces_curv, dim3(grid_for(nf)), dim3(256), 0, stream, WL, WR, s_dev + 3 * d * cells, F,
+                         (int)mf[0], (int)mf[1], (int)mf[2], d, n[0], n[1], n[2], gas);
+    else
+      hipLaunchKernelGGL(k_roe_faces, dim3(grid_for(nf)), dim3(256), 0, stream, WL, WR, F, nf, d, gas);
+    const int64_t m[3] = {n[0], n[1], n[2]};
+    const double hd = s_dev ? 1.0 : h[d];
+    const double c1 = 75.0 / (64.0 * hd), c2 = -25.0 / (384.0 * hd), c3 = 3.0 / (640.0 * hd);
+    if (d == 0)
+      launch_window6(F, r_dev, nullptr, m, d, 5, Eq2OpT<false>{c1, c2, c3}, stream);
+    else
+      launch_window6(F, r_dev, nullptr, m, d, 5, Eq2OpT<true>{c1, c2, c3}, stream);
+  }
+  if (s_dev) hipLaunchKernelGGL(k_div_jinv, dim3(grid_for(cells)), dim3(256), 0, stream, r_dev, jinv_dev, cells);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+}
+
+}  // namespace cfd
+
 extern "C" cfd_status cfd_wcns5_euler_residual_periodic(const double* q_dev, double* r_dev, void* work_dev,
                                                         size_t work_bytes, const int32_t n[3], const double h[3],
                                                         double gamma, double entropy_fix, double eps,
@@ -315,46 +649,45 @@ extern "C" cfd_status cfd_wcns5_euler_residual_periodic(const double* q_dev, dou
     if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
     for (int d = 0; d < 3; ++d)
       if (!(h[d] > 0.0) || !std::isfinite(h[d])) cfd::host_fail(CFD_EINVAL, "spacings must be positive and finite");
-    if (!(gamma > 1.0) || !std::isfinite(gamma)) cfd::host_fail(CFD_EINVAL, "gamma must exceed 1");
-    if (!(entropy_fix >= 0.0) || !std::isfinite(entropy_fix)) cfd::host_fail(CFD_EINVAL, "bad entropy_fix");
-    if (!(eps > 0.0) || !std::isfinite(eps)) cfd::host_fail(CFD_EINVAL, "eps must be positive and finite");
-    int64_t pmax, fmax;
-    cfd::wcns5_work(n, pmax, fmax);
-    const size_t need = (size_t)(8 * (pmax + 3 * fmax));
-    if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_euler_work_bytes()");
+    cfd::wcns5_residual_core(q_dev, nullptr, nullptr, r_dev, work_dev, work_bytes, n, h, gamma, entropy_fix, eps,
+                             stream);
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_metrics_periodic(const double* xv_dev, const double period[9], const int32_t n[3],
+                                                 double* s_dev, double* jinv_dev, hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!xv_dev || !period || !n || !s_dev || !jinv_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    for (int t = 0; t < 9; ++t)
+      if (!std::isfinite(period[t])) cfd::host_fail(CFD_EINVAL, "periods must be finite");
     const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-    auto apart = [](const void* a, int64_t na, const void* b, int64_t nb) {
-      const char *a0 = static_cast<const char*>(a), *b0 = static_cast<const char*>(b);
-      return a0 + na <= b0 || b0 + nb <= a0;
-    };
-    if (!apart(q_dev, 40 * cells, r_dev, 40 * cells) || !apart(q_dev, 40 * cells, work_dev, (int64_t)need) ||
-        !apart(r_dev, 40 * cells, work_dev, (int64_t)need))
-      cfd::host_fail(CFD_EINVAL, "q, r and the workspace must not overlap");
-    double* W = static_cast<double*>(work_dev);
-    double* WL = W + pmax;
-    double* WR = WL + fmax;
-    double* F = WR + fmax;
-    cfd::Gas<double> gas{};
-    gas.gamma = gamma;
-    gas.gm1 = gamma - 1.0;
-    gas.gg = gamma / (gamma - 1.0);
-    gas.eps_h = entropy_fix;
+    if (cells > ((int64_t)1 << 34)) cfd::host_fail(CFD_EINVAL, "block too large");
+    if (!cfd::apart(xv_dev, 24 * cells, s_dev, 72 * cells) || !cfd::apart(xv_dev, 24 * cells, jinv_dev, 8 * cells) ||
+        !cfd::apart(s_dev, 72 * cells, jinv_dev, 8 * cells))
+      cfd::host_fail(CFD_EINVAL, "vertices, metrics and jinv must not overlap");
+    cfd::PeriodicGrid g{};
+    g.xv = xv_dev;
     for (int d = 0; d < 3; ++d) {
-      int64_t mp[3] = {n[0], n[1], n[2]}, mf[3] = {n[0], n[1], n[2]};
-      mp[d] += 10;
-      mf[d] += 5;
-      const int64_t nf = mf[0] * mf[1] * mf[2];
-      hipLaunchKernelGGL(cfd::k_pad_prim_periodic, dim3(cfd::grid_for(mp[0] * mp[1] * mp[2])), dim3(256), 0, stream,
-                         q_dev, W, n[0], n[1], n[2], d, gamma - 1.0);
-      cfd::launch_window6(W, WL, WR, mf, d, 5, cfd::Wcns5Op{eps}, stream);
-      hipLaunchKernelGGL(cfd::k_roe_faces, dim3(cfd::grid_for(nf)), dim3(256), 0, stream, WL, WR, F, nf, d, gas);
-      const int64_t m[3] = {n[0], n[1], n[2]};
-      const double c1 = 75.0 / (64.0 * h[d]), c2 = -25.0 / (384.0 * h[d]), c3 = 3.0 / (640.0 * h[d]);
-      if (d == 0)
-        cfd::launch_window6(F, r_dev, nullptr, m, d, 5, cfd::Eq2OpT<false>{c1, c2, c3}, stream);
-      else
-        cfd::launch_window6(F, r_dev, nullptr, m, d, 5, cfd::Eq2OpT<true>{c1, c2, c3}, stream);
+      g.n[d] = n[d];
+      for (int c = 0; c < 3; ++c) g.P[d][c] = period[3 * d + c];
     }
+    const dim3 grid(cfd::grid_for(cells));
+    cfd::launch_metrics(g, s_dev, jinv_dev, cells, stream);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_euler_residual_curv_periodic(const double* q_dev, const double* s_dev,
+                                                             const double* jinv_dev, double* r_dev, void* work_dev,
+                                                             size_t work_bytes, const int32_t n[3], double gamma,
+                                                             double entropy_fix, double eps, hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!q_dev || !s_dev || !jinv_dev || !r_dev || !work_dev || !n) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    cfd::wcns5_residual_core(q_dev, s_dev, jinv_dev, r_dev, work_dev, work_bytes, n, nullptr, gamma, entropy_fix, eps,
+                             stream);
   });
 }
 
@@ -376,6 +709,40 @@ extern "C" cfd_status cfd_wcns5_euler_step_work_bytes(const int32_t n[3], size_t
   });
 }
 
+namespace cfd {
+
+// nsteps RK3 steps in place on q with the residual core (Cartesian when s is
+// NULL).  The workspace: the residual's, then the step's start state and R.
+void wcns5_steps_core(double* q_dev, const double* s_dev, const double* jinv_dev, void* work_dev, size_t work_bytes,
+                      const int32_t n[3], const double* h, double gamma, double entropy_fix, double eps, double dt,
+                      int32_t nsteps, hipStream_t stream) {
+  if (n[0] < 1 || n[1] < 1 || n[2] < 1) host_fail(CFD_EINVAL, "every extent must be >= 1");
+  if (!(dt > 0.0) || !std::isfinite(dt)) host_fail(CFD_EINVAL, "dt must be positive and finite");
+  if (nsteps < 0) host_fail(CFD_EINVAL, "nsteps must be >= 0");
+  const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+  const size_t rw = wcns5_residual_work(n);
+  if (work_bytes < rw + (size_t)2 * 40 * cells)
+    host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_euler_step_work_bytes()");
+  if (!apart(q_dev, 40 * cells, work_dev, (int64_t)work_bytes)) host_fail(CFD_EINVAL, "q and the workspace overlap");
+  if (s_dev && (!apart(q_dev, 40 * cells, s_dev, 72 * cells) || !apart(q_dev, 40 * cells, jinv_dev, 8 * cells)))
+    host_fail(CFD_EINVAL, "q must not overlap the metrics");
+  double* qn = reinterpret_cast<double*>(static_cast<char*>(work_dev) + rw);
+  double* r = qn + 5 * cells;
+  const int64_t nv = 5 * cells;
+  const int g = grid_for(nv);
+  const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
+  for (int it = 0; it < nsteps; ++it)
+    for (int st = 0; st < 3; ++st) {
+      wcns5_residual_core(q_dev, s_dev, jinv_dev, r, work_dev, rw, n, h, gamma, entropy_fix, eps, stream);
+      hipLaunchKernelGGL(k_rk3_stage, dim3(g), dim3(256), 0, stream, q_dev, qn, r, nv, dt, a[st], b[st],
+                         st == 0 ? 1 : 0);
+    }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+}
+
+}  // namespace cfd
+
 extern "C" cfd_status cfd_wcns5_euler_steps_periodic(double* q_dev, void* work_dev, size_t work_bytes,
                                                      const int32_t n[3], const double h[3], double gamma,
                                                      double entropy_fix, double eps, double dt, int32_t nsteps,
@@ -383,29 +750,21 @@ extern "C" cfd_status cfd_wcns5_euler_steps_periodic(double* q_dev, void* work_d
   return cfd::host_guarded([&] {
     if (!q_dev || !work_dev || !n || !h) cfd::host_fail(CFD_EINVAL, "NULL argument");
     if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
-    if (!(dt > 0.0) || !std::isfinite(dt)) cfd::host_fail(CFD_EINVAL, "dt must be positive and finite");
-    if (nsteps < 0) cfd::host_fail(CFD_EINVAL, "nsteps must be >= 0");
-    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-    const size_t rw = wcns5_residual_work(n);
-    if (work_bytes < rw + (size_t)2 * 40 * cells)
-      cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_euler_step_work_bytes()");
-    const char *qa = reinterpret_cast<const char*>(q_dev), *wa = static_cast<const char*>(work_dev);
-    if (qa < wa + work_bytes && wa < qa + 40 * cells) cfd::host_fail(CFD_EINVAL, "q and the workspace overlap");
-    double* qn = reinterpret_cast<double*>(static_cast<char*>(work_dev) + rw);
-    double* r = qn + 5 * cells;
-    const int64_t nv = 5 * cells;
-    const int g = cfd::grid_for(nv);
-    const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
-    for (int it = 0; it < nsteps; ++it)
-      for (int st = 0; st < 3; ++st) {
-        const cfd_status s = cfd_wcns5_euler_residual_periodic(q_dev, r, work_dev, rw, n, h, gamma, entropy_fix,
-                                                               eps, stream);
-        if (s != CFD_OK) cfd::host_fail(s, cfd_last_error(nullptr));
-        hipLaunchKernelGGL(cfd::k_rk3_stage, dim3(g), dim3(256), 0, stream, q_dev, qn, r, nv, dt, a[st], b[st],
-                           st == 0 ? 1 : 0);
-      }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    for (int d = 0; d < 3; ++d)
+      if (!(h[d] > 0.0) || !std::isfinite(h[d])) cfd::host_fail(CFD_EINVAL, "spacings must be positive and finite");
+    cfd::wcns5_steps_core(q_dev, nullptr, nullptr, work_dev, work_bytes, n, h, gamma, entropy_fix, eps, dt, nsteps,
+                          stream);
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_euler_steps_curv_periodic(double* q_dev, const double* s_dev, const double* jinv_dev,
+                                                          void* work_dev, size_t work_bytes, const int32_t n[3],
+                                                          double gamma, double entropy_fix, double eps, double dt,
+                                                          int32_t nsteps, hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!q_dev || !s_dev || !jinv_dev || !work_dev || !n) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    cfd::wcns5_steps_core(q_dev, s_dev, jinv_dev, work_dev, work_bytes, n, nullptr, gamma, entropy_fix, eps, dt,
+                          nsteps, stream);
   });
 }
 
@@ -499,17 +858,81 @@ __global__ void __launch_bounds__(256) k_c4_visc_faces(const double* __restrict_
   }
 }
 
-// r[1 + v] -= (F_{i-3/2} - 27 F_{i-1/2} + 27 F_{i+1/2} - F_{i+3/2}) / 24h, v = 0..3.
+// r[1 + v] -= (F_{i-3/2} - 27 F_{i-1/2} + 27 F_{i+1/2} - F_{i+3/2}) / 24h, v = 0..3;
+// with jinv (curvilinear blocks, h = 1) the difference is divided by J^{-1}.
 __global__ void __launch_bounds__(256) k_c4_flux_sub(const double* __restrict__ fv, double* __restrict__ r, Cells3 C,
-                                                     int d, double ihd) {
+                                                     int d, double ihd, const double* __restrict__ jinv) {
   const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
     const int64_t m2 = C.step(i, j, k, d, -2), m1 = C.step(i, j, k, d, -1), p1 = C.step(i, j, k, d, 1);
     for (int v = 0; v < 4; ++v) {
       const double* F = fv + v * cells;
-      r[(1 + v) * cells + c] -= (F[m2] - 27.0 * F[m1] + 27.0 * F[c] - F[p1]) * (ihd / 24.0);
+      const double dF = (F[m2] - 27.0 * F[m1] + 27.0 * F[c] - F[p1]) * (ihd / 24.0);
+      r[(1 + v) * cells + c] -= jinv ? dF / jinv[c] : dF;
     }
+  }
+}
+
+// Curvilinear blocks: the metrics at the cells, each S_t interpolated from its
+// faces along t: sc[(t * 3 + x) * cells + c] (faces i + 1/2 at index i).
+__global__ void __launch_bounds__(256) k_c4_cell_metrics(const double* __restrict__ s, double* __restrict__ sc,
+                                                         Cells3 C) {
+  const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
+    for (int t = 0; t < 3; ++t) {
+      const int64_t m2 = C.step(i, j, k, t, -2), m1 = C.step(i, j, k, t, -1), p1 = C.step(i, j, k, t, 1);
+      for (int x = 0; x < 3; ++x) {
+        const double* f = s + (t * 3 + x) * cells;
+        sc[(t * 3 + x) * cells + c] = (-f[m2] + 9.0 * f[m1] + 9.0 * f[c] - f[p1]) / 16.0;
+      }
+    }
+  }
+}
+
+// Curvilinear viscous flux through face i + 1/2 along d (stored at the index
+// of cell i): face values of u, v, w, T; index derivatives (compact along d,
+// face values of the cell derivatives across); the physical gradient by the
+// chain rule J sum_t S_t d/dxi_t with S_t (t != d) and J^{-1} interpolated to
+// the face; the stress and heat flux contracted with the face's S_d.
+__global__ void __launch_bounds__(256) k_c4_visc_faces_curv(const double* __restrict__ phi,
+                                                            const double* __restrict__ g,
+                                                            const double* __restrict__ s,
+                                                            const double* __restrict__ sc,
+                                                            const double* __restrict__ jinv, double* __restrict__ fv,
+                                                            Cells3 C, int d, Gas<double> gas) {
+  const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
+    const int64_t m1 = C.step(i, j, k, d, -1), p1 = C.step(i, j, k, d, 1), p2 = C.step(i, j, k, d, 2);
+    auto fval = [&](const double* f) { return (-f[m1] + 9.0 * f[c] + 9.0 * f[p1] - f[p2]) / 16.0; };
+    double Sf[3][3], Sd[3];
+    for (int t = 0; t < 3; ++t)
+      for (int x = 0; x < 3; ++x) Sf[t][x] = t == d ? s[(d * 3 + x) * cells + c] : fval(sc + (t * 3 + x) * cells);
+    for (int x = 0; x < 3; ++x) Sd[x] = Sf[d][x];
+    const double Jf = 1.0 / fval(jinv);
+    double pf[4], grad[4][3];
+    for (int a = 0; a < 4; ++a) {
+      const double* f = phi + a * cells;
+      pf[a] = fval(f);
+      double dxi[3];
+      for (int t = 0; t < 3; ++t)
+        dxi[t] = t == d ? (f[m1] - 27.0 * f[c] + 27.0 * f[p1] - f[p2]) * (1.0 / 24.0) : fval(g + (a * 3 + t) * cells);
+      for (int x = 0; x < 3; ++x) grad[a][x] = Jf * (Sf[0][x] * dxi[0] + Sf[1][x] * dxi[1] + Sf[2][x] * dxi[2]);
+    }
+    const double T = pf[3];
+    const double mu = gas.mu_inf * T * sqrt(T) * (1.0 + gas.s_star) / (T + gas.s_star);
+    const double kc = mu * gas.kfac;
+    const double div = grad[0][0] + grad[1][1] + grad[2][2];
+    double tau[3][3];
+    for (int x = 0; x < 3; ++x)
+      for (int y = 0; y < 3; ++y) tau[x][y] = mu * (grad[x][y] + grad[y][x]);
+    for (int x = 0; x < 3; ++x) tau[x][x] = tau[x][x] - (2.0 / 3.0) * mu * div;
+    double e[3];
+    for (int x = 0; x < 3; ++x) e[x] = pf[0] * tau[x][0] + pf[1] * tau[x][1] + pf[2] * tau[x][2] + kc * grad[3][x];
+    for (int m = 0; m < 3; ++m) fv[m * cells + c] = Sd[0] * tau[0][m] + Sd[1] * tau[1][m] + Sd[2] * tau[2][m];
+    fv[3 * cells + c] = Sd[0] * e[0] + Sd[1] * e[1] + Sd[2] * e[2];
   }
 }
 
@@ -560,7 +983,283 @@ extern "C" cfd_status cfd_c4_viscous_add_periodic(const double* q_dev, double* r
     hipLaunchKernelGGL(cfd::k_c4_grads, dim3(gr), dim3(256), 0, stream, phi, g, C, 1.0 / h[0], 1.0 / h[1], 1.0 / h[2]);
     for (int d = 0; d < 3; ++d) {
       hipLaunchKernelGGL(cfd::k_c4_visc_faces, dim3(gr), dim3(256), 0, stream, phi, g, fv, C, d, 1.0 / h[d], gas);
-      hipLaunchKernelGGL(cfd::k_c4_flux_sub, dim3(gr), dim3(256), 0, stream, fv, r_dev, C, d, 1.0 / h[d]);
+      hipLaunchKernelGGL(cfd::k_c4_flux_sub, dim3(gr), dim3(256), 0, stream, fv, r_dev, C, d, 1.0 / h[d],
+                         static_cast<const double*>(nullptr));
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  });
+}
+
+extern "C" cfd_status cfd_c4_viscous_curv_work_bytes(const int32_t n[3], size_t* bytes) {
+  return cfd::host_guarded([&] {
+    if (!n || !bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    *bytes = (size_t)8 * 29 * ((size_t)n[0] * n[1] * n[2]);    // phi, index gradients, face flux, cell metrics
+  });
+}
+
+extern "C" cfd_status cfd_c4_viscous_add_curv_periodic(const double* q_dev, const double* s_dev,
+                                                       const double* jinv_dev, double* r_dev, void* work_dev,
+                                                       size_t work_bytes, const int32_t n[3], double gamma,
+                                                       double prandtl, double mu_inf, double s_star,
+                                                       hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!q_dev || !s_dev || !jinv_dev || !r_dev || !work_dev || !n) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    if (!(gamma > 1.0) || !(prandtl > 0.0) || !(mu_inf >= 0.0) || !(s_star > 0.0) || !std::isfinite(mu_inf))
+      cfd::host_fail(CFD_EINVAL, "bad gas parameters");
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    const size_t need = (size_t)8 * 29 * cells;
+    if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_c4_viscous_curv_work_bytes()");
+    const void* ins[3] = {q_dev, s_dev, jinv_dev};
+    const int64_t in_bytes[3] = {40 * cells, 72 * cells, 8 * cells};
+    for (int t = 0; t < 3; ++t)
+      if (!cfd::apart(ins[t], in_bytes[t], r_dev, 40 * cells) || !cfd::apart(ins[t], in_bytes[t], work_dev, (int64_t)need))
+        cfd::host_fail(CFD_EINVAL, "r and the workspace must not overlap q, the metrics or each other");
+    if (!cfd::apart(r_dev, 40 * cells, work_dev, (int64_t)need))
+      cfd::host_fail(CFD_EINVAL, "r and the workspace must not overlap q, the metrics or each other");
+    double* phi = static_cast<double*>(work_dev);
+    double* g = phi + 4 * cells;
+    double* fv = g + 12 * cells;
+    double* sc = fv + 4 * cells;
+    cfd::Cells3 C{{n[0], n[1], n[2]}};
+    cfd::Gas<double> gas{};
+    gas.gamma = gamma;
+    gas.gm1 = gamma - 1.0;
+    gas.mu_inf = mu_inf;
+    gas.s_star = s_star;
+    gas.prandtl = prandtl;
+    gas.kfac = gamma / ((gamma - 1.0) * prandtl);
+    const int gr = cfd::grid_for(cells);
+    hipLaunchKernelGGL(cfd::k_c4_phi, dim3(gr), dim3(256), 0, stream, q_dev, phi, cells, gamma - 1.0);
+    hipLaunchKernelGGL(cfd::k_c4_grads, dim3(gr), dim3(256), 0, stream, phi, g, C, 1.0, 1.0, 1.0);
+    hipLaunchKernelGGL(cfd::k_c4_cell_metrics, dim3(gr), dim3(256), 0, stream, s_dev, sc, C);
+    for (int d = 0; d < 3; ++d) {
+      hipLaunchKernelGGL(cfd::k_c4_visc_faces_curv, dim3(gr), dim3(256), 0, stream, phi, g, s_dev, sc, jinv_dev, fv,
+                         C, d, gas);
+      hipLaunchKernelGGL(cfd::k_c4_flux_sub, dim3(gr), dim3(256), 0, stream, fv, r_dev, C, d, 1.0, jinv_dev);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  });
+}
+
+// ------------------------------------------------------------ time step
+// The paper leaves the step size open; the finite-volume path's reading on
+// these blocks: dt_c = CFL J^{-1} / (sum_d L_d + 4 sum_d Lv_d) with
+// L_d = |u . Sb_d| + c |Sb_d|, Lv_d = max(4/3, gamma/Pr)(mu/rho)|Sb_d|^2/J^{-1}
+// (viscous flow only), Sb_d the mean of the cell's two d-face area vectors;
+// the step is the least dt_c.  Each workgroup reduces its cells in LDS and
+// takes one atomic minimum on the bits of the result (ordered like the
+// values for positive doubles, so the outcome does not depend on the order).
+namespace cfd {
+
+__global__ void k_dt_init(unsigned long long* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = 0x7FF0000000000000ull;   // +inf
+}
+
+__global__ void __launch_bounds__(256) k_cfl_dt_curv(const double* __restrict__ q, const double* __restrict__ s,
+                                                     const double* __restrict__ jinv, Cells3 C, Gas<double> gas,
+                                                     double cfl, int viscous, unsigned long long* out) {
+  __shared__ double red[256];
+  const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
+  const double coef = fmax(4.0 / 3.0, gas.gamma / gas.prandtl);
+  double best = __longlong_as_double(0x7FF0000000000000ll);
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
+    const Prim<double> p = to_prim<double>(q[c], q[cells + c], q[2 * cells + c], q[3 * cells + c], q[4 * cells + c],
+                                           gas.gm1);
+    const double a = sqrt(gas.gamma * p.p / p.r);
+    const double V = jinv[c];
+    double mu = 0.0;
+    if (viscous) {
+      const double T = p.p / p.r;
+      mu = gas.mu_inf * T * sqrt(T) * (1.0 + gas.s_star) / (T + gas.s_star);
+    }
+    double lam = 0.0, lamv = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const int64_t lo = C.step(i, j, k, d, -1);
+      const double* sd = s + 3 * d * cells;
+      const double bx = 0.5 * (sd[lo] + sd[c]), by = 0.5 * (sd[cells + lo] + sd[cells + c]),
+                   bz = 0.5 * (sd[2 * cells + lo] + sd[2 * cells + c]);
+      const double mag = sqrt(bx * bx + by * by + bz * bz);
+      lam = lam + (fabs(p.u * bx + p.v * by + p.w * bz) + a * mag);
+      if (viscous) lamv = lamv + coef * (mu / p.r) * mag * mag / V;
+    }
+    double dt = cfl * V / (lam + 4.0 * lamv);
+    if (!(dt > 0.0)) dt = 0.0;                  // a non-physical cell or J^{-1} <= 0 gives a step of 0
+    best = fmin(best, dt);
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMin(out, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+}  // namespace cfd
+
+extern "C" cfd_status cfd_wcns5_time_step_curv_periodic(const double* q_dev, const double* s_dev,
+                                                        const double* jinv_dev, const int32_t n[3], double gamma,
+                                                        double cfl, int32_t viscous, double prandtl, double mu_inf,
+                                                        double s_star, double* dt_dev, hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!q_dev || !s_dev || !jinv_dev || !n || !dt_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) cfd::host_fail(CFD_EINVAL, "gamma must exceed 1");
+    if (!(cfl > 0.0) || !std::isfinite(cfl)) cfd::host_fail(CFD_EINVAL, "cfl must be positive and finite");
+    if (viscous && (!(prandtl > 0.0) || !(mu_inf >= 0.0) || !(s_star > 0.0) || !std::isfinite(mu_inf)))
+      cfd::host_fail(CFD_EINVAL, "bad gas parameters");
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    if (!cfd::apart(dt_dev, 8, q_dev, 40 * cells) || !cfd::apart(dt_dev, 8, s_dev, 72 * cells) ||
+        !cfd::apart(dt_dev, 8, jinv_dev, 8 * cells))
+      cfd::host_fail(CFD_EINVAL, "dt must not overlap the inputs");
+    if ((reinterpret_cast<uintptr_t>(dt_dev) & 7) != 0) cfd::host_fail(CFD_EINVAL, "dt must be 8-byte aligned");
+    cfd::Cells3 C{{n[0], n[1], n[2]}};
+    cfd::Gas<double> gas{};
+    gas.gamma = gamma;
+    gas.gm1 = gamma - 1.0;
+    gas.mu_inf = mu_inf;
+    gas.s_star = s_star;
+    gas.prandtl = viscous ? prandtl : 1.0;
+    auto* out = reinterpret_cast<unsigned long long*>(dt_dev);
+    hipLaunchKernelGGL(cfd::k_dt_init, dim3(1), dim3(64), 0, stream, out);
+    hipLaunchKernelGGL(cfd::k_cfl_dt_curv, dim3(cfd::grid_for(cells)), dim3(256), 0, stream, q_dev, s_dev, jinv_dev, C,
+                       gas, cfl, viscous ? 1 : 0, out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  });
+}
+
+// ------------------------------------------------------------ block seams
+extern "C" cfd_status cfd_wcns5_metrics_ext(const double* xe_dev, const int32_t n[3], double* s_dev, double* jinv_dev,
+                                            hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!xe_dev || !n || !s_dev || !jinv_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    if (cells > ((int64_t)1 << 34)) cfd::host_fail(CFD_EINVAL, "block too large");
+    const int64_t ecells = (int64_t)(n[0] + 5) * (n[1] + 5) * (n[2] + 5);
+    if (!cfd::apart(xe_dev, 24 * ecells, s_dev, 72 * cells) || !cfd::apart(xe_dev, 24 * ecells, jinv_dev, 8 * cells) ||
+        !cfd::apart(s_dev, 72 * cells, jinv_dev, 8 * cells))
+      cfd::host_fail(CFD_EINVAL, "vertices, metrics and jinv must not overlap");
+    cfd::ExtGrid g{xe_dev, {n[0], n[1], n[2]}};
+    cfd::launch_metrics(g, s_dev, jinv_dev, cells, stream);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  });
+}
+
+namespace {
+
+// Checks the face-to-face table: every neighbour in range, the link returned
+// by the neighbour's opposite face, the same transverse extents, at least
+// five cells across the seam.  Returns the largest residual workspace.
+size_t check_seams(int32_t nblk, const int32_t* dims, const int32_t* nbr) {
+  if (nblk < 1 || nblk > 65536) cfd::host_fail(CFD_EINVAL, "nblk must be in [1, 65536]");
+  if (!dims || !nbr) cfd::host_fail(CFD_EINVAL, "NULL argument");
+  size_t most = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const int32_t* n = dims + 3 * b;
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    if ((int64_t)n[0] * n[1] * n[2] > ((int64_t)1 << 34)) cfd::host_fail(CFD_EINVAL, "block too large");
+  }
+  for (int b = 0; b < nblk; ++b) {
+    const int32_t* n = dims + 3 * b;
+    for (int f = 0; f < 6; ++f) {
+      const int d = f / 2, c = nbr[6 * b + f];
+      if (c < 0 || c >= nblk) cfd::host_fail(CFD_EINVAL, "neighbour index out of range");
+      if (nbr[6 * c + (f ^ 1)] != b) cfd::host_fail(CFD_EINVAL, "neighbour links must be mutual (face f <-> f^1)");
+      for (int t = 0; t < 3; ++t)
+        if (t != d && dims[3 * c + t] != n[t]) cfd::host_fail(CFD_EINVAL, "joined faces must have the same extents");
+      if (dims[3 * c + d] < 5) cfd::host_fail(CFD_EINVAL, "a neighbour must be at least 5 cells across the seam");
+    }
+    int64_t pmax, fmax;
+    cfd::wcns5_work(n, pmax, fmax);
+    most = std::max(most, (size_t)(8 * (pmax + 3 * fmax)));
+  }
+  return most;
+}
+
+}  // namespace
+
+extern "C" cfd_status cfd_wcns5_euler_blocks_work_bytes(int32_t nblk, const int32_t* dims, const int32_t* nbr,
+                                                        size_t* bytes) {
+  return cfd::host_guarded([&] {
+    if (!bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    *bytes = check_seams(nblk, dims, nbr);
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_t* dims, const int32_t* nbr,
+                                                      const double* const* q_dev, const double* const* s_dev,
+                                                      const double* const* jinv_dev, double* const* r_dev,
+                                                      void* work_dev, size_t work_bytes, double gamma,
+                                                      double entropy_fix, double eps, hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    const size_t need = check_seams(nblk, dims, nbr);
+    if (!q_dev || !s_dev || !jinv_dev || !r_dev || !work_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) cfd::host_fail(CFD_EINVAL, "gamma must exceed 1");
+    if (!(entropy_fix >= 0.0) || !std::isfinite(entropy_fix)) cfd::host_fail(CFD_EINVAL, "bad entropy_fix");
+    if (!(eps > 0.0) || !std::isfinite(eps)) cfd::host_fail(CFD_EINVAL, "eps must be positive and finite");
+    if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_euler_blocks_work_bytes()");
+    auto cells_of = [&](int b) { return (int64_t)dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2]; };
+    for (int b = 0; b < nblk; ++b) {
+      if (!q_dev[b] || !s_dev[b] || !jinv_dev[b] || !r_dev[b]) cfd::host_fail(CFD_EINVAL, "NULL block pointer");
+      const int64_t cb = cells_of(b);
+      if (!cfd::apart(r_dev[b], 40 * cb, work_dev, (int64_t)need))
+        cfd::host_fail(CFD_EINVAL, "a residual overlaps the workspace");
+      for (int c = 0; c < nblk; ++c) {
+        const int64_t cc = cells_of(c);
+        if (!cfd::apart(r_dev[b], 40 * cb, q_dev[c], 40 * cc) || !cfd::apart(r_dev[b], 40 * cb, s_dev[c], 72 * cc) ||
+            !cfd::apart(r_dev[b], 40 * cb, jinv_dev[c], 8 * cc) ||
+            (c != b && !cfd::apart(r_dev[b], 40 * cb, r_dev[c], 40 * cc)))
+          cfd::host_fail(CFD_EINVAL, "a residual overlaps an input or another residual");
+        if (!cfd::apart(work_dev, (int64_t)need, q_dev[c], 40 * cc) ||
+            !cfd::apart(work_dev, (int64_t)need, s_dev[c], 72 * cc) ||
+            !cfd::apart(work_dev, (int64_t)need, jinv_dev[c], 8 * cc))
+          cfd::host_fail(CFD_EINVAL, "the workspace overlaps an input");
+      }
+    }
+    cfd::Gas<double> gas{};
+    gas.gamma = gamma;
+    gas.gm1 = gamma - 1.0;
+    gas.gg = gamma / (gamma - 1.0);
+    gas.eps_h = entropy_fix;
+    for (int b = 0; b < nblk; ++b) {
+      const int32_t* n = dims + 3 * b;
+      int64_t pmax, fmax;
+      cfd::wcns5_work(n, pmax, fmax);
+      double* W = static_cast<double*>(work_dev);
+      double* WL = W + pmax;
+      double* WR = WL + fmax;
+      double* F = WR + fmax;
+      const int64_t cells = cells_of(b);
+      for (int d = 0; d < 3; ++d) {
+        const int lo = nbr[6 * b + 2 * d], hi = nbr[6 * b + 2 * d + 1];
+        const int nlo = dims[3 * lo + d], nhi = dims[3 * hi + d];
+        int64_t mp[3] = {n[0], n[1], n[2]}, mf[3] = {n[0], n[1], n[2]};
+        mp[d] += 10;
+        mf[d] += 5;
+        const int64_t nf = mf[0] * mf[1] * mf[2];
+        hipLaunchKernelGGL(cfd::k_pad_prim_blocks, dim3(cfd::grid_for(mp[0] * mp[1] * mp[2])), dim3(256), 0, stream,
+                           q_dev[b], q_dev[lo], q_dev[hi], W, n[0], n[1], n[2], d, nlo, nhi, gamma - 1.0);
+        cfd::launch_window6(W, WL, WR, mf, d, 5, cfd::Wcns5Op{eps}, stream);
+        hipLaunchKernelGGL(cfd::k_roe_faces_blocks, dim3(cfd::grid_for(nf)), dim3(256), 0, stream, WL, WR, s_dev[b],
+                           s_dev[lo], s_dev[hi], F, (int)mf[0], (int)mf[1], (int)mf[2], d, n[0], n[1], n[2], nlo, nhi,
+                           gas);
+        const int64_t m[3] = {n[0], n[1], n[2]};
+        const double c1 = 75.0 / 64.0, c2 = -25.0 / 384.0, c3 = 3.0 / 640.0;
+        if (d == 0)
+          cfd::launch_window6(F, r_dev[b], nullptr, m, d, 5, cfd::Eq2OpT<false>{c1, c2, c3}, stream);
+        else
+          cfd::launch_window6(F, r_dev[b], nullptr, m, d, 5, cfd::Eq2OpT<true>{c1, c2, c3}, stream);
+      }
+      hipLaunchKernelGGL(cfd::k_div_jinv, dim3(cfd::grid_for(cells)), dim3(256), 0, stream, r_dev[b], jinv_dev[b],
+                         cells);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));

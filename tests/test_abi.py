@@ -205,3 +205,122 @@ def test_c4_viscous_bad_arguments():
         st = L.cfd_c4_viscous_add_periodic(a["q"], a["r"], a["w"], a["wb"], n, h, a["g"], a["pr"], a["mu"], 0.38,
                                            None)
         assert st == st_want, kw
+
+
+def test_curvilinear_metrics_and_residual_bad_arguments():
+    L = B.lib()
+    n = (C.c_int32 * 3)(8, 4, 2)
+    per = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
+    xv, s, j = C.c_void_p(0x100000), C.c_void_p(0x900000), C.c_void_p(0x1100000)
+    ok = dict(xv=xv, per=per, n=n, s=s, j=j)
+    bad = [dict(xv=None), dict(per=None), dict(s=None), dict(j=None), dict(n=(C.c_int32 * 3)(8, 0, 2)),
+           dict(per=(C.c_double * 9)(1, 0, 0, 0, float("nan"), 0, 0, 0, 1)), dict(s=xv),
+           dict(j=C.c_void_p(0x900000 + 8 * 64))]
+    for b in bad:
+        a = dict(ok, **b)
+        assert L.cfd_wcns5_metrics_periodic(a["xv"], a["per"], a["n"], a["s"], a["j"], None) == -1, b
+    nb = C.c_size_t()
+    assert L.cfd_wcns5_euler_work_bytes(n, C.byref(nb)) == 0
+    q, r, w = C.c_void_p(0x2100000), C.c_void_p(0x2900000), C.c_void_p(0x3100000)
+    ok = dict(q=q, s=s, j=j, r=r, w=w, wb=nb.value, n=n, g=1.4, ef=0.1, eps=1e-6)
+    bad = {-2: [dict(wb=nb.value - 8)],
+           -1: [dict(q=None), dict(s=None), dict(j=None), dict(r=None), dict(w=None), dict(g=1.0), dict(ef=-0.1),
+                dict(eps=0.0), dict(n=(C.c_int32 * 3)(0, 4, 2)), dict(r=q), dict(r=s),
+                dict(j=C.c_void_p(0x2900000 + 8 * 10)), dict(w=C.c_void_p(0x900000 + 8 * 100))]}
+    for st_want, cases_ in bad.items():
+        for b in cases_:
+            a = dict(ok, **b)
+            st = L.cfd_wcns5_euler_residual_curv_periodic(a["q"], a["s"], a["j"], a["r"], a["w"], a["wb"], a["n"],
+                                                          a["g"], a["ef"], a["eps"], None)
+            assert st == st_want, b
+
+
+def test_curvilinear_steps_bad_arguments():
+    L = B.lib()
+    n = (C.c_int32 * 3)(8, 4, 2)
+    nb = C.c_size_t()
+    assert L.cfd_wcns5_euler_step_work_bytes(n, C.byref(nb)) == 0
+    q, s, j, w = C.c_void_p(0x100000), C.c_void_p(0x900000), C.c_void_p(0x1100000), C.c_void_p(0x2100000)
+    ok = dict(q=q, s=s, j=j, w=w, wb=nb.value, n=n, g=1.4, ef=0.1, eps=1e-6, dt=0.01, ns=2)
+    bad = {-2: [dict(wb=nb.value - 8)],
+           -1: [dict(q=None), dict(s=None), dict(j=None), dict(w=None), dict(dt=0.0), dict(ns=-1), dict(g=1.0),
+                dict(n=(C.c_int32 * 3)(8, 4, 0)), dict(s=C.c_void_p(0x100000 + 8 * 4)),
+                dict(w=C.c_void_p(0x100000 + 8))]}
+    for st_want, cases_ in bad.items():
+        for b in cases_:
+            a = dict(ok, **b)
+            st = L.cfd_wcns5_euler_steps_curv_periodic(a["q"], a["s"], a["j"], a["w"], a["wb"], a["n"], a["g"],
+                                                       a["ef"], a["eps"], a["dt"], a["ns"], None)
+            assert st == st_want, b
+
+
+def test_curvilinear_viscous_bad_arguments():
+    L = B.lib()
+    n = (C.c_int32 * 3)(8, 4, 2)
+    nb = C.c_size_t()
+    assert L.cfd_c4_viscous_curv_work_bytes(n, C.byref(nb)) == 0
+    assert nb.value == 8 * 29 * 64
+    q, s, j, r, w = (C.c_void_p(a) for a in (0x100000, 0x900000, 0x1100000, 0x2100000, 0x3100000))
+    ok = dict(q=q, s=s, j=j, r=r, w=w, wb=nb.value, n=n, g=1.4, pr=0.72, mu=1e-3, ss=0.38)
+    bad = {-2: [dict(wb=nb.value - 8)],
+           -1: [dict(q=None), dict(s=None), dict(j=None), dict(r=None), dict(w=None), dict(g=1.0), dict(pr=0.0),
+                dict(mu=-1.0), dict(ss=0.0), dict(n=(C.c_int32 * 3)(8, 4, 0)), dict(r=q), dict(r=s),
+                dict(r=C.c_void_p(0x1100000 - 8)), dict(w=C.c_void_p(0x2100000 + 8))]}
+    for st_want, cases_ in bad.items():
+        for b in cases_:
+            a = dict(ok, **b)
+            st = L.cfd_c4_viscous_add_curv_periodic(a["q"], a["s"], a["j"], a["r"], a["w"], a["wb"], a["n"], a["g"],
+                                                    a["pr"], a["mu"], a["ss"], None)
+            assert st == st_want, b
+
+
+def test_curvilinear_time_step_bad_arguments():
+    L = B.lib()
+    n = (C.c_int32 * 3)(8, 4, 2)
+    q, s, j, dt = (C.c_void_p(a) for a in (0x100000, 0x900000, 0x1100000, 0x2100000))
+    ok = dict(q=q, s=s, j=j, n=n, g=1.4, cfl=0.5, v=1, pr=0.72, mu=1e-3, ss=0.38, dt=dt)
+    bad = [dict(q=None), dict(s=None), dict(j=None), dict(dt=None), dict(n=(C.c_int32 * 3)(0, 4, 2)), dict(g=1.0),
+           dict(cfl=0.0), dict(cfl=float("inf")), dict(pr=0.0), dict(mu=-1.0), dict(ss=0.0),
+           dict(dt=C.c_void_p(0x100000 + 8)), dict(dt=C.c_void_p(0x2100004))]
+    for b in bad:
+        a = dict(ok, **b)
+        st = L.cfd_wcns5_time_step_curv_periodic(a["q"], a["s"], a["j"], a["n"], a["g"], a["cfl"], a["v"], a["pr"],
+                                                 a["mu"], a["ss"], a["dt"], None)
+        assert st == -1, b
+
+
+def test_block_seams_bad_arguments():
+    L = B.lib()
+    # two blocks 8 x 6 x 5 side by side along i, each its own neighbour along j and k
+    dims = (C.c_int32 * 6)(8, 6, 5, 8, 6, 5)
+    nbr = (C.c_int32 * 12)(1, 1, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1)
+    nb = C.c_size_t()
+    assert L.cfd_wcns5_euler_blocks_work_bytes(2, dims, nbr, C.byref(nb)) == 0
+    # largest padded direction k (5 + 10 cells, 5 + 5 faces over 48 lines): 5*48*15 + 3 * 5*48*10
+    assert nb.value == 8 * (5 * 48 * 15 + 3 * 5 * 48 * 10)
+    bad_tables = [(C.c_int32 * 12)(1, 1, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2),      # out of range
+                  (C.c_int32 * 12)(1, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1)]      # not mutual
+    for t in bad_tables:
+        assert L.cfd_wcns5_euler_blocks_work_bytes(2, dims, t, C.byref(nb)) == -1
+    assert L.cfd_wcns5_euler_blocks_work_bytes(2, (C.c_int32 * 6)(8, 6, 5, 8, 7, 5), nbr, C.byref(nb)) == -1
+    assert L.cfd_wcns5_euler_blocks_work_bytes(2, (C.c_int32 * 6)(8, 6, 4, 8, 6, 4), nbr, C.byref(nb)) == -1
+    assert L.cfd_wcns5_euler_blocks_work_bytes(0, dims, nbr, C.byref(nb)) == -1
+    assert L.cfd_wcns5_euler_blocks_work_bytes(2, dims, nbr, C.byref(nb)) == 0
+    P = lambda *a: (C.c_void_p * 2)(*[C.c_void_p(v) for v in a])         # noqa: E731
+    q, s, j, r = P(0x100000, 0x200000), P(0x300000, 0x400000), P(0x500000, 0x600000), P(0x700000, 0x800000)
+    w = C.c_void_p(0x900000)
+    ok = dict(q=q, s=s, j=j, r=r, w=w, wb=nb.value, g=1.4, ef=0.1, eps=1e-6)
+    bad = {-2: [dict(wb=nb.value - 8)],
+           -1: [dict(q=None), dict(w=None), dict(g=1.0), dict(eps=0.0), dict(r=P(0x700000, 0x700000 + 8)),
+                dict(r=P(0x100000, 0x800000)), dict(w=C.c_void_p(0x500000)), dict(q=P(0x100000, 0))]}
+    for st_want, cases_ in bad.items():
+        for b in cases_:
+            a = dict(ok, **b)
+            st = L.cfd_wcns5_euler_residual_blocks(2, dims, nbr, a["q"], a["s"], a["j"], a["r"], a["w"], a["wb"],
+                                                   a["g"], a["ef"], a["eps"], None)
+            assert st == st_want, b
+    xe = C.c_void_p(0x100000)
+    n = (C.c_int32 * 3)(8, 6, 5)
+    for b in (dict(xe=None), dict(s=None), dict(n=(C.c_int32 * 3)(8, 0, 6)), dict(s=xe)):
+        a = dict(dict(xe=xe, n=n, s=C.c_void_p(0x900000), j=C.c_void_p(0xA00000)), **b)
+        assert L.cfd_wcns5_metrics_ext(a["xe"], a["n"], a["s"], a["j"], None) == -1, b

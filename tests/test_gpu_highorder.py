@@ -3,6 +3,9 @@ Eq. 2) through the C ABI, against the FP64 oracle on the same seeded face
 fields: every direction, ragged extents, one cell along the direction, one
 variable; at a full block size by sampled cells; and the exactness on
 polynomials up to degree 6 that pins the oracle, on the GPU's own output.
+The WCNS-E-5 edges, the periodic Cartesian residual, RK3 steps and the
+fourth-order viscous terms follow, each against the oracle and by the
+properties that pin it (curvilinear blocks: test_gpu_zcurvilinear.py).
 
 Tolerance: the kernel may fuse the three products into FMAs, the oracle
 rounds each; the terms reach about 2.7 max|F| / h and a few roundings
