@@ -32,7 +32,8 @@ Test infrastructure, like the rest of this package.  Two operators:
    viscous flux through each face's area vector (reading stated below);
 8. the CFL time step on such blocks (cfl_time_step_curv_periodic), and
    blocks joined face to face (wcns5_euler_residual_blocks, block_vertices):
-   the stencils run across seams with a five-cell exchange.
+   the stencils run across seams with a five-cell exchange, and the viscous
+   terms across the same seams (viscous_residual_blocks).
 
 Section 2.2, Eq. (2): the cell-centred derivative of a face-centred flux F
 along one index direction with grid size h,
@@ -447,3 +448,77 @@ def wcns5_euler_residual_blocks(Qs, Ss, Jinvs, nbr, gamma: float, eps_h: float, 
             R = R + staggered_diff6(F, d, 1.0)
         out.append(R / Jinv)
     return out
+
+
+def viscous_residual_blocks(Qs, Ss, Jinvs, nbr, gamma: float, prandtl: float, mu_inf: float, s_star: float):
+    """-div F_v of curvilinear blocks joined face to face (nbr as for
+    wcns5_euler_residual_blocks): the terms of viscous_residual_curv_periodic
+    with every four-point stencil running across the seams.  Each field is
+    padded along the stencil's direction with the neighbours' values (their
+    cell derivatives and cell metrics are their own), the periodic operator
+    applied and the padding cropped, so a block that is its own neighbour is
+    the periodic block."""
+    from .flux import primitives, sutherland
+    nb = len(Qs)
+    axis = [2, 1, 0]                                          # axis of direction d within a [k, j, i] field
+
+    def pad(fields, b, d, below, above, lead=0):
+        """fields[b]: array whose axis lead + axis[d] runs along d."""
+        ax = lead + axis[d]
+        lo, hi = nbr[b][2 * d], nbr[b][2 * d + 1]
+        nlo = fields[lo].shape[ax]
+        return np.concatenate([_win(fields[lo], ax, nlo - below, below), fields[b],
+                               _win(fields[hi], ax, 0, above)], axis=ax)
+
+    def crop(f, d, below, n, lead=0):
+        return _win(f, lead + axis[d], below, n)
+
+    Ws = [primitives(Q, gamma) for Q in Qs]
+    phis = [np.stack([W[1], W[2], W[3], W[4] / W[0]]) for W in Ws]            # [4, k, j, i]
+    dims = [(Q.shape[3], Q.shape[2], Q.shape[1]) for Q in Qs]
+    Gs = []
+    for b in range(nb):                                                         # G[a][t] at the cells
+        G = [[None] * 3 for _ in range(4)]
+        for t in range(3):
+            p = pad(phis, b, t, 2, 2, lead=1)
+            for a in range(4):
+                G[a][t] = crop(c4_cell_deriv(p[a], axis[t], 1.0), t, 2, dims[b][t])
+        Gs.append(np.stack([np.stack(G[a]) for a in range(4)]))                 # [4, 3, k, j, i]
+    Scs = []
+    for b in range(nb):                                                         # metrics at the cells
+        Scs.append(np.stack([crop(c4_face_to_cell(pad([S[t] for S in Ss], b, t, 2, 1, lead=1), 1 + axis[t]),
+                                  t, 2, dims[b][t], lead=1) for t in range(3)]))
+    Rvs = [np.zeros_like(Q) for Q in Qs]
+    for d in range(3):
+        ax = axis[d]
+        Fvs = []
+        for b in range(nb):
+            n = dims[b][d]
+            ph = pad(phis, b, d, 1, 2, lead=1)
+            G = pad(Gs, b, d, 1, 2, lead=2)
+            Sc = pad(Scs, b, d, 1, 2, lead=2)
+            Jp = pad(Jinvs, b, d, 1, 2)
+            fv = lambda f, lead=0: crop(c4_face_value(f, lead + ax), d, 1, n, lead)         # noqa: E731
+            pf = [fv(ph[a]) for a in range(4)]
+            dxi = [[crop(c4_face_deriv(ph[a], ax, 1.0), d, 1, n) if t == d else fv(G[a][t]) for t in range(3)]
+                   for a in range(4)]
+            Sf = [Ss[b][d] if t == d else fv(Sc[t], 1) for t in range(3)]
+            Jf = 1.0 / fv(Jp)
+            grad = [[Jf * (Sf[0][x] * dxi[a][0] + Sf[1][x] * dxi[a][1] + Sf[2][x] * dxi[a][2]) for x in range(3)]
+                    for a in range(4)]
+            mu = sutherland(pf[3], mu_inf, s_star)
+            kc = mu * gamma / ((gamma - 1.0) * prandtl)
+            div = grad[0][0] + grad[1][1] + grad[2][2]
+            tau = [[mu * (grad[x][y] + grad[y][x]) for y in range(3)] for x in range(3)]
+            for x in range(3):
+                tau[x][x] = tau[x][x] - (2.0 / 3.0) * mu * div
+            e = [pf[0] * tau[x][0] + pf[1] * tau[x][1] + pf[2] * tau[x][2] + kc * grad[3][x] for x in range(3)]
+            S = Ss[b][d]
+            F = [S[0] * tau[0][m] + S[1] * tau[1][m] + S[2] * tau[2][m] for m in range(3)]
+            F.append(S[0] * e[0] + S[1] * e[1] + S[2] * e[2])
+            Fvs.append(np.stack(F))
+        for b in range(nb):
+            Fp = pad(Fvs, b, d, 2, 1, lead=1)
+            for c in range(4):
+                Rvs[b][1 + c] = Rvs[b][1 + c] - crop(c4_flux_diff(Fp[c], ax, 1.0), d, 2, dims[b][d]) / Jinvs[b]
+    return Rvs

@@ -18,7 +18,7 @@ Curvilinear viscous terms: exact reduction to the Cartesian ones, rotation
 equivariance, fourth-order convergence of closed-form shear and conduction
 fields sampled on a wavy grid.  Time step: closed form and rotation
 invariance.  Block seams: a periodic block cut into blocks joined face to face
-gives bitwise its own metrics and residual.
+gives bitwise its own metrics, residual and viscous terms.
 """
 import os
 from fractions import Fraction
@@ -696,3 +696,21 @@ def test_split_periodic_block_gives_the_same_metrics_and_residual():
         assert np.array_equal(Rb, R[:, o[2]:o[2] + e[2], o[1]:o[1] + e[1], o[0]:o[0] + e[0]])
     # one block that is its own neighbour on every face is the periodic block
     assert np.array_equal(ho.wcns5_euler_residual_blocks([q], [S], [Jinv], [[0] * 6], 1.4, 0.1)[0], R)
+
+
+def test_split_periodic_block_gives_the_same_viscous_terms():
+    """The same 12-block split: the curvilinear viscous terms across the seams
+    are bitwise the unsplit block's."""
+    n = (16, 18, 12)
+    Xv, P, _ = _wavy_grid(n, (3.0, 2.0, 1.5), 0.08)
+    S, Jinv = ho.metrics6(ho.periodic_vertices(Xv, P))
+    q, _ = _smooth_state(n, 8)
+    Rv = ho.viscous_residual_curv_periodic(q, S, Jinv, 1.4, 0.72, 0.02, 0.38)
+    lo, m, nbr = _split_box(n, ([7], [5, 11], [6]))
+    sls = [(slice(o[2], o[2] + e[2]), slice(o[1], o[1] + e[1]), slice(o[0], o[0] + e[0])) for o, e in zip(lo, m)]
+    Rs = ho.viscous_residual_blocks([q[(slice(None),) + sl] for sl in sls],
+                                    [S[(slice(None), slice(None)) + sl] for sl in sls], [Jinv[sl] for sl in sls],
+                                    nbr, 1.4, 0.72, 0.02, 0.38)
+    for sl, Rb in zip(sls, Rs):
+        assert np.array_equal(Rb, Rv[(slice(None),) + sl])
+    assert np.array_equal(ho.viscous_residual_blocks([q], [S], [Jinv], [[0] * 6], 1.4, 0.72, 0.02, 0.38)[0], Rv)
