@@ -443,6 +443,20 @@ cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_t* dims, co
                                            size_t work_bytes, double gamma, double entropy_fix, double eps,
                                            hipStream_t stream);
 
+/* The fourth-order viscous terms of cfd_c4_viscous_add_curv_periodic on blocks
+ * joined face to face (the table, extents and pointer arrays as for
+ * cfd_wcns5_euler_residual_blocks): every four-point stencil runs across the
+ * seams, reading the neighbours' u, v, w, T, cell derivatives, cell metrics,
+ * J^{-1} and face fluxes; adds -div F_v to each r_dev[b].  work_dev:
+ * cfd_c4_viscous_blocks_work_bytes() bytes (29 doubles per cell of every
+ * block).  Gas parameters and errors as for the periodic call.  Asynchronous
+ * on stream. */
+cfd_status cfd_c4_viscous_blocks_work_bytes(int32_t nblk, const int32_t* dims, const int32_t* nbr, size_t* bytes);
+cfd_status cfd_c4_viscous_add_blocks(int32_t nblk, const int32_t* dims, const int32_t* nbr, const double* const* q_dev,
+                                     const double* const* s_dev, const double* const* jinv_dev, double* const* r_dev,
+                                     void* work_dev, size_t work_bytes, double gamma, double prandtl, double mu_inf,
+                                     double s_star, hipStream_t stream);
+
 /* The global time step of a periodic curvilinear block for the RK3 steps
  * above (the paper leaves the step size of Eqs. 4-6 open; the finite-volume
  * path's reading): per cell dt_c = cfl J^{-1} / (sum_d L_d + 4 sum_d Lv_d),

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/cfd.h"
 #include "host_services.hpp"
@@ -1260,6 +1261,247 @@ extern "C" cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_
       }
       hipLaunchKernelGGL(cfd::k_div_jinv, dim3(cfd::grid_for(cells)), dim3(256), 0, stream, r_dev[b], jinv_dev[b],
                          cells);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  });
+}
+
+// ------------------------------------------- viscous terms across block seams
+// The curvilinear viscous kernels above with every four-point stencil along
+// d reading across the block's two d-faces: a Line names a family of fields
+// (field f of a block at f * cells + cell) in the block and in its two
+// neighbours along d.  The arithmetic is that of the periodic kernels.
+namespace cfd {
+
+struct Line {
+  const double* own;
+  const double* lo;
+  const double* hi;
+  int64_t cown, clo, chi;  // field strides: the cells of each block
+  int nlo, nhi;            // the neighbours' extents along d
+};
+
+// Field f at the cell s steps along d from (i, j, k) of a block of extents n
+// (|s| <= 2; a neighbour is at least five cells deep).
+__device__ __forceinline__ double line_at(const Line& L, int f, int i, int j, int k, int s, int d, const int n[3]) {
+  int c[3] = {i, j, k};
+  int x = c[d] + s;
+  const double* base = L.own;
+  int64_t cells = L.cown;
+  int nd = n[d];
+  if (x < 0) {
+    base = L.lo;
+    cells = L.clo;
+    x += L.nlo;
+    nd = L.nlo;
+  } else if (x >= n[d]) {
+    base = L.hi;
+    cells = L.chi;
+    x -= n[d];
+    nd = L.nhi;
+  }
+  c[d] = x;
+  const int64_t e0 = d == 0 ? nd : n[0], e1 = d == 1 ? nd : n[1];
+  return base[f * cells + ((int64_t)c[2] * e1 + c[1]) * e0 + c[0]];
+}
+
+struct Dims3 {
+  int n[3];
+};
+
+// g[(a * 3 + t) * cells + c] = index derivative of phi_a along t.
+__global__ void __launch_bounds__(256) k_c4_grads_line(Line phi, double* __restrict__ g, Dims3 D, int t) {
+  const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
+    for (int a = 0; a < 4; ++a) {
+      const double m2 = line_at(phi, a, i, j, k, -2, t, D.n), m1 = line_at(phi, a, i, j, k, -1, t, D.n),
+                   p1 = line_at(phi, a, i, j, k, 1, t, D.n), p2 = line_at(phi, a, i, j, k, 2, t, D.n);
+      g[(a * 3 + t) * cells + c] = (m2 - 8.0 * m1 + 8.0 * p1 - p2) * (1.0 / 12.0);
+    }
+  }
+}
+
+// sc[(t * 3 + x) * cells + c]: S_t at the cells from its faces along t.
+__global__ void __launch_bounds__(256) k_c4_cell_metrics_line(Line S, double* __restrict__ sc, Dims3 D, int t) {
+  const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
+    for (int x = 0; x < 3; ++x) {
+      const int f = t * 3 + x;
+      sc[f * cells + c] = (-line_at(S, f, i, j, k, -2, t, D.n) + 9.0 * line_at(S, f, i, j, k, -1, t, D.n) +
+                           9.0 * line_at(S, f, i, j, k, 0, t, D.n) - line_at(S, f, i, j, k, 1, t, D.n)) /
+                          16.0;
+    }
+  }
+}
+
+// Fields of the per-block viscous workspace: phi 0..3, g 4..15, fv 16..19, sc 20..28.
+constexpr int VW_PHI = 0, VW_G = 4, VW_FV = 16, VW_SC = 20, VW_FIELDS = 29;
+
+__global__ void __launch_bounds__(256) k_c4_visc_faces_line(Line W, Line J, const double* __restrict__ s,
+                                                            double* __restrict__ fv, Dims3 D, int d,
+                                                            Gas<double> gas) {
+  const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
+    auto fvl = [&](const Line& L, int f) {
+      return (-line_at(L, f, i, j, k, -1, d, D.n) + 9.0 * line_at(L, f, i, j, k, 0, d, D.n) +
+              9.0 * line_at(L, f, i, j, k, 1, d, D.n) - line_at(L, f, i, j, k, 2, d, D.n)) /
+             16.0;
+    };
+    double Sf[3][3], Sd[3];
+    for (int t = 0; t < 3; ++t)
+      for (int x = 0; x < 3; ++x) Sf[t][x] = t == d ? s[(d * 3 + x) * cells + c] : fvl(W, VW_SC + t * 3 + x);
+    for (int x = 0; x < 3; ++x) Sd[x] = Sf[d][x];
+    const double Jf = 1.0 / fvl(J, 0);
+    double pf[4], grad[4][3];
+    for (int a = 0; a < 4; ++a) {
+      pf[a] = fvl(W, VW_PHI + a);
+      double dxi[3];
+      for (int t = 0; t < 3; ++t)
+        dxi[t] = t == d ? (line_at(W, VW_PHI + a, i, j, k, -1, d, D.n) - 27.0 * line_at(W, VW_PHI + a, i, j, k, 0, d, D.n) +
+                           27.0 * line_at(W, VW_PHI + a, i, j, k, 1, d, D.n) -
+                           line_at(W, VW_PHI + a, i, j, k, 2, d, D.n)) *
+                              (1.0 / 24.0)
+                        : fvl(W, VW_G + a * 3 + t);
+      for (int x = 0; x < 3; ++x) grad[a][x] = Jf * (Sf[0][x] * dxi[0] + Sf[1][x] * dxi[1] + Sf[2][x] * dxi[2]);
+    }
+    const double T = pf[3];
+    const double mu = gas.mu_inf * T * sqrt(T) * (1.0 + gas.s_star) / (T + gas.s_star);
+    const double kc = mu * gas.kfac;
+    const double div = grad[0][0] + grad[1][1] + grad[2][2];
+    double tau[3][3];
+    for (int x = 0; x < 3; ++x)
+      for (int y = 0; y < 3; ++y) tau[x][y] = mu * (grad[x][y] + grad[y][x]);
+    for (int x = 0; x < 3; ++x) tau[x][x] = tau[x][x] - (2.0 / 3.0) * mu * div;
+    double e[3];
+    for (int x = 0; x < 3; ++x) e[x] = pf[0] * tau[x][0] + pf[1] * tau[x][1] + pf[2] * tau[x][2] + kc * grad[3][x];
+    for (int m = 0; m < 3; ++m) fv[m * cells + c] = Sd[0] * tau[0][m] + Sd[1] * tau[1][m] + Sd[2] * tau[2][m];
+    fv[3 * cells + c] = Sd[0] * e[0] + Sd[1] * e[1] + Sd[2] * e[2];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_c4_flux_sub_line(Line W, double* __restrict__ r,
+                                                          const double* __restrict__ jinv, Dims3 D, int d) {
+  const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
+    for (int v = 0; v < 4; ++v) {
+      const int f = VW_FV + v;
+      const double dF = (line_at(W, f, i, j, k, -2, d, D.n) - 27.0 * line_at(W, f, i, j, k, -1, d, D.n) +
+                         27.0 * line_at(W, f, i, j, k, 0, d, D.n) - line_at(W, f, i, j, k, 1, d, D.n)) *
+                        (1.0 / 24.0);
+      r[(1 + v) * cells + c] -= dF / jinv[c];
+    }
+  }
+}
+
+}  // namespace cfd
+
+namespace {
+
+int64_t block_cells(const int32_t* dims, int b) {
+  return (int64_t)dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+}
+
+}  // namespace
+
+extern "C" cfd_status cfd_c4_viscous_blocks_work_bytes(int32_t nblk, const int32_t* dims, const int32_t* nbr,
+                                                       size_t* bytes) {
+  return cfd::host_guarded([&] {
+    if (!bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    check_seams(nblk, dims, nbr);
+    size_t total = 0;
+    for (int b = 0; b < nblk; ++b) total += (size_t)8 * cfd::VW_FIELDS * block_cells(dims, b);
+    *bytes = total;
+  });
+}
+
+extern "C" cfd_status cfd_c4_viscous_add_blocks(int32_t nblk, const int32_t* dims, const int32_t* nbr,
+                                                const double* const* q_dev, const double* const* s_dev,
+                                                const double* const* jinv_dev, double* const* r_dev, void* work_dev,
+                                                size_t work_bytes, double gamma, double prandtl, double mu_inf,
+                                                double s_star, hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    check_seams(nblk, dims, nbr);
+    if (!q_dev || !s_dev || !jinv_dev || !r_dev || !work_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (!(gamma > 1.0) || !(prandtl > 0.0) || !(mu_inf >= 0.0) || !(s_star > 0.0) || !std::isfinite(mu_inf))
+      cfd::host_fail(CFD_EINVAL, "bad gas parameters");
+    std::vector<int64_t> off(nblk + 1, 0);
+    for (int b = 0; b < nblk; ++b) off[b + 1] = off[b] + cfd::VW_FIELDS * block_cells(dims, b);
+    const size_t need = (size_t)8 * off[nblk];
+    if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_c4_viscous_blocks_work_bytes()");
+    for (int b = 0; b < nblk; ++b) {
+      if (!q_dev[b] || !s_dev[b] || !jinv_dev[b] || !r_dev[b]) cfd::host_fail(CFD_EINVAL, "NULL block pointer");
+      const int64_t cb = block_cells(dims, b);
+      if (!cfd::apart(r_dev[b], 40 * cb, work_dev, (int64_t)need))
+        cfd::host_fail(CFD_EINVAL, "a residual overlaps the workspace");
+      for (int c = 0; c < nblk; ++c) {
+        const int64_t cc = block_cells(dims, c);
+        if (!cfd::apart(r_dev[b], 40 * cb, q_dev[c], 40 * cc) || !cfd::apart(r_dev[b], 40 * cb, s_dev[c], 72 * cc) ||
+            !cfd::apart(r_dev[b], 40 * cb, jinv_dev[c], 8 * cc) ||
+            (c != b && !cfd::apart(r_dev[b], 40 * cb, r_dev[c], 40 * cc)))
+          cfd::host_fail(CFD_EINVAL, "a residual overlaps an input or another residual");
+        if (!cfd::apart(work_dev, (int64_t)need, q_dev[c], 40 * cc) ||
+            !cfd::apart(work_dev, (int64_t)need, s_dev[c], 72 * cc) ||
+            !cfd::apart(work_dev, (int64_t)need, jinv_dev[c], 8 * cc))
+          cfd::host_fail(CFD_EINVAL, "the workspace overlaps an input");
+      }
+    }
+    cfd::Gas<double> gas{};
+    gas.gamma = gamma;
+    gas.gm1 = gamma - 1.0;
+    gas.mu_inf = mu_inf;
+    gas.s_star = s_star;
+    gas.prandtl = prandtl;
+    gas.kfac = gamma / ((gamma - 1.0) * prandtl);
+    double* W = static_cast<double*>(work_dev);
+    // the line along d around block b over per-block arrays (bases), or over
+    // the per-block workspaces when bases is NULL
+    auto line = [&](int b, int d, const double* const* bases) {
+      const int lo = nbr[6 * b + 2 * d], hi = nbr[6 * b + 2 * d + 1];
+      cfd::Line L{};
+      L.own = bases ? bases[b] : W + off[b];
+      L.lo = bases ? bases[lo] : W + off[lo];
+      L.hi = bases ? bases[hi] : W + off[hi];
+      L.cown = block_cells(dims, b);
+      L.clo = block_cells(dims, lo);
+      L.chi = block_cells(dims, hi);
+      L.nlo = dims[3 * lo + d];
+      L.nhi = dims[3 * hi + d];
+      return L;
+    };
+    for (int b = 0; b < nblk; ++b) {
+      const int64_t cb = block_cells(dims, b);
+      hipLaunchKernelGGL(cfd::k_c4_phi, dim3(cfd::grid_for(cb)), dim3(256), 0, stream, q_dev[b], W + off[b], cb,
+                         gamma - 1.0);
+    }
+    for (int b = 0; b < nblk; ++b) {
+      const int64_t cb = block_cells(dims, b);
+      const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
+      for (int t = 0; t < 3; ++t) {
+        hipLaunchKernelGGL(cfd::k_c4_grads_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream,
+                           line(b, t, nullptr), W + off[b] + cfd::VW_G * cb, D, t);
+        hipLaunchKernelGGL(cfd::k_c4_cell_metrics_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream,
+                           line(b, t, s_dev), W + off[b] + cfd::VW_SC * cb, D, t);
+      }
+    }
+    for (int d = 0; d < 3; ++d) {
+      for (int b = 0; b < nblk; ++b) {
+        const int64_t cb = block_cells(dims, b);
+        const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
+        hipLaunchKernelGGL(cfd::k_c4_visc_faces_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream,
+                           line(b, d, nullptr), line(b, d, jinv_dev), s_dev[b],
+                           W + off[b] + cfd::VW_FV * cb, D, d, gas);
+      }
+      for (int b = 0; b < nblk; ++b) {
+        const int64_t cb = block_cells(dims, b);
+        const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
+        hipLaunchKernelGGL(cfd::k_c4_flux_sub_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream,
+                           line(b, d, nullptr), r_dev[b], jinv_dev[b], D, d);
+      }
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));

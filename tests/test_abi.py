@@ -324,3 +324,29 @@ def test_block_seams_bad_arguments():
     for b in (dict(xe=None), dict(s=None), dict(n=(C.c_int32 * 3)(8, 0, 6)), dict(s=xe)):
         a = dict(dict(xe=xe, n=n, s=C.c_void_p(0x900000), j=C.c_void_p(0xA00000)), **b)
         assert L.cfd_wcns5_metrics_ext(a["xe"], a["n"], a["s"], a["j"], None) == -1, b
+
+
+def test_viscous_seams_bad_arguments():
+    L = B.lib()
+    dims = (C.c_int32 * 6)(8, 6, 5, 8, 6, 5)
+    nbr = (C.c_int32 * 12)(1, 1, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1)
+    nb = C.c_size_t()
+    assert L.cfd_c4_viscous_blocks_work_bytes(2, dims, nbr, C.byref(nb)) == 0
+    assert nb.value == 8 * 29 * 240 * 2
+    bad_nbr = (C.c_int32 * 12)(1, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1)
+    assert L.cfd_c4_viscous_blocks_work_bytes(2, dims, bad_nbr, C.byref(nb)) == -1
+    assert L.cfd_c4_viscous_blocks_work_bytes(2, dims, nbr, C.byref(nb)) == 0
+    P = lambda *a: (C.c_void_p * 2)(*[C.c_void_p(v) for v in a])         # noqa: E731
+    q, s, j, r = P(0x100000, 0x200000), P(0x300000, 0x400000), P(0x500000, 0x600000), P(0x700000, 0x800000)
+    w = C.c_void_p(0x900000)
+    ok = dict(q=q, s=s, j=j, r=r, w=w, wb=nb.value, g=1.4, pr=0.72, mu=1e-3, ss=0.38)
+    bad = {-2: [dict(wb=nb.value - 8)],
+           -1: [dict(q=None), dict(w=None), dict(g=1.0), dict(pr=0.0), dict(mu=-1.0),
+                dict(r=P(0x700000, 0x700000 + 8)), dict(r=P(0x300000, 0x800000)), dict(w=C.c_void_p(0x600000)),
+                dict(j=P(0x500000, 0))]}
+    for st_want, cases_ in bad.items():
+        for b in cases_:
+            a = dict(ok, **b)
+            st = L.cfd_c4_viscous_add_blocks(2, dims, nbr, a["q"], a["s"], a["j"], a["r"], a["w"], a["wb"], a["g"],
+                                             a["pr"], a["mu"], a["ss"], None)
+            assert st == st_want, b
