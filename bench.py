@@ -199,8 +199,9 @@ def bench_wcns5_euler(a) -> int:
     """The periodic inviscid WCNS-E-5 residual of a 256x128x128 block (a
     smooth seeded flow): K residuals after W warm-up ones, hipEvents on the
     launch stream.  The roofline counts each kernel of the pipeline reading
-    its inputs once and writing its outputs once (padding, edge states, Roe
-    faces, Eq. 2 with the running sum), i.e. the intermediates' HBM traffic."""
+    its inputs once and writing its outputs once (padding, the face states
+    with Roe's flux in one pass, Eq. 2 with the running sum), i.e. the
+    intermediates' HBM traffic."""
     import numpy as np
     import torch
     from paper_1710_09995_amd.binding import (c4_viscous_add_curv_periodic, c4_viscous_add_periodic,
@@ -271,7 +272,7 @@ def bench_wcns5_euler(a) -> int:
     for d in range(3):
         P = cells // n[d] * (n[d] + 10)
         F = cells // n[d] * (n[d] + 5)
-        nbytes += 8 * 5 * ((cells + P) + (P + 2 * F) + (2 * F + F) + (F + cells * (1 if d == 0 else 2)))
+        nbytes += 8 * 5 * ((cells + P) + (P + F) + (F + cells * (1 if d == 0 else 2)))
         if curv:
             nbytes += 8 * 3 * F                # the faces' area vectors
     if curv:                                   # R divided by J^{-1}
@@ -293,8 +294,7 @@ def bench_wcns5_euler(a) -> int:
                    "metrics_setup_ms": None if setup_ms is None else round(setup_ms, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "pipeline: k_pad_prim_periodic, k_window6_*<Wcns5Op>, "
-                               + ("k_roe_faces_curv" if curv else "k_roe_faces") + ", k_window6_*<Eq2OpT>"
+                     "kernel": "pipeline: k_pad_prim_periodic, k_wcns5_roe_faces, k_window6_*<Eq2OpT>"
                                + (", k_div_jinv" if curv else "")
                                + (", k_c4_phi, k_c4_grads, k_c4_cell_metrics, k_c4_visc_faces_curv, k_c4_flux_sub"
                                   if viscous and curv else

@@ -298,10 +298,12 @@ cfd_status cfd_wcns5_edges(const double* u_dev, double* left_dev, double* right_
  * states (cfd_wcns5_edges), Roe's flux per unit area through each face (the
  * flux splitting of the residual kernels, Harten factor entropy_fix), and
  * Eq. (2) (cfd_staggered_diff6); R = the sum over directions, so that
- * dQ/dt = -R (Section 2.2, Eq. 3 with the paper's spatial operator).
- * Curvilinear blocks: cfd_wcns5_euler_residual_curv_periodic below.
+ * dQ/dt = -R (Section 2.2, Eq. 3 with the paper's spatial operator).  The
+ * face states and Roe's flux are formed in one pass, the states staying in
+ * registers.  Curvilinear blocks: cfd_wcns5_euler_residual_curv_periodic below.
  * q_dev, r_dev: [5][nk][nj][ni] dense FP64 (conserved variables, residual);
- * work_dev: cfd_wcns5_euler_work_bytes() bytes of device memory.  All the
+ * work_dev: cfd_wcns5_euler_work_bytes() bytes of device memory (the padded
+ * primitives and the face flux of the largest direction).  All the
  * caller's, pairwise disjoint.  n[t] >= 1, h > 0, gamma > 1, entropy_fix >= 0,
  * eps > 0, else CFD_EINVAL; a short workspace gives CFD_ENOMEM.
  * Asynchronous on stream. */

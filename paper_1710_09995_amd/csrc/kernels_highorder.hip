@@ -195,19 +195,6 @@ __global__ void __launch_bounds__(256) k_pad_prim_periodic(const double* __restr
   }
 }
 
-// Roe's flux per unit area through faces of unit normal e_d, from the left
-// and right primitive states (each [5][nf]).
-__global__ void __launch_bounds__(256) k_roe_faces(const double* __restrict__ wl, const double* __restrict__ wr,
-                                                   double* __restrict__ f, int64_t nf, int d, Gas<double> gas) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nf; t += (int64_t)gridDim.x * blockDim.x) {
-    const Prim<double> L{wl[t], wl[nf + t], wl[2 * nf + t], wl[3 * nf + t], wl[4 * nf + t]};
-    const Prim<double> R{wr[t], wr[nf + t], wr[2 * nf + t], wr[3 * nf + t], wr[4 * nf + t]};
-    double fl[5];
-    roe<double>(L, R, d == 0 ? 1.0 : 0.0, d == 1 ? 1.0 : 0.0, d == 2 ? 1.0 : 0.0, gas, fl);
-    for (int v = 0; v < 5; ++v) f[v * nf + t] = fl[v];
-  }
-}
-
 int grid_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 8192); }
 
 // ------------------------------------------------------- curvilinear blocks
@@ -344,40 +331,87 @@ __global__ void __launch_bounds__(256) k_metric_jinv(Grid g, double* __restrict_
   }
 }
 
-// Roe's flux through the area vector of each face along d (flux times |S|):
-// face p of the m0 x m1 x m2 face grid (m_d = n_d + 5) is face v + 1/2 with
-// v = (p - 3) mod n_d, whose area vector sits at index v of the metric field.
-__global__ void __launch_bounds__(256) k_roe_faces_curv(const double* __restrict__ wl, const double* __restrict__ wr,
-                                                        const double* __restrict__ sd, double* __restrict__ f,
-                                                        int m0, int m1, int m2, int d, int n0, int n1, int n2,
-                                                        Gas<double> gas) {
-  const int64_t nf = (int64_t)m0 * m1 * m2;
-  const int64_t cells = (int64_t)n0 * n1 * n2;
-  const int nd = d == 0 ? n0 : (d == 1 ? n1 : n2);
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nf; t += (int64_t)gridDim.x * blockDim.x) {
-    int a = (int)(t % m0), b = (int)((t / m0) % m1), c = (int)(t / ((int64_t)m0 * m1));
-    const int p = d == 0 ? a : (d == 1 ? b : c);
-    const int v = ((p - 3) % nd + nd) % nd;
-    if (d == 0) a = v;
-    if (d == 1) b = v;
-    if (d == 2) c = v;
-    const int64_t ci = ((int64_t)c * n1 + b) * n0 + a;
-    const double sx = sd[ci], sy = sd[cells + ci], sz = sd[2 * cells + ci];
-    const double area = fsqrt(sx * sx + sy * sy + sz * sz);
-    const double ia = frcp(area);
-    const Prim<double> L{wl[t], wl[nf + t], wl[2 * nf + t], wl[3 * nf + t], wl[4 * nf + t]};
-    const Prim<double> R{wr[t], wr[nf + t], wr[2 * nf + t], wr[3 * nf + t], wr[4 * nf + t]};
-    double fl[5];
-    roe<double>(L, R, sx * ia, sy * ia, sz * ia, gas, fl);
-    for (int q = 0; q < 5; ++q) f[q * nf + t] = fl[q] * area;
-  }
-}
-
 __global__ void __launch_bounds__(256) k_div_jinv(double* __restrict__ r, const double* __restrict__ jinv,
                                                   int64_t cells) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += (int64_t)gridDim.x * blockDim.x) {
     const double j = jinv[t];
     for (int q = 0; q < 5; ++q) r[q * cells + t] = r[q * cells + t] / j;
+  }
+}
+
+// Blocks joined face to face.  Index of cell (a, b, c) of a block whose
+// extent along d is nd and whose other extents are the caller's.
+__device__ __forceinline__ int64_t seam_index(int a, int b, int c, int d, int nd, int n0, int n1) {
+  const int64_t e0 = d == 0 ? nd : n0, e1 = d == 1 ? nd : n1;
+  return ((int64_t)c * e1 + b) * e0 + a;
+}
+
+// Face states and Roe's flux in one pass: thread per face p of the face grid
+// (m_d = n_d + 5 along d) reads the six padded cells p .. p + 5 of the five
+// primitives (extents m with m_d + 5 along d), forms the WCNS-E-5 left and
+// right states (Wcns5Op's arithmetic) and Roe's flux (per unit area through
+// e_d, or through the face's area vector): the face states never leave
+// registers.  Without
+// metrics (s == NULL) the face normal is e_d and the flux per unit area;
+// else the area vector of face v = p - 3 comes from the block (0 <= v < n_d)
+// or the neighbour below (v + nlo) or above (v - n_d), whose cells counts
+// are slo/shi (a periodic block passes itself).
+__global__ void __launch_bounds__(256) k_wcns5_roe_faces(const double* __restrict__ w, double* __restrict__ f,
+                                                         int m0, int m1, int m2, int d, double eps,
+                                                         const double* __restrict__ s,
+                                                         const double* __restrict__ slo,
+                                                         const double* __restrict__ shi, int n0, int n1, int n2,
+                                                         int nlo, int nhi, Gas<double> gas) {
+  const int64_t nf = (int64_t)m0 * m1 * m2;
+  const int64_t p0 = m0 + (d == 0 ? 5 : 0), p1 = m1 + (d == 1 ? 5 : 0);
+  const int64_t np = p0 * p1 * (m2 + (d == 2 ? 5 : 0));
+  const int64_t step = d == 0 ? 1 : (d == 1 ? p0 : p0 * p1);
+  const int nd = d == 0 ? n0 : (d == 1 ? n1 : n2);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nf; t += (int64_t)gridDim.x * blockDim.x) {
+    int a = (int)(t % m0), b = (int)((t / m0) % m1), c = (int)(t / ((int64_t)m0 * m1));
+    const int64_t base = ((int64_t)c * p1 + b) * p0 + a;   // padded cell p of the window (index p along d)
+    double L[5], R[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double* wv = w + v * np + base;
+      const double u0 = wv[0], u1 = wv[step], u2 = wv[2 * step], u3 = wv[3 * step], u4 = wv[4 * step],
+                   u5 = wv[5 * step];
+      L[v] = wcns5_left(u0, u1, u2, u3, u4, eps);
+      R[v] = wcns5_left(u5, u4, u3, u2, u1, eps);
+    }
+    const Prim<double> PL{L[0], L[1], L[2], L[3], L[4]};
+    const Prim<double> PR{R[0], R[1], R[2], R[3], R[4]};
+    double fl[5];
+    if (!s) {
+      roe<double>(PL, PR, d == 0 ? 1.0 : 0.0, d == 1 ? 1.0 : 0.0, d == 2 ? 1.0 : 0.0, gas, fl);
+      for (int q = 0; q < 5; ++q) f[q * nf + t] = fl[q];
+    } else {
+      // v in [-3, n_d + 1]; a modulo (not one wrap) keeps a periodic block
+      // thinner than three cells, which passes itself, inside its faces
+      int v = (d == 0 ? a : (d == 1 ? b : c)) - 3;
+      const double* src = s;
+      int sd = nd;
+      if (v < 0) {
+        src = slo;
+        sd = nlo;
+        v = ((v % nlo) + nlo) % nlo;
+      } else if (v >= nd) {
+        src = shi;
+        sd = nhi;
+        v = (v - nd) % nhi;
+      }
+      if (d == 0) a = v;
+      if (d == 1) b = v;
+      if (d == 2) c = v;
+      const int64_t scells = (int64_t)(d == 0 ? sd : n0) * (d == 1 ? sd : n1) * (d == 2 ? sd : n2);
+      const int64_t ci = seam_index(a, b, c, d, sd, n0, n1);
+      const double* sdv = src + 3 * d * scells;
+      const double sx = sdv[ci], sy = sdv[scells + ci], sz = sdv[2 * scells + ci];
+      const double area = fsqrt(sx * sx + sy * sy + sz * sz);
+      const double ia = frcp(area);
+      roe<double>(PL, PR, sx * ia, sy * ia, sz * ia, gas, fl);
+      for (int q = 0; q < 5; ++q) f[q * nf + t] = fl[q] * area;
+    }
   }
 }
 
@@ -390,12 +424,6 @@ void launch_metrics(const Grid& g, double* s_dev, double* jinv_dev, int64_t cell
   hipLaunchKernelGGL(k_metric_jinv<Grid>, grid, dim3(256), 0, stream, g, jinv_dev);
 }
 
-// Blocks joined face to face.  Index of cell (a, b, c) of a block whose
-// extent along d is nd and whose other extents are the caller's.
-__device__ __forceinline__ int64_t seam_index(int a, int b, int c, int d, int nd, int n0, int n1) {
-  const int64_t e0 = d == 0 ? nd : n0, e1 = d == 1 ? nd : n1;
-  return ((int64_t)c * e1 + b) * e0 + a;
-}
 
 // Primitives padded by five cells on each side along d, those beyond the
 // block taken from the neighbours across its two d-faces (qlo: its last five
@@ -436,48 +464,6 @@ __global__ void __launch_bounds__(256) k_pad_prim_blocks(const double* __restric
   }
 }
 
-// Roe's flux through the area vector of face p (m_d = n_d + 5 faces along
-// d): face v + 1/2, v = p - 3; the three faces below the block and the two
-// above come from the neighbours' metrics (slo: its last faces, shi: its first).
-__global__ void __launch_bounds__(256) k_roe_faces_blocks(const double* __restrict__ wl,
-                                                          const double* __restrict__ wr,
-                                                          const double* __restrict__ s, const double* __restrict__ slo,
-                                                          const double* __restrict__ shi, double* __restrict__ f,
-                                                          int m0, int m1, int m2, int d, int n0, int n1, int n2,
-                                                          int nlo, int nhi, Gas<double> gas) {
-  const int64_t nf = (int64_t)m0 * m1 * m2;
-  const int nd = d == 0 ? n0 : (d == 1 ? n1 : n2);
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nf; t += (int64_t)gridDim.x * blockDim.x) {
-    int a = (int)(t % m0), b = (int)((t / m0) % m1), c = (int)(t / ((int64_t)m0 * m1));
-    int v = (d == 0 ? a : (d == 1 ? b : c)) - 3;
-    const double* src = s;
-    int sd = nd;
-    if (v < 0) {
-      src = slo;
-      sd = nlo;
-      v += nlo;
-    } else if (v >= nd) {
-      src = shi;
-      sd = nhi;
-      v -= nd;
-    }
-    if (d == 0) a = v;
-    if (d == 1) b = v;
-    if (d == 2) c = v;
-    const int64_t scells = (int64_t)(d == 0 ? sd : n0) * (d == 1 ? sd : n1) * (d == 2 ? sd : n2);
-    const int64_t ci = seam_index(a, b, c, d, sd, n0, n1);
-    const double* sdv = src + 3 * d * scells;
-    const double sx = sdv[ci], sy = sdv[scells + ci], sz = sdv[2 * scells + ci];
-    const double area = fsqrt(sx * sx + sy * sy + sz * sz);
-    const double ia = frcp(area);
-    const Prim<double> L{wl[t], wl[nf + t], wl[2 * nf + t], wl[3 * nf + t], wl[4 * nf + t]};
-    const Prim<double> R{wr[t], wr[nf + t], wr[2 * nf + t], wr[3 * nf + t], wr[4 * nf + t]};
-    double fl[5];
-    roe<double>(L, R, sx * ia, sy * ia, sz * ia, gas, fl);
-    for (int qv = 0; qv < 5; ++qv) f[qv * nf + t] = fl[qv] * area;
-  }
-}
-
 // One Runge-Kutta stage of Eqs. (4)-(6) with lambda = -dt, in place:
 // q <- a qn + b (q - dt r) (a = 0, b = 1: the first stage; then 3/4, 1/4 and
 // 1/3, 2/3).  keep_qn also stores q into qn first (the step's start state).
@@ -496,8 +482,8 @@ __global__ void __launch_bounds__(256) k_rk3_stage(double* __restrict__ q, doubl
   }
 }
 
-// Workspace of the periodic WCNS-E-5 residual (doubles): the padded primitives
-// and the two face states and the face flux of the largest direction.
+// Workspace of the WCNS-E-5 residual (doubles): the padded primitives and the
+// face flux of the largest direction.
 void wcns5_work(const int32_t n[3], int64_t& pmax, int64_t& fmax) {
   const int64_t cells = (int64_t)n[0] * n[1] * n[2];
   pmax = fmax = 0;
@@ -571,7 +557,7 @@ extern "C" cfd_status cfd_wcns5_euler_work_bytes(const int32_t n[3], size_t* byt
     if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
     int64_t pmax, fmax;
     cfd::wcns5_work(n, pmax, fmax);
-    *bytes = (size_t)(8 * (pmax + 3 * fmax));
+    *bytes = (size_t)(8 * (pmax + fmax));
   });
 }
 
@@ -594,7 +580,7 @@ void wcns5_residual_core(const double* q_dev, const double* s_dev, const double*
   if (!(eps > 0.0) || !std::isfinite(eps)) host_fail(CFD_EINVAL, "eps must be positive and finite");
   int64_t pmax, fmax;
   wcns5_work(n, pmax, fmax);
-  const size_t need = (size_t)(8 * (pmax + 3 * fmax));
+  const size_t need = (size_t)(8 * (pmax + fmax));
   if (work_bytes < need) host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_euler_work_bytes()");
   const int64_t cells = (int64_t)n[0] * n[1] * n[2];
   if (!apart(q_dev, 40 * cells, r_dev, 40 * cells) || !apart(q_dev, 40 * cells, work_dev, (int64_t)need) ||
@@ -605,9 +591,7 @@ void wcns5_residual_core(const double* q_dev, const double* s_dev, const double*
                 !apart(work_dev, (int64_t)need, jinv_dev, 8 * cells)))
     host_fail(CFD_EINVAL, "r and the workspace must not overlap the metrics");
   double* W = static_cast<double*>(work_dev);
-  double* WL = W + pmax;
-  double* WR = WL + fmax;
-  double* F = WR + fmax;
+  double* F = W + pmax;
   Gas<double> gas{};
   gas.gamma = gamma;
   gas.gm1 = gamma - 1.0;
@@ -620,12 +604,8 @@ void wcns5_residual_core(const double* q_dev, const double* s_dev, const double*
     const int64_t nf = mf[0] * mf[1] * mf[2];
     hipLaunchKernelGGL(k_pad_prim_periodic, dim3(grid_for(mp[0] * mp[1] * mp[2])), dim3(256), 0, stream, q_dev, W,
                        n[0], n[1], n[2], d, gamma - 1.0);
-    launch_window6(W, WL, WR, mf, d, 5, Wcns5Op{eps}, stream);
-    if (s_dev)
-      hipLaunchKernelGGL(k_roe_faces_curv, dim3(grid_for(nf)), dim3(256), 0, stream, WL, WR, s_dev + 3 * d * cells, F,
-                         (int)mf[0], (int)mf[1], (int)mf[2], d, n[0], n[1], n[2], gas);
-    else
-      hipLaunchKernelGGL(k_roe_faces, dim3(grid_for(nf)), dim3(256), 0, stream, WL, WR, F, nf, d, gas);
+    hipLaunchKernelGGL(k_wcns5_roe_faces, dim3(grid_for(nf)), dim3(256), 0, stream, W, F, (int)mf[0], (int)mf[1],
+                       (int)mf[2], d, eps, s_dev, s_dev, s_dev, n[0], n[1], n[2], n[d], n[d], gas);
     const int64_t m[3] = {n[0], n[1], n[2]};
     const double hd = s_dev ? 1.0 : h[d];
     const double c1 = 75.0 / (64.0 * hd), c2 = -25.0 / (384.0 * hd), c3 = 3.0 / (640.0 * hd);
@@ -697,7 +677,7 @@ namespace {
 size_t wcns5_residual_work(const int32_t n[3]) {
   int64_t pmax, fmax;
   cfd::wcns5_work(n, pmax, fmax);
-  return (size_t)(8 * (pmax + 3 * fmax));
+  return (size_t)(8 * (pmax + fmax));
 }
 
 }  // namespace
@@ -1180,7 +1160,7 @@ size_t check_seams(int32_t nblk, const int32_t* dims, const int32_t* nbr) {
     }
     int64_t pmax, fmax;
     cfd::wcns5_work(n, pmax, fmax);
-    most = std::max(most, (size_t)(8 * (pmax + 3 * fmax)));
+    most = std::max(most, (size_t)(8 * (pmax + fmax)));
   }
   return most;
 }
@@ -1235,9 +1215,7 @@ extern "C" cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_
       int64_t pmax, fmax;
       cfd::wcns5_work(n, pmax, fmax);
       double* W = static_cast<double*>(work_dev);
-      double* WL = W + pmax;
-      double* WR = WL + fmax;
-      double* F = WR + fmax;
+      double* F = W + pmax;
       const int64_t cells = cells_of(b);
       for (int d = 0; d < 3; ++d) {
         const int lo = nbr[6 * b + 2 * d], hi = nbr[6 * b + 2 * d + 1];
@@ -1248,9 +1226,8 @@ extern "C" cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_
         const int64_t nf = mf[0] * mf[1] * mf[2];
         hipLaunchKernelGGL(cfd::k_pad_prim_blocks, dim3(cfd::grid_for(mp[0] * mp[1] * mp[2])), dim3(256), 0, stream,
                            q_dev[b], q_dev[lo], q_dev[hi], W, n[0], n[1], n[2], d, nlo, nhi, gamma - 1.0);
-        cfd::launch_window6(W, WL, WR, mf, d, 5, cfd::Wcns5Op{eps}, stream);
-        hipLaunchKernelGGL(cfd::k_roe_faces_blocks, dim3(cfd::grid_for(nf)), dim3(256), 0, stream, WL, WR, s_dev[b],
-                           s_dev[lo], s_dev[hi], F, (int)mf[0], (int)mf[1], (int)mf[2], d, n[0], n[1], n[2], nlo, nhi,
+        hipLaunchKernelGGL(cfd::k_wcns5_roe_faces, dim3(cfd::grid_for(nf)), dim3(256), 0, stream, W, F, (int)mf[0],
+                           (int)mf[1], (int)mf[2], d, eps, s_dev[b], s_dev[lo], s_dev[hi], n[0], n[1], n[2], nlo, nhi,
                            gas);
         const int64_t m[3] = {n[0], n[1], n[2]};
         const double c1 = 75.0 / 64.0, c2 = -25.0 / 384.0, c3 = 3.0 / 640.0;

@@ -144,8 +144,8 @@ def test_wcns5_residual_work_bytes_and_bad_arguments():
     nb = C.c_size_t()
     assert L.cfd_wcns5_euler_work_bytes(n, C.byref(nb)) == 0
     # the largest padded direction is k (2 cells: 32 lines of 2 + 10 padded cells, 2 + 5 faces):
-    # 5 * 32 * 12 padded primitives + 3 arrays of 5 * 32 * 7 face values
-    assert nb.value == 8 * (5 * 32 * 12 + 3 * 5 * 32 * 7)
+    # 5 * 32 * 12 padded primitives + 5 * 32 * 7 face fluxes
+    assert nb.value == 8 * (5 * 32 * 12 + 5 * 32 * 7)
     q, r, w = C.c_void_p(0x100000), C.c_void_p(0x900000), C.c_void_p(0x1100000)
     h = (C.c_double * 3)(0.1, 0.1, 0.1)
     ok = dict(q=q, r=r, w=w, wb=nb.value, n=n, h=h, g=1.4, ef=0.1, eps=1e-6)
@@ -296,8 +296,8 @@ def test_block_seams_bad_arguments():
     nbr = (C.c_int32 * 12)(1, 1, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1)
     nb = C.c_size_t()
     assert L.cfd_wcns5_euler_blocks_work_bytes(2, dims, nbr, C.byref(nb)) == 0
-    # largest padded direction k (5 + 10 cells, 5 + 5 faces over 48 lines): 5*48*15 + 3 * 5*48*10
-    assert nb.value == 8 * (5 * 48 * 15 + 3 * 5 * 48 * 10)
+    # largest padded direction k (5 + 10 cells, 5 + 5 faces over 48 lines): 5*48*15 + 5*48*10
+    assert nb.value == 8 * (5 * 48 * 15 + 5 * 48 * 10)
     bad_tables = [(C.c_int32 * 12)(1, 1, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2),      # out of range
                   (C.c_int32 * 12)(1, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1)]      # not mutual
     for t in bad_tables:

@@ -43,7 +43,7 @@ def _curv_grid(n, kind):
 
 
 @pytest.mark.parametrize("n,kind", [((37, 21, 13), "wavy"), ((16, 16, 16), "wavy"), ((9, 7, 5), "affine"),
-                                    ((70, 3, 2), "wavy")])
+                                    ((70, 3, 2), "wavy"), ((2, 9, 7), "wavy")])
 def test_curvilinear_metrics_and_residual_parity(n, kind):
     """Metrics and residual against the oracle on the same grid and state:
     S and J^{-1} within 1e-13 of their largest entry (a few ulps; the kernel
