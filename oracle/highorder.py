@@ -33,7 +33,9 @@ Test infrastructure, like the rest of this package.  Two operators:
 8. the CFL time step on such blocks (cfl_time_step_curv_periodic), and
    blocks joined face to face (wcns5_euler_residual_blocks, block_vertices):
    the stencils run across seams with a five-cell exchange, and the viscous
-   terms across the same seams (viscous_residual_blocks).
+   terms across the same seams (viscous_residual_blocks);
+9. RK3 Navier-Stokes steps on periodic curvilinear blocks
+   (ns_steps_curv_periodic).
 
 Section 2.2, Eq. (2): the cell-centred derivative of a face-centred flux F
 along one index direction with grid size h,
@@ -522,3 +524,20 @@ def viscous_residual_blocks(Qs, Ss, Jinvs, nbr, gamma: float, prandtl: float, mu
             for c in range(4):
                 Rvs[b][1 + c] = Rvs[b][1 + c] - crop(c4_flux_diff(Fp[c], ax, 1.0), d, 2, dims[b][d]) / Jinvs[b]
     return Rvs
+
+
+def ns_steps_curv_periodic(Q: np.ndarray, S: np.ndarray, Jinv: np.ndarray, gamma: float, eps_h: float,
+                           prandtl: float, mu_inf: float, s_star: float, dt: float, nsteps: int,
+                           eps: float = 1e-6) -> np.ndarray:
+    """nsteps SSP-RK3 steps (Eqs. 4-6, lambda = -dt) of the Navier-Stokes
+    equations on a periodic curvilinear block: R = the inviscid WCNS-E-5
+    residual plus the fourth-order viscous terms, a fixed dt."""
+    from .solver import ssp_rk3
+
+    def R(x):
+        return (wcns5_euler_residual_curv_periodic(x, S, Jinv, gamma, eps_h, eps)
+                + viscous_residual_curv_periodic(x, S, Jinv, gamma, prandtl, mu_inf, s_star))
+    q = Q
+    for _ in range(nsteps):
+        q = ssp_rk3(q, dt, R)
+    return q

@@ -18,7 +18,9 @@ Curvilinear viscous terms: exact reduction to the Cartesian ones, rotation
 equivariance, fourth-order convergence of closed-form shear and conduction
 fields sampled on a wavy grid.  Time step: closed form and rotation
 invariance.  Block seams: a periodic block cut into blocks joined face to face
-gives bitwise its own metrics, residual and viscous terms.
+gives bitwise its own metrics, residual and viscous terms.  Navier-Stokes
+steps: a small shear wave decays at the viscous rate, fourth order on a
+Cartesian and a wavy grid.
 """
 import os
 from fractions import Fraction
@@ -714,3 +716,38 @@ def test_split_periodic_block_gives_the_same_viscous_terms():
     for sl, Rb in zip(sls, Rs):
         assert np.array_equal(Rb, Rv[(slice(None),) + sl])
     assert np.array_equal(ho.viscous_residual_blocks([q], [S], [Jinv], [[0] * 6], 1.4, 0.72, 0.02, 0.38)[0], Rv)
+
+
+def _shear_wave(m, wavy, eps_a=1e-3):
+    """A small shear wave u = 0.3 + eps_a sin y (rho = p = T = 1, v = w = 0) on
+    the periodic box [0, 2 pi)^2 x [0, 2 pi) sampled on a Cartesian or a wavy
+    grid of m x m x 4 cells: (q, metrics, y at the solution points)."""
+    from paper_1710_09995_amd import cases
+    L = 2 * np.pi
+    n = (m, m, 4)
+    Xv, P, fmap = _wavy_grid(n, (L, L, L), 0.02 if wavy else 0.0, planar=True)
+    S, Jinv = ho.metrics6(ho.periodic_vertices(Xv, P))
+    X, Y, Z = fmap(_positions(n, (0.0, 0.0, 0.0)))
+    one = np.ones_like(X)
+    return cases.conserved_from(one, 0.3 + eps_a * np.sin(Y), 0 * X, 0 * X, one, 1.4), S, Jinv, Y, Xv, P
+
+
+@pytest.mark.parametrize("wavy", [False, True])
+def test_ns_steps_shear_wave_decays_at_the_viscous_rate(wavy):
+    """RK3 Navier-Stokes steps: a small shear wave has no pressure gradient
+    and, with v = 0, no upwind dissipation (the shear wave's eigenvalue is the
+    normal velocity), so the x-momentum equation reduces to u_t = nu u_yy and
+    the wave decays as exp(-nu t) (nu = mu(T = 1) / rho = mu_inf; viscous
+    heating changes mu by O(eps^2)).  At t = 1 the error falls at fourth
+    order on a Cartesian and on a wavy grid; a uniform stream stays uniform."""
+    nu, eps_a = 0.05, 1e-3
+    errs = []
+    for m in (8, 16, 32):
+        q, S, Jinv, Y, _, _ = _shear_wave(m, wavy, eps_a)
+        qe = ho.ns_steps_curv_periodic(q, S, Jinv, 1.4, 0.1, 0.72, nu, 0.38, 0.05, 20)
+        errs.append(np.max(np.abs(qe[1] / qe[0] - 0.3 - eps_a * np.exp(-nu) * np.sin(Y))) / eps_a)
+    orders = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) > 3.8 and errs[-1] < 2e-6, (errs, orders)
+    from paper_1710_09995_amd import cases
+    qu = cases.conserved_from(np.full(q.shape[1:], 1.2), 0.5, -0.3, 0.2, 1.0 / 1.4, 1.4)
+    assert np.max(np.abs(ho.ns_steps_curv_periodic(qu, S, Jinv, 1.4, 0.1, 0.72, nu, 0.38, 0.02, 3) - qu)) <= 1e-12
