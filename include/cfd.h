@@ -445,6 +445,19 @@ cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_t* dims, co
                                            size_t work_bytes, double gamma, double entropy_fix, double eps,
                                            hipStream_t stream);
 
+/* nsteps RK3 steps (Eqs. 4-6, lambda = -dt, fixed dt) of the Navier-Stokes
+ * equations on a periodic curvilinear block, in place on q_dev: each stage's
+ * residual is cfd_wcns5_euler_residual_curv_periodic plus the viscous terms
+ * of cfd_c4_viscous_add_curv_periodic.  work_dev: cfd_wcns5_ns_step_work_bytes()
+ * bytes (the larger of the two scratch areas, which the stage reuses, then the
+ * step's start state and R).  Arguments and errors as for those calls and
+ * cfd_wcns5_euler_steps_curv_periodic.  Asynchronous on stream. */
+cfd_status cfd_wcns5_ns_step_work_bytes(const int32_t n[3], size_t* bytes);
+cfd_status cfd_wcns5_ns_steps_curv_periodic(double* q_dev, const double* s_dev, const double* jinv_dev,
+                                            void* work_dev, size_t work_bytes, const int32_t n[3], double gamma,
+                                            double entropy_fix, double eps, double prandtl, double mu_inf,
+                                            double s_star, double dt, int32_t nsteps, hipStream_t stream);
+
 /* The fourth-order viscous terms of cfd_c4_viscous_add_curv_periodic on blocks
  * joined face to face (the table, extents and pointer arrays as for
  * cfd_wcns5_euler_residual_blocks): every four-point stencil runs across the

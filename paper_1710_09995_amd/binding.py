@@ -70,7 +70,7 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_wcns5_euler_steps_curv_periodic", "cfd_c4_viscous_curv_work_bytes",
            "cfd_c4_viscous_add_curv_periodic", "cfd_wcns5_time_step_curv_periodic", "cfd_wcns5_metrics_ext",
            "cfd_wcns5_euler_blocks_work_bytes", "cfd_wcns5_euler_residual_blocks", "cfd_c4_viscous_blocks_work_bytes",
-           "cfd_c4_viscous_add_blocks",
+           "cfd_c4_viscous_add_blocks", "cfd_wcns5_ns_step_work_bytes", "cfd_wcns5_ns_steps_curv_periodic",
            "cfd_status_string", "cfd_last_error"]
 
 _lib = None
@@ -149,6 +149,10 @@ def lib(build_if_missing: bool = True):
     L.cfd_c4_viscous_add_blocks.argtypes = [i32, i32p, i32p, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
                                             C.POINTER(vp), vp, C.c_size_t, C.c_double, C.c_double, C.c_double,
                                             C.c_double, vp]
+    L.cfd_wcns5_ns_step_work_bytes.argtypes = [i32p, C.POINTER(C.c_size_t)]
+    L.cfd_wcns5_ns_steps_curv_periodic.argtypes = [vp, vp, vp, vp, C.c_size_t, i32p, C.c_double, C.c_double,
+                                                   C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, i32,
+                                                   vp]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]
@@ -528,6 +532,32 @@ def c4_viscous_add_blocks(qs, rs, Ss, jinvs, nbr, gamma: float = 1.4, prandtl: f
                                            nbytes.value, float(gamma), float(prandtl), float(mu_inf), float(s_star),
                                            _stream_handle(torch, stream)))
     return rs
+
+
+def wcns5_ns_steps_curv_periodic(q, S, jinv, dt: float, nsteps: int, gamma: float = 1.4, entropy_fix: float = 0.1,
+                                 eps: float = 1e-6, prandtl: float = 0.72, mu_inf: float = 1e-3,
+                                 s_star: float = 110.4 / 288.15, work=None, stream=None):
+    """nsteps RK3 Navier-Stokes steps on a periodic curvilinear block on the
+    device (cfd_wcns5_ns_steps_curv_periodic), in place on q (contiguous FP64
+    CUDA tensor [5, nk, nj, ni]); S, jinv from wcns5_metrics_periodic.
+    Returns q."""
+    import torch
+    if q.dtype != torch.float64 or not q.is_cuda or not q.is_contiguous() or q.dim() != 4 or q.shape[0] != 5:
+        raise ValueError("q must be a contiguous float64 CUDA tensor [5, nk, nj, ni]")
+    nk, nj, ni = (int(v) for v in q.shape[1:])
+    for t, shp in ((S, (3, 3, nk, nj, ni)), (jinv, (nk, nj, ni))):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp:
+            raise ValueError("S and jinv must be contiguous float64 CUDA tensors of the block's shape")
+    nn = (C.c_int32 * 3)(ni, nj, nk)
+    nbytes = C.c_size_t()
+    _check(lib().cfd_wcns5_ns_step_work_bytes(nn, C.byref(nbytes)))
+    if work is None or work.numel() * work.element_size() < nbytes.value:
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+    _check(lib().cfd_wcns5_ns_steps_curv_periodic(_ptr(q), _ptr(S), _ptr(jinv), _ptr(work), nbytes.value, nn,
+                                                  float(gamma), float(entropy_fix), float(eps), float(prandtl),
+                                                  float(mu_inf), float(s_star), float(dt), int(nsteps),
+                                                  _stream_handle(torch, stream)))
+    return q
 
 
 class Solver:

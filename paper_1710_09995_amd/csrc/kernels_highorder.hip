@@ -694,16 +694,25 @@ namespace cfd {
 
 // nsteps RK3 steps in place on q with the residual core (Cartesian when s is
 // NULL).  The workspace: the residual's, then the step's start state and R.
+Gas<double> viscous_gas(double gamma, double prandtl, double mu_inf, double s_star);
+void c4_viscous_curv_core(const double* q_dev, const double* s_dev, const double* jinv_dev, double* r_dev,
+                          double* work, const int32_t n[3], const Gas<double>& gas, hipStream_t stream);
+
+// With visc (curvilinear blocks only) each stage adds the fourth-order
+// viscous terms to the residual; their scratch shares the residual's, which
+// is free again once R is formed.
 void wcns5_steps_core(double* q_dev, const double* s_dev, const double* jinv_dev, void* work_dev, size_t work_bytes,
                       const int32_t n[3], const double* h, double gamma, double entropy_fix, double eps, double dt,
-                      int32_t nsteps, hipStream_t stream) {
+                      int32_t nsteps, hipStream_t stream, const Gas<double>* visc = nullptr) {
   if (n[0] < 1 || n[1] < 1 || n[2] < 1) host_fail(CFD_EINVAL, "every extent must be >= 1");
   if (!(dt > 0.0) || !std::isfinite(dt)) host_fail(CFD_EINVAL, "dt must be positive and finite");
   if (nsteps < 0) host_fail(CFD_EINVAL, "nsteps must be >= 0");
   const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-  const size_t rw = wcns5_residual_work(n);
+  const size_t rw0 = wcns5_residual_work(n);
+  const size_t rw = visc ? std::max(rw0, (size_t)8 * 29 * cells) : rw0;
   if (work_bytes < rw + (size_t)2 * 40 * cells)
-    host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_euler_step_work_bytes()");
+    host_fail(CFD_ENOMEM, visc ? "workspace smaller than cfd_wcns5_ns_step_work_bytes()"
+                               : "workspace smaller than cfd_wcns5_euler_step_work_bytes()");
   if (!apart(q_dev, 40 * cells, work_dev, (int64_t)work_bytes)) host_fail(CFD_EINVAL, "q and the workspace overlap");
   if (s_dev && (!apart(q_dev, 40 * cells, s_dev, 72 * cells) || !apart(q_dev, 40 * cells, jinv_dev, 8 * cells)))
     host_fail(CFD_EINVAL, "q must not overlap the metrics");
@@ -714,7 +723,8 @@ void wcns5_steps_core(double* q_dev, const double* s_dev, const double* jinv_dev
   const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
   for (int it = 0; it < nsteps; ++it)
     for (int st = 0; st < 3; ++st) {
-      wcns5_residual_core(q_dev, s_dev, jinv_dev, r, work_dev, rw, n, h, gamma, entropy_fix, eps, stream);
+      wcns5_residual_core(q_dev, s_dev, jinv_dev, r, work_dev, rw0, n, h, gamma, entropy_fix, eps, stream);
+      if (visc) c4_viscous_curv_core(q_dev, s_dev, jinv_dev, r, static_cast<double*>(work_dev), n, *visc, stream);
       hipLaunchKernelGGL(k_rk3_stage, dim3(g), dim3(256), 0, stream, q_dev, qn, r, nv, dt, a[st], b[st],
                          st == 0 ? 1 : 0);
     }
@@ -972,6 +982,41 @@ extern "C" cfd_status cfd_c4_viscous_add_periodic(const double* q_dev, double* r
   });
 }
 
+namespace cfd {
+
+Gas<double> viscous_gas(double gamma, double prandtl, double mu_inf, double s_star) {
+  Gas<double> gas{};
+  gas.gamma = gamma;
+  gas.gm1 = gamma - 1.0;
+  gas.mu_inf = mu_inf;
+  gas.s_star = s_star;
+  gas.prandtl = prandtl;
+  gas.kfac = gamma / ((gamma - 1.0) * prandtl);
+  return gas;
+}
+
+// The curvilinear viscous terms added into r (work: 29 doubles per cell).
+void c4_viscous_curv_core(const double* q_dev, const double* s_dev, const double* jinv_dev, double* r_dev,
+                          double* work, const int32_t n[3], const Gas<double>& gas, hipStream_t stream) {
+  const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+  double* phi = work;
+  double* g = phi + 4 * cells;
+  double* fv = g + 12 * cells;
+  double* sc = fv + 4 * cells;
+  Cells3 C{{n[0], n[1], n[2]}};
+  const int gr = grid_for(cells);
+  hipLaunchKernelGGL(k_c4_phi, dim3(gr), dim3(256), 0, stream, q_dev, phi, cells, gas.gm1);
+  hipLaunchKernelGGL(k_c4_grads, dim3(gr), dim3(256), 0, stream, phi, g, C, 1.0, 1.0, 1.0);
+  hipLaunchKernelGGL(k_c4_cell_metrics, dim3(gr), dim3(256), 0, stream, s_dev, sc, C);
+  for (int d = 0; d < 3; ++d) {
+    hipLaunchKernelGGL(k_c4_visc_faces_curv, dim3(gr), dim3(256), 0, stream, phi, g, s_dev, sc, jinv_dev, fv, C, d,
+                       gas);
+    hipLaunchKernelGGL(k_c4_flux_sub, dim3(gr), dim3(256), 0, stream, fv, r_dev, C, d, 1.0, jinv_dev);
+  }
+}
+
+}  // namespace cfd
+
 extern "C" cfd_status cfd_c4_viscous_curv_work_bytes(const int32_t n[3], size_t* bytes) {
   return cfd::host_guarded([&] {
     if (!n || !bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
@@ -1000,27 +1045,8 @@ extern "C" cfd_status cfd_c4_viscous_add_curv_periodic(const double* q_dev, cons
         cfd::host_fail(CFD_EINVAL, "r and the workspace must not overlap q, the metrics or each other");
     if (!cfd::apart(r_dev, 40 * cells, work_dev, (int64_t)need))
       cfd::host_fail(CFD_EINVAL, "r and the workspace must not overlap q, the metrics or each other");
-    double* phi = static_cast<double*>(work_dev);
-    double* g = phi + 4 * cells;
-    double* fv = g + 12 * cells;
-    double* sc = fv + 4 * cells;
-    cfd::Cells3 C{{n[0], n[1], n[2]}};
-    cfd::Gas<double> gas{};
-    gas.gamma = gamma;
-    gas.gm1 = gamma - 1.0;
-    gas.mu_inf = mu_inf;
-    gas.s_star = s_star;
-    gas.prandtl = prandtl;
-    gas.kfac = gamma / ((gamma - 1.0) * prandtl);
-    const int gr = cfd::grid_for(cells);
-    hipLaunchKernelGGL(cfd::k_c4_phi, dim3(gr), dim3(256), 0, stream, q_dev, phi, cells, gamma - 1.0);
-    hipLaunchKernelGGL(cfd::k_c4_grads, dim3(gr), dim3(256), 0, stream, phi, g, C, 1.0, 1.0, 1.0);
-    hipLaunchKernelGGL(cfd::k_c4_cell_metrics, dim3(gr), dim3(256), 0, stream, s_dev, sc, C);
-    for (int d = 0; d < 3; ++d) {
-      hipLaunchKernelGGL(cfd::k_c4_visc_faces_curv, dim3(gr), dim3(256), 0, stream, phi, g, s_dev, sc, jinv_dev, fv,
-                         C, d, gas);
-      hipLaunchKernelGGL(cfd::k_c4_flux_sub, dim3(gr), dim3(256), 0, stream, fv, r_dev, C, d, 1.0, jinv_dev);
-    }
+    cfd::c4_viscous_curv_core(q_dev, s_dev, jinv_dev, r_dev, static_cast<double*>(work_dev), n,
+                              cfd::viscous_gas(gamma, prandtl, mu_inf, s_star), stream);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   });
@@ -1482,5 +1508,30 @@ extern "C" cfd_status cfd_c4_viscous_add_blocks(int32_t nblk, const int32_t* dim
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  });
+}
+
+// ------------------------------------------------ Navier-Stokes RK3 steps
+extern "C" cfd_status cfd_wcns5_ns_step_work_bytes(const int32_t n[3], size_t* bytes) {
+  return cfd::host_guarded([&] {
+    if (!n || !bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    *bytes = std::max(wcns5_residual_work(n), (size_t)8 * 29 * cells) + (size_t)2 * 40 * cells;
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_ns_steps_curv_periodic(double* q_dev, const double* s_dev, const double* jinv_dev,
+                                                       void* work_dev, size_t work_bytes, const int32_t n[3],
+                                                       double gamma, double entropy_fix, double eps, double prandtl,
+                                                       double mu_inf, double s_star, double dt, int32_t nsteps,
+                                                       hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!q_dev || !s_dev || !jinv_dev || !work_dev || !n) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (!(gamma > 1.0) || !(prandtl > 0.0) || !(mu_inf >= 0.0) || !(s_star > 0.0) || !std::isfinite(mu_inf))
+      cfd::host_fail(CFD_EINVAL, "bad gas parameters");
+    const cfd::Gas<double> gas = cfd::viscous_gas(gamma, prandtl, mu_inf, s_star);
+    cfd::wcns5_steps_core(q_dev, s_dev, jinv_dev, work_dev, work_bytes, n, nullptr, gamma, entropy_fix, eps, dt, nsteps,
+                          stream, &gas);
   });
 }

@@ -276,3 +276,30 @@ def test_viscous_seams_match_the_unsplit_block():
     top = max(float(np.max(np.abs(w))) for w in want)
     for got, w in zip(rs, want):
         assert np.max(np.abs(got.cpu().numpy() - w)) <= 1e-12 * top
+
+
+def test_ns_steps_parity_and_shear_wave():
+    """RK3 Navier-Stokes steps on the device: 4 steps of the smooth flow on
+    the wavy grid against the oracle's (oracle metrics on both sides, within
+    1e-12 of max |q|), and the shear wave of the oracle's pin on a wavy grid
+    with the device's own metrics: fourth-order decay at exp(-nu t)."""
+    import torch
+    from paper_1710_09995_amd.binding import wcns5_metrics_periodic, wcns5_ns_steps_curv_periodic
+    from test_oracle_highorder import _shear_wave
+    n = (20, 12, 8)
+    Xv, P = _curv_grid(n, "wavy")
+    So, Jo = ho.metrics6(ho.periodic_vertices(Xv, P))
+    q = _smooth_state(n, seed=12)
+    say("ns steps", n)
+    got = wcns5_ns_steps_curv_periodic(torch.from_numpy(q.copy()).cuda(), _dev(So), _dev(Jo), 0.01, 4, 1.4, 0.1,
+                                       1e-6, 0.72, 0.02, 0.38).cpu().numpy()
+    want = ho.ns_steps_curv_periodic(q, So, Jo, 1.4, 0.1, 0.72, 0.02, 0.38, 0.01, 4)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    nu, eps_a = 0.05, 1e-3
+    errs = []
+    for m in (8, 16, 32):
+        qw, _, _, Y, Xw, Pw = _shear_wave(m, True, eps_a)
+        S, J = wcns5_metrics_periodic(_dev(Xw), Pw)
+        qe = wcns5_ns_steps_curv_periodic(_dev(qw), S, J, 0.05, 20, 1.4, 0.1, 1e-6, 0.72, nu, 0.38).cpu().numpy()
+        errs.append(np.max(np.abs(qe[1] / qe[0] - 0.3 - eps_a * np.exp(-nu) * np.sin(Y))) / eps_a)
+    assert min(np.log2(errs[i] / errs[i + 1]) for i in range(2)) > 3.8 and errs[-1] < 2e-6, errs
