@@ -35,7 +35,14 @@ Test infrastructure, like the rest of this package.  Two operators:
    the stencils run across seams with a five-cell exchange, and the viscous
    terms across the same seams (viscous_residual_blocks);
 9. RK3 Navier-Stokes steps on periodic curvilinear blocks
-   (ns_steps_curv_periodic).
+   (ns_steps_curv_periodic);
+10. an implicit step (implicit_steps_curv_periodic): backward Euler with a
+   flux-split approximate Jacobian relaxed by point-Jacobi sweeps, the
+   reading of the sparse linear solve the paper's flowchart names (stated
+   below).  Pinned by the explicit Euler limit, a kept uniform stream, the
+   sweeps' fixed point and stability past the explicit limit; its accuracy
+   as a linear solver of the exact Jacobian is not a claim ("parity
+   unpinned" for the approximate Jacobian itself).
 
 Section 2.2, Eq. (2): the cell-centred derivative of a face-centred flux F
 along one index direction with grid size h,
@@ -540,4 +547,72 @@ def ns_steps_curv_periodic(Q: np.ndarray, S: np.ndarray, Jinv: np.ndarray, gamma
     q = Q
     for _ in range(nsteps):
         q = ssp_rk3(q, dt, R)
+    return q
+
+
+# ------------------------------------------------------------ implicit step
+# The paper's flowchart solves a large sparse linear system each step and
+# notes that its convergence degrades when the domain is decomposed; it does
+# not give the method.  The reading taken here, chosen to be data parallel:
+# backward Euler (I/dt + dR/dQ) dQ = -R with the first-order flux-split
+# approximation of dR/dQ, A+- = (A +- lambda I)/2 at every face, lambda the
+# spectral radius |u . S| + c |S| of the mean of the two cells' primitive
+# states, and point-Jacobi sweeps (data-parallel lower-upper relaxation).
+# With J = 1 / J^{-1} and, along each direction, the faces f+ = i + 1/2 and
+# f- = i - 1/2 of cell i:
+#   D_i  = 1/dt + J_i sum_d (lambda_f+ + lambda_f-) / 2
+#   O_i  = sum_d [ (dF(i+1; S_f+) - lambda_f+ dQ_{i+1}) - (dF(i-1; S_f-) + lambda_f- dQ_{i-1}) ] / 2
+#   dQ_i <- (-R_i - J_i O_i) / D_i,   dF(m; S) = F(Q_m + dQ_m) . S - F(Q_m) . S,
+# starting from dQ = -R / D; the step is Q + dQ.  (The difference of A_f+ and
+# A_f- on the diagonal vanishes with the metric identities and is dropped.)
+
+def euler_flux_through(Q: np.ndarray, S: np.ndarray, gamma: float) -> np.ndarray:
+    """The physical inviscid flux of states Q ([5, ...]) through area vectors S ([3, ...])."""
+    from .flux import primitives
+    W = primitives(Q, gamma)
+    U = W[1] * S[0] + W[2] * S[1] + W[3] * S[2]
+    return np.stack([Q[0] * U, Q[1] * U + W[4] * S[0], Q[2] * U + W[4] * S[1], Q[3] * U + W[4] * S[2],
+                     (Q[4] + W[4]) * U])
+
+
+def _face_lambda(W, Sf, d, gamma):
+    """Spectral radius at faces i + 1/2 along d from the mean primitive state of cells i, i + 1."""
+    ax = 1 + [2, 1, 0][d]
+    Wm = 0.5 * (W + np.roll(W, -1, axis=ax))
+    c = np.sqrt(gamma * Wm[4] / Wm[0])
+    return np.abs(Wm[1] * Sf[0] + Wm[2] * Sf[1] + Wm[3] * Sf[2]) + c * np.sqrt(np.sum(Sf * Sf, axis=0))
+
+
+def implicit_sweeps_curv_periodic(Q, R, S, Jinv, gamma: float, dt: float, sweeps: int):
+    """dQ of the reading above (R: the residual at Q), after `sweeps` Jacobi sweeps."""
+    from .flux import primitives
+    W = primitives(Q, gamma)
+    Jc = 1.0 / Jinv
+    lam = [_face_lambda(W, S[d], d, gamma) for d in range(3)]       # faces i + 1/2
+    axis = [3, 2, 1]                                                # axis of d in [5, k, j, i]
+    D = 1.0 / dt + Jc * sum(0.5 * (lam[d] + np.roll(lam[d], 1, axis=axis[d] - 1)) for d in range(3))
+    dQ = -R / D
+    for _ in range(sweeps):
+        O = np.zeros_like(Q)
+        for d in range(3):
+            ax = axis[d]
+            Sp, Sm = S[d], np.roll(S[d], 1, axis=ax)               # faces i + 1/2, i - 1/2
+            lp, lm = lam[d], np.roll(lam[d], 1, axis=ax - 1)
+            Qp, dQp = np.roll(Q, -1, axis=ax), np.roll(dQ, -1, axis=ax)
+            Qm, dQm = np.roll(Q, 1, axis=ax), np.roll(dQ, 1, axis=ax)
+            dFp = euler_flux_through(Qp + dQp, Sp, gamma) - euler_flux_through(Qp, Sp, gamma)
+            dFm = euler_flux_through(Qm + dQm, Sm, gamma) - euler_flux_through(Qm, Sm, gamma)
+            O = O + 0.5 * ((dFp - lp * dQp) - (dFm + lm * dQm))
+        dQ = (-R - Jc * O) / D
+    return dQ
+
+
+def implicit_steps_curv_periodic(Q, S, Jinv, gamma: float, eps_h: float, dt: float, nsteps: int, sweeps: int,
+                                 eps: float = 1e-6):
+    """nsteps implicit steps (the reading above) of the inviscid curvilinear
+    periodic WCNS-E-5 residual."""
+    q = Q
+    for _ in range(nsteps):
+        R = wcns5_euler_residual_curv_periodic(q, S, Jinv, gamma, eps_h, eps)
+        q = q + implicit_sweeps_curv_periodic(q, R, S, Jinv, gamma, dt, sweeps)
     return q

@@ -20,7 +20,9 @@ fields sampled on a wavy grid.  Time step: closed form and rotation
 invariance.  Block seams: a periodic block cut into blocks joined face to face
 gives bitwise its own metrics, residual and viscous terms.  Navier-Stokes
 steps: a small shear wave decays at the viscous rate, fourth order on a
-Cartesian and a wavy grid.
+Cartesian and a wavy grid.  Implicit step: the explicit Euler limit, a kept
+uniform stream, the sweeps' fixed point, stability at 20 times the explicit
+step.
 """
 import os
 from fractions import Fraction
@@ -751,3 +753,54 @@ def test_ns_steps_shear_wave_decays_at_the_viscous_rate(wavy):
     from paper_1710_09995_amd import cases
     qu = cases.conserved_from(np.full(q.shape[1:], 1.2), 0.5, -0.3, 0.2, 1.0 / 1.4, 1.4)
     assert np.max(np.abs(ho.ns_steps_curv_periodic(qu, S, Jinv, 1.4, 0.1, 0.72, nu, 0.38, 0.02, 3) - qu)) <= 1e-12
+
+
+# ------------------------------------------------------------ implicit step
+
+def _implicit_setup():
+    n = (12, 10, 8)
+    Xv, P, _ = _wavy_grid(n, (3.0, 2.0, 1.5), 0.08)
+    S, Jinv = ho.metrics6(ho.periodic_vertices(Xv, P))
+    q, _ = _smooth_state(n, 3)
+    return q, S, Jinv
+
+
+def test_implicit_step_explicit_euler_limit_and_freestream():
+    """Backward Euler's first-order limit: dQ = -dt R + O(dt^2), so
+    |dQ + dt R| / (dt max|R|) falls in proportion to dt; a uniform stream
+    (R = 0) gives dQ = 0 exactly."""
+    from paper_1710_09995_amd import cases
+    q, S, Jinv = _implicit_setup()
+    R = ho.wcns5_euler_residual_curv_periodic(q, S, Jinv, 1.4, 0.1)
+    rel = []
+    for dt in (1e-3, 1e-4, 1e-5):
+        dQ = ho.implicit_sweeps_curv_periodic(q, R, S, Jinv, 1.4, dt, 3)
+        rel.append(np.max(np.abs(dQ + dt * R)) / (dt * np.max(np.abs(R))))
+    assert rel[0] < 0.02 and 9.0 < rel[0] / rel[1] < 11.0 and 9.0 < rel[1] / rel[2] < 11.0, rel
+    qu = cases.conserved_from(np.full(q.shape[1:], 1.2), 0.5, -0.3, 0.2, 1.0 / 1.4, 1.4)
+    Ru = ho.wcns5_euler_residual_curv_periodic(qu, S, Jinv, 1.4, 0.1)
+    assert np.max(np.abs(ho.implicit_steps_curv_periodic(qu, S, Jinv, 1.4, 0.1, 0.5, 2, 4) - qu)) <= 1e-12
+    assert np.max(np.abs(Ru)) <= 1e-12
+
+
+def test_implicit_sweeps_converge_to_the_relaxation_fixed_point():
+    """Point-Jacobi on a diagonally dominant operator contracts: after 60
+    sweeps dQ solves D dQ + J O(dQ) = -R to rounding, checked by one more
+    sweep changing nothing (1e-14 of max |dQ|)."""
+    q, S, Jinv = _implicit_setup()
+    R = ho.wcns5_euler_residual_curv_periodic(q, S, Jinv, 1.4, 0.1)
+    a = ho.implicit_sweeps_curv_periodic(q, R, S, Jinv, 1.4, 0.05, 60)
+    b = ho.implicit_sweeps_curv_periodic(q, R, S, Jinv, 1.4, 0.05, 61)
+    assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(a))
+
+
+def test_implicit_steps_stable_past_the_explicit_limit():
+    """At 20 times the CFL-1 step, RK3 on the same residual blows up within 20
+    steps while the implicit steps stay bounded with positive density."""
+    q, S, Jinv = _implicit_setup()
+    dt = 20.0 * ho.cfl_time_step_curv_periodic(q, S, Jinv, 1.4, 1.0)
+    with np.errstate(all="ignore"):
+        qe = ho.wcns5_euler_steps_curv_periodic(q, S, Jinv, 1.4, 0.1, dt, 20)
+    assert not np.all(np.isfinite(qe)) or np.max(np.abs(qe)) > 1e3
+    qi = ho.implicit_steps_curv_periodic(q, S, Jinv, 1.4, 0.1, dt, 20, 4)
+    assert np.all(np.isfinite(qi)) and qi[0].min() > 0.5 and np.max(np.abs(qi - q)) < 1.0
