@@ -458,6 +458,24 @@ cfd_status cfd_wcns5_ns_steps_curv_periodic(double* q_dev, const double* s_dev, 
                                             double entropy_fix, double eps, double prandtl, double mu_inf,
                                             double s_star, double dt, int32_t nsteps, hipStream_t stream);
 
+/* Implicit steps on a periodic curvilinear block (the sparse linear solve per
+ * step that the paper's flowchart names, without its method; this reading is
+ * data parallel): backward Euler (I/dt + dR/dQ) dQ = -R for the residual of
+ * cfd_wcns5_euler_residual_curv_periodic, with the flux-split approximate
+ * Jacobian A+- = (A +- lambda I)/2 at each face (lambda = |u . S| + c |S| of
+ * the mean primitive state of the two cells), relaxed by `sweeps` point-Jacobi
+ * sweeps from dQ = -R / D, D = 1/dt + J sum_d (lambda_+ + lambda_-)/2; the
+ * off-diagonal products are flux differences F(Q + dQ) . S - F(Q) . S.  Then
+ * q += dQ; nsteps times, in place.  work_dev: cfd_wcns5_implicit_step_work_bytes()
+ * bytes.  dt > 0, nsteps >= 0, 0 <= sweeps <= 1000, gamma > 1, and q, the
+ * metrics and the workspace pairwise disjoint, else CFD_EINVAL; a short
+ * workspace gives CFD_ENOMEM.  Asynchronous on stream. */
+cfd_status cfd_wcns5_implicit_step_work_bytes(const int32_t n[3], size_t* bytes);
+cfd_status cfd_wcns5_implicit_steps_curv_periodic(double* q_dev, const double* s_dev, const double* jinv_dev,
+                                                  void* work_dev, size_t work_bytes, const int32_t n[3], double gamma,
+                                                  double entropy_fix, double eps, double dt, int32_t nsteps,
+                                                  int32_t sweeps, hipStream_t stream);
+
 /* The fourth-order viscous terms of cfd_c4_viscous_add_curv_periodic on blocks
  * joined face to face (the table, extents and pointer arrays as for
  * cfd_wcns5_euler_residual_blocks): every four-point stencil runs across the

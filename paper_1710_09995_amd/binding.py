@@ -71,6 +71,7 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_c4_viscous_add_curv_periodic", "cfd_wcns5_time_step_curv_periodic", "cfd_wcns5_metrics_ext",
            "cfd_wcns5_euler_blocks_work_bytes", "cfd_wcns5_euler_residual_blocks", "cfd_c4_viscous_blocks_work_bytes",
            "cfd_c4_viscous_add_blocks", "cfd_wcns5_ns_step_work_bytes", "cfd_wcns5_ns_steps_curv_periodic",
+           "cfd_wcns5_implicit_step_work_bytes", "cfd_wcns5_implicit_steps_curv_periodic",
            "cfd_status_string", "cfd_last_error"]
 
 _lib = None
@@ -153,6 +154,9 @@ def lib(build_if_missing: bool = True):
     L.cfd_wcns5_ns_steps_curv_periodic.argtypes = [vp, vp, vp, vp, C.c_size_t, i32p, C.c_double, C.c_double,
                                                    C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, i32,
                                                    vp]
+    L.cfd_wcns5_implicit_step_work_bytes.argtypes = [i32p, C.POINTER(C.c_size_t)]
+    L.cfd_wcns5_implicit_steps_curv_periodic.argtypes = [vp, vp, vp, vp, C.c_size_t, i32p, C.c_double, C.c_double,
+                                                         C.c_double, C.c_double, i32, i32, vp]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]
@@ -557,6 +561,29 @@ def wcns5_ns_steps_curv_periodic(q, S, jinv, dt: float, nsteps: int, gamma: floa
                                                   float(gamma), float(entropy_fix), float(eps), float(prandtl),
                                                   float(mu_inf), float(s_star), float(dt), int(nsteps),
                                                   _stream_handle(torch, stream)))
+    return q
+
+
+def wcns5_implicit_steps_curv_periodic(q, S, jinv, dt: float, nsteps: int, sweeps: int, gamma: float = 1.4,
+                                       entropy_fix: float = 0.1, eps: float = 1e-6, work=None, stream=None):
+    """nsteps implicit steps (backward Euler, point-Jacobi sweeps) of the
+    curvilinear periodic WCNS-E-5 Euler residual on the device
+    (cfd_wcns5_implicit_steps_curv_periodic), in place on q.  Returns q."""
+    import torch
+    if q.dtype != torch.float64 or not q.is_cuda or not q.is_contiguous() or q.dim() != 4 or q.shape[0] != 5:
+        raise ValueError("q must be a contiguous float64 CUDA tensor [5, nk, nj, ni]")
+    nk, nj, ni = (int(v) for v in q.shape[1:])
+    for t, shp in ((S, (3, 3, nk, nj, ni)), (jinv, (nk, nj, ni))):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp:
+            raise ValueError("S and jinv must be contiguous float64 CUDA tensors of the block's shape")
+    nn = (C.c_int32 * 3)(ni, nj, nk)
+    nbytes = C.c_size_t()
+    _check(lib().cfd_wcns5_implicit_step_work_bytes(nn, C.byref(nbytes)))
+    if work is None or work.numel() * work.element_size() < nbytes.value:
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+    _check(lib().cfd_wcns5_implicit_steps_curv_periodic(_ptr(q), _ptr(S), _ptr(jinv), _ptr(work), nbytes.value, nn,
+                                                        float(gamma), float(entropy_fix), float(eps), float(dt),
+                                                        int(nsteps), int(sweeps), _stream_handle(torch, stream)))
     return q
 
 

@@ -1535,3 +1535,164 @@ extern "C" cfd_status cfd_wcns5_ns_steps_curv_periodic(double* q_dev, const doub
                           stream, &gas);
   });
 }
+
+// ------------------------------------------------------------ implicit step
+// Backward Euler (I/dt + dR/dQ) dQ = -R on a periodic curvilinear block with
+// the flux-split approximate Jacobian A+- = (A +- lambda I)/2 at every face
+// (lambda = |u . S| + c |S| of the mean primitive state of the face's two
+// cells) relaxed by point-Jacobi sweeps: the paper's flowchart solves a sparse
+// linear system per step without naming the method; this one is data parallel.
+//   D_i = 1/dt + J_i sum_d (lambda_{i+1/2} + lambda_{i-1/2}) / 2
+//   dQ_i <- (-R_i - J_i sum_d [(dF_{i+1} - lambda_{i+1/2} dQ_{i+1})
+//                              - (dF_{i-1} + lambda_{i-1/2} dQ_{i-1})] / 2) / D_i
+// with dF_m = F(Q_m + dQ_m) . S - F(Q_m) . S through the face between.
+namespace cfd {
+
+__device__ __forceinline__ void euler_flux_dot(double q0, double q1, double q2, double q3, double q4, double sx,
+                                               double sy, double sz, double gm1, double F[5]) {
+  const Prim<double> w = to_prim<double>(q0, q1, q2, q3, q4, gm1);
+  const double U = w.u * sx + w.v * sy + w.w * sz;
+  F[0] = q0 * U;
+  F[1] = q1 * U + w.p * sx;
+  F[2] = q2 * U + w.p * sy;
+  F[3] = q3 * U + w.p * sz;
+  F[4] = (q4 + w.p) * U;
+}
+
+// lam[d * cells + c]: the spectral radius at face c + 1/2 along d.
+__global__ void __launch_bounds__(256) k_impl_lambda(const double* __restrict__ q, const double* __restrict__ s,
+                                                     double* __restrict__ lam, Cells3 C, double gamma) {
+  const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
+  const double gm1 = gamma - 1.0;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
+    const Prim<double> a = to_prim<double>(q[c], q[cells + c], q[2 * cells + c], q[3 * cells + c], q[4 * cells + c],
+                                           gm1);
+    for (int d = 0; d < 3; ++d) {
+      const int64_t p = C.step(i, j, k, d, 1);
+      const Prim<double> b = to_prim<double>(q[p], q[cells + p], q[2 * cells + p], q[3 * cells + p],
+                                             q[4 * cells + p], gm1);
+      const double r = 0.5 * (a.r + b.r), u = 0.5 * (a.u + b.u), v = 0.5 * (a.v + b.v), w = 0.5 * (a.w + b.w),
+                   pr = 0.5 * (a.p + b.p);
+      const double* sd = s + 3 * d * cells;
+      const double sx = sd[c], sy = sd[cells + c], sz = sd[2 * cells + c];
+      lam[d * cells + c] = fabs(u * sx + v * sy + w * sz) + sqrt(gamma * pr / r) * sqrt(sx * sx + sy * sy + sz * sz);
+    }
+  }
+}
+
+// The diagonal D and the first iterate dQ = -R / D.
+__global__ void __launch_bounds__(256) k_impl_diag(const double* __restrict__ r, const double* __restrict__ lam,
+                                                   const double* __restrict__ jinv, double* __restrict__ diag,
+                                                   double* __restrict__ dq, Cells3 C, double dt) {
+  const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
+    double sum = 0.0;
+    for (int d = 0; d < 3; ++d) sum = sum + 0.5 * (lam[d * cells + c] + lam[d * cells + C.step(i, j, k, d, -1)]);
+    const double D = 1.0 / dt + (1.0 / jinv[c]) * sum;
+    diag[c] = D;
+    for (int v = 0; v < 5; ++v) dq[v * cells + c] = -r[v * cells + c] / D;
+  }
+}
+
+// One Jacobi sweep: dq_in -> dq_out.
+__global__ void __launch_bounds__(256) k_impl_sweep(const double* __restrict__ q, const double* __restrict__ r,
+                                                    const double* __restrict__ s, const double* __restrict__ lam,
+                                                    const double* __restrict__ jinv, const double* __restrict__ diag,
+                                                    const double* __restrict__ dq_in, double* __restrict__ dq_out,
+                                                    Cells3 C, double gm1) {
+  const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
+    double O[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int d = 0; d < 3; ++d) {
+      const int64_t p = C.step(i, j, k, d, 1), m = C.step(i, j, k, d, -1);
+      const double* sd = s + 3 * d * cells;
+      const double lp = lam[d * cells + c], lm = lam[d * cells + m];
+      double Fa[5], Fb[5], dFp[5], dFm[5];
+      {
+        const double sx = sd[c], sy = sd[cells + c], sz = sd[2 * cells + c];
+        euler_flux_dot(q[p] + dq_in[p], q[cells + p] + dq_in[cells + p], q[2 * cells + p] + dq_in[2 * cells + p],
+                       q[3 * cells + p] + dq_in[3 * cells + p], q[4 * cells + p] + dq_in[4 * cells + p], sx, sy, sz,
+                       gm1, Fa);
+        euler_flux_dot(q[p], q[cells + p], q[2 * cells + p], q[3 * cells + p], q[4 * cells + p], sx, sy, sz, gm1, Fb);
+        for (int v = 0; v < 5; ++v) dFp[v] = Fa[v] - Fb[v];
+      }
+      {
+        const double sx = sd[m], sy = sd[cells + m], sz = sd[2 * cells + m];
+        euler_flux_dot(q[m] + dq_in[m], q[cells + m] + dq_in[cells + m], q[2 * cells + m] + dq_in[2 * cells + m],
+                       q[3 * cells + m] + dq_in[3 * cells + m], q[4 * cells + m] + dq_in[4 * cells + m], sx, sy, sz,
+                       gm1, Fa);
+        euler_flux_dot(q[m], q[cells + m], q[2 * cells + m], q[3 * cells + m], q[4 * cells + m], sx, sy, sz, gm1, Fb);
+        for (int v = 0; v < 5; ++v) dFm[v] = Fa[v] - Fb[v];
+      }
+      for (int v = 0; v < 5; ++v)
+        O[v] = O[v] + 0.5 * ((dFp[v] - lp * dq_in[v * cells + p]) - (dFm[v] + lm * dq_in[v * cells + m]));
+    }
+    const double J = 1.0 / jinv[c], D = diag[c];
+    for (int v = 0; v < 5; ++v) dq_out[v * cells + c] = (-r[v * cells + c] - J * O[v]) / D;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_impl_apply(double* __restrict__ q, const double* __restrict__ dq, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    q[t] = q[t] + dq[t];
+}
+
+}  // namespace cfd
+
+extern "C" cfd_status cfd_wcns5_implicit_step_work_bytes(const int32_t n[3], size_t* bytes) {
+  return cfd::host_guarded([&] {
+    if (!n || !bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    *bytes = wcns5_residual_work(n) + (size_t)8 * 19 * cells;     // R, two dQ, lambda (3), D
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_implicit_steps_curv_periodic(double* q_dev, const double* s_dev,
+                                                             const double* jinv_dev, void* work_dev,
+                                                             size_t work_bytes, const int32_t n[3], double gamma,
+                                                             double entropy_fix, double eps, double dt,
+                                                             int32_t nsteps, int32_t sweeps, hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!q_dev || !s_dev || !jinv_dev || !work_dev || !n) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    if (!(dt > 0.0) || !std::isfinite(dt)) cfd::host_fail(CFD_EINVAL, "dt must be positive and finite");
+    if (nsteps < 0 || sweeps < 0 || sweeps > 1000) cfd::host_fail(CFD_EINVAL, "nsteps >= 0, sweeps in [0, 1000]");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) cfd::host_fail(CFD_EINVAL, "gamma must exceed 1");
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    const size_t rw = wcns5_residual_work(n);
+    const size_t need = rw + (size_t)8 * 19 * cells;
+    if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_implicit_step_work_bytes()");
+    if (!cfd::apart(q_dev, 40 * cells, work_dev, (int64_t)work_bytes) ||
+        !cfd::apart(q_dev, 40 * cells, s_dev, 72 * cells) || !cfd::apart(q_dev, 40 * cells, jinv_dev, 8 * cells))
+      cfd::host_fail(CFD_EINVAL, "q must not overlap the workspace or the metrics");
+    if (!cfd::apart(work_dev, (int64_t)work_bytes, s_dev, 72 * cells) ||
+        !cfd::apart(work_dev, (int64_t)work_bytes, jinv_dev, 8 * cells))
+      cfd::host_fail(CFD_EINVAL, "the workspace must not overlap the metrics");
+    double* R = reinterpret_cast<double*>(static_cast<char*>(work_dev) + rw);
+    double* dqa = R + 5 * cells;
+    double* dqb = dqa + 5 * cells;
+    double* lam = dqb + 5 * cells;
+    double* diag = lam + 3 * cells;
+    const cfd::Cells3 C{{n[0], n[1], n[2]}};
+    const int gr = cfd::grid_for(cells);
+    for (int it = 0; it < nsteps; ++it) {
+      cfd::wcns5_residual_core(q_dev, s_dev, jinv_dev, R, work_dev, rw, n, nullptr, gamma, entropy_fix, eps, stream);
+      hipLaunchKernelGGL(cfd::k_impl_lambda, dim3(gr), dim3(256), 0, stream, q_dev, s_dev, lam, C, gamma);
+      hipLaunchKernelGGL(cfd::k_impl_diag, dim3(gr), dim3(256), 0, stream, R, lam, jinv_dev, diag, dqa, C, dt);
+      double *cur = dqa, *nxt = dqb;
+      for (int k = 0; k < sweeps; ++k) {
+        hipLaunchKernelGGL(cfd::k_impl_sweep, dim3(gr), dim3(256), 0, stream, q_dev, R, s_dev, lam, jinv_dev, diag,
+                           cur, nxt, C, gamma - 1.0);
+        std::swap(cur, nxt);
+      }
+      hipLaunchKernelGGL(cfd::k_impl_apply, dim3(cfd::grid_for(5 * cells)), dim3(256), 0, stream, q_dev, cur,
+                         5 * cells);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  });
+}

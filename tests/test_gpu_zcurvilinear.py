@@ -303,3 +303,26 @@ def test_ns_steps_parity_and_shear_wave():
         qe = wcns5_ns_steps_curv_periodic(_dev(qw), S, J, 0.05, 20, 1.4, 0.1, 1e-6, 0.72, nu, 0.38).cpu().numpy()
         errs.append(np.max(np.abs(qe[1] / qe[0] - 0.3 - eps_a * np.exp(-nu) * np.sin(Y))) / eps_a)
     assert min(np.log2(errs[i] / errs[i + 1]) for i in range(2)) > 3.8 and errs[-1] < 2e-6, errs
+
+
+def test_implicit_steps_parity_and_stability():
+    """Implicit steps on the device against the oracle's (3 steps, 4 sweeps,
+    the smooth flow on the wavy grid, oracle metrics on both sides): within
+    1e-11 of max |q| (the sweeps form flux differences F(Q + dQ) - F(Q),
+    where the kernels' rounding differs from the oracle's); and at 20 times
+    the CFL-1 step, with the device's own metrics, the steps stay bounded."""
+    import torch
+    from paper_1710_09995_amd.binding import wcns5_implicit_steps_curv_periodic, wcns5_metrics_periodic
+    n = (20, 12, 8)
+    Xv, P = _curv_grid(n, "wavy")
+    So, Jo = ho.metrics6(ho.periodic_vertices(Xv, P))
+    q = _smooth_state(n, seed=14)
+    say("implicit steps", n)
+    got = wcns5_implicit_steps_curv_periodic(torch.from_numpy(q.copy()).cuda(), _dev(So), _dev(Jo), 0.02, 3,
+                                             4).cpu().numpy()
+    want = ho.implicit_steps_curv_periodic(q, So, Jo, 1.4, 0.1, 0.02, 3, 4)
+    assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
+    S, J = wcns5_metrics_periodic(_dev(Xv), P)
+    dt = 20.0 * ho.cfl_time_step_curv_periodic(q, So, Jo, 1.4, 1.0)
+    qi = wcns5_implicit_steps_curv_periodic(torch.from_numpy(q.copy()).cuda(), S, J, dt, 20, 4).cpu().numpy()
+    assert np.all(np.isfinite(qi)) and qi[0].min() > 0.5 and np.max(np.abs(qi - q)) < 1.5
