@@ -304,6 +304,77 @@ def bench_wcns5_euler(a) -> int:
     return 0
 
 
+def bench_implicit(a) -> int:
+    """Implicit steps (backward Euler, 4 point-Jacobi sweeps) of the inviscid
+    WCNS-E-5 residual on the wavy periodic 256x128x128 grid of --op
+    wcns5_curv, at 5 times the CFL-1 step; K steps after W warm-up ones,
+    hipEvents on the launch stream.  Algorithmic bytes: the residual's
+    pipeline plus, per sweep, each cell's state, update, residual, metrics,
+    radii, J^{-1} and diagonal read once and the update written once."""
+    import numpy as np
+    import torch
+    from paper_1710_09995_amd.binding import (wcns5_implicit_steps_curv_periodic, wcns5_metrics_periodic,
+                                              wcns5_time_step_curv_periodic)
+    n = (256, 128, 128)
+    ni, nj, nk = n
+    cells = ni * nj * nk
+    rng = np.random.default_rng(0)
+    ph = rng.uniform(0, 2 * np.pi, 4)
+    s2 = 2 * np.pi
+    z, y, x = np.meshgrid(np.arange(nk) / nk, np.arange(nj) / nj, np.arange(ni) / ni, indexing="ij")
+    rho = 1 + 0.2 * np.sin(s2 * x + ph[0]) * np.cos(s2 * y + ph[1]) + 0.1 * np.sin(s2 * z + ph[2])
+    u, v, w = 0.5 + 0.1 * np.sin(s2 * y + ph[3]), 0.1 * np.sin(s2 * z), 0.1 * np.sin(s2 * x)
+    p = 1 + 0.1 * np.cos(s2 * (x + y + z))
+    q0 = torch.from_numpy(np.stack([rho, rho * u, rho * v, rho * w,
+                                    p / 0.4 + 0.5 * rho * (u * u + v * v + w * w)])).cuda()
+    L, amp = (1.0, 0.5, 0.5), 0.05
+    zb, yb, xb = np.meshgrid((np.arange(nk) + 0.5) * L[2] / nk, (np.arange(nj) + 0.5) * L[1] / nj,
+                             (np.arange(ni) + 0.5) * L[0] / ni, indexing="ij")
+    wx, wy, wz = s2 * xb / L[0], s2 * yb / L[1], s2 * zb / L[2]
+    xv = torch.from_numpy(np.stack([xb + amp * L[0] * np.sin(wy) * np.sin(wz),
+                                    yb + amp * L[1] * np.sin(wz) * np.sin(wx),
+                                    zb + amp * L[2] * np.sin(wx) * np.sin(wy)])).cuda()
+    S, jinv = wcns5_metrics_periodic(xv, np.diag(L))
+    dt = 5.0 * float(wcns5_time_step_curv_periodic(q0, S, jinv, 1.0).cpu()[0])
+    q = q0.clone()
+    sweeps = 4
+    for _ in range(a.warmup):
+        wcns5_implicit_steps_curv_periodic(q, S, jinv, dt, 1, sweeps)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(a.steps):
+        wcns5_implicit_steps_curv_periodic(q, S, jinv, dt, 1, sweeps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    nbytes = 0
+    for d in range(3):
+        P = cells // n[d] * (n[d] + 10)
+        F = cells // n[d] * (n[d] + 5)
+        nbytes += 8 * 5 * ((cells + P) + (P + F) + (F + cells * (1 if d == 0 else 2))) + 8 * 3 * F
+    nbytes += 8 * cells * (5 + 5 + 1)                                   # R / J^{-1}
+    nbytes += 8 * cells * ((5 + 9 + 3) + (5 + 3 + 1 + 1 + 5))           # radii; diagonal and first iterate
+    nbytes += sweeps * 8 * cells * (5 + 5 + 5 + 9 + 3 + 1 + 1 + 5)      # one sweep
+    nbytes += 8 * cells * 15                                            # q += dQ
+    achieved = nbytes / (ms / 1e3) / 1e9
+    finite = bool(torch.isfinite(q).all())
+    print(json.dumps({
+        "metric": "Mcell/s of implicit steps (backward Euler, 4 Jacobi sweeps) on the curvilinear WCNS-E-5 residual",
+        "value": round(cells / (ms / 1e3) / 1e6, 1), "unit": "Mcell/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded smooth periodic flow, wavy grid)",
+        "config": {"workload": "implicit_wcns5_curv_periodic_256x128x128", "sweeps": sweeps, "cfl": 5.0,
+                   "finite": finite},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "pipeline: residual, k_impl_lambda, k_impl_diag, k_impl_sweep x4, k_impl_apply",
+                     "mean_ms": round(ms, 4), "pipeline_bytes": nbytes},
+        "cpu_baseline": None}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -328,14 +399,15 @@ def main(argv=None):
                     help="with --split: cut positions snap to multiples of these (1,1,1 = plain bisection)")
     ap.add_argument("--groups", type=int, default=8,
                     help="with --split: groups (devices) the pieces are regrouped into for the balance report")
-    ap.add_argument("--op", default=None, choices=["diff6", "wcns5", "wcns5_euler", "ns_periodic", "wcns5_curv", "ns_curv"],
+    ap.add_argument("--op", default=None, choices=["diff6", "wcns5", "wcns5_euler", "ns_periodic", "wcns5_curv", "ns_curv", "implicit_curv"],
                     help="time one operator instead of the solver, on a 256x128x128 block, 5 variables, each "
                          "direction: diff6 = the sixth-order staggered flux difference (Section 2.2, Eq. 2); "
                          "wcns5 = the WCNS-E-5 weighted cell-edge interpolation; wcns5_euler = the periodic "
                          "inviscid WCNS-E-5 residual (all three directions); ns_periodic = that residual plus the "
                          "fourth-order central viscous terms; wcns5_curv = the inviscid residual on a wavy "
                          "curvilinear periodic grid (metrics computed once, their time reported); ns_curv = that "
-                         "residual plus the curvilinear fourth-order viscous terms")
+                         "residual plus the curvilinear fourth-order viscous terms; implicit_curv = implicit "
+                         "steps (backward Euler, Jacobi sweeps) on the curvilinear residual")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (HBM counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -351,6 +423,8 @@ def main(argv=None):
         return 0
     if a.op in ("wcns5_euler", "ns_periodic", "wcns5_curv", "ns_curv") and a.gpus == 1:
         return bench_wcns5_euler(a)
+    if a.op == "implicit_curv" and a.gpus == 1:
+        return bench_implicit(a)
     if a.op is not None and a.gpus == 1:
         return bench_op(a)
     if a.gpus != 1:
