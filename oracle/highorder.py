@@ -39,7 +39,7 @@ Test infrastructure, like the rest of this package.  Two operators:
 10. an implicit step (implicit_steps_curv_periodic): backward Euler with a
    flux-split approximate Jacobian relaxed by point-Jacobi sweeps, the
    reading of the sparse linear solve the paper's flowchart names (stated
-   below).  Pinned by the explicit Euler limit, a kept uniform stream, the
+   below), with the viscous terms and a central diffusion split optional.  Pinned by the explicit Euler limit, a kept uniform stream, the
    sweeps' fixed point and stability past the explicit limit; its accuracy
    as a linear solver of the exact Jacobian is not a claim ("parity
    unpinned" for the approximate Jacobian itself).
@@ -583,14 +583,33 @@ def _face_lambda(W, Sf, d, gamma):
     return np.abs(Wm[1] * Sf[0] + Wm[2] * Sf[1] + Wm[3] * Sf[2]) + c * np.sqrt(np.sum(Sf * Sf, axis=0))
 
 
-def implicit_sweeps_curv_periodic(Q, R, S, Jinv, gamma: float, dt: float, sweeps: int):
+# For viscous flow the residual adds the fourth-order viscous terms and the
+# operator a central diffusion split: with the viscous spectral radius
+#   lv_f = max(4/3, gamma/Pr) (mu/rho)_f |S_f|^2 / J^{-1}_f
+# at each face (mu/rho and J^{-1} the means of the face's two cells),
+# D_i gains J_i sum_d (lv_f+ + lv_f-) and O_i gains -(lv_f+ dQ_{i+1} + lv_f- dQ_{i-1}).
+
+def _face_lambda_visc(W, Sf, Jinv, d, gamma, prandtl, mu_inf, s_star):
+    from .flux import sutherland
+    ax = [2, 1, 0][d]
+    nu = sutherland(W[4] / W[0], mu_inf, s_star) / W[0]
+    num = 0.5 * (nu + np.roll(nu, -1, axis=ax))
+    jm = 0.5 * (Jinv + np.roll(Jinv, -1, axis=ax))
+    return max(4.0 / 3.0, gamma / prandtl) * num * np.sum(Sf * Sf, axis=0) / jm
+
+
+def implicit_sweeps_curv_periodic(Q, R, S, Jinv, gamma: float, dt: float, sweeps: int, viscous: bool = False,
+                                  prandtl: float = 0.72, mu_inf: float = 0.0, s_star: float = 110.4 / 288.15):
     """dQ of the reading above (R: the residual at Q), after `sweeps` Jacobi sweeps."""
     from .flux import primitives
     W = primitives(Q, gamma)
     Jc = 1.0 / Jinv
     lam = [_face_lambda(W, S[d], d, gamma) for d in range(3)]       # faces i + 1/2
+    lv = [(_face_lambda_visc(W, S[d], Jinv, d, gamma, prandtl, mu_inf, s_star) if viscous else 0.0 * Jinv)
+          for d in range(3)]
     axis = [3, 2, 1]                                                # axis of d in [5, k, j, i]
-    D = 1.0 / dt + Jc * sum(0.5 * (lam[d] + np.roll(lam[d], 1, axis=axis[d] - 1)) for d in range(3))
+    D = 1.0 / dt + Jc * sum(0.5 * (lam[d] + np.roll(lam[d], 1, axis=axis[d] - 1))
+                            + (lv[d] + np.roll(lv[d], 1, axis=axis[d] - 1)) for d in range(3))
     dQ = -R / D
     for _ in range(sweeps):
         O = np.zeros_like(Q)
@@ -598,21 +617,25 @@ def implicit_sweeps_curv_periodic(Q, R, S, Jinv, gamma: float, dt: float, sweeps
             ax = axis[d]
             Sp, Sm = S[d], np.roll(S[d], 1, axis=ax)               # faces i + 1/2, i - 1/2
             lp, lm = lam[d], np.roll(lam[d], 1, axis=ax - 1)
+            vp, vm = lv[d], np.roll(lv[d], 1, axis=ax - 1)
             Qp, dQp = np.roll(Q, -1, axis=ax), np.roll(dQ, -1, axis=ax)
             Qm, dQm = np.roll(Q, 1, axis=ax), np.roll(dQ, 1, axis=ax)
             dFp = euler_flux_through(Qp + dQp, Sp, gamma) - euler_flux_through(Qp, Sp, gamma)
             dFm = euler_flux_through(Qm + dQm, Sm, gamma) - euler_flux_through(Qm, Sm, gamma)
-            O = O + 0.5 * ((dFp - lp * dQp) - (dFm + lm * dQm))
+            O = O + 0.5 * ((dFp - lp * dQp) - (dFm + lm * dQm)) - (vp * dQp + vm * dQm)
         dQ = (-R - Jc * O) / D
     return dQ
 
 
 def implicit_steps_curv_periodic(Q, S, Jinv, gamma: float, eps_h: float, dt: float, nsteps: int, sweeps: int,
-                                 eps: float = 1e-6):
-    """nsteps implicit steps (the reading above) of the inviscid curvilinear
-    periodic WCNS-E-5 residual."""
+                                 eps: float = 1e-6, viscous: bool = False, prandtl: float = 0.72,
+                                 mu_inf: float = 0.0, s_star: float = 110.4 / 288.15):
+    """nsteps implicit steps (the reading above) of the curvilinear periodic
+    WCNS-E-5 residual, with the fourth-order viscous terms when viscous."""
     q = Q
     for _ in range(nsteps):
         R = wcns5_euler_residual_curv_periodic(q, S, Jinv, gamma, eps_h, eps)
-        q = q + implicit_sweeps_curv_periodic(q, R, S, Jinv, gamma, dt, sweeps)
+        if viscous:
+            R = R + viscous_residual_curv_periodic(q, S, Jinv, gamma, prandtl, mu_inf, s_star)
+        q = q + implicit_sweeps_curv_periodic(q, R, S, Jinv, gamma, dt, sweeps, viscous, prandtl, mu_inf, s_star)
     return q

@@ -804,3 +804,31 @@ def test_implicit_steps_stable_past_the_explicit_limit():
     assert not np.all(np.isfinite(qe)) or np.max(np.abs(qe)) > 1e3
     qi = ho.implicit_steps_curv_periodic(q, S, Jinv, 1.4, 0.1, dt, 20, 4)
     assert np.all(np.isfinite(qi)) and qi[0].min() > 0.5 and np.max(np.abs(qi - q)) < 1.0
+
+
+def test_viscous_implicit_step_limits_and_steady_convergence():
+    """With viscous terms: the explicit Euler limit dQ = -dt R + O(dt^2) holds
+    for the Navier-Stokes residual; and on the decaying shear wave (whose
+    steady state is the uniform mean flow) 10 implicit steps at 100 times the
+    CFL-1 step with 6 sweeps shrink the residual several times more than 10
+    RK3 steps at the CFL-1 step (point-Jacobi damps the wave's smooth mode
+    slowly, so a larger step gains little beyond that)."""
+    nu = 0.05
+    q, S, Jinv, Y, _, _ = _shear_wave(16, True, 1e-3)
+
+    def Rns(x):
+        return (ho.wcns5_euler_residual_curv_periodic(x, S, Jinv, 1.4, 0.1)
+                + ho.viscous_residual_curv_periodic(x, S, Jinv, 1.4, 0.72, nu, 0.38))
+    R0 = Rns(q)
+    rel = []
+    for dt in (1e-3, 1e-4):
+        dQ = ho.implicit_sweeps_curv_periodic(q, R0, S, Jinv, 1.4, dt, 3, True, 0.72, nu, 0.38)
+        rel.append(np.max(np.abs(dQ + dt * R0)) / (dt * np.max(np.abs(R0))))
+    assert 9.0 < rel[0] / rel[1] < 11.0, rel
+    dt1 = ho.cfl_time_step_curv_periodic(q, S, Jinv, 1.4, 1.0, True, 0.72, nu, 0.38)
+    qi = ho.implicit_steps_curv_periodic(q, S, Jinv, 1.4, 0.1, 100.0 * dt1, 10, 6, viscous=True, mu_inf=nu,
+                                         s_star=0.38)
+    qe = ho.ns_steps_curv_periodic(q, S, Jinv, 1.4, 0.1, 0.72, nu, 0.38, dt1, 10)
+    r_impl = np.max(np.abs(Rns(qi))) / np.max(np.abs(R0))
+    r_expl = np.max(np.abs(Rns(qe))) / np.max(np.abs(R0))
+    assert r_impl < 0.85 and (1.0 - r_impl) > 5.0 * (1.0 - r_expl), (r_impl, r_expl)
