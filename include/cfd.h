@@ -465,15 +465,21 @@ cfd_status cfd_wcns5_ns_steps_curv_periodic(double* q_dev, const double* s_dev, 
  * Jacobian A+- = (A +- lambda I)/2 at each face (lambda = |u . S| + c |S| of
  * the mean primitive state of the two cells), relaxed by `sweeps` point-Jacobi
  * sweeps from dQ = -R / D, D = 1/dt + J sum_d (lambda_+ + lambda_-)/2; the
- * off-diagonal products are flux differences F(Q + dQ) . S - F(Q) . S.  Then
- * q += dQ; nsteps times, in place.  work_dev: cfd_wcns5_implicit_step_work_bytes()
- * bytes.  dt > 0, nsteps >= 0, 0 <= sweeps <= 1000, gamma > 1, and q, the
- * metrics and the workspace pairwise disjoint, else CFD_EINVAL; a short
- * workspace gives CFD_ENOMEM.  Asynchronous on stream. */
+ * off-diagonal products are flux differences F(Q + dQ) . S - F(Q) . S.  With
+ * viscous != 0 the residual adds cfd_c4_viscous_add_curv_periodic's terms and
+ * the operator a central diffusion split: per face the viscous spectral radius
+ * lv = max(4/3, gamma/Pr)(mu/rho)|S|^2 / J^{-1} (means of the two cells) adds
+ * J sum_d (lv_+ + lv_-) to D and -(lv_+ dQ_{i+1} + lv_- dQ_{i-1}) to the
+ * off-diagonal sum.  Then q += dQ; nsteps times, in place.  work_dev:
+ * cfd_wcns5_implicit_step_work_bytes() bytes.  dt > 0, nsteps >= 0,
+ * 0 <= sweeps <= 1000, gamma > 1, for viscous flow Pr > 0, mu_inf >= 0,
+ * s_star > 0, and q, the metrics and the workspace pairwise disjoint, else
+ * CFD_EINVAL; a short workspace gives CFD_ENOMEM.  Asynchronous on stream. */
 cfd_status cfd_wcns5_implicit_step_work_bytes(const int32_t n[3], size_t* bytes);
 cfd_status cfd_wcns5_implicit_steps_curv_periodic(double* q_dev, const double* s_dev, const double* jinv_dev,
                                                   void* work_dev, size_t work_bytes, const int32_t n[3], double gamma,
-                                                  double entropy_fix, double eps, double dt, int32_t nsteps,
+                                                  double entropy_fix, double eps, int32_t viscous, double prandtl,
+                                                  double mu_inf, double s_star, double dt, int32_t nsteps,
                                                   int32_t sweeps, hipStream_t stream);
 
 /* The fourth-order viscous terms of cfd_c4_viscous_add_curv_periodic on blocks

@@ -156,7 +156,8 @@ def lib(build_if_missing: bool = True):
                                                    vp]
     L.cfd_wcns5_implicit_step_work_bytes.argtypes = [i32p, C.POINTER(C.c_size_t)]
     L.cfd_wcns5_implicit_steps_curv_periodic.argtypes = [vp, vp, vp, vp, C.c_size_t, i32p, C.c_double, C.c_double,
-                                                         C.c_double, C.c_double, i32, i32, vp]
+                                                         C.c_double, i32, C.c_double, C.c_double, C.c_double,
+                                                         C.c_double, i32, i32, vp]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]
@@ -565,10 +566,13 @@ def wcns5_ns_steps_curv_periodic(q, S, jinv, dt: float, nsteps: int, gamma: floa
 
 
 def wcns5_implicit_steps_curv_periodic(q, S, jinv, dt: float, nsteps: int, sweeps: int, gamma: float = 1.4,
-                                       entropy_fix: float = 0.1, eps: float = 1e-6, work=None, stream=None):
+                                       entropy_fix: float = 0.1, eps: float = 1e-6, viscous: bool = False,
+                                       prandtl: float = 0.72, mu_inf: float = 1e-3, s_star: float = 110.4 / 288.15,
+                                       work=None, stream=None):
     """nsteps implicit steps (backward Euler, point-Jacobi sweeps) of the
-    curvilinear periodic WCNS-E-5 Euler residual on the device
-    (cfd_wcns5_implicit_steps_curv_periodic), in place on q.  Returns q."""
+    curvilinear periodic WCNS-E-5 residual, with the fourth-order viscous
+    terms when viscous, on the device (cfd_wcns5_implicit_steps_curv_periodic),
+    in place on q.  Returns q."""
     import torch
     if q.dtype != torch.float64 or not q.is_cuda or not q.is_contiguous() or q.dim() != 4 or q.shape[0] != 5:
         raise ValueError("q must be a contiguous float64 CUDA tensor [5, nk, nj, ni]")
@@ -582,8 +586,10 @@ def wcns5_implicit_steps_curv_periodic(q, S, jinv, dt: float, nsteps: int, sweep
     if work is None or work.numel() * work.element_size() < nbytes.value:
         work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
     _check(lib().cfd_wcns5_implicit_steps_curv_periodic(_ptr(q), _ptr(S), _ptr(jinv), _ptr(work), nbytes.value, nn,
-                                                        float(gamma), float(entropy_fix), float(eps), float(dt),
-                                                        int(nsteps), int(sweeps), _stream_handle(torch, stream)))
+                                                        float(gamma), float(entropy_fix), float(eps),
+                                                        1 if viscous else 0, float(prandtl), float(mu_inf),
+                                                        float(s_star), float(dt), int(nsteps), int(sweeps),
+                                                        _stream_handle(torch, stream)))
     return q
 
 

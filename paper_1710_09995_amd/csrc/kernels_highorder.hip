@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/cfd.h"
@@ -1561,7 +1562,9 @@ __device__ __forceinline__ void euler_flux_dot(double q0, double q1, double q2, 
 
 // lam[d * cells + c]: the spectral radius at face c + 1/2 along d.
 __global__ void __launch_bounds__(256) k_impl_lambda(const double* __restrict__ q, const double* __restrict__ s,
-                                                     double* __restrict__ lam, Cells3 C, double gamma) {
+                                                     const double* __restrict__ jinv, double* __restrict__ lam,
+                                                     double* __restrict__ lamv, Cells3 C, double gamma,
+                                                     Gas<double> visc, int viscous) {
   const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
   const double gm1 = gamma - 1.0;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
@@ -1577,19 +1580,31 @@ __global__ void __launch_bounds__(256) k_impl_lambda(const double* __restrict__ 
       const double* sd = s + 3 * d * cells;
       const double sx = sd[c], sy = sd[cells + c], sz = sd[2 * cells + c];
       lam[d * cells + c] = fabs(u * sx + v * sy + w * sz) + sqrt(gamma * pr / r) * sqrt(sx * sx + sy * sy + sz * sz);
+      if (viscous) {
+        const double Ta = a.p / a.r, Tb = b.p / b.r;
+        const double na = visc.mu_inf * Ta * sqrt(Ta) * (1.0 + visc.s_star) / (Ta + visc.s_star) / a.r;
+        const double nb = visc.mu_inf * Tb * sqrt(Tb) * (1.0 + visc.s_star) / (Tb + visc.s_star) / b.r;
+        const double num = 0.5 * (na + nb), jm = 0.5 * (jinv[c] + jinv[p]);
+        lamv[d * cells + c] = fmax(4.0 / 3.0, gamma / visc.prandtl) * num * (sx * sx + sy * sy + sz * sz) / jm;
+      }
     }
   }
 }
 
 // The diagonal D and the first iterate dQ = -R / D.
 __global__ void __launch_bounds__(256) k_impl_diag(const double* __restrict__ r, const double* __restrict__ lam,
-                                                   const double* __restrict__ jinv, double* __restrict__ diag,
-                                                   double* __restrict__ dq, Cells3 C, double dt) {
+                                                   const double* __restrict__ lamv, const double* __restrict__ jinv,
+                                                   double* __restrict__ diag, double* __restrict__ dq, Cells3 C,
+                                                   double dt, int viscous) {
   const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
     double sum = 0.0;
-    for (int d = 0; d < 3; ++d) sum = sum + 0.5 * (lam[d * cells + c] + lam[d * cells + C.step(i, j, k, d, -1)]);
+    for (int d = 0; d < 3; ++d) {
+      const int64_t m = C.step(i, j, k, d, -1);
+      const double t = 0.5 * (lam[d * cells + c] + lam[d * cells + m]);
+      sum = sum + (viscous ? t + (lamv[d * cells + c] + lamv[d * cells + m]) : t);
+    }
     const double D = 1.0 / dt + (1.0 / jinv[c]) * sum;
     diag[c] = D;
     for (int v = 0; v < 5; ++v) dq[v * cells + c] = -r[v * cells + c] / D;
@@ -1599,9 +1614,9 @@ __global__ void __launch_bounds__(256) k_impl_diag(const double* __restrict__ r,
 // One Jacobi sweep: dq_in -> dq_out.
 __global__ void __launch_bounds__(256) k_impl_sweep(const double* __restrict__ q, const double* __restrict__ r,
                                                     const double* __restrict__ s, const double* __restrict__ lam,
-                                                    const double* __restrict__ jinv, const double* __restrict__ diag,
-                                                    const double* __restrict__ dq_in, double* __restrict__ dq_out,
-                                                    Cells3 C, double gm1) {
+                                                    const double* __restrict__ lamv, const double* __restrict__ jinv,
+                                                    const double* __restrict__ diag, const double* __restrict__ dq_in,
+                                                    double* __restrict__ dq_out, Cells3 C, double gm1, int viscous) {
   const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
@@ -1627,8 +1642,11 @@ __global__ void __launch_bounds__(256) k_impl_sweep(const double* __restrict__ q
         euler_flux_dot(q[m], q[cells + m], q[2 * cells + m], q[3 * cells + m], q[4 * cells + m], sx, sy, sz, gm1, Fb);
         for (int v = 0; v < 5; ++v) dFm[v] = Fa[v] - Fb[v];
       }
-      for (int v = 0; v < 5; ++v)
+      const double vp = viscous ? lamv[d * cells + c] : 0.0, vm = viscous ? lamv[d * cells + m] : 0.0;
+      for (int v = 0; v < 5; ++v) {
         O[v] = O[v] + 0.5 * ((dFp[v] - lp * dq_in[v * cells + p]) - (dFm[v] + lm * dq_in[v * cells + m]));
+        if (viscous) O[v] = O[v] - (vp * dq_in[v * cells + p] + vm * dq_in[v * cells + m]);
+      }
     }
     const double J = 1.0 / jinv[c], D = diag[c];
     for (int v = 0; v < 5; ++v) dq_out[v * cells + c] = (-r[v * cells + c] - J * O[v]) / D;
@@ -1647,14 +1665,16 @@ extern "C" cfd_status cfd_wcns5_implicit_step_work_bytes(const int32_t n[3], siz
     if (!n || !bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
     if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
     const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-    *bytes = wcns5_residual_work(n) + (size_t)8 * 19 * cells;     // R, two dQ, lambda (3), D
+    // scratch of the residual or the viscous terms, then R, two dQ, lambda (3), viscous lambda (3), D
+    *bytes = std::max(wcns5_residual_work(n), (size_t)8 * 29 * cells) + (size_t)8 * 22 * cells;
   });
 }
 
 extern "C" cfd_status cfd_wcns5_implicit_steps_curv_periodic(double* q_dev, const double* s_dev,
                                                              const double* jinv_dev, void* work_dev,
                                                              size_t work_bytes, const int32_t n[3], double gamma,
-                                                             double entropy_fix, double eps, double dt,
+                                                             double entropy_fix, double eps, int32_t viscous,
+                                                             double prandtl, double mu_inf, double s_star, double dt,
                                                              int32_t nsteps, int32_t sweeps, hipStream_t stream) {
   return cfd::host_guarded([&] {
     if (!q_dev || !s_dev || !jinv_dev || !work_dev || !n) cfd::host_fail(CFD_EINVAL, "NULL argument");
@@ -1662,9 +1682,12 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_curv_periodic(double* q_dev, cons
     if (!(dt > 0.0) || !std::isfinite(dt)) cfd::host_fail(CFD_EINVAL, "dt must be positive and finite");
     if (nsteps < 0 || sweeps < 0 || sweeps > 1000) cfd::host_fail(CFD_EINVAL, "nsteps >= 0, sweeps in [0, 1000]");
     if (!(gamma > 1.0) || !std::isfinite(gamma)) cfd::host_fail(CFD_EINVAL, "gamma must exceed 1");
+    if (viscous && (!(prandtl > 0.0) || !(mu_inf >= 0.0) || !(s_star > 0.0) || !std::isfinite(mu_inf)))
+      cfd::host_fail(CFD_EINVAL, "bad gas parameters");
     const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-    const size_t rw = wcns5_residual_work(n);
-    const size_t need = rw + (size_t)8 * 19 * cells;
+    const size_t rw0 = wcns5_residual_work(n);
+    const size_t rw = std::max(rw0, (size_t)8 * 29 * cells);
+    const size_t need = rw + (size_t)8 * 22 * cells;
     if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_implicit_step_work_bytes()");
     if (!cfd::apart(q_dev, 40 * cells, work_dev, (int64_t)work_bytes) ||
         !cfd::apart(q_dev, 40 * cells, s_dev, 72 * cells) || !cfd::apart(q_dev, 40 * cells, jinv_dev, 8 * cells))
@@ -1676,17 +1699,23 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_curv_periodic(double* q_dev, cons
     double* dqa = R + 5 * cells;
     double* dqb = dqa + 5 * cells;
     double* lam = dqb + 5 * cells;
-    double* diag = lam + 3 * cells;
+    double* lamv = lam + 3 * cells;
+    double* diag = lamv + 3 * cells;
+    const cfd::Gas<double> vgas = cfd::viscous_gas(gamma, viscous ? prandtl : 1.0, mu_inf, s_star);
     const cfd::Cells3 C{{n[0], n[1], n[2]}};
     const int gr = cfd::grid_for(cells);
     for (int it = 0; it < nsteps; ++it) {
-      cfd::wcns5_residual_core(q_dev, s_dev, jinv_dev, R, work_dev, rw, n, nullptr, gamma, entropy_fix, eps, stream);
-      hipLaunchKernelGGL(cfd::k_impl_lambda, dim3(gr), dim3(256), 0, stream, q_dev, s_dev, lam, C, gamma);
-      hipLaunchKernelGGL(cfd::k_impl_diag, dim3(gr), dim3(256), 0, stream, R, lam, jinv_dev, diag, dqa, C, dt);
+      cfd::wcns5_residual_core(q_dev, s_dev, jinv_dev, R, work_dev, rw0, n, nullptr, gamma, entropy_fix, eps, stream);
+      if (viscous)
+        cfd::c4_viscous_curv_core(q_dev, s_dev, jinv_dev, R, static_cast<double*>(work_dev), n, vgas, stream);
+      hipLaunchKernelGGL(cfd::k_impl_lambda, dim3(gr), dim3(256), 0, stream, q_dev, s_dev, jinv_dev, lam, lamv, C,
+                         gamma, vgas, viscous ? 1 : 0);
+      hipLaunchKernelGGL(cfd::k_impl_diag, dim3(gr), dim3(256), 0, stream, R, lam, lamv, jinv_dev, diag, dqa, C, dt,
+                         viscous ? 1 : 0);
       double *cur = dqa, *nxt = dqb;
       for (int k = 0; k < sweeps; ++k) {
-        hipLaunchKernelGGL(cfd::k_impl_sweep, dim3(gr), dim3(256), 0, stream, q_dev, R, s_dev, lam, jinv_dev, diag,
-                           cur, nxt, C, gamma - 1.0);
+        hipLaunchKernelGGL(cfd::k_impl_sweep, dim3(gr), dim3(256), 0, stream, q_dev, R, s_dev, lam, lamv, jinv_dev,
+                           diag, cur, nxt, C, gamma - 1.0, viscous ? 1 : 0);
         std::swap(cur, nxt);
       }
       hipLaunchKernelGGL(cfd::k_impl_apply, dim3(cfd::grid_for(5 * cells)), dim3(256), 0, stream, q_dev, cur,

@@ -377,16 +377,19 @@ def test_implicit_steps_bad_arguments():
     n = (C.c_int32 * 3)(8, 4, 2)
     nb = C.c_size_t()
     assert L.cfd_wcns5_implicit_step_work_bytes(n, C.byref(nb)) == 0
-    assert nb.value == 8 * (5 * 32 * 12 + 5 * 32 * 7) + 8 * 19 * 64
+    # the larger scratch (the viscous terms' 29 doubles per cell here) + 22 doubles per cell
+    assert nb.value == max(8 * (5 * 32 * 12 + 5 * 32 * 7), 8 * 29 * 64) + 8 * 22 * 64
     q, s, j, w = C.c_void_p(0x100000), C.c_void_p(0x900000), C.c_void_p(0x1100000), C.c_void_p(0x2100000)
-    ok = dict(q=q, s=s, j=j, w=w, wb=nb.value, g=1.4, ef=0.1, eps=1e-6, dt=0.01, ns=2, sw=3)
+    ok = dict(q=q, s=s, j=j, w=w, wb=nb.value, g=1.4, ef=0.1, eps=1e-6, v=1, pr=0.72, mu=1e-3, ss=0.38, dt=0.01,
+              ns=2, sw=3)
     bad = {-2: [dict(wb=nb.value - 8)],
            -1: [dict(q=None), dict(s=None), dict(j=None), dict(w=None), dict(g=1.0), dict(dt=0.0), dict(ns=-1),
                 dict(sw=-1), dict(sw=1001), dict(w=C.c_void_p(0x100000 + 8)), dict(s=C.c_void_p(0x100000 + 8)),
-                dict(w=C.c_void_p(0x1100000 - 8))]}
+                dict(w=C.c_void_p(0x1100000 - 8)), dict(pr=0.0), dict(mu=-1.0), dict(ss=0.0)]}
     for st_want, cases_ in bad.items():
         for b in cases_:
             a = dict(ok, **b)
             st = L.cfd_wcns5_implicit_steps_curv_periodic(a["q"], a["s"], a["j"], a["w"], a["wb"], n, a["g"], a["ef"],
-                                                          a["eps"], a["dt"], a["ns"], a["sw"], None)
+                                                          a["eps"], a["v"], a["pr"], a["mu"], a["ss"], a["dt"],
+                                                          a["ns"], a["sw"], None)
             assert st == st_want, b

@@ -326,3 +326,21 @@ def test_implicit_steps_parity_and_stability():
     dt = 20.0 * ho.cfl_time_step_curv_periodic(q, So, Jo, 1.4, 1.0)
     qi = wcns5_implicit_steps_curv_periodic(torch.from_numpy(q.copy()).cuda(), S, J, dt, 20, 4).cpu().numpy()
     assert np.all(np.isfinite(qi)) and qi[0].min() > 0.5 and np.max(np.abs(qi - q)) < 1.5
+
+
+def test_viscous_implicit_steps_parity():
+    """Implicit Navier-Stokes steps on the device against the oracle's (3 steps,
+    4 sweeps, the smooth flow on the wavy grid, oracle metrics on both sides),
+    within 1e-11 of max |q|."""
+    import torch
+    from paper_1710_09995_amd.binding import wcns5_implicit_steps_curv_periodic
+    n = (20, 12, 8)
+    Xv, P = _curv_grid(n, "wavy")
+    So, Jo = ho.metrics6(ho.periodic_vertices(Xv, P))
+    q = _smooth_state(n, seed=15)
+    say("viscous implicit steps", n)
+    got = wcns5_implicit_steps_curv_periodic(torch.from_numpy(q.copy()).cuda(), _dev(So), _dev(Jo), 0.02, 3, 4,
+                                             viscous=True, prandtl=0.72, mu_inf=0.02, s_star=0.38).cpu().numpy()
+    want = ho.implicit_steps_curv_periodic(q, So, Jo, 1.4, 0.1, 0.02, 3, 4, viscous=True, prandtl=0.72, mu_inf=0.02,
+                                           s_star=0.38)
+    assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
