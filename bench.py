@@ -275,8 +275,8 @@ def bench_wcns5_euler(a) -> int:
         nbytes += 8 * 5 * ((cells + P) + (P + F) + (F + cells * (1 if d == 0 else 2)))
         if curv:
             nbytes += 8 * 3 * F                # the faces' area vectors
-    if curv:                                   # R divided by J^{-1}
-        nbytes += 8 * cells * (5 + 5 + 1)
+    if curv:                                   # J^{-1} read by the last Eq. 2 pass
+        nbytes += 8 * cells
     if viscous and curv:   # as below, plus the cell metrics (9 in, 9 out), per face S_d, S_t across, J^{-1}
         nbytes += 8 * cells * ((5 + 4) + (4 + 12) + (9 + 9) + 3 * ((4 + 8 + 3 + 6 + 1) + 4) + 3 * (4 + 1 + 8))
     elif viscous:   # phi (Q in, 4 out), gradients (4 in, 12 out), per direction faces (16 in, 4 out) and the sum
@@ -295,7 +295,7 @@ def bench_wcns5_euler(a) -> int:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "pipeline: k_pad_prim_periodic, k_wcns5_roe_faces, k_window6_*<Eq2OpT>"
-                               + (", k_div_jinv" if curv else "")
+                               + (" (the last pass dividing by J^-1)" if curv else "")
                                + (", k_c4_phi, k_c4_grads, k_c4_cell_metrics, k_c4_visc_faces_curv, k_c4_flux_sub"
                                   if viscous and curv else
                                   ", k_c4_phi, k_c4_grads, k_c4_visc_faces, k_c4_flux_sub" if viscous else ""),
@@ -354,7 +354,7 @@ def bench_implicit(a) -> int:
         P = cells // n[d] * (n[d] + 10)
         F = cells // n[d] * (n[d] + 5)
         nbytes += 8 * 5 * ((cells + P) + (P + F) + (F + cells * (1 if d == 0 else 2))) + 8 * 3 * F
-    nbytes += 8 * cells * (5 + 5 + 1)                                   # R / J^{-1}
+    nbytes += 8 * cells                                                 # J^{-1} in the last Eq. 2 pass
     nbytes += 8 * cells * ((5 + 9 + 3) + (5 + 3 + 1 + 1 + 5))           # radii; diagonal and first iterate
     nbytes += sweeps * 8 * cells * (5 + 5 + 5 + 9 + 3 + 1 + 1 + 5)      # one sweep
     nbytes += 8 * cells * 15                                            # q += dQ

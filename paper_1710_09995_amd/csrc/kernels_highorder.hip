@@ -39,6 +39,7 @@ template <bool ACC_>
 struct Eq2OpT {
   static constexpr int NOUT = 1;
   static constexpr bool ACC = ACC_;
+  static constexpr bool DIV = false;
   double c1, c2, c3;
   __device__ __forceinline__ void operator()(const double* w, double* o) const {
     o[0] = c1 * (w[3] - w[2]) + c2 * (w[4] - w[1]) + c3 * (w[5] - w[0]);
@@ -66,10 +67,24 @@ __device__ __forceinline__ double wcns5_left(double um2, double um1, double u0, 
 struct Wcns5Op {
   static constexpr int NOUT = 2;
   static constexpr bool ACC = false;
+  static constexpr bool DIV = false;
   double eps;
   __device__ __forceinline__ void operator()(const double* w, double* o) const {
     o[0] = wcns5_left(w[0], w[1], w[2], w[3], w[4], eps);
     o[1] = wcns5_left(w[5], w[4], w[3], w[2], w[1], eps);
+  }
+};
+
+// Eq. (2) added into the output, the sum then divided by J^{-1} of the cell:
+// the last direction's pass of a curvilinear residual (along j or k only).
+struct Eq2DivOp {
+  static constexpr int NOUT = 1;
+  static constexpr bool ACC = true;
+  static constexpr bool DIV = true;
+  double c1, c2, c3;
+  const double* jinv;
+  __device__ __forceinline__ void operator()(const double* w, double* o) const {
+    o[0] = c1 * (w[3] - w[2]) + c2 * (w[4] - w[1]) + c3 * (w[5] - w[0]);
   }
 };
 
@@ -144,7 +159,13 @@ __global__ void __launch_bounds__(256) k_window6_march(const double* __restrict_
     double o[Op::NOUT];
     op(&win[s], o);
     const int64_t at = ob + (int64_t)(c0 + s) * sout;
-    if constexpr (Op::ACC) out0[at] += o[0]; else out0[at] = o[0];
+    if constexpr (Op::DIV) {
+      out0[at] = (out0[at] + o[0]) / op.jinv[at - (int64_t)v * mi * mj * mk];
+    } else if constexpr (Op::ACC) {
+      out0[at] += o[0];
+    } else {
+      out0[at] = o[0];
+    }
     if constexpr (Op::NOUT > 1) out1[at] = o[Op::NOUT - 1];
   }
 }
@@ -153,6 +174,7 @@ __global__ void __launch_bounds__(256) k_window6_march(const double* __restrict_
 template <class Op>
 void launch_window6(const double* in, double* out0, double* out1, const int64_t m[3], int d, int nvar, const Op& op,
                     hipStream_t stream) {
+  if (Op::DIV && d == 0) host_fail(CFD_EINVAL, "the dividing Eq. 2 pass runs along j or k only");
   if (d == 0) {
     const int64_t nseg = (m[0] + SEG - 1) / SEG;
     const int64_t nrows = (int64_t)nvar * m[1] * m[2];
@@ -332,13 +354,6 @@ __global__ void __launch_bounds__(256) k_metric_jinv(Grid g, double* __restrict_
   }
 }
 
-__global__ void __launch_bounds__(256) k_div_jinv(double* __restrict__ r, const double* __restrict__ jinv,
-                                                  int64_t cells) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += (int64_t)gridDim.x * blockDim.x) {
-    const double j = jinv[t];
-    for (int q = 0; q < 5; ++q) r[q * cells + t] = r[q * cells + t] / j;
-  }
-}
 
 // Blocks joined face to face.  Index of cell (a, b, c) of a block whose
 // extent along d is nd and whose other extents are the caller's.
@@ -612,10 +627,11 @@ void wcns5_residual_core(const double* q_dev, const double* s_dev, const double*
     const double c1 = 75.0 / (64.0 * hd), c2 = -25.0 / (384.0 * hd), c3 = 3.0 / (640.0 * hd);
     if (d == 0)
       launch_window6(F, r_dev, nullptr, m, d, 5, Eq2OpT<false>{c1, c2, c3}, stream);
+    else if (d == 2 && s_dev)       // the last pass also divides the sum by J^{-1}
+      launch_window6(F, r_dev, nullptr, m, d, 5, Eq2DivOp{c1, c2, c3, jinv_dev}, stream);
     else
       launch_window6(F, r_dev, nullptr, m, d, 5, Eq2OpT<true>{c1, c2, c3}, stream);
   }
-  if (s_dev) hipLaunchKernelGGL(k_div_jinv, dim3(grid_for(cells)), dim3(256), 0, stream, r_dev, jinv_dev, cells);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
 }
@@ -1243,7 +1259,6 @@ extern "C" cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_
       cfd::wcns5_work(n, pmax, fmax);
       double* W = static_cast<double*>(work_dev);
       double* F = W + pmax;
-      const int64_t cells = cells_of(b);
       for (int d = 0; d < 3; ++d) {
         const int lo = nbr[6 * b + 2 * d], hi = nbr[6 * b + 2 * d + 1];
         const int nlo = dims[3 * lo + d], nhi = dims[3 * hi + d];
@@ -1260,11 +1275,11 @@ extern "C" cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_
         const double c1 = 75.0 / 64.0, c2 = -25.0 / 384.0, c3 = 3.0 / 640.0;
         if (d == 0)
           cfd::launch_window6(F, r_dev[b], nullptr, m, d, 5, cfd::Eq2OpT<false>{c1, c2, c3}, stream);
+        else if (d == 2)            // the last pass also divides the sum by J^{-1}
+          cfd::launch_window6(F, r_dev[b], nullptr, m, d, 5, cfd::Eq2DivOp{c1, c2, c3, jinv_dev[b]}, stream);
         else
           cfd::launch_window6(F, r_dev[b], nullptr, m, d, 5, cfd::Eq2OpT<true>{c1, c2, c3}, stream);
       }
-      hipLaunchKernelGGL(cfd::k_div_jinv, dim3(cfd::grid_for(cells)), dim3(256), 0, stream, r_dev[b], jinv_dev[b],
-                         cells);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
