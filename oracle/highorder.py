@@ -36,7 +36,8 @@ Test infrastructure, like the rest of this package.  Two operators:
    terms across the same seams (viscous_residual_blocks);
 9. RK3 Navier-Stokes steps on periodic curvilinear blocks
    (ns_steps_curv_periodic);
-10. an implicit step (implicit_steps_curv_periodic): backward Euler with a
+10. an implicit step (implicit_steps_curv_periodic, and implicit_steps_blocks
+   for blocks joined face to face): backward Euler with a
    flux-split approximate Jacobian relaxed by point-Jacobi sweeps, the
    reading of the sparse linear solve the paper's flowchart names (stated
    below), with the viscous terms and a central diffusion split optional.  Pinned by the explicit Euler limit, a kept uniform stream, the
@@ -575,12 +576,16 @@ def euler_flux_through(Q: np.ndarray, S: np.ndarray, gamma: float) -> np.ndarray
                      (Q[4] + W[4]) * U])
 
 
-def _face_lambda(W, Sf, d, gamma):
-    """Spectral radius at faces i + 1/2 along d from the mean primitive state of cells i, i + 1."""
-    ax = 1 + [2, 1, 0][d]
-    Wm = 0.5 * (W + np.roll(W, -1, axis=ax))
+def _lambda_of(W, Wn, Sf, gamma):
+    """Spectral radius through Sf of the mean of primitive states W and Wn."""
+    Wm = 0.5 * (W + Wn)
     c = np.sqrt(gamma * Wm[4] / Wm[0])
     return np.abs(Wm[1] * Sf[0] + Wm[2] * Sf[1] + Wm[3] * Sf[2]) + c * np.sqrt(np.sum(Sf * Sf, axis=0))
+
+
+def _face_lambda(W, Sf, d, gamma):
+    """Spectral radius at faces i + 1/2 along d from the mean primitive state of cells i, i + 1."""
+    return _lambda_of(W, np.roll(W, -1, axis=1 + [2, 1, 0][d]), Sf, gamma)
 
 
 # For viscous flow the residual adds the fourth-order viscous terms and the
@@ -639,3 +644,57 @@ def implicit_steps_curv_periodic(Q, S, Jinv, gamma: float, eps_h: float, dt: flo
             R = R + viscous_residual_curv_periodic(q, S, Jinv, gamma, prandtl, mu_inf, s_star)
         q = q + implicit_sweeps_curv_periodic(q, R, S, Jinv, gamma, dt, sweeps, viscous, prandtl, mu_inf, s_star)
     return q
+
+
+def implicit_steps_blocks(Qs, Ss, Jinvs, nbr, gamma: float, eps_h: float, dt: float, nsteps: int, sweeps: int,
+                          eps: float = 1e-6):
+    """Inviscid implicit steps (the reading above) on blocks joined face to face
+    (nbr as for wcns5_euler_residual_blocks).  A cell's neighbours across a
+    seam are the neighbour block's cells and every sweep reads only the
+    previous iterate, so point-Jacobi is the same iteration however the domain
+    is cut: a split block gives bitwise the unsplit block's steps."""
+    from .flux import primitives
+    nb = len(Qs)
+
+    def shift(fields, b, d, s, lead):
+        """fields[b] seen from cell i + s (s = +1 or -1) along d, across the seams."""
+        ax = lead + [2, 1, 0][d]
+        f = fields[b]
+        n = f.shape[ax]
+        if s == 1:
+            hi = fields[nbr[b][2 * d + 1]]
+            return np.concatenate([_win(f, ax, 1, n - 1), _win(hi, ax, 0, 1)], axis=ax)
+        lo = fields[nbr[b][2 * d]]
+        return np.concatenate([_win(lo, ax, lo.shape[ax] - 1, 1), _win(f, ax, 0, n - 1)], axis=ax)
+
+    qs = list(Qs)
+    for _ in range(nsteps):
+        Rs = wcns5_euler_residual_blocks(qs, Ss, Jinvs, nbr, gamma, eps_h, eps)
+        Ws = [primitives(q, gamma) for q in qs]
+        lams = [[_lambda_of(Ws[b], shift(Ws, b, d, 1, 1), Ss[b][d], gamma) for d in range(3)] for b in range(nb)]
+        Ds, dQs = [], []
+        for b in range(nb):
+            Jc = 1.0 / Jinvs[b]
+            L = [[lams[c][d] for c in range(nb)] for d in range(3)]
+            D = 1.0 / dt + Jc * sum(0.5 * (lams[b][d] + shift(L[d], b, d, -1, 0)) for d in range(3))
+            Ds.append(D)
+            dQs.append(-Rs[b] / D)
+        for _ in range(sweeps):
+            new = []
+            for b in range(nb):
+                Jc = 1.0 / Jinvs[b]
+                O = np.zeros_like(qs[b])
+                for d in range(3):
+                    Sd = [S[d] for S in Ss]
+                    Ld = [lams[c][d] for c in range(nb)]
+                    Sp, Sm = Ss[b][d], shift(Sd, b, d, -1, 1)
+                    lp, lm = lams[b][d], shift(Ld, b, d, -1, 0)
+                    Qp, dQp = shift(qs, b, d, 1, 1), shift(dQs, b, d, 1, 1)
+                    Qm, dQm = shift(qs, b, d, -1, 1), shift(dQs, b, d, -1, 1)
+                    dFp = euler_flux_through(Qp + dQp, Sp, gamma) - euler_flux_through(Qp, Sp, gamma)
+                    dFm = euler_flux_through(Qm + dQm, Sm, gamma) - euler_flux_through(Qm, Sm, gamma)
+                    O = O + 0.5 * ((dFp - lp * dQp) - (dFm + lm * dQm))
+                new.append((-Rs[b] - Jc * O) / Ds[b])
+            dQs = new
+        qs = [q + dq for q, dq in zip(qs, dQs)]
+    return qs
