@@ -1210,6 +1210,49 @@ size_t check_seams(int32_t nblk, const int32_t* dims, const int32_t* nbr) {
 
 }  // namespace
 
+namespace cfd {
+
+// The residual of blocks joined face to face (arguments checked by the caller).
+void wcns5_blocks_residual_launch(int32_t nblk, const int32_t* dims, const int32_t* nbr, const double* const* q_dev,
+                                  const double* const* s_dev, const double* const* jinv_dev, double* const* r_dev,
+                                  void* work_dev, double gamma, double entropy_fix, double eps, hipStream_t stream) {
+  Gas<double> gas{};
+  gas.gamma = gamma;
+  gas.gm1 = gamma - 1.0;
+  gas.gg = gamma / (gamma - 1.0);
+  gas.eps_h = entropy_fix;
+  for (int b = 0; b < nblk; ++b) {
+    const int32_t* n = dims + 3 * b;
+    int64_t pmax, fmax;
+    wcns5_work(n, pmax, fmax);
+    double* W = static_cast<double*>(work_dev);
+    double* F = W + pmax;
+    for (int d = 0; d < 3; ++d) {
+      const int lo = nbr[6 * b + 2 * d], hi = nbr[6 * b + 2 * d + 1];
+      const int nlo = dims[3 * lo + d], nhi = dims[3 * hi + d];
+      int64_t mp[3] = {n[0], n[1], n[2]}, mf[3] = {n[0], n[1], n[2]};
+      mp[d] += 10;
+      mf[d] += 5;
+      const int64_t nf = mf[0] * mf[1] * mf[2];
+      hipLaunchKernelGGL(k_pad_prim_blocks, dim3(grid_for(mp[0] * mp[1] * mp[2])), dim3(256), 0, stream,
+                         q_dev[b], q_dev[lo], q_dev[hi], W, n[0], n[1], n[2], d, nlo, nhi, gamma - 1.0);
+      hipLaunchKernelGGL(k_wcns5_roe_faces, dim3(grid_for(nf)), dim3(256), 0, stream, W, F, (int)mf[0],
+                         (int)mf[1], (int)mf[2], d, eps, s_dev[b], s_dev[lo], s_dev[hi], n[0], n[1], n[2], nlo, nhi,
+                         gas);
+      const int64_t m[3] = {n[0], n[1], n[2]};
+      const double c1 = 75.0 / 64.0, c2 = -25.0 / 384.0, c3 = 3.0 / 640.0;
+      if (d == 0)
+        launch_window6(F, r_dev[b], nullptr, m, d, 5, Eq2OpT<false>{c1, c2, c3}, stream);
+      else if (d == 2)            // the last pass also divides the sum by J^{-1}
+        launch_window6(F, r_dev[b], nullptr, m, d, 5, Eq2DivOp{c1, c2, c3, jinv_dev[b]}, stream);
+      else
+        launch_window6(F, r_dev[b], nullptr, m, d, 5, Eq2OpT<true>{c1, c2, c3}, stream);
+    }
+  }
+}
+
+}  // namespace cfd
+
 extern "C" cfd_status cfd_wcns5_euler_blocks_work_bytes(int32_t nblk, const int32_t* dims, const int32_t* nbr,
                                                         size_t* bytes) {
   return cfd::host_guarded([&] {
@@ -1248,39 +1291,8 @@ extern "C" cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_
           cfd::host_fail(CFD_EINVAL, "the workspace overlaps an input");
       }
     }
-    cfd::Gas<double> gas{};
-    gas.gamma = gamma;
-    gas.gm1 = gamma - 1.0;
-    gas.gg = gamma / (gamma - 1.0);
-    gas.eps_h = entropy_fix;
-    for (int b = 0; b < nblk; ++b) {
-      const int32_t* n = dims + 3 * b;
-      int64_t pmax, fmax;
-      cfd::wcns5_work(n, pmax, fmax);
-      double* W = static_cast<double*>(work_dev);
-      double* F = W + pmax;
-      for (int d = 0; d < 3; ++d) {
-        const int lo = nbr[6 * b + 2 * d], hi = nbr[6 * b + 2 * d + 1];
-        const int nlo = dims[3 * lo + d], nhi = dims[3 * hi + d];
-        int64_t mp[3] = {n[0], n[1], n[2]}, mf[3] = {n[0], n[1], n[2]};
-        mp[d] += 10;
-        mf[d] += 5;
-        const int64_t nf = mf[0] * mf[1] * mf[2];
-        hipLaunchKernelGGL(cfd::k_pad_prim_blocks, dim3(cfd::grid_for(mp[0] * mp[1] * mp[2])), dim3(256), 0, stream,
-                           q_dev[b], q_dev[lo], q_dev[hi], W, n[0], n[1], n[2], d, nlo, nhi, gamma - 1.0);
-        hipLaunchKernelGGL(cfd::k_wcns5_roe_faces, dim3(cfd::grid_for(nf)), dim3(256), 0, stream, W, F, (int)mf[0],
-                           (int)mf[1], (int)mf[2], d, eps, s_dev[b], s_dev[lo], s_dev[hi], n[0], n[1], n[2], nlo, nhi,
-                           gas);
-        const int64_t m[3] = {n[0], n[1], n[2]};
-        const double c1 = 75.0 / 64.0, c2 = -25.0 / 384.0, c3 = 3.0 / 640.0;
-        if (d == 0)
-          cfd::launch_window6(F, r_dev[b], nullptr, m, d, 5, cfd::Eq2OpT<false>{c1, c2, c3}, stream);
-        else if (d == 2)            // the last pass also divides the sum by J^{-1}
-          cfd::launch_window6(F, r_dev[b], nullptr, m, d, 5, cfd::Eq2DivOp{c1, c2, c3, jinv_dev[b]}, stream);
-        else
-          cfd::launch_window6(F, r_dev[b], nullptr, m, d, 5, cfd::Eq2OpT<true>{c1, c2, c3}, stream);
-      }
-    }
+    cfd::wcns5_blocks_residual_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, r_dev, work_dev, gamma, entropy_fix, eps,
+                                      stream);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   });
@@ -1735,6 +1747,203 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_curv_periodic(double* q_dev, cons
       }
       hipLaunchKernelGGL(cfd::k_impl_apply, dim3(cfd::grid_for(5 * cells)), dim3(256), 0, stream, q_dev, cur,
                          5 * cells);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  });
+}
+
+// ------------------------------------------- implicit steps on joined blocks
+// The implicit kernels above with every neighbour read through the tables of
+// blocks joined face to face (Line): a sweep reads only the previous iterate,
+// so the iteration, and its bits, do not depend on how the domain is cut.
+namespace cfd {
+
+struct Lines3 {
+  Line l[3];
+};
+
+__global__ void __launch_bounds__(256) k_impl_lambda_line(const double* __restrict__ q, Lines3 Q,
+                                                          const double* __restrict__ s, double* __restrict__ lam,
+                                                          Dims3 D, double gamma) {
+  const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
+  const double gm1 = gamma - 1.0;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
+    const Prim<double> a = to_prim<double>(q[c], q[cells + c], q[2 * cells + c], q[3 * cells + c], q[4 * cells + c],
+                                           gm1);
+    for (int d = 0; d < 3; ++d) {
+      const Line& L = Q.l[d];
+      const Prim<double> b = to_prim<double>(line_at(L, 0, i, j, k, 1, d, D.n), line_at(L, 1, i, j, k, 1, d, D.n),
+                                             line_at(L, 2, i, j, k, 1, d, D.n), line_at(L, 3, i, j, k, 1, d, D.n),
+                                             line_at(L, 4, i, j, k, 1, d, D.n), gm1);
+      const double r = 0.5 * (a.r + b.r), u = 0.5 * (a.u + b.u), v = 0.5 * (a.v + b.v), w = 0.5 * (a.w + b.w),
+                   pr = 0.5 * (a.p + b.p);
+      const double* sd = s + 3 * d * cells;
+      const double sx = sd[c], sy = sd[cells + c], sz = sd[2 * cells + c];
+      lam[d * cells + c] = fabs(u * sx + v * sy + w * sz) + sqrt(gamma * pr / r) * sqrt(sx * sx + sy * sy + sz * sz);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_impl_diag_line(const double* __restrict__ r, const double* __restrict__ lam,
+                                                        Lines3 L, const double* __restrict__ jinv,
+                                                        double* __restrict__ diag, double* __restrict__ dq, Dims3 D,
+                                                        double dt) {
+  const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
+    double sum = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double t = 0.5 * (lam[d * cells + c] + line_at(L.l[d], d, i, j, k, -1, d, D.n));
+      sum = sum + t;
+    }
+    const double Dg = 1.0 / dt + (1.0 / jinv[c]) * sum;
+    diag[c] = Dg;
+    for (int v = 0; v < 5; ++v) dq[v * cells + c] = -r[v * cells + c] / Dg;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_impl_sweep_line(Lines3 Q, Lines3 DQ, Lines3 S, Lines3 L,
+                                                         const double* __restrict__ r, const double* __restrict__ s,
+                                                         const double* __restrict__ lam,
+                                                         const double* __restrict__ jinv,
+                                                         const double* __restrict__ diag, double* __restrict__ dq_out,
+                                                         Dims3 D, double gm1) {
+  const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
+    double O[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int d = 0; d < 3; ++d) {
+      double qp[5], dqp[5], qm[5], dqm[5];
+      for (int v = 0; v < 5; ++v) {
+        qp[v] = line_at(Q.l[d], v, i, j, k, 1, d, D.n);
+        dqp[v] = line_at(DQ.l[d], v, i, j, k, 1, d, D.n);
+        qm[v] = line_at(Q.l[d], v, i, j, k, -1, d, D.n);
+        dqm[v] = line_at(DQ.l[d], v, i, j, k, -1, d, D.n);
+      }
+      const double* sd = s + 3 * d * cells;
+      const double lp = lam[d * cells + c], lm = line_at(L.l[d], d, i, j, k, -1, d, D.n);
+      double Fa[5], Fb[5], dFp[5], dFm[5];
+      {
+        const double sx = sd[c], sy = sd[cells + c], sz = sd[2 * cells + c];
+        euler_flux_dot(qp[0] + dqp[0], qp[1] + dqp[1], qp[2] + dqp[2], qp[3] + dqp[3], qp[4] + dqp[4], sx, sy, sz,
+                       gm1, Fa);
+        euler_flux_dot(qp[0], qp[1], qp[2], qp[3], qp[4], sx, sy, sz, gm1, Fb);
+        for (int v = 0; v < 5; ++v) dFp[v] = Fa[v] - Fb[v];
+      }
+      {
+        const double sx = line_at(S.l[d], 3 * d, i, j, k, -1, d, D.n),
+                     sy = line_at(S.l[d], 3 * d + 1, i, j, k, -1, d, D.n),
+                     sz = line_at(S.l[d], 3 * d + 2, i, j, k, -1, d, D.n);
+        euler_flux_dot(qm[0] + dqm[0], qm[1] + dqm[1], qm[2] + dqm[2], qm[3] + dqm[3], qm[4] + dqm[4], sx, sy, sz,
+                       gm1, Fa);
+        euler_flux_dot(qm[0], qm[1], qm[2], qm[3], qm[4], sx, sy, sz, gm1, Fb);
+        for (int v = 0; v < 5; ++v) dFm[v] = Fa[v] - Fb[v];
+      }
+      for (int v = 0; v < 5; ++v) O[v] = O[v] + 0.5 * ((dFp[v] - lp * dqp[v]) - (dFm[v] + lm * dqm[v]));
+    }
+    const double J = 1.0 / jinv[c], Dg = diag[c];
+    for (int v = 0; v < 5; ++v) dq_out[v * cells + c] = (-r[v * cells + c] - J * O[v]) / Dg;
+  }
+}
+
+}  // namespace cfd
+
+extern "C" cfd_status cfd_wcns5_implicit_blocks_work_bytes(int32_t nblk, const int32_t* dims, const int32_t* nbr,
+                                                           size_t* bytes) {
+  return cfd::host_guarded([&] {
+    if (!bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    size_t total = check_seams(nblk, dims, nbr);          // the residual's scratch
+    for (int b = 0; b < nblk; ++b) total += (size_t)8 * 19 * block_cells(dims, b);
+    *bytes = total;
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_t* dims, const int32_t* nbr,
+                                                      double* const* q_dev, const double* const* s_dev,
+                                                      const double* const* jinv_dev, void* work_dev,
+                                                      size_t work_bytes, double gamma, double entropy_fix, double eps,
+                                                      double dt, int32_t nsteps, int32_t sweeps, hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    const size_t scratch = check_seams(nblk, dims, nbr);
+    if (!q_dev || !s_dev || !jinv_dev || !work_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) cfd::host_fail(CFD_EINVAL, "gamma must exceed 1");
+    if (!(entropy_fix >= 0.0) || !std::isfinite(entropy_fix)) cfd::host_fail(CFD_EINVAL, "bad entropy_fix");
+    if (!(eps > 0.0) || !std::isfinite(eps)) cfd::host_fail(CFD_EINVAL, "eps must be positive and finite");
+    if (!(dt > 0.0) || !std::isfinite(dt)) cfd::host_fail(CFD_EINVAL, "dt must be positive and finite");
+    if (nsteps < 0 || sweeps < 0 || sweeps > 1000) cfd::host_fail(CFD_EINVAL, "nsteps >= 0, sweeps in [0, 1000]");
+    std::vector<int64_t> off(nblk + 1, 0);
+    for (int b = 0; b < nblk; ++b) off[b + 1] = off[b] + 19 * block_cells(dims, b);
+    const size_t need = scratch + (size_t)8 * off[nblk];
+    if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_implicit_blocks_work_bytes()");
+    for (int b = 0; b < nblk; ++b) {
+      if (!q_dev[b] || !s_dev[b] || !jinv_dev[b]) cfd::host_fail(CFD_EINVAL, "NULL block pointer");
+      const int64_t cb = block_cells(dims, b);
+      if (!cfd::apart(q_dev[b], 40 * cb, work_dev, (int64_t)need)) cfd::host_fail(CFD_EINVAL, "q overlaps the workspace");
+      for (int c = 0; c < nblk; ++c) {
+        const int64_t cc = block_cells(dims, c);
+        if (!cfd::apart(q_dev[b], 40 * cb, s_dev[c], 72 * cc) || !cfd::apart(q_dev[b], 40 * cb, jinv_dev[c], 8 * cc) ||
+            (c != b && !cfd::apart(q_dev[b], 40 * cb, q_dev[c], 40 * cc)))
+          cfd::host_fail(CFD_EINVAL, "a state overlaps the metrics or another state");
+        if (!cfd::apart(work_dev, (int64_t)need, s_dev[c], 72 * cc) ||
+            !cfd::apart(work_dev, (int64_t)need, jinv_dev[c], 8 * cc))
+          cfd::host_fail(CFD_EINVAL, "the workspace overlaps the metrics");
+      }
+    }
+    double* base = reinterpret_cast<double*>(static_cast<char*>(work_dev) + scratch);
+    std::vector<double*> R(nblk), dqa(nblk), dqb(nblk), lam(nblk), diag(nblk);
+    for (int b = 0; b < nblk; ++b) {
+      const int64_t cb = block_cells(dims, b);
+      R[b] = base + off[b];
+      dqa[b] = R[b] + 5 * cb;
+      dqb[b] = dqa[b] + 5 * cb;
+      lam[b] = dqb[b] + 5 * cb;
+      diag[b] = lam[b] + 3 * cb;
+    }
+    auto lines = [&](int b, const std::vector<const double*>& arr) {
+      cfd::Lines3 L{};
+      for (int d = 0; d < 3; ++d) {
+        const int lo = nbr[6 * b + 2 * d], hi = nbr[6 * b + 2 * d + 1];
+        L.l[d] = cfd::Line{arr[b], arr[lo], arr[hi], block_cells(dims, b), block_cells(dims, lo), block_cells(dims, hi),
+                           dims[3 * lo + d], dims[3 * hi + d]};
+      }
+      return L;
+    };
+    std::vector<const double*> qv(q_dev, q_dev + nblk), sv(s_dev, s_dev + nblk), lamv(lam.begin(), lam.end());
+    std::vector<double*> rv(R.begin(), R.end());
+    for (int it = 0; it < nsteps; ++it) {
+      cfd::wcns5_blocks_residual_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, rv.data(), work_dev, gamma,
+                                        entropy_fix, eps, stream);
+      for (int b = 0; b < nblk; ++b) {
+        const int64_t cb = block_cells(dims, b);
+        const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
+        hipLaunchKernelGGL(cfd::k_impl_lambda_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream, q_dev[b],
+                           lines(b, qv), s_dev[b], lam[b], D, gamma);
+      }
+      for (int b = 0; b < nblk; ++b) {
+        const int64_t cb = block_cells(dims, b);
+        const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
+        hipLaunchKernelGGL(cfd::k_impl_diag_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream, R[b], lam[b],
+                           lines(b, lamv), jinv_dev[b], diag[b], dqa[b], D, dt);
+      }
+      std::vector<double*> cur = dqa, nxt = dqb;
+      for (int k = 0; k < sweeps; ++k) {
+        std::vector<const double*> curv(cur.begin(), cur.end());
+        for (int b = 0; b < nblk; ++b) {
+          const int64_t cb = block_cells(dims, b);
+          const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
+          hipLaunchKernelGGL(cfd::k_impl_sweep_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream, lines(b, qv),
+                             lines(b, curv), lines(b, sv), lines(b, lamv), R[b], s_dev[b], lam[b], jinv_dev[b],
+                             diag[b], nxt[b], D, gamma - 1.0);
+        }
+        std::swap(cur, nxt);
+      }
+      for (int b = 0; b < nblk; ++b) {
+        const int64_t cb = block_cells(dims, b);
+        hipLaunchKernelGGL(cfd::k_impl_apply, dim3(cfd::grid_for(5 * cb)), dim3(256), 0, stream, q_dev[b], cur[b],
+                           5 * cb);
+      }
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
