@@ -35,7 +35,8 @@ Test infrastructure, like the rest of this package.  Two operators:
    the stencils run across seams with a five-cell exchange, and the viscous
    terms across the same seams (viscous_residual_blocks);
 9. RK3 Navier-Stokes steps on periodic curvilinear blocks
-   (ns_steps_curv_periodic);
+   (ns_steps_curv_periodic) and on blocks joined face to face
+   (ns_steps_blocks);
 10. an implicit step (implicit_steps_curv_periodic, and implicit_steps_blocks
    for blocks joined face to face): backward Euler with a
    flux-split approximate Jacobian relaxed by point-Jacobi sweeps, the
@@ -697,4 +698,25 @@ def implicit_steps_blocks(Qs, Ss, Jinvs, nbr, gamma: float, eps_h: float, dt: fl
                 new.append((-Rs[b] - Jc * O) / Ds[b])
             dQs = new
         qs = [q + dq for q, dq in zip(qs, dQs)]
+    return qs
+
+
+def ns_steps_blocks(Qs, Ss, Jinvs, nbr, gamma: float, eps_h: float, prandtl: float, mu_inf: float, s_star: float,
+                    dt: float, nsteps: int, eps: float = 1e-6):
+    """nsteps SSP-RK3 steps (Eqs. 4-6, lambda = -dt) of the Navier-Stokes
+    equations on blocks joined face to face: every stage's residual is
+    wcns5_euler_residual_blocks plus viscous_residual_blocks over all blocks
+    at that stage (the oracle solver's ssp_rk3, stage by stage)."""
+    def R(xs):
+        inv = wcns5_euler_residual_blocks(xs, Ss, Jinvs, nbr, gamma, eps_h, eps)
+        vis = viscous_residual_blocks(xs, Ss, Jinvs, nbr, gamma, prandtl, mu_inf, s_star)
+        return [a + b for a, b in zip(inv, vis)]
+    qs = list(Qs)
+    for _ in range(nsteps):
+        r0 = R(qs)
+        q1 = [q - dt * r for q, r in zip(qs, r0)]
+        r1 = R(q1)
+        q2 = [0.75 * q + 0.25 * (a - dt * r) for q, a, r in zip(qs, q1, r1)]
+        r2 = R(q2)
+        qs = [(1.0 / 3.0) * q + (2.0 / 3.0) * (a - dt * r) for q, a, r in zip(qs, q2, r2)]
     return qs
