@@ -498,6 +498,21 @@ cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_t* dims, co
                                            size_t work_bytes, double gamma, double entropy_fix, double eps, double dt,
                                            int32_t nsteps, int32_t sweeps, hipStream_t stream);
 
+/* RK3 Navier-Stokes steps (Eqs. 4-6, lambda = -dt, fixed dt) on blocks joined
+ * face to face, in place on every q_dev[b]: each stage's residual is
+ * cfd_wcns5_euler_residual_blocks plus cfd_c4_viscous_add_blocks over all
+ * blocks at that stage (table, extents and pointer arrays as for those
+ * calls).  work_dev: cfd_wcns5_ns_blocks_work_bytes() bytes (the larger of the
+ * residual's and the viscous terms' scratch, then each block's start state
+ * and R).  Errors as for those calls and cfd_wcns5_ns_steps_curv_periodic; no
+ * state may overlap another, the metrics or the workspace.  Asynchronous on
+ * stream. */
+cfd_status cfd_wcns5_ns_blocks_work_bytes(int32_t nblk, const int32_t* dims, const int32_t* nbr, size_t* bytes);
+cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dims, const int32_t* nbr, double* const* q_dev,
+                                     const double* const* s_dev, const double* const* jinv_dev, void* work_dev,
+                                     size_t work_bytes, double gamma, double entropy_fix, double eps, double prandtl,
+                                     double mu_inf, double s_star, double dt, int32_t nsteps, hipStream_t stream);
+
 /* The fourth-order viscous terms of cfd_c4_viscous_add_curv_periodic on blocks
  * joined face to face (the table, extents and pointer arrays as for
  * cfd_wcns5_euler_residual_blocks): every four-point stencil runs across the

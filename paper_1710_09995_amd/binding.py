@@ -72,7 +72,8 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_wcns5_euler_blocks_work_bytes", "cfd_wcns5_euler_residual_blocks", "cfd_c4_viscous_blocks_work_bytes",
            "cfd_c4_viscous_add_blocks", "cfd_wcns5_ns_step_work_bytes", "cfd_wcns5_ns_steps_curv_periodic",
            "cfd_wcns5_implicit_step_work_bytes", "cfd_wcns5_implicit_steps_curv_periodic",
-           "cfd_wcns5_implicit_blocks_work_bytes", "cfd_wcns5_implicit_steps_blocks",
+           "cfd_wcns5_implicit_blocks_work_bytes", "cfd_wcns5_implicit_steps_blocks", "cfd_wcns5_ns_blocks_work_bytes",
+           "cfd_wcns5_ns_steps_blocks",
            "cfd_status_string", "cfd_last_error"]
 
 _lib = None
@@ -163,6 +164,10 @@ def lib(build_if_missing: bool = True):
     L.cfd_wcns5_implicit_steps_blocks.argtypes = [i32, i32p, i32p, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp,
                                                   C.c_size_t, C.c_double, C.c_double, C.c_double, C.c_double, i32,
                                                   i32, vp]
+    L.cfd_wcns5_ns_blocks_work_bytes.argtypes = [i32, i32p, i32p, C.POINTER(C.c_size_t)]
+    L.cfd_wcns5_ns_steps_blocks.argtypes = [i32, i32p, i32p, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp,
+                                            C.c_size_t, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                            C.c_double, C.c_double, i32, vp]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]
@@ -624,6 +629,37 @@ def wcns5_implicit_steps_blocks(qs, Ss, jinvs, nbr, dt: float, nsteps: int, swee
     _check(lib().cfd_wcns5_implicit_steps_blocks(nblk, dims, nb, ptrs(qs), ptrs(Ss), ptrs(jinvs), _ptr(work),
                                                  nbytes.value, float(gamma), float(entropy_fix), float(eps), float(dt),
                                                  int(nsteps), int(sweeps), _stream_handle(torch, stream)))
+    return qs
+
+
+def wcns5_ns_steps_blocks(qs, Ss, jinvs, nbr, dt: float, nsteps: int, gamma: float = 1.4, entropy_fix: float = 0.1,
+                          eps: float = 1e-6, prandtl: float = 0.72, mu_inf: float = 1e-3,
+                          s_star: float = 110.4 / 288.15, work=None, stream=None):
+    """RK3 Navier-Stokes steps on blocks joined face to face on the device
+    (cfd_wcns5_ns_steps_blocks), in place on every q; per block q, S, jinv
+    contiguous FP64 CUDA tensors; nbr as for wcns5_euler_residual_blocks.
+    Returns qs."""
+    import torch
+    nblk = len(qs)
+    dims = (C.c_int32 * (3 * nblk))()
+    for b, q in enumerate(qs):
+        if q.dtype != torch.float64 or not q.is_cuda or not q.is_contiguous() or q.dim() != 4 or q.shape[0] != 5:
+            raise ValueError("every q must be a contiguous float64 CUDA tensor [5, nk, nj, ni]")
+        nk, nj, ni = (int(v) for v in q.shape[1:])
+        dims[3 * b:3 * b + 3] = [ni, nj, nk]
+        for t, shp in ((Ss[b], (3, 3, nk, nj, ni)), (jinvs[b], (nk, nj, ni))):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp:
+                raise ValueError("S and jinv must be contiguous float64 CUDA tensors of each block's shape")
+    nb = (C.c_int32 * (6 * nblk))(*[int(v) for row in nbr for v in row])
+    nbytes = C.c_size_t()
+    _check(lib().cfd_wcns5_ns_blocks_work_bytes(nblk, dims, nb, C.byref(nbytes)))
+    if work is None or work.numel() * work.element_size() < nbytes.value:
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=qs[0].device)
+    ptrs = lambda ts: (C.c_void_p * nblk)(*[_ptr(t) for t in ts])   # noqa: E731
+    _check(lib().cfd_wcns5_ns_steps_blocks(nblk, dims, nb, ptrs(qs), ptrs(Ss), ptrs(jinvs), _ptr(work), nbytes.value,
+                                           float(gamma), float(entropy_fix), float(eps), float(prandtl),
+                                           float(mu_inf), float(s_star), float(dt), int(nsteps),
+                                           _stream_handle(torch, stream)))
     return qs
 
 

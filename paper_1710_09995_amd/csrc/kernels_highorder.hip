@@ -1439,6 +1439,64 @@ int64_t block_cells(const int32_t* dims, int b) {
 
 }  // namespace
 
+namespace cfd {
+
+// The viscous terms of blocks joined face to face added into r (arguments
+// checked by the caller; W: 29 doubles per cell of every block).
+void c4_viscous_blocks_launch(int32_t nblk, const int32_t* dims, const int32_t* nbr, const double* const* q_dev,
+                              const double* const* s_dev, const double* const* jinv_dev, double* const* r_dev,
+                              double* W, const Gas<double>& gas, hipStream_t stream) {
+  std::vector<int64_t> off(nblk + 1, 0);
+  for (int b = 0; b < nblk; ++b) off[b + 1] = off[b] + VW_FIELDS * block_cells(dims, b);
+  // the line along d around block b over per-block arrays (bases), or over
+  // the per-block workspaces when bases is NULL
+  auto line = [&](int b, int d, const double* const* bases) {
+    const int lo = nbr[6 * b + 2 * d], hi = nbr[6 * b + 2 * d + 1];
+    Line L{};
+    L.own = bases ? bases[b] : W + off[b];
+    L.lo = bases ? bases[lo] : W + off[lo];
+    L.hi = bases ? bases[hi] : W + off[hi];
+    L.cown = block_cells(dims, b);
+    L.clo = block_cells(dims, lo);
+    L.chi = block_cells(dims, hi);
+    L.nlo = dims[3 * lo + d];
+    L.nhi = dims[3 * hi + d];
+    return L;
+  };
+  for (int b = 0; b < nblk; ++b) {
+    const int64_t cb = block_cells(dims, b);
+    hipLaunchKernelGGL(k_c4_phi, dim3(grid_for(cb)), dim3(256), 0, stream, q_dev[b], W + off[b], cb,
+                       gas.gm1);
+  }
+  for (int b = 0; b < nblk; ++b) {
+    const int64_t cb = block_cells(dims, b);
+    const Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
+    for (int t = 0; t < 3; ++t) {
+      hipLaunchKernelGGL(k_c4_grads_line, dim3(grid_for(cb)), dim3(256), 0, stream,
+                         line(b, t, nullptr), W + off[b] + VW_G * cb, D, t);
+      hipLaunchKernelGGL(k_c4_cell_metrics_line, dim3(grid_for(cb)), dim3(256), 0, stream,
+                         line(b, t, s_dev), W + off[b] + VW_SC * cb, D, t);
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    for (int b = 0; b < nblk; ++b) {
+      const int64_t cb = block_cells(dims, b);
+      const Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
+      hipLaunchKernelGGL(k_c4_visc_faces_line, dim3(grid_for(cb)), dim3(256), 0, stream,
+                         line(b, d, nullptr), line(b, d, jinv_dev), s_dev[b],
+                         W + off[b] + VW_FV * cb, D, d, gas);
+    }
+    for (int b = 0; b < nblk; ++b) {
+      const int64_t cb = block_cells(dims, b);
+      const Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
+      hipLaunchKernelGGL(k_c4_flux_sub_line, dim3(grid_for(cb)), dim3(256), 0, stream,
+                         line(b, d, nullptr), r_dev[b], jinv_dev[b], D, d);
+    }
+  }
+}
+
+}  // namespace cfd
+
 extern "C" cfd_status cfd_c4_viscous_blocks_work_bytes(int32_t nblk, const int32_t* dims, const int32_t* nbr,
                                                        size_t* bytes) {
   return cfd::host_guarded([&] {
@@ -1481,59 +1539,8 @@ extern "C" cfd_status cfd_c4_viscous_add_blocks(int32_t nblk, const int32_t* dim
           cfd::host_fail(CFD_EINVAL, "the workspace overlaps an input");
       }
     }
-    cfd::Gas<double> gas{};
-    gas.gamma = gamma;
-    gas.gm1 = gamma - 1.0;
-    gas.mu_inf = mu_inf;
-    gas.s_star = s_star;
-    gas.prandtl = prandtl;
-    gas.kfac = gamma / ((gamma - 1.0) * prandtl);
-    double* W = static_cast<double*>(work_dev);
-    // the line along d around block b over per-block arrays (bases), or over
-    // the per-block workspaces when bases is NULL
-    auto line = [&](int b, int d, const double* const* bases) {
-      const int lo = nbr[6 * b + 2 * d], hi = nbr[6 * b + 2 * d + 1];
-      cfd::Line L{};
-      L.own = bases ? bases[b] : W + off[b];
-      L.lo = bases ? bases[lo] : W + off[lo];
-      L.hi = bases ? bases[hi] : W + off[hi];
-      L.cown = block_cells(dims, b);
-      L.clo = block_cells(dims, lo);
-      L.chi = block_cells(dims, hi);
-      L.nlo = dims[3 * lo + d];
-      L.nhi = dims[3 * hi + d];
-      return L;
-    };
-    for (int b = 0; b < nblk; ++b) {
-      const int64_t cb = block_cells(dims, b);
-      hipLaunchKernelGGL(cfd::k_c4_phi, dim3(cfd::grid_for(cb)), dim3(256), 0, stream, q_dev[b], W + off[b], cb,
-                         gamma - 1.0);
-    }
-    for (int b = 0; b < nblk; ++b) {
-      const int64_t cb = block_cells(dims, b);
-      const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
-      for (int t = 0; t < 3; ++t) {
-        hipLaunchKernelGGL(cfd::k_c4_grads_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream,
-                           line(b, t, nullptr), W + off[b] + cfd::VW_G * cb, D, t);
-        hipLaunchKernelGGL(cfd::k_c4_cell_metrics_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream,
-                           line(b, t, s_dev), W + off[b] + cfd::VW_SC * cb, D, t);
-      }
-    }
-    for (int d = 0; d < 3; ++d) {
-      for (int b = 0; b < nblk; ++b) {
-        const int64_t cb = block_cells(dims, b);
-        const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
-        hipLaunchKernelGGL(cfd::k_c4_visc_faces_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream,
-                           line(b, d, nullptr), line(b, d, jinv_dev), s_dev[b],
-                           W + off[b] + cfd::VW_FV * cb, D, d, gas);
-      }
-      for (int b = 0; b < nblk; ++b) {
-        const int64_t cb = block_cells(dims, b);
-        const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
-        hipLaunchKernelGGL(cfd::k_c4_flux_sub_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream,
-                           line(b, d, nullptr), r_dev[b], jinv_dev[b], D, d);
-      }
-    }
+    cfd::c4_viscous_blocks_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, r_dev, static_cast<double*>(work_dev),
+                                  cfd::viscous_gas(gamma, prandtl, mu_inf, s_star), stream);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   });
@@ -1945,6 +1952,85 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_
                            5 * cb);
       }
     }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  });
+}
+
+// ------------------------------------- Navier-Stokes RK3 steps on joined blocks
+extern "C" cfd_status cfd_wcns5_ns_blocks_work_bytes(int32_t nblk, const int32_t* dims, const int32_t* nbr,
+                                                     size_t* bytes) {
+  return cfd::host_guarded([&] {
+    if (!bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    const size_t rscratch = check_seams(nblk, dims, nbr);
+    size_t vscratch = 0, states = 0;
+    for (int b = 0; b < nblk; ++b) {
+      vscratch += (size_t)8 * cfd::VW_FIELDS * block_cells(dims, b);
+      states += (size_t)8 * 10 * block_cells(dims, b);
+    }
+    *bytes = std::max(rscratch, vscratch) + states;
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dims, const int32_t* nbr,
+                                                double* const* q_dev, const double* const* s_dev,
+                                                const double* const* jinv_dev, void* work_dev, size_t work_bytes,
+                                                double gamma, double entropy_fix, double eps, double prandtl,
+                                                double mu_inf, double s_star, double dt, int32_t nsteps,
+                                                hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    const size_t rscratch = check_seams(nblk, dims, nbr);
+    if (!q_dev || !s_dev || !jinv_dev || !work_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) cfd::host_fail(CFD_EINVAL, "gamma must exceed 1");
+    if (!(entropy_fix >= 0.0) || !std::isfinite(entropy_fix)) cfd::host_fail(CFD_EINVAL, "bad entropy_fix");
+    if (!(eps > 0.0) || !std::isfinite(eps)) cfd::host_fail(CFD_EINVAL, "eps must be positive and finite");
+    if (!(prandtl > 0.0) || !(mu_inf >= 0.0) || !(s_star > 0.0) || !std::isfinite(mu_inf))
+      cfd::host_fail(CFD_EINVAL, "bad gas parameters");
+    if (!(dt > 0.0) || !std::isfinite(dt)) cfd::host_fail(CFD_EINVAL, "dt must be positive and finite");
+    if (nsteps < 0) cfd::host_fail(CFD_EINVAL, "nsteps must be >= 0");
+    std::vector<int64_t> off(nblk + 1, 0);
+    size_t vscratch = 0;
+    for (int b = 0; b < nblk; ++b) {
+      off[b + 1] = off[b] + 10 * block_cells(dims, b);
+      vscratch += (size_t)8 * cfd::VW_FIELDS * block_cells(dims, b);
+    }
+    const size_t scratch = std::max(rscratch, vscratch);
+    const size_t need = scratch + (size_t)8 * off[nblk];
+    if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_ns_blocks_work_bytes()");
+    for (int b = 0; b < nblk; ++b) {
+      if (!q_dev[b] || !s_dev[b] || !jinv_dev[b]) cfd::host_fail(CFD_EINVAL, "NULL block pointer");
+      const int64_t cb = block_cells(dims, b);
+      if (!cfd::apart(q_dev[b], 40 * cb, work_dev, (int64_t)need)) cfd::host_fail(CFD_EINVAL, "q overlaps the workspace");
+      for (int c = 0; c < nblk; ++c) {
+        const int64_t cc = block_cells(dims, c);
+        if (!cfd::apart(q_dev[b], 40 * cb, s_dev[c], 72 * cc) || !cfd::apart(q_dev[b], 40 * cb, jinv_dev[c], 8 * cc) ||
+            (c != b && !cfd::apart(q_dev[b], 40 * cb, q_dev[c], 40 * cc)))
+          cfd::host_fail(CFD_EINVAL, "a state overlaps the metrics or another state");
+        if (!cfd::apart(work_dev, (int64_t)need, s_dev[c], 72 * cc) ||
+            !cfd::apart(work_dev, (int64_t)need, jinv_dev[c], 8 * cc))
+          cfd::host_fail(CFD_EINVAL, "the workspace overlaps the metrics");
+      }
+    }
+    double* base = reinterpret_cast<double*>(static_cast<char*>(work_dev) + scratch);
+    std::vector<double*> qn(nblk), R(nblk);
+    for (int b = 0; b < nblk; ++b) {
+      qn[b] = base + off[b];
+      R[b] = qn[b] + 5 * block_cells(dims, b);
+    }
+    const cfd::Gas<double> vgas = cfd::viscous_gas(gamma, prandtl, mu_inf, s_star);
+    const double a[3] = {0.0, 0.75, 1.0 / 3.0}, bb[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int it = 0; it < nsteps; ++it)
+      for (int st = 0; st < 3; ++st) {
+        cfd::wcns5_blocks_residual_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, R.data(), work_dev, gamma,
+                                          entropy_fix, eps, stream);
+        cfd::c4_viscous_blocks_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, R.data(),
+                                      static_cast<double*>(work_dev), vgas, stream);
+        for (int b = 0; b < nblk; ++b) {
+          const int64_t nv = 5 * block_cells(dims, b);
+          hipLaunchKernelGGL(cfd::k_rk3_stage, dim3(cfd::grid_for(nv)), dim3(256), 0, stream, q_dev[b], qn[b], R[b],
+                             nv, dt, a[st], bb[st], st == 0 ? 1 : 0);
+        }
+      }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   });

@@ -376,3 +376,33 @@ def test_implicit_steps_on_split_blocks_match_the_unsplit_block():
     top = max(float(np.max(np.abs(w))) for w in want)
     for g, w in zip(got, want):
         assert np.max(np.abs(g.cpu().numpy() - w)) <= 1e-11 * top
+
+
+def test_ns_steps_on_split_blocks_match_the_unsplit_block():
+    """The paper's explicit method on a multi-block grid on the device: 2 RK3
+    Navier-Stokes steps on the 12-block split of a periodic wavy block are
+    bitwise the unsplit block's, and match the oracle's blocks within 1e-12."""
+    import torch
+    from paper_1710_09995_amd.binding import wcns5_metrics_periodic, wcns5_ns_steps_blocks, wcns5_ns_steps_curv_periodic
+    from test_oracle_highorder import _split_box
+    n = (40, 30, 24)
+    Xv, P = _curv_grid(n, "wavy")
+    say("ns blocks", n)
+    S, J = wcns5_metrics_periodic(torch.from_numpy(Xv).cuda(), P)
+    q = _smooth_state(n, seed=17)
+    qt = torch.from_numpy(q).cuda()
+    lo, m, nbr = _split_box(n, ([17], [8, 20], [11]))
+    sls = [(slice(o[2], o[2] + e[2]), slice(o[1], o[1] + e[1]), slice(o[0], o[0] + e[0])) for o, e in zip(lo, m)]
+    qs = [qt[(slice(None),) + sl].contiguous() for sl in sls]
+    Ss = [S[(slice(None), slice(None)) + sl].contiguous() for sl in sls]
+    Js = [J[sl].contiguous() for sl in sls]
+    q0s = [t.cpu().numpy() for t in qs]
+    whole = wcns5_ns_steps_curv_periodic(qt.clone(), S, J, 0.005, 2, 1.4, 0.1, 1e-6, 0.72, 0.02, 0.38)
+    got = wcns5_ns_steps_blocks(qs, Ss, Js, nbr, 0.005, 2, 1.4, 0.1, 1e-6, 0.72, 0.02, 0.38)
+    for sl, g in zip(sls, got):
+        assert torch.equal(g, whole[(slice(None),) + sl])
+    want = ho.ns_steps_blocks(q0s, [t.cpu().numpy() for t in Ss], [t.cpu().numpy() for t in Js], nbr, 1.4, 0.1, 0.72,
+                              0.02, 0.38, 0.005, 2)
+    top = max(float(np.max(np.abs(w))) for w in want)
+    for g, w in zip(got, want):
+        assert np.max(np.abs(g.cpu().numpy() - w)) <= 1e-12 * top
