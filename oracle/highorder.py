@@ -648,8 +648,9 @@ def implicit_steps_curv_periodic(Q, S, Jinv, gamma: float, eps_h: float, dt: flo
 
 
 def implicit_steps_blocks(Qs, Ss, Jinvs, nbr, gamma: float, eps_h: float, dt: float, nsteps: int, sweeps: int,
-                          eps: float = 1e-6):
-    """Inviscid implicit steps (the reading above) on blocks joined face to face
+                          eps: float = 1e-6, viscous: bool = False, prandtl: float = 0.72, mu_inf: float = 0.0,
+                          s_star: float = 110.4 / 288.15):
+    """Implicit steps (the reading above, viscous optional) on blocks joined face to face
     (nbr as for wcns5_euler_residual_blocks).  A cell's neighbours across a
     seam are the neighbour block's cells and every sweep reads only the
     previous iterate, so point-Jacobi is the same iteration however the domain
@@ -668,16 +669,27 @@ def implicit_steps_blocks(Qs, Ss, Jinvs, nbr, gamma: float, eps_h: float, dt: fl
         lo = fields[nbr[b][2 * d]]
         return np.concatenate([_win(lo, ax, lo.shape[ax] - 1, 1), _win(f, ax, 0, n - 1)], axis=ax)
 
+    from .flux import sutherland
+    coef = max(4.0 / 3.0, gamma / prandtl)
     qs = list(Qs)
     for _ in range(nsteps):
         Rs = wcns5_euler_residual_blocks(qs, Ss, Jinvs, nbr, gamma, eps_h, eps)
+        if viscous:
+            Rv = viscous_residual_blocks(qs, Ss, Jinvs, nbr, gamma, prandtl, mu_inf, s_star)
+            Rs = [a + v for a, v in zip(Rs, Rv)]
         Ws = [primitives(q, gamma) for q in qs]
         lams = [[_lambda_of(Ws[b], shift(Ws, b, d, 1, 1), Ss[b][d], gamma) for d in range(3)] for b in range(nb)]
+        nus = [sutherland(W[4] / W[0], mu_inf, s_star) / W[0] for W in Ws]
+        lvs = [[(coef * (0.5 * (nus[b] + shift(nus, b, d, 1, 0))) * np.sum(Ss[b][d] * Ss[b][d], axis=0)
+                 / (0.5 * (Jinvs[b] + shift(Jinvs, b, d, 1, 0))) if viscous else 0.0 * Jinvs[b]) for d in range(3)]
+               for b in range(nb)]
         Ds, dQs = [], []
         for b in range(nb):
             Jc = 1.0 / Jinvs[b]
             L = [[lams[c][d] for c in range(nb)] for d in range(3)]
-            D = 1.0 / dt + Jc * sum(0.5 * (lams[b][d] + shift(L[d], b, d, -1, 0)) for d in range(3))
+            V = [[lvs[c][d] for c in range(nb)] for d in range(3)]
+            D = 1.0 / dt + Jc * sum(0.5 * (lams[b][d] + shift(L[d], b, d, -1, 0))
+                                    + (lvs[b][d] + shift(V[d], b, d, -1, 0)) for d in range(3))
             Ds.append(D)
             dQs.append(-Rs[b] / D)
         for _ in range(sweeps):
@@ -694,7 +706,8 @@ def implicit_steps_blocks(Qs, Ss, Jinvs, nbr, gamma: float, eps_h: float, dt: fl
                     Qm, dQm = shift(qs, b, d, -1, 1), shift(dQs, b, d, -1, 1)
                     dFp = euler_flux_through(Qp + dQp, Sp, gamma) - euler_flux_through(Qp, Sp, gamma)
                     dFm = euler_flux_through(Qm + dQm, Sm, gamma) - euler_flux_through(Qm, Sm, gamma)
-                    O = O + 0.5 * ((dFp - lp * dQp) - (dFm + lm * dQm))
+                    vp, vm = lvs[b][d], shift([lvs[c][d] for c in range(nb)], b, d, -1, 0)
+                    O = O + 0.5 * ((dFp - lp * dQp) - (dFm + lm * dQm)) - (vp * dQp + vm * dQm)
                 new.append((-Rs[b] - Jc * O) / Ds[b])
             dQs = new
         qs = [q + dq for q, dq in zip(qs, dQs)]

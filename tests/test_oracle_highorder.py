@@ -868,3 +868,21 @@ def test_ns_steps_on_split_blocks_equal_the_unsplit_block():
                              [Jinv[sl] for sl in sls], nbr, 1.4, 0.1, 0.72, 0.02, 0.38, 0.01, 2)
     for sl, g in zip(sls, got):
         assert np.array_equal(g, want[(slice(None),) + sl])
+
+
+def test_viscous_implicit_steps_on_split_blocks_equal_the_unsplit_block():
+    """The same 12-block split with viscous terms: 2 implicit Navier-Stokes
+    steps with 4 sweeps on the blocks are bitwise the unsplit block's."""
+    n = (16, 18, 12)
+    Xv, P, _ = _wavy_grid(n, (3.0, 2.0, 1.5), 0.08)
+    S, Jinv = ho.metrics6(ho.periodic_vertices(Xv, P))
+    q, _ = _smooth_state(n, 11)
+    kw = dict(viscous=True, prandtl=0.72, mu_inf=0.02, s_star=0.38)
+    want = ho.implicit_steps_curv_periodic(q, S, Jinv, 1.4, 0.1, 0.05, 2, 4, **kw)
+    lo, m, nbr = _split_box(n, ([7], [5, 11], [6]))
+    sls = [(slice(o[2], o[2] + e[2]), slice(o[1], o[1] + e[1]), slice(o[0], o[0] + e[0])) for o, e in zip(lo, m)]
+    got = ho.implicit_steps_blocks([q[(slice(None),) + sl] for sl in sls],
+                                   [S[(slice(None), slice(None)) + sl] for sl in sls], [Jinv[sl] for sl in sls],
+                                   nbr, 1.4, 0.1, 0.05, 2, 4, **kw)
+    for sl, g in zip(sls, got):
+        assert np.array_equal(g, want[(slice(None),) + sl])
