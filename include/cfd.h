@@ -482,11 +482,12 @@ cfd_status cfd_wcns5_implicit_steps_curv_periodic(double* q_dev, const double* s
                                                   double mu_inf, double s_star, double dt, int32_t nsteps,
                                                   int32_t sweeps, hipStream_t stream);
 
-/* Inviscid implicit steps (those of cfd_wcns5_implicit_steps_curv_periodic) on
- * blocks joined face to face (table, extents and pointer arrays as for
- * cfd_wcns5_euler_residual_blocks; q_dev[b] updated in place): the residual
- * of cfd_wcns5_euler_residual_blocks, and every sweep reads the neighbours'
- * states, updates, radii and face metrics across the seams.  Each sweep reads
+/* Implicit steps (those of cfd_wcns5_implicit_steps_curv_periodic, viscous
+ * optional) on blocks joined face to face (table, extents and pointer arrays
+ * as for cfd_wcns5_euler_residual_blocks; q_dev[b] updated in place): the
+ * residual of cfd_wcns5_euler_residual_blocks (plus cfd_c4_viscous_add_blocks
+ * when viscous), and every sweep reads the neighbours' states, updates, radii
+ * and face metrics across the seams.  Each sweep reads
  * only the previous iterate, so the steps do not depend on how the domain is
  * cut (a split block gives the unsplit block's bits).  work_dev:
  * cfd_wcns5_implicit_blocks_work_bytes() bytes.  Errors as for the periodic
@@ -495,7 +496,8 @@ cfd_status cfd_wcns5_implicit_steps_curv_periodic(double* q_dev, const double* s
 cfd_status cfd_wcns5_implicit_blocks_work_bytes(int32_t nblk, const int32_t* dims, const int32_t* nbr, size_t* bytes);
 cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_t* dims, const int32_t* nbr, double* const* q_dev,
                                            const double* const* s_dev, const double* const* jinv_dev, void* work_dev,
-                                           size_t work_bytes, double gamma, double entropy_fix, double eps, double dt,
+                                           size_t work_bytes, double gamma, double entropy_fix, double eps,
+                                           int32_t viscous, double prandtl, double mu_inf, double s_star, double dt,
                                            int32_t nsteps, int32_t sweeps, hipStream_t stream);
 
 /* RK3 Navier-Stokes steps (Eqs. 4-6, lambda = -dt, fixed dt) on blocks joined

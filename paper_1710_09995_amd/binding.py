@@ -162,8 +162,8 @@ def lib(build_if_missing: bool = True):
                                                          C.c_double, i32, i32, vp]
     L.cfd_wcns5_implicit_blocks_work_bytes.argtypes = [i32, i32p, i32p, C.POINTER(C.c_size_t)]
     L.cfd_wcns5_implicit_steps_blocks.argtypes = [i32, i32p, i32p, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp,
-                                                  C.c_size_t, C.c_double, C.c_double, C.c_double, C.c_double, i32,
-                                                  i32, vp]
+                                                  C.c_size_t, C.c_double, C.c_double, C.c_double, i32, C.c_double,
+                                                  C.c_double, C.c_double, C.c_double, i32, i32, vp]
     L.cfd_wcns5_ns_blocks_work_bytes.argtypes = [i32, i32p, i32p, C.POINTER(C.c_size_t)]
     L.cfd_wcns5_ns_steps_blocks.argtypes = [i32, i32p, i32p, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp,
                                             C.c_size_t, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -604,8 +604,10 @@ def wcns5_implicit_steps_curv_periodic(q, S, jinv, dt: float, nsteps: int, sweep
 
 
 def wcns5_implicit_steps_blocks(qs, Ss, jinvs, nbr, dt: float, nsteps: int, sweeps: int, gamma: float = 1.4,
-                                entropy_fix: float = 0.1, eps: float = 1e-6, work=None, stream=None):
-    """Inviscid implicit steps on blocks joined face to face on the device
+                                entropy_fix: float = 0.1, eps: float = 1e-6, viscous: bool = False,
+                                prandtl: float = 0.72, mu_inf: float = 1e-3, s_star: float = 110.4 / 288.15,
+                                work=None, stream=None):
+    """Implicit steps (viscous optional) on blocks joined face to face on the device
     (cfd_wcns5_implicit_steps_blocks), in place on every q; per block q, S,
     jinv contiguous FP64 CUDA tensors; nbr as for
     wcns5_euler_residual_blocks.  Returns qs."""
@@ -627,8 +629,9 @@ def wcns5_implicit_steps_blocks(qs, Ss, jinvs, nbr, dt: float, nsteps: int, swee
         work = torch.empty(nbytes.value, dtype=torch.uint8, device=qs[0].device)
     ptrs = lambda ts: (C.c_void_p * nblk)(*[_ptr(t) for t in ts])   # noqa: E731
     _check(lib().cfd_wcns5_implicit_steps_blocks(nblk, dims, nb, ptrs(qs), ptrs(Ss), ptrs(jinvs), _ptr(work),
-                                                 nbytes.value, float(gamma), float(entropy_fix), float(eps), float(dt),
-                                                 int(nsteps), int(sweeps), _stream_handle(torch, stream)))
+                                                 nbytes.value, float(gamma), float(entropy_fix), float(eps),
+                                                 1 if viscous else 0, float(prandtl), float(mu_inf), float(s_star),
+                                                 float(dt), int(nsteps), int(sweeps), _stream_handle(torch, stream)))
     return qs
 
 

@@ -1771,8 +1771,10 @@ struct Lines3 {
 };
 
 __global__ void __launch_bounds__(256) k_impl_lambda_line(const double* __restrict__ q, Lines3 Q,
-                                                          const double* __restrict__ s, double* __restrict__ lam,
-                                                          Dims3 D, double gamma) {
+                                                          const double* __restrict__ s,
+                                                          const double* __restrict__ jinv, Lines3 JL,
+                                                          double* __restrict__ lam, double* __restrict__ lamv,
+                                                          Dims3 D, double gamma, Gas<double> visc, int viscous) {
   const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
   const double gm1 = gamma - 1.0;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
@@ -1789,21 +1791,28 @@ __global__ void __launch_bounds__(256) k_impl_lambda_line(const double* __restri
       const double* sd = s + 3 * d * cells;
       const double sx = sd[c], sy = sd[cells + c], sz = sd[2 * cells + c];
       lam[d * cells + c] = fabs(u * sx + v * sy + w * sz) + sqrt(gamma * pr / r) * sqrt(sx * sx + sy * sy + sz * sz);
+      if (viscous) {
+        const double Ta = a.p / a.r, Tb = b.p / b.r;
+        const double na = visc.mu_inf * Ta * sqrt(Ta) * (1.0 + visc.s_star) / (Ta + visc.s_star) / a.r;
+        const double nb = visc.mu_inf * Tb * sqrt(Tb) * (1.0 + visc.s_star) / (Tb + visc.s_star) / b.r;
+        const double num = 0.5 * (na + nb), jm = 0.5 * (jinv[c] + line_at(JL.l[d], 0, i, j, k, 1, d, D.n));
+        lamv[d * cells + c] = fmax(4.0 / 3.0, gamma / visc.prandtl) * num * (sx * sx + sy * sy + sz * sz) / jm;
+      }
     }
   }
 }
 
 __global__ void __launch_bounds__(256) k_impl_diag_line(const double* __restrict__ r, const double* __restrict__ lam,
-                                                        Lines3 L, const double* __restrict__ jinv,
-                                                        double* __restrict__ diag, double* __restrict__ dq, Dims3 D,
-                                                        double dt) {
+                                                        Lines3 L, const double* __restrict__ lamv, Lines3 LV,
+                                                        const double* __restrict__ jinv, double* __restrict__ diag,
+                                                        double* __restrict__ dq, Dims3 D, double dt, int viscous) {
   const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
     double sum = 0.0;
     for (int d = 0; d < 3; ++d) {
       const double t = 0.5 * (lam[d * cells + c] + line_at(L.l[d], d, i, j, k, -1, d, D.n));
-      sum = sum + t;
+      sum = sum + (viscous ? t + (lamv[d * cells + c] + line_at(LV.l[d], d, i, j, k, -1, d, D.n)) : t);
     }
     const double Dg = 1.0 / dt + (1.0 / jinv[c]) * sum;
     diag[c] = Dg;
@@ -1811,9 +1820,10 @@ __global__ void __launch_bounds__(256) k_impl_diag_line(const double* __restrict
   }
 }
 
-__global__ void __launch_bounds__(256) k_impl_sweep_line(Lines3 Q, Lines3 DQ, Lines3 S, Lines3 L,
-                                                         const double* __restrict__ r, const double* __restrict__ s,
-                                                         const double* __restrict__ lam,
+__global__ void __launch_bounds__(256) k_impl_sweep_line(Lines3 Q, Lines3 DQ, Lines3 S, Lines3 L, Lines3 LV,
+                                                         int viscous, const double* __restrict__ r,
+                                                         const double* __restrict__ s, const double* __restrict__ lam,
+                                                         const double* __restrict__ lamv,
                                                          const double* __restrict__ jinv,
                                                          const double* __restrict__ diag, double* __restrict__ dq_out,
                                                          Dims3 D, double gm1) {
@@ -1848,7 +1858,12 @@ __global__ void __launch_bounds__(256) k_impl_sweep_line(Lines3 Q, Lines3 DQ, Li
         euler_flux_dot(qm[0], qm[1], qm[2], qm[3], qm[4], sx, sy, sz, gm1, Fb);
         for (int v = 0; v < 5; ++v) dFm[v] = Fa[v] - Fb[v];
       }
-      for (int v = 0; v < 5; ++v) O[v] = O[v] + 0.5 * ((dFp[v] - lp * dqp[v]) - (dFm[v] + lm * dqm[v]));
+      const double vp = viscous ? lamv[d * cells + c] : 0.0,
+                   vm = viscous ? line_at(LV.l[d], d, i, j, k, -1, d, D.n) : 0.0;
+      for (int v = 0; v < 5; ++v) {
+        O[v] = O[v] + 0.5 * ((dFp[v] - lp * dqp[v]) - (dFm[v] + lm * dqm[v]));
+        if (viscous) O[v] = O[v] - (vp * dqp[v] + vm * dqm[v]);
+      }
     }
     const double J = 1.0 / jinv[c], Dg = diag[c];
     for (int v = 0; v < 5; ++v) dq_out[v * cells + c] = (-r[v * cells + c] - J * O[v]) / Dg;
@@ -1861,9 +1876,13 @@ extern "C" cfd_status cfd_wcns5_implicit_blocks_work_bytes(int32_t nblk, const i
                                                            size_t* bytes) {
   return cfd::host_guarded([&] {
     if (!bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
-    size_t total = check_seams(nblk, dims, nbr);          // the residual's scratch
-    for (int b = 0; b < nblk; ++b) total += (size_t)8 * 19 * block_cells(dims, b);
-    *bytes = total;
+    const size_t rscratch = check_seams(nblk, dims, nbr);
+    size_t vscratch = 0, rest = 0;
+    for (int b = 0; b < nblk; ++b) {
+      vscratch += (size_t)8 * cfd::VW_FIELDS * block_cells(dims, b);   // the viscous terms' scratch
+      rest += (size_t)8 * 22 * block_cells(dims, b);                   // R, two dQ, radii (3 + 3), D
+    }
+    *bytes = std::max(rscratch, vscratch) + rest;
   });
 }
 
@@ -1871,9 +1890,15 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_
                                                       double* const* q_dev, const double* const* s_dev,
                                                       const double* const* jinv_dev, void* work_dev,
                                                       size_t work_bytes, double gamma, double entropy_fix, double eps,
+                                                      int32_t viscous, double prandtl, double mu_inf, double s_star,
                                                       double dt, int32_t nsteps, int32_t sweeps, hipStream_t stream) {
   return cfd::host_guarded([&] {
-    const size_t scratch = check_seams(nblk, dims, nbr);
+    const size_t rscratch = check_seams(nblk, dims, nbr);
+    if (viscous && (!(prandtl > 0.0) || !(mu_inf >= 0.0) || !(s_star > 0.0) || !std::isfinite(mu_inf)))
+      cfd::host_fail(CFD_EINVAL, "bad gas parameters");
+    size_t vscratch = 0;
+    for (int b = 0; b < nblk; ++b) vscratch += (size_t)8 * cfd::VW_FIELDS * block_cells(dims, b);
+    const size_t scratch = std::max(rscratch, vscratch);
     if (!q_dev || !s_dev || !jinv_dev || !work_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
     if (!(gamma > 1.0) || !std::isfinite(gamma)) cfd::host_fail(CFD_EINVAL, "gamma must exceed 1");
     if (!(entropy_fix >= 0.0) || !std::isfinite(entropy_fix)) cfd::host_fail(CFD_EINVAL, "bad entropy_fix");
@@ -1881,7 +1906,7 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_
     if (!(dt > 0.0) || !std::isfinite(dt)) cfd::host_fail(CFD_EINVAL, "dt must be positive and finite");
     if (nsteps < 0 || sweeps < 0 || sweeps > 1000) cfd::host_fail(CFD_EINVAL, "nsteps >= 0, sweeps in [0, 1000]");
     std::vector<int64_t> off(nblk + 1, 0);
-    for (int b = 0; b < nblk; ++b) off[b + 1] = off[b] + 19 * block_cells(dims, b);
+    for (int b = 0; b < nblk; ++b) off[b + 1] = off[b] + 22 * block_cells(dims, b);
     const size_t need = scratch + (size_t)8 * off[nblk];
     if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_implicit_blocks_work_bytes()");
     for (int b = 0; b < nblk; ++b) {
@@ -1899,15 +1924,17 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_
       }
     }
     double* base = reinterpret_cast<double*>(static_cast<char*>(work_dev) + scratch);
-    std::vector<double*> R(nblk), dqa(nblk), dqb(nblk), lam(nblk), diag(nblk);
+    std::vector<double*> R(nblk), dqa(nblk), dqb(nblk), lam(nblk), lamv(nblk), diag(nblk);
     for (int b = 0; b < nblk; ++b) {
       const int64_t cb = block_cells(dims, b);
       R[b] = base + off[b];
       dqa[b] = R[b] + 5 * cb;
       dqb[b] = dqa[b] + 5 * cb;
       lam[b] = dqb[b] + 5 * cb;
-      diag[b] = lam[b] + 3 * cb;
+      lamv[b] = lam[b] + 3 * cb;
+      diag[b] = lamv[b] + 3 * cb;
     }
+    const cfd::Gas<double> vgas = cfd::viscous_gas(gamma, viscous ? prandtl : 1.0, mu_inf, s_star);
     auto lines = [&](int b, const std::vector<const double*>& arr) {
       cfd::Lines3 L{};
       for (int d = 0; d < 3; ++d) {
@@ -1917,22 +1944,28 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_
       }
       return L;
     };
-    std::vector<const double*> qv(q_dev, q_dev + nblk), sv(s_dev, s_dev + nblk), lamv(lam.begin(), lam.end());
+    std::vector<const double*> qv(q_dev, q_dev + nblk), sv(s_dev, s_dev + nblk), jv(jinv_dev, jinv_dev + nblk),
+        lamc(lam.begin(), lam.end()), lamvc(lamv.begin(), lamv.end());
     std::vector<double*> rv(R.begin(), R.end());
     for (int it = 0; it < nsteps; ++it) {
       cfd::wcns5_blocks_residual_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, rv.data(), work_dev, gamma,
                                         entropy_fix, eps, stream);
+      if (viscous)
+        cfd::c4_viscous_blocks_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, rv.data(),
+                                      static_cast<double*>(work_dev), vgas, stream);
       for (int b = 0; b < nblk; ++b) {
         const int64_t cb = block_cells(dims, b);
         const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
         hipLaunchKernelGGL(cfd::k_impl_lambda_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream, q_dev[b],
-                           lines(b, qv), s_dev[b], lam[b], D, gamma);
+                           lines(b, qv), s_dev[b], jinv_dev[b], lines(b, jv), lam[b], lamv[b], D, gamma, vgas,
+                           viscous ? 1 : 0);
       }
       for (int b = 0; b < nblk; ++b) {
         const int64_t cb = block_cells(dims, b);
         const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
         hipLaunchKernelGGL(cfd::k_impl_diag_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream, R[b], lam[b],
-                           lines(b, lamv), jinv_dev[b], diag[b], dqa[b], D, dt);
+                           lines(b, lamc), lamv[b], lines(b, lamvc), jinv_dev[b], diag[b], dqa[b], D, dt,
+                           viscous ? 1 : 0);
       }
       std::vector<double*> cur = dqa, nxt = dqb;
       for (int k = 0; k < sweeps; ++k) {
@@ -1941,8 +1974,8 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_
           const int64_t cb = block_cells(dims, b);
           const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
           hipLaunchKernelGGL(cfd::k_impl_sweep_line, dim3(cfd::grid_for(cb)), dim3(256), 0, stream, lines(b, qv),
-                             lines(b, curv), lines(b, sv), lines(b, lamv), R[b], s_dev[b], lam[b], jinv_dev[b],
-                             diag[b], nxt[b], D, gamma - 1.0);
+                             lines(b, curv), lines(b, sv), lines(b, lamc), lines(b, lamvc), viscous ? 1 : 0, R[b],
+                             s_dev[b], lam[b], lamv[b], jinv_dev[b], diag[b], nxt[b], D, gamma - 1.0);
         }
         std::swap(cur, nxt);
       }

@@ -401,20 +401,22 @@ def test_implicit_blocks_bad_arguments():
     nbr = (C.c_int32 * 12)(1, 1, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1)
     nb = C.c_size_t()
     assert L.cfd_wcns5_implicit_blocks_work_bytes(2, dims, nbr, C.byref(nb)) == 0
-    assert nb.value == 8 * (5 * 48 * 15 + 5 * 48 * 10) + 8 * 19 * 240 * 2
+    assert nb.value == max(8 * (5 * 48 * 15 + 5 * 48 * 10), 8 * 29 * 480) + 8 * 22 * 480
     P = lambda *a: (C.c_void_p * 2)(*[C.c_void_p(v) for v in a])         # noqa: E731
     q, s, j = P(0x100000, 0x200000), P(0x300000, 0x400000), P(0x500000, 0x600000)
     w = C.c_void_p(0x900000)
-    ok = dict(q=q, s=s, j=j, w=w, wb=nb.value, g=1.4, ef=0.1, eps=1e-6, dt=0.01, ns=1, sw=2)
+    ok = dict(q=q, s=s, j=j, w=w, wb=nb.value, g=1.4, ef=0.1, eps=1e-6, v=1, pr=0.72, mu=1e-3, ss=0.38, dt=0.01,
+              ns=1, sw=2)
     bad = {-2: [dict(wb=nb.value - 8)],
-           -1: [dict(q=None), dict(w=None), dict(g=1.0), dict(dt=0.0), dict(sw=-1), dict(ns=-1),
+           -1: [dict(q=None), dict(w=None), dict(g=1.0), dict(dt=0.0), dict(sw=-1), dict(ns=-1), dict(pr=0.0),
                 dict(q=P(0x100000, 0x100000 + 8)), dict(q=P(0x300000, 0x200000)), dict(w=C.c_void_p(0x500000)),
                 dict(j=P(0x500000, 0))]}
     for st_want, cases_ in bad.items():
         for b in cases_:
             a = dict(ok, **b)
             st = L.cfd_wcns5_implicit_steps_blocks(2, dims, nbr, a["q"], a["s"], a["j"], a["w"], a["wb"], a["g"],
-                                                   a["ef"], a["eps"], a["dt"], a["ns"], a["sw"], None)
+                                                   a["ef"], a["eps"], a["v"], a["pr"], a["mu"], a["ss"], a["dt"],
+                                                   a["ns"], a["sw"], None)
             assert st == st_want, b
 
 

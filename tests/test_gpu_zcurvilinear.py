@@ -406,3 +406,35 @@ def test_ns_steps_on_split_blocks_match_the_unsplit_block():
     top = max(float(np.max(np.abs(w))) for w in want)
     for g, w in zip(got, want):
         assert np.max(np.abs(g.cpu().numpy() - w)) <= 1e-12 * top
+
+
+def test_viscous_implicit_steps_on_split_blocks_match_the_unsplit_block():
+    """The 12-block split with viscous terms: 2 implicit Navier-Stokes steps
+    with 4 sweeps on the blocks are bitwise the unsplit block's on the device,
+    and match the oracle's blocks within 1e-11."""
+    import torch
+    from paper_1710_09995_amd.binding import (wcns5_implicit_steps_blocks, wcns5_implicit_steps_curv_periodic,
+                                              wcns5_metrics_periodic)
+    from test_oracle_highorder import _split_box
+    n = (40, 30, 24)
+    Xv, P = _curv_grid(n, "wavy")
+    say("viscous implicit blocks", n)
+    S, J = wcns5_metrics_periodic(torch.from_numpy(Xv).cuda(), P)
+    q = _smooth_state(n, seed=18)
+    qt = torch.from_numpy(q).cuda()
+    lo, m, nbr = _split_box(n, ([17], [8, 20], [11]))
+    sls = [(slice(o[2], o[2] + e[2]), slice(o[1], o[1] + e[1]), slice(o[0], o[0] + e[0])) for o, e in zip(lo, m)]
+    qs = [qt[(slice(None),) + sl].contiguous() for sl in sls]
+    Ss = [S[(slice(None), slice(None)) + sl].contiguous() for sl in sls]
+    Js = [J[sl].contiguous() for sl in sls]
+    q0s = [t.cpu().numpy() for t in qs]
+    kw = dict(viscous=True, prandtl=0.72, mu_inf=0.02, s_star=0.38)
+    whole = wcns5_implicit_steps_curv_periodic(qt.clone(), S, J, 0.05, 2, 4, **kw)
+    got = wcns5_implicit_steps_blocks(qs, Ss, Js, nbr, 0.05, 2, 4, **kw)
+    for sl, g in zip(sls, got):
+        assert torch.equal(g, whole[(slice(None),) + sl])
+    want = ho.implicit_steps_blocks(q0s, [t.cpu().numpy() for t in Ss], [t.cpu().numpy() for t in Js], nbr, 1.4, 0.1,
+                                    0.05, 2, 4, **kw)
+    top = max(float(np.max(np.abs(w))) for w in want)
+    for g, w in zip(got, want):
+        assert np.max(np.abs(g.cpu().numpy() - w)) <= 1e-11 * top
