@@ -208,25 +208,26 @@ def test_curvilinear_time_step_parity(viscous):
     assert abs(got - want) <= 1e-14 * want
 
 
-def test_block_seams_match_the_unsplit_block():
+@pytest.mark.parametrize("n,cuts", [((40, 30, 24), ([17], [8, 20], [11])), ((30, 15, 10), ([5, 25], [5], [5]))])
+def test_block_seams_match_the_unsplit_block(n, cuts):
     """A periodic wavy block cut into 2 x 3 x 2 blocks joined face to face:
     each block's metrics from its own vertices (cfd_wcns5_metrics_ext) match
     the unsplit block's within 1e-13 (the wrapped coordinates are formed on
     the host here and on the device there); with the unsplit block's metrics
     sliced, the blocks' residuals are bitwise the unsplit residual's slices;
-    and the residuals match the oracle's blocks within 1e-12."""
+    and the residuals match the oracle's blocks within 1e-12.  The second
+    split has blocks exactly five cells deep, the least a seam allows."""
     import torch
     from paper_1710_09995_amd.binding import (wcns5_euler_residual_blocks, wcns5_euler_residual_curv_periodic,
                                               wcns5_metrics_ext, wcns5_metrics_periodic)
     from test_oracle_highorder import _split_box
-    n = (40, 30, 24)
     Xv, P = _curv_grid(n, "wavy")
-    say("block seams", n)
+    say("block seams", n, cuts)
     S, J = wcns5_metrics_periodic(torch.from_numpy(Xv).cuda(), P)
     q = _smooth_state(n, seed=4)
     qt = torch.from_numpy(q).cuda()
     R = wcns5_euler_residual_curv_periodic(qt, S, J)
-    lo, m, nbr = _split_box(n, ([17], [8, 20], [11]))
+    lo, m, nbr = _split_box(n, cuts)
     qs, Ss, Js, Sx, Jx = [], [], [], [], []
     for o, e in zip(lo, m):
         sl = (slice(o[2], o[2] + e[2]), slice(o[1], o[1] + e[1]), slice(o[0], o[0] + e[0]))
@@ -378,20 +379,20 @@ def test_implicit_steps_on_split_blocks_match_the_unsplit_block():
         assert np.max(np.abs(g.cpu().numpy() - w)) <= 1e-11 * top
 
 
-def test_ns_steps_on_split_blocks_match_the_unsplit_block():
+@pytest.mark.parametrize("n,cuts", [((40, 30, 24), ([17], [8, 20], [11])), ((30, 15, 10), ([5, 25], [5], [5]))])
+def test_ns_steps_on_split_blocks_match_the_unsplit_block(n, cuts):
     """The paper's explicit method on a multi-block grid on the device: 2 RK3
     Navier-Stokes steps on the 12-block split of a periodic wavy block are
     bitwise the unsplit block's, and match the oracle's blocks within 1e-12."""
     import torch
     from paper_1710_09995_amd.binding import wcns5_metrics_periodic, wcns5_ns_steps_blocks, wcns5_ns_steps_curv_periodic
     from test_oracle_highorder import _split_box
-    n = (40, 30, 24)
     Xv, P = _curv_grid(n, "wavy")
-    say("ns blocks", n)
+    say("ns blocks", n, cuts)
     S, J = wcns5_metrics_periodic(torch.from_numpy(Xv).cuda(), P)
     q = _smooth_state(n, seed=17)
     qt = torch.from_numpy(q).cuda()
-    lo, m, nbr = _split_box(n, ([17], [8, 20], [11]))
+    lo, m, nbr = _split_box(n, cuts)
     sls = [(slice(o[2], o[2] + e[2]), slice(o[1], o[1] + e[1]), slice(o[0], o[0] + e[0])) for o, e in zip(lo, m)]
     qs = [qt[(slice(None),) + sl].contiguous() for sl in sls]
     Ss = [S[(slice(None), slice(None)) + sl].contiguous() for sl in sls]
