@@ -375,6 +375,81 @@ def bench_implicit(a) -> int:
     return 0
 
 
+def bench_ns_blocks(a) -> int:
+    """RK3 Navier-Stokes steps on the wavy periodic 256x128x128 grid of --op
+    wcns5_curv cut into 2 x 2 x 2 blocks joined face to face, against the same
+    steps on the unsplit periodic block in the same run: K steps after W
+    warm-up ones each, hipEvents on the launch stream."""
+    import numpy as np
+    import torch
+    from paper_1710_09995_amd.binding import (wcns5_metrics_periodic, wcns5_ns_steps_blocks,
+                                              wcns5_ns_steps_curv_periodic, wcns5_time_step_curv_periodic)
+    n = (256, 128, 128)
+    ni, nj, nk = n
+    cells = ni * nj * nk
+    rng = np.random.default_rng(0)
+    ph = rng.uniform(0, 2 * np.pi, 4)
+    s2 = 2 * np.pi
+    z, y, x = np.meshgrid(np.arange(nk) / nk, np.arange(nj) / nj, np.arange(ni) / ni, indexing="ij")
+    rho = 1 + 0.2 * np.sin(s2 * x + ph[0]) * np.cos(s2 * y + ph[1]) + 0.1 * np.sin(s2 * z + ph[2])
+    u, v, w = 0.5 + 0.1 * np.sin(s2 * y + ph[3]), 0.1 * np.sin(s2 * z), 0.1 * np.sin(s2 * x)
+    p = 1 + 0.1 * np.cos(s2 * (x + y + z))
+    q0 = torch.from_numpy(np.stack([rho, rho * u, rho * v, rho * w,
+                                    p / 0.4 + 0.5 * rho * (u * u + v * v + w * w)])).cuda()
+    L, amp = (1.0, 0.5, 0.5), 0.05
+    zb, yb, xb = np.meshgrid((np.arange(nk) + 0.5) * L[2] / nk, (np.arange(nj) + 0.5) * L[1] / nj,
+                             (np.arange(ni) + 0.5) * L[0] / ni, indexing="ij")
+    wx, wy, wz = s2 * xb / L[0], s2 * yb / L[1], s2 * zb / L[2]
+    xv = torch.from_numpy(np.stack([xb + amp * L[0] * np.sin(wy) * np.sin(wz),
+                                    yb + amp * L[1] * np.sin(wz) * np.sin(wx),
+                                    zb + amp * L[2] * np.sin(wx) * np.sin(wy)])).cuda()
+    S, jinv = wcns5_metrics_periodic(xv, np.diag(L))
+    mu = 1e-3
+    dt = float(wcns5_time_step_curv_periodic(q0, S, jinv, 0.5, 1.4, True, 0.72, mu).cpu()[0])
+    half = (ni // 2, nj // 2, nk // 2)
+    sls, nbr = [], []
+    for c in range(2):
+        for b in range(2):
+            for aa in range(2):
+                sls.append((slice(c * half[2], (c + 1) * half[2]), slice(b * half[1], (b + 1) * half[1]),
+                            slice(aa * half[0], (aa + 1) * half[0])))
+                idx = lambda i, j, k: (k % 2) * 4 + (j % 2) * 2 + (i % 2)          # noqa: E731
+                nbr.append([idx(aa - 1, b, c), idx(aa + 1, b, c), idx(aa, b - 1, c), idx(aa, b + 1, c),
+                            idx(aa, b, c - 1), idx(aa, b, c + 1)])
+    qs = [q0[(slice(None),) + sl].contiguous() for sl in sls]
+    Ss = [S[(slice(None), slice(None)) + sl].contiguous() for sl in sls]
+    Js = [jinv[sl].contiguous() for sl in sls]
+    qw = q0.clone()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(a.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / a.steps
+    ms_blocks = timed(lambda: wcns5_ns_steps_blocks(qs, Ss, Js, nbr, dt, 1, 1.4, 0.1, 1e-6, 0.72, mu))
+    ms_whole = timed(lambda: wcns5_ns_steps_curv_periodic(qw, S, jinv, dt, 1, 1.4, 0.1, 1e-6, 0.72, mu))
+    finite = bool(all(torch.isfinite(t).all() for t in qs))
+    print(json.dumps({
+        "metric": "Mcell-stage/s of RK3 Navier-Stokes steps (WCNS-E-5 + fourth-order viscous) on 8 curvilinear "
+                  "blocks joined face to face",
+        "value": round(cells * 3 / (ms_blocks / 1e3) / 1e6, 1), "unit": "Mcell-stage/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_blocks, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded smooth periodic flow, "
+        "wavy grid)",
+        "config": {"workload": "ns_wcns5_c4_blocks_2x2x2_of_256x128x128", "blocks": 8, "finite": finite,
+                   "unsplit_ms_per_step": round(ms_whole, 4),
+                   "unsplit_mcell_stage_s": round(cells * 3 / (ms_whole / 1e3) / 1e6, 1)},
+        "roofline": None, "cpu_baseline": None}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -399,7 +474,8 @@ def main(argv=None):
                     help="with --split: cut positions snap to multiples of these (1,1,1 = plain bisection)")
     ap.add_argument("--groups", type=int, default=8,
                     help="with --split: groups (devices) the pieces are regrouped into for the balance report")
-    ap.add_argument("--op", default=None, choices=["diff6", "wcns5", "wcns5_euler", "ns_periodic", "wcns5_curv", "ns_curv", "implicit_curv"],
+    ap.add_argument("--op", default=None, choices=["diff6", "wcns5", "wcns5_euler", "ns_periodic", "wcns5_curv", "ns_curv", "implicit_curv",
+                             "ns_blocks"],
                     help="time one operator instead of the solver, on a 256x128x128 block, 5 variables, each "
                          "direction: diff6 = the sixth-order staggered flux difference (Section 2.2, Eq. 2); "
                          "wcns5 = the WCNS-E-5 weighted cell-edge interpolation; wcns5_euler = the periodic "
@@ -407,7 +483,9 @@ def main(argv=None):
                          "fourth-order central viscous terms; wcns5_curv = the inviscid residual on a wavy "
                          "curvilinear periodic grid (metrics computed once, their time reported); ns_curv = that "
                          "residual plus the curvilinear fourth-order viscous terms; implicit_curv = implicit "
-                         "steps (backward Euler, Jacobi sweeps) on the curvilinear residual")
+                         "steps (backward Euler, Jacobi sweeps) on the curvilinear residual; ns_blocks = RK3 "
+                         "Navier-Stokes steps on that grid cut into 2 x 2 x 2 blocks joined face to face, with the "
+                         "unsplit block timed beside it")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (HBM counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -425,6 +503,8 @@ def main(argv=None):
         return bench_wcns5_euler(a)
     if a.op == "implicit_curv" and a.gpus == 1:
         return bench_implicit(a)
+    if a.op == "ns_blocks" and a.gpus == 1:
+        return bench_ns_blocks(a)
     if a.op is not None and a.gpus == 1:
         return bench_op(a)
     if a.gpus != 1:
