@@ -1341,14 +1341,45 @@ struct Dims3 {
   int n[3];
 };
 
+// A neighbour resolved once: field f of the cell s steps along d is at
+// base[f * cells + idx], whichever block holds it.
+struct LineRef {
+  const double* base;
+  int64_t cells, idx;
+  __device__ __forceinline__ double operator[](int f) const { return base[f * cells + idx]; }
+};
+
+__device__ __forceinline__ LineRef line_ref(const Line& L, int i, int j, int k, int s, int d, const int n[3]) {
+  int c[3] = {i, j, k};
+  int x = c[d] + s;
+  LineRef r{L.own, L.cown, 0};
+  int nd = n[d];
+  if (x < 0) {
+    r.base = L.lo;
+    r.cells = L.clo;
+    x += L.nlo;
+    nd = L.nlo;
+  } else if (x >= n[d]) {
+    r.base = L.hi;
+    r.cells = L.chi;
+    x -= n[d];
+    nd = L.nhi;
+  }
+  c[d] = x;
+  const int64_t e0 = d == 0 ? nd : n[0], e1 = d == 1 ? nd : n[1];
+  r.idx = ((int64_t)c[2] * e1 + c[1]) * e0 + c[0];
+  return r;
+}
+
 // g[(a * 3 + t) * cells + c] = index derivative of phi_a along t.
 __global__ void __launch_bounds__(256) k_c4_grads_line(Line phi, double* __restrict__ g, Dims3 D, int t) {
   const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
+    const LineRef rm2 = line_ref(phi, i, j, k, -2, t, D.n), rm1 = line_ref(phi, i, j, k, -1, t, D.n),
+                  rp1 = line_ref(phi, i, j, k, 1, t, D.n), rp2 = line_ref(phi, i, j, k, 2, t, D.n);
     for (int a = 0; a < 4; ++a) {
-      const double m2 = line_at(phi, a, i, j, k, -2, t, D.n), m1 = line_at(phi, a, i, j, k, -1, t, D.n),
-                   p1 = line_at(phi, a, i, j, k, 1, t, D.n), p2 = line_at(phi, a, i, j, k, 2, t, D.n);
+      const double m2 = rm2[a], m1 = rm1[a], p1 = rp1[a], p2 = rp2[a];
       g[(a * 3 + t) * cells + c] = (m2 - 8.0 * m1 + 8.0 * p1 - p2) * (1.0 / 12.0);
     }
   }
@@ -1359,11 +1390,11 @@ __global__ void __launch_bounds__(256) k_c4_cell_metrics_line(Line S, double* __
   const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
+    const LineRef rm2 = line_ref(S, i, j, k, -2, t, D.n), rm1 = line_ref(S, i, j, k, -1, t, D.n),
+                  r0 = line_ref(S, i, j, k, 0, t, D.n), rp1 = line_ref(S, i, j, k, 1, t, D.n);
     for (int x = 0; x < 3; ++x) {
       const int f = t * 3 + x;
-      sc[f * cells + c] = (-line_at(S, f, i, j, k, -2, t, D.n) + 9.0 * line_at(S, f, i, j, k, -1, t, D.n) +
-                           9.0 * line_at(S, f, i, j, k, 0, t, D.n) - line_at(S, f, i, j, k, 1, t, D.n)) /
-                          16.0;
+      sc[f * cells + c] = (-rm2[f] + 9.0 * rm1[f] + 9.0 * r0[f] - rp1[f]) / 16.0;
     }
   }
 }
@@ -1377,10 +1408,17 @@ __global__ void __launch_bounds__(256) k_c4_visc_faces_line(Line W, Line J, cons
   const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
+    const LineRef wm1 = line_ref(W, i, j, k, -1, d, D.n), w0 = line_ref(W, i, j, k, 0, d, D.n),
+                  wp1 = line_ref(W, i, j, k, 1, d, D.n), wp2 = line_ref(W, i, j, k, 2, d, D.n);
+    const LineRef jm1 = line_ref(J, i, j, k, -1, d, D.n), j0 = line_ref(J, i, j, k, 0, d, D.n),
+                  jp1 = line_ref(J, i, j, k, 1, d, D.n), jp2 = line_ref(J, i, j, k, 2, d, D.n);
     auto fvl = [&](const Line& L, int f) {
-      return (-line_at(L, f, i, j, k, -1, d, D.n) + 9.0 * line_at(L, f, i, j, k, 0, d, D.n) +
-              9.0 * line_at(L, f, i, j, k, 1, d, D.n) - line_at(L, f, i, j, k, 2, d, D.n)) /
-             16.0;
+      const bool w = &L == &W;
+      const LineRef& a = w ? wm1 : jm1;
+      const LineRef& b = w ? w0 : j0;
+      const LineRef& c2 = w ? wp1 : jp1;
+      const LineRef& d2 = w ? wp2 : jp2;
+      return (-a[f] + 9.0 * b[f] + 9.0 * c2[f] - d2[f]) / 16.0;
     };
     double Sf[3][3], Sd[3];
     for (int t = 0; t < 3; ++t)
@@ -1392,9 +1430,7 @@ __global__ void __launch_bounds__(256) k_c4_visc_faces_line(Line W, Line J, cons
       pf[a] = fvl(W, VW_PHI + a);
       double dxi[3];
       for (int t = 0; t < 3; ++t)
-        dxi[t] = t == d ? (line_at(W, VW_PHI + a, i, j, k, -1, d, D.n) - 27.0 * line_at(W, VW_PHI + a, i, j, k, 0, d, D.n) +
-                           27.0 * line_at(W, VW_PHI + a, i, j, k, 1, d, D.n) -
-                           line_at(W, VW_PHI + a, i, j, k, 2, d, D.n)) *
+        dxi[t] = t == d ? (wm1[VW_PHI + a] - 27.0 * w0[VW_PHI + a] + 27.0 * wp1[VW_PHI + a] - wp2[VW_PHI + a]) *
                               (1.0 / 24.0)
                         : fvl(W, VW_G + a * 3 + t);
       for (int x = 0; x < 3; ++x) grad[a][x] = Jf * (Sf[0][x] * dxi[0] + Sf[1][x] * dxi[1] + Sf[2][x] * dxi[2]);
@@ -1419,11 +1455,11 @@ __global__ void __launch_bounds__(256) k_c4_flux_sub_line(Line W, double* __rest
   const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
+    const LineRef rm2 = line_ref(W, i, j, k, -2, d, D.n), rm1 = line_ref(W, i, j, k, -1, d, D.n),
+                  r0 = line_ref(W, i, j, k, 0, d, D.n), rp1 = line_ref(W, i, j, k, 1, d, D.n);
     for (int v = 0; v < 4; ++v) {
       const int f = VW_FV + v;
-      const double dF = (line_at(W, f, i, j, k, -2, d, D.n) - 27.0 * line_at(W, f, i, j, k, -1, d, D.n) +
-                         27.0 * line_at(W, f, i, j, k, 0, d, D.n) - line_at(W, f, i, j, k, 1, d, D.n)) *
-                        (1.0 / 24.0);
+      const double dF = (rm2[f] - 27.0 * rm1[f] + 27.0 * r0[f] - rp1[f]) * (1.0 / 24.0);
       r[(1 + v) * cells + c] -= dF / jinv[c];
     }
   }
