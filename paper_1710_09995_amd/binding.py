@@ -247,6 +247,17 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _scratch(torch, nbytes, device, stream):
+    """Temporary device workspace for one call on `stream`.  The caching
+    allocator ties a block to the stream current at allocation; when the call
+    runs on another stream the block is recorded there too, so that it is not
+    handed out again before that stream's work on it has finished."""
+    t = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    if stream is not None and stream != torch.cuda.current_stream(device):
+        t.record_stream(stream)
+    return t
+
+
 def staggered_diff6(f, n, d: int, h: float, out=None, stream=None):
     """Eq. (2) of Section 2.2 on the device (cfd_staggered_diff6): f is a
     contiguous FP64 CUDA tensor [nvar, Nk, Nj, Ni] of face values with
@@ -301,7 +312,7 @@ def wcns5_euler_residual_periodic(q, h, gamma: float = 1.4, entropy_fix: float =
     nbytes = C.c_size_t()
     _check(lib().cfd_wcns5_euler_work_bytes(nn, C.byref(nbytes)))
     if work is None or work.numel() * work.element_size() < nbytes.value:
-        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+        work = _scratch(torch, nbytes.value, q.device, stream)
     if out is None:
         out = torch.empty_like(q)
     hh = (C.c_double * 3)(*[float(v) for v in h])
@@ -323,7 +334,7 @@ def wcns5_euler_steps_periodic(q, h, dt: float, nsteps: int, gamma: float = 1.4,
     nbytes = C.c_size_t()
     _check(lib().cfd_wcns5_euler_step_work_bytes(nn, C.byref(nbytes)))
     if work is None or work.numel() * work.element_size() < nbytes.value:
-        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+        work = _scratch(torch, nbytes.value, q.device, stream)
     hh = (C.c_double * 3)(*[float(v) for v in h])
     _check(lib().cfd_wcns5_euler_steps_periodic(_ptr(q), _ptr(work), nbytes.value, nn, hh, float(gamma),
                                                 float(entropy_fix), float(eps), float(dt), int(nsteps),
@@ -345,7 +356,7 @@ def c4_viscous_add_periodic(q, r, h, gamma: float = 1.4, prandtl: float = 0.72, 
     nbytes = C.c_size_t()
     _check(lib().cfd_c4_viscous_work_bytes(nn, C.byref(nbytes)))
     if work is None or work.numel() * work.element_size() < nbytes.value:
-        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+        work = _scratch(torch, nbytes.value, q.device, stream)
     hh = (C.c_double * 3)(*[float(v) for v in h])
     _check(lib().cfd_c4_viscous_add_periodic(_ptr(q), _ptr(r), _ptr(work), nbytes.value, nn, hh, float(gamma),
                                              float(prandtl), float(mu_inf), float(s_star),
@@ -390,7 +401,7 @@ def wcns5_euler_residual_curv_periodic(q, S, jinv, gamma: float = 1.4, entropy_f
     nbytes = C.c_size_t()
     _check(lib().cfd_wcns5_euler_work_bytes(nn, C.byref(nbytes)))
     if work is None or work.numel() * work.element_size() < nbytes.value:
-        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+        work = _scratch(torch, nbytes.value, q.device, stream)
     if out is None:
         out = torch.empty_like(q)
     _check(lib().cfd_wcns5_euler_residual_curv_periodic(_ptr(q), _ptr(S), _ptr(jinv), _ptr(out), _ptr(work),
@@ -415,7 +426,7 @@ def wcns5_euler_steps_curv_periodic(q, S, jinv, dt: float, nsteps: int, gamma: f
     nbytes = C.c_size_t()
     _check(lib().cfd_wcns5_euler_step_work_bytes(nn, C.byref(nbytes)))
     if work is None or work.numel() * work.element_size() < nbytes.value:
-        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+        work = _scratch(torch, nbytes.value, q.device, stream)
     _check(lib().cfd_wcns5_euler_steps_curv_periodic(_ptr(q), _ptr(S), _ptr(jinv), _ptr(work), nbytes.value, nn,
                                                      float(gamma), float(entropy_fix), float(eps), float(dt),
                                                      int(nsteps), _stream_handle(torch, stream)))
@@ -440,7 +451,7 @@ def c4_viscous_add_curv_periodic(q, r, S, jinv, gamma: float = 1.4, prandtl: flo
     nbytes = C.c_size_t()
     _check(lib().cfd_c4_viscous_curv_work_bytes(nn, C.byref(nbytes)))
     if work is None or work.numel() * work.element_size() < nbytes.value:
-        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+        work = _scratch(torch, nbytes.value, q.device, stream)
     _check(lib().cfd_c4_viscous_add_curv_periodic(_ptr(q), _ptr(S), _ptr(jinv), _ptr(r), _ptr(work), nbytes.value,
                                                   nn, float(gamma), float(prandtl), float(mu_inf), float(s_star),
                                                   _stream_handle(torch, stream)))
@@ -507,7 +518,7 @@ def wcns5_euler_residual_blocks(qs, Ss, jinvs, nbr, gamma: float = 1.4, entropy_
     nbytes = C.c_size_t()
     _check(lib().cfd_wcns5_euler_blocks_work_bytes(nblk, dims, nb, C.byref(nbytes)))
     if work is None or work.numel() * work.element_size() < nbytes.value:
-        work = torch.empty(max(nbytes.value, 8), dtype=torch.uint8, device=qs[0].device)
+        work = _scratch(torch, max(nbytes.value, 8), qs[0].device, stream)
     if outs is None:
         outs = [torch.empty_like(q) for q in qs]
     ptrs = lambda ts: (C.c_void_p * nblk)(*[_ptr(t) for t in ts])   # noqa: E731
@@ -541,7 +552,7 @@ def c4_viscous_add_blocks(qs, rs, Ss, jinvs, nbr, gamma: float = 1.4, prandtl: f
     nbytes = C.c_size_t()
     _check(lib().cfd_c4_viscous_blocks_work_bytes(nblk, dims, nb, C.byref(nbytes)))
     if work is None or work.numel() * work.element_size() < nbytes.value:
-        work = torch.empty(nbytes.value, dtype=torch.uint8, device=qs[0].device)
+        work = _scratch(torch, nbytes.value, qs[0].device, stream)
     ptrs = lambda ts: (C.c_void_p * nblk)(*[_ptr(t) for t in ts])   # noqa: E731
     _check(lib().cfd_c4_viscous_add_blocks(nblk, dims, nb, ptrs(qs), ptrs(Ss), ptrs(jinvs), ptrs(rs), _ptr(work),
                                            nbytes.value, float(gamma), float(prandtl), float(mu_inf), float(s_star),
@@ -567,7 +578,7 @@ def wcns5_ns_steps_curv_periodic(q, S, jinv, dt: float, nsteps: int, gamma: floa
     nbytes = C.c_size_t()
     _check(lib().cfd_wcns5_ns_step_work_bytes(nn, C.byref(nbytes)))
     if work is None or work.numel() * work.element_size() < nbytes.value:
-        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+        work = _scratch(torch, nbytes.value, q.device, stream)
     _check(lib().cfd_wcns5_ns_steps_curv_periodic(_ptr(q), _ptr(S), _ptr(jinv), _ptr(work), nbytes.value, nn,
                                                   float(gamma), float(entropy_fix), float(eps), float(prandtl),
                                                   float(mu_inf), float(s_star), float(dt), int(nsteps),
@@ -594,7 +605,7 @@ def wcns5_implicit_steps_curv_periodic(q, S, jinv, dt: float, nsteps: int, sweep
     nbytes = C.c_size_t()
     _check(lib().cfd_wcns5_implicit_step_work_bytes(nn, C.byref(nbytes)))
     if work is None or work.numel() * work.element_size() < nbytes.value:
-        work = torch.empty(nbytes.value, dtype=torch.uint8, device=q.device)
+        work = _scratch(torch, nbytes.value, q.device, stream)
     _check(lib().cfd_wcns5_implicit_steps_curv_periodic(_ptr(q), _ptr(S), _ptr(jinv), _ptr(work), nbytes.value, nn,
                                                         float(gamma), float(entropy_fix), float(eps),
                                                         1 if viscous else 0, float(prandtl), float(mu_inf),
@@ -626,7 +637,7 @@ def wcns5_implicit_steps_blocks(qs, Ss, jinvs, nbr, dt: float, nsteps: int, swee
     nbytes = C.c_size_t()
     _check(lib().cfd_wcns5_implicit_blocks_work_bytes(nblk, dims, nb, C.byref(nbytes)))
     if work is None or work.numel() * work.element_size() < nbytes.value:
-        work = torch.empty(nbytes.value, dtype=torch.uint8, device=qs[0].device)
+        work = _scratch(torch, nbytes.value, qs[0].device, stream)
     ptrs = lambda ts: (C.c_void_p * nblk)(*[_ptr(t) for t in ts])   # noqa: E731
     _check(lib().cfd_wcns5_implicit_steps_blocks(nblk, dims, nb, ptrs(qs), ptrs(Ss), ptrs(jinvs), _ptr(work),
                                                  nbytes.value, float(gamma), float(entropy_fix), float(eps),
@@ -657,7 +668,7 @@ def wcns5_ns_steps_blocks(qs, Ss, jinvs, nbr, dt: float, nsteps: int, gamma: flo
     nbytes = C.c_size_t()
     _check(lib().cfd_wcns5_ns_blocks_work_bytes(nblk, dims, nb, C.byref(nbytes)))
     if work is None or work.numel() * work.element_size() < nbytes.value:
-        work = torch.empty(nbytes.value, dtype=torch.uint8, device=qs[0].device)
+        work = _scratch(torch, nbytes.value, qs[0].device, stream)
     ptrs = lambda ts: (C.c_void_p * nblk)(*[_ptr(t) for t in ts])   # noqa: E731
     _check(lib().cfd_wcns5_ns_steps_blocks(nblk, dims, nb, ptrs(qs), ptrs(Ss), ptrs(jinvs), _ptr(work), nbytes.value,
                                            float(gamma), float(entropy_fix), float(eps), float(prandtl),
