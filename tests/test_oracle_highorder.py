@@ -765,6 +765,96 @@ def _implicit_setup():
     return q, S, Jinv
 
 
+def _physical_flux_dot(Q, S, gamma):
+    """F(Q) . S written out from Eq. (1)'s inviscid flux: (rho U, rho u U + p S,
+    (rho E + p) U) with U = u . S."""
+    rho = Q[0]
+    u, v, w = Q[1] / rho, Q[2] / rho, Q[3] / rho
+    p = (gamma - 1.0) * (Q[4] - 0.5 * rho * (u * u + v * v + w * w))
+    U = u * S[0] + v * S[1] + w * S[2]
+    return np.stack([rho * U, rho * u * U + p * S[0], rho * v * U + p * S[1], rho * w * U + p * S[2],
+                     (Q[4] + p) * U])
+
+
+def _llf_residual_frozen(Q, Q0, S, Jinv, gamma, nu_visc=None, prandtl=0.72, s_star=0.38):
+    """First-order local Lax-Friedrichs residual with its dissipation frozen at
+    Q0, R1 = J sum_d (Fh_{i+1/2} - Fh_{i-1/2}) with
+    Fh_f = (F(Q_L) + F(Q_R)) . S_f / 2 - (lam_f / 2 + lv_f)(Q_R - Q_L),
+    lam_f = |u_m . S_f| + c_m |S_f| of the mean primitive state of the face's
+    two cells (at Q0), and for viscous flow lv_f = max(4/3, gamma/Pr) nu_m |S_f|^2 / Jinv_m
+    (means of the two cells; nu = mu/rho, Sutherland).  Also returns
+    G = J sum_d F(Q_i) . (S_{i+1/2} - S_{i-1/2}) / 2, the part of R1 that the
+    implicit reading leaves off its diagonal."""
+    R1 = np.zeros_like(Q)
+    G = np.zeros_like(Q)
+    rho0 = Q0[0]
+    u0 = Q0[1:4] / rho0
+    p0 = (gamma - 1.0) * (Q0[4] - 0.5 * rho0 * np.sum(u0 * u0, axis=0))
+    prim0 = np.concatenate([rho0[None], u0, p0[None]])
+    for d in range(3):
+        ax = 3 - d
+        Sf = S[d]                                   # faces i + 1/2 of cells i
+        Qr = np.roll(Q, -1, axis=ax)
+        Wm = 0.5 * (prim0 + np.roll(prim0, -1, axis=ax))
+        lam = (np.abs(Wm[1] * Sf[0] + Wm[2] * Sf[1] + Wm[3] * Sf[2])
+               + np.sqrt(gamma * Wm[4] / Wm[0]) * np.sqrt(np.sum(Sf * Sf, axis=0)))
+        diss = 0.5 * lam
+        if nu_visc is not None:
+            T = p0 / rho0
+            mu = nu_visc * T * np.sqrt(T) * (1.0 + s_star) / (T + s_star)
+            nu = mu / rho0
+            num = 0.5 * (nu + np.roll(nu, -1, axis=ax - 1))
+            jm = 0.5 * (Jinv + np.roll(Jinv, -1, axis=ax - 1))
+            diss = diss + max(4.0 / 3.0, gamma / prandtl) * num * np.sum(Sf * Sf, axis=0) / jm
+        Fh = 0.5 * (_physical_flux_dot(Q, Sf, gamma) + _physical_flux_dot(Qr, Sf, gamma)) - diss * (Qr - Q)
+        R1 = R1 + (Fh - np.roll(Fh, 1, axis=ax))
+        G = G + 0.5 * _physical_flux_dot(Q, Sf - np.roll(Sf, 1, axis=ax), gamma)
+    return R1 / Jinv, G / Jinv
+
+
+@pytest.mark.parametrize("viscous", [False, True])
+def test_implicit_operator_is_the_frozen_llf_jacobian(viscous):
+    """The implicit reading's linear operator, read off the sweeps as a black
+    box (zero sweeps from dQ = -R / D give D; one sweep from R = -D dQ gives
+    D dQ + J O(dQ) = D (2 dQ - dQ_1)), equals I/dt plus the Jacobian of the
+    first-order local Lax-Friedrichs residual with frozen dissipation (less
+    the cell's own flux through S_{i+1/2} - S_{i-1/2}, which the reading
+    drops), the Jacobian taken by central differences of that residual,
+    written here independently of the oracle.  The operator's central
+    difference agrees to O(|dQ|^2) (1e-8 at |dQ| = 1e-4 |Q|), and the
+    one-sided form L(dQ) / |dQ| converges at first order, i.e. L(dQ) equals
+    the Jacobian times dQ to O(|dQ|^2)."""
+    q, S, Jinv = _implicit_setup()
+    gamma, dt = 1.4, 0.05
+    kw = dict(viscous=True, prandtl=0.72, mu_inf=0.02, s_star=0.38) if viscous else {}
+
+    def sweeps(R, n):
+        return ho.implicit_sweeps_curv_periodic(q, R, S, Jinv, gamma, dt, n, **kw)
+
+    ones = np.ones_like(q)
+    D = -ones / sweeps(ones, 0)
+    assert np.all(D > 1.0 / dt)
+
+    def L_oracle(dq):
+        return D * (2.0 * dq - sweeps(-D * dq, 1))
+
+    rng = np.random.default_rng(21)
+    vdir = rng.uniform(-1.0, 1.0, q.shape) * np.abs(q).max(axis=(1, 2, 3), keepdims=True)
+    nu = 0.02 if viscous else None
+
+    def R1_minus_G(x):
+        R1, G = _llf_residual_frozen(x, q, S, Jinv, gamma, nu)
+        return R1 - G
+    h = 1e-5
+    L_ref = vdir / dt + (R1_minus_G(q + h * vdir) - R1_minus_G(q - h * vdir)) / (2.0 * h)
+    scale = np.abs(L_ref).max()
+    eta = 1e-4
+    central = (L_oracle(eta * vdir) - L_oracle(-eta * vdir)) / (2.0 * eta)
+    assert np.abs(central - L_ref).max() <= 1e-8 * scale
+    one_sided = [np.abs(L_oracle(e * vdir) / e - L_ref).max() / scale for e in (1e-2, 1e-3, 1e-4)]
+    assert one_sided[0] < 0.1 and all(8.0 < one_sided[i] / one_sided[i + 1] < 12.0 for i in range(2)), one_sided
+
+
 def test_implicit_step_explicit_euler_limit_and_freestream():
     """Backward Euler's first-order limit: dQ = -dt R + O(dt^2), so
     |dQ + dt R| / (dt max|R|) falls in proportion to dt; a uniform stream
