@@ -677,6 +677,15 @@ def wcns5_ns_steps_blocks(qs, Ss, jinvs, nbr, dt: float, nsteps: int, gamma: flo
     return qs
 
 
+
+def _on_device(torch, x, device):
+    """A contiguous FP64 device tensor of a NumPy array or a tensor (a device
+    tensor already in place is used as it is)."""
+    if torch.is_tensor(x):
+        return x.to(device=device, dtype=torch.float64).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(device)
+
+
 class Solver:
     """One context over one GPU's share of blocks.
 
@@ -701,7 +710,7 @@ class Solver:
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
             self.q = torch.full((self.arena_elems,), float("nan"), dtype=torch.float64, device=self.device)
-            nodes = [torch.from_numpy(np.ascontiguousarray(x)).to(self.device) for x in case.nodes]
+            nodes = [_on_device(torch, x, self.device) for x in case.nodes]
             nptrs = (C.c_void_p * len(nodes))(*[t.data_ptr() for t in nodes])
             conns = to_conns(case.conns)
             bcs = to_bcs(case.bcs)
@@ -763,7 +772,7 @@ class Solver:
     def set_state(self, q0: Sequence[np.ndarray], arena=None):
         arena = self.q if arena is None else arena
         for v, q in zip(self.interior_views(arena), q0):
-            v.copy_(self.torch.from_numpy(np.ascontiguousarray(q)).to(self.device))
+            v.copy_(_on_device(self.torch, q, self.device))
 
     def state(self, arena=None) -> List[np.ndarray]:
         self.torch.cuda.synchronize(self.device)

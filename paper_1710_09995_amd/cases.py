@@ -123,17 +123,34 @@ def freestream_velocity(p: Params) -> np.ndarray:
                              math.sin(p.beta)])
 
 
-def centroids(nodes: np.ndarray) -> np.ndarray:
-    """Mean of the 8 corner nodes of every cell: [3, nk, nj, ni]."""
+def centroids(nodes):
+    """Mean of the 8 corner nodes of every cell: [3, nk, nj, ni] (NumPy or torch)."""
     x = nodes
-    return 0.125 * (x[:, :-1, :-1, :-1] + x[:, :-1, :-1, 1:] + x[:, :-1, 1:, :-1]
-                    + x[:, :-1, 1:, 1:] + x[:, 1:, :-1, :-1] + x[:, 1:, :-1, 1:]
-                    + x[:, 1:, 1:, :-1] + x[:, 1:, 1:, 1:])
+    c = x[:, :-1, :-1, :-1] + x[:, :-1, :-1, 1:]
+    c += x[:, :-1, 1:, :-1]
+    c += x[:, :-1, 1:, 1:]
+    c += x[:, 1:, :-1, :-1]
+    c += x[:, 1:, :-1, 1:]
+    c += x[:, 1:, 1:, :-1]
+    c += x[:, 1:, 1:, 1:]
+    c *= 0.125
+    return c
 
 
-def conserved_from(rho, u, v, w, p, gamma) -> np.ndarray:
-    e = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
-    return np.stack([rho, rho * u, rho * v, rho * w, e]).astype(np.float64)
+def conserved_from(rho, u, v, w, p, gamma):
+    """Conserved variables [5, ...] from primitives; u, v, w may be scalars
+    (a uniform velocity).  NumPy, or torch for device-generated inputs."""
+    if isinstance(rho, np.ndarray):
+        q = np.empty((5,) + rho.shape)
+    else:
+        import torch
+        q = torch.empty((5,) + tuple(rho.shape), dtype=torch.float64, device=rho.device)
+    q[0] = rho
+    q[1] = rho * u
+    q[2] = rho * v
+    q[3] = rho * w
+    q[4] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return q
 
 
 def uniform_state(dims, p: Params) -> np.ndarray:
@@ -277,16 +294,38 @@ def bump_ns_case(ni: int = 256, nj: int = 128, nk: int = 128, seed: int = 0, mac
 
 
 def pressure_pulses(C, centres, amp, sigma, par: Params):
-    """Isentropic Gaussian pressure pulses on the uniform stream."""
-    s = np.zeros(C.shape[1:])
+    """Isentropic Gaussian pressure pulses on the uniform stream.
+
+    C: cell centres [3, ...] (NumPy or torch).  A pulse whose exponent exceeds
+    750 at every cell (judged from the box bounding C) contributes exactly
+    0.0 in FP64 (exp underflows), so it is skipped: the sum is bitwise the
+    full one."""
+    xp = _xp(C)
+    s = xp.zeros(C.shape[1:], dtype=C.dtype, **_dev_kw(C))
+    lo = [float(C[a].min()) for a in range(3)]
+    hi = [float(C[a].max()) for a in range(3)]
     for c in centres:
+        d2 = sum(max(0.0, lo[a] - c[a], c[a] - hi[a]) ** 2 for a in range(3))
+        if d2 / (2.0 * sigma * sigma) > 750.0:
+            continue
         r2 = (C[0] - c[0]) ** 2 + (C[1] - c[1]) ** 2 + (C[2] - c[2]) ** 2
-        s = s + np.exp(-r2 / (2.0 * sigma * sigma))
+        s = s + xp.exp(-r2 / (2.0 * sigma * sigma))
     pr = 1.0 + amp * s
     rho = pr ** (1.0 / par.gamma)
     uinf = freestream_velocity(par)
-    one = np.ones_like(pr)
-    return conserved_from(rho, uinf[0] * one, uinf[1] * one, uinf[2] * one, pr, par.gamma)
+    return conserved_from(rho, float(uinf[0]), float(uinf[1]), float(uinf[2]), pr, par.gamma)
+
+
+def _xp(a):
+    """The array module of a (NumPy, or torch for device-generated inputs)."""
+    if isinstance(a, np.ndarray):
+        return np
+    import torch
+    return torch
+
+
+def _dev_kw(a):
+    return {} if isinstance(a, np.ndarray) else {"device": a.device}
 
 
 def batched_euler_case(nblk: int = 64, seed: int = 0, lo: int = 16, hi: int = 161,
@@ -316,18 +355,21 @@ def batched_euler_case(nblk: int = 64, seed: int = 0, lo: int = 16, hi: int = 16
         acc += dims[int(b)][0]
     par = Params(mach=mach, viscous=0, flux_fp32=flux_fp32, cfl=cfl)
     nodes = []
+    w = 2.0 * math.pi / lam
     for b in range(nblk):
         ni, nj, nk = dims[b]
-        I = np.arange(ni + 1) + xoff[b]
-        J = np.arange(nj + 1)
-        K = np.arange(nk + 1)
-        KK, JJ, II = np.meshgrid(K, J, I, indexing="ij")
-        x, y, z = II * h, JJ * h, KK * h
-        w = 2.0 * math.pi / lam
-        X = np.stack([x + A * np.sin(w * y) * np.sin(w * z),
-                      y + A * np.sin(w * x) * np.sin(w * z),
-                      z + A * np.sin(w * x) * np.sin(w * y)])
-        nodes.append(X.astype(np.float64))
+        # x, y, z are each a function of one index; the mapping's sines are
+        # evaluated once per index and broadcast (the same bits as on the
+        # full lattice)
+        x = ((np.arange(ni + 1) + xoff[b]) * h)[None, None, :]
+        y = (np.arange(nj + 1) * h)[None, :, None]
+        z = (np.arange(nk + 1) * h)[:, None, None]
+        sx, sy, sz = np.sin(w * x), np.sin(w * y), np.sin(w * z)
+        X = np.empty((3, nk + 1, nj + 1, ni + 1))
+        X[0] = x + A * sy * sz
+        X[1] = y + A * sx * sz
+        X[2] = z + A * sx * sy
+        nodes.append(X)
     ymax = max(d[1] for d in dims) * h
     zmax = max(d[2] for d in dims) * h
     centres = np.column_stack([rng.uniform(0.0, acc * h, 8), rng.uniform(0.0, ymax, 8),
@@ -444,10 +486,31 @@ def channel_conditions(n: int, seed: int) -> np.ndarray:
     return np.column_stack([rng.uniform(0.5, 0.85, n), rng.uniform(0.02, 0.1, n)])
 
 
+class LazyStates:
+    """Initial states computed block by block when read (device-generated
+    workloads whose states do not all fit in memory at once)."""
+
+    def __init__(self, n, make):
+        self._n = n
+        self._make = make
+
+    def __len__(self):
+        return self._n
+
+    def __getitem__(self, b):
+        if not 0 <= b < self._n:
+            raise IndexError(b)
+        return self._make(b)
+
+    def __iter__(self):
+        return (self._make(b) for b in range(self._n))
+
+
 def paper_share_case(nbx: int = 4, nbz: int = 4, ni: int = 512, nj: int = 512, nk: int = 144,
                      seed: int = 0, mach: float = 0.8, reynolds: float = 1.0e6,
                      flux_fp32: int = 1, viscous: int = 1, amp: float = 0.05,
-                     stretch: float = 2.0, pulses: bool = True, cfl: float = 0.5, log=None) -> Case:
+                     stretch: float = 2.0, pulses: bool = True, cfl: float = 0.5, log=None,
+                     device=None) -> Case:
     """One GPU's share of a large multi-block wall-bounded flow.
 
     nbx x nbz blocks tile x in [0, nbx] and z in [0, nbz], each block one
@@ -457,33 +520,57 @@ def paper_share_case(nbx: int = 4, nbz: int = 4, ni: int = 512, nj: int = 512, n
     outer x and z faces are periodic.  Eight seeded isentropic Gaussian
     pressure pulses (amplitude 1e-2, sigma 0.1) ride on the stream.  log, if
     given, is called with a progress line after every block.
+
+    device (e.g. "cuda:0"): the same recipe evaluated with torch on that
+    device; nodes are device tensors and the initial states a LazyStates
+    (each block's state computed from its nodes when read), so the 604 M
+    cell workload is generated in seconds without host memory.  The device's
+    sin/tanh/exp may round differently from NumPy's, so the two paths agree
+    to rounding, not bitwise; parity tests use the NumPy path for both sides.
     """
     rng = np.random.default_rng(seed)
     par = Params(mach=mach, reynolds=reynolds, viscous=viscous, flux_fp32=flux_fp32, cfl=cfl)
     Lx, Lz = float(nbx), float(nbz)
     centres = np.column_stack([rng.uniform(0.0, Lx, 8), rng.uniform(0.2, 0.8, 8),
                                rng.uniform(0.0, Lz, 8)])
+    if device is not None:
+        import torch
+        xp = torch
+        kw = {"dtype": torch.float64, "device": torch.device(device)}
+    else:
+        xp = np
+        kw = {"dtype": np.float64}
     dims, nodes, q0 = [], [], []
     bid = {}
     for bx in range(nbx):
         for bz in range(nbz):
             bid[(bx, bz)] = len(dims)
-            zz = bz + np.arange(ni + 1) / ni
-            xx = bx + np.arange(nj + 1) / nj
-            eta = np.arange(nk + 1) / nk
-            E, Xg, Zg = np.meshgrid(eta, xx, zz, indexing="ij")
-            yw = amp * np.sin(math.pi * Xg) ** 2 * (0.75 + 0.25 * np.cos(2.0 * math.pi * Zg))
-            t = 1.0 + np.tanh(stretch * (E - 1.0)) / math.tanh(stretch)
+            zz = bz + xp.arange(ni + 1, **kw) / ni
+            xx = bx + xp.arange(nj + 1, **kw) / nj
+            eta = xp.arange(nk + 1, **kw) / nk
+            E, Xg, Zg = xp.meshgrid(eta, xx, zz, indexing="ij")
+            yw = amp * xp.sin(math.pi * Xg) ** 2 * (0.75 + 0.25 * xp.cos(2.0 * math.pi * Zg))
+            t = 1.0 + xp.tanh(stretch * (E - 1.0)) / math.tanh(stretch)
             Y = yw + (1.0 - yw) * t
-            X = np.stack([Xg, Y, Zg]).astype(np.float64)
+            X = xp.stack([Xg, Y, Zg])
+            if device is None:
+                X = X.astype(np.float64, copy=False)
             dims.append((ni, nj, nk))
             nodes.append(X)
-            if pulses:
-                q0.append(pressure_pulses(centroids(X), centres, 1e-2, 0.1, par))
-            else:
-                q0.append(uniform_state((ni, nj, nk), par))
+            if device is None:
+                if pulses:
+                    q0.append(pressure_pulses(centroids(X), centres, 1e-2, 0.1, par))
+                else:
+                    q0.append(uniform_state((ni, nj, nk), par))
             if log:
                 log(f"# block {len(dims)}/{nbx * nbz} generated")
+    if device is not None:
+        def make(b, nodes=nodes):
+            if pulses:
+                return pressure_pulses(centroids(nodes[b]), centres, 1e-2, 0.1, par)
+            import torch
+            return torch.from_numpy(uniform_state((ni, nj, nk), par)).to(nodes[b].device)
+        q0 = LazyStates(len(dims), make)
     conns, bcs = [], []
     for bx in range(nbx):
         for bz in range(nbz):
