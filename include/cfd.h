@@ -312,6 +312,26 @@ cfd_status cfd_wcns5_euler_residual_periodic(const double* q_dev, double* r_dev,
                                             const int32_t n[3], const double h[3], double gamma, double entropy_fix,
                                             double eps, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the residual of
+ * cfd_wcns5_euler_residual_periodic, bitwise the same, with its scratch (the
+ * padded primitives and one direction's face flux) in a static device array
+ * of CFD_WCNS5_NOALLOC_MAX_BYTES bytes that the library holds on every device
+ * it runs on until the process ends.  No workspace argument: the call
+ * allocates nothing and calls no allocating routine.  A block whose
+ * cfd_wcns5_euler_work_bytes() exceeds the maximum (about 90^3 cells) gives
+ * CFD_ENOMEM before any launch.  q_dev, r_dev and the stream must be on the
+ * device current on the calling thread (else CFD_EINVAL).  The array is
+ * overwritten in full by every call (nothing in it has to start at zero), and
+ * all calls on one device share it: calls that overlap in time on one device
+ * (different streams, or threads) race and give undefined results; order
+ * them on one stream.  Other arguments and errors as for
+ * cfd_wcns5_euler_residual_periodic.  Asynchronous on stream. */
+#define CFD_WCNS5_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+cfd_status cfd_wcns5_euler_residual_periodic_noalloc(const double* q_dev, double* r_dev, const int32_t n[3],
+                                                     const double h[3], double gamma, double entropy_fix,
+                                                     double eps, hipStream_t stream);
+
 /* Metrics of one curvilinear block periodic in all three directions, for the
  * geometric conservation law that Section 2.2 requires of the scheme on
  * curvilinear grids (the paper defers the formulas to its reference; this is

@@ -64,7 +64,8 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_mlp_sizes", "cfd_mlp_forward", "cfd_mlp_mse", "cfd_mlp_backward", "cfd_mlp_adam",
            "cfd_mlp_to_bf16", "cfd_mlp_features", "cfd_mlp_targets", "cfd_mlp_to_state",
            "cfd_split_plan", "cfd_split_tables", "cfd_regroup", "cfd_staggered_diff6", "cfd_wcns5_edges",
-           "cfd_wcns5_euler_work_bytes", "cfd_wcns5_euler_residual_periodic", "cfd_wcns5_euler_step_work_bytes",
+           "cfd_wcns5_euler_work_bytes", "cfd_wcns5_euler_residual_periodic",
+           "cfd_wcns5_euler_residual_periodic_noalloc", "cfd_wcns5_euler_step_work_bytes",
            "cfd_wcns5_euler_steps_periodic", "cfd_c4_viscous_work_bytes", "cfd_c4_viscous_add_periodic",
            "cfd_wcns5_metrics_periodic", "cfd_wcns5_euler_residual_curv_periodic",
            "cfd_wcns5_euler_steps_curv_periodic", "cfd_c4_viscous_curv_work_bytes",
@@ -127,6 +128,8 @@ def lib(build_if_missing: bool = True):
     L.cfd_wcns5_euler_work_bytes.argtypes = [i32p, C.POINTER(C.c_size_t)]
     L.cfd_wcns5_euler_residual_periodic.argtypes = [vp, vp, vp, C.c_size_t, i32p, C.POINTER(C.c_double), C.c_double,
                                                     C.c_double, C.c_double, vp]
+    L.cfd_wcns5_euler_residual_periodic_noalloc.argtypes = [vp, vp, i32p, C.POINTER(C.c_double), C.c_double,
+                                                            C.c_double, C.c_double, vp]
     L.cfd_wcns5_euler_step_work_bytes.argtypes = [i32p, C.POINTER(C.c_size_t)]
     L.cfd_c4_viscous_work_bytes.argtypes = [i32p, C.POINTER(C.c_size_t)]
     L.cfd_c4_viscous_add_periodic.argtypes = [vp, vp, vp, C.c_size_t, i32p, C.POINTER(C.c_double), C.c_double,
@@ -319,6 +322,26 @@ def wcns5_euler_residual_periodic(q, h, gamma: float = 1.4, entropy_fix: float =
     _check(lib().cfd_wcns5_euler_residual_periodic(_ptr(q), _ptr(out), _ptr(work), nbytes.value, nn, hh,
                                                    float(gamma), float(entropy_fix), float(eps),
                                                    _stream_handle(torch, stream)))
+    return out
+
+
+def wcns5_euler_residual_periodic_noalloc(q, h, out, gamma: float = 1.4, entropy_fix: float = 0.1,
+                                          eps: float = 1e-6, stream=None):
+    """The residual of wcns5_euler_residual_periodic through the entry point
+    that allocates nothing (cfd_wcns5_euler_residual_periodic_noalloc): its
+    scratch is the library's static device array, so no workspace is passed
+    and `out` (contiguous FP64 CUDA tensor shaped like q) must be given."""
+    import torch
+    if q.dtype != torch.float64 or not q.is_cuda or not q.is_contiguous() or q.dim() != 4 or q.shape[0] != 5:
+        raise ValueError("q must be a contiguous float64 CUDA tensor [5, nk, nj, ni]")
+    if out.shape != q.shape or out.dtype != torch.float64 or not out.is_contiguous() or out.device != q.device:
+        raise ValueError("out must be a contiguous float64 tensor shaped like q on its device")
+    nk, nj, ni = (int(v) for v in q.shape[1:])
+    nn = (C.c_int32 * 3)(ni, nj, nk)
+    hh = (C.c_double * 3)(*[float(v) for v in h])
+    _check(lib().cfd_wcns5_euler_residual_periodic_noalloc(_ptr(q), _ptr(out), nn, hh, float(gamma),
+                                                           float(entropy_fix), float(eps),
+                                                           _stream_handle(torch, stream)))
     return out
 
 

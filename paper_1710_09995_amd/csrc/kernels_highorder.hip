@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -649,6 +650,68 @@ extern "C" cfd_status cfd_wcns5_euler_residual_periodic(const double* q_dev, dou
       if (!(h[d] > 0.0) || !std::isfinite(h[d])) cfd::host_fail(CFD_EINVAL, "spacings must be positive and finite");
     cfd::wcns5_residual_core(q_dev, nullptr, nullptr, r_dev, work_dev, work_bytes, n, h, gamma, entropy_fix, eps,
                              stream);
+  });
+}
+
+// Scratch of cfd_wcns5_euler_residual_periodic_noalloc: every device the
+// library runs on holds its own copy from module load to process end.  In host
+// code the name is only a handle; the device address comes from
+// hipGetSymbolAddress, once per device, and only that address reaches kernels.
+static __device__ __align__(256) double scratch[CFD_WCNS5_NOALLOC_MAX_BYTES / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, which must be the
+// stream's device; looked up on the first call on each device.
+void* scratch_address(hipStream_t stream) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) cfd::host_fail(CFD_EUNSUPPORTED, "device ordinal beyond the scratch table");
+  hipDevice_t sdev = -1;
+  e = hipStreamGetDevice(stream, &sdev);
+  if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("hipStreamGetDevice: ") + hipGetErrorString(e));
+  if (sdev != dev) cfd::host_fail(CFD_EINVAL, "the stream is not on the current device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      cfd::host_fail(CFD_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  return g_scratch_addr[dev];
+}
+
+}  // namespace
+
+extern "C" cfd_status cfd_wcns5_euler_residual_periodic_noalloc(const double* q_dev, double* r_dev,
+                                                                const int32_t n[3], const double h[3], double gamma,
+                                                                double entropy_fix, double eps, hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!q_dev || !r_dev || !n || !h) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    for (int d = 0; d < 3; ++d)
+      if (!(h[d] > 0.0) || !std::isfinite(h[d])) cfd::host_fail(CFD_EINVAL, "spacings must be positive and finite");
+    // at least 80 bytes per cell (padded primitives and face flux): reject
+    // huge extents before the exact count, whose products could overflow
+    double need = 80.0 * (double)n[0] * (double)n[1] * (double)n[2];
+    if (need <= (double)CFD_WCNS5_NOALLOC_MAX_BYTES) {
+      int64_t pmax, fmax;
+      cfd::wcns5_work(n, pmax, fmax);
+      need = 8.0 * ((double)pmax + (double)fmax);
+    }
+    if (need > (double)CFD_WCNS5_NOALLOC_MAX_BYTES)
+      cfd::host_fail(CFD_ENOMEM, "block needs " + std::to_string((long long)need) +
+                                     " bytes of scratch, more than CFD_WCNS5_NOALLOC_MAX_BYTES = " +
+                                     std::to_string((long long)CFD_WCNS5_NOALLOC_MAX_BYTES));
+    void* work = scratch_address(stream);
+    cfd::wcns5_residual_core(q_dev, nullptr, nullptr, r_dev, work, CFD_WCNS5_NOALLOC_MAX_BYTES, n, h, gamma,
+                             entropy_fix, eps, stream);
   });
 }
 
