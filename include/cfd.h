@@ -97,9 +97,12 @@ typedef struct {
 } cfd_params;
 
 /* Tuning knobs of the stage kernels.  Any value changes speed only: the
- * state is bitwise identical across all valid settings; the history's norms
- * and totals are sums in a fixed order that depends on the kernel and tiles,
- * so across settings they agree to rounding (and bitwise run to run).
+ * state is bitwise identical across all valid settings, and so are the
+ * history's time step, max |R_rho| and conserved totals (sum V Q is reduced
+ * over a fixed cut of the grid's 64-cell row chunks that does not depend on
+ * the tiles); the L2 norms of R are sums in an order that depends on the
+ * kernel and tiles, so across settings they agree to rounding (and bitwise
+ * run to run).
  * kernel: 0 = tiled face-once kernel, 1 = simple per-cell kernel,
  *   2 = plane-ring face-once kernel (a ring of three primitive planes in LDS,
  *   two barriers per plane; tile_j = 4 or 8).
@@ -125,17 +128,16 @@ typedef struct { int32_t kernel, tile_j, tile_k, use_graph, order; } cfd_tuning;
 cfd_status cfd_layout(int32_t nblk, const cfd_dims* dims, int32_t ghost_layers,
                       int64_t* block_offset, int64_t* block_strides, int64_t* arena_elems);
 
-/* Bytes of device workspace cfd_create_blocks needs (metrics; for viscous
- * flow also the viscous face metrics, 21 doubles per padded cell; two stage
- * arenas, tables, reduction partials).  Host-only, synchronous. */
+/* Bytes of device workspace cfd_create_blocks needs (metrics, 10 doubles per
+ * padded cell; two stage arenas, tables, reduction partials).  Host-only,
+ * synchronous. */
 cfd_status cfd_workspace_size(const cfd_params* params, int32_t nblk, const cfd_dims* dims,
                               size_t* workspace_bytes);
 
 /* Build a context: validate the tables (every boundary cell face covered
  * exactly once, ranges in bounds, connected extents match), fill ghost
- * nodes, compute face vectors and volumes (metrics) into the workspace
- * (for viscous flow also the face-averaged transverse face vectors and the
- * auxiliary-cell volumes of the face gradients) and build the tile list.  nodes_dev[b] points to block b's node coordinates,
+ * nodes, compute face vectors and volumes (metrics) into the workspace and
+ * build the tile list.  nodes_dev[b] points to block b's node coordinates,
  * FP64 [3][nk+1][nj+1][ni+1], device memory; they may be freed on return.
  * Synchronises `stream` before returning.  On error *out is NULL. */
 cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_dims* dims,

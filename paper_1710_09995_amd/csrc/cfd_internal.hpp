@@ -8,9 +8,6 @@ namespace cfd {
 constexpr int NG = 2;          // ghost layers
 constexpr int NV = 5;          // conserved variables
 constexpr int NM = 10;         // metric components: S_i(3), S_j(3), S_k(3), V
-constexpr int NVM = 21;        // viscous face metrics: per direction d, on the lower d-face,
-                               // the two averaged transverse face vectors (6) and the
-                               // auxiliary-cell volume (1), at index 7 d + ...
 constexpr int NHIST = 12;      // history row: dt, L2(R) x5, sum VQ x5, max|R_rho|
 constexpr int NPART = 13;      // per-workgroup partials: sum R^2 x5, sum VQ x5, max|R_rho|, nonfinite, min dt
 
@@ -27,10 +24,10 @@ struct BlockDesc {
   int64_t qoff;        // state arena: element index of padded cell (-g,-g,-g), var 0
   int64_t moff;        // metrics arena offset (NM vars, same strides)
   int64_t soff;        // scalar arena offset (1 var, same strides)
-  int64_t voff;        // viscous face metric arena offset (NVM vars, same strides)
   int64_t sv, sk, sj;  // element strides of var, k, j (i stride is 1)
   int64_t xoff;        // node scratch: element index of padded node (-g,-g,-g), coord 0
   int64_t xsv, xsk, xsj;
+  int64_t coff;        // row chunks (runs of up to 64 cells along i) of the blocks before this one
 };
 
 // One patch of one sweep (connection or physical boundary), cells or nodes.
@@ -93,7 +90,7 @@ struct StepParams {
 // Arguments of the residual / stage kernels.
 // mode 0 writes R; mode 1 is stage 1: out = Qs - dt R(Qs), and either
 // rout = R(Qs) (for the norms kernel) or, in the plane-ring kernel, the norm
-// partials of R(Qs) and of V Qs per workgroup; mode 2 is stages 2-3:
+// partials of R(Qs) per workgroup; mode 2 is stages 2-3:
 // out = a Qn + b (Qs - dt R(Qs)); mode 3 (plane-ring kernel only) is stage 3
 // plus the CFL time step of the new state (per-workgroup minimum into
 // partials, per-cell steps into dt_out with local stepping).
@@ -105,7 +102,6 @@ struct StageArgs {
   double* partials;   // [gridDim.x][NPART] partials (modes 1 and 3, plane-ring kernel)
   double* dt_out;     // per-cell steps of the new state (mode 3, local stepping)
   const double* met;
-  const double* vmet; // viscous face metrics (viscous flow only)
   const double* dt;   // global dt (1 double) or per-cell scalar arena (local)
   double a, b;
   int32_t local_dt;

@@ -14,10 +14,12 @@
 //   B. after the barrier: the cell update of plane k (its inputs were loaded
 //      before the faces) together with the fill of W(k+2) into the slot of
 //      W(k-1) and the queue load of W(k+3), so their memory latencies overlap.
-// Stage 1 accumulates the norm partials of R(Qn) and V Qn in registers (this
-// kernel has the register room) instead of writing R for a separate norms
-// kernel, and stage 3 (mode 3) evaluates the CFL time step of the state it
-// writes (the next step's), instead of a separate time-step kernel.
+// Stage 1 accumulates the norm partials of R(Qn) in registers (this kernel
+// has the register room) instead of writing R for a separate norms kernel
+// (the totals sum V Qn come from a row-chunk kernel whose cut of the grid
+// does not depend on the tiles), and stage 3 (mode 3) evaluates the CFL time
+// step of the state it writes (the next step's), instead of a separate
+// time-step kernel.
 // The i-face fluxes are exchanged between neighbouring lanes of the wave
 // (shuffle) instead of through LDS; only the tile's edge i-faces and the
 // j-faces go through LDS.  Every face flux gets the same bits as in the
@@ -88,8 +90,8 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
   };
 
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-  // partials: stage 1 (mode 1) sum R^2, sum V Qs, max |R_rho|, non-finite
-  // count; stage 3 (mode 3) minimum time step of the new state
+  // partials: stage 1 (mode 1) sum R^2, max |R_rho|, non-finite count;
+  // stage 3 (mode 3) minimum time step of the new state
   double acc[NPART];
   init_partials(acc);
 
@@ -107,7 +109,6 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
     const bool has_xi = tx < TJ && i0 + 64 <= ni && j0 + tx < nj;  // wave 1: i-faces at column i0+64
     const double* qb = A.qs + B.qoff;
     const double* mb = A.met + B.moff;
-    const double* vb = VISC ? A.vmet + B.voff : nullptr;
     const int64_t sj = B.sj, sk = B.sk, sv = B.sv;
     auto off = [&](int ii, int jj, int kk) -> int64_t {
       return (int64_t)(kk + NG) * sk + (int64_t)(jj + NG) * sj + (ii + NG);
@@ -139,7 +140,7 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
     Prim<T> q3{};
     if (act) {
       const int64_t c0 = off(i, j, k0);
-      face_flux_global<T, VISC>(qb, mb, vb, B, c0, 2, gas, Fklo);
+      face_flux_global<T, VISC>(qb, mb, B, c0, 2, gas, Fklo);
       q3 = ld_prim<T>(qb, c0 + 2 * sk, sv, gas.gm1);
     }
     __syncthreads();   // the previous tile's LDS users are done
@@ -174,7 +175,7 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
           wphi(sp, pj, pi - 1, a); wphi(sp, pj, pi, b); wphi(sm, pj, pi - 1, e); wphi(sm, pj, pi, g);
           tdiff(a, b, e, g, d2);
           double St[2][3], vf;
-          face_vmetrics(vb, sv, c, 0, St, vf);
+          visc_metrics(mb, sv, c - 1, c, 0, sj, sk, St, vf);
           face_viscous<T>(pl, pr, sx, sy, sz, n, d1, d2, St, vf, gas, f);
         }
         scale_flux_f64(f, area, F);
@@ -200,7 +201,7 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
           wphi(sp, pj - 1, pi, a); wphi(sp, pj, pi, b); wphi(sm, pj - 1, pi, e); wphi(sm, pj, pi, g);
           tdiff(a, b, e, g, d2);
           double St[2][3], vf;
-          face_vmetrics(vb, sv, c, 1, St, vf);
+          visc_metrics(mb, sv, c - sj, c, 1, sj, sk, St, vf);
           face_viscous<T>(pl, pr, sx, sy, sz, n, d1, d2, St, vf, gas, f);
         }
         double F[5];
@@ -241,7 +242,7 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
           wphi(s0, pj + 1, pi, a); wphi(sp, pj + 1, pi, b); wphi(s0, pj - 1, pi, e); wphi(sp, pj - 1, pi, g);
           tdiff(a, b, e, g, d2);
           double St[2][3], vf;
-          face_vmetrics(vb, sv, cu, 2, St, vf);
+          visc_metrics(mb, sv, cu - sk, cu, 2, sj, sk, St, vf);
           face_viscous<T>(pl, pr, sx, sy, sz, n, d1, d2, St, vf, gas, f);
         }
         scale_flux_f64(f, area, Fku);
@@ -297,7 +298,6 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
 #pragma unroll
           for (int q = 0; q < 5; ++q) {
             acc[q] += Rc[q] * Rc[q];
-            acc[5 + q] += cin.vol * cin.qv[q];
             if (!finite(Rc[q])) acc[11] += 1.0;
             if (!finite(cin.qv[q])) acc[11] += 1.0;
           }

@@ -36,15 +36,14 @@ __global__ void __launch_bounds__(256) k_stage_simple(StageArgs A, const BlockDe
     const int kend = min(td.k0 + A.tile_k, B.n[2]);
     const double* qb = A.qs + B.qoff;
     const double* mb = A.met + B.moff;
-    const double* vb = VISC ? A.vmet + B.voff : nullptr;
     for (int j = td.j0 + ty; j < min(td.j0 + A.tile_j, B.n[1]); j += nty) {
       if (i >= B.n[0]) break;
       for (int k = td.k0; k < kend; ++k) {
         const int64_t c = (int64_t)(k + NG) * B.sk + (int64_t)(j + NG) * B.sj + (i + NG);
         double Fl[5], Fu[5], D[3][5];
         for (int d = 0; d < 3; ++d) {
-          face_flux_global<T, VISC>(qb, mb, vb, B, c, d, gas, Fl);
-          face_flux_global<T, VISC>(qb, mb, vb, B, c + dstride(d, B.sj, B.sk), d, gas, Fu);
+          face_flux_global<T, VISC>(qb, mb, B, c, d, gas, Fl);
+          face_flux_global<T, VISC>(qb, mb, B, c + dstride(d, B.sj, B.sk), d, gas, Fu);
           for (int q = 0; q < 5; ++q) D[d][q] = Fu[q] - Fl[q];
         }
         finish_cell<MODE>(A, B, c, D[0], D[1], D[2]);
@@ -54,11 +53,11 @@ __global__ void __launch_bounds__(256) k_stage_simple(StageArgs A, const BlockDe
 }
 
 // ------------------------------------------------- row-per-wave reductions
-// The time-step and norms kernels give every wave a contiguous run of 64-cell
-// i-rows of the tile list (rows of a tile: j fastest, then k).  With a grid
-// that is a multiple of 8, workgroup b runs on XCD b % 8 and the runs of one
-// XCD's workgroups are adjacent, so a row's k+1 neighbour is mostly read
-// through the same L2.
+// The time-step and norms kernels give every wave a contiguous run of the
+// grid's 64-cell row chunks (below).  With a grid that is a multiple of 8,
+// workgroup b runs on XCD b % 8 and the runs of one XCD's workgroups are
+// adjacent, so a row's j+1 and k+1 neighbours are mostly read through the
+// same L2.
 __device__ __forceinline__ void wave_rows(int64_t nrows, int64_t& r0, int64_t& r1) {
   const int wpb = blockDim.x >> 6;
   const int nb = gridDim.x, b = blockIdx.x;
@@ -69,6 +68,45 @@ __device__ __forceinline__ void wave_rows(int64_t nrows, int64_t& r0, int64_t& r
   r1 = nrows * (w + 1) / nw;
 }
 
+// The grid's row chunks, numbered block by block and, within a block, i
+// chunk fastest, then j, then k: chunk u of block b (coff[b] <= u < coff[b+1])
+// covers cells i = 64 ic .. 64 ic + 63 of row (j, k).  The time-step and norms
+// kernels cut this numbering alone into contiguous runs per wave, with a grid
+// that depends on the chunk count only, so their per-workgroup partials (and
+// the fixed-order sums of them) do not depend on the stage kernels' tiles.
+__device__ __forceinline__ int block_of_chunk(const BlockDesc* __restrict__ blocks, int nblk, int64_t u) {
+  int lo = 0, hi = nblk - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (blocks[mid].coff <= u) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct ChunkWalk {
+  const BlockDesc* blocks;
+  int nblk, b;
+  BlockDesc B;
+  __device__ void start(const BlockDesc* bl, int nb, int64_t u) {
+    blocks = bl;
+    nblk = nb;
+    b = block_of_chunk(bl, nb, u);
+    B = bl[b];
+  }
+  // cell (i, j, k) of this lane in chunk u (u ascending over calls); false past the row's end
+  __device__ bool cell(int64_t u, int lane, int& i, int& j, int& k) {
+    while (b + 1 < nblk && u >= blocks[b + 1].coff) B = blocks[++b];
+    const int nci = (B.n[0] + 63) >> 6;
+    const int64_t v = u - B.coff;
+    const int64_t row = v / nci;
+    i = (int)(v - row * nci) * 64 + lane;
+    j = (int)(row % B.n[1]);
+    k = (int)(row / B.n[1]);
+    return i < B.n[0];
+  }
+};
+
 // ------------------------------------------------------------- time step
 // dt_c = CFL V / (sum_d L_d + 4 sum_d Lv_d) with S_d averaged over the cell's
 // two d-faces; per-workgroup partials: minimum dt (slot 12), sum V Q
@@ -76,22 +114,19 @@ __device__ __forceinline__ void wave_rows(int64_t nrows, int64_t& r0, int64_t& r
 // stored.
 __global__ void __launch_bounds__(256) k_dt(const double* __restrict__ q, const double* __restrict__ met,
                                             double* __restrict__ dtcell, double* __restrict__ partials,
-                                            const BlockDesc* __restrict__ blocks,
-                                            const TileDesc* __restrict__ tiles, int ntiles, int tile_j,
-                                            int tile_k, StepParams P) {
+                                            const BlockDesc* __restrict__ blocks, int nblk, int64_t nchunks,
+                                            StepParams P) {
   double acc[NPART];
   init_partials(acc);
   const int lane = threadIdx.x & 63;
-  const int rpt = tile_j * tile_k;
   int64_t r0, r1;
-  wave_rows((int64_t)ntiles * rpt, r0, r1);
+  wave_rows(nchunks, r0, r1);
+  ChunkWalk W;
+  if (r0 < r1) W.start(blocks, nblk, r0);
   for (int64_t u = r0; u < r1; ++u) {
-    const int tile = (int)(u / rpt);
-    const int r = (int)(u - (int64_t)tile * rpt);
-    const TileDesc td = tiles[tile];
-    const BlockDesc B = blocks[td.blk];
-    const int i = td.i0 + lane, j = td.j0 + r % tile_j, k = td.k0 + r / tile_j;
-    if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
+    int i, j, k;
+    if (!W.cell(u, lane, i, j, k)) continue;
+    const BlockDesc& B = W.B;
     const double* qb = q + B.qoff;
     const double* mb = met + B.moff;
     const int64_t c = (int64_t)(k + NG) * B.sk + (int64_t)(j + NG) * B.sj + (i + NG);
@@ -112,31 +147,28 @@ __global__ void __launch_bounds__(256) k_dt(const double* __restrict__ q, const 
 // ------------------------------------------------------------- norms
 // Partials of sum R^2 (slots 0-4), max |R_rho| (10) and the non-finite count
 // (11) of r, and of sum V Q (5-9) and the non-finite count of q; either of q
-// (then met too) and r may be null.
+// (then met too) and r may be null.  Same cut of the grid as k_dt, so its
+// sum V Q rows are bitwise k_dt's.
 __global__ void __launch_bounds__(256) k_norms(const double* __restrict__ q, const double* __restrict__ r,
                                                const double* __restrict__ met, double* __restrict__ partials,
-                                               const BlockDesc* __restrict__ blocks,
-                                               const TileDesc* __restrict__ tiles, int ntiles, int tile_j,
-                                               int tile_k) {
+                                               const BlockDesc* __restrict__ blocks, int nblk, int64_t nchunks) {
   double acc[NPART];
   init_partials(acc);
   const int lane = threadIdx.x & 63;
-  const int rpt = tile_j * tile_k;
   int64_t r0, r1;
-  wave_rows((int64_t)ntiles * rpt, r0, r1);
+  wave_rows(nchunks, r0, r1);
+  ChunkWalk W;
+  if (r0 < r1) W.start(blocks, nblk, r0);
   for (int64_t u = r0; u < r1; ++u) {
-    const int tile = (int)(u / rpt);
-    const int rr = (int)(u - (int64_t)tile * rpt);
-    const TileDesc td = tiles[tile];
-    const BlockDesc B = blocks[td.blk];
-    const int i = td.i0 + lane, j = td.j0 + rr % tile_j, k = td.k0 + rr / tile_j;
-    if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
+    int i, j, k;
+    if (!W.cell(u, lane, i, j, k)) continue;
+    const BlockDesc& B = W.B;
     const int64_t c = (int64_t)(k + NG) * B.sk + (int64_t)(j + NG) * B.sj + (i + NG);
     if (q) {
-      const double vol = met[B.moff + 9 * B.sv + c];
       double qv[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) qv[v] = q[B.qoff + v * B.sv + c];
+      const double vol = met[B.moff + 9 * B.sv + c];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         acc[5 + v] += vol * qv[v];
@@ -226,18 +258,14 @@ void launch_stage_simple(const StageArgs& A, int mode, bool visc, bool fp32, con
 #undef CFD_DISPATCH
 }
 
-void launch_dt(const double* q, const double* met, double* dtcell, double* partials,
-               const BlockDesc* blocks, const TileDesc* tiles, int ntiles, int tile_j, int tile_k,
-               const StepParams& P, int nwg, hipStream_t s) {
-  hipLaunchKernelGGL(k_dt, dim3(nwg), dim3(256), 0, s, q, met, dtcell, partials, blocks, tiles, ntiles,
-                     tile_j, tile_k, P);
+void launch_dt(const double* q, const double* met, double* dtcell, double* partials, const BlockDesc* blocks,
+               int nblk, int64_t nchunks, const StepParams& P, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_dt, dim3(nwg), dim3(256), 0, s, q, met, dtcell, partials, blocks, nblk, nchunks, P);
 }
 
-void launch_norms(const double* q, const double* r, const double* met, double* partials,
-                  const BlockDesc* blocks, const TileDesc* tiles, int ntiles, int tile_j, int tile_k,
-                  int nwg, hipStream_t s) {
-  hipLaunchKernelGGL(k_norms, dim3(nwg), dim3(256), 0, s, q, r, met, partials, blocks, tiles, ntiles,
-                     tile_j, tile_k);
+void launch_norms(const double* q, const double* r, const double* met, double* partials, const BlockDesc* blocks,
+                  int nblk, int64_t nchunks, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_norms, dim3(nwg), dim3(256), 0, s, q, r, met, partials, blocks, nblk, nchunks);
 }
 
 void launch_finalize(const double* partials, int nrows, int mode, double inv_ncells, double* dt,

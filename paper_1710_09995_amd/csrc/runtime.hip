@@ -25,7 +25,6 @@ void launch_copy_nodes(const double* src, double* x, const BlockDesc& B, hipStre
 void launch_ghost_nodes(double* x, const BlockDesc* blocks, const PatchDesc* patches, int npatch,
                         int maxcount, hipStream_t s);
 void launch_metrics(const double* x, double* met, const BlockDesc& B, hipStream_t s);
-void launch_visc_metrics(const double* met, double* vmet, const BlockDesc& B, hipStream_t s);
 void launch_metric_ghosts(double* met, const BlockDesc* blocks, const PatchDesc* patches, int npatch,
                           int maxcount, hipStream_t s);
 void launch_ghost_q(double* q, const double* met, const BlockDesc* blocks, const PatchDesc* patches,
@@ -38,12 +37,10 @@ bool stage_tiled(const StageArgs& A, int mode, bool visc, bool fp32, const Block
 void launch_stage_simple(const StageArgs& A, int mode, bool visc, bool fp32, const BlockDesc* blocks,
                          const TileDesc* tiles, const Gas<double>& g64, const Gas<float>& g32, int nwg,
                          hipStream_t s);
-void launch_dt(const double* q, const double* met, double* dtcell, double* partials,
-               const BlockDesc* blocks, const TileDesc* tiles, int ntiles, int tile_j, int tile_k,
-               const StepParams& P, int nwg, hipStream_t s);
-void launch_norms(const double* q, const double* r, const double* met, double* partials,
-                  const BlockDesc* blocks, const TileDesc* tiles, int ntiles, int tile_j, int tile_k,
-                  int nwg, hipStream_t s);
+void launch_dt(const double* q, const double* met, double* dtcell, double* partials, const BlockDesc* blocks,
+               int nblk, int64_t nchunks, const StepParams& P, int nwg, hipStream_t s);
+void launch_norms(const double* q, const double* r, const double* met, double* partials, const BlockDesc* blocks,
+                  int nblk, int64_t nchunks, int nwg, hipStream_t s);
 void mlp_forward(const MlpDims& D, const uint16_t* P, const float* x, const int32_t* idx, int64_t n, float* y,
                  float* cache, hipStream_t s);
 int mlp_mse(const float* y, const float* t, const int32_t* idx, int64_t n, int d_out, float* dy, double* partials,
@@ -95,8 +92,8 @@ struct Err : std::exception {
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-  std::vector<int64_t> qoff, moff, soff, voff, sv, sk, sj, xoff, xsv, xsk, xsj;
-  int64_t q_elems = 0, m_elems = 0, s_elems = 0, v_elems = 0, x_elems = 0;
+  std::vector<int64_t> qoff, moff, soff, sv, sk, sj, xoff, xsv, xsk, xsj;
+  int64_t q_elems = 0, m_elems = 0, s_elems = 0, x_elems = 0;
 };
 
 // Aligned offset so that interior i = 0 (padded index g) sits on 128 bytes.
@@ -119,7 +116,6 @@ Layout make_layout(int nblk, const cfd_dims* dims) {
     L.qoff.push_back(place(L.q_elems, NV, sv));
     L.moff.push_back(place(L.m_elems, NM, sv));
     L.soff.push_back(place(L.s_elems, 1, sv));
-    L.voff.push_back(place(L.v_elems, NVM, sv));
     const int64_t xsj = ni + 1 + 2 * NG, xsk = xsj * (nj + 1 + 2 * NG), xsv = xsk * (nk + 1 + 2 * NG);
     L.xsj.push_back(xsj);
     L.xsk.push_back(xsk);
@@ -130,12 +126,11 @@ Layout make_layout(int nblk, const cfd_dims* dims) {
   L.q_elems = round_up(L.q_elems + 16, 16);
   L.m_elems = round_up(L.m_elems + 16, 16);
   L.s_elems = round_up(L.s_elems + 16, 16);
-  L.v_elems = round_up(L.v_elems + 16, 16);
   return L;
 }
 
 struct WsLayout {
-  size_t met, vmet, qa, qb, scal, blocks, patches, tiles, part_dt, part_nrm, scalars, cell_start, total;
+  size_t met, qa, qb, scal, blocks, patches, tiles, part_dt, part_nrm, scalars, cell_start, total;
   size_t node_scratch;   // aliases qa.. during setup
   int64_t max_tiles;
   int npatch_total;
@@ -150,13 +145,11 @@ int64_t max_tiles_for(int nblk, const cfd_dims* dims) {
   return t;
 }
 
-WsLayout make_ws(const Layout& L, int nblk, const cfd_dims* dims, int npatch_total, bool local_dt, bool viscous) {
+WsLayout make_ws(const Layout& L, int nblk, const cfd_dims* dims, int npatch_total, bool local_dt) {
   WsLayout W{};
   size_t c = 0;
   W.met = c;
   c = align256(c + (size_t)L.m_elems * 8);
-  W.vmet = c;   // viscous face metrics (viscous flow only)
-  if (viscous) c = align256(c + (size_t)L.v_elems * 8);
   W.qa = c;
   c = align256(c + (size_t)L.q_elems * 8);
   W.qb = c;
@@ -333,6 +326,7 @@ struct cfd_ctx {
   TileDesc* dtiles = nullptr;
   int ntiles = 0;
   int64_t ncells = 0;
+  int64_t nchunks = 0;   // 64-cell row chunks of the grid (time-step and norms kernels)
   cfd_tuning tun{2, 8, 32, 1, 1};   // replaced by default_tuning() when the blocks are created
   StepParams SP{};
   Gas<double> g64{};
@@ -384,7 +378,6 @@ struct cfd_ctx {
   }
 
   double* met() const { return reinterpret_cast<double*>(ws + W.met); }
-  double* vmet() const { return reinterpret_cast<double*>(ws + W.vmet); }
   double* qa() const { return reinterpret_cast<double*>(ws + W.qa); }
   double* qb() const { return reinterpret_cast<double*>(ws + W.qb); }
   double* scal() const { return params.local_dt ? reinterpret_cast<double*>(ws + W.scal) : nullptr; }
@@ -518,13 +511,13 @@ int nwg_for(const cfd_ctx* c, int per_cu) {
 }
 
 // Grid of the row-per-wave time-step and norms kernels: 8 four-wave
-// workgroups per CU, capped by the number of 64-cell rows and by half the
-// partials buffer (a step stores both kernels' rows in it, one after the
-// other).
+// workgroups per CU, capped by the number of 64-cell row chunks and by half
+// the partials buffer (a step stores two kernels' rows in it, one after the
+// other).  A function of the grid alone, not of the stage kernels' tiles, so
+// that the sums of V Q these kernels reduce are the same bits for every tuning.
 int dt_nwg(const cfd_ctx* c) {
-  const int64_t rows = (int64_t)c->ntiles * c->tun.tile_j * c->tun.tile_k;
   return (int)std::max<int64_t>(
-      1, std::min<int64_t>({(rows + 3) / 4, (int64_t)NWG_MAX / 2, (int64_t)c->num_cu * 8}));
+      1, std::min<int64_t>({(c->nchunks + 3) / 4, (int64_t)NWG_MAX / 2, (int64_t)c->num_cu * 8}));
 }
 
 // Run a launch; with profiling on, bracket it with a hipEvent pair on its stream.
@@ -552,7 +545,6 @@ void ghost_fill(cfd_ctx* c, double* q, hipStream_t s) {
 StageArgs stage_args(cfd_ctx* c) {
   StageArgs A{};
   A.met = c->met();
-  A.vmet = c->params.viscous ? c->vmet() : nullptr;
   A.local_dt = c->params.local_dt;
   A.dt = c->params.local_dt ? c->scal() : c->d_dt();
   A.ntiles = c->ntiles;
@@ -608,8 +600,7 @@ void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, hipStream_t s) {
 void time_step_pass(cfd_ctx* c, const double* q, hipStream_t s) {
   const int nwg = dt_nwg(c);
   timed(c, 2, s, [&] {
-    launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
-              c->tun.tile_k, c->SP, nwg, s);
+    launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->nblk, c->nchunks, c->SP, nwg, s);
   });
   launch_finalize(c->part_dt(), nwg, 0, 0.0, c->d_dt(), nullptr, nullptr, s);
 }
@@ -624,13 +615,18 @@ bool fused_dt(const cfd_ctx* c) { return c->tun.kernel == 2 && c->params.viscous
 //  - Time step: with fused_dt, left in d_dt (and the per-cell arena) by the
 //    previous step's stage 3, or by the time-step pass cfd_step runs before
 //    its first step; otherwise a time-step pass first (k_dt writes partial
-//    rows [0, nwg) of part_dt: min dt, sum V Q^n).
+//    rows [0, nwg_dt) of part_dt: min dt, sum V Q^n).
 //  - History: the plane-ring kernel's stage 1 reduces the norm partials of
-//    R(Q^n) and V Q^n itself; the other kernels write R(Q^n) to qb (free until
-//    stage 2 overwrites it) and the norms kernel adds the R rows after k_dt's.
+//    R(Q^n) itself; the other kernels write R(Q^n) to qb (free until stage 2
+//    overwrites it) and the norms kernel adds the R rows after k_dt's.
+//  - Totals sum V Q^n: always from rows [0, nwg_dt) of a row-chunk kernel
+//    (k_dt, or with the plane-ring kernel k_norms over Q^n, only when the
+//    step keeps a history), whose cut of the grid does not depend on the
+//    tiles; the rows after them carry zeros in those slots, so the fixed-order
+//    finalize gives the same totals for every tuning and stage kernel.
 // (Taking dt of the new state inside the tiled kernel's third stage was
 // measured slower: its extra metric loads cost more than the separate pass.)
-void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
+void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history) {
   const bool ring = c->tun.kernel == 2;
   const bool fuse = fused_dt(c);
   const double inv_n = 1.0 / (double)c->ncells;
@@ -642,15 +638,20 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s) {
   A.qn = q;
   A.out = c->qa();
   if (ring) {
-    A.partials = c->part_nrm();
+    const int ntot = history ? nwg_dt : 0;
+    if (history)
+      timed(c, 3, s, [&] {
+        launch_norms(q, nullptr, c->met(), c->part_nrm(), c->dblocks, c->nblk, c->nchunks, nwg_dt, s);
+      });
+    A.partials = c->part_nrm() + (int64_t)ntot * NPART;
     launch_stage(c, A, 1, s);
-    launch_finalize(c->part_nrm(), stage_nwg(c, 1), 1, inv_n, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
+    launch_finalize(c->part_nrm(), ntot + stage_nwg(c, 1), 1, inv_n, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
   } else {
     A.rout = c->qb();
     launch_stage(c, A, 1, s);
     timed(c, 3, s, [&] {
-      launch_norms(nullptr, c->qb(), nullptr, c->part_dt() + (int64_t)nwg_dt * NPART, c->dblocks, c->dtiles,
-                   c->ntiles, c->tun.tile_j, c->tun.tile_k, nwg_dt, s);
+      launch_norms(nullptr, c->qb(), nullptr, c->part_dt() + (int64_t)nwg_dt * NPART, c->dblocks, c->nblk,
+                   c->nchunks, nwg_dt, s);
     });
     launch_finalize(c->part_dt(), 2 * nwg_dt, 1, inv_n, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
   }
@@ -752,7 +753,7 @@ cfd_status cfd_workspace_size(const cfd_params* params, int32_t nblk, const cfd_
     Layout L = make_layout(nblk, dims);
     // patch count is bounded by 6 faces x a generous number of patches; the
     // exact count is only known with the tables, so reserve for 64 per face.
-    WsLayout W = make_ws(L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0, params->viscous != 0);
+    WsLayout W = make_ws(L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0);
     *workspace_bytes = W.total;
   });
 }
@@ -782,11 +783,11 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
     c->L = make_layout(nblk, dims);
     size_t need = 0;
     {
-      WsLayout Wfull = make_ws(c->L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0, params->viscous != 0);
+      WsLayout Wfull = make_ws(c->L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0);
       need = Wfull.total;
     }
     if (workspace_bytes < need) fail(CFD_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    c->W = make_ws(c->L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0, params->viscous != 0);
+    c->W = make_ws(c->L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0);
     c->ws = static_cast<char*>(workspace_dev);
     c->dblocks = reinterpret_cast<BlockDesc*>(c->ws + c->W.blocks);
     c->dpatches = reinterpret_cast<PatchDesc*>(c->ws + c->W.patches);
@@ -800,7 +801,6 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
       B.qoff = c->L.qoff[b];
       B.moff = c->L.moff[b];
       B.soff = c->L.soff[b];
-      B.voff = c->L.voff[b];
       B.sv = c->L.sv[b];
       B.sk = c->L.sk[b];
       B.sj = c->L.sj[b];
@@ -808,6 +808,8 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
       B.xsv = c->L.xsv[b];
       B.xsk = c->L.xsk[b];
       B.xsj = c->L.xsj[b];
+      B.coff = c->nchunks;
+      c->nchunks += (int64_t)((dims[b].ni + 63) / 64) * dims[b].nj * dims[b].nk;
       c->hblocks.push_back(B);
       c->ncells += (int64_t)dims[b].ni * dims[b].nj * dims[b].nk;
     }
@@ -834,7 +836,6 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
     if (!all.empty())
       HIPCHK(hipMemcpyAsync(c->dpatches, all.data(), sizeof(PatchDesc) * all.size(), hipMemcpyHostToDevice, stream));
     // setup pipeline: padded nodes -> ghost nodes -> metrics -> metric ghosts
-    // (-> viscous face metrics)
     double* x = reinterpret_cast<double*>(c->ws + c->W.node_scratch);
     for (int b = 0; b < nblk; ++b) launch_copy_nodes(nodes_dev[b], x, c->hblocks[b], stream);
     check_launch();
@@ -847,10 +848,6 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
       launch_metric_ghosts(c->met(), c->dblocks, c->dpatches + c->poff[3 + d], c->pcount[3 + d], c->pmax[3 + d],
                            stream);
     check_launch();
-    if (params->viscous) {
-      for (int b = 0; b < nblk; ++b) launch_visc_metrics(c->met(), c->vmet(), c->hblocks[b], stream);
-      check_launch();
-    }
     HIPCHK(hipStreamSynchronize(stream));
     {
       std::vector<int64_t> cs(nblk + 1, 0);
@@ -964,8 +961,7 @@ cfd_status cfd_time_step(cfd_ctx* c, const double* q, double* dt_dev, hipStream_
   return guard(c, [&] {
     if (!c || !q || !dt_dev) fail(CFD_EINVAL, "NULL argument");
     const int nwg = dt_nwg(c);
-    launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j,
-              c->tun.tile_k, c->SP, nwg, s);
+    launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->nblk, c->nchunks, c->SP, nwg, s);
     launch_finalize(c->part_dt(), nwg, 0, 0.0, dt_dev, nullptr, nullptr, s);
     check_launch();
   });
@@ -983,10 +979,12 @@ cfd_status cfd_step(cfd_ctx* c, double* q, int32_t nsteps, double* hist, hipStre
         c->drop_graph();
         c->graph_q = q;
       }
-      auto capture = [&](int steps, hipGraph_t& g, hipGraphExec_t& ge) {
+      // the one-step graph keeps the history (totals pass included); the
+      // multi-step graph serves runs without one
+      auto capture = [&](int steps, bool history, hipGraph_t& g, hipGraphExec_t& ge) {
         HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         try {
-          for (int n = 0; n < steps; ++n) enqueue_step(c, q, c->cap_stream);
+          for (int n = 0; n < steps; ++n) enqueue_step(c, q, c->cap_stream, history);
         } catch (...) {
           hipGraph_t gg = nullptr;
           hipStreamEndCapture(c->cap_stream, &gg);
@@ -998,11 +996,11 @@ cfd_status cfd_step(cfd_ctx* c, double* q, int32_t nsteps, double* hist, hipStre
       };
       int n0 = 0;
       if (!hist && nsteps >= cfd_ctx::STEPS_PER_GRAPH) {
-        if (!c->gexec_n) capture(cfd_ctx::STEPS_PER_GRAPH, c->graph_n, c->gexec_n);
+        if (!c->gexec_n) capture(cfd_ctx::STEPS_PER_GRAPH, false, c->graph_n, c->gexec_n);
         for (; n0 + cfd_ctx::STEPS_PER_GRAPH <= nsteps; n0 += cfd_ctx::STEPS_PER_GRAPH)
           HIPCHK(hipGraphLaunch(c->gexec_n, s));
       }
-      if (n0 < nsteps && !c->gexec) capture(1, c->graph, c->gexec);
+      if (n0 < nsteps && !c->gexec) capture(1, true, c->graph, c->gexec);
       for (int n = n0; n < nsteps; ++n) {
         HIPCHK(hipGraphLaunch(c->gexec, s));
         if (hist)
@@ -1011,7 +1009,7 @@ cfd_status cfd_step(cfd_ctx* c, double* q, int32_t nsteps, double* hist, hipStre
       }
     } else {
       for (int n = 0; n < nsteps; ++n) {
-        enqueue_step(c, q, s);
+        enqueue_step(c, q, s, hist != nullptr);
         check_launch();
         if (hist)
           HIPCHK(hipMemcpyAsync(hist + (int64_t)n * NHIST, c->d_hist(), sizeof(double) * NHIST,
@@ -1025,8 +1023,7 @@ cfd_status cfd_norms(cfd_ctx* c, const double* q, const double* r, double* out, 
   cfd_status st = guard(c, [&] {
     if (!c || !q || !out) fail(CFD_EINVAL, "NULL argument");
     const int nwg = dt_nwg(c);
-    launch_norms(q, r, c->met(), c->part_nrm(), c->dblocks, c->dtiles, c->ntiles, c->tun.tile_j, c->tun.tile_k,
-                 nwg, s);
+    launch_norms(q, r, c->met(), c->part_nrm(), c->dblocks, c->nblk, c->nchunks, nwg, s);
     // history row layout: [dt, L2 x5, VQ x5, max]; norms output drops dt
     launch_finalize(c->part_nrm(), nwg, 1, 1.0 / (double)c->ncells, nullptr, c->d_norms(), c->d_nonfinite(), s);
     check_launch();
