@@ -128,16 +128,17 @@ typedef struct { int32_t kernel, tile_j, tile_k, use_graph, order; } cfd_tuning;
 cfd_status cfd_layout(int32_t nblk, const cfd_dims* dims, int32_t ghost_layers,
                       int64_t* block_offset, int64_t* block_strides, int64_t* arena_elems);
 
-/* Bytes of device workspace cfd_create_blocks needs (metrics, 10 doubles per
- * padded cell; two stage arenas, tables, reduction partials).  Host-only,
- * synchronous. */
+/* Bytes of device workspace cfd_create_blocks needs (metrics; for viscous
+ * flow also the viscous face metrics, 21 doubles per padded cell; two stage
+ * arenas, tables, reduction partials).  Host-only, synchronous. */
 cfd_status cfd_workspace_size(const cfd_params* params, int32_t nblk, const cfd_dims* dims,
                               size_t* workspace_bytes);
 
 /* Build a context: validate the tables (every boundary cell face covered
  * exactly once, ranges in bounds, connected extents match), fill ghost
- * nodes, compute face vectors and volumes (metrics) into the workspace and
- * build the tile list.  nodes_dev[b] points to block b's node coordinates,
+ * nodes, compute face vectors and volumes (metrics) into the workspace
+ * (for viscous flow also the face-averaged transverse face vectors and the
+ * auxiliary-cell volumes of the face gradients) and build the tile list.  nodes_dev[b] points to block b's node coordinates,
  * FP64 [3][nk+1][nj+1][ni+1], device memory; they may be freed on return.
  * Synchronises `stream` before returning.  On error *out is NULL. */
 cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_dims* dims,

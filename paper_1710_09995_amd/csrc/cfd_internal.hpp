@@ -8,6 +8,9 @@ namespace cfd {
 constexpr int NG = 2;          // ghost layers
 constexpr int NV = 5;          // conserved variables
 constexpr int NM = 10;         // metric components: S_i(3), S_j(3), S_k(3), V
+constexpr int NVM = 21;        // viscous face metrics: per direction d, on the lower d-face,
+                               // the two averaged transverse face vectors (6) and the
+                               // auxiliary-cell volume (1), at index 7 d + ...
 constexpr int NHIST = 12;      // history row: dt, L2(R) x5, sum VQ x5, max|R_rho|
 constexpr int NPART = 13;      // per-workgroup partials: sum R^2 x5, sum VQ x5, max|R_rho|, nonfinite, min dt
 
@@ -24,6 +27,7 @@ struct BlockDesc {
   int64_t qoff;        // state arena: element index of padded cell (-g,-g,-g), var 0
   int64_t moff;        // metrics arena offset (NM vars, same strides)
   int64_t soff;        // scalar arena offset (1 var, same strides)
+  int64_t voff;        // viscous face metric arena offset (NVM vars, same strides)
   int64_t sv, sk, sj;  // element strides of var, k, j (i stride is 1)
   int64_t xoff;        // node scratch: element index of padded node (-g,-g,-g), coord 0
   int64_t xsv, xsk, xsj;
@@ -102,6 +106,7 @@ struct StageArgs {
   double* partials;   // [gridDim.x][NPART] partials (modes 1 and 3, plane-ring kernel)
   double* dt_out;     // per-cell steps of the new state (mode 3, local stepping)
   const double* met;
+  const double* vmet; // viscous face metrics (viscous flow only)
   const double* dt;   // global dt (1 double) or per-cell scalar arena (local)
   double a, b;
   int32_t local_dt;

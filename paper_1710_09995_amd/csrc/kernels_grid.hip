@@ -281,7 +281,33 @@ __global__ void k_ghost_q(double* __restrict__ q, const double* __restrict__ met
   for (int m = 1; m <= NG; ++m) wall(wv[m - 1], pos3(d, side == 0 ? -m : n - 1 + m, p1, p2, B.sj, B.sk));
 }
 
+// Viscous face metrics of one block: for every cell position (i, j, k) in
+// [0, n]^3 and direction d, the terms of its lower d-face (see visc_metrics).
+__global__ void k_visc_metrics(const double* __restrict__ met, double* __restrict__ vmet, BlockDesc B) {
+  const int64_t wi = B.n[0] + 1, wj = B.n[1] + 1, total = wi * wj * (B.n[2] + 1);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % wi), j = (int)((t / wi) % wj), k = (int)(t / (wi * wj));
+    const int64_t c = (int64_t)(k + NG) * B.sk + (int64_t)(j + NG) * B.sj + (i + NG);
+    const double* mb = met + B.moff;
+    double* vb = vmet + B.voff;
+    for (int d = 0; d < 3; ++d) {
+      double St[2][3], vf;
+      visc_metrics(mb, B.sv, c - dstride(d, B.sj, B.sk), c, d, B.sj, B.sk, St, vf);
+      for (int u = 0; u < 2; ++u)
+        for (int x = 0; x < 3; ++x) vb[(int64_t)(7 * d + 3 * u + x) * B.sv + c] = St[u][x];
+      vb[(int64_t)(7 * d + 6) * B.sv + c] = vf;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
+
+void launch_visc_metrics(const double* met, double* vmet, const BlockDesc& B, hipStream_t s) {
+  const int64_t total = (int64_t)(B.n[0] + 1) * (B.n[1] + 1) * (B.n[2] + 1);
+  int64_t nb = (total + 255) / 256;
+  if (nb > 65535) nb = 65535;
+  hipLaunchKernelGGL(k_visc_metrics, dim3((unsigned)nb), dim3(256), 0, s, met, vmet, B);
+}
 
 void launch_copy_nodes(const double* src, double* x, const BlockDesc& B, hipStream_t s) {
   const int64_t total = (int64_t)3 * (B.n[0] + 1) * (B.n[1] + 1) * (B.n[2] + 1);

@@ -109,6 +109,7 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
     const bool has_xi = tx < TJ && i0 + 64 <= ni && j0 + tx < nj;  // wave 1: i-faces at column i0+64
     const double* qb = A.qs + B.qoff;
     const double* mb = A.met + B.moff;
+    const double* vb = VISC ? A.vmet + B.voff : nullptr;
     const int64_t sj = B.sj, sk = B.sk, sv = B.sv;
     auto off = [&](int ii, int jj, int kk) -> int64_t {
       return (int64_t)(kk + NG) * sk + (int64_t)(jj + NG) * sj + (ii + NG);
@@ -140,7 +141,7 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
     Prim<T> q3{};
     if (act) {
       const int64_t c0 = off(i, j, k0);
-      face_flux_global<T, VISC>(qb, mb, B, c0, 2, gas, Fklo);
+      face_flux_global<T, VISC>(qb, mb, vb, B, c0, 2, gas, Fklo);
       q3 = ld_prim<T>(qb, c0 + 2 * sk, sv, gas.gm1);
     }
     __syncthreads();   // the previous tile's LDS users are done
@@ -175,7 +176,7 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
           wphi(sp, pj, pi - 1, a); wphi(sp, pj, pi, b); wphi(sm, pj, pi - 1, e); wphi(sm, pj, pi, g);
           tdiff(a, b, e, g, d2);
           double St[2][3], vf;
-          visc_metrics(mb, sv, c - 1, c, 0, sj, sk, St, vf);
+          face_vmetrics(vb, sv, c, 0, St, vf);
           face_viscous<T>(pl, pr, sx, sy, sz, n, d1, d2, St, vf, gas, f);
         }
         scale_flux_f64(f, area, F);
@@ -201,7 +202,7 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
           wphi(sp, pj - 1, pi, a); wphi(sp, pj, pi, b); wphi(sm, pj - 1, pi, e); wphi(sm, pj, pi, g);
           tdiff(a, b, e, g, d2);
           double St[2][3], vf;
-          visc_metrics(mb, sv, c - sj, c, 1, sj, sk, St, vf);
+          face_vmetrics(vb, sv, c, 1, St, vf);
           face_viscous<T>(pl, pr, sx, sy, sz, n, d1, d2, St, vf, gas, f);
         }
         double F[5];
@@ -242,7 +243,7 @@ __global__ void __launch_bounds__(64 * TJ, (ring_min_waves<T, VISC>())) k_stage_
           wphi(s0, pj + 1, pi, a); wphi(sp, pj + 1, pi, b); wphi(s0, pj - 1, pi, e); wphi(sp, pj - 1, pi, g);
           tdiff(a, b, e, g, d2);
           double St[2][3], vf;
-          visc_metrics(mb, sv, cu - sk, cu, 2, sj, sk, St, vf);
+          face_vmetrics(vb, sv, cu, 2, St, vf);
           face_viscous<T>(pl, pr, sx, sy, sz, n, d1, d2, St, vf, gas, f);
         }
         scale_flux_f64(f, area, Fku);

@@ -36,14 +36,15 @@ __global__ void __launch_bounds__(256) k_stage_simple(StageArgs A, const BlockDe
     const int kend = min(td.k0 + A.tile_k, B.n[2]);
     const double* qb = A.qs + B.qoff;
     const double* mb = A.met + B.moff;
+    const double* vb = VISC ? A.vmet + B.voff : nullptr;
     for (int j = td.j0 + ty; j < min(td.j0 + A.tile_j, B.n[1]); j += nty) {
       if (i >= B.n[0]) break;
       for (int k = td.k0; k < kend; ++k) {
         const int64_t c = (int64_t)(k + NG) * B.sk + (int64_t)(j + NG) * B.sj + (i + NG);
         double Fl[5], Fu[5], D[3][5];
         for (int d = 0; d < 3; ++d) {
-          face_flux_global<T, VISC>(qb, mb, B, c, d, gas, Fl);
-          face_flux_global<T, VISC>(qb, mb, B, c + dstride(d, B.sj, B.sk), d, gas, Fu);
+          face_flux_global<T, VISC>(qb, mb, vb, B, c, d, gas, Fl);
+          face_flux_global<T, VISC>(qb, mb, vb, B, c + dstride(d, B.sj, B.sk), d, gas, Fu);
           for (int q = 0; q < 5; ++q) D[d][q] = Fu[q] - Fl[q];
         }
         finish_cell<MODE>(A, B, c, D[0], D[1], D[2]);

@@ -112,6 +112,7 @@ __global__ void CFD_TILED_BOUNDS(64 * TJ) k_stage_tiled(StageArgs A, const Block
     const bool has_xi = tx < TJ && i0 + 64 <= ni && j0 + tx < nj;
     const double* qb = A.qs + B.qoff;
     const double* mb = A.met + B.moff;
+    const double* vb = VISC ? A.vmet + B.voff : nullptr;
     const int64_t sj = B.sj, sk = B.sk, sv = B.sv;
     auto off = [&](int ii, int jj, int kk) -> int64_t {
       return (int64_t)(kk + NG) * sk + (int64_t)(jj + NG) * sj + (ii + NG);
@@ -122,7 +123,7 @@ __global__ void CFD_TILED_BOUNDS(64 * TJ) k_stage_tiled(StageArgs A, const Block
     double Fklo[5] = {0, 0, 0, 0, 0};
     if (act) {
       const int64_t c0 = off(i, j, k0);
-      face_flux_global<T, VISC>(qb, mb, B, c0, 2, gas, Fklo);
+      face_flux_global<T, VISC>(qb, mb, vb, B, c0, 2, gas, Fklo);
       q0 = ld_prim<T>(qb, c0 - sk, sv, gas.gm1);
       q1 = ld_prim<T>(qb, c0, sv, gas.gm1);
       q2 = ld_prim<T>(qb, c0 + sk, sv, gas.gm1);
@@ -178,7 +179,7 @@ __global__ void CFD_TILED_BOUNDS(64 * TJ) k_stage_tiled(StageArgs A, const Block
           pphi(sPp, qj, qi - 1, a); pphi(sPp, qj, qi, b); pphi(sPm, qj, qi - 1, e); pphi(sPm, qj, qi, g);
           tdiff(a, b, e, g, d2);
           double St[2][3], vf;
-          visc_metrics(mb, sv, c - 1, c, 0, sj, sk, St, vf);
+          face_vmetrics(vb, sv, c, 0, St, vf);
           face_viscous<T>(pl, pr, sx, sy, sz, n, d1, d2, St, vf, gas, f);
         }
         double F[5];
@@ -201,7 +202,7 @@ __global__ void CFD_TILED_BOUNDS(64 * TJ) k_stage_tiled(StageArgs A, const Block
           pphi(sPp, qj - 1, qi, a); pphi(sPp, qj, qi, b); pphi(sPm, qj - 1, qi, e); pphi(sPm, qj, qi, g);
           tdiff(a, b, e, g, d2);
           double St[2][3], vf;
-          visc_metrics(mb, sv, c - sj, c, 1, sj, sk, St, vf);
+          face_vmetrics(vb, sv, c, 1, St, vf);
           face_viscous<T>(pl, pr, sx, sy, sz, n, d1, d2, St, vf, gas, f);
         }
         double F[5];
@@ -231,7 +232,7 @@ __global__ void CFD_TILED_BOUNDS(64 * TJ) k_stage_tiled(StageArgs A, const Block
           wphi(pj + 1, pi, a); pphi(sPp, qj + 1, qi, b); wphi(pj - 1, pi, e); pphi(sPp, qj - 1, qi, g);
           tdiff(a, b, e, g, d2);
           double St[2][3], vf;
-          visc_metrics(mb, sv, cu - sk, cu, 2, sj, sk, St, vf);
+          face_vmetrics(vb, sv, cu, 2, St, vf);
           face_viscous<T>(pl, pr, sx, sy, sz, n, d1, d2, St, vf, gas, f);
         }
         scale_flux_f64(f, area, Fku);

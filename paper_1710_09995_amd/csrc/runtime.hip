@@ -25,6 +25,7 @@ void launch_copy_nodes(const double* src, double* x, const BlockDesc& B, hipStre
 void launch_ghost_nodes(double* x, const BlockDesc* blocks, const PatchDesc* patches, int npatch,
                         int maxcount, hipStream_t s);
 void launch_metrics(const double* x, double* met, const BlockDesc& B, hipStream_t s);
+void launch_visc_metrics(const double* met, double* vmet, const BlockDesc& B, hipStream_t s);
 void launch_metric_ghosts(double* met, const BlockDesc* blocks, const PatchDesc* patches, int npatch,
                           int maxcount, hipStream_t s);
 void launch_ghost_q(double* q, const double* met, const BlockDesc* blocks, const PatchDesc* patches,
@@ -92,8 +93,8 @@ struct Err : std::exception {
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-  std::vector<int64_t> qoff, moff, soff, sv, sk, sj, xoff, xsv, xsk, xsj;
-  int64_t q_elems = 0, m_elems = 0, s_elems = 0, x_elems = 0;
+  std::vector<int64_t> qoff, moff, soff, voff, sv, sk, sj, xoff, xsv, xsk, xsj;
+  int64_t q_elems = 0, m_elems = 0, s_elems = 0, v_elems = 0, x_elems = 0;
 };
 
 // Aligned offset so that interior i = 0 (padded index g) sits on 128 bytes.
@@ -116,6 +117,7 @@ Layout make_layout(int nblk, const cfd_dims* dims) {
     L.qoff.push_back(place(L.q_elems, NV, sv));
     L.moff.push_back(place(L.m_elems, NM, sv));
     L.soff.push_back(place(L.s_elems, 1, sv));
+    L.voff.push_back(place(L.v_elems, NVM, sv));
     const int64_t xsj = ni + 1 + 2 * NG, xsk = xsj * (nj + 1 + 2 * NG), xsv = xsk * (nk + 1 + 2 * NG);
     L.xsj.push_back(xsj);
     L.xsk.push_back(xsk);
@@ -126,11 +128,12 @@ Layout make_layout(int nblk, const cfd_dims* dims) {
   L.q_elems = round_up(L.q_elems + 16, 16);
   L.m_elems = round_up(L.m_elems + 16, 16);
   L.s_elems = round_up(L.s_elems + 16, 16);
+  L.v_elems = round_up(L.v_elems + 16, 16);
   return L;
 }
 
 struct WsLayout {
-  size_t met, qa, qb, scal, blocks, patches, tiles, part_dt, part_nrm, scalars, cell_start, total;
+  size_t met, vmet, qa, qb, scal, blocks, patches, tiles, part_dt, part_nrm, scalars, cell_start, total;
   size_t node_scratch;   // aliases qa.. during setup
   int64_t max_tiles;
   int npatch_total;
@@ -145,11 +148,13 @@ int64_t max_tiles_for(int nblk, const cfd_dims* dims) {
   return t;
 }
 
-WsLayout make_ws(const Layout& L, int nblk, const cfd_dims* dims, int npatch_total, bool local_dt) {
+WsLayout make_ws(const Layout& L, int nblk, const cfd_dims* dims, int npatch_total, bool local_dt, bool viscous) {
   WsLayout W{};
   size_t c = 0;
   W.met = c;
   c = align256(c + (size_t)L.m_elems * 8);
+  W.vmet = c;   // viscous face metrics (viscous flow only)
+  if (viscous) c = align256(c + (size_t)L.v_elems * 8);
   W.qa = c;
   c = align256(c + (size_t)L.q_elems * 8);
   W.qb = c;
@@ -378,6 +383,7 @@ struct cfd_ctx {
   }
 
   double* met() const { return reinterpret_cast<double*>(ws + W.met); }
+  double* vmet() const { return reinterpret_cast<double*>(ws + W.vmet); }
   double* qa() const { return reinterpret_cast<double*>(ws + W.qa); }
   double* qb() const { return reinterpret_cast<double*>(ws + W.qb); }
   double* scal() const { return params.local_dt ? reinterpret_cast<double*>(ws + W.scal) : nullptr; }
@@ -545,6 +551,7 @@ void ghost_fill(cfd_ctx* c, double* q, hipStream_t s) {
 StageArgs stage_args(cfd_ctx* c) {
   StageArgs A{};
   A.met = c->met();
+  A.vmet = c->params.viscous ? c->vmet() : nullptr;
   A.local_dt = c->params.local_dt;
   A.dt = c->params.local_dt ? c->scal() : c->d_dt();
   A.ntiles = c->ntiles;
@@ -753,7 +760,7 @@ cfd_status cfd_workspace_size(const cfd_params* params, int32_t nblk, const cfd_
     Layout L = make_layout(nblk, dims);
     // patch count is bounded by 6 faces x a generous number of patches; the
     // exact count is only known with the tables, so reserve for 64 per face.
-    WsLayout W = make_ws(L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0);
+    WsLayout W = make_ws(L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0, params->viscous != 0);
     *workspace_bytes = W.total;
   });
 }
@@ -783,11 +790,11 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
     c->L = make_layout(nblk, dims);
     size_t need = 0;
     {
-      WsLayout Wfull = make_ws(c->L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0);
+      WsLayout Wfull = make_ws(c->L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0, params->viscous != 0);
       need = Wfull.total;
     }
     if (workspace_bytes < need) fail(CFD_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    c->W = make_ws(c->L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0);
+    c->W = make_ws(c->L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0, params->viscous != 0);
     c->ws = static_cast<char*>(workspace_dev);
     c->dblocks = reinterpret_cast<BlockDesc*>(c->ws + c->W.blocks);
     c->dpatches = reinterpret_cast<PatchDesc*>(c->ws + c->W.patches);
@@ -801,6 +808,7 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
       B.qoff = c->L.qoff[b];
       B.moff = c->L.moff[b];
       B.soff = c->L.soff[b];
+      B.voff = c->L.voff[b];
       B.sv = c->L.sv[b];
       B.sk = c->L.sk[b];
       B.sj = c->L.sj[b];
@@ -836,6 +844,7 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
     if (!all.empty())
       HIPCHK(hipMemcpyAsync(c->dpatches, all.data(), sizeof(PatchDesc) * all.size(), hipMemcpyHostToDevice, stream));
     // setup pipeline: padded nodes -> ghost nodes -> metrics -> metric ghosts
+    // (-> viscous face metrics)
     double* x = reinterpret_cast<double*>(c->ws + c->W.node_scratch);
     for (int b = 0; b < nblk; ++b) launch_copy_nodes(nodes_dev[b], x, c->hblocks[b], stream);
     check_launch();
@@ -848,6 +857,10 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
       launch_metric_ghosts(c->met(), c->dblocks, c->dpatches + c->poff[3 + d], c->pcount[3 + d], c->pmax[3 + d],
                            stream);
     check_launch();
+    if (params->viscous) {
+      for (int b = 0; b < nblk; ++b) launch_visc_metrics(c->met(), c->vmet(), c->hblocks[b], stream);
+      check_launch();
+    }
     HIPCHK(hipStreamSynchronize(stream));
     {
       std::vector<int64_t> cs(nblk + 1, 0);

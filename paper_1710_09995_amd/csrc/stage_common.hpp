@@ -47,10 +47,9 @@ __device__ __forceinline__ void tdiff(const T a[4], const T b[4], const T e[4], 
 
 // Metric terms of the viscous face between cells cl (L) and c (R) in
 // direction d: averaged transverse face vectors (ascending transverse order)
-// and the auxiliary volume, from the face vectors and volumes of the four
-// cells around the face's auxiliary cell.  The stage kernels form them where
-// they need them (the loads mostly hit in cache: they are the neighbouring
-// cells' own metrics), so no per-face copy of them streams from memory.
+// and the auxiliary volume.  The grid is fixed, so these are evaluated once,
+// when the blocks are created, into the viscous face metric arena; the stage
+// kernels read them back with face_vmetrics (the same bits).
 __device__ __forceinline__ void visc_metrics(const double* __restrict__ mb, int64_t sv, int64_t cl, int64_t c,
                                              int d, int64_t sj, int64_t sk, double St[2][3], double& vf) {
   int tt = 0;
@@ -66,6 +65,16 @@ __device__ __forceinline__ void visc_metrics(const double* __restrict__ mb, int6
     ++tt;
   }
   vf = 0.5 * (mb[9 * sv + cl] + mb[9 * sv + c]);
+}
+
+// Viscous metric terms of the lower d-face of cell c, from the arena vb.
+__device__ __forceinline__ void face_vmetrics(const double* __restrict__ vb, int64_t sv, int64_t c, int d,
+                                              double St[2][3], double& vf) {
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int x = 0; x < 3; ++x) St[u][x] = vb[(int64_t)(7 * d + 3 * u + x) * sv + c];
+  vf = vb[(int64_t)(7 * d + 6) * sv + c];
 }
 
 // Inviscid part of one face: MUSCL states from cells c-2, c-1 (L), c (R),
@@ -126,8 +135,8 @@ __device__ __forceinline__ void scale_flux_f64(const float f[5], double area, do
 // read from global memory.
 template <typename T, bool VISC>
 __device__ __forceinline__ void face_flux_global(const double* __restrict__ qb, const double* __restrict__ mb,
-                                                 const BlockDesc& B, int64_t c, int d, const Gas<T>& gas,
-                                                 double F[5]) {
+                                                 const double* __restrict__ vb, const BlockDesc& B, int64_t c,
+                                                 int d, const Gas<T>& gas, double F[5]) {
   const int64_t sd = dstride(d, B.sj, B.sk);
   const int64_t sv = B.sv;
   const double sx = mb[(3 * d) * sv + c], sy = mb[(3 * d + 1) * sv + c], sz = mb[(3 * d + 2) * sv + c];
@@ -166,7 +175,7 @@ __device__ __forceinline__ void face_flux_global(const double* __restrict__ qb, 
       ++tt;
     }
     double St[2][3], vf;
-    visc_metrics(mb, sv, cl, c, d, B.sj, B.sk, St, vf);
+    face_vmetrics(vb, sv, c, d, St, vf);
     face_viscous<T>(pl, pr, sx, sy, sz, n, dd[0], dd[1], St, vf, gas, f);
   }
   scale_flux_f64(f, area, F);
