@@ -128,9 +128,10 @@ def read_traffic(kernel_label: str):
 
 
 def source_sha() -> str:
+    """Hash of the sources that define the plane-ring stage kernel (the kernel
+    the committed counter summaries measure)."""
     h = hashlib.sha256()
-    for f in ("kernels_ring.hip", "kernels_tiled.hip", "kernels_stage.hip", "stage_common.hpp", "physics.hpp",
-              "cfd_internal.hpp"):
+    for f in ("kernels_ring.hip", "stage_common.hpp", "physics.hpp", "cfd_internal.hpp"):
         p = os.path.join(ROOT, "paper_1710_09995_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
