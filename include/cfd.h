@@ -174,6 +174,31 @@ cfd_status cfd_residual(cfd_ctx* ctx, const double* q_arena_dev, double* r_arena
 cfd_status cfd_step(cfd_ctx* ctx, double* q_arena_dev, int32_t nsteps, double* hist_dev,
                     hipStream_t stream);
 
+/* Implicit steps on the finite-volume residual (the sparse linear solve per
+ * step that Section 2.3's flowchart names, without its method; this reading
+ * is data parallel): backward Euler
+ *   (V_c / dt_c + d(V R)_c / dQ) dQ = -V_c R_c
+ * with dt_c the CFL step of cfd_step's reading at Courant number `cfl` (per
+ * cell with local_dt, else the global minimum), the first-order flux-split
+ * approximate Jacobian at every face f between cells L and R (flux
+ * (F(Q_L) + F(Q_R)) . S_f / 2 - mu_f (Q_R - Q_L), dissipation frozen at Q^n:
+ * mu_f = lambda_f / 2 + lv_f, lambda_f = |u_m . S_f| + c_m |S_f| of the mean
+ * primitive state of the two cells, for viscous flow lv_f = max(4/3, gamma/Pr)
+ * (mean mu/rho) |S_f|^2 / (mean V)), relaxed by `sweeps` point-Jacobi sweeps
+ * from dQ = -V R / D, D_c = V_c / dt_c + the cell's six mu_f; the update is
+ * copied across block connections and is zero in the ghost cells of physical
+ * boundaries (the boundary conditions act through the residual); then
+ * Q += dQ.  nsteps times, in place on q_arena_dev; hist_dev (nullable) gets
+ * one row per step as for cfd_step (dt = the least per-cell step).
+ * work_dev: cfd_implicit_work_size() bytes of device memory, 256-byte
+ * aligned, not overlapping the state (the residual, two update iterates, the
+ * face coefficients, diagonal and per-cell steps, each in the state layout).
+ * nsteps >= 0, 0 <= sweeps <= 1000, cfl > 0, else CFD_EINVAL; a short
+ * workspace gives CFD_ENOMEM.  Asynchronous on stream. */
+cfd_status cfd_implicit_work_size(const cfd_ctx* ctx, size_t* bytes);
+cfd_status cfd_step_implicit(cfd_ctx* ctx, double* q_arena_dev, int32_t nsteps, int32_t sweeps, double cfl,
+                             void* work_dev, size_t work_bytes, double* hist_dev, hipStream_t stream);
+
 /* Norms: out[0..4] = L2 of r (0 if r_arena_dev is NULL), out[5..9] = sum V q,
  * out[10] = max |r_rho|, out[11] = count of non-finite values in q and r.
  * Deterministic fixed-order reductions.  flags & CFD_NORMS_HOST: `out` is

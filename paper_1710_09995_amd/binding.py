@@ -59,7 +59,8 @@ class MlpDesc(C.Structure):
 
 
 EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy", "cfd_set_tuning",
-           "cfd_get_tuning", "cfd_fill_ghosts", "cfd_residual", "cfd_step", "cfd_norms",
+           "cfd_get_tuning", "cfd_fill_ghosts", "cfd_residual", "cfd_step", "cfd_implicit_work_size",
+           "cfd_step_implicit", "cfd_norms",
            "cfd_time_step", "cfd_copy_metrics", "cfd_set_profiling", "cfd_profile_read",
            "cfd_mlp_sizes", "cfd_mlp_forward", "cfd_mlp_mse", "cfd_mlp_backward", "cfd_mlp_adam",
            "cfd_mlp_to_bf16", "cfd_mlp_features", "cfd_mlp_targets", "cfd_mlp_to_state",
@@ -103,6 +104,8 @@ def lib(build_if_missing: bool = True):
     L.cfd_fill_ghosts.argtypes = [vp, vp, vp]
     L.cfd_residual.argtypes = [vp, vp, vp, vp]
     L.cfd_step.argtypes = [vp, vp, i32, vp, vp]
+    L.cfd_implicit_work_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.cfd_step_implicit.argtypes = [vp, vp, i32, i32, C.c_double, vp, C.c_size_t, vp, vp]
     L.cfd_norms.argtypes = [vp, vp, vp, vp, i32, vp]
     L.cfd_time_step.argtypes = [vp, vp, vp, vp]
     L.cfd_copy_metrics.argtypes = [vp, i32, vp, vp]
@@ -821,6 +824,27 @@ class Solver:
             h = self.torch.zeros((nsteps, 12), dtype=self.torch.float64, device=self.device)
         _check(lib().cfd_step(self.ctx, _ptr(arena), int(nsteps), _ptr(h) if h is not None else None,
                               self._s()), self.ctx)
+        return h
+
+    def step_implicit(self, nsteps: int = 1, sweeps: int = 8, cfl: float = 20.0, hist: bool = True, arena=None):
+        """nsteps implicit steps (cfd_step_implicit: backward Euler, frozen
+        flux-split Jacobian, `sweeps` point-Jacobi sweeps, CFL step at `cfl`);
+        returns the history [nsteps, 12] (device) or None."""
+        arena = self.q if arena is None else arena
+        torch = self.torch
+        if getattr(self, "_impl_work", None) is None:
+            nb = C.c_size_t()
+            _check(lib().cfd_implicit_work_size(self.ctx, C.byref(nb)), self.ctx)
+            self._impl_work = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        w = self._impl_work
+        base = w.data_ptr()
+        off = (-base) % 256
+        h = None
+        if hist and nsteps > 0:
+            h = torch.zeros((nsteps, 12), dtype=torch.float64, device=self.device)
+        _check(lib().cfd_step_implicit(self.ctx, _ptr(arena), int(nsteps), int(sweeps), float(cfl),
+                                       C.c_void_p(base + off), C.c_size_t(w.numel() - off),
+                                       _ptr(h) if h is not None else None, self._s()), self.ctx)
         return h
 
     def time_step(self, arena=None) -> float:

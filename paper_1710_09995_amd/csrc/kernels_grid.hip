@@ -166,9 +166,11 @@ __global__ void k_metric_ghosts(double* __restrict__ met, const BlockDesc* __res
 // cells of a row are adjacent in memory while neighbouring points are a row
 // apart, so a thread per (point, layer) puts a row's layers on adjacent lanes
 // and halves the memory segments each access touches.
+// With delta set, q is an update (the implicit step's dQ): connections copy it
+// as they copy the state, and the ghost cells of physical patches get zero.
 __global__ void k_ghost_q(double* __restrict__ q, const double* __restrict__ met,
                           const BlockDesc* __restrict__ blocks,
-                          const PatchDesc* __restrict__ patches, StepParams SP) {
+                          const PatchDesc* __restrict__ patches, StepParams SP, int delta) {
   const PatchDesc& P = patches[blockIdx.y];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int d = P.face >> 1, side = P.face & 1;
@@ -210,6 +212,19 @@ __global__ void k_ghost_q(double* __restrict__ q, const double* __restrict__ met
     }
     for (int m = 0; m < NG; ++m)
       for (int v = 0; v < NV; ++v) qb[v * B.sv + od[m]] = val[m][v];
+    return;
+  }
+  if (delta) {
+    if (per != 1) {     // this thread's layer only
+      const int m = 1 + t % per;
+      const int64_t od = pos3(d, side == 0 ? -m : n - 1 + m, p1, p2, B.sj, B.sk);
+      for (int v = 0; v < NV; ++v) qb[v * B.sv + od] = 0.0;
+      return;
+    }
+    for (int m = 1; m <= NG; ++m) {
+      const int64_t od = pos3(d, side == 0 ? -m : n - 1 + m, p1, p2, B.sj, B.sk);
+      for (int v = 0; v < NV; ++v) qb[v * B.sv + od] = 0.0;
+    }
     return;
   }
   // boundary face vector at this transverse position
@@ -339,10 +354,10 @@ void launch_metric_ghosts(double* met, const BlockDesc* blocks, const PatchDesc*
 
 void launch_ghost_q(double* q, const double* met, const BlockDesc* blocks,
                     const PatchDesc* patches, int npatch, int nthreads, const StepParams& SP,
-                    hipStream_t s) {
+                    hipStream_t s, int delta) {
   if (npatch == 0) return;
   hipLaunchKernelGGL(k_ghost_q, dim3((nthreads + 127) / 128, npatch), dim3(128), 0, s, q, met,
-                     blocks, patches, SP);
+                     blocks, patches, SP, delta);
 }
 
 }  // namespace cfd

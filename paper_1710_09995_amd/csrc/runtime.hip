@@ -19,6 +19,7 @@
 #include "../../include/cfd.h"
 #include "cfd_internal.hpp"
 #include "host_services.hpp"
+#include "implicit.hpp"
 
 namespace cfd {
 void launch_copy_nodes(const double* src, double* x, const BlockDesc& B, hipStream_t s);
@@ -29,7 +30,7 @@ void launch_visc_metrics(const double* met, double* vmet, const BlockDesc& B, hi
 void launch_metric_ghosts(double* met, const BlockDesc* blocks, const PatchDesc* patches, int npatch,
                           int maxcount, hipStream_t s);
 void launch_ghost_q(double* q, const double* met, const BlockDesc* blocks, const PatchDesc* patches,
-                    int npatch, int nthreads, const StepParams& SP, hipStream_t s);
+                    int npatch, int nthreads, const StepParams& SP, hipStream_t s, int delta = 0);
 bool stage_ring(const StageArgs& A, int mode, bool visc, bool fp32, const BlockDesc* blocks, const TileDesc* tiles,
                 const Gas<double>& g64, const Gas<float>& g32, int nwg, hipStream_t s, int* occ);
 bool stage_tiled(const StageArgs& A, int mode, bool visc, bool fp32, const BlockDesc* blocks,
@@ -705,6 +706,68 @@ cfd_status guard(cfd_ctx* c, F&& f) {
   }
 }
 
+// Implicit step workspace: four arenas in the state layout (the residual of
+// Q^n, two update iterates, and the face coefficients / diagonal / per-cell
+// step), each 256-byte aligned.
+size_t implicit_arena_bytes(const cfd_ctx* c) { return align256((size_t)c->L.q_elems * sizeof(double)); }
+
+// One implicit step on the finite-volume residual (kernels_implicit.hip):
+// ghost fill of Q^n, the CFL step at `cfl` (global minimum; the per-cell steps
+// come with the face coefficients), R(Q^n), the history row (norms of R, totals
+// of Q^n, minimum step), face coefficients and the diagonal, `sweeps` Jacobi
+// sweeps each after a ghost fill of the iterate (connections copy it, physical
+// patches zero it), Q += dQ.
+void enqueue_implicit_step(cfd_ctx* c, double* q, int sweeps, double cfl, char* work, hipStream_t s) {
+  const size_t ab = implicit_arena_bytes(c);
+  double* R = reinterpret_cast<double*>(work);
+  double* dA = reinterpret_cast<double*>(work + ab);
+  double* dB = reinterpret_cast<double*>(work + 2 * ab);
+  double* MU = reinterpret_cast<double*>(work + 3 * ab);
+  StepParams P = c->SP;
+  P.cfl = cfl;
+  const int nwg = dt_nwg(c);
+  ghost_fill(c, q, s);
+  timed(c, 2, s, [&] {
+    launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->nblk, c->nchunks, P, nwg, s);
+  });
+  launch_finalize(c->part_dt(), nwg, 0, 0.0, c->d_dt(), nullptr, nullptr, s);
+  StageArgs A = stage_args(c);
+  A.qs = q;
+  A.qn = q;
+  A.out = R;
+  launch_stage(c, A, 0, s);
+  timed(c, 3, s, [&] { launch_norms(q, R, c->met(), c->part_nrm(), c->dblocks, c->nblk, c->nchunks, nwg, s); });
+  launch_finalize(c->part_nrm(), nwg, 1, 1.0 / (double)c->ncells, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
+  ImplicitArgs I{};
+  I.q = q;
+  I.met = c->met();
+  I.r = R;
+  I.mu = MU;
+  I.dt = c->d_dt();
+  I.local = c->params.local_dt;
+  I.viscous = c->params.viscous;
+  I.gamma = c->SP.gamma;
+  I.prandtl = c->SP.prandtl;
+  I.mu_inf = c->SP.mu_inf;
+  I.s_star = c->SP.s_star;
+  I.cfl = cfl;
+  launch_ifv_faces(I, c->dblocks, c->nblk, c->nchunks, P, nwg, s);
+  I.dq_out = dA;
+  launch_ifv_diag(I, c->dblocks, c->nblk, c->nchunks, nwg, s);
+  double* cur = dA;
+  double* nxt = dB;
+  for (int k = 0; k < sweeps; ++k) {
+    for (int d = 0; d < 3; ++d)
+      launch_ghost_q(cur, c->met(), c->dblocks, c->dpatches + c->poff[3 + d], c->pcount[3 + d], c->qthreads[d],
+                     c->SP, s, 1);
+    I.dq_in = cur;
+    I.dq_out = nxt;
+    timed(c, 0, s, [&] { launch_ifv_sweep(I, c->dblocks, c->nblk, c->nchunks, nwg, s); });
+    std::swap(cur, nxt);
+  }
+  launch_ifv_apply(q, cur, c->dblocks, c->nblk, c->nchunks, nwg, s);
+}
+
 void check_launch() {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) fail(CFD_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
@@ -1028,6 +1091,36 @@ cfd_status cfd_step(cfd_ctx* c, double* q, int32_t nsteps, double* hist, hipStre
           HIPCHK(hipMemcpyAsync(hist + (int64_t)n * NHIST, c->d_hist(), sizeof(double) * NHIST,
                                 hipMemcpyDeviceToDevice, s));
       }
+    }
+  });
+}
+
+cfd_status cfd_implicit_work_size(const cfd_ctx* c, size_t* bytes) {
+  return guard(const_cast<cfd_ctx*>(c), [&] {
+    if (!c || !bytes) fail(CFD_EINVAL, "NULL argument");
+    *bytes = 4 * implicit_arena_bytes(c);
+  });
+}
+
+cfd_status cfd_step_implicit(cfd_ctx* c, double* q, int32_t nsteps, int32_t sweeps, double cfl, void* work,
+                             size_t work_bytes, double* hist, hipStream_t s) {
+  return guard(c, [&] {
+    if (!c || !q || !work) fail(CFD_EINVAL, "NULL argument");
+    if (nsteps < 0) fail(CFD_EINVAL, "nsteps must be >= 0");
+    if (sweeps < 0 || sweeps > 1000) fail(CFD_EINVAL, "sweeps must be in [0, 1000]");
+    if (!(cfl > 0.0) || !std::isfinite(cfl)) fail(CFD_EINVAL, "cfl must be positive and finite");
+    if (work_bytes < 4 * implicit_arena_bytes(c)) fail(CFD_ENOMEM, "workspace smaller than cfd_implicit_work_size()");
+    if (reinterpret_cast<uintptr_t>(work) % 256) fail(CFD_EINVAL, "workspace must be 256-byte aligned");
+    const size_t qb = (size_t)c->L.q_elems * sizeof(double);
+    const char* w0 = static_cast<const char*>(work);
+    const char* q0 = reinterpret_cast<const char*>(q);
+    if (!(w0 + work_bytes <= q0 || q0 + qb <= w0)) fail(CFD_EINVAL, "state and workspace overlap");
+    for (int n = 0; n < nsteps; ++n) {
+      enqueue_implicit_step(c, q, sweeps, cfl, static_cast<char*>(work), s);
+      check_launch();
+      if (hist)
+        HIPCHK(hipMemcpyAsync(hist + (int64_t)n * NHIST, c->d_hist(), sizeof(double) * NHIST,
+                              hipMemcpyDeviceToDevice, s));
     }
   });
 }
