@@ -585,6 +585,39 @@ bool apart(const void* a, int64_t na, const void* b, int64_t nb) {
   return a0 + na <= b0 || b0 + nb <= a0;
 }
 
+// Interior cells of block b of a dims table (3 entries per block).
+int64_t block_cells(const int32_t* dims, int b) {
+  return (int64_t)dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+}
+
+// One argument buffer of a multi-block call: `bytes` bytes at p, written by
+// the call or only read.
+struct ArgSpan {
+  uintptr_t p;
+  int64_t bytes;
+  bool written;
+};
+ArgSpan span(const void* p, int64_t bytes, bool written) {
+  return ArgSpan{reinterpret_cast<uintptr_t>(p), bytes, written};
+}
+
+// Fails with msg when a written buffer overlaps any other one (read-only
+// buffers may share memory).  In the order of start addresses a buffer
+// overlaps an earlier one exactly when it starts below the largest end among
+// them, so one pass after the sort checks all pairs: O(n log n) however many
+// blocks a call names.
+void check_spans(std::vector<ArgSpan>& v, const char* msg) {
+  std::sort(v.begin(), v.end(), [](const ArgSpan& a, const ArgSpan& b) { return a.p < b.p; });
+  uintptr_t end_any = 0, end_written = 0;
+  for (const ArgSpan& a : v) {
+    if (a.bytes <= 0) continue;
+    if (a.p < end_written || (a.written && a.p < end_any)) host_fail(CFD_EINVAL, msg);
+    const uintptr_t e = a.p + (uintptr_t)a.bytes;
+    end_any = std::max(end_any, e);
+    if (a.written) end_written = std::max(end_written, e);
+  }
+}
+
 // The periodic WCNS-E-5 residual along the three directions.  Cartesian when
 // s is NULL (face normals e_d, Eq. (2) with the spacings h); else curvilinear:
 // Roe's flux through the face area vectors s, Eq. (2) in index units and a
@@ -1336,24 +1369,14 @@ extern "C" cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_
     if (!(entropy_fix >= 0.0) || !std::isfinite(entropy_fix)) cfd::host_fail(CFD_EINVAL, "bad entropy_fix");
     if (!(eps > 0.0) || !std::isfinite(eps)) cfd::host_fail(CFD_EINVAL, "eps must be positive and finite");
     if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_euler_blocks_work_bytes()");
-    auto cells_of = [&](int b) { return (int64_t)dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2]; };
+    std::vector<cfd::ArgSpan> spans{cfd::span(work_dev, (int64_t)need, true)};
     for (int b = 0; b < nblk; ++b) {
       if (!q_dev[b] || !s_dev[b] || !jinv_dev[b] || !r_dev[b]) cfd::host_fail(CFD_EINVAL, "NULL block pointer");
-      const int64_t cb = cells_of(b);
-      if (!cfd::apart(r_dev[b], 40 * cb, work_dev, (int64_t)need))
-        cfd::host_fail(CFD_EINVAL, "a residual overlaps the workspace");
-      for (int c = 0; c < nblk; ++c) {
-        const int64_t cc = cells_of(c);
-        if (!cfd::apart(r_dev[b], 40 * cb, q_dev[c], 40 * cc) || !cfd::apart(r_dev[b], 40 * cb, s_dev[c], 72 * cc) ||
-            !cfd::apart(r_dev[b], 40 * cb, jinv_dev[c], 8 * cc) ||
-            (c != b && !cfd::apart(r_dev[b], 40 * cb, r_dev[c], 40 * cc)))
-          cfd::host_fail(CFD_EINVAL, "a residual overlaps an input or another residual");
-        if (!cfd::apart(work_dev, (int64_t)need, q_dev[c], 40 * cc) ||
-            !cfd::apart(work_dev, (int64_t)need, s_dev[c], 72 * cc) ||
-            !cfd::apart(work_dev, (int64_t)need, jinv_dev[c], 8 * cc))
-          cfd::host_fail(CFD_EINVAL, "the workspace overlaps an input");
-      }
+      const int64_t cb = cfd::block_cells(dims, b);
+      spans.insert(spans.end(), {cfd::span(q_dev[b], 40 * cb, false), cfd::span(s_dev[b], 72 * cb, false),
+                                 cfd::span(jinv_dev[b], 8 * cb, false), cfd::span(r_dev[b], 40 * cb, true)});
     }
+    cfd::check_spans(spans, "a residual or the workspace overlaps an input, another residual or the workspace");
     cfd::wcns5_blocks_residual_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, r_dev, work_dev, gamma, entropy_fix, eps,
                                       stream);
     const hipError_t e = hipGetLastError();
@@ -1532,9 +1555,7 @@ __global__ void __launch_bounds__(256) k_c4_flux_sub_line(Line W, double* __rest
 
 namespace {
 
-int64_t block_cells(const int32_t* dims, int b) {
-  return (int64_t)dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
-}
+using cfd::block_cells;
 
 }  // namespace
 
@@ -1621,23 +1642,14 @@ extern "C" cfd_status cfd_c4_viscous_add_blocks(int32_t nblk, const int32_t* dim
     for (int b = 0; b < nblk; ++b) off[b + 1] = off[b] + cfd::VW_FIELDS * block_cells(dims, b);
     const size_t need = (size_t)8 * off[nblk];
     if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_c4_viscous_blocks_work_bytes()");
+    std::vector<cfd::ArgSpan> spans{cfd::span(work_dev, (int64_t)need, true)};
     for (int b = 0; b < nblk; ++b) {
       if (!q_dev[b] || !s_dev[b] || !jinv_dev[b] || !r_dev[b]) cfd::host_fail(CFD_EINVAL, "NULL block pointer");
-      const int64_t cb = block_cells(dims, b);
-      if (!cfd::apart(r_dev[b], 40 * cb, work_dev, (int64_t)need))
-        cfd::host_fail(CFD_EINVAL, "a residual overlaps the workspace");
-      for (int c = 0; c < nblk; ++c) {
-        const int64_t cc = block_cells(dims, c);
-        if (!cfd::apart(r_dev[b], 40 * cb, q_dev[c], 40 * cc) || !cfd::apart(r_dev[b], 40 * cb, s_dev[c], 72 * cc) ||
-            !cfd::apart(r_dev[b], 40 * cb, jinv_dev[c], 8 * cc) ||
-            (c != b && !cfd::apart(r_dev[b], 40 * cb, r_dev[c], 40 * cc)))
-          cfd::host_fail(CFD_EINVAL, "a residual overlaps an input or another residual");
-        if (!cfd::apart(work_dev, (int64_t)need, q_dev[c], 40 * cc) ||
-            !cfd::apart(work_dev, (int64_t)need, s_dev[c], 72 * cc) ||
-            !cfd::apart(work_dev, (int64_t)need, jinv_dev[c], 8 * cc))
-          cfd::host_fail(CFD_EINVAL, "the workspace overlaps an input");
-      }
+      const int64_t cb = cfd::block_cells(dims, b);
+      spans.insert(spans.end(), {cfd::span(q_dev[b], 40 * cb, false), cfd::span(s_dev[b], 72 * cb, false),
+                                 cfd::span(jinv_dev[b], 8 * cb, false), cfd::span(r_dev[b], 40 * cb, true)});
     }
+    cfd::check_spans(spans, "a residual or the workspace overlaps an input, another residual or the workspace");
     cfd::c4_viscous_blocks_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, r_dev, static_cast<double*>(work_dev),
                                   cfd::viscous_gas(gamma, prandtl, mu_inf, s_star), stream);
     const hipError_t e = hipGetLastError();
@@ -2008,20 +2020,14 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_
     for (int b = 0; b < nblk; ++b) off[b + 1] = off[b] + 22 * block_cells(dims, b);
     const size_t need = scratch + (size_t)8 * off[nblk];
     if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_implicit_blocks_work_bytes()");
+    std::vector<cfd::ArgSpan> spans{cfd::span(work_dev, (int64_t)need, true)};
     for (int b = 0; b < nblk; ++b) {
       if (!q_dev[b] || !s_dev[b] || !jinv_dev[b]) cfd::host_fail(CFD_EINVAL, "NULL block pointer");
-      const int64_t cb = block_cells(dims, b);
-      if (!cfd::apart(q_dev[b], 40 * cb, work_dev, (int64_t)need)) cfd::host_fail(CFD_EINVAL, "q overlaps the workspace");
-      for (int c = 0; c < nblk; ++c) {
-        const int64_t cc = block_cells(dims, c);
-        if (!cfd::apart(q_dev[b], 40 * cb, s_dev[c], 72 * cc) || !cfd::apart(q_dev[b], 40 * cb, jinv_dev[c], 8 * cc) ||
-            (c != b && !cfd::apart(q_dev[b], 40 * cb, q_dev[c], 40 * cc)))
-          cfd::host_fail(CFD_EINVAL, "a state overlaps the metrics or another state");
-        if (!cfd::apart(work_dev, (int64_t)need, s_dev[c], 72 * cc) ||
-            !cfd::apart(work_dev, (int64_t)need, jinv_dev[c], 8 * cc))
-          cfd::host_fail(CFD_EINVAL, "the workspace overlaps the metrics");
-      }
+      const int64_t cb = cfd::block_cells(dims, b);
+      spans.insert(spans.end(), {cfd::span(q_dev[b], 40 * cb, true), cfd::span(s_dev[b], 72 * cb, false),
+                                 cfd::span(jinv_dev[b], 8 * cb, false)});
     }
+    cfd::check_spans(spans, "a state or the workspace overlaps the metrics, another state or the workspace");
     double* base = reinterpret_cast<double*>(static_cast<char*>(work_dev) + scratch);
     std::vector<double*> R(nblk), dqa(nblk), dqb(nblk), lam(nblk), lamv(nblk), diag(nblk);
     for (int b = 0; b < nblk; ++b) {
@@ -2129,20 +2135,14 @@ extern "C" cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dim
     const size_t scratch = std::max(rscratch, vscratch);
     const size_t need = scratch + (size_t)8 * off[nblk];
     if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_ns_blocks_work_bytes()");
+    std::vector<cfd::ArgSpan> spans{cfd::span(work_dev, (int64_t)need, true)};
     for (int b = 0; b < nblk; ++b) {
       if (!q_dev[b] || !s_dev[b] || !jinv_dev[b]) cfd::host_fail(CFD_EINVAL, "NULL block pointer");
-      const int64_t cb = block_cells(dims, b);
-      if (!cfd::apart(q_dev[b], 40 * cb, work_dev, (int64_t)need)) cfd::host_fail(CFD_EINVAL, "q overlaps the workspace");
-      for (int c = 0; c < nblk; ++c) {
-        const int64_t cc = block_cells(dims, c);
-        if (!cfd::apart(q_dev[b], 40 * cb, s_dev[c], 72 * cc) || !cfd::apart(q_dev[b], 40 * cb, jinv_dev[c], 8 * cc) ||
-            (c != b && !cfd::apart(q_dev[b], 40 * cb, q_dev[c], 40 * cc)))
-          cfd::host_fail(CFD_EINVAL, "a state overlaps the metrics or another state");
-        if (!cfd::apart(work_dev, (int64_t)need, s_dev[c], 72 * cc) ||
-            !cfd::apart(work_dev, (int64_t)need, jinv_dev[c], 8 * cc))
-          cfd::host_fail(CFD_EINVAL, "the workspace overlaps the metrics");
-      }
+      const int64_t cb = cfd::block_cells(dims, b);
+      spans.insert(spans.end(), {cfd::span(q_dev[b], 40 * cb, true), cfd::span(s_dev[b], 72 * cb, false),
+                                 cfd::span(jinv_dev[b], 8 * cb, false)});
     }
+    cfd::check_spans(spans, "a state or the workspace overlaps the metrics, another state or the workspace");
     double* base = reinterpret_cast<double*>(static_cast<char*>(work_dev) + scratch);
     std::vector<double*> qn(nblk), R(nblk);
     for (int b = 0; b < nblk; ++b) {

@@ -440,3 +440,58 @@ def test_ns_blocks_bad_arguments():
             st = L.cfd_wcns5_ns_steps_blocks(2, dims, nbr, a["q"], a["s"], a["j"], a["w"], a["wb"], a["g"], a["ef"],
                                              a["eps"], a["pr"], a["mu"], a["ss"], a["dt"], a["ns"], None)
             assert st == st_want, b
+
+
+def _self_joined(nblk, n=5):
+    """nblk blocks of n^3 cells, each its own neighbour across every face."""
+    dims = (C.c_int32 * (3 * nblk))(*([n, n, n] * nblk))
+    nbr = (C.c_int32 * (6 * nblk))(*[b for b in range(nblk) for _ in range(6)])
+    return dims, nbr
+
+
+def _fake_spans(nblk, sizes, base=1 << 40):
+    """Disjoint fake device addresses (never dereferenced: every call below
+    fails its argument checks before any launch), 256-byte aligned."""
+    out, at = [], base
+    for size in sizes:
+        ptrs = []
+        for _ in range(nblk):
+            ptrs.append(at)
+            at += (size + 255) // 256 * 256
+        out.append(ptrs)
+    return out, at
+
+
+@pytest.mark.parametrize("nblk", [3, 65536])
+def test_block_entry_points_reject_overlapping_buffers(nblk):
+    """The joined-block entry points check every pair of buffers for overlap
+    (in O(n log n): 65536 blocks take well under a second) and refuse a
+    written buffer that overlaps any other before launching anything."""
+    import time
+    L = B.lib()
+    vp = C.c_void_p
+    dims, nbr = _self_joined(nblk)
+    cells = 125
+    need = C.c_size_t()
+    B._check(L.cfd_wcns5_euler_blocks_work_bytes(nblk, dims, nbr, C.byref(need)))
+    (q, s, j, r), end = _fake_spans(nblk, [40 * cells, 72 * cells, 8 * cells, 40 * cells])
+    arr = lambda v: (vp * nblk)(*v)   # noqa: E731
+
+    def residual(q, s, j, r, work):
+        return L.cfd_wcns5_euler_residual_blocks(nblk, dims, nbr, arr(q), arr(s), arr(j), arr(r), work,
+                                                 need.value, 1.4, 0.1, 1e-6, None)
+    cases_ = [
+        (q, s, j, r[:-1] + [q[0] + 8], end),             # last residual inside the first state
+        (q, s, j, r[:-1] + [r[0] + 40 * cells - 8], end),  # two residuals share 8 bytes
+        (q, s, j, r, s[nblk // 2]),                        # the workspace starts inside a face-metric array
+    ]
+    for args in cases_:
+        t0 = time.perf_counter()
+        st = residual(*args)
+        assert st == -1 and "overlaps" in L.cfd_last_error(None).decode(), st
+        assert time.perf_counter() - t0 < 5.0
+    iw = C.c_size_t()
+    B._check(L.cfd_wcns5_implicit_blocks_work_bytes(nblk, dims, nbr, C.byref(iw)))
+    st = L.cfd_wcns5_implicit_steps_blocks(nblk, dims, nbr, arr(q[:-1] + [q[0] + 16]), arr(s), arr(j), end,
+                                           iw.value, 1.4, 0.1, 1e-6, 0, 0.72, 0.0, 0.38, 1e-3, 1, 2, None)
+    assert st == -1 and "overlaps" in L.cfd_last_error(None).decode()
