@@ -1,0 +1,209 @@
+"""Closures of the WCNS-E-5 scheme at physical block faces (oracle; plain FP64
+NumPy; test infrastructure, imported only by the tests).
+
+Section 2.2 leaves the conditions at block boundaries to its references and
+does not print them.  The reading taken here ("ghost blocks") keeps every
+interior stencil unchanged up to the boundary:
+
+* a block face on a wall or the far field gets a ghost block GHOST = 5 cells
+  deep across that face (the reach of the interpolation and of Eq. 2's
+  stencil), with the face's transverse extents, joined to the owner face to
+  face; the residual of the owner is then the joined-block residual of
+  highorder.py (R19) over the owner and its ghost blocks;
+* geometry: the owner's vertex lines are extended past each bounded face by
+  linear extrapolation, x_(b - m) = x_b + m (x_b - x_(b+1)) for the boundary
+  plane b and the plane next to it inside; each block (owner or ghost) takes
+  its metrics from its own window of the extended vertices (vertices -3 ..
+  n + 1), so both sides of a boundary face compute it from the same
+  coordinates and a uniform stream stays uniform (the metrics' identity holds
+  on any vertex set);
+* state of a ghost block, refilled from the owner before every residual: the
+  ghost cell m = 1 .. 5 cells beyond the face mirrors the owner cell m - 1
+  cells inside it:
+    - slip wall: momentum reflected about the unit normal of the boundary
+      face (its area vector S_d of the sixth-order metrics), rho and energy
+      copied;
+    - no-slip adiabatic wall: momentum negated, rho and energy copied;
+    - far field: every layer the characteristic state of the finite-volume
+      path's far field (Riemann invariants along the outward normal, from
+      the first owner cell and the freestream);
+* restriction: one bounded direction, both of whose faces carry a condition,
+  and periodic transverse directions (no corner ghost blocks are needed
+  then); the two ghost blocks close the bounded direction into a ring so that
+  every link of the joined-block table is mutual.  The wall-bump geometry
+  (periodic x and z, wall and far field across y) has this form.
+
+Pins (tests/test_oracle_closures.py): a uniform stream on the curved wall-bump
+grid with the far field on both bounded faces stays uniform; a state mirrored
+about a flat slip wall gives, with the closures, the residual of the
+periodic domain of twice the height that holds the state and its mirror image
+(inviscid and viscous); the vertex extension reproduces a grid that is linear
+along the bounded direction; and away from the boundary the closed residual
+equals the residual of the same state continued periodically.
+"""
+from __future__ import annotations
+
+from types import SimpleNamespace
+
+import numpy as np
+
+from . import highorder as ho
+from .ghosts import FARFIELD, NOSLIP_ADIABATIC, SLIPWALL, _farfield_state
+
+GHOST = 5
+XLAYERS = 7          # extrapolated vertex planes beyond a bounded face (a ghost block's vertices -3 .. 6)
+
+
+def _axis(d):
+    return 3 - d     # array axis of direction d in [3, k, j, i]
+
+
+def extended_vertices(Xv: np.ndarray, period, bounded: int):
+    """Xv [3, ...]: the owner's vertices; along periodic directions the n
+    upper corners 0 .. n - 1 (period[d] is the grid's displacement over one
+    period), along the bounded direction the n + 1 planes -1 .. n - 1.
+    Returns (E, origin): E spans vertices -3 .. n + 1 along periodic
+    directions and -1 - XLAYERS .. n - 1 + XLAYERS along the bounded one;
+    origin[d] is the array index of vertex 0 along d."""
+    shape = Xv.shape[1:]
+    n = [shape[2], shape[1], shape[0]]
+    if bounded in range(3):
+        n[bounded] -= 1
+    X = Xv
+    origin = [0, 0, 0]
+    for d in range(3):
+        ax = _axis(d)
+        if d == bounded:
+            continue
+        idx = np.arange(-3, n[d] + 2)
+        wrap, q = idx % n[d], idx // n[d]
+        X = np.take(X, wrap, axis=ax)
+        shp = [1, 1, 1, 1]
+        shp[ax] = idx.size
+        X = X + q.reshape(shp) * np.asarray(period[d], dtype=np.float64).reshape(3, 1, 1, 1)
+        origin[d] = 3
+    if bounded in range(3):
+        ax = _axis(bounded)
+        L = XLAYERS                                             # planes -1 - L .. -2 below plane -1
+        lo0, lo1 = ho._win(X, ax, 0, 1), ho._win(X, ax, 1, 1)
+        hi0, hi1 = ho._win(X, ax, n[bounded], 1), ho._win(X, ax, n[bounded] - 1, 1)
+        below = [lo0 + m * (lo0 - lo1) for m in range(L, 0, -1)]
+        above = [hi0 + m * (hi0 - hi1) for m in range(1, XLAYERS + 1)]
+        X = np.concatenate(below + [X] + above, axis=ax)
+        origin[bounded] = L + 1                                 # plane -1 sits at index L
+    return X, origin
+
+
+def layout(n, bounded: int, kinds):
+    """Blocks and neighbour table of an owner of n cells with a ghost block on
+    each face of the bounded direction.  kinds = (kind of the low face, kind
+    of the high face), each ghosts.FARFIELD, SLIPWALL or NOSLIP_ADIABATIC.
+    Returns (dims, nbr, ghosts) with ghosts = [(block, side, kind)]; block 0
+    is the owner, 1 the low ghost block, 2 the high one.  Along the bounded
+    direction the three close into a ring (the low ghost's far face joins
+    the high ghost's), so every link is mutual; the owner's residual never
+    reads past its ghost blocks' first five cells."""
+    if len(kinds) != 2 or any(k not in (FARFIELD, SLIPWALL, NOSLIP_ADIABATIC) for k in kinds):
+        raise ValueError("both faces of the bounded direction need a wall or far-field condition")
+    m = list(n)
+    m[bounded] = GHOST
+    dims = [tuple(n), tuple(m), tuple(m)]
+    nbr = [[b] * 6 for b in range(3)]
+    lo, hi = 2 * bounded, 2 * bounded + 1
+    nbr[0][lo], nbr[1][hi] = 1, 0
+    nbr[0][hi], nbr[2][lo] = 2, 0
+    nbr[1][lo], nbr[2][hi] = 2, 1
+    return dims, nbr, [(1, 0, kinds[0]), (2, 1, kinds[1])]
+
+
+def block_metrics(E, origin, n, bounded, ghosts):
+    """(S, Jinv) of the owner and of every ghost block from their windows of
+    the extended vertices."""
+    def window(lo):
+        Xw = E
+        for d in range(3):
+            ext = (n[d] if d != bounded or lo is None else GHOST) + 5
+            start = origin[d] - 3 + (0 if d != bounded or lo is None else lo)
+            Xw = ho._win(Xw, _axis(d), start, ext)
+        return Xw
+    out = [ho.metrics6(window(None))]
+    for _, side, _ in ghosts:
+        lo = -GHOST if side == 0 else n[bounded]
+        out.append(ho.metrics6(window(lo)))
+    return out
+
+
+def fill_ghosts(Qs, Ss, bounded, ghosts, gamma, freestream):
+    """Refill the ghost blocks' states (Qs[g], in place) from the owner Qs[0].
+    freestream: (mach, alpha, beta) of the far field."""
+    d = bounded
+    ax = _axis(d)
+    Q = Qs[0]
+    n = Q.shape[ax]
+    params = SimpleNamespace(gamma=gamma, mach=freestream[0], alpha=freestream[1], beta=freestream[2])
+    for g, side, kind in ghosts:
+        # unit normal of the boundary face (+d direction): the ghost block's
+        # last face below the owner, the owner's last face above it
+        Sb = ho._win(Ss[g][d], ax, GHOST - 1, 1) if side == 0 else ho._win(Ss[0][d], ax, n - 1, 1)
+        nhat = Sb / np.sqrt(np.sum(Sb * Sb, axis=0))
+        for m in range(1, GHOST + 1):
+            own = m - 1 if side == 0 else n - m
+            loc = GHOST - m if side == 0 else m - 1
+            Qi = ho._win(Q, ax, own, 1)
+            if kind == SLIPWALL:
+                Qg = Qi.copy()
+                mn = np.sum(Qi[1:4] * nhat, axis=0)
+                Qg[1:4] = Qi[1:4] - 2.0 * mn[None] * nhat
+            elif kind == NOSLIP_ADIABATIC:
+                Qg = Qi.copy()
+                Qg[1:4] = -Qi[1:4]
+            elif kind == FARFIELD:
+                Q0 = ho._win(Q, ax, 0 if side == 0 else n - 1, 1)
+                Qg = _farfield_state(Q0, -nhat if side == 0 else nhat, params)
+            else:
+                raise ValueError(f"unknown boundary kind {kind}")
+            sl = [slice(None)] * 4
+            sl[ax] = slice(loc, loc + 1)
+            Qs[g][tuple(sl)] = Qg
+
+
+class Closed:
+    """An owner block with ghost blocks: geometry set up once."""
+
+    def __init__(self, Xv, period, bounded, kinds, gamma=1.4, freestream=(0.5, 0.0, 0.0)):
+        self.bounded = bounded
+        shape = Xv.shape[1:]
+        n = [shape[2], shape[1], shape[0]]
+        n[bounded] -= 1
+        self.n = tuple(n)
+        self.E, self.origin = extended_vertices(Xv, period, bounded)
+        self.dims, self.nbr, self.ghosts = layout(self.n, bounded, kinds)
+        mets = block_metrics(self.E, self.origin, self.n, bounded, self.ghosts)
+        self.S = [m[0] for m in mets]
+        self.Jinv = [m[1] for m in mets]
+        self.gamma = gamma
+        self.freestream = freestream
+
+    def blocks(self, Q):
+        """[owner, ghost blocks] with the ghost states filled from Q."""
+        Qs = [Q] + [np.zeros((5,) + tuple(reversed(m))) for m in self.dims[1:]]
+        fill_ghosts(Qs, self.S, self.bounded, self.ghosts, self.gamma, self.freestream)
+        return Qs
+
+    def residual(self, Q, eps_h=0.1, eps=1e-6, viscous=None):
+        """R (dQ/dt = -R) of the owner; viscous = (prandtl, mu_inf, s_star) adds
+        the fourth-order viscous terms."""
+        Qs = self.blocks(Q)
+        R = ho.wcns5_euler_residual_blocks(Qs, self.S, self.Jinv, self.nbr, self.gamma, eps_h, eps)[0]
+        if viscous is not None:
+            R = R + ho.viscous_residual_blocks(Qs, self.S, self.Jinv, self.nbr, self.gamma, *viscous)[0]
+        return R
+
+    def ns_steps(self, Q, dt, nsteps, eps_h=0.1, eps=1e-6, viscous=None):
+        """nsteps SSP-RK3 steps (Eqs. 4-6, lambda = -dt) with the ghost blocks
+        refilled before every stage's residual."""
+        from .solver import ssp_rk3
+        q = Q
+        for _ in range(nsteps):
+            q = ssp_rk3(q, dt, lambda x: self.residual(x, eps_h, eps, viscous))
+        return q
