@@ -10,7 +10,16 @@ sequences the calls and moves tensors):
              becomes the initial state instead of the uniform stream;
   4. compare: steps and wall seconds until the density residual L2(R_rho)
              falls below 1e-8 of the cold start's initial residual (one
-             absolute threshold for both starts).
+             absolute threshold for both starts; a start's own lower initial
+             residual earns it nothing).
+The channel cases use the steady limiter constant (cases.STEADY_LIMITER_EPS),
+with which every case of the family converges linearly under local RK3
+steps, so the training data are converged solutions and both starts reach
+the target.  The march's tail decays at one rate whatever the start, so what
+a start saves at 1e-8 is set by how little of the slowest mode it carries;
+the network's own fitting error excites that mode, hence the long training
+(20000 Adam iterations bring the fit's mean squared error to about 1e-6,
+where 1500 left 4e-5 and a warm start slower than the cold one at 1e-8).
 """
 from __future__ import annotations
 
@@ -68,7 +77,7 @@ class TrainingData:
     info: dict = field(default_factory=dict)
 
 
-def generate(n_cases: int = 256, seed: int = 0, dims=(48, 24, 24), drop: float = 1e-8, max_steps: int = 20000,
+def generate(n_cases: int = 256, seed: int = 0, dims=(48, 24, 24), drop: float = 1e-8, max_steps: int = 60000,
              log=None) -> TrainingData:
     conds = cases.channel_conditions(n_cases, seed)
     case = cases.channel_batch_case(conds, *dims)
@@ -82,7 +91,7 @@ def generate(n_cases: int = 256, seed: int = 0, dims=(48, 24, 24), drop: float =
     return TrainingData(x, t, conds, steps + 1, secs, final, {"r0": r0})
 
 
-def train(data: TrainingData, iters: int = 3000, batch: int = 8192, lr: float = 2e-3, seed: int = 0,
+def train(data: TrainingData, iters: int = 20000, batch: int = 8192, lr: float = 2e-3, seed: int = 0,
           log=None) -> Mlp:
     import torch
     net = Mlp(cases.mlp_init(**NET, seed=seed), **NET)
@@ -107,7 +116,8 @@ def warm_state(solver: Solver, net: Mlp, conds):
 DECADES = tuple(10.0 ** -e for e in range(1, 9))     # residual drops 1e-1 .. 1e-8
 
 
-def march_decades(solver: Solver, r_ref: float, max_steps: int, chunk: int = 250, t_extra: float = 0.0):
+def march_decades(solver: Solver, r_ref: float, max_steps: int, chunk: int = 250, t_extra: float = 0.0,
+                  log=None, log_every: int = 20000):
     """March up to max_steps; for every drop d in DECADES record the first step
     (and the wall seconds, plus t_extra) at which L2(R_rho) < d * r_ref."""
     torch = solver.torch
@@ -126,6 +136,8 @@ def march_decades(solver: Solver, r_ref: float, max_steps: int, chunk: int = 250
             hit = np.nonzero(r < d * r_ref)[0]
             if hit.size:
                 reached[d] = (done + int(hit[0]), now)
+        if log and (done + n) // log_every > done // log_every:
+            log(f"#   step {done + n}: drop {r[-1] / r_ref:.2e}, {now:.1f} s")
         done += n
         last = float(r[-1])
         if not np.isfinite(last):
@@ -147,7 +159,8 @@ class Comparison:
     inference_s: float
 
 
-def compare(net: Mlp, conds, dims=(192, 96, 96), max_steps: int = 20000, log=None) -> List[Comparison]:
+def compare(net: Mlp, conds, dims=(192, 96, 96), max_steps: int = 200000, log=None, chunk: int = 500
+            ) -> List[Comparison]:
     """Cold (uniform stream) vs warm (network) start on each condition; one
     absolute reference, the cold start's initial residual, for both."""
     out = []
@@ -156,7 +169,7 @@ def compare(net: Mlp, conds, dims=(192, 96, 96), max_steps: int = 20000, log=Non
         s = Solver(case)
         r_cold0 = s.step(1, hist=True)[0, 1].item()     # residual of the uniform stream
         s.set_state(case.q0)
-        cold, _, cold_final = march_decades(s, r_cold0, max_steps)
+        cold, _, cold_final = march_decades(s, r_cold0, max_steps, chunk, log=log)
         s.set_state(case.q0)
         s.torch.cuda.synchronize(s.device)
         t0 = time.perf_counter()
@@ -165,7 +178,7 @@ def compare(net: Mlp, conds, dims=(192, 96, 96), max_steps: int = 20000, log=Non
         t_inf = time.perf_counter() - t0
         r_warm0 = s.step(1, hist=True)[0, 1].item()
         warm_state(s, net, [(mach, hb)])
-        warm, _, warm_final = march_decades(s, r_cold0, max_steps, t_extra=t_inf)
+        warm, _, warm_final = march_decades(s, r_cold0, max_steps, chunk, t_extra=t_inf, log=log)
         c = Comparison(float(mach), float(hb), r_cold0, r_warm0, cold, warm, cold_final, warm_final, max_steps,
                        t_inf)
         if log:
@@ -185,6 +198,19 @@ def deepest_common(c: Comparison) -> Optional[float]:
     return min(common) if common else None
 
 
+TARGET = DECADES[-1]
+
+
+def target_seconds(res: List[Comparison]):
+    """Per case (cold s, warm s) to the 1e-8 target; a start that did not reach
+    it within the cap counts as None."""
+    out = []
+    for c in res:
+        out.append((c.cold[TARGET][1] if TARGET in c.cold else None,
+                    c.warm[TARGET][1] if TARGET in c.warm else None))
+    return out
+
+
 def main(argv=None):
     import argparse
     import json
@@ -192,26 +218,41 @@ def main(argv=None):
     ap.add_argument("--cases", type=int, default=256)
     ap.add_argument("--coarse", type=int, nargs=3, default=[48, 24, 24])
     ap.add_argument("--fine", type=int, nargs=3, default=[192, 96, 96])
-    ap.add_argument("--data-steps", type=int, default=12000)
-    ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--data-steps", type=int, default=60000)
+    ap.add_argument("--iters", type=int, default=20000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--test", type=int, default=4)
     ap.add_argument("--test-seed", type=int, default=12345)
-    ap.add_argument("--cap", type=int, default=20000)
+    ap.add_argument("--cap", type=int, default=200000)
+    ap.add_argument("--chunk", type=int, default=500)
+    ap.add_argument("--test-skip", type=int, default=0, help="skip the first K held-out conditions")
+    ap.add_argument("--save-net", default=None, help="write the trained weights (.npz)")
+    ap.add_argument("--load-net", default=None, help="skip data and training; use these weights (.npz)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)   # noqa: E731
     t0 = time.perf_counter()
-    data = generate(a.cases, 0, tuple(a.coarse), drop=1e-12, max_steps=a.data_steps, log=log)
-    log(f"# data: {data.x.shape[0]} points from {a.cases} cases, {data.steps} steps in {data.seconds:.1f} s, "
-        f"residual {data.info['r0']:.3e} -> {data.final_residual:.3e}")
-    t1 = time.perf_counter()
-    net = train(data, iters=a.iters, batch=a.batch, log=log)
-    net.torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    log(f"# training: {a.iters} iterations in {t2 - t1:.1f} s")
-    tests = cases.channel_conditions(a.test, a.test_seed)
-    res = compare(net, tests, tuple(a.fine), a.cap, log=log)
+    if a.load_net:
+        with np.load(a.load_net, allow_pickle=False) as z:
+            net = Mlp([(z[f"w{k}"], z[f"b{k}"]) for k in range(len(z.files) // 2)], **NET)
+        data = None
+        t1 = t2 = time.perf_counter()
+    else:
+        data = generate(a.cases, 0, tuple(a.coarse), drop=1e-8, max_steps=a.data_steps, log=log)
+        log(f"# data: {data.x.shape[0]} points from {a.cases} cases, {data.steps} steps in {data.seconds:.1f} s, "
+            f"residual {data.info['r0']:.3e} -> {data.final_residual:.3e}")
+        t1 = time.perf_counter()
+        net = train(data, iters=a.iters, batch=a.batch, log=log)
+        net.torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        log(f"# training: {a.iters} iterations in {t2 - t1:.1f} s")
+        if a.save_net:
+            flat = {}
+            for k, (w, b) in enumerate(net.params()):
+                flat[f"w{k}"], flat[f"b{k}"] = w, b
+            np.savez(a.save_net, **flat)
+    tests = cases.channel_conditions(a.test_skip + a.test, a.test_seed)[a.test_skip:]
+    res = compare(net, tests, tuple(a.fine), a.cap, log=log, chunk=a.chunk)
     summary = []
     for c in res:
         d = deepest_common(c)
@@ -222,10 +263,19 @@ def main(argv=None):
                         "deepest_common_drop": d,
                         "speedup_steps": (c.cold[d][0] / max(1, c.warm[d][0])) if d else None,
                         "speedup_seconds": (c.cold[d][1] / max(1e-9, c.warm[d][1])) if d else None,
-                        "inference_s": c.inference_s, "cap": c.steps_cap})
-    out = {"train_cases": a.cases, "coarse": a.coarse, "fine": a.fine, "data_steps": data.steps,
-           "data_seconds": data.seconds, "train_iters": a.iters, "train_seconds": t2 - t1,
-           "total_seconds": time.perf_counter() - t0, "tests": summary}
+                        "inference_s": c.inference_s, "cap": c.steps_cap,
+                        "target_cold": c.cold.get(TARGET), "target_warm": c.warm.get(TARGET)})
+    ts = target_seconds(res)
+    both = [(x, y) for x, y in ts if x is not None and y is not None]
+    out = {"train_cases": a.cases, "coarse": a.coarse, "fine": a.fine,
+           "data_steps": data.steps if data else None, "data_seconds": data.seconds if data else None,
+           "train_iters": a.iters, "train_seconds": t2 - t1, "net": a.load_net or "trained here",
+           "data_final_drop": data.final_residual / data.info["r0"] if data else None,
+           "total_seconds": time.perf_counter() - t0, "tests": summary,
+           "target": TARGET, "reached_cold": sum(x is not None for x, _ in ts),
+           "reached_warm": sum(y is not None for _, y in ts),
+           "median_seconds_cold": float(np.median([x for x, _ in both])) if both else None,
+           "median_seconds_warm": float(np.median([y for _, y in both])) if both else None}
     print(json.dumps(out), flush=True)
     if a.out:
         with open(a.out, "w") as f:

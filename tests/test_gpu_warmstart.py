@@ -1,11 +1,14 @@
 """GPU: what the trained warm-start network gains over the uniform-stream start.
 
-Small version of the pipeline (32 coarse training cases of 24 x 12 x 12,
-two held-out cases of 48 x 24 x 24): the network is trained by the library's
-own forward/backward/Adam kernels on solutions the solver produced, and the
-warm start must begin below the cold start's residual and reach the deepest
-residual decade both starts reach in fewer steps.  The network's output has
-no closed form (parity unpinned); the residual history decides.
+Small version of the pipeline with the grid ratio of the full one (32 coarse
+training cases of 24 x 12 x 12 marched to a 1e-8 drop, three held-out cases
+of 48 x 24 x 24): the network is trained by the library's own
+forward/backward/Adam kernels on converged solutions the solver produced.
+Both starts march with local RK3 steps to one absolute target, 1e-8 of the
+cold start's initial L2(R_rho); the warm start (network inference included)
+must reach it in fewer steps on every case and in fewer wall seconds over
+the median case.  The network's output has no closed form (parity
+unpinned); the residual history decides.
 """
 import numpy as np
 import pytest
@@ -15,18 +18,21 @@ from gpu_util import say
 pytestmark = pytest.mark.gpu
 
 
-def test_warm_start_beats_cold_start():
+def test_warm_start_reaches_the_target_sooner_than_the_cold_start():
     from paper_1710_09995_amd import cases, warmstart
-    data = warmstart.generate(32, seed=0, dims=(24, 12, 12), drop=1e-12, max_steps=3000)
-    say("data", data.x.shape[0], "points, residual", data.info["r0"], "->", data.final_residual)
-    assert data.final_residual < 1e-2 * data.info["r0"]
-    net = warmstart.train(data, iters=800, batch=4096)
-    tests = cases.channel_conditions(2, 12345)
-    res = warmstart.compare(net, tests, dims=(48, 24, 24), max_steps=4000, log=say)
+    data = warmstart.generate(32, seed=0, dims=(24, 12, 12), drop=1e-8, max_steps=40000)
+    say("data", data.x.shape[0], "points,", data.steps, "steps, residual", data.info["r0"], "->",
+        data.final_residual)
+    assert data.final_residual < 1e-8 * data.info["r0"]
+    net = warmstart.train(data, iters=20000, batch=8192)
+    tests = cases.channel_conditions(3, 12345)
+    res = warmstart.compare(net, tests, dims=(48, 24, 24), max_steps=100000, log=say, chunk=500)
+    T = warmstart.TARGET
     for c in res:
+        assert T in c.cold and T in c.warm, (c.mach, c.hb)
+        say(f"  M={c.mach:.3f} h={c.hb:.3f}: to {T:.0e}: cold {c.cold[T][0]} steps {c.cold[T][1]:.2f} s, "
+            f"warm {c.warm[T][0]} steps {c.warm[T][1]:.2f} s (inference {c.inference_s * 1e3:.1f} ms)")
         assert c.r_warm0 < c.r_cold0
-        d = warmstart.deepest_common(c)
-        assert d is not None
-        say(f"  M={c.mach:.3f}: deepest common drop {d:.0e}: cold {c.cold[d][0]} steps, warm {c.warm[d][0]} steps")
-        assert c.warm[d][0] < c.cold[d][0]
-        assert np.isfinite(c.warm_final) and c.warm_final <= c.cold_final * 1.5
+        assert c.warm[T][0] < c.cold[T][0]
+    secs = warmstart.target_seconds(res)
+    assert np.median([w for _, w in secs]) < np.median([c for c, _ in secs])
