@@ -603,6 +603,38 @@ def paper_share_case(nbx: int = 4, nbz: int = 4, ni: int = 512, nj: int = 512, n
     return Case("paper_share", par, dims, nodes, conns, bcs, q0, info={"seed": seed})
 
 
+def coarsen_case(case: Case) -> Case:
+    """The next coarser grid of a multigrid hierarchy: every block keeps every
+    second node along each direction (the coarse cells are unions of 2 x 2 x 2
+    fine cells, nested exactly), and the connection and boundary tables keep
+    their patches with every range halved.  Every extent and patch bound must
+    be even.  The initial state is the uniform stream (a cycle overwrites it
+    with the restricted fine state)."""
+    dims, nodes = [], []
+    for (ni, nj, nk), X in zip(case.dims, case.nodes):
+        if ni % 2 or nj % 2 or nk % 2:
+            raise ValueError(f"block extents {ni, nj, nk} are not all even")
+        dims.append((ni // 2, nj // 2, nk // 2))
+        nodes.append(np.ascontiguousarray(X[:, ::2, ::2, ::2]))
+
+    def half(v):
+        if any(x % 2 for x in v):
+            raise ValueError(f"patch bound {v} is not even")
+        return tuple(x // 2 for x in v)
+    conns = [replace(c, lo=half(c.lo), hi=half(c.hi), nbr_lo=half(c.nbr_lo)) for c in case.conns]
+    bcs = [replace(b, lo=half(b.lo), hi=half(b.hi)) for b in case.bcs]
+    q0 = [uniform_state(d, case.params) for d in dims]
+    return Case(case.name + "_coarse", case.params, dims, nodes, conns, bcs, q0, dict(case.info))
+
+
+def hierarchy(case: Case, nlevels: int) -> List[Case]:
+    """[case, its coarsening, ...], nlevels grids."""
+    out = [case]
+    for _ in range(nlevels - 1):
+        out.append(coarsen_case(out[-1]))
+    return out
+
+
 def split_periodic_box(case: Case, parts=(2, 2, 2)) -> Case:
     """Split a single periodic block into parts[0] x parts[1] x parts[2] blocks.
 
