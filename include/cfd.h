@@ -199,6 +199,39 @@ cfd_status cfd_implicit_work_size(const cfd_ctx* ctx, size_t* bytes);
 cfd_status cfd_step_implicit(cfd_ctx* ctx, double* q_arena_dev, int32_t nsteps, int32_t sweeps, double cfl,
                              void* work_dev, size_t work_bytes, double* hist_dev, hipStream_t stream);
 
+/* Multigrid cycles for steady marches.  The paper's convergence test
+ * (Section 2.3) asks for a residual drop, and the explicit stages of Eqs.
+ * (4)-(6) damp a fine grid's smooth error modes slowly; the paper names no
+ * accelerator.  This is the library's: full approximation storage (FAS) on
+ * nested grids with the RK3 step as the smoother.  levels[0] is the grid
+ * being solved, levels[l + 1] its coarsening (every extent halved: the coarse
+ * grid keeps every second node, the connection and boundary tables every
+ * range halved; the caller builds it as its own context with cfd_create_blocks
+ * and the same parameters).  q_levels[l]: a state arena of level l
+ * (q_levels[0] is the state advanced; the others are working states).
+ *
+ * One V-cycle: going down, on each level l, `pre` RK3 steps of
+ * dQ/dt = -(R_l(Q) + F_l) with the level's own CFL steps (F_0 = 0; the
+ * coarsest level takes `coarse` steps); then the next level's state
+ * Q^0 = sum_children V Q / sum_children V and forcing
+ * F_{l+1} = sum_children V (R_l + F_l) / V_{l+1} - R_{l+1}(Q^0) (so that a
+ * level whose residual vanishes sees none on the coarse grid); going up,
+ * Q_l += Q_{l+1} - Q^0_{l+1} on each coarse cell's 8 children.  With one level
+ * a cycle is `coarse` plain RK3 steps.  hist (device, may be NULL):
+ * [ncycles][12] rows of cfd_step's layout, each the finest level's first step
+ * of the cycle (R without forcing).
+ *
+ * cfd_mg_work_size: bytes of work for the hierarchy (three state-layout
+ * arenas per level).  cfd_mg_cycles: work_dev 256-byte aligned, disjoint
+ * from every level's state; CFD_EINVAL on a hierarchy whose extents do not
+ * halve, different block counts or time-step modes, nlevels outside [1, 16],
+ * pre or coarse outside [0, 1000], overlapping states; CFD_ENOMEM on a short
+ * workspace.  Asynchronous on stream. */
+cfd_status cfd_mg_work_size(cfd_ctx* const* levels, int32_t nlevels, size_t* bytes);
+cfd_status cfd_mg_cycles(cfd_ctx* const* levels, double* const* q_levels, int32_t nlevels, int32_t pre,
+                         int32_t coarse, int32_t ncycles, void* work_dev, size_t work_bytes, double* hist_dev,
+                         hipStream_t stream);
+
 /* Norms: out[0..4] = L2 of r (0 if r_arena_dev is NULL), out[5..9] = sum V q,
  * out[10] = max |r_rho|, out[11] = count of non-finite values in q and r.
  * Deterministic fixed-order reductions.  flags & CFD_NORMS_HOST: `out` is
@@ -562,6 +595,72 @@ cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dims, const in
                                      const double* const* s_dev, const double* const* jinv_dev, void* work_dev,
                                      size_t work_bytes, double gamma, double entropy_fix, double eps, double prandtl,
                                      double mu_inf, double s_star, double dt, int32_t nsteps, hipStream_t stream);
+
+/* Closures of the WCNS-E-5 scheme at walls and the far field (Section 2.2
+ * leaves the conditions at block boundaries to its references; this is the
+ * library's reading).  An owner block whose faces across one direction
+ * `bounded` are physical, and whose other directions are periodic, gets two
+ * ghost blocks, CFD_WCNS5_GHOST cells across `bounded` with the owner's
+ * transverse extents, joined to its low and high faces in an ordinary
+ * joined-block table (the two ghost blocks' far faces joined to each other,
+ * so that every link is mutual).  Every stencil of the owner then runs
+ * unchanged up to the boundary:
+ *
+ * cfd_wcns5_extend_vertices: the vertices the owner and its ghost blocks take
+ * their metrics from.  xv_dev [3][nk'][nj'][ni']: along a periodic direction
+ * d the n_d upper corners 0 .. n_d - 1 (n'_d = n_d; period[3 d + c] is the
+ * grid's displacement over one period), along `bounded` the n_d + 1 vertex
+ * planes -1 .. n_d - 1 (the boundary surfaces are the first and the last).
+ * xe_dev [3][Ek][Ej][Ei]: along a periodic direction E_d = n_d + 5 (vertices
+ * -3 .. n_d + 1, vertex v = vertex v mod n_d plus floor(v / n_d) periods);
+ * along `bounded` E_d = n_d + 1 + 2 CFD_WCNS5_XLAYERS (planes -1 - XLAYERS ..
+ * n_d - 1 + XLAYERS, those beyond the boundary continued linearly from the
+ * two planes at that end: x_(b - m) = x_b + m (x_b - x_(b + 1))).  bounded =
+ * -1 makes every direction periodic.  The owner's metrics
+ * (cfd_wcns5_metrics_ext) come from the window of vertices -3 .. n + 1 along
+ * every direction, the low ghost block's from -8 .. 1 along `bounded`, the
+ * high one's from n - 3 .. n + 6.  CFD_EINVAL on bad extents, a non-finite
+ * period or overlapping input and output.
+ *
+ * cfd_wcns5_fill_ghost_blocks: the ghost blocks' states from the owner's
+ * q_dev [5][nk][nj][ni] (layouts of cfd_wcns5_euler_residual_blocks).  The
+ * ghost cell m = 1 .. 5 cells beyond a wall takes the owner cell m - 1
+ * inside it with the momentum reflected about the boundary face's unit normal
+ * (CFD_BC_SLIPWALL) or negated (CFD_BC_NOSLIP_ADIABATIC), density and energy
+ * copied; every layer beyond the far field (CFD_BC_FARFIELD) takes the
+ * characteristic state of the owner's first cell (Riemann invariants along the
+ * outward normal, freestream rho = p = 1 and velocity uinf).  The normal comes
+ * from the face metrics: the low ghost block's last face (s_lo_dev) and the
+ * owner's last face (s_dev).  kind[0]: the low face, kind[1]: the high face.
+ * CFD_EINVAL on a bad argument or when a ghost state overlaps the owner's
+ * state, a metric array or the other ghost state.
+ *
+ * cfd_wcns5_steps_blocks_closed: cfd_wcns5_ns_steps_blocks with the ghost
+ * blocks of *closure refilled before every stage's residual and the viscous
+ * terms only when viscous != 0 (same workspace size).  The closure is checked
+ * against the table (distinct blocks in range, ghost extents, the ghost
+ * blocks joined to the owner's two faces across `bounded`).  The ghost blocks'
+ * own states after a call are scratch.  Asynchronous on stream. */
+#define CFD_WCNS5_GHOST 5
+#define CFD_WCNS5_XLAYERS 7
+typedef struct {
+  int32_t owner, ghost_lo, ghost_hi;   /* block indices in the joined-block table */
+  int32_t bounded;                     /* the direction 0..2 whose two faces are physical */
+  int32_t kind[2];                     /* cfd_bc_kind of the low and the high face */
+  double uinf[3];                      /* far-field velocity (rho = p = 1) */
+} cfd_wcns5_closure;
+cfd_status cfd_wcns5_extend_vertices(const double* xv_dev, const int32_t n[3], int32_t bounded,
+                                     const double period[9], double* xe_dev, hipStream_t stream);
+cfd_status cfd_wcns5_fill_ghost_blocks(const double* q_dev, double* q_lo_dev, double* q_hi_dev, const double* s_dev,
+                                       const double* s_lo_dev, const int32_t n[3], int32_t bounded,
+                                       const int32_t kind[2], double gamma, const double uinf[3],
+                                       hipStream_t stream);
+cfd_status cfd_wcns5_steps_blocks_closed(int32_t nblk, const int32_t* dims, const int32_t* nbr, double* const* q_dev,
+                                         const double* const* s_dev, const double* const* jinv_dev,
+                                         const cfd_wcns5_closure* closure, int32_t viscous, void* work_dev,
+                                         size_t work_bytes, double gamma, double entropy_fix, double eps,
+                                         double prandtl, double mu_inf, double s_star, double dt, int32_t nsteps,
+                                         hipStream_t stream);
 
 /* The fourth-order viscous terms of cfd_c4_viscous_add_curv_periodic on blocks
  * joined face to face (the table, extents and pointer arrays as for

@@ -53,6 +53,11 @@ class Tuning(C.Structure):
                 ("use_graph", C.c_int32), ("order", C.c_int32)]
 
 
+class WcnsClosure(C.Structure):
+    _fields_ = [("owner", C.c_int32), ("ghost_lo", C.c_int32), ("ghost_hi", C.c_int32), ("bounded", C.c_int32),
+                ("kind", C.c_int32 * 2), ("uinf", C.c_double * 3)]
+
+
 class MlpDesc(C.Structure):
     _fields_ = [("d_in", C.c_int32), ("d_hidden", C.c_int32), ("n_hidden", C.c_int32), ("d_out", C.c_int32),
                 ("activation", C.c_int32)]
@@ -60,7 +65,7 @@ class MlpDesc(C.Structure):
 
 EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy", "cfd_set_tuning",
            "cfd_get_tuning", "cfd_fill_ghosts", "cfd_residual", "cfd_step", "cfd_implicit_work_size",
-           "cfd_step_implicit", "cfd_norms",
+           "cfd_step_implicit", "cfd_mg_work_size", "cfd_mg_cycles", "cfd_norms",
            "cfd_time_step", "cfd_copy_metrics", "cfd_set_profiling", "cfd_profile_read",
            "cfd_mlp_sizes", "cfd_mlp_forward", "cfd_mlp_mse", "cfd_mlp_backward", "cfd_mlp_adam",
            "cfd_mlp_to_bf16", "cfd_mlp_features", "cfd_mlp_targets", "cfd_mlp_to_state",
@@ -75,7 +80,8 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_c4_viscous_add_blocks", "cfd_wcns5_ns_step_work_bytes", "cfd_wcns5_ns_steps_curv_periodic",
            "cfd_wcns5_implicit_step_work_bytes", "cfd_wcns5_implicit_steps_curv_periodic",
            "cfd_wcns5_implicit_blocks_work_bytes", "cfd_wcns5_implicit_steps_blocks", "cfd_wcns5_ns_blocks_work_bytes",
-           "cfd_wcns5_ns_steps_blocks",
+           "cfd_wcns5_ns_steps_blocks", "cfd_wcns5_extend_vertices", "cfd_wcns5_fill_ghost_blocks",
+           "cfd_wcns5_steps_blocks_closed",
            "cfd_status_string", "cfd_last_error"]
 
 _lib = None
@@ -174,6 +180,14 @@ def lib(build_if_missing: bool = True):
     L.cfd_wcns5_ns_steps_blocks.argtypes = [i32, i32p, i32p, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp,
                                             C.c_size_t, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                             C.c_double, C.c_double, i32, vp]
+    L.cfd_mg_work_size.argtypes = [C.POINTER(vp), i32, C.POINTER(C.c_size_t)]
+    L.cfd_mg_cycles.argtypes = [C.POINTER(vp), C.POINTER(vp), i32, i32, i32, i32, vp, C.c_size_t, vp, vp]
+    L.cfd_wcns5_extend_vertices.argtypes = [vp, i32p, i32, C.POINTER(C.c_double), vp, vp]
+    L.cfd_wcns5_fill_ghost_blocks.argtypes = [vp, vp, vp, vp, vp, i32p, i32, i32p, C.c_double,
+                                              C.POINTER(C.c_double), vp]
+    L.cfd_wcns5_steps_blocks_closed.argtypes = [i32, i32p, i32p, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                                C.POINTER(WcnsClosure), i32, vp, C.c_size_t, C.c_double, C.c_double,
+                                                C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, i32, vp]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]
@@ -702,6 +716,158 @@ def wcns5_ns_steps_blocks(qs, Ss, jinvs, nbr, dt: float, nsteps: int, gamma: flo
                                            _stream_handle(torch, stream)))
     return qs
 
+
+
+class Multigrid:
+    """Multigrid V-cycles (cfd_mg_cycles) for a solver's steady march: the
+    solver's grid and nlevels - 1 coarsenings (cases.hierarchy), each level a
+    Solver of its own whose state is a working state of the cycle."""
+
+    def __init__(self, solver, nlevels: int = 3, pre: int = 1, coarse: int = 2):
+        from . import cases as _cases
+        torch = solver.torch
+        self.torch = torch
+        self.solver = solver
+        self.pre, self.coarse = int(pre), int(coarse)
+        hier = _cases.hierarchy(solver.case, nlevels)
+        self.levels = [solver] + [Solver(c, device=str(solver.device), stream=solver.stream) for c in hier[1:]]
+        self._ctx = (C.c_void_p * nlevels)(*[lv.ctx.value for lv in self.levels])
+        nb = C.c_size_t()
+        _check(lib().cfd_mg_work_size(self._ctx, nlevels, C.byref(nb)))
+        self._work = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=solver.device)
+        base = self._work.data_ptr()
+        self._w = C.c_void_p(base + (-base) % 256)
+        self._wb = C.c_size_t(int(nb.value))
+
+    def cycles(self, n: int, hist: bool = True, arena=None):
+        """n V-cycles in place on the solver's state (or arena); returns the
+        history [n, 12] (device) or None."""
+        torch = self.torch
+        q0 = self.solver.q if arena is None else arena
+        qs = (C.c_void_p * len(self.levels))(*([_ptr(q0)] + [_ptr(lv.q) for lv in self.levels[1:]]))
+        h = torch.zeros((n, 12), dtype=torch.float64, device=self.solver.device) if hist and n > 0 else None
+        _check(lib().cfd_mg_cycles(self._ctx, qs, len(self.levels), self.pre, self.coarse, int(n), self._w, self._wb,
+                                   _ptr(h) if h is not None else None, self.solver._s()), self.solver.ctx)
+        return h
+
+    def close(self):
+        for lv in self.levels[1:]:
+            lv.close()
+        self.levels = self.levels[:1]
+
+
+WCNS5_GHOST = 5
+WCNS5_XLAYERS = 7
+
+
+def wcns5_extend_vertices(xv, bounded: int, period, stream=None):
+    """Vertices for the closures (cfd_wcns5_extend_vertices): xv a contiguous
+    FP64 CUDA tensor [3, nk', nj', ni'] (n_d upper corners along periodic
+    directions, n_d + 1 planes along `bounded`), period [3][3] the
+    displacement over one period per direction.  Returns the extended
+    vertices [3, Ek, Ej, Ei]."""
+    import torch
+    if xv.dtype != torch.float64 or not xv.is_cuda or not xv.is_contiguous() or xv.dim() != 4 or xv.shape[0] != 3:
+        raise ValueError("xv must be a contiguous float64 CUDA tensor [3, nk', nj', ni']")
+    n = [int(xv.shape[3]), int(xv.shape[2]), int(xv.shape[1])]
+    if bounded in (0, 1, 2):
+        n[bounded] -= 1
+    e = [n[d] + 1 + 2 * WCNS5_XLAYERS if d == bounded else n[d] + 5 for d in range(3)]
+    xe = torch.empty((3, e[2], e[1], e[0]), dtype=torch.float64, device=xv.device)
+    per = (C.c_double * 9)(*[float(v) for row in period for v in row])
+    _check(lib().cfd_wcns5_extend_vertices(_ptr(xv), (C.c_int32 * 3)(*n), int(bounded), per, _ptr(xe),
+                                           _stream_handle(torch, stream)))
+    return xe
+
+
+def wcns5_fill_ghost_blocks(q, q_lo, q_hi, S, S_lo, bounded: int, kinds, uinf, gamma: float = 1.4, stream=None):
+    """Ghost-block states from the owner's state (cfd_wcns5_fill_ghost_blocks),
+    in place on q_lo and q_hi."""
+    import torch
+    nk, nj, ni = (int(v) for v in q.shape[1:])
+    _check(lib().cfd_wcns5_fill_ghost_blocks(_ptr(q), _ptr(q_lo), _ptr(q_hi), _ptr(S), _ptr(S_lo),
+                                             (C.c_int32 * 3)(ni, nj, nk), int(bounded),
+                                             (C.c_int32 * 2)(*[int(k) for k in kinds]), float(gamma),
+                                             (C.c_double * 3)(*[float(u) for u in uinf]),
+                                             _stream_handle(torch, stream)))
+
+
+class WcnsClosedBlock:
+    """A curvilinear block periodic along two directions whose two faces across
+    the third (`bounded`) are walls or the far field, closed by ghost blocks
+    (cfd_wcns5_extend_vertices, cfd_wcns5_metrics_ext, cfd_wcns5_fill_ghost_blocks,
+    and the joined-block residual, viscous terms and RK3 steps).  xv: the
+    owner's vertices as for wcns5_extend_vertices (a CUDA tensor); kinds: the
+    cfd_bc_kind of the low and high face; uinf: the far-field velocity."""
+
+    def __init__(self, xv, period, bounded: int, kinds, uinf=(0.0, 0.0, 0.0), gamma: float = 1.4, stream=None):
+        import torch
+        self.torch = torch
+        self.stream = stream
+        self.bounded, self.kinds, self.uinf, self.gamma = int(bounded), tuple(kinds), tuple(uinf), float(gamma)
+        xe = wcns5_extend_vertices(xv, bounded, period, stream)
+        n = [int(xv.shape[3]), int(xv.shape[2]), int(xv.shape[1])]
+        n[bounded] -= 1
+        self.n = tuple(n)
+        d = self.bounded
+        org = [3, 3, 3]
+        org[d] = WCNS5_XLAYERS + 1
+        mets = []
+        for lo, ext in ((0, n[d]), (-WCNS5_GHOST, WCNS5_GHOST), (n[d], WCNS5_GHOST)):
+            sl = []
+            for a in (2, 1, 0):
+                start = org[a] - 3 + (lo if a == d else 0)
+                cnt = (ext if a == d else n[a]) + 5
+                sl.append(slice(start, start + cnt))
+            mets.append(wcns5_metrics_ext(xe[(slice(None),) + tuple(sl)].contiguous(), stream))
+        self.S = [m[0] for m in mets]
+        self.jinv = [m[1] for m in mets]
+        gd = list(n)
+        gd[d] = WCNS5_GHOST
+        self.dims = [tuple(n), tuple(gd), tuple(gd)]
+        nbr = [[b] * 6 for b in range(3)]
+        nbr[0][2 * d], nbr[1][2 * d + 1] = 1, 0
+        nbr[0][2 * d + 1], nbr[2][2 * d] = 2, 0
+        nbr[1][2 * d], nbr[2][2 * d + 1] = 2, 1
+        self.nbr = nbr
+        self.ghosts = [torch.zeros((5, g[2], g[1], g[0]), dtype=torch.float64, device=xv.device)
+                       for g in self.dims[1:]]
+
+    def fill(self, q):
+        wcns5_fill_ghost_blocks(q, self.ghosts[0], self.ghosts[1], self.S[0], self.S[1], self.bounded, self.kinds,
+                                self.uinf, self.gamma, self.stream)
+
+    def residual(self, q, entropy_fix: float = 0.1, eps: float = 1e-6, viscous=None):
+        """R of the owner (dQ/dt = -R); viscous = (prandtl, mu_inf, s_star) adds the
+        fourth-order viscous terms."""
+        self.fill(q)
+        qs = [q] + self.ghosts
+        rs = wcns5_euler_residual_blocks(qs, self.S, self.jinv, self.nbr, self.gamma, entropy_fix, eps,
+                                         stream=self.stream)
+        if viscous is not None:
+            c4_viscous_add_blocks(qs, rs, self.S, self.jinv, self.nbr, self.gamma, *viscous, stream=self.stream)
+        return rs[0]
+
+    def steps(self, q, dt: float, nsteps: int, entropy_fix: float = 0.1, eps: float = 1e-6, viscous=None,
+              work=None):
+        """nsteps RK3 steps in place on q (cfd_wcns5_steps_blocks_closed)."""
+        torch = self.torch
+        qs = [q] + self.ghosts
+        dims = (C.c_int32 * 9)(*[v for m in self.dims for v in m])
+        nb = (C.c_int32 * 18)(*[v for row in self.nbr for v in row])
+        nbytes = C.c_size_t()
+        _check(lib().cfd_wcns5_ns_blocks_work_bytes(3, dims, nb, C.byref(nbytes)))
+        if work is None or work.numel() * work.element_size() < nbytes.value:
+            work = _scratch(torch, nbytes.value, q.device, self.stream)
+        cl = WcnsClosure(0, 1, 2, self.bounded, (C.c_int32 * 2)(*self.kinds), (C.c_double * 3)(*self.uinf))
+        pr, mu, ss = viscous if viscous is not None else (0.72, 0.0, 110.4 / 288.15)
+        ptrs = lambda ts: (C.c_void_p * 3)(*[_ptr(t) for t in ts])   # noqa: E731
+        _check(lib().cfd_wcns5_steps_blocks_closed(3, dims, nb, ptrs(qs), ptrs(self.S), ptrs(self.jinv), C.byref(cl),
+                                                   1 if viscous is not None else 0, _ptr(work), nbytes.value,
+                                                   self.gamma, float(entropy_fix), float(eps), float(pr), float(mu),
+                                                   float(ss), float(dt), int(nsteps),
+                                                   _stream_handle(torch, self.stream)))
+        return q
 
 
 def _on_device(torch, x, device):

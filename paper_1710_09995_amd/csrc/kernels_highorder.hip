@@ -2110,12 +2110,190 @@ extern "C" cfd_status cfd_wcns5_ns_blocks_work_bytes(int32_t nblk, const int32_t
   });
 }
 
-extern "C" cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dims, const int32_t* nbr,
-                                                double* const* q_dev, const double* const* s_dev,
-                                                const double* const* jinv_dev, void* work_dev, size_t work_bytes,
-                                                double gamma, double entropy_fix, double eps, double prandtl,
-                                                double mu_inf, double s_star, double dt, int32_t nsteps,
-                                                hipStream_t stream) {
+namespace cfd {
+
+// ------------------------------------------------ closures at physical faces
+// Walls and the far field of the WCNS-E-5 scheme as ghost blocks: five-cell
+// blocks joined to an owner across the two faces of one bounded direction
+// (whose transverse directions are periodic), with metrics from the owner's
+// vertex lines extended by linear extrapolation and states refilled from the
+// owner before every residual (mirrored for walls, the characteristic state
+// for the far field).  The owner's residual is then the joined-block residual.
+
+constexpr int WCNS_GHOST = 5;
+
+struct Period9 {
+  double p[9];   // displacement over one period along direction d: p[3 d + component]
+};
+
+// Vertices of a block extended for its metrics and its ghost blocks'
+// (cfd_wcns5_extend_vertices): along a periodic direction vertex v of the
+// output is vertex v mod n plus floor(v / n) periods; along the bounded one
+// plane pl = -XL .. n + XL, copied for 0 <= pl <= n, else continued linearly
+// from the two planes at that end.
+__global__ void __launch_bounds__(256) k_extend_vertices(const double* __restrict__ xv, int ni, int nj, int nk,
+                                                         int bounded, Period9 P, double* __restrict__ xe, int ei,
+                                                         int ej, int ek) {
+  const int n[3] = {ni, nj, nk};
+  const int s[3] = {ni + (bounded == 0), nj + (bounded == 1), nk + (bounded == 2)};
+  const int64_t scells = (int64_t)s[0] * s[1] * s[2];
+  const int64_t total = (int64_t)ei * ej * ek;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int e[3] = {(int)(t % ei), (int)((t / ei) % ej), (int)(t / ((int64_t)ei * ej))};
+    int src[3], q[3] = {0, 0, 0}, a = 0, b = 0, m = 0;
+    for (int d = 0; d < 3; ++d) {
+      if (d == bounded) {
+        const int pl = e[d] - CFD_WCNS5_XLAYERS;
+        if (pl < 0) {
+          a = 0, b = 1, m = -pl;
+        } else if (pl > n[d]) {
+          a = n[d], b = n[d] - 1, m = pl - n[d];
+        } else {
+          a = pl, b = pl, m = 0;
+        }
+        src[d] = 0;
+      } else {
+        const int v = e[d] - 3;
+        const int w = ((v % n[d]) + n[d]) % n[d];
+        src[d] = w;
+        q[d] = (v - w) / n[d];
+      }
+    }
+    for (int c = 0; c < 3; ++c) {
+      double x0, x1;
+      int i0[3] = {src[0], src[1], src[2]}, i1[3] = {src[0], src[1], src[2]};
+      if (bounded >= 0) {
+        i0[bounded] = a;
+        i1[bounded] = b;
+      }
+      x0 = xv[c * scells + ((int64_t)i0[2] * s[1] + i0[1]) * s[0] + i0[0]];
+      x1 = xv[c * scells + ((int64_t)i1[2] * s[1] + i1[1]) * s[0] + i1[0]];
+      for (int d = 0; d < 3; ++d)
+        if (d != bounded) {
+          x0 = x0 + (double)q[d] * P.p[3 * d + c];
+          x1 = x1 + (double)q[d] * P.p[3 * d + c];
+        }
+      xe[c * total + t] = m == 0 ? x0 : x0 + (double)m * (x0 - x1);
+    }
+  }
+}
+
+// Ghost-block states (cfd_wcns5_fill_ghost_blocks): one thread per side,
+// layer m = 1 .. 5 and transverse point.
+__global__ void __launch_bounds__(256) k_fill_ghost_blocks(const double* __restrict__ q, double* __restrict__ qlo,
+                                                           double* __restrict__ qhi, const double* __restrict__ slo,
+                                                           const double* __restrict__ sown, int ni, int nj, int nk,
+                                                           int d, int kind_lo, int kind_hi, double gamma, double ux,
+                                                           double uy, double uz) {
+  const int n[3] = {ni, nj, nk};
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  const int64_t npt = (int64_t)n[t1] * n[t2];
+  const int64_t total = 2 * WCNS_GHOST * npt;
+  int gd[3] = {ni, nj, nk};
+  gd[d] = WCNS_GHOST;
+  const int64_t ocells = (int64_t)ni * nj * nk, gcells = (int64_t)gd[0] * gd[1] * gd[2];
+  const double uinf[3] = {ux, uy, uz};
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pt = t % npt;
+    const int m = 1 + (int)((t / npt) % WCNS_GHOST);
+    const int side = (int)(t / (npt * WCNS_GHOST));
+    int c[3];
+    c[t1] = (int)(pt % n[t1]);
+    c[t2] = (int)(pt / n[t1]);
+    auto own_at = [&](int along) {
+      int x[3] = {c[0], c[1], c[2]};
+      x[d] = along;
+      return ((int64_t)x[2] * nj + x[1]) * ni + x[0];
+    };
+    auto ghost_at = [&](int along) {
+      int x[3] = {c[0], c[1], c[2]};
+      x[d] = along;
+      return ((int64_t)x[2] * gd[1] + x[1]) * gd[0] + x[0];
+    };
+    // unit normal (+d) of the boundary face: the low ghost block's last face,
+    // or the owner's last face
+    const double* sb = side == 0 ? slo : sown;
+    const int64_t fb = side == 0 ? ghost_at(WCNS_GHOST - 1) : own_at(n[d] - 1);
+    const int64_t fc = side == 0 ? gcells : ocells;
+    const double sx = sb[(3 * d) * fc + fb], sy = sb[(3 * d + 1) * fc + fb], sz = sb[(3 * d + 2) * fc + fb];
+    const double nrm = sqrt(sx * sx + sy * sy + sz * sz);
+    const double nx = sx / nrm, ny = sy / nrm, nz = sz / nrm;
+    const int kind = side == 0 ? kind_lo : kind_hi;
+    double qi[5], qg[5];
+    if (kind == CFD_BC_FARFIELD) {
+      const int64_t o0 = own_at(side == 0 ? 0 : n[d] - 1);
+      for (int v = 0; v < 5; ++v) qi[v] = q[v * ocells + o0];
+      const double sg = side == 0 ? -1.0 : 1.0;
+      farfield_state(qi, sg * nx, sg * ny, sg * nz, gamma, uinf, qg);
+    } else {
+      const int64_t om = own_at(side == 0 ? m - 1 : n[d] - m);
+      for (int v = 0; v < 5; ++v) qi[v] = q[v * ocells + om];
+      qg[0] = qi[0];
+      qg[4] = qi[4];
+      if (kind == CFD_BC_SLIPWALL) {
+        const double mn = qi[1] * nx + qi[2] * ny + qi[3] * nz;
+        qg[1] = qi[1] - 2.0 * mn * nx;
+        qg[2] = qi[2] - 2.0 * mn * ny;
+        qg[3] = qi[3] - 2.0 * mn * nz;
+      } else {
+        qg[1] = -qi[1];
+        qg[2] = -qi[2];
+        qg[3] = -qi[3];
+      }
+    }
+    double* qd = side == 0 ? qlo : qhi;
+    const int64_t og = ghost_at(side == 0 ? WCNS_GHOST - m : m - 1);
+    for (int v = 0; v < 5; ++v) qd[v * gcells + og] = qg[v];
+  }
+}
+
+void fill_ghost_blocks_launch(const double* q, double* qlo, double* qhi, const double* slo, const double* sown,
+                              const int32_t n[3], int d, const int32_t kind[2], double gamma, const double uinf[3],
+                              hipStream_t stream) {
+  const int64_t total = 2 * WCNS_GHOST * (int64_t)n[(d + 1) % 3] * n[(d + 2) % 3];
+  hipLaunchKernelGGL(k_fill_ghost_blocks, dim3(grid_for(total)), dim3(256), 0, stream, q, qlo, qhi, slo, sown, n[0],
+                     n[1], n[2], d, kind[0], kind[1], gamma, uinf[0], uinf[1], uinf[2]);
+}
+
+}  // namespace cfd
+
+namespace {
+
+// Checks a closure against the joined-block table: indices in range and
+// distinct, the ghost blocks five cells across the bounded direction with the
+// owner's transverse extents and joined to the owner's two faces, the kinds
+// known, the far-field velocity finite.
+void check_closure(int32_t nblk, const int32_t* dims, const int32_t* nbr, const cfd_wcns5_closure& c) {
+  const int d = c.bounded;
+  if (d < 0 || d > 2) cfd::host_fail(CFD_EINVAL, "closure: bounded must be 0, 1 or 2");
+  const int32_t b[3] = {c.owner, c.ghost_lo, c.ghost_hi};
+  for (int x = 0; x < 3; ++x)
+    if (b[x] < 0 || b[x] >= nblk) cfd::host_fail(CFD_EINVAL, "closure: block index out of range");
+  if (b[0] == b[1] || b[0] == b[2] || b[1] == b[2]) cfd::host_fail(CFD_EINVAL, "closure: blocks must be distinct");
+  for (int x = 1; x < 3; ++x)
+    for (int t = 0; t < 3; ++t) {
+      const int want = t == d ? cfd::WCNS_GHOST : dims[3 * c.owner + t];
+      if (dims[3 * b[x] + t] != want)
+        cfd::host_fail(CFD_EINVAL, "closure: a ghost block must be 5 cells across the bounded direction, with the "
+                                   "owner's transverse extents");
+    }
+  if (nbr[6 * c.owner + 2 * d] != c.ghost_lo || nbr[6 * c.owner + 2 * d + 1] != c.ghost_hi)
+    cfd::host_fail(CFD_EINVAL, "closure: the ghost blocks must be joined to the owner's two bounded faces");
+  for (int x = 0; x < 2; ++x)
+    if (c.kind[x] != CFD_BC_FARFIELD && c.kind[x] != CFD_BC_SLIPWALL && c.kind[x] != CFD_BC_NOSLIP_ADIABATIC)
+      cfd::host_fail(CFD_EINVAL, "closure: kind must be CFD_BC_FARFIELD, CFD_BC_SLIPWALL or CFD_BC_NOSLIP_ADIABATIC");
+  for (int x = 0; x < 3; ++x)
+    if (!std::isfinite(c.uinf[x])) cfd::host_fail(CFD_EINVAL, "closure: far-field velocity must be finite");
+}
+
+// RK3 steps on joined blocks (cfd_wcns5_ns_steps_blocks), with the ghost
+// blocks of `closure` (if any) refilled before every stage and the viscous
+// terms only when `viscous`.
+cfd_status ns_steps_blocks_impl(int32_t nblk, const int32_t* dims, const int32_t* nbr, double* const* q_dev,
+                                const double* const* s_dev, const double* const* jinv_dev,
+                                const cfd_wcns5_closure* closure, bool viscous, void* work_dev, size_t work_bytes,
+                                double gamma, double entropy_fix, double eps, double prandtl, double mu_inf,
+                                double s_star, double dt, int32_t nsteps, hipStream_t stream) {
   return cfd::host_guarded([&] {
     const size_t rscratch = check_seams(nblk, dims, nbr);
     if (!q_dev || !s_dev || !jinv_dev || !work_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
@@ -2126,6 +2304,7 @@ extern "C" cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dim
       cfd::host_fail(CFD_EINVAL, "bad gas parameters");
     if (!(dt > 0.0) || !std::isfinite(dt)) cfd::host_fail(CFD_EINVAL, "dt must be positive and finite");
     if (nsteps < 0) cfd::host_fail(CFD_EINVAL, "nsteps must be >= 0");
+    if (closure) check_closure(nblk, dims, nbr, *closure);
     std::vector<int64_t> off(nblk + 1, 0);
     size_t vscratch = 0;
     for (int b = 0; b < nblk; ++b) {
@@ -2153,10 +2332,15 @@ extern "C" cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dim
     const double a[3] = {0.0, 0.75, 1.0 / 3.0}, bb[3] = {1.0, 0.25, 2.0 / 3.0};
     for (int it = 0; it < nsteps; ++it)
       for (int st = 0; st < 3; ++st) {
+        if (closure)
+          cfd::fill_ghost_blocks_launch(q_dev[closure->owner], q_dev[closure->ghost_lo], q_dev[closure->ghost_hi],
+                                        s_dev[closure->ghost_lo], s_dev[closure->owner], dims + 3 * closure->owner,
+                                        closure->bounded, closure->kind, gamma, closure->uinf, stream);
         cfd::wcns5_blocks_residual_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, R.data(), work_dev, gamma,
                                           entropy_fix, eps, stream);
-        cfd::c4_viscous_blocks_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, R.data(),
-                                      static_cast<double*>(work_dev), vgas, stream);
+        if (viscous)
+          cfd::c4_viscous_blocks_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, R.data(),
+                                        static_cast<double*>(work_dev), vgas, stream);
         for (int b = 0; b < nblk; ++b) {
           const int64_t nv = 5 * block_cells(dims, b);
           hipLaunchKernelGGL(cfd::k_rk3_stage, dim3(cfd::grid_for(nv)), dim3(256), 0, stream, q_dev[b], qn[b], R[b],
@@ -2165,5 +2349,81 @@ extern "C" cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dim
       }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  });
+}
+
+}  // namespace
+
+extern "C" cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dims, const int32_t* nbr,
+                                                double* const* q_dev, const double* const* s_dev,
+                                                const double* const* jinv_dev, void* work_dev, size_t work_bytes,
+                                                double gamma, double entropy_fix, double eps, double prandtl,
+                                                double mu_inf, double s_star, double dt, int32_t nsteps,
+                                                hipStream_t stream) {
+  return ns_steps_blocks_impl(nblk, dims, nbr, q_dev, s_dev, jinv_dev, nullptr, true, work_dev, work_bytes, gamma,
+                              entropy_fix, eps, prandtl, mu_inf, s_star, dt, nsteps, stream);
+}
+
+extern "C" cfd_status cfd_wcns5_steps_blocks_closed(int32_t nblk, const int32_t* dims, const int32_t* nbr,
+                                                    double* const* q_dev, const double* const* s_dev,
+                                                    const double* const* jinv_dev, const cfd_wcns5_closure* closure,
+                                                    int32_t viscous, void* work_dev, size_t work_bytes, double gamma,
+                                                    double entropy_fix, double eps, double prandtl, double mu_inf,
+                                                    double s_star, double dt, int32_t nsteps, hipStream_t stream) {
+  if (!closure) return cfd::host_guarded([] { cfd::host_fail(CFD_EINVAL, "NULL closure"); });
+  return ns_steps_blocks_impl(nblk, dims, nbr, q_dev, s_dev, jinv_dev, closure, viscous != 0, work_dev, work_bytes,
+                              gamma, entropy_fix, eps, prandtl, mu_inf, s_star, dt, nsteps, stream);
+}
+
+extern "C" cfd_status cfd_wcns5_extend_vertices(const double* xv_dev, const int32_t n[3], int32_t bounded,
+                                                const double period[9], double* xe_dev, hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!xv_dev || !n || !period || !xe_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (bounded < -1 || bounded > 2) cfd::host_fail(CFD_EINVAL, "bounded must be -1, 0, 1 or 2");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    for (int x = 0; x < 9; ++x)
+      if (!std::isfinite(period[x])) cfd::host_fail(CFD_EINVAL, "period must be finite");
+    int64_t e[3], sv = 1, ev = 1;
+    for (int d = 0; d < 3; ++d) {
+      e[d] = d == bounded ? n[d] + 1 + 2 * CFD_WCNS5_XLAYERS : n[d] + 5;
+      sv *= n[d] + (d == bounded);
+      ev *= e[d];
+    }
+    if (ev > ((int64_t)1 << 34)) cfd::host_fail(CFD_EINVAL, "block too large");
+    if (!cfd::apart(xv_dev, 24 * sv, xe_dev, 24 * ev)) cfd::host_fail(CFD_EINVAL, "input and output overlap");
+    cfd::Period9 P;
+    for (int x = 0; x < 9; ++x) P.p[x] = period[x];
+    hipLaunchKernelGGL(cfd::k_extend_vertices, dim3(cfd::grid_for(ev)), dim3(256), 0, stream, xv_dev, n[0], n[1], n[2],
+                       bounded, P, xe_dev, (int)e[0], (int)e[1], (int)e[2]);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(err));
+  });
+}
+
+extern "C" cfd_status cfd_wcns5_fill_ghost_blocks(const double* q_dev, double* q_lo_dev, double* q_hi_dev,
+                                                  const double* s_dev, const double* s_lo_dev, const int32_t n[3],
+                                                  int32_t bounded, const int32_t kind[2], double gamma,
+                                                  const double uinf[3], hipStream_t stream) {
+  return cfd::host_guarded([&] {
+    if (!q_dev || !q_lo_dev || !q_hi_dev || !s_dev || !s_lo_dev || !n || !kind || !uinf)
+      cfd::host_fail(CFD_EINVAL, "NULL argument");
+    if (bounded < 0 || bounded > 2) cfd::host_fail(CFD_EINVAL, "bounded must be 0, 1 or 2");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) cfd::host_fail(CFD_EINVAL, "gamma must exceed 1");
+    for (int x = 0; x < 2; ++x)
+      if (kind[x] != CFD_BC_FARFIELD && kind[x] != CFD_BC_SLIPWALL && kind[x] != CFD_BC_NOSLIP_ADIABATIC)
+        cfd::host_fail(CFD_EINVAL, "kind must be CFD_BC_FARFIELD, CFD_BC_SLIPWALL or CFD_BC_NOSLIP_ADIABATIC");
+    for (int x = 0; x < 3; ++x)
+      if (!std::isfinite(uinf[x])) cfd::host_fail(CFD_EINVAL, "uinf must be finite");
+    const int64_t oc = (int64_t)n[0] * n[1] * n[2];
+    if (oc > ((int64_t)1 << 34)) cfd::host_fail(CFD_EINVAL, "block too large");
+    const int64_t gc = oc / n[bounded] * cfd::WCNS_GHOST;
+    std::vector<cfd::ArgSpan> spans{cfd::span(q_dev, 40 * oc, false), cfd::span(s_dev, 72 * oc, false),
+                                    cfd::span(s_lo_dev, 72 * gc, false), cfd::span(q_lo_dev, 40 * gc, true),
+                                    cfd::span(q_hi_dev, 40 * gc, true)};
+    cfd::check_spans(spans, "a ghost state overlaps the owner's state, a metric array or the other ghost state");
+    cfd::fill_ghost_blocks_launch(q_dev, q_lo_dev, q_hi_dev, s_lo_dev, s_dev, n, bounded, kind, gamma, uinf, stream);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(err));
   });
 }
