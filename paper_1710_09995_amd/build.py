@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcfd.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["runtime.hip", "kernels_grid.hip", "kernels_stage.hip", "kernels_tiled.hip", "kernels_ring.hip",
-           "kernels_mlp.hip", "kernels_highorder.hip", "kernels_implicit.hip", "partition.cpp"]
+           "kernels_mlp.hip", "kernels_highorder.hip", "kernels_implicit.hip", "kernels_mg.hip", "partition.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=on: a*b+c is fused only within one source expression, so a face

@@ -20,6 +20,7 @@
 #include "cfd_internal.hpp"
 #include "host_services.hpp"
 #include "implicit.hpp"
+#include "mg.hpp"
 
 namespace cfd {
 void launch_copy_nodes(const double* src, double* x, const BlockDesc& B, hipStream_t s);
@@ -634,9 +635,17 @@ bool fused_dt(const cfd_ctx* c) { return c->tun.kernel == 2 && c->params.viscous
 //    finalize gives the same totals for every tuning and stage kernel.
 // (Taking dt of the new state inside the tiled kernel's third stage was
 // measured slower: its extra metric loads cost more than the separate pass.)
-void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history) {
+void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history, const double* force = nullptr,
+                  bool no_fuse = false) {
   const bool ring = c->tun.kernel == 2;
-  const bool fuse = fused_dt(c);
+  const bool fuse = fused_dt(c) && !no_fuse && !force;
+  const int nwg_f = dt_nwg(c);
+  // a multigrid level's forcing: each stage's output minus b dt F
+  auto forced = [&](double* out, double b) {
+    if (force)
+      launch_mg_force(out, force, c->params.local_dt ? c->scal() : c->d_dt(), c->params.local_dt, b, c->dblocks,
+                      c->nblk, c->nchunks, nwg_f, s);
+  };
   const double inv_n = 1.0 / (double)c->ncells;
   const int nwg_dt = dt_nwg(c);
   ghost_fill(c, q, s);
@@ -663,6 +672,7 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history) {
     });
     launch_finalize(c->part_dt(), 2 * nwg_dt, 1, inv_n, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
   }
+  forced(c->qa(), 1.0);
   A.rout = nullptr;
   A.partials = nullptr;
   ghost_fill(c, c->qa(), s);
@@ -671,6 +681,7 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history) {
   A.a = 0.75;
   A.b = 0.25;
   launch_stage(c, A, 2, s);
+  forced(c->qb(), 0.25);
   ghost_fill(c, c->qb(), s);
   A.qs = c->qb();
   A.out = q;
@@ -684,6 +695,7 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history) {
   } else {
     launch_stage(c, A, 2, s);
   }
+  forced(q, 2.0 / 3.0);
 }
 
 template <typename F>
@@ -1121,6 +1133,121 @@ cfd_status cfd_step_implicit(cfd_ctx* c, double* q, int32_t nsteps, int32_t swee
       if (hist)
         HIPCHK(hipMemcpyAsync(hist + (int64_t)n * NHIST, c->d_hist(), sizeof(double) * NHIST,
                               hipMemcpyDeviceToDevice, s));
+    }
+  });
+}
+
+// ---------------------------------------------------------------- multigrid
+// Levels of a hierarchy: the same block count, every extent of level l + 1
+// half the one of level l (the coarse grid keeps every second node; the
+// tables are the caller's coarsening), the same time-step mode.
+void check_hierarchy(cfd_ctx* const* lv, int n) {
+  if (!lv) fail(CFD_EINVAL, "NULL argument");
+  if (n < 1 || n > 16) fail(CFD_EINVAL, "nlevels must be in [1, 16]");
+  for (int l = 0; l < n; ++l)
+    if (!lv[l]) fail(CFD_EINVAL, "NULL level");
+  for (int l = 1; l < n; ++l) {
+    if (lv[l] == lv[l - 1]) fail(CFD_EINVAL, "levels must be distinct contexts");
+    if (lv[l]->nblk != lv[0]->nblk) fail(CFD_EINVAL, "every level must have the same blocks");
+    if (lv[l]->params.local_dt != lv[0]->params.local_dt)
+      fail(CFD_EINVAL, "every level must take the same time-step mode");
+    for (int b = 0; b < lv[0]->nblk; ++b) {
+      const cfd_dims& f = lv[l - 1]->dims[b];
+      const cfd_dims& c = lv[l]->dims[b];
+      if (f.ni != 2 * c.ni || f.nj != 2 * c.nj || f.nk != 2 * c.nk)
+        fail(CFD_EINVAL, "every extent of a level must be twice the next level's");
+    }
+  }
+}
+
+// Per level: its residual, its forcing and its restricted initial state, each
+// a state-layout arena of the level, 256-byte aligned.
+size_t mg_level_bytes(const cfd_ctx* c) { return 3 * implicit_arena_bytes(c); }
+
+// One V-cycle (full approximation storage, RK3 smoothing; see cfd.h).
+void enqueue_mg_cycle(cfd_ctx* const* lv, double* const* q, int L, int pre, int coarse, char* work, double* hist,
+                      hipStream_t s) {
+  std::vector<double*> R(L), F(L), Q0(L);
+  char* at = work;
+  for (int l = 0; l < L; ++l) {
+    const size_t ab = implicit_arena_bytes(lv[l]);
+    R[l] = reinterpret_cast<double*>(at);
+    F[l] = reinterpret_cast<double*>(at + ab);
+    Q0[l] = reinterpret_cast<double*>(at + 2 * ab);
+    at += 3 * ab;
+  }
+  const int nblk = lv[0]->nblk;
+  for (int l = 0; l < L; ++l) {
+    cfd_ctx* c = lv[l];
+    const int steps = l == L - 1 ? coarse : pre;
+    for (int n = 0; n < steps; ++n) {
+      const bool rec = hist && l == 0 && n == 0;
+      enqueue_step(c, q[l], s, rec, l ? F[l] : nullptr, true);
+      if (rec) HIPCHK(hipMemcpyAsync(hist, c->d_hist(), sizeof(double) * NHIST, hipMemcpyDeviceToDevice, s));
+    }
+    if (l == L - 1) break;
+    cfd_ctx* cn = lv[l + 1];
+    ghost_fill(c, q[l], s);
+    StageArgs A = stage_args(c);
+    A.qs = q[l];
+    A.qn = q[l];
+    A.out = R[l];
+    launch_stage(c, A, 0, s);
+    launch_mg_restrict(q[l], c->met(), R[l], l ? F[l] : nullptr, c->dblocks, q[l + 1], Q0[l + 1], F[l + 1],
+                       cn->met(), cn->dblocks, nblk, cn->nchunks, dt_nwg(cn), s);
+    ghost_fill(cn, q[l + 1], s);
+    StageArgs B = stage_args(cn);
+    B.qs = q[l + 1];
+    B.qn = q[l + 1];
+    B.out = R[l + 1];
+    launch_stage(cn, B, 0, s);
+    launch_mg_forcing(F[l + 1], R[l + 1], cn->dblocks, nblk, cn->nchunks, dt_nwg(cn), s);
+  }
+  for (int l = L - 2; l >= 0; --l)
+    launch_mg_prolong(q[l], lv[l]->dblocks, q[l + 1], Q0[l + 1], lv[l + 1]->dblocks, nblk, lv[l]->nchunks,
+                      dt_nwg(lv[l]), s);
+}
+
+cfd_status cfd_mg_work_size(cfd_ctx* const* levels, int32_t nlevels, size_t* bytes) {
+  return guard(nullptr, [&] {
+    if (!bytes) fail(CFD_EINVAL, "NULL argument");
+    check_hierarchy(levels, nlevels);
+    size_t b = 0;
+    for (int l = 0; l < nlevels; ++l) b += mg_level_bytes(levels[l]);
+    *bytes = b;
+  });
+}
+
+cfd_status cfd_mg_cycles(cfd_ctx* const* levels, double* const* q_levels, int32_t nlevels, int32_t pre,
+                         int32_t coarse, int32_t ncycles, void* work, size_t work_bytes, double* hist,
+                         hipStream_t s) {
+  return guard(levels && nlevels > 0 ? levels[0] : nullptr, [&] {
+    check_hierarchy(levels, nlevels);
+    if (!q_levels || !work) fail(CFD_EINVAL, "NULL argument");
+    if (pre < 0 || coarse < 0 || pre > 1000 || coarse > 1000) fail(CFD_EINVAL, "pre and coarse must be in [0, 1000]");
+    if (ncycles < 0) fail(CFD_EINVAL, "ncycles must be >= 0");
+    if (hist && pre < 1 && nlevels > 1) fail(CFD_EINVAL, "a history needs at least one step on the finest level");
+    if (hist && nlevels == 1 && coarse < 1) fail(CFD_EINVAL, "a history needs at least one step on the finest level");
+    size_t need = 0;
+    for (int l = 0; l < nlevels; ++l) need += mg_level_bytes(levels[l]);
+    if (work_bytes < need) fail(CFD_ENOMEM, "workspace smaller than cfd_mg_work_size()");
+    if (reinterpret_cast<uintptr_t>(work) % 256) fail(CFD_EINVAL, "workspace must be 256-byte aligned");
+    const char* w0 = static_cast<const char*>(work);
+    for (int l = 0; l < nlevels; ++l) {
+      if (!q_levels[l]) fail(CFD_EINVAL, "NULL state");
+      const size_t qb = (size_t)levels[l]->L.q_elems * sizeof(double);
+      const char* a = reinterpret_cast<const char*>(q_levels[l]);
+      if (!(w0 + need <= a || a + qb <= w0)) fail(CFD_EINVAL, "a state and the workspace overlap");
+      for (int m = 0; m < l; ++m) {
+        const size_t mb = (size_t)levels[m]->L.q_elems * sizeof(double);
+        const char* b = reinterpret_cast<const char*>(q_levels[m]);
+        if (!(a + qb <= b || b + mb <= a)) fail(CFD_EINVAL, "the levels' states overlap");
+      }
+    }
+    for (int n = 0; n < ncycles; ++n) {
+      enqueue_mg_cycle(levels, q_levels, nlevels, pre, coarse, static_cast<char*>(work),
+                       hist ? hist + (int64_t)n * NHIST : nullptr, s);
+      check_launch();
     }
   });
 }
