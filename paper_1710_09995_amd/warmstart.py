@@ -31,26 +31,47 @@ from typing import List, Optional
 import numpy as np
 
 from . import cases
-from .binding import Mlp, Solver
+from .binding import Mlp, Multigrid, Solver
 
 NET = dict(d_in=5, d_hidden=128, n_hidden=4, d_out=5)
 
 
-def march(solver: Solver, threshold: float, max_steps: int, chunk: int = 500, log=None):
-    """Advance until L2(R_rho) < threshold (checked every `chunk` steps).
+# The steady march: multigrid V-cycles (3 levels, one RK3 step per level on
+# the way down, two on the coarsest; cfd_mg_cycles) by default, plain RK3
+# steps with levels = 1.  Plain RK3 at CFL 1 needs about the square of the
+# cell count along the channel in steps per residual decade: on 192 x 96 x 96
+# neither start reaches 1e-3 within 2e5 steps, while the cycles reach 1e-8
+# in a few thousand.  Deeper hierarchies or more steps per level were
+# measured to stall on transonic cases.
+LEVELS, PRE, COARSE = 3, 1, 2
+
+
+def _marcher(solver: Solver, levels: int):
+    """A function n -> history [n, 12] advancing the solver's state by n
+    steps (levels = 1) or n V-cycles."""
+    if levels <= 1:
+        return lambda n: solver.step(n, hist=True), None
+    mg = Multigrid(solver, levels, PRE, COARSE)
+    return mg.cycles, mg
+
+
+def march(solver: Solver, threshold: float, max_steps: int, chunk: int = 500, log=None, levels: int = LEVELS):
+    """Advance until L2(R_rho) < threshold (checked every `chunk` steps or
+    cycles).
 
     Returns (steps, seconds, history of (step, L2(R_rho))).  The residual of
     step n is the one of the state at its start, so the count is the number
     of steps taken before a state with residual below threshold was seen.
     """
     torch = solver.torch
+    adv, mg = _marcher(solver, levels)
     torch.cuda.synchronize(solver.device)
     t0 = time.perf_counter()
     done = 0
     hist = []
     while done < max_steps:
         n = min(chunk, max_steps - done)
-        h = solver.step(n, hist=True)
+        h = adv(n)
         r = h[:, 1].cpu().numpy()          # L2(R_rho) per step (synchronises)
         below = np.nonzero(r < threshold)[0]
         hist.extend((done + k, float(r[k])) for k in range(0, n, max(1, n // 10)))
@@ -63,7 +84,10 @@ def march(solver: Solver, threshold: float, max_steps: int, chunk: int = 500, lo
         if not np.isfinite(r[-1]):
             break
     torch.cuda.synchronize(solver.device)
-    return done, time.perf_counter() - t0, hist
+    secs = time.perf_counter() - t0
+    if mg is not None:
+        mg.close()
+    return done, secs, hist
 
 
 @dataclass
@@ -77,13 +101,14 @@ class TrainingData:
     info: dict = field(default_factory=dict)
 
 
-def generate(n_cases: int = 256, seed: int = 0, dims=(48, 24, 24), drop: float = 1e-8, max_steps: int = 60000,
-             log=None) -> TrainingData:
+def generate(n_cases: int = 256, seed: int = 0, dims=(48, 24, 24), drop: float = 1e-8, max_steps: int = 20000,
+             log=None, levels: int = LEVELS) -> TrainingData:
     conds = cases.channel_conditions(n_cases, seed)
     case = cases.channel_batch_case(conds, *dims)
     s = Solver(case)
     r0 = s.step(1, hist=True)[0, 1].item()
-    steps, secs, hist = march(s, drop * r0, max_steps, log=log)
+    s.set_state(case.q0)
+    steps, secs, hist = march(s, drop * r0, max_steps, log=log, levels=levels)
     x = s.mlp_features(conds)
     t = s.mlp_targets(conds)
     final = hist[-1][1] if hist else r0
@@ -117,10 +142,12 @@ DECADES = tuple(10.0 ** -e for e in range(1, 9))     # residual drops 1e-1 .. 1e
 
 
 def march_decades(solver: Solver, r_ref: float, max_steps: int, chunk: int = 250, t_extra: float = 0.0,
-                  log=None, log_every: int = 20000):
-    """March up to max_steps; for every drop d in DECADES record the first step
-    (and the wall seconds, plus t_extra) at which L2(R_rho) < d * r_ref."""
+                  log=None, log_every: int = 20000, advance=None):
+    """March up to max_steps (steps, or cycles with a multigrid `advance`);
+    for every drop d in DECADES record the first step (and the wall seconds,
+    plus t_extra) at which L2(R_rho) < d * r_ref."""
     torch = solver.torch
+    advance = advance or (lambda n: solver.step(n, hist=True))
     torch.cuda.synchronize(solver.device)
     t0 = time.perf_counter()
     reached = {}
@@ -128,7 +155,7 @@ def march_decades(solver: Solver, r_ref: float, max_steps: int, chunk: int = 250
     last = float("nan")
     while done < max_steps and len(reached) < len(DECADES):
         n = min(chunk, max_steps - done)
-        r = solver.step(n, hist=True)[:, 1].cpu().numpy()
+        r = advance(n)[:, 1].cpu().numpy()
         now = time.perf_counter() - t0 + t_extra
         for d in DECADES:
             if d in reached:
@@ -159,17 +186,19 @@ class Comparison:
     inference_s: float
 
 
-def compare(net: Mlp, conds, dims=(192, 96, 96), max_steps: int = 200000, log=None, chunk: int = 500
-            ) -> List[Comparison]:
+def compare(net: Mlp, conds, dims=(192, 96, 96), max_steps: int = 20000, log=None, chunk: int = 250,
+            levels: int = LEVELS) -> List[Comparison]:
     """Cold (uniform stream) vs warm (network) start on each condition; one
-    absolute reference, the cold start's initial residual, for both."""
+    absolute reference, the cold start's initial residual, for both; the same
+    steady march (multigrid cycles, or RK3 steps with levels = 1) for both."""
     out = []
     for mach, hb in conds:
         case = cases.channel_case(*dims, mach=float(mach), hb=float(hb))
         s = Solver(case)
+        adv, mg = _marcher(s, levels)
         r_cold0 = s.step(1, hist=True)[0, 1].item()     # residual of the uniform stream
         s.set_state(case.q0)
-        cold, _, cold_final = march_decades(s, r_cold0, max_steps, chunk, log=log)
+        cold, _, cold_final = march_decades(s, r_cold0, max_steps, chunk, log=log, advance=adv)
         s.set_state(case.q0)
         s.torch.cuda.synchronize(s.device)
         t0 = time.perf_counter()
@@ -178,13 +207,15 @@ def compare(net: Mlp, conds, dims=(192, 96, 96), max_steps: int = 200000, log=No
         t_inf = time.perf_counter() - t0
         r_warm0 = s.step(1, hist=True)[0, 1].item()
         warm_state(s, net, [(mach, hb)])
-        warm, _, warm_final = march_decades(s, r_cold0, max_steps, chunk, t_extra=t_inf, log=log)
+        warm, _, warm_final = march_decades(s, r_cold0, max_steps, chunk, t_extra=t_inf, log=log, advance=adv)
         c = Comparison(float(mach), float(hb), r_cold0, r_warm0, cold, warm, cold_final, warm_final, max_steps,
                        t_inf)
         if log:
             log(f"# M={mach:.3f} h={hb:.3f}: r0 cold {r_cold0:.3e} warm {r_warm0:.3e}; "
                 f"cold {summarise(cold)}; warm {summarise(warm)}")
         out.append(c)
+        if mg is not None:
+            mg.close()
         s.close()
     return out
 
@@ -218,13 +249,14 @@ def main(argv=None):
     ap.add_argument("--cases", type=int, default=256)
     ap.add_argument("--coarse", type=int, nargs=3, default=[48, 24, 24])
     ap.add_argument("--fine", type=int, nargs=3, default=[192, 96, 96])
-    ap.add_argument("--data-steps", type=int, default=60000)
+    ap.add_argument("--data-steps", type=int, default=20000, help="cap on the training data's steps or cycles")
+    ap.add_argument("--levels", type=int, default=LEVELS, help="multigrid levels of the steady march (1: plain RK3)")
     ap.add_argument("--iters", type=int, default=20000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--test", type=int, default=4)
     ap.add_argument("--test-seed", type=int, default=12345)
-    ap.add_argument("--cap", type=int, default=200000)
-    ap.add_argument("--chunk", type=int, default=500)
+    ap.add_argument("--cap", type=int, default=20000, help="steps (levels 1) or cycles per start")
+    ap.add_argument("--chunk", type=int, default=250)
     ap.add_argument("--test-skip", type=int, default=0, help="skip the first K held-out conditions")
     ap.add_argument("--save-net", default=None, help="write the trained weights (.npz)")
     ap.add_argument("--load-net", default=None, help="skip data and training; use these weights (.npz)")
@@ -238,7 +270,7 @@ def main(argv=None):
         data = None
         t1 = t2 = time.perf_counter()
     else:
-        data = generate(a.cases, 0, tuple(a.coarse), drop=1e-8, max_steps=a.data_steps, log=log)
+        data = generate(a.cases, 0, tuple(a.coarse), drop=1e-8, max_steps=a.data_steps, log=log, levels=a.levels)
         log(f"# data: {data.x.shape[0]} points from {a.cases} cases, {data.steps} steps in {data.seconds:.1f} s, "
             f"residual {data.info['r0']:.3e} -> {data.final_residual:.3e}")
         t1 = time.perf_counter()
@@ -252,7 +284,7 @@ def main(argv=None):
                 flat[f"w{k}"], flat[f"b{k}"] = w, b
             np.savez(a.save_net, **flat)
     tests = cases.channel_conditions(a.test_skip + a.test, a.test_seed)[a.test_skip:]
-    res = compare(net, tests, tuple(a.fine), a.cap, log=log, chunk=a.chunk)
+    res = compare(net, tests, tuple(a.fine), a.cap, log=log, chunk=a.chunk, levels=a.levels)
     summary = []
     for c in res:
         d = deepest_common(c)
@@ -267,7 +299,7 @@ def main(argv=None):
                         "target_cold": c.cold.get(TARGET), "target_warm": c.warm.get(TARGET)})
     ts = target_seconds(res)
     both = [(x, y) for x, y in ts if x is not None and y is not None]
-    out = {"train_cases": a.cases, "coarse": a.coarse, "fine": a.fine,
+    out = {"train_cases": a.cases, "coarse": a.coarse, "fine": a.fine, "levels": a.levels,
            "data_steps": data.steps if data else None, "data_seconds": data.seconds if data else None,
            "train_iters": a.iters, "train_seconds": t2 - t1, "net": a.load_net or "trained here",
            "data_final_drop": data.final_residual / data.info["r0"] if data else None,
