@@ -490,9 +490,10 @@ def mlp_init(d_in: int = 5, d_hidden: int = 128, n_hidden: int = 4, d_out: int =
 
 
 def channel_conditions(n: int, seed: int) -> np.ndarray:
-    """Inflow Mach in [0.5, 0.85) and bump height in [0.02, 0.1) per case."""
-    rng = np.random.default_rng(seed)
-    return np.column_stack([rng.uniform(0.5, 0.85, n), rng.uniform(0.02, 0.1, n)])
+    """Inflow Mach in [0.5, 0.85) and bump height in [0.02, 0.1) per case,
+    drawn a pair at a time: the first k cases are the same for every n >= k."""
+    u = np.random.default_rng(seed).uniform(size=(n, 2))
+    return np.column_stack([0.5 + 0.35 * u[:, 0], 0.02 + 0.08 * u[:, 1]])
 
 
 class LazyStates:

@@ -40,3 +40,22 @@ def test_warm_start_reaches_the_target_sooner_than_the_cold_start(levels):
         assert c.warm[T][0] < c.cold[T][0]
     secs = warmstart.target_seconds(res)
     assert np.median([w for _, w in secs]) < np.median([c for c, _ in secs])
+
+
+def test_warm_start_at_full_size():
+    """The full sizes of the pipeline on one held-out case: 128 coarse training
+    cases of 48 x 24 x 24 marched by multigrid cycles to a 1e-8 drop, the
+    network trained on them, the first held-out condition of seed 12345 on
+    192 x 96 x 96.  The warm start (inference included) reaches the 1e-8
+    target in fewer cycles and fewer wall seconds than the cold start."""
+    from paper_1710_09995_amd import cases, warmstart
+    data = warmstart.generate(128, seed=0, dims=(48, 24, 24), drop=1e-8, max_steps=20000)
+    say("data", data.x.shape[0], "points,", data.steps, "cycles", f"{data.seconds:.1f} s")
+    assert data.final_residual < 1e-8 * data.info["r0"]
+    net = warmstart.train(data, iters=20000, batch=8192)
+    c, = warmstart.compare(net, cases.channel_conditions(1, 12345), dims=(192, 96, 96), max_steps=20000, log=say)
+    T = warmstart.TARGET
+    assert T in c.cold and T in c.warm
+    say(f"  M={c.mach:.3f} h={c.hb:.3f}: cold {c.cold[T][0]} cycles {c.cold[T][1]:.2f} s, "
+        f"warm {c.warm[T][0]} cycles {c.warm[T][1]:.2f} s")
+    assert c.warm[T][0] < c.cold[T][0] and c.warm[T][1] < c.cold[T][1]
