@@ -13,6 +13,7 @@
 #include <exception>
 #include <stdexcept>
 #include <string>
+#include <atomic>
 #include <map>
 #include <vector>
 
@@ -348,6 +349,14 @@ struct cfd_ctx {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph_n = nullptr;
   hipGraphExec_t gexec_n = nullptr;
+  // A captured multigrid cycle led by this context (the finest level), valid
+  // for the hierarchy and arguments in mg_key; id is unique per context and
+  // gen counts its retunings, so a cycle over a level since retuned or
+  // destroyed is captured again.
+  uint64_t id = 0, gen = 0;
+  std::vector<uint64_t> mg_key;
+  hipGraph_t mg_graph = nullptr;
+  hipGraphExec_t mg_gexec = nullptr;
   int num_cu = 256;
   std::map<int, int> occ_cache;
   std::string last_error;
@@ -408,8 +417,18 @@ struct cfd_ctx {
     graph_q = nullptr;
     gexec_n = nullptr;
     graph_n = nullptr;
+    drop_mg_graph();
+  }
+  void drop_mg_graph() {
+    if (mg_gexec) hipGraphExecDestroy(mg_gexec);
+    if (mg_graph) hipGraphDestroy(mg_graph);
+    mg_gexec = nullptr;
+    mg_graph = nullptr;
+    mg_key.clear();
   }
 };
+
+std::atomic<uint64_t> g_ctx_ids{1};
 
 namespace {
 
@@ -859,6 +878,7 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
     const int npatch = count_patches(nconn, nbc);
     if (npatch > 2 * 6 * 64 * nblk) fail(CFD_EUNSUPPORTED, "more than 64 patches per face on average");
     c = new cfd_ctx();
+    c->id = g_ctx_ids++;
     c->params = *params;
     c->nblk = nblk;
     c->dims.assign(dims, dims + nblk);
@@ -1013,6 +1033,7 @@ cfd_status cfd_set_tuning(cfd_ctx* c, const cfd_tuning* t) {
       fail(CFD_EINVAL, "the plane-ring kernel takes tile_j = 4 or 8");
     c->drop_graph();
     c->tun = *t;
+    ++c->gen;
     HIPCHK(hipDeviceSynchronize());
     build_tiles(c, c->cap_stream);
   });
@@ -1165,8 +1186,10 @@ void check_hierarchy(cfd_ctx* const* lv, int n) {
 size_t mg_level_bytes(const cfd_ctx* c) { return 3 * implicit_arena_bytes(c); }
 
 // One V-cycle (full approximation storage, RK3 smoothing; see cfd.h).
-void enqueue_mg_cycle(cfd_ctx* const* lv, double* const* q, int L, int pre, int coarse, char* work, double* hist,
-                      hipStream_t s) {
+// record: the finest level's first step keeps its history row (in lv[0]'s
+// history slot); hist (nullable): copied there after that step.
+void enqueue_mg_cycle(cfd_ctx* const* lv, double* const* q, int L, int pre, int coarse, char* work, bool record,
+                      double* hist, hipStream_t s) {
   std::vector<double*> R(L), F(L), Q0(L);
   char* at = work;
   for (int l = 0; l < L; ++l) {
@@ -1181,9 +1204,10 @@ void enqueue_mg_cycle(cfd_ctx* const* lv, double* const* q, int L, int pre, int 
     cfd_ctx* c = lv[l];
     const int steps = l == L - 1 ? coarse : pre;
     for (int n = 0; n < steps; ++n) {
-      const bool rec = hist && l == 0 && n == 0;
+      const bool rec = record && l == 0 && n == 0;
       enqueue_step(c, q[l], s, rec, l ? F[l] : nullptr, true);
-      if (rec) HIPCHK(hipMemcpyAsync(hist, c->d_hist(), sizeof(double) * NHIST, hipMemcpyDeviceToDevice, s));
+      if (rec && hist)
+        HIPCHK(hipMemcpyAsync(hist, c->d_hist(), sizeof(double) * NHIST, hipMemcpyDeviceToDevice, s));
     }
     if (l == L - 1) break;
     cfd_ctx* cn = lv[l + 1];
@@ -1244,10 +1268,46 @@ cfd_status cfd_mg_cycles(cfd_ctx* const* levels, double* const* q_levels, int32_
         if (!(a + qb <= b || b + mb <= a)) fail(CFD_EINVAL, "the levels' states overlap");
       }
     }
+    cfd_ctx* c0 = levels[0];
+    bool graph = c0->tun.use_graph != 0;
+    for (int l = 0; l < nlevels; ++l) graph = graph && !levels[l]->profiling;
+    if (!graph) {
+      for (int n = 0; n < ncycles; ++n) {
+        enqueue_mg_cycle(levels, q_levels, nlevels, pre, coarse, static_cast<char*>(work), hist != nullptr,
+                         hist ? hist + (int64_t)n * NHIST : nullptr, s);
+        check_launch();
+      }
+      return;
+    }
+    // one captured cycle, replayed; its history row is copied out after each
+    std::vector<uint64_t> key{(uint64_t)nlevels, (uint64_t)pre, (uint64_t)coarse, hist ? 1u : 0u,
+                              (uint64_t)reinterpret_cast<uintptr_t>(work)};
+    for (int l = 0; l < nlevels; ++l) {
+      key.push_back(levels[l]->id);
+      key.push_back(levels[l]->gen);
+      key.push_back((uint64_t)reinterpret_cast<uintptr_t>(q_levels[l]));
+    }
+    if (ncycles > 0 && (!c0->mg_gexec || c0->mg_key != key)) {
+      c0->drop_mg_graph();
+      HIPCHK(hipStreamBeginCapture(c0->cap_stream, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue_mg_cycle(levels, q_levels, nlevels, pre, coarse, static_cast<char*>(work), hist != nullptr, nullptr,
+                         c0->cap_stream);
+      } catch (...) {
+        hipGraph_t gg = nullptr;
+        hipStreamEndCapture(c0->cap_stream, &gg);
+        if (gg) hipGraphDestroy(gg);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(c0->cap_stream, &c0->mg_graph));
+      HIPCHK(hipGraphInstantiate(&c0->mg_gexec, c0->mg_graph, nullptr, nullptr, 0));
+      c0->mg_key = key;
+    }
     for (int n = 0; n < ncycles; ++n) {
-      enqueue_mg_cycle(levels, q_levels, nlevels, pre, coarse, static_cast<char*>(work),
-                       hist ? hist + (int64_t)n * NHIST : nullptr, s);
-      check_launch();
+      HIPCHK(hipGraphLaunch(c0->mg_gexec, s));
+      if (hist)
+        HIPCHK(hipMemcpyAsync(hist + (int64_t)n * NHIST, c0->d_hist(), sizeof(double) * NHIST,
+                              hipMemcpyDeviceToDevice, s));
     }
   });
 }

@@ -87,3 +87,35 @@ def test_cycles_reach_the_target_before_the_rk3_march():
     say(f"  RK3 in the same wall time: {done} steps, drop {r[-1] / r0:.2e}")
     s.close()
     assert r[-1] > 1e-8 * r0
+
+
+def test_captured_cycles_are_bitwise_the_eager_cycles():
+    """The cycle replayed from its captured graph (the default) against the same
+    cycles launched one by one (graphs off on the finest level): bitwise the
+    same states and history rows after every call, with the program's own
+    eager work (a residual evaluation) and synchronisations between the
+    replays; a retuned coarse level makes the next call capture again."""
+    import torch
+    from paper_1710_09995_amd.binding import Multigrid, Solver
+    case = cases.channel_case(32, 16, 8, mach=0.7, hb=0.06)
+    sa, sb = Solver(case), Solver(case)
+    sb.set_tuning(use_graph=0)
+    ma, mb = Multigrid(sa, 3, 1, 2), Multigrid(sb, 3, 1, 2)
+    for n in (3, 1, 4):
+        ha, hb = ma.cycles(n), mb.cycles(n)
+        torch.cuda.synchronize()
+        assert torch.equal(ha, hb)
+        for x, y in zip(sa.state(), sb.state()):
+            assert np.array_equal(x, y)
+        sa.residual()
+        torch.cuda.synchronize()
+    ma.levels[1].set_tuning(tile_k=16)
+    mb.levels[1].set_tuning(tile_k=16)
+    ha, hb = ma.cycles(2), mb.cycles(2)
+    assert torch.equal(ha, hb)
+    for x, y in zip(sa.state(), sb.state()):
+        assert np.array_equal(x, y)
+    for m in (ma, mb):
+        m.close()
+    sa.close()
+    sb.close()
