@@ -102,10 +102,14 @@ def cpu_baseline(name: str, flux: str, budget_s: float = 12.0):
             "sample": f"{sample}; {n} steps of {c.ncells} cells in {dt:.1f} s, single-threaded NumPy"}
 
 
-def read_profile_value(kernel_label: str, kind: str, key: str):
+STAGE_SOURCES = ("kernels_ring.hip", "stage_common.hpp", "physics.hpp", "cfd_internal.hpp")
+HIGHORDER_SOURCES = ("kernels_highorder.hip", "physics.hpp")
+
+
+def read_profile_value(kernel_label: str, kind: str, key: str, sources=STAGE_SOURCES):
     """A per-launch figure from a committed rocprofv3 --pmc summary
-    (profiles/<label>_<kind>.txt), valid only while the stage-kernel sources
-    are unchanged."""
+    (profiles/<label>_<kind>.txt), valid only while the sources of the
+    kernels it measured are unchanged."""
     path = os.path.join(ROOT, "profiles", f"{kernel_label}_{kind}.txt")
     if not os.path.exists(path):
         return None
@@ -114,7 +118,7 @@ def read_profile_value(kernel_label: str, kind: str, key: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_sha") != source_sha():
+    if vals.get("source_sha") != source_sha(sources):
         return None
     try:
         return float(vals[key])
@@ -127,11 +131,11 @@ def read_traffic(kernel_label: str):
     return read_profile_value(kernel_label, "pmc", "hbm_bytes_per_launch")
 
 
-def source_sha() -> str:
-    """Hash of the sources that define the plane-ring stage kernel (the kernel
-    the committed counter summaries measure)."""
+def source_sha(sources=STAGE_SOURCES) -> str:
+    """Hash of the sources that define the measured kernels (by default the
+    plane-ring stage kernel, which the headline's counter summaries measure)."""
     h = hashlib.sha256()
-    for f in ("kernels_ring.hip", "stage_common.hpp", "physics.hpp", "cfd_internal.hpp"):
+    for f in sources:
         p = os.path.join(ROOT, "paper_1710_09995_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
@@ -360,6 +364,8 @@ def bench_wcns5_euler(a) -> int:
     elif viscous:   # phi (Q in, 4 out), gradients (4 in, 12 out), per direction faces (16 in, 4 out) and the sum
         nbytes += 8 * cells * ((5 + 4) + (4 + 12) + 3 * ((4 + 8) + 4) + 3 * (4 + 8))
     achieved = nbytes / (ms / 1e3) / 1e9
+    label = ("ns_wcns5_c4" if viscous else "wcns5_euler") + ("_curv" if curv else "") + "_periodic_256x128x128"
+    traffic = read_profile_value(label, "pmc", "hbm_bytes_per_residual", HIGHORDER_SOURCES)
     print(json.dumps({
         "metric": "Mcell/s of the periodic " + ("curvilinear " if curv else "") +
                   ("Navier-Stokes (WCNS-E-5 inviscid + fourth-order viscous)" if viscous else "inviscid WCNS-E-5") +
@@ -371,7 +377,8 @@ def bench_wcns5_euler(a) -> int:
                                "_periodic_256x128x128",
                    "metrics_setup_ms": None if setup_ms is None else round(setup_ms, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_rate_gbs": None if traffic is None else round(traffic / (ms / 1e3) / 1e9, 1),
                      "kernel": "pipeline: k_pad_prim_periodic, k_wcns5_roe_faces, k_window6_*<Eq2OpT>"
                                + (" (the last pass dividing by J^-1)" if curv else "")
                                + (", k_c4_phi, k_c4_grads, k_c4_cell_metrics, k_c4_visc_faces_curv, k_c4_flux_sub"
