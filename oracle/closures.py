@@ -31,15 +31,19 @@ interior stencil unchanged up to the boundary:
   and periodic transverse directions (no corner ghost blocks are needed
   then); the two ghost blocks close the bounded direction into a ring so that
   every link of the joined-block table is mutual.  The wall-bump geometry
-  (periodic x and z, wall and far field across y) has this form.
+  (periodic x and z, wall and far field across y) has this form, and so has
+  the one-GPU share (blocks tiling x and z, wall and far field across the
+  third direction): ClosedBlocks cuts the periodic directions into owners,
+  each with its ghost blocks joined to its neighbours' ghost blocks.
 
 Pins (tests/test_oracle_closures.py): a uniform stream on the curved wall-bump
 grid with the far field on both bounded faces stays uniform; a state mirrored
 about a flat slip wall gives, with the closures, the residual of the
 periodic domain of twice the height that holds the state and its mirror image
 (inviscid and viscous); the vertex extension reproduces a grid that is linear
-along the bounded direction; and away from the boundary the closed residual
-equals the residual of the same state continued periodically.
+along the bounded direction; away from the boundary the closed residual does
+not see the closure; and owners tiling the periodic directions give bitwise
+the single closed block's residual.
 """
 from __future__ import annotations
 
@@ -207,3 +211,104 @@ class Closed:
         for _ in range(nsteps):
             q = ssp_rk3(q, dt, lambda x: self.residual(x, eps_h, eps, viscous))
         return q
+
+
+class ClosedBlocks:
+    """Owner blocks tiling a grid that is periodic along the two directions
+    other than `bounded`, each owner with its two ghost blocks.  Xv: the whole
+    grid's vertices as for extended_vertices; cuts[d] (d != bounded): the
+    block boundaries along d, a list 0 = c_0 < c_1 < ... < c_m = n_d.  Owners
+    are numbered along the first periodic direction fastest; block 3 o is
+    owner o, 3 o + 1 its low ghost block, 3 o + 2 its high one.  Owners join
+    their neighbours across the cuts (wrapping around the periodic
+    directions); a ghost block joins the same-side ghost block of its owner's
+    neighbour, so the ghost layers of a tiling are the ghost layers of the
+    untiled block cut the same way."""
+
+    def __init__(self, Xv, period, bounded, kinds, cuts, gamma=1.4, freestream=(0.5, 0.0, 0.0)):
+        if len(kinds) != 2 or any(k not in (FARFIELD, SLIPWALL, NOSLIP_ADIABATIC) for k in kinds):
+            raise ValueError("both faces of the bounded direction need a wall or far-field condition")
+        self.bounded, self.kinds, self.gamma, self.freestream = bounded, tuple(kinds), gamma, freestream
+        shape = Xv.shape[1:]
+        N = [shape[2], shape[1], shape[0]]
+        N[bounded] -= 1
+        self.N = tuple(N)
+        self.E, self.origin = extended_vertices(Xv, period, bounded)
+        per = [d for d in range(3) if d != bounded]
+        self.per = per
+        self.cuts = {d: list(cuts[d]) for d in per}
+        for d in per:
+            c = self.cuts[d]
+            if c[0] != 0 or c[-1] != N[d] or any(b <= a for a, b in zip(c, c[1:])):
+                raise ValueError(f"bad cuts along {d}: {c}")
+        m0, m1 = len(self.cuts[per[0]]) - 1, len(self.cuts[per[1]]) - 1
+        self.tiles = (m0, m1)
+        self.owners = []           # (lo index per direction, extents)
+        for b1 in range(m1):
+            for b0 in range(m0):
+                lo, ext = [0, 0, 0], list(N)
+                for d, b in ((per[0], b0), (per[1], b1)):
+                    lo[d] = self.cuts[d][b]
+                    ext[d] = self.cuts[d][b + 1] - self.cuts[d][b]
+                self.owners.append((tuple(lo), tuple(ext)))
+        no = len(self.owners)
+        self.dims, self.nbr = [], []
+        for o, (lo, ext) in enumerate(self.owners):
+            g = list(ext)
+            g[bounded] = GHOST
+            self.dims += [tuple(ext), tuple(g), tuple(g)]
+        self.nbr = [[0] * 6 for _ in range(3 * no)]
+        B = 2 * bounded
+        for o in range(no):
+            b0, b1 = o % m0, o // m0
+            for d, (t, m) in zip(per, ((b0, m0), (b1, m1))):
+                for side in (0, 1):
+                    step = -1 if side == 0 else 1
+                    tn = (t + step) % m
+                    on = (tn + b1 * m0) if d == per[0] else (b0 + tn * m0)
+                    for r in range(3):                      # owner, low ghost, high ghost
+                        self.nbr[3 * o + r][2 * d + side] = 3 * on + r
+            self.nbr[3 * o][B], self.nbr[3 * o + 1][B + 1] = 3 * o + 1, 3 * o
+            self.nbr[3 * o][B + 1], self.nbr[3 * o + 2][B] = 3 * o + 2, 3 * o
+            self.nbr[3 * o + 1][B], self.nbr[3 * o + 2][B + 1] = 3 * o + 2, 3 * o + 1
+        self.S, self.Jinv = [], []
+        for lo, ext in self.owners:
+            for start, cnt in ((0, N[bounded]), (-GHOST, GHOST), (N[bounded], GHOST)):
+                Xw = self.E
+                for d in range(3):
+                    if d == bounded:
+                        s0, c0 = self.origin[d] - 3 + start, cnt + 5
+                    else:
+                        s0, c0 = self.origin[d] - 3 + lo[d], ext[d] + 5
+                    Xw = ho._win(Xw, _axis(d), s0, c0)
+                S, J = ho.metrics6(Xw)
+                self.S.append(S)
+                self.Jinv.append(J)
+
+    def split(self, Q):
+        """The owners' states cut from a whole-grid state [5, Nk, Nj, Ni]."""
+        out = []
+        for lo, ext in self.owners:
+            sl = [slice(None)] + [slice(lo[d], lo[d] + ext[d]) for d in (2, 1, 0)]
+            out.append(Q[tuple(sl)].copy())
+        return out
+
+    def blocks(self, Qo):
+        """All blocks' states (owners Qo, ghost blocks filled from them)."""
+        Qs = []
+        for o, Q in enumerate(Qo):
+            g = [np.zeros((5,) + tuple(reversed(self.dims[3 * o + r]))) for r in (1, 2)]
+            trio = [Q] + g
+            fill_ghosts(trio, [self.S[3 * o], self.S[3 * o + 1], self.S[3 * o + 2]], self.bounded,
+                        [(1, 0, self.kinds[0]), (2, 1, self.kinds[1])], self.gamma, self.freestream)
+            Qs += trio
+        return Qs
+
+    def residual(self, Qo, eps_h=0.1, eps=1e-6, viscous=None):
+        """R of every owner (list)."""
+        Qs = self.blocks(Qo)
+        R = ho.wcns5_euler_residual_blocks(Qs, self.S, self.Jinv, self.nbr, self.gamma, eps_h, eps)
+        if viscous is not None:
+            V = ho.viscous_residual_blocks(Qs, self.S, self.Jinv, self.nbr, self.gamma, *viscous)
+            R = [a + b for a, b in zip(R, V)]
+        return [R[3 * o] for o in range(len(self.owners))]

@@ -13,7 +13,9 @@ its references; oracle/closures.py):
   ghost blocks in one comparison;
 * the vertex extension continues a grid linear along the bounded direction
   exactly;
-* cells more than the stencils' reach from both faces do not see the closure.
+* cells more than the stencils' reach from both faces do not see the closure;
+* owners tiling the periodic directions (each with ghost blocks joined to
+  its neighbours' ghost blocks) give bitwise the single closed block.
 """
 import numpy as np
 import pytest
@@ -133,3 +135,23 @@ def test_cells_far_from_both_faces_do_not_see_the_closure():
     b = cl.Closed(Xv, P, 1, (NOSLIP_ADIABATIC, SLIPWALL), GAMMA).residual(q, viscous=VISC)
     assert np.array_equal(a[:, :, 8:-8], b[:, :, 8:-8])
     assert np.max(np.abs(a[:, :, :3] - b[:, :, :3])) > 1e-6
+
+
+@pytest.mark.parametrize("viscous", [False, True])
+def test_tiled_owners_give_the_single_block(viscous):
+    """The wall-bump grid cut unevenly into 2 x 2 owners along its periodic
+    directions, each with its own ghost blocks joined to its neighbours'
+    ghost blocks: every owner's closed residual is bitwise the single closed
+    block's residual there (the stencils and ghost layers are the same)."""
+    n = (24, 16, 12)
+    Xv, P = _bump(n)
+    q = _smooth_state(n, seed=6)
+    kinds = (NOSLIP_ADIABATIC, FARFIELD)
+    one = cl.Closed(Xv, P, 1, kinds, GAMMA, freestream=(0.8, 0.0, 0.0))
+    R1 = one.residual(q, viscous=VISC if viscous else None)
+    tl = cl.ClosedBlocks(Xv, P, 1, kinds, {0: [0, 10, 24], 2: [0, 5, 12]}, GAMMA, freestream=(0.8, 0.0, 0.0))
+    Rs = tl.residual(tl.split(q), viscous=VISC if viscous else None)
+    assert len(Rs) == 4
+    for (lo, ext), R in zip(tl.owners, Rs):
+        sl = (slice(None), slice(lo[2], lo[2] + ext[2]), slice(lo[1], lo[1] + ext[1]), slice(lo[0], lo[0] + ext[0]))
+        assert np.array_equal(R, R1[sl]), (lo, ext)
