@@ -635,12 +635,18 @@ cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dims, const in
  * CFD_EINVAL on a bad argument or when a ghost state overlaps the owner's
  * state, a metric array or the other ghost state.
  *
+ * Owners that tile the periodic directions (as blocks of the one-GPU share
+ * tile x and z) each get their own two ghost blocks; a ghost block joins the
+ * same-side ghost block of its owner's neighbour across the cut, so the
+ * tiling's ghost layers are those of the untiled block cut the same way.
+ *
  * cfd_wcns5_steps_blocks_closed: cfd_wcns5_ns_steps_blocks with the ghost
- * blocks of *closure refilled before every stage's residual and the viscous
- * terms only when viscous != 0 (same workspace size).  The closure is checked
- * against the table (distinct blocks in range, ghost extents, the ghost
- * blocks joined to the owner's two faces across `bounded`).  The ghost blocks'
- * own states after a call are scratch.  Asynchronous on stream. */
+ * blocks of the nclosures closures[] refilled before every stage's residual
+ * and the viscous terms only when viscous != 0 (same workspace size).  Each
+ * closure is checked against the table (distinct blocks in range, ghost
+ * extents, the ghost blocks joined to the owner's two faces across
+ * `bounded`), and no block may belong to two closures.  The ghost blocks' own
+ * states after a call are scratch.  Asynchronous on stream. */
 #define CFD_WCNS5_GHOST 5
 #define CFD_WCNS5_XLAYERS 7
 typedef struct {
@@ -657,8 +663,8 @@ cfd_status cfd_wcns5_fill_ghost_blocks(const double* q_dev, double* q_lo_dev, do
                                        hipStream_t stream);
 cfd_status cfd_wcns5_steps_blocks_closed(int32_t nblk, const int32_t* dims, const int32_t* nbr, double* const* q_dev,
                                          const double* const* s_dev, const double* const* jinv_dev,
-                                         const cfd_wcns5_closure* closure, int32_t viscous, void* work_dev,
-                                         size_t work_bytes, double gamma, double entropy_fix, double eps,
+                                         const cfd_wcns5_closure* closures, int32_t nclosures, int32_t viscous,
+                                         void* work_dev, size_t work_bytes, double gamma, double entropy_fix, double eps,
                                          double prandtl, double mu_inf, double s_star, double dt, int32_t nsteps,
                                          hipStream_t stream);
 

@@ -186,8 +186,9 @@ def lib(build_if_missing: bool = True):
     L.cfd_wcns5_fill_ghost_blocks.argtypes = [vp, vp, vp, vp, vp, i32p, i32, i32p, C.c_double,
                                               C.POINTER(C.c_double), vp]
     L.cfd_wcns5_steps_blocks_closed.argtypes = [i32, i32p, i32p, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
-                                                C.POINTER(WcnsClosure), i32, vp, C.c_size_t, C.c_double, C.c_double,
-                                                C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, i32, vp]
+                                                C.POINTER(WcnsClosure), i32, i32, vp, C.c_size_t, C.c_double,
+                                                C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                                C.c_double, i32, vp]
     L.cfd_status_string.argtypes = [i32]
     L.cfd_status_string.restype = C.c_char_p
     L.cfd_last_error.argtypes = [vp]
@@ -792,81 +793,154 @@ def wcns5_fill_ghost_blocks(q, q_lo, q_hi, S, S_lo, bounded: int, kinds, uinf, g
                                              _stream_handle(torch, stream)))
 
 
-class WcnsClosedBlock:
-    """A curvilinear block periodic along two directions whose two faces across
-    the third (`bounded`) are walls or the far field, closed by ghost blocks
-    (cfd_wcns5_extend_vertices, cfd_wcns5_metrics_ext, cfd_wcns5_fill_ghost_blocks,
-    and the joined-block residual, viscous terms and RK3 steps).  xv: the
-    owner's vertices as for wcns5_extend_vertices (a CUDA tensor); kinds: the
-    cfd_bc_kind of the low and high face; uinf: the far-field velocity."""
+class WcnsClosedTiling:
+    """Owner blocks tiling the two periodic directions of a curvilinear grid
+    whose two faces across the third (`bounded`) are walls or the far field,
+    each owner closed by its two ghost blocks (cfd_wcns5_extend_vertices,
+    cfd_wcns5_metrics_ext, cfd_wcns5_fill_ghost_blocks, the joined-block
+    residual, viscous terms and RK3 steps).  xv: the whole grid's vertices as
+    for wcns5_extend_vertices (a CUDA tensor); cuts[d] for the periodic d: the
+    block boundaries 0 = c_0 < ... < c_m = n_d (default: one owner); kinds: the
+    cfd_bc_kind of the low and high face; uinf: the far-field velocity.
+    Owners are numbered along the first periodic direction fastest; block
+    3 o + r of the tables is owner o (r = 0) or its low (1) or high (2) ghost
+    block."""
 
-    def __init__(self, xv, period, bounded: int, kinds, uinf=(0.0, 0.0, 0.0), gamma: float = 1.4, stream=None):
+    def __init__(self, xv, period, bounded: int, kinds, uinf=(0.0, 0.0, 0.0), gamma: float = 1.4, cuts=None,
+                 stream=None):
         import torch
         self.torch = torch
         self.stream = stream
         self.bounded, self.kinds, self.uinf, self.gamma = int(bounded), tuple(kinds), tuple(uinf), float(gamma)
-        xe = wcns5_extend_vertices(xv, bounded, period, stream)
-        n = [int(xv.shape[3]), int(xv.shape[2]), int(xv.shape[1])]
-        n[bounded] -= 1
-        self.n = tuple(n)
         d = self.bounded
+        N = [int(xv.shape[3]), int(xv.shape[2]), int(xv.shape[1])]
+        N[d] -= 1
+        self.N = tuple(N)
+        per = [t for t in range(3) if t != d]
+        cuts = dict(cuts or {})
+        cuts = {t: [int(v) for v in cuts.get(t, [0, N[t]])] for t in per}
+        for t in per:
+            c = cuts[t]
+            if c[0] != 0 or c[-1] != N[t] or any(b <= a for a, b in zip(c, c[1:])):
+                raise ValueError(f"bad cuts along direction {t}: {c}")
+        m0, m1 = len(cuts[per[0]]) - 1, len(cuts[per[1]]) - 1
+        self.owners = []
+        for b1 in range(m1):
+            for b0 in range(m0):
+                lo, ext = [0, 0, 0], list(N)
+                for t, b in ((per[0], b0), (per[1], b1)):
+                    lo[t], ext[t] = cuts[t][b], cuts[t][b + 1] - cuts[t][b]
+                self.owners.append((tuple(lo), tuple(ext)))
+        no = len(self.owners)
+        self.dims, nbr = [], [[0] * 6 for _ in range(3 * no)]
+        for o, (lo, ext) in enumerate(self.owners):
+            g = list(ext)
+            g[d] = WCNS5_GHOST
+            self.dims += [tuple(ext), tuple(g), tuple(g)]
+            b0, b1 = o % m0, o // m0
+            for t, (pos, m) in zip(per, ((b0, m0), (b1, m1))):
+                for side in (0, 1):
+                    pn = (pos + (-1 if side == 0 else 1)) % m
+                    on = pn + b1 * m0 if t == per[0] else b0 + pn * m0
+                    for r in range(3):
+                        nbr[3 * o + r][2 * t + side] = 3 * on + r
+            B = 2 * d
+            nbr[3 * o][B], nbr[3 * o + 1][B + 1] = 3 * o + 1, 3 * o
+            nbr[3 * o][B + 1], nbr[3 * o + 2][B] = 3 * o + 2, 3 * o
+            nbr[3 * o + 1][B], nbr[3 * o + 2][B + 1] = 3 * o + 2, 3 * o + 1
+        self.nbr = nbr
+        xe = wcns5_extend_vertices(xv, d, period, stream)
         org = [3, 3, 3]
         org[d] = WCNS5_XLAYERS + 1
-        mets = []
-        for lo, ext in ((0, n[d]), (-WCNS5_GHOST, WCNS5_GHOST), (n[d], WCNS5_GHOST)):
-            sl = []
-            for a in (2, 1, 0):
-                start = org[a] - 3 + (lo if a == d else 0)
-                cnt = (ext if a == d else n[a]) + 5
-                sl.append(slice(start, start + cnt))
-            mets.append(wcns5_metrics_ext(xe[(slice(None),) + tuple(sl)].contiguous(), stream))
-        self.S = [m[0] for m in mets]
-        self.jinv = [m[1] for m in mets]
-        gd = list(n)
-        gd[d] = WCNS5_GHOST
-        self.dims = [tuple(n), tuple(gd), tuple(gd)]
-        nbr = [[b] * 6 for b in range(3)]
-        nbr[0][2 * d], nbr[1][2 * d + 1] = 1, 0
-        nbr[0][2 * d + 1], nbr[2][2 * d] = 2, 0
-        nbr[1][2 * d], nbr[2][2 * d + 1] = 2, 1
-        self.nbr = nbr
+        self.S, self.jinv = [], []
+        for lo, ext in self.owners:
+            for start, cnt in ((0, N[d]), (-WCNS5_GHOST, WCNS5_GHOST), (N[d], WCNS5_GHOST)):
+                sl = []
+                for a in (2, 1, 0):
+                    if a == d:
+                        sl.append(slice(org[a] - 3 + start, org[a] - 3 + start + cnt + 5))
+                    else:
+                        sl.append(slice(org[a] - 3 + lo[a], org[a] - 3 + lo[a] + ext[a] + 5))
+                S, J = wcns5_metrics_ext(xe[(slice(None),) + tuple(sl)].contiguous(), stream)
+                self.S.append(S)
+                self.jinv.append(J)
         self.ghosts = [torch.zeros((5, g[2], g[1], g[0]), dtype=torch.float64, device=xv.device)
-                       for g in self.dims[1:]]
+                       for o in range(no) for g in self.dims[3 * o + 1:3 * o + 3]]
 
-    def fill(self, q):
-        wcns5_fill_ghost_blocks(q, self.ghosts[0], self.ghosts[1], self.S[0], self.S[1], self.bounded, self.kinds,
-                                self.uinf, self.gamma, self.stream)
+    def split(self, q):
+        """The owners' states (contiguous copies) cut from a whole-grid state."""
+        out = []
+        for lo, ext in self.owners:
+            sl = [slice(None)] + [slice(lo[a], lo[a] + ext[a]) for a in (2, 1, 0)]
+            out.append(q[tuple(sl)].contiguous())
+        return out
 
-    def residual(self, q, entropy_fix: float = 0.1, eps: float = 1e-6, viscous=None):
-        """R of the owner (dQ/dt = -R); viscous = (prandtl, mu_inf, s_star) adds the
-        fourth-order viscous terms."""
-        self.fill(q)
-        qs = [q] + self.ghosts
-        rs = wcns5_euler_residual_blocks(qs, self.S, self.jinv, self.nbr, self.gamma, entropy_fix, eps,
+    def _all(self, qs):
+        return [x for o, q in enumerate(qs) for x in (q, self.ghosts[2 * o], self.ghosts[2 * o + 1])]
+
+    def _fill_all(self, qs):
+        for o, q in enumerate(qs):
+            wcns5_fill_ghost_blocks(q, self.ghosts[2 * o], self.ghosts[2 * o + 1], self.S[3 * o], self.S[3 * o + 1],
+                                    self.bounded, self.kinds, self.uinf, self.gamma, self.stream)
+
+    def fill(self, qs):
+        """The ghost blocks' states from the owners' states."""
+        self._fill_all(qs)
+
+    def residual(self, qs, entropy_fix: float = 0.1, eps: float = 1e-6, viscous=None):
+        """R of every owner (dQ/dt = -R); viscous = (prandtl, mu_inf, s_star) adds
+        the fourth-order viscous terms."""
+        self._fill_all(qs)
+        allq = self._all(qs)
+        rs = wcns5_euler_residual_blocks(allq, self.S, self.jinv, self.nbr, self.gamma, entropy_fix, eps,
                                          stream=self.stream)
         if viscous is not None:
-            c4_viscous_add_blocks(qs, rs, self.S, self.jinv, self.nbr, self.gamma, *viscous, stream=self.stream)
-        return rs[0]
+            c4_viscous_add_blocks(allq, rs, self.S, self.jinv, self.nbr, self.gamma, *viscous, stream=self.stream)
+        return [rs[3 * o] for o in range(len(qs))]
 
-    def steps(self, q, dt: float, nsteps: int, entropy_fix: float = 0.1, eps: float = 1e-6, viscous=None,
+    def steps(self, qs, dt: float, nsteps: int, entropy_fix: float = 0.1, eps: float = 1e-6, viscous=None,
               work=None):
-        """nsteps RK3 steps in place on q (cfd_wcns5_steps_blocks_closed)."""
+        """nsteps RK3 steps in place on the owners' states (cfd_wcns5_steps_blocks_closed)."""
         torch = self.torch
-        qs = [q] + self.ghosts
-        dims = (C.c_int32 * 9)(*[v for m in self.dims for v in m])
-        nb = (C.c_int32 * 18)(*[v for row in self.nbr for v in row])
+        allq = self._all(qs)
+        nb = len(allq)
+        dims = (C.c_int32 * (3 * nb))(*[v for m in self.dims for v in m])
+        nbt = (C.c_int32 * (6 * nb))(*[v for row in self.nbr for v in row])
         nbytes = C.c_size_t()
-        _check(lib().cfd_wcns5_ns_blocks_work_bytes(3, dims, nb, C.byref(nbytes)))
+        _check(lib().cfd_wcns5_ns_blocks_work_bytes(nb, dims, nbt, C.byref(nbytes)))
         if work is None or work.numel() * work.element_size() < nbytes.value:
-            work = _scratch(torch, nbytes.value, q.device, self.stream)
-        cl = WcnsClosure(0, 1, 2, self.bounded, (C.c_int32 * 2)(*self.kinds), (C.c_double * 3)(*self.uinf))
+            work = _scratch(torch, nbytes.value, qs[0].device, self.stream)
+        no = len(qs)
+        cls = (WcnsClosure * no)(*[WcnsClosure(3 * o, 3 * o + 1, 3 * o + 2, self.bounded,
+                                               (C.c_int32 * 2)(*self.kinds), (C.c_double * 3)(*self.uinf))
+                                   for o in range(no)])
         pr, mu, ss = viscous if viscous is not None else (0.72, 0.0, 110.4 / 288.15)
-        ptrs = lambda ts: (C.c_void_p * 3)(*[_ptr(t) for t in ts])   # noqa: E731
-        _check(lib().cfd_wcns5_steps_blocks_closed(3, dims, nb, ptrs(qs), ptrs(self.S), ptrs(self.jinv), C.byref(cl),
+        ptrs = lambda ts: (C.c_void_p * nb)(*[_ptr(t) for t in ts])   # noqa: E731
+        _check(lib().cfd_wcns5_steps_blocks_closed(nb, dims, nbt, ptrs(allq), ptrs(self.S), ptrs(self.jinv), cls, no,
                                                    1 if viscous is not None else 0, _ptr(work), nbytes.value,
                                                    self.gamma, float(entropy_fix), float(eps), float(pr), float(mu),
                                                    float(ss), float(dt), int(nsteps),
                                                    _stream_handle(torch, self.stream)))
+        return qs
+
+
+class WcnsClosedBlock(WcnsClosedTiling):
+    """One owner block (the untiled WcnsClosedTiling): the same calls on a
+    single state q instead of a list; S, jinv: [owner, low ghost, high ghost];
+    ghosts: [low, high]."""
+
+    def __init__(self, xv, period, bounded: int, kinds, uinf=(0.0, 0.0, 0.0), gamma: float = 1.4, stream=None):
+        super().__init__(xv, period, bounded, kinds, uinf, gamma, None, stream)
+
+    def fill(self, q):
+        self._fill_all([q])
+
+    def residual(self, q, entropy_fix: float = 0.1, eps: float = 1e-6, viscous=None):
+        return super().residual([q], entropy_fix, eps, viscous)[0]
+
+    def steps(self, q, dt: float, nsteps: int, entropy_fix: float = 0.1, eps: float = 1e-6, viscous=None,
+              work=None):
+        super().steps([q], dt, nsteps, entropy_fix, eps, viscous, work)
         return q
 
 

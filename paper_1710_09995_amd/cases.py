@@ -604,6 +604,26 @@ def paper_share_case(nbx: int = 4, nbz: int = 4, ni: int = 512, nj: int = 512, n
     return Case("paper_share", par, dims, nodes, conns, bcs, q0, info={"seed": seed})
 
 
+def paper_share_vertices(nbx: int = 4, nbz: int = 4, ni: int = 512, nj: int = 512, nk: int = 144,
+                         amp: float = 0.05, stretch: float = 2.0):
+    """The whole grid of paper_share_case (its nbx x nbz blocks side by side)
+    as the vertex array of the WCNS-E-5 closures: index i = z and j = x
+    periodic (their nbz ni and nbx nj upper corners), k = wall-normal with its
+    nk + 1 vertex planes (the wall first).  Returns (Xv [3, nk + 1, nbx nj,
+    nbz ni], period [3][3]); vertex (i, j, k) sits where paper_share_case puts
+    node (i + 1, j + 1, k) of the whole grid."""
+    NI, NJ = nbz * ni, nbx * nj
+    zz = (np.arange(NI) + 1.0) / ni
+    xx = (np.arange(NJ) + 1.0) / nj
+    eta = np.arange(nk + 1) / nk
+    E, Xg, Zg = np.meshgrid(eta, xx, zz, indexing="ij")
+    yw = amp * np.sin(math.pi * Xg) ** 2 * (0.75 + 0.25 * np.cos(2.0 * math.pi * Zg))
+    t = 1.0 + np.tanh(stretch * (E - 1.0)) / math.tanh(stretch)
+    Y = yw + (1.0 - yw) * t
+    period = [(0.0, 0.0, float(nbz)), (float(nbx), 0.0, 0.0), (0.0, 0.0, 0.0)]
+    return np.stack([Xg, Y, Zg]).astype(np.float64), period
+
+
 def coarsen_case(case: Case) -> Case:
     """The next coarser grid of a multigrid hierarchy: every block keeps every
     second node along each direction (the coarse cells are unions of 2 x 2 x 2

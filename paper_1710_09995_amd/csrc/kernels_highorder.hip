@@ -2287,11 +2287,12 @@ void check_closure(int32_t nblk, const int32_t* dims, const int32_t* nbr, const 
 }
 
 // RK3 steps on joined blocks (cfd_wcns5_ns_steps_blocks), with the ghost
-// blocks of `closure` (if any) refilled before every stage and the viscous
-// terms only when `viscous`.
+// blocks of the nclosures closures refilled before every stage and the
+// viscous terms only when `viscous`.
 cfd_status ns_steps_blocks_impl(int32_t nblk, const int32_t* dims, const int32_t* nbr, double* const* q_dev,
                                 const double* const* s_dev, const double* const* jinv_dev,
-                                const cfd_wcns5_closure* closure, bool viscous, void* work_dev, size_t work_bytes,
+                                const cfd_wcns5_closure* closures, int32_t nclosures, bool viscous, void* work_dev,
+                                size_t work_bytes,
                                 double gamma, double entropy_fix, double eps, double prandtl, double mu_inf,
                                 double s_star, double dt, int32_t nsteps, hipStream_t stream) {
   return cfd::host_guarded([&] {
@@ -2304,7 +2305,17 @@ cfd_status ns_steps_blocks_impl(int32_t nblk, const int32_t* dims, const int32_t
       cfd::host_fail(CFD_EINVAL, "bad gas parameters");
     if (!(dt > 0.0) || !std::isfinite(dt)) cfd::host_fail(CFD_EINVAL, "dt must be positive and finite");
     if (nsteps < 0) cfd::host_fail(CFD_EINVAL, "nsteps must be >= 0");
-    if (closure) check_closure(nblk, dims, nbr, *closure);
+    if (nclosures < 0 || (nclosures > 0 && !closures)) cfd::host_fail(CFD_EINVAL, "bad closure list");
+    if (nclosures > 0) {
+      std::vector<char> used(nblk, 0);
+      for (int c = 0; c < nclosures; ++c) {
+        check_closure(nblk, dims, nbr, closures[c]);
+        for (int32_t b : {closures[c].owner, closures[c].ghost_lo, closures[c].ghost_hi}) {
+          if (used[b]) cfd::host_fail(CFD_EINVAL, "closure: a block belongs to two closures");
+          used[b] = 1;
+        }
+      }
+    }
     std::vector<int64_t> off(nblk + 1, 0);
     size_t vscratch = 0;
     for (int b = 0; b < nblk; ++b) {
@@ -2332,10 +2343,12 @@ cfd_status ns_steps_blocks_impl(int32_t nblk, const int32_t* dims, const int32_t
     const double a[3] = {0.0, 0.75, 1.0 / 3.0}, bb[3] = {1.0, 0.25, 2.0 / 3.0};
     for (int it = 0; it < nsteps; ++it)
       for (int st = 0; st < 3; ++st) {
-        if (closure)
-          cfd::fill_ghost_blocks_launch(q_dev[closure->owner], q_dev[closure->ghost_lo], q_dev[closure->ghost_hi],
-                                        s_dev[closure->ghost_lo], s_dev[closure->owner], dims + 3 * closure->owner,
-                                        closure->bounded, closure->kind, gamma, closure->uinf, stream);
+        for (int c = 0; c < nclosures; ++c) {
+          const cfd_wcns5_closure& cl = closures[c];
+          cfd::fill_ghost_blocks_launch(q_dev[cl.owner], q_dev[cl.ghost_lo], q_dev[cl.ghost_hi], s_dev[cl.ghost_lo],
+                                        s_dev[cl.owner], dims + 3 * cl.owner, cl.bounded, cl.kind, gamma, cl.uinf,
+                                        stream);
+        }
         cfd::wcns5_blocks_residual_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, R.data(), work_dev, gamma,
                                           entropy_fix, eps, stream);
         if (viscous)
@@ -2360,19 +2373,21 @@ extern "C" cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dim
                                                 double gamma, double entropy_fix, double eps, double prandtl,
                                                 double mu_inf, double s_star, double dt, int32_t nsteps,
                                                 hipStream_t stream) {
-  return ns_steps_blocks_impl(nblk, dims, nbr, q_dev, s_dev, jinv_dev, nullptr, true, work_dev, work_bytes, gamma,
+  return ns_steps_blocks_impl(nblk, dims, nbr, q_dev, s_dev, jinv_dev, nullptr, 0, true, work_dev, work_bytes, gamma,
                               entropy_fix, eps, prandtl, mu_inf, s_star, dt, nsteps, stream);
 }
 
 extern "C" cfd_status cfd_wcns5_steps_blocks_closed(int32_t nblk, const int32_t* dims, const int32_t* nbr,
                                                     double* const* q_dev, const double* const* s_dev,
-                                                    const double* const* jinv_dev, const cfd_wcns5_closure* closure,
+                                                    const double* const* jinv_dev,
+                                                    const cfd_wcns5_closure* closures, int32_t nclosures,
                                                     int32_t viscous, void* work_dev, size_t work_bytes, double gamma,
                                                     double entropy_fix, double eps, double prandtl, double mu_inf,
                                                     double s_star, double dt, int32_t nsteps, hipStream_t stream) {
-  if (!closure) return cfd::host_guarded([] { cfd::host_fail(CFD_EINVAL, "NULL closure"); });
-  return ns_steps_blocks_impl(nblk, dims, nbr, q_dev, s_dev, jinv_dev, closure, viscous != 0, work_dev, work_bytes,
-                              gamma, entropy_fix, eps, prandtl, mu_inf, s_star, dt, nsteps, stream);
+  if (!closures || nclosures < 1)
+    return cfd::host_guarded([] { cfd::host_fail(CFD_EINVAL, "at least one closure is needed"); });
+  return ns_steps_blocks_impl(nblk, dims, nbr, q_dev, s_dev, jinv_dev, closures, nclosures, viscous != 0, work_dev,
+                              work_bytes, gamma, entropy_fix, eps, prandtl, mu_inf, s_star, dt, nsteps, stream);
 }
 
 extern "C" cfd_status cfd_wcns5_extend_vertices(const double* xv_dev, const int32_t n[3], int32_t bounded,

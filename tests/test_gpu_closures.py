@@ -152,3 +152,39 @@ def test_full_size_bump_grid_keeps_a_uniform_stream():
     w = WcnsClosedBlock(xv, PERIOD, 1, (NOSLIP_ADIABATIC, FARFIELD), UINF, GAMMA)
     w.steps(q, 1e-4, 2, viscous=(0.72, UINF[0] / 1e6, 0.38))
     assert bool(torch.isfinite(q).all())
+
+
+def test_tiled_owners_on_the_one_gpu_share_geometry():
+    """The one-GPU share's geometry at reduced size: 4 x 4 blocks of 16 x 16 x
+    12 cells tiling z and x, no-slip wall below and far field above the
+    wall-normal direction, each block closed by its own ghost blocks.  On the
+    device the tiled residual (viscous terms included) and two RK3
+    Navier-Stokes steps are bitwise the single closed block's, and the
+    residual matches the oracle's tiling."""
+    import torch
+    from paper_1710_09995_amd.binding import WcnsClosedBlock, WcnsClosedTiling
+    Xv, P = cases.paper_share_vertices(4, 4, 16, 16, 12)
+    n = (64, 64, 12)
+    say("closed tiling 4 x 4 of 16 x 16 x 12")
+    kinds = (NOSLIP_ADIABATIC, FARFIELD)
+    cuts = {0: [0, 16, 32, 48, 64], 1: [0, 16, 32, 48, 64]}
+    xv = _dev(Xv)
+    one = WcnsClosedBlock(xv, P, 2, kinds, UINF, GAMMA)
+    tl = WcnsClosedTiling(xv, P, 2, kinds, UINF, GAMMA, cuts=cuts)
+    q = _smooth_state(n, seed=9)
+    qd = _dev(q)
+    R1 = one.residual(qd, viscous=VISC)
+    Rs = tl.residual(tl.split(qd), viscous=VISC)
+    o = ocl.ClosedBlocks(Xv, P, 2, kinds, cuts, GAMMA, freestream=(MACH, 0.0, 0.0))
+    want = o.residual(o.split(q), viscous=VISC)
+    for (lo, ext), R, W in zip(tl.owners, Rs, want):
+        sl = (slice(None), slice(lo[2], lo[2] + ext[2]), slice(lo[1], lo[1] + ext[1]), slice(lo[0], lo[0] + ext[0]))
+        assert torch.equal(R, R1[sl]), (lo, ext)
+        assert _rel(R.cpu().numpy(), W) <= 1e-12, (lo, ext, _rel(R.cpu().numpy(), W))
+    visc = (0.72, 0.002, 0.38)
+    qs = tl.split(qd)
+    one.steps(qd, 2e-4, 2, viscous=visc)
+    tl.steps(qs, 2e-4, 2, viscous=visc)
+    for (lo, ext), x in zip(tl.owners, qs):
+        sl = (slice(None), slice(lo[2], lo[2] + ext[2]), slice(lo[1], lo[1] + ext[1]), slice(lo[0], lo[0] + ext[0]))
+        assert torch.equal(x, qd[sl]), (lo, ext)
