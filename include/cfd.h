@@ -224,7 +224,7 @@ cfd_status cfd_step_implicit(cfd_ctx* ctx, double* q_arena_dev, int32_t nsteps, 
  * cfd_mg_work_size: bytes of work for the hierarchy (three state-layout
  * arenas per level).  cfd_mg_cycles: work_dev 256-byte aligned, disjoint
  * from every level's state; CFD_EINVAL on a hierarchy whose extents do not
- * halve, different block counts or time-step modes, nlevels outside [1, 16],
+ * halve, different block counts or flow parameters, nlevels outside [1, 16],
  * pre or coarse outside [0, 1000], overlapping states; CFD_ENOMEM on a short
  * workspace.  Asynchronous on stream. */
 cfd_status cfd_mg_work_size(cfd_ctx* const* levels, int32_t nlevels, size_t* bytes);

@@ -1161,7 +1161,7 @@ cfd_status cfd_step_implicit(cfd_ctx* c, double* q, int32_t nsteps, int32_t swee
 // ---------------------------------------------------------------- multigrid
 // Levels of a hierarchy: the same block count, every extent of level l + 1
 // half the one of level l (the coarse grid keeps every second node; the
-// tables are the caller's coarsening), the same time-step mode.
+// tables are the caller's coarsening), the same flow parameters.
 void check_hierarchy(cfd_ctx* const* lv, int n) {
   if (!lv) fail(CFD_EINVAL, "NULL argument");
   if (n < 1 || n > 16) fail(CFD_EINVAL, "nlevels must be in [1, 16]");
@@ -1170,8 +1170,12 @@ void check_hierarchy(cfd_ctx* const* lv, int n) {
   for (int l = 1; l < n; ++l) {
     if (lv[l] == lv[l - 1]) fail(CFD_EINVAL, "levels must be distinct contexts");
     if (lv[l]->nblk != lv[0]->nblk) fail(CFD_EINVAL, "every level must have the same blocks");
-    if (lv[l]->params.local_dt != lv[0]->params.local_dt)
-      fail(CFD_EINVAL, "every level must take the same time-step mode");
+    const cfd_params &a = lv[l]->params, &b = lv[0]->params;
+    if (a.gamma != b.gamma || a.prandtl != b.prandtl || a.mach != b.mach || a.alpha != b.alpha || a.beta != b.beta ||
+        a.reynolds != b.reynolds || a.sutherland != b.sutherland || a.cfl != b.cfl ||
+        a.entropy_fix != b.entropy_fix || a.limiter_eps != b.limiter_eps || a.viscous != b.viscous ||
+        a.flux_fp32 != b.flux_fp32 || a.local_dt != b.local_dt)
+      fail(CFD_EINVAL, "every level must take the same flow parameters");
     for (int b = 0; b < lv[0]->nblk; ++b) {
       const cfd_dims& f = lv[l - 1]->dims[b];
       const cfd_dims& c = lv[l]->dims[b];

@@ -119,3 +119,22 @@ def test_captured_cycles_are_bitwise_the_eager_cycles():
         m.close()
     sa.close()
     sb.close()
+
+
+def test_hierarchy_is_checked():
+    """A level that is not the coarsening of the one above (same extents, or
+    other flow parameters) is refused before anything runs."""
+    import ctypes as C
+    from paper_1710_09995_amd import binding as B
+    from paper_1710_09995_amd.binding import Solver
+    case = cases.channel_case(16, 8, 4, mach=0.6, hb=0.05)
+    coarse = cases.coarsen_case(case)
+    a, b, c = Solver(case), Solver(case), Solver(coarse.with_params(mach=0.61))
+    nb = C.c_size_t()
+    for pair, what in (((a, b), "twice"), ((a, c), "flow parameters")):
+        lv = (C.c_void_p * 2)(*[s.ctx.value for s in pair])
+        with pytest.raises(B.CfdError) as e:
+            B._check(B.lib().cfd_mg_work_size(lv, 2, C.byref(nb)))
+        assert e.value.status == -1 and what in str(e.value)
+    for s in (a, b, c):
+        s.close()
