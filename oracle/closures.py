@@ -42,8 +42,12 @@ about a flat slip wall gives, with the closures, the residual of the
 periodic domain of twice the height that holds the state and its mirror image
 (inviscid and viscous); the vertex extension reproduces a grid that is linear
 along the bounded direction; away from the boundary the closed residual does
-not see the closure; and owners tiling the periodic directions give bitwise
-the single closed block's residual.
+not see the closure; owners tiling the periodic directions give bitwise
+the single closed block's residual; and a block closed across two
+directions (ClosedDuct: corner ghost blocks filled in sweep order) keeps a
+uniform stream on the warm-start channel grid and, with walls on all four
+faces of a flat duct, gives the periodic residual of the field mirrored
+across both directions (a skipped corner fill fails it).
 """
 from __future__ import annotations
 
@@ -312,3 +316,122 @@ class ClosedBlocks:
             V = ho.viscous_residual_blocks(Qs, self.S, self.Jinv, self.nbr, self.gamma, *viscous)
             R = [a + b for a, b in zip(R, V)]
         return [R[3 * o] for o in range(len(self.owners))]
+
+
+def extended_vertices_multi(Xv: np.ndarray, period, bounded):
+    """extended_vertices for one or two bounded directions (ascending tuple):
+    the periodic directions wrapped first, then each bounded direction in
+    ascending order continued linearly past both ends (the corner vertices
+    past two ends come from continuing the already continued planes)."""
+    bounded = tuple(sorted(bounded))
+    shape = Xv.shape[1:]
+    n = [shape[2], shape[1], shape[0]]
+    for d in bounded:
+        n[d] -= 1
+    X = Xv
+    origin = [0, 0, 0]
+    for d in range(3):
+        if d in bounded:
+            continue
+        ax = _axis(d)
+        idx = np.arange(-3, n[d] + 2)
+        wrap, q = idx % n[d], idx // n[d]
+        X = np.take(X, wrap, axis=ax)
+        shp = [1, 1, 1, 1]
+        shp[ax] = idx.size
+        X = X + q.reshape(shp) * np.asarray(period[d], dtype=np.float64).reshape(3, 1, 1, 1)
+        origin[d] = 3
+    for d in bounded:
+        ax = _axis(d)
+        lo0, lo1 = ho._win(X, ax, 0, 1), ho._win(X, ax, 1, 1)
+        hi0, hi1 = ho._win(X, ax, n[d], 1), ho._win(X, ax, n[d] - 1, 1)
+        below = [lo0 + m * (lo0 - lo1) for m in range(XLAYERS, 0, -1)]
+        above = [hi0 + m * (hi0 - hi1) for m in range(1, XLAYERS + 1)]
+        X = np.concatenate(below + [X] + above, axis=ax)
+        origin[d] = XLAYERS + 1
+    return X, origin
+
+
+class ClosedDuct:
+    """One owner block periodic along one direction and closed across the
+    other two (bounded = (d1, d2), d1 < d2; kinds[d] = (low kind, high kind)):
+    ghost blocks on its four bounded faces and corner ghost blocks where two
+    of them meet.  Blocks: 0 owner; 1, 2 the low and high ghost blocks across
+    d1; 3, 4 across d2; 5 .. 8 the corners (d1 side, d2 side) = (lo, lo),
+    (lo, hi), (hi, lo), (hi, hi).  Along each bounded direction the ghost
+    blocks close into rings, so every link is mutual.  Fill order (the sweep
+    order of the finite-volume ghost fill): across d1 from the owner, then
+    across d2 from the owner and, for the corners, from the d1 ghost blocks
+    (the d2 condition applied to their cells)."""
+
+    def __init__(self, Xv, period, bounded, kinds, gamma=1.4, freestream=(0.5, 0.0, 0.0)):
+        d1, d2 = sorted(bounded)
+        self.d1, self.d2, self.kinds, self.gamma, self.freestream = d1, d2, kinds, gamma, freestream
+        for d in (d1, d2):
+            if len(kinds[d]) != 2 or any(k not in (FARFIELD, SLIPWALL, NOSLIP_ADIABATIC) for k in kinds[d]):
+                raise ValueError("every bounded face needs a wall or far-field condition")
+        shape = Xv.shape[1:]
+        n = [shape[2], shape[1], shape[0]]
+        n[d1] -= 1
+        n[d2] -= 1
+        self.n = tuple(n)
+        self.E, self.origin = extended_vertices_multi(Xv, period, (d1, d2))
+        # (start, count) along d1 and d2 for each block, in block order
+        G = GHOST
+        spans = {d: {"own": (0, n[d]), "lo": (-G, G), "hi": (n[d], G)} for d in (d1, d2)}
+        order = [("own", "own"), ("lo", "own"), ("hi", "own"), ("own", "lo"), ("own", "hi"),
+                 ("lo", "lo"), ("lo", "hi"), ("hi", "lo"), ("hi", "hi")]
+        self.where = order
+        self.dims = []
+        self.S, self.Jinv = [], []
+        for w1, w2 in order:
+            ext = list(n)
+            ext[d1] = spans[d1][w1][1]
+            ext[d2] = spans[d2][w2][1]
+            self.dims.append(tuple(ext))
+            Xw = self.E
+            for d in range(3):
+                if d == d1:
+                    st, c = spans[d1][w1]
+                elif d == d2:
+                    st, c = spans[d2][w2]
+                else:
+                    st, c = 0, n[d]
+                Xw = ho._win(Xw, _axis(d), self.origin[d] - 3 + st, c + 5)
+            S, J = ho.metrics6(Xw)
+            self.S.append(S)
+            self.Jinv.append(J)
+        idx = {w: b for b, w in enumerate(order)}
+        nxt = {"lo": "own", "own": "hi", "hi": "lo"}          # the block above along a bounded direction (ring)
+        self.nbr = [[b] * 6 for b in range(9)]
+        for b, (w1, w2) in enumerate(order):
+            up1, up2 = idx[(nxt[w1], w2)], idx[(w1, nxt[w2])]
+            self.nbr[b][2 * d1 + 1] = up1
+            self.nbr[up1][2 * d1] = b
+            self.nbr[b][2 * d2 + 1] = up2
+            self.nbr[up2][2 * d2] = b
+        # fills: (source block, low ghost, high ghost, direction, kinds), in order
+        self.fills = [(0, 1, 2, d1, kinds[d1]), (0, 3, 4, d2, kinds[d2]),
+                      (1, 5, 6, d2, kinds[d2]), (2, 7, 8, d2, kinds[d2])]
+
+    def blocks(self, Q):
+        Qs = [Q] + [np.zeros((5,) + tuple(reversed(m))) for m in self.dims[1:]]
+        for src, lo, hi, d, k in self.fills:
+            trio = [Qs[src], Qs[lo], Qs[hi]]
+            fill_ghosts(trio, [self.S[src], self.S[lo], self.S[hi]], d, [(1, 0, k[0]), (2, 1, k[1])], self.gamma,
+                        self.freestream)
+        return Qs
+
+    def residual(self, Q, eps_h=0.1, eps=1e-6, viscous=None):
+        Qs = self.blocks(Q)
+        R = ho.wcns5_euler_residual_blocks(Qs, self.S, self.Jinv, self.nbr, self.gamma, eps_h, eps)[0]
+        if viscous is not None:
+            R = R + ho.viscous_residual_blocks(Qs, self.S, self.Jinv, self.nbr, self.gamma, *viscous)[0]
+        return R
+
+    def ns_steps(self, Q, dt, nsteps, eps_h=0.1, eps=1e-6, viscous=None):
+        from .solver import ssp_rk3
+        q = Q
+        for _ in range(nsteps):
+            q = ssp_rk3(q, dt, lambda x: self.residual(x, eps_h, eps, viscous))
+        return q

@@ -15,7 +15,10 @@ its references; oracle/closures.py):
   exactly;
 * cells more than the stencils' reach from both faces do not see the closure;
 * owners tiling the periodic directions (each with ghost blocks joined to
-  its neighbours' ghost blocks) give bitwise the single closed block.
+  its neighbours' ghost blocks) give bitwise the single closed block;
+* closed across two directions (corner ghost blocks): a uniform stream on the
+  warm-start channel grid stays uniform, and walls on all four faces of a
+  flat duct give the periodic residual of the doubly mirrored field.
 """
 import numpy as np
 import pytest
@@ -155,3 +158,64 @@ def test_tiled_owners_give_the_single_block(viscous):
     for (lo, ext), R in zip(tl.owners, Rs):
         sl = (slice(None), slice(lo[2], lo[2] + ext[2]), slice(lo[1], lo[1] + ext[1]), slice(lo[0], lo[0] + ext[0]))
         assert np.array_equal(R, R1[sl]), (lo, ext)
+
+
+def _channel_vertices(n=(24, 12, 8)):
+    c = cases.channel_case(*n, mach=0.6, hb=0.06)
+    return np.ascontiguousarray(c.nodes[0][:, 1:, :, :]), [(0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0)]
+
+
+@pytest.mark.parametrize("viscous", [False, True])
+def test_duct_keeps_a_uniform_stream(viscous):
+    """The warm-start channel grid (bump on the lower wall), closed across x
+    and y with the far field on all four faces, corners included: a uniform
+    stream stays uniform."""
+    Xv, P = _channel_vertices()
+    kinds = {0: (FARFIELD, FARFIELD), 1: (FARFIELD, FARFIELD)}
+    d = cl.ClosedDuct(Xv, P, (0, 1), kinds, GAMMA, freestream=(0.6, 0.0, 0.0))
+    q = _freestream(d.n, 0.6)
+    assert np.max(np.abs(d.residual(q, viscous=VISC if viscous else None))) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", [SLIPWALL, NOSLIP_ADIABATIC])
+@pytest.mark.parametrize("viscous", [False, True])
+def test_duct_walls_equal_the_mirrored_periodic_field(kind, viscous):
+    """A flat duct (uniform in x and y, stretched along the periodic z) with
+    walls on all four faces: the state, its mirror images across x and y and
+    across both form a field periodic over twice the width and height; the
+    closed residual (corner ghost blocks included: the viscous terms read
+    them) equals the periodic residual of that field."""
+    ni, nj, nk = 10, 8, 6
+    hx, hy = 0.1, 0.12
+    k = np.arange(1, nk + 1)
+    z = k / nk + 0.03 * np.sin(2 * np.pi * k / nk)
+    X = np.empty((3, nk, nj + 1, ni + 1))
+    X[0] = (np.arange(ni + 1) * hx)[None, None, :]
+    X[1] = (np.arange(nj + 1) * hy)[None, :, None]
+    X[2] = z[:, None, None]
+    P = [(0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0)]
+    d = cl.ClosedDuct(X, P, (0, 1), {0: (kind, kind), 1: (kind, kind)}, GAMMA)
+    q = _smooth_state((ni, nj, nk), seed=11)
+    R = d.residual(q, viscous=VISC if viscous else None)
+
+    def mirror(a, axis_vel):
+        out = a.copy()
+        if kind == SLIPWALL:
+            out[axis_vel] = -a[axis_vel]
+        else:
+            out[1:4] = -a[1:4]
+        return out
+    qx = mirror(q[:, :, :, ::-1], 1)
+    top = np.concatenate([q, qx], axis=3)
+    qd = np.concatenate([top, mirror(top[:, :, ::-1, :], 2)], axis=2)
+    Xd = np.empty((3, nk, 2 * nj, 2 * ni))
+    Xd[0] = (np.arange(1, 2 * ni + 1) * hx)[None, None, :]
+    Xd[1] = (np.arange(1, 2 * nj + 1) * hy)[None, :, None]
+    Xd[2] = z[:, None, None]
+    Pd = [(2 * ni * hx, 0.0, 0.0), (0.0, 2 * nj * hy, 0.0), (0.0, 0.0, 1.0)]
+    Sd, Jd = ho.metrics6(ho.periodic_vertices(Xd, Pd))
+    Rd = ho.wcns5_euler_residual_curv_periodic(qd, Sd, Jd, GAMMA, 0.1)
+    if viscous:
+        Rd = Rd + ho.viscous_residual_curv_periodic(qd, Sd, Jd, GAMMA, *VISC)
+    ref = Rd[:, :, :nj, :ni]
+    assert np.max(np.abs(R - ref)) <= 1e-12 * np.max(np.abs(ref)), np.max(np.abs(R - ref))
