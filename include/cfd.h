@@ -645,8 +645,10 @@ cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dims, const in
  * and the viscous terms only when viscous != 0 (same workspace size).  Each
  * closure is checked against the table (distinct blocks in range, ghost
  * extents, the ghost blocks joined to the owner's two faces across
- * `bounded`), and no block may belong to two closures.  The ghost blocks' own
- * states after a call are scratch.  Asynchronous on stream. */
+ * `bounded`).  Closures are applied in list order; a block may be the ghost
+ * block of one closure only, and the owner of a closure may be the ghost
+ * block of an earlier one (corners), not of a later one.  The ghost blocks'
+ * own states after a call are scratch.  Asynchronous on stream. */
 #define CFD_WCNS5_GHOST 5
 #define CFD_WCNS5_XLAYERS 7
 typedef struct {
@@ -657,6 +659,18 @@ typedef struct {
 } cfd_wcns5_closure;
 cfd_status cfd_wcns5_extend_vertices(const double* xv_dev, const int32_t n[3], int32_t bounded,
                                      const double period[9], double* xe_dev, hipStream_t stream);
+/* The same for one or two bounded directions, bit d of bounded_mask set for a
+ * bounded direction d (at most two bits; 0: all periodic).  With two, the
+ * lower direction is continued first and the second from those values, so
+ * the vertices past two ends (the corner ghost blocks') continue the
+ * continued planes.  A block closed across two directions has, besides its
+ * four face ghost blocks, four corner ghost blocks CFD_WCNS5_GHOST cells
+ * across both; a corner is filled by a closure whose owner is the face ghost
+ * block across the lower direction (its cells mirrored across the higher
+ * direction's boundary), listed after the closure that fills that face ghost
+ * block: the sweep order of the finite-volume ghost fill. */
+cfd_status cfd_wcns5_extend_vertices_mask(const double* xv_dev, const int32_t n[3], int32_t bounded_mask,
+                                          const double period[9], double* xe_dev, hipStream_t stream);
 cfd_status cfd_wcns5_fill_ghost_blocks(const double* q_dev, double* q_lo_dev, double* q_hi_dev, const double* s_dev,
                                        const double* s_lo_dev, const int32_t n[3], int32_t bounded,
                                        const int32_t kind[2], double gamma, const double uinf[3],

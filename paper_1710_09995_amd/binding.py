@@ -80,7 +80,8 @@ EXPORTS = ["cfd_layout", "cfd_workspace_size", "cfd_create_blocks", "cfd_destroy
            "cfd_c4_viscous_add_blocks", "cfd_wcns5_ns_step_work_bytes", "cfd_wcns5_ns_steps_curv_periodic",
            "cfd_wcns5_implicit_step_work_bytes", "cfd_wcns5_implicit_steps_curv_periodic",
            "cfd_wcns5_implicit_blocks_work_bytes", "cfd_wcns5_implicit_steps_blocks", "cfd_wcns5_ns_blocks_work_bytes",
-           "cfd_wcns5_ns_steps_blocks", "cfd_wcns5_extend_vertices", "cfd_wcns5_fill_ghost_blocks",
+           "cfd_wcns5_ns_steps_blocks", "cfd_wcns5_extend_vertices", "cfd_wcns5_extend_vertices_mask",
+           "cfd_wcns5_fill_ghost_blocks",
            "cfd_wcns5_steps_blocks_closed",
            "cfd_status_string", "cfd_last_error"]
 
@@ -183,6 +184,7 @@ def lib(build_if_missing: bool = True):
     L.cfd_mg_work_size.argtypes = [C.POINTER(vp), i32, C.POINTER(C.c_size_t)]
     L.cfd_mg_cycles.argtypes = [C.POINTER(vp), C.POINTER(vp), i32, i32, i32, i32, vp, C.c_size_t, vp, vp]
     L.cfd_wcns5_extend_vertices.argtypes = [vp, i32p, i32, C.POINTER(C.c_double), vp, vp]
+    L.cfd_wcns5_extend_vertices_mask.argtypes = [vp, i32p, i32, C.POINTER(C.c_double), vp, vp]
     L.cfd_wcns5_fill_ghost_blocks.argtypes = [vp, vp, vp, vp, vp, i32p, i32, i32p, C.c_double,
                                               C.POINTER(C.c_double), vp]
     L.cfd_wcns5_steps_blocks_closed.argtypes = [i32, i32p, i32p, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
@@ -941,6 +943,102 @@ class WcnsClosedBlock(WcnsClosedTiling):
     def steps(self, q, dt: float, nsteps: int, entropy_fix: float = 0.1, eps: float = 1e-6, viscous=None,
               work=None):
         super().steps([q], dt, nsteps, entropy_fix, eps, viscous, work)
+        return q
+
+
+class WcnsClosedDuct:
+    """A curvilinear block periodic along one direction and closed across the
+    other two (bounded = (d1, d2), d1 < d2; kinds[d] = (low, high) cfd_bc_kind
+    of direction d): four face ghost blocks and four corner ghost blocks.
+    xv: vertices with n_d + 1 planes along each bounded direction and the n_t
+    upper corners along the periodic one (a CUDA tensor).  Blocks: 0 owner;
+    1, 2 the low and high ghost blocks across d1; 3, 4 across d2; 5 .. 8 the
+    corners (d1 side, d2 side) = (lo, lo), (lo, hi), (hi, lo), (hi, hi).  The
+    corners are filled from the d1 ghost blocks after those (sweep order)."""
+
+    def __init__(self, xv, period, bounded, kinds, uinf=(0.0, 0.0, 0.0), gamma: float = 1.4, stream=None):
+        import torch
+        self.torch = torch
+        self.stream = stream
+        d1, d2 = sorted(int(d) for d in bounded)
+        self.d1, self.d2, self.uinf, self.gamma = d1, d2, tuple(uinf), float(gamma)
+        self.kinds = {d1: tuple(kinds[d1]), d2: tuple(kinds[d2])}
+        n = [int(xv.shape[3]), int(xv.shape[2]), int(xv.shape[1])]
+        n[d1] -= 1
+        n[d2] -= 1
+        self.n = tuple(n)
+        e = [n[d] + 1 + 2 * WCNS5_XLAYERS if d in (d1, d2) else n[d] + 5 for d in range(3)]
+        xe = torch.empty((3, e[2], e[1], e[0]), dtype=torch.float64, device=xv.device)
+        per = (C.c_double * 9)(*[float(v) for row in period for v in row])
+        _check(lib().cfd_wcns5_extend_vertices_mask(_ptr(xv), (C.c_int32 * 3)(*n), (1 << d1) | (1 << d2), per,
+                                                    _ptr(xe), _stream_handle(torch, stream)))
+        G = WCNS5_GHOST
+        spans = {d: {"own": (0, n[d]), "lo": (-G, G), "hi": (n[d], G)} for d in (d1, d2)}
+        order = [("own", "own"), ("lo", "own"), ("hi", "own"), ("own", "lo"), ("own", "hi"),
+                 ("lo", "lo"), ("lo", "hi"), ("hi", "lo"), ("hi", "hi")]
+        org = [WCNS5_XLAYERS + 1 if d in (d1, d2) else 3 for d in range(3)]
+        self.dims, self.S, self.jinv = [], [], []
+        for w1, w2 in order:
+            ext, sl = list(n), []
+            ext[d1], ext[d2] = spans[d1][w1][1], spans[d2][w2][1]
+            self.dims.append(tuple(ext))
+            for a in (2, 1, 0):
+                st = spans[d1][w1][0] if a == d1 else spans[d2][w2][0] if a == d2 else 0
+                sl.append(slice(org[a] - 3 + st, org[a] - 3 + st + ext[a] + 5))
+            S, J = wcns5_metrics_ext(xe[(slice(None),) + tuple(sl)].contiguous(), stream)
+            self.S.append(S)
+            self.jinv.append(J)
+        idx = {w: b for b, w in enumerate(order)}
+        nxt = {"lo": "own", "own": "hi", "hi": "lo"}
+        self.nbr = [[b] * 6 for b in range(9)]
+        for b, (w1, w2) in enumerate(order):
+            up1, up2 = idx[(nxt[w1], w2)], idx[(w1, nxt[w2])]
+            self.nbr[b][2 * d1 + 1], self.nbr[up1][2 * d1] = up1, b
+            self.nbr[b][2 * d2 + 1], self.nbr[up2][2 * d2] = up2, b
+        self.ghosts = [torch.zeros((5, m[2], m[1], m[0]), dtype=torch.float64, device=xv.device)
+                       for m in self.dims[1:]]
+        # (owner, low ghost, high ghost, direction), in fill order
+        self.fills = [(0, 1, 2, d1), (0, 3, 4, d2), (1, 5, 6, d2), (2, 7, 8, d2)]
+
+    def _all(self, q):
+        return [q] + self.ghosts
+
+    def fill(self, q):
+        allq = self._all(q)
+        for o, lo, hi, d in self.fills:
+            wcns5_fill_ghost_blocks(allq[o], allq[lo], allq[hi], self.S[o], self.S[lo], d, self.kinds[d], self.uinf,
+                                    self.gamma, self.stream)
+
+    def residual(self, q, entropy_fix: float = 0.1, eps: float = 1e-6, viscous=None):
+        """R of the owner (dQ/dt = -R); viscous = (prandtl, mu_inf, s_star)."""
+        self.fill(q)
+        allq = self._all(q)
+        rs = wcns5_euler_residual_blocks(allq, self.S, self.jinv, self.nbr, self.gamma, entropy_fix, eps,
+                                         stream=self.stream)
+        if viscous is not None:
+            c4_viscous_add_blocks(allq, rs, self.S, self.jinv, self.nbr, self.gamma, *viscous, stream=self.stream)
+        return rs[0]
+
+    def steps(self, q, dt: float, nsteps: int, entropy_fix: float = 0.1, eps: float = 1e-6, viscous=None,
+              work=None):
+        """nsteps RK3 steps in place on q (cfd_wcns5_steps_blocks_closed with the four fills)."""
+        torch = self.torch
+        allq = self._all(q)
+        dims = (C.c_int32 * 27)(*[v for m in self.dims for v in m])
+        nbt = (C.c_int32 * 54)(*[v for row in self.nbr for v in row])
+        nbytes = C.c_size_t()
+        _check(lib().cfd_wcns5_ns_blocks_work_bytes(9, dims, nbt, C.byref(nbytes)))
+        if work is None or work.numel() * work.element_size() < nbytes.value:
+            work = _scratch(torch, nbytes.value, q.device, self.stream)
+        cls = (WcnsClosure * 4)(*[WcnsClosure(o, lo, hi, d, (C.c_int32 * 2)(*self.kinds[d]),
+                                              (C.c_double * 3)(*self.uinf)) for o, lo, hi, d in self.fills])
+        pr, mu, ss = viscous if viscous is not None else (0.72, 0.0, 110.4 / 288.15)
+        ptrs = lambda ts: (C.c_void_p * 9)(*[_ptr(t) for t in ts])   # noqa: E731
+        _check(lib().cfd_wcns5_steps_blocks_closed(9, dims, nbt, ptrs(allq), ptrs(self.S), ptrs(self.jinv), cls, 4,
+                                                   1 if viscous is not None else 0, _ptr(work), nbytes.value,
+                                                   self.gamma, float(entropy_fix), float(eps), float(pr), float(mu),
+                                                   float(ss), float(dt), int(nsteps),
+                                                   _stream_handle(torch, self.stream)))
         return q
 
 

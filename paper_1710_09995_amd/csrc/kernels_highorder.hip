@@ -2127,29 +2127,34 @@ struct Period9 {
 };
 
 // Vertices of a block extended for its metrics and its ghost blocks'
-// (cfd_wcns5_extend_vertices): along a periodic direction vertex v of the
-// output is vertex v mod n plus floor(v / n) periods; along the bounded one
+// (cfd_wcns5_extend_vertices_mask): along a periodic direction vertex v of
+// the output is vertex v mod n plus floor(v / n) periods; along a bounded one
 // plane pl = -XL .. n + XL, copied for 0 <= pl <= n, else continued linearly
-// from the two planes at that end.
+// from the two planes at that end.  With two bounded directions the first
+// (lower) is continued first and the second from those values, so a corner
+// vertex continues the continued planes.
 __global__ void __launch_bounds__(256) k_extend_vertices(const double* __restrict__ xv, int ni, int nj, int nk,
-                                                         int bounded, Period9 P, double* __restrict__ xe, int ei,
+                                                         int mask, Period9 P, double* __restrict__ xe, int ei,
                                                          int ej, int ek) {
   const int n[3] = {ni, nj, nk};
-  const int s[3] = {ni + (bounded == 0), nj + (bounded == 1), nk + (bounded == 2)};
+  const int s[3] = {ni + ((mask >> 0) & 1), nj + ((mask >> 1) & 1), nk + ((mask >> 2) & 1)};
   const int64_t scells = (int64_t)s[0] * s[1] * s[2];
   const int64_t total = (int64_t)ei * ej * ek;
+  int bd[2] = {-1, -1}, nb = 0;
+  for (int d = 0; d < 3; ++d)
+    if ((mask >> d) & 1) bd[nb++] = d;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
     const int e[3] = {(int)(t % ei), (int)((t / ei) % ej), (int)(t / ((int64_t)ei * ej))};
-    int src[3], q[3] = {0, 0, 0}, a = 0, b = 0, m = 0;
+    int src[3], q[3] = {0, 0, 0}, a[3] = {0, 0, 0}, b[3] = {0, 0, 0}, m[3] = {0, 0, 0};
     for (int d = 0; d < 3; ++d) {
-      if (d == bounded) {
+      if ((mask >> d) & 1) {
         const int pl = e[d] - CFD_WCNS5_XLAYERS;
         if (pl < 0) {
-          a = 0, b = 1, m = -pl;
+          a[d] = 0, b[d] = 1, m[d] = -pl;
         } else if (pl > n[d]) {
-          a = n[d], b = n[d] - 1, m = pl - n[d];
+          a[d] = n[d], b[d] = n[d] - 1, m[d] = pl - n[d];
         } else {
-          a = pl, b = pl, m = 0;
+          a[d] = pl, b[d] = pl, m[d] = 0;
         }
         src[d] = 0;
       } else {
@@ -2160,20 +2165,39 @@ __global__ void __launch_bounds__(256) k_extend_vertices(const double* __restric
       }
     }
     for (int c = 0; c < 3; ++c) {
-      double x0, x1;
-      int i0[3] = {src[0], src[1], src[2]}, i1[3] = {src[0], src[1], src[2]};
-      if (bounded >= 0) {
-        i0[bounded] = a;
-        i1[bounded] = b;
-      }
-      x0 = xv[c * scells + ((int64_t)i0[2] * s[1] + i0[1]) * s[0] + i0[0]];
-      x1 = xv[c * scells + ((int64_t)i1[2] * s[1] + i1[1]) * s[0] + i1[0]];
-      for (int d = 0; d < 3; ++d)
-        if (d != bounded) {
-          x0 = x0 + (double)q[d] * P.p[3 * d + c];
-          x1 = x1 + (double)q[d] * P.p[3 * d + c];
+      // the wrapped vertex at the bounded-direction indices idx, plus its periods
+      auto at = [&](const int idx[3]) {
+        double x = xv[c * scells + ((int64_t)idx[2] * s[1] + idx[1]) * s[0] + idx[0]];
+        for (int d = 0; d < 3; ++d)
+          if (!((mask >> d) & 1)) x = x + (double)q[d] * P.p[3 * d + c];
+        return x;
+      };
+      // continued along the first bounded direction (if any) at second-direction plane p2
+      auto first = [&](int p2) {
+        int i0[3] = {src[0], src[1], src[2]}, i1[3] = {src[0], src[1], src[2]};
+        if (nb > 0) {
+          i0[bd[0]] = a[bd[0]];
+          i1[bd[0]] = b[bd[0]];
         }
-      xe[c * total + t] = m == 0 ? x0 : x0 + (double)m * (x0 - x1);
+        if (nb > 1) i0[bd[1]] = i1[bd[1]] = p2;
+        const double x0 = at(i0);
+        if (nb == 0 || m[bd[0]] == 0) return x0;
+        const double x1 = at(i1);
+        return x0 + (double)m[bd[0]] * (x0 - x1);
+      };
+      double x;
+      if (nb < 2) {
+        x = first(0);
+      } else {
+        const double y0 = first(a[bd[1]]);
+        if (m[bd[1]] == 0) {
+          x = y0;
+        } else {
+          const double y1 = first(b[bd[1]]);
+          x = y0 + (double)m[bd[1]] * (y0 - y1);
+        }
+      }
+      xe[c * total + t] = x;
     }
   }
 }
@@ -2307,12 +2331,18 @@ cfd_status ns_steps_blocks_impl(int32_t nblk, const int32_t* dims, const int32_t
     if (nsteps < 0) cfd::host_fail(CFD_EINVAL, "nsteps must be >= 0");
     if (nclosures < 0 || (nclosures > 0 && !closures)) cfd::host_fail(CFD_EINVAL, "bad closure list");
     if (nclosures > 0) {
-      std::vector<char> used(nblk, 0);
+      // a block is the ghost block of at most one closure; an owner may be the
+      // ghost block of an earlier closure (corner blocks filled from a face's
+      // ghost block), never of a later one (it would be read before written)
+      std::vector<char> ghost(nblk, 0), owner(nblk, 0);
       for (int c = 0; c < nclosures; ++c) {
-        check_closure(nblk, dims, nbr, closures[c]);
-        for (int32_t b : {closures[c].owner, closures[c].ghost_lo, closures[c].ghost_hi}) {
-          if (used[b]) cfd::host_fail(CFD_EINVAL, "closure: a block belongs to two closures");
-          used[b] = 1;
+        const cfd_wcns5_closure& cl = closures[c];
+        check_closure(nblk, dims, nbr, cl);
+        owner[cl.owner] = 1;
+        for (int32_t b : {cl.ghost_lo, cl.ghost_hi}) {
+          if (ghost[b]) cfd::host_fail(CFD_EINVAL, "closure: a block is the ghost block of two closures");
+          if (owner[b]) cfd::host_fail(CFD_EINVAL, "closure: a ghost block is the owner of an earlier closure");
+          ghost[b] = 1;
         }
       }
     }
@@ -2390,18 +2420,20 @@ extern "C" cfd_status cfd_wcns5_steps_blocks_closed(int32_t nblk, const int32_t*
                               work_bytes, gamma, entropy_fix, eps, prandtl, mu_inf, s_star, dt, nsteps, stream);
 }
 
-extern "C" cfd_status cfd_wcns5_extend_vertices(const double* xv_dev, const int32_t n[3], int32_t bounded,
-                                                const double period[9], double* xe_dev, hipStream_t stream) {
+extern "C" cfd_status cfd_wcns5_extend_vertices_mask(const double* xv_dev, const int32_t n[3], int32_t bounded_mask,
+                                                     const double period[9], double* xe_dev, hipStream_t stream) {
   return cfd::host_guarded([&] {
     if (!xv_dev || !n || !period || !xe_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
-    if (bounded < -1 || bounded > 2) cfd::host_fail(CFD_EINVAL, "bounded must be -1, 0, 1 or 2");
+    if (bounded_mask < 0 || bounded_mask > 7 || bounded_mask == 7)
+      cfd::host_fail(CFD_EINVAL, "bounded_mask must name at most two directions");
     if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
     for (int x = 0; x < 9; ++x)
       if (!std::isfinite(period[x])) cfd::host_fail(CFD_EINVAL, "period must be finite");
     int64_t e[3], sv = 1, ev = 1;
     for (int d = 0; d < 3; ++d) {
-      e[d] = d == bounded ? n[d] + 1 + 2 * CFD_WCNS5_XLAYERS : n[d] + 5;
-      sv *= n[d] + (d == bounded);
+      const bool b = (bounded_mask >> d) & 1;
+      e[d] = b ? n[d] + 1 + 2 * CFD_WCNS5_XLAYERS : n[d] + 5;
+      sv *= n[d] + (b ? 1 : 0);
       ev *= e[d];
     }
     if (ev > ((int64_t)1 << 34)) cfd::host_fail(CFD_EINVAL, "block too large");
@@ -2409,10 +2441,17 @@ extern "C" cfd_status cfd_wcns5_extend_vertices(const double* xv_dev, const int3
     cfd::Period9 P;
     for (int x = 0; x < 9; ++x) P.p[x] = period[x];
     hipLaunchKernelGGL(cfd::k_extend_vertices, dim3(cfd::grid_for(ev)), dim3(256), 0, stream, xv_dev, n[0], n[1], n[2],
-                       bounded, P, xe_dev, (int)e[0], (int)e[1], (int)e[2]);
+                       (int)bounded_mask, P, xe_dev, (int)e[0], (int)e[1], (int)e[2]);
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(err));
   });
+}
+
+extern "C" cfd_status cfd_wcns5_extend_vertices(const double* xv_dev, const int32_t n[3], int32_t bounded,
+                                                const double period[9], double* xe_dev, hipStream_t stream) {
+  if (bounded < -1 || bounded > 2)
+    return cfd::host_guarded([] { cfd::host_fail(CFD_EINVAL, "bounded must be -1, 0, 1 or 2"); });
+  return cfd_wcns5_extend_vertices_mask(xv_dev, n, bounded < 0 ? 0 : 1 << bounded, period, xe_dev, stream);
 }
 
 extern "C" cfd_status cfd_wcns5_fill_ghost_blocks(const double* q_dev, double* q_lo_dev, double* q_hi_dev,

@@ -188,3 +188,92 @@ def test_tiled_owners_on_the_one_gpu_share_geometry():
     for (lo, ext), x in zip(tl.owners, qs):
         sl = (slice(None), slice(lo[2], lo[2] + ext[2]), slice(lo[1], lo[1] + ext[1]), slice(lo[0], lo[0] + ext[0]))
         assert torch.equal(x, qd[sl]), (lo, ext)
+
+
+def _channel(n):
+    c = cases.channel_case(*n, mach=0.6, hb=0.06)
+    return np.ascontiguousarray(c.nodes[0][:, 1:, :, :]), [(0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0)]
+
+
+C4_KINDS = {0: (FARFIELD, FARFIELD), 1: (SLIPWALL, SLIPWALL)}
+UINF_C4 = (0.6 * math.sqrt(GAMMA), 0.0, 0.0)
+
+
+def _duct_pair(n, kinds=C4_KINDS):
+    from paper_1710_09995_amd.binding import WcnsClosedDuct
+    Xv, P = _channel(n)
+    o = ocl.ClosedDuct(Xv, P, (0, 1), kinds, GAMMA, freestream=(0.6, 0.0, 0.0))
+    g = WcnsClosedDuct(_dev(Xv), P, (0, 1), kinds, UINF_C4, GAMMA)
+    return Xv, P, o, g
+
+
+def test_duct_geometry_and_ghost_states_match_the_oracle():
+    """The warm-start channel geometry (far field across x, slip walls across
+    y, periodic z), closed by four face and four corner ghost blocks: the
+    vertices continued in two directions, every block's metrics and every
+    ghost state (corners included) against the oracle."""
+    from paper_1710_09995_amd.binding import wcns5_extend_vertices
+    import ctypes as C
+    from paper_1710_09995_amd import binding as B
+    n = (24, 12, 8)
+    say("duct geometry", n)
+    Xv, P, o, g = _duct_pair(n)
+    assert len(g.S) == 9
+    for b in range(9):
+        assert _rel(g.S[b].cpu().numpy(), o.S[b]) <= 1e-13, b
+        assert _rel(g.jinv[b].cpu().numpy(), o.Jinv[b]) <= 1e-13, b
+    q = _smooth_state(n, seed=12)
+    want = o.blocks(q)
+    qd = _dev(q)
+    g.fill(qd)
+    for b in range(1, 9):
+        assert _rel(g.ghosts[b - 1].cpu().numpy(), want[b]) <= 1e-14, b
+
+
+@pytest.mark.parametrize("viscous", [False, True])
+def test_duct_residual_matches_the_oracle(viscous):
+    n = (24, 16, 8)
+    say("duct residual", n, "viscous", viscous)
+    _, _, o, g = _duct_pair(n, {0: (FARFIELD, FARFIELD), 1: (NOSLIP_ADIABATIC, SLIPWALL)})
+    q = _smooth_state(n, seed=13)
+    want = o.residual(q, viscous=VISC if viscous else None)
+    got = g.residual(_dev(q), viscous=VISC if viscous else None).cpu().numpy()
+    err = _rel(got, want)
+    say(f"  max error / max|R| {err:.2e}")
+    assert err <= 1e-12 and float(np.linalg.norm(got - want) / np.linalg.norm(want)) <= 1e-12
+
+
+def test_duct_steps_match_the_oracle():
+    n = (24, 12, 8)
+    _, _, o, g = _duct_pair(n)
+    q = _smooth_state(n, seed=14)
+    visc = (0.72, 0.002, 0.38)
+    want = o.ns_steps(q, 5e-4, 2, viscous=visc)
+    got = g.steps(_dev(q), 5e-4, 2, viscous=visc).cpu().numpy()
+    dq = float(np.max(np.abs(got - want)) / np.max(np.abs(want - q)))
+    say(f"  duct NS steps: max error / max|Q| {_rel(got, want):.2e}, / max|Q - Q0| {dq:.2e}")
+    assert _rel(got, want) <= 1e-12 and dq <= 1e-10
+
+
+def test_full_size_channel_duct_keeps_a_uniform_stream():
+    """The warm-start fine grid (192 x 96 x 96 channel with its bump), closed
+    across x and y with the far field on all four faces: a uniform stream's
+    residual stays at 1e-13 of its face terms; with the warm-start conditions
+    (far field across x, slip walls across y) RK3 steps from it stay finite."""
+    import torch
+    from paper_1710_09995_amd.binding import WcnsClosedDuct
+    n = (192, 96, 96)
+    say("full-size channel duct", n)
+    Xv, P = _channel(n)
+    xv = _dev(Xv)
+    g = WcnsClosedDuct(xv, P, (0, 1), {0: (FARFIELD, FARFIELD), 1: (FARFIELD, FARFIELD)}, UINF_C4, GAMMA)
+    q = _dev(cases.uniform_state(n, cases.Params(mach=0.6)))
+    S, jinv = g.S[0], g.jinv[0]
+    area = sum(torch.sqrt((S[d] ** 2).sum(0)) for d in range(3))
+    scale = float((area / jinv).max()) * (1.0 + UINF_C4[0] ** 2)
+    top = float(g.residual(q).abs().max())
+    say(f"  max |R| {top:.2e} = {top / scale:.1e} of the face-term scale {scale:.0f}")
+    assert top <= 1e-13 * scale
+    w = WcnsClosedDuct(xv, P, (0, 1), C4_KINDS, UINF_C4, GAMMA)
+    w.steps(q, 1e-4, 2)
+    assert bool(torch.isfinite(q).all())
