@@ -535,6 +535,63 @@ def bench_ns_blocks(a) -> int:
     return 0
 
 
+def bench_ns_share(a) -> int:
+    """RK3 Navier-Stokes steps of the paper's operator (WCNS-E-5 and the
+    fourth-order viscous terms) on the one-GPU share's geometry closed by
+    ghost blocks (no-slip wall below, far field above the wall-normal
+    direction): 2 x 2 of its 512 x 512 x 144 blocks tiling x and z (151 M
+    cells; the operator's working arrays take some 430 B per cell, so the 16
+    blocks of the share do not fit with them), a uniform stream at M 0.8,
+    Re 1e6 per unit length.  K steps after W warm-up ones at a fixed step,
+    hipEvents on the launch stream."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1710_09995_amd import cases
+    from paper_1710_09995_amd.binding import WcnsClosedTiling
+    nb, ni, nj, nk = 2, 512, 512, 144
+    t0 = time.perf_counter()
+    Xv, P = cases.paper_share_vertices(nb, nb, ni, nj, nk)
+    xv = torch.from_numpy(Xv).cuda()
+    del Xv
+    N = (nb * ni, nb * nj, nk)
+    cuts = {0: [b * ni for b in range(nb + 1)], 1: [b * nj for b in range(nb + 1)]}
+    uinf = (0.8 * math.sqrt(1.4), 0.0, 0.0)
+    tl = WcnsClosedTiling(xv, P, 2, (3, 1), uinf, 1.4, cuts=cuts)      # no-slip wall below, far field above
+    del xv
+    q0 = torch.from_numpy(cases.uniform_state((ni, nj, nk), cases.Params(mach=0.8))).cuda()
+    qs = [q0.clone() for _ in tl.owners]
+    del q0
+    setup_s = time.perf_counter() - t0
+    visc = (0.72, uinf[0] / 1e6, 110.4 / 288.15)
+    dt = 1e-5
+    work = None
+    stream = torch.cuda.current_stream()
+    for _ in range(a.warmup):
+        tl.steps(qs, dt, 1, viscous=visc, work=work)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(a.steps):
+        tl.steps(qs, dt, 1, viscous=visc, work=work)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    cells = N[0] * N[1] * N[2]
+    finite = bool(all(torch.isfinite(t).all() for t in qs))
+    print(json.dumps({
+        "metric": "Mcell-stage/s of RK3 Navier-Stokes steps of the paper's operator (WCNS-E-5 + fourth-order "
+                  "viscous) on the one-GPU share's geometry closed at the wall and far field",
+        "value": round(cells * 3 / (ms / 1e3) / 1e6, 1), "unit": "Mcell-stage/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (uniform stream at M 0.8)",
+        "config": {"workload": f"ns_wcns5_c4_share_{nb}x{nb}_of_{ni}x{nj}x{nk}", "cells": cells,
+                   "blocks": len(tl.owners), "ghost_blocks": 2 * len(tl.owners), "setup_s": round(setup_s, 1),
+                   "finite": finite},
+        "roofline": None, "cpu_baseline": None}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -563,7 +620,7 @@ def main(argv=None):
     ap.add_argument("--groups", type=int, default=8,
                     help="with --split: groups (devices) the pieces are regrouped into for the balance report")
     ap.add_argument("--op", default=None, choices=["diff6", "wcns5", "wcns5_euler", "ns_periodic", "wcns5_curv", "ns_curv", "implicit_curv",
-                             "ns_blocks"],
+                             "ns_blocks", "ns_share"],
                     help="time one operator instead of the solver, on a 256x128x128 block, 5 variables, each "
                          "direction: diff6 = the sixth-order staggered flux difference (Section 2.2, Eq. 2); "
                          "wcns5 = the WCNS-E-5 weighted cell-edge interpolation; wcns5_euler = the periodic "
@@ -573,7 +630,8 @@ def main(argv=None):
                          "residual plus the curvilinear fourth-order viscous terms; implicit_curv = implicit "
                          "steps (backward Euler, Jacobi sweeps) on the curvilinear residual; ns_blocks = RK3 "
                          "Navier-Stokes steps on that grid cut into 2 x 2 x 2 blocks joined face to face, with the "
-                         "unsplit block timed beside it")
+                         "unsplit block timed beside it; ns_share = RK3 Navier-Stokes steps on 2 x 2 of the one-GPU "
+                         "share's 512x512x144 blocks closed at the wall and far field")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (HBM counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -593,6 +651,8 @@ def main(argv=None):
         return bench_implicit(a)
     if a.op == "ns_blocks" and a.gpus == 1:
         return bench_ns_blocks(a)
+    if a.op == "ns_share" and a.gpus == 1:
+        return bench_ns_share(a)
     if a.op is not None and a.gpus == 1:
         return bench_op(a)
     if a.gpus != 1:
