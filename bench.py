@@ -592,6 +592,40 @@ def bench_ns_share(a) -> int:
     return 0
 
 
+def bench_mg_channel(a) -> int:
+    """Multigrid V-cycles of the steady march (three levels, one RK3 step on
+    each finer level, two on the coarsest) on the 192 x 96 x 96 channel with
+    a bump at M 0.6 (the warm-start family's grid): K cycles after W warm-up
+    ones, one cfd_mg_cycles call, hipEvents on the launch stream, no history
+    kept.  The state drifts toward the steady flow while it is timed; the
+    cycle's work does not depend on it."""
+    import torch
+    from paper_1710_09995_amd import cases
+    from paper_1710_09995_amd.binding import Multigrid, Solver
+    case = cases.channel_case(192, 96, 96, mach=0.6, hb=0.05)
+    s = Solver(case)
+    mg = Multigrid(s, 3, 1, 2)
+    mg.cycles(a.warmup, hist=False)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    mg.cycles(a.steps, hist=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    cells = 192 * 96 * 96
+    print(json.dumps({
+        "metric": "fine-grid Mcell-cycle/s of three-level multigrid V-cycles (RK3 smoother) on the channel",
+        "value": round(cells / (ms / 1e3) / 1e6, 1), "unit": "Mcell-cycle/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (channel with a bump, M 0.6)",
+        "config": {"workload": "mg_channel_192x96x96_3levels_pre1_coarse2", "cells": cells,
+                   "finite": bool(all(torch.isfinite(v).all() for v in s.interior_views()))},
+        "roofline": None, "cpu_baseline": None}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -620,7 +654,7 @@ def main(argv=None):
     ap.add_argument("--groups", type=int, default=8,
                     help="with --split: groups (devices) the pieces are regrouped into for the balance report")
     ap.add_argument("--op", default=None, choices=["diff6", "wcns5", "wcns5_euler", "ns_periodic", "wcns5_curv", "ns_curv", "implicit_curv",
-                             "ns_blocks", "ns_share"],
+                             "ns_blocks", "ns_share", "mg_channel"],
                     help="time one operator instead of the solver, on a 256x128x128 block, 5 variables, each "
                          "direction: diff6 = the sixth-order staggered flux difference (Section 2.2, Eq. 2); "
                          "wcns5 = the WCNS-E-5 weighted cell-edge interpolation; wcns5_euler = the periodic "
@@ -631,7 +665,8 @@ def main(argv=None):
                          "steps (backward Euler, Jacobi sweeps) on the curvilinear residual; ns_blocks = RK3 "
                          "Navier-Stokes steps on that grid cut into 2 x 2 x 2 blocks joined face to face, with the "
                          "unsplit block timed beside it; ns_share = RK3 Navier-Stokes steps on 2 x 2 of the one-GPU "
-                         "share's 512x512x144 blocks closed at the wall and far field")
+                         "share's 512x512x144 blocks closed at the wall and far field; mg_channel = three-level "
+                         "multigrid V-cycles on the 192x96x96 channel (a cycle is a step)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (HBM counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -653,6 +688,8 @@ def main(argv=None):
         return bench_ns_blocks(a)
     if a.op == "ns_share" and a.gpus == 1:
         return bench_ns_share(a)
+    if a.op == "mg_channel" and a.gpus == 1:
+        return bench_mg_channel(a)
     if a.op is not None and a.gpus == 1:
         return bench_op(a)
     if a.gpus != 1:

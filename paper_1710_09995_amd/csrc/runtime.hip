@@ -646,7 +646,8 @@ bool fused_dt(const cfd_ctx* c) { return c->tun.kernel == 2 && c->params.viscous
 //    rows [0, nwg_dt) of part_dt: min dt, sum V Q^n).
 //  - History: the plane-ring kernel's stage 1 reduces the norm partials of
 //    R(Q^n) itself; the other kernels write R(Q^n) to qb (free until stage 2
-//    overwrites it) and the norms kernel adds the R rows after k_dt's.
+//    overwrites it) and the norms kernel adds the R rows after k_dt's (only
+//    when the step keeps a history: without one they skip both).
 //  - Totals sum V Q^n: always from rows [0, nwg_dt) of a row-chunk kernel
 //    (k_dt, or with the plane-ring kernel k_norms over Q^n, only when the
 //    step keeps a history), whose cut of the grid does not depend on the
@@ -682,7 +683,7 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history, const doub
     A.partials = c->part_nrm() + (int64_t)ntot * NPART;
     launch_stage(c, A, 1, s);
     launch_finalize(c->part_nrm(), ntot + stage_nwg(c, 1), 1, inv_n, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
-  } else {
+  } else if (history) {
     A.rout = c->qb();
     launch_stage(c, A, 1, s);
     timed(c, 3, s, [&] {
@@ -690,6 +691,8 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history, const doub
                    c->nchunks, nwg_dt, s);
     });
     launch_finalize(c->part_dt(), 2 * nwg_dt, 1, inv_n, c->d_dt(), c->d_hist(), c->d_nonfinite(), s);
+  } else {
+    launch_stage(c, A, 1, s);
   }
   forced(c->qa(), 1.0);
   A.rout = nullptr;

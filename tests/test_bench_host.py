@@ -31,7 +31,7 @@ def test_traffic_needs_matching_sources(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "source_sha", lambda: "abc123")
+    monkeypatch.setattr(bench, "source_sha", lambda sources=None: "abc123")
     assert bench.read_traffic("stage_x") is None                       # no summary
     (prof / "stage_x_pmc.txt").write_text("# comment: ignored\nsource_sha: abc123\nhbm_bytes_per_launch: 12345\n")
     assert bench.read_traffic("stage_x") == 12345.0
