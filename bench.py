@@ -310,7 +310,11 @@ def bench_wcns5_euler(a) -> int:
     nb = C.c_size_t()
     B._check(B.lib().cfd_wcns5_euler_work_bytes((C.c_int32 * 3)(ni, nj, nk), C.byref(nb)))
     work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
-    vwork = torch.empty(8 * (29 if curv else 20) * cells, dtype=torch.uint8, device="cuda") if viscous else None
+    vwork = None
+    if viscous:
+        B._check((B.lib().cfd_c4_viscous_curv_work_bytes if curv else B.lib().cfd_c4_viscous_work_bytes)(
+            (C.c_int32 * 3)(ni, nj, nk), C.byref(nb)))
+        vwork = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
     setup_ms = None
     if curv:   # a wavy periodic grid on the box 1 x 1/2 x 1/2: each coordinate displaced by sines of the others
         L, amp = (1.0, 0.5, 0.5), 0.05
@@ -359,8 +363,10 @@ def bench_wcns5_euler(a) -> int:
             nbytes += 8 * 3 * F                # the faces' area vectors
     if curv:                                   # J^{-1} read by the last Eq. 2 pass
         nbytes += 8 * cells
-    if viscous and curv:   # as below, plus the cell metrics (9 in, 9 out), per face S_d, S_t across, J^{-1}
-        nbytes += 8 * cells * ((5 + 4) + (4 + 12) + (9 + 9) + 3 * ((4 + 8 + 3 + 6 + 1) + 4) + 3 * (4 + 1 + 8))
+    if viscous and curv:   # phi (Q in, 4 out), gradients (4 in, 12 out), the cell metrics (9 in, 9 out) and per
+        # direction the face metrics (9 + 1 in, 7 out) that this one-shot call forms each time, then per direction
+        # the fused faces and differences (phi 4 + gradients 8 + face metrics 7 + S_d 3 + J^{-1} 1 in, r 4 in and out)
+        nbytes += 8 * cells * ((5 + 4) + (4 + 12) + (9 + 9) + 3 * (10 + 7) + 3 * (4 + 8 + 7 + 3 + 1 + 4 + 4))
     elif viscous:   # phi (Q in, 4 out), gradients (4 in, 12 out), per direction faces (16 in, 4 out) and the sum
         nbytes += 8 * cells * ((5 + 4) + (4 + 12) + 3 * ((4 + 8) + 4) + 3 * (4 + 8))
     achieved = nbytes / (ms / 1e3) / 1e9
@@ -381,8 +387,8 @@ def bench_wcns5_euler(a) -> int:
                      "traffic_rate_gbs": None if traffic is None else round(traffic / (ms / 1e3) / 1e9, 1),
                      "kernel": "pipeline: k_pad_prim_periodic, k_wcns5_roe_faces, k_window6_*<Eq2OpT>"
                                + (" (the last pass dividing by J^-1)" if curv else "")
-                               + (", k_c4_phi, k_c4_grads, k_c4_cell_metrics, k_c4_visc_faces_curv, k_c4_flux_sub"
-                                  if viscous and curv else
+                               + (", k_c4_phi, k_c4_grads, k_c4_cell_metrics, k_c4_face_metrics, k_c4_visc_rows, "
+                                  "k_c4_visc_march<1>, k_c4_visc_march<2>" if viscous and curv else
                                   ", k_c4_phi, k_c4_grads, k_c4_visc_faces, k_c4_flux_sub" if viscous else ""),
                      "mean_ms": round(ms, 4), "pipeline_bytes": nbytes},
         "cpu_baseline": None}), flush=True)
@@ -463,8 +469,9 @@ def bench_implicit(a) -> int:
 def bench_ns_blocks(a) -> int:
     """RK3 Navier-Stokes steps on the wavy periodic 256x128x128 grid of --op
     wcns5_curv cut into 2 x 2 x 2 blocks joined face to face, against the same
-    steps on the unsplit periodic block in the same run: K steps after W
-    warm-up ones each, hipEvents on the launch stream."""
+    steps on the unsplit periodic block in the same run: one call of K steps
+    after one call of W warm-up steps each (a call forms the viscous face
+    metrics once), hipEvents on the launch stream."""
     import numpy as np
     import torch
     from paper_1710_09995_amd.binding import (wcns5_metrics_periodic, wcns5_ns_steps_blocks,
@@ -508,18 +515,17 @@ def bench_ns_blocks(a) -> int:
     stream = torch.cuda.current_stream()
 
     def timed(fn):
-        for _ in range(a.warmup):
-            fn()
+        if a.warmup > 0:
+            fn(a.warmup)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for _ in range(a.steps):
-            fn()
+        fn(a.steps)
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / a.steps
-    ms_blocks = timed(lambda: wcns5_ns_steps_blocks(qs, Ss, Js, nbr, dt, 1, 1.4, 0.1, 1e-6, 0.72, mu))
-    ms_whole = timed(lambda: wcns5_ns_steps_curv_periodic(qw, S, jinv, dt, 1, 1.4, 0.1, 1e-6, 0.72, mu))
+    ms_blocks = timed(lambda k: wcns5_ns_steps_blocks(qs, Ss, Js, nbr, dt, k, 1.4, 0.1, 1e-6, 0.72, mu))
+    ms_whole = timed(lambda k: wcns5_ns_steps_curv_periodic(qw, S, jinv, dt, k, 1.4, 0.1, 1e-6, 0.72, mu))
     finite = bool(all(torch.isfinite(t).all() for t in qs))
     print(json.dumps({
         "metric": "Mcell-stage/s of RK3 Navier-Stokes steps (WCNS-E-5 + fourth-order viscous) on 8 curvilinear "
@@ -542,7 +548,8 @@ def bench_ns_share(a) -> int:
     direction): 2 x 2 of its 512 x 512 x 144 blocks tiling x and z (151 M
     cells; the operator's working arrays take some 430 B per cell, so the 16
     blocks of the share do not fit with them), a uniform stream at M 0.8,
-    Re 1e6 per unit length.  K steps after W warm-up ones at a fixed step,
+    Re 1e6 per unit length.  One call of K steps after one call of W warm-up
+    steps at a fixed step (a call forms the viscous face metrics once),
     hipEvents on the launch stream."""
     import math
     import numpy as np
@@ -567,13 +574,12 @@ def bench_ns_share(a) -> int:
     dt = 1e-5
     work = None
     stream = torch.cuda.current_stream()
-    for _ in range(a.warmup):
-        tl.steps(qs, dt, 1, viscous=visc, work=work)
+    if a.warmup > 0:
+        tl.steps(qs, dt, a.warmup, viscous=visc, work=work)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(a.steps):
-        tl.steps(qs, dt, 1, viscous=visc, work=work)
+    tl.steps(qs, dt, a.steps, viscous=visc, work=work)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / a.steps

@@ -484,9 +484,11 @@ cfd_status cfd_wcns5_euler_steps_periodic(double* q_dev, void* work_dev, size_t 
  * through S_d; r -= J times the staggered difference, summed over d.  On a
  * uniform Cartesian grid this equals cfd_c4_viscous_add_periodic.
  * q_dev, r_dev: [5][nk][nj][ni]; s_dev, jinv_dev from the metrics call;
- * work_dev: cfd_c4_viscous_curv_work_bytes() bytes.  r and the workspace must
- * not overlap each other, q or the metrics.  Errors as for the Cartesian terms.
- * Asynchronous on stream. */
+ * work_dev: cfd_c4_viscous_curv_work_bytes() bytes (37 doubles per cell: u,
+ * v, w, T and their index derivatives, then the face metrics of the three
+ * directions, formed from s and J^{-1} on each call).  r and the workspace
+ * must not overlap each other, q or the metrics.  Errors as for the Cartesian
+ * terms.  Asynchronous on stream. */
 cfd_status cfd_c4_viscous_curv_work_bytes(const int32_t n[3], size_t* bytes);
 cfd_status cfd_c4_viscous_add_curv_periodic(const double* q_dev, const double* s_dev, const double* jinv_dev,
                                             double* r_dev, void* work_dev, size_t work_bytes, const int32_t n[3],
@@ -530,8 +532,9 @@ cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_t* dims, co
  * equations on a periodic curvilinear block, in place on q_dev: each stage's
  * residual is cfd_wcns5_euler_residual_curv_periodic plus the viscous terms
  * of cfd_c4_viscous_add_curv_periodic.  work_dev: cfd_wcns5_ns_step_work_bytes()
- * bytes (the larger of the two scratch areas, which the stage reuses, then the
- * step's start state and R).  Arguments and errors as for those calls and
+ * bytes (the larger of the two scratch areas, which the stage reuses, the
+ * viscous face metrics, formed once per call, then the step's start state and
+ * R).  Arguments and errors as for those calls and
  * cfd_wcns5_euler_steps_curv_periodic.  Asynchronous on stream. */
 cfd_status cfd_wcns5_ns_step_work_bytes(const int32_t n[3], size_t* bytes);
 cfd_status cfd_wcns5_ns_steps_curv_periodic(double* q_dev, const double* s_dev, const double* jinv_dev,
@@ -587,7 +590,8 @@ cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_t* dims, co
  * blocks at that stage (table, extents and pointer arrays as for those
  * calls).  work_dev: cfd_wcns5_ns_blocks_work_bytes() bytes (the larger of the
  * residual's and the viscous terms' scratch, then each block's start state
- * and R).  Errors as for those calls and cfd_wcns5_ns_steps_curv_periodic; no
+ * and R, then the viscous face metrics, formed once per call).  Errors as for
+ * those calls and cfd_wcns5_ns_steps_curv_periodic; no
  * state may overlap another, the metrics or the workspace.  Asynchronous on
  * stream. */
 cfd_status cfd_wcns5_ns_blocks_work_bytes(int32_t nblk, const int32_t* dims, const int32_t* nbr, size_t* bytes);
@@ -686,10 +690,10 @@ cfd_status cfd_wcns5_steps_blocks_closed(int32_t nblk, const int32_t* dims, cons
  * joined face to face (the table, extents and pointer arrays as for
  * cfd_wcns5_euler_residual_blocks): every four-point stencil runs across the
  * seams, reading the neighbours' u, v, w, T, cell derivatives, cell metrics,
- * J^{-1} and face fluxes; adds -div F_v to each r_dev[b].  work_dev:
- * cfd_c4_viscous_blocks_work_bytes() bytes (29 doubles per cell of every
- * block).  Gas parameters and errors as for the periodic call.  Asynchronous
- * on stream. */
+ * J^{-1} and face metrics; adds -div F_v to each r_dev[b].  work_dev:
+ * cfd_c4_viscous_blocks_work_bytes() bytes (37 doubles per cell of every
+ * block, as for the periodic call).  Gas parameters and errors as for the
+ * periodic call.  Asynchronous on stream. */
 cfd_status cfd_c4_viscous_blocks_work_bytes(int32_t nblk, const int32_t* dims, const int32_t* nbr, size_t* bytes);
 cfd_status cfd_c4_viscous_add_blocks(int32_t nblk, const int32_t* dims, const int32_t* nbr, const double* const* q_dev,
                                      const double* const* s_dev, const double* const* jinv_dev, double* const* r_dev,

@@ -808,8 +808,19 @@ namespace cfd {
 // nsteps RK3 steps in place on q with the residual core (Cartesian when s is
 // NULL).  The workspace: the residual's, then the step's start state and R.
 Gas<double> viscous_gas(double gamma, double prandtl, double mu_inf, double s_star);
+// Viscous scratch of a periodic block: phi (4) and index gradients (12) per
+// cell, shared with the residual's scratch; the face metrics (21 per cell)
+// are computed once per call and kept apart from it.
+constexpr int VW_FIELDS = 16, FM_FIELDS = 21;
+void c4_face_metrics_curv(const double* s_dev, const double* jinv_dev, double* sc_tmp, double* fm, const int32_t n[3],
+                          hipStream_t stream);
 void c4_viscous_curv_core(const double* q_dev, const double* s_dev, const double* jinv_dev, double* r_dev,
-                          double* work, const int32_t n[3], const Gas<double>& gas, hipStream_t stream);
+                          double* work, const double* fm, const int32_t n[3], const Gas<double>& gas,
+                          hipStream_t stream);
+// Bytes of a periodic block's residual-or-viscous scratch followed by its
+// face metrics (the metrics start at visc_fm_offset).
+size_t visc_fm_offset(size_t rw0, int64_t cells) { return std::max(rw0, (size_t)8 * VW_FIELDS * cells); }
+size_t visc_region(size_t rw0, int64_t cells) { return visc_fm_offset(rw0, cells) + (size_t)8 * FM_FIELDS * cells; }
 
 // With visc (curvilinear blocks only) each stage adds the fourth-order
 // viscous terms to the residual; their scratch shares the residual's, which
@@ -822,7 +833,7 @@ void wcns5_steps_core(double* q_dev, const double* s_dev, const double* jinv_dev
   if (nsteps < 0) host_fail(CFD_EINVAL, "nsteps must be >= 0");
   const int64_t cells = (int64_t)n[0] * n[1] * n[2];
   const size_t rw0 = wcns5_residual_work(n);
-  const size_t rw = visc ? std::max(rw0, (size_t)8 * 29 * cells) : rw0;
+  const size_t rw = visc ? visc_region(rw0, cells) : rw0;
   if (work_bytes < rw + (size_t)2 * 40 * cells)
     host_fail(CFD_ENOMEM, visc ? "workspace smaller than cfd_wcns5_ns_step_work_bytes()"
                                : "workspace smaller than cfd_wcns5_euler_step_work_bytes()");
@@ -834,10 +845,12 @@ void wcns5_steps_core(double* q_dev, const double* s_dev, const double* jinv_dev
   const int64_t nv = 5 * cells;
   const int g = grid_for(nv);
   const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
+  double* fm = visc ? reinterpret_cast<double*>(static_cast<char*>(work_dev) + visc_fm_offset(rw0, cells)) : nullptr;
+  if (visc && nsteps > 0) c4_face_metrics_curv(s_dev, jinv_dev, static_cast<double*>(work_dev), fm, n, stream);
   for (int it = 0; it < nsteps; ++it)
     for (int st = 0; st < 3; ++st) {
       wcns5_residual_core(q_dev, s_dev, jinv_dev, r, work_dev, rw0, n, h, gamma, entropy_fix, eps, stream);
-      if (visc) c4_viscous_curv_core(q_dev, s_dev, jinv_dev, r, static_cast<double*>(work_dev), n, *visc, stream);
+      if (visc) c4_viscous_curv_core(q_dev, s_dev, jinv_dev, r, static_cast<double*>(work_dev), fm, n, *visc, stream);
       hipLaunchKernelGGL(k_rk3_stage, dim3(g), dim3(256), 0, stream, q_dev, qn, r, nv, dt, a[st], b[st],
                          st == 0 ? 1 : 0);
     }
@@ -995,51 +1008,6 @@ __global__ void __launch_bounds__(256) k_c4_cell_metrics(const double* __restric
   }
 }
 
-// Curvilinear viscous flux through face i + 1/2 along d (stored at the index
-// of cell i): face values of u, v, w, T; index derivatives (compact along d,
-// face values of the cell derivatives across); the physical gradient by the
-// chain rule J sum_t S_t d/dxi_t with S_t (t != d) and J^{-1} interpolated to
-// the face; the stress and heat flux contracted with the face's S_d.
-__global__ void __launch_bounds__(256) k_c4_visc_faces_curv(const double* __restrict__ phi,
-                                                            const double* __restrict__ g,
-                                                            const double* __restrict__ s,
-                                                            const double* __restrict__ sc,
-                                                            const double* __restrict__ jinv, double* __restrict__ fv,
-                                                            Cells3 C, int d, Gas<double> gas) {
-  const int64_t cells = (int64_t)C.n[0] * C.n[1] * C.n[2];
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(c % C.n[0]), j = (int)((c / C.n[0]) % C.n[1]), k = (int)(c / ((int64_t)C.n[0] * C.n[1]));
-    const int64_t m1 = C.step(i, j, k, d, -1), p1 = C.step(i, j, k, d, 1), p2 = C.step(i, j, k, d, 2);
-    auto fval = [&](const double* f) { return (-f[m1] + 9.0 * f[c] + 9.0 * f[p1] - f[p2]) / 16.0; };
-    double Sf[3][3], Sd[3];
-    for (int t = 0; t < 3; ++t)
-      for (int x = 0; x < 3; ++x) Sf[t][x] = t == d ? s[(d * 3 + x) * cells + c] : fval(sc + (t * 3 + x) * cells);
-    for (int x = 0; x < 3; ++x) Sd[x] = Sf[d][x];
-    const double Jf = 1.0 / fval(jinv);
-    double pf[4], grad[4][3];
-    for (int a = 0; a < 4; ++a) {
-      const double* f = phi + a * cells;
-      pf[a] = fval(f);
-      double dxi[3];
-      for (int t = 0; t < 3; ++t)
-        dxi[t] = t == d ? (f[m1] - 27.0 * f[c] + 27.0 * f[p1] - f[p2]) * (1.0 / 24.0) : fval(g + (a * 3 + t) * cells);
-      for (int x = 0; x < 3; ++x) grad[a][x] = Jf * (Sf[0][x] * dxi[0] + Sf[1][x] * dxi[1] + Sf[2][x] * dxi[2]);
-    }
-    const double T = pf[3];
-    const double mu = gas.mu_inf * T * sqrt(T) * (1.0 + gas.s_star) / (T + gas.s_star);
-    const double kc = mu * gas.kfac;
-    const double div = grad[0][0] + grad[1][1] + grad[2][2];
-    double tau[3][3];
-    for (int x = 0; x < 3; ++x)
-      for (int y = 0; y < 3; ++y) tau[x][y] = mu * (grad[x][y] + grad[y][x]);
-    for (int x = 0; x < 3; ++x) tau[x][x] = tau[x][x] - (2.0 / 3.0) * mu * div;
-    double e[3];
-    for (int x = 0; x < 3; ++x) e[x] = pf[0] * tau[x][0] + pf[1] * tau[x][1] + pf[2] * tau[x][2] + kc * grad[3][x];
-    for (int m = 0; m < 3; ++m) fv[m * cells + c] = Sd[0] * tau[0][m] + Sd[1] * tau[1][m] + Sd[2] * tau[2][m];
-    fv[3 * cells + c] = Sd[0] * e[0] + Sd[1] * e[1] + Sd[2] * e[2];
-  }
-}
-
 }  // namespace cfd
 
 extern "C" cfd_status cfd_c4_viscous_work_bytes(const int32_t n[3], size_t* bytes) {
@@ -1108,33 +1076,13 @@ Gas<double> viscous_gas(double gamma, double prandtl, double mu_inf, double s_st
   return gas;
 }
 
-// The curvilinear viscous terms added into r (work: 29 doubles per cell).
-void c4_viscous_curv_core(const double* q_dev, const double* s_dev, const double* jinv_dev, double* r_dev,
-                          double* work, const int32_t n[3], const Gas<double>& gas, hipStream_t stream) {
-  const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-  double* phi = work;
-  double* g = phi + 4 * cells;
-  double* fv = g + 12 * cells;
-  double* sc = fv + 4 * cells;
-  Cells3 C{{n[0], n[1], n[2]}};
-  const int gr = grid_for(cells);
-  hipLaunchKernelGGL(k_c4_phi, dim3(gr), dim3(256), 0, stream, q_dev, phi, cells, gas.gm1);
-  hipLaunchKernelGGL(k_c4_grads, dim3(gr), dim3(256), 0, stream, phi, g, C, 1.0, 1.0, 1.0);
-  hipLaunchKernelGGL(k_c4_cell_metrics, dim3(gr), dim3(256), 0, stream, s_dev, sc, C);
-  for (int d = 0; d < 3; ++d) {
-    hipLaunchKernelGGL(k_c4_visc_faces_curv, dim3(gr), dim3(256), 0, stream, phi, g, s_dev, sc, jinv_dev, fv, C, d,
-                       gas);
-    hipLaunchKernelGGL(k_c4_flux_sub, dim3(gr), dim3(256), 0, stream, fv, r_dev, C, d, 1.0, jinv_dev);
-  }
-}
-
 }  // namespace cfd
 
 extern "C" cfd_status cfd_c4_viscous_curv_work_bytes(const int32_t n[3], size_t* bytes) {
   return cfd::host_guarded([&] {
     if (!n || !bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
     if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
-    *bytes = (size_t)8 * 29 * ((size_t)n[0] * n[1] * n[2]);    // phi, index gradients, face flux, cell metrics
+    *bytes = (size_t)8 * (cfd::VW_FIELDS + cfd::FM_FIELDS) * ((size_t)n[0] * n[1] * n[2]);  // phi, gradients, face metrics
   });
 }
 
@@ -1149,7 +1097,7 @@ extern "C" cfd_status cfd_c4_viscous_add_curv_periodic(const double* q_dev, cons
     if (!(gamma > 1.0) || !(prandtl > 0.0) || !(mu_inf >= 0.0) || !(s_star > 0.0) || !std::isfinite(mu_inf))
       cfd::host_fail(CFD_EINVAL, "bad gas parameters");
     const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-    const size_t need = (size_t)8 * 29 * cells;
+    const size_t need = (size_t)8 * (cfd::VW_FIELDS + cfd::FM_FIELDS) * cells;
     if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_c4_viscous_curv_work_bytes()");
     const void* ins[3] = {q_dev, s_dev, jinv_dev};
     const int64_t in_bytes[3] = {40 * cells, 72 * cells, 8 * cells};
@@ -1158,8 +1106,11 @@ extern "C" cfd_status cfd_c4_viscous_add_curv_periodic(const double* q_dev, cons
         cfd::host_fail(CFD_EINVAL, "r and the workspace must not overlap q, the metrics or each other");
     if (!cfd::apart(r_dev, 40 * cells, work_dev, (int64_t)need))
       cfd::host_fail(CFD_EINVAL, "r and the workspace must not overlap q, the metrics or each other");
-    cfd::c4_viscous_curv_core(q_dev, s_dev, jinv_dev, r_dev, static_cast<double*>(work_dev), n,
-                              cfd::viscous_gas(gamma, prandtl, mu_inf, s_star), stream);
+    double* w = static_cast<double*>(work_dev);
+    double* fm = w + cfd::VW_FIELDS * cells;
+    cfd::c4_face_metrics_curv(s_dev, jinv_dev, w, fm, n, stream);
+    cfd::c4_viscous_curv_core(q_dev, s_dev, jinv_dev, r_dev, w, fm, n, cfd::viscous_gas(gamma, prandtl, mu_inf, s_star),
+                              stream);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   });
@@ -1485,70 +1436,346 @@ __global__ void __launch_bounds__(256) k_c4_cell_metrics_line(Line S, double* __
   }
 }
 
-// Fields of the per-block viscous workspace: phi 0..3, g 4..15, fv 16..19, sc 20..28.
-constexpr int VW_PHI = 0, VW_G = 4, VW_FV = 16, VW_SC = 20, VW_FIELDS = 29;
+// Fields of a block's viscous workspace: phi 0..3 and the index gradients
+// g 4..15 (g[a * 3 + t]: phi_a along t); the face metrics, 21 per cell, sit in
+// an array of their own (fm[(d * 7 + m) * cells + c] at the d-face above cell
+// c: m = 0..5 the cell metrics S_t, t != d in increasing t, interpolated to
+// the face; m = 6 the inverse of J^{-1} interpolated likewise).
+constexpr int VW_PHI = 0, VW_G = 4;
 
-__global__ void __launch_bounds__(256) k_c4_visc_faces_line(Line W, Line J, const double* __restrict__ s,
-                                                            double* __restrict__ fv, Dims3 D, int d,
-                                                            Gas<double> gas) {
+// The cell s steps away along d (x = the coordinate along d, possibly outside
+// the block): with a neighbour at least five cells deep one step across the
+// seam; a block that is its own neighbour and thinner than the stencil wraps
+// as often as needed (the periodic single block).
+__device__ __forceinline__ LineRef wrap_ref(const Line& L, const int c0[3], int x, int d, const int n[3]) {
+  int c[3] = {c0[0], c0[1], c0[2]};
+  LineRef r{L.own, L.cown, 0};
+  int nd = n[d];
+  if (x < 0) {
+    r.base = L.lo;
+    r.cells = L.clo;
+    nd = L.nlo;
+    x += nd;
+    if (x < 0) x = (x % nd + nd) % nd;
+  } else if (x >= nd) {
+    r.base = L.hi;
+    r.cells = L.chi;
+    x -= nd;
+    nd = L.nhi;
+    if (x >= nd) x %= nd;
+  }
+  c[d] = x;
+  const int64_t e0 = d == 0 ? nd : n[0], e1 = d == 1 ? nd : n[1];
+  r.idx = ((int64_t)c[2] * e1 + c[1]) * e0 + c[0];
+  return r;
+}
+
+// Face metrics along d from the cell metrics sc (9 fields, S_t[x] at t * 3 + x)
+// and J^{-1}, four-point face values across the seams.
+__global__ void __launch_bounds__(256) k_c4_face_metrics(Line SC, Line J, double* __restrict__ fm, Dims3 D, int d) {
   const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
-    const LineRef wm1 = line_ref(W, i, j, k, -1, d, D.n), w0 = line_ref(W, i, j, k, 0, d, D.n),
-                  wp1 = line_ref(W, i, j, k, 1, d, D.n), wp2 = line_ref(W, i, j, k, 2, d, D.n);
-    const LineRef jm1 = line_ref(J, i, j, k, -1, d, D.n), j0 = line_ref(J, i, j, k, 0, d, D.n),
-                  jp1 = line_ref(J, i, j, k, 1, d, D.n), jp2 = line_ref(J, i, j, k, 2, d, D.n);
-    auto fvl = [&](const Line& L, int f) {
-      const bool w = &L == &W;
-      const LineRef& a = w ? wm1 : jm1;
-      const LineRef& b = w ? w0 : j0;
-      const LineRef& c2 = w ? wp1 : jp1;
-      const LineRef& d2 = w ? wp2 : jp2;
-      return (-a[f] + 9.0 * b[f] + 9.0 * c2[f] - d2[f]) / 16.0;
-    };
-    double Sf[3][3], Sd[3];
-    for (int t = 0; t < 3; ++t)
-      for (int x = 0; x < 3; ++x) Sf[t][x] = t == d ? s[(d * 3 + x) * cells + c] : fvl(W, VW_SC + t * 3 + x);
-    for (int x = 0; x < 3; ++x) Sd[x] = Sf[d][x];
-    const double Jf = 1.0 / fvl(J, 0);
-    double pf[4], grad[4][3];
-    for (int a = 0; a < 4; ++a) {
-      pf[a] = fvl(W, VW_PHI + a);
-      double dxi[3];
-      for (int t = 0; t < 3; ++t)
-        dxi[t] = t == d ? (wm1[VW_PHI + a] - 27.0 * w0[VW_PHI + a] + 27.0 * wp1[VW_PHI + a] - wp2[VW_PHI + a]) *
-                              (1.0 / 24.0)
-                        : fvl(W, VW_G + a * 3 + t);
-      for (int x = 0; x < 3; ++x) grad[a][x] = Jf * (Sf[0][x] * dxi[0] + Sf[1][x] * dxi[1] + Sf[2][x] * dxi[2]);
+    const int p[3] = {(int)(c % D.n[0]), (int)((c / D.n[0]) % D.n[1]), (int)(c / ((int64_t)D.n[0] * D.n[1]))};
+    const LineRef a = wrap_ref(SC, p, p[d] - 1, d, D.n), b = wrap_ref(SC, p, p[d], d, D.n),
+                  e = wrap_ref(SC, p, p[d] + 1, d, D.n), f = wrap_ref(SC, p, p[d] + 2, d, D.n);
+    int m = 0;
+    for (int t = 0; t < 3; ++t) {
+      if (t == d) continue;
+      for (int x = 0; x < 3; ++x) {
+        const int v = t * 3 + x;
+        fm[(d * 7 + m++) * cells + c] = (-a[v] + 9.0 * b[v] + 9.0 * e[v] - f[v]) / 16.0;
+      }
     }
-    const double T = pf[3];
-    const double mu = gas.mu_inf * T * sqrt(T) * (1.0 + gas.s_star) / (T + gas.s_star);
-    const double kc = mu * gas.kfac;
-    const double div = grad[0][0] + grad[1][1] + grad[2][2];
-    double tau[3][3];
-    for (int x = 0; x < 3; ++x)
-      for (int y = 0; y < 3; ++y) tau[x][y] = mu * (grad[x][y] + grad[y][x]);
-    for (int x = 0; x < 3; ++x) tau[x][x] = tau[x][x] - (2.0 / 3.0) * mu * div;
-    double e[3];
-    for (int x = 0; x < 3; ++x) e[x] = pf[0] * tau[x][0] + pf[1] * tau[x][1] + pf[2] * tau[x][2] + kc * grad[3][x];
-    for (int m = 0; m < 3; ++m) fv[m * cells + c] = Sd[0] * tau[0][m] + Sd[1] * tau[1][m] + Sd[2] * tau[2][m];
-    fv[3 * cells + c] = Sd[0] * e[0] + Sd[1] * e[1] + Sd[2] * e[2];
+    const LineRef ja = wrap_ref(J, p, p[d] - 1, d, D.n), jb = wrap_ref(J, p, p[d], d, D.n),
+                  je = wrap_ref(J, p, p[d] + 1, d, D.n), jf = wrap_ref(J, p, p[d] + 2, d, D.n);
+    fm[(d * 7 + 6) * cells + c] = 1.0 / ((-ja[0] + 9.0 * jb[0] + 9.0 * je[0] - jf[0]) / 16.0);
   }
 }
 
-__global__ void __launch_bounds__(256) k_c4_flux_sub_line(Line W, double* __restrict__ r,
-                                                          const double* __restrict__ jinv, Dims3 D, int d) {
-  const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
-    const LineRef rm2 = line_ref(W, i, j, k, -2, d, D.n), rm1 = line_ref(W, i, j, k, -1, d, D.n),
-                  r0 = line_ref(W, i, j, k, 0, d, D.n), rp1 = line_ref(W, i, j, k, 1, d, D.n);
-    for (int v = 0; v < 4; ++v) {
-      const int f = VW_FV + v;
-      const double dF = (rm2[f] - 27.0 * rm1[f] + 27.0 * r0[f] - rp1[f]) * (1.0 / 24.0);
-      r[(1 + v) * cells + c] -= dF / jinv[c];
-    }
+// A cell's inputs of the d-face fluxes: phi (4) and the index derivatives of
+// phi across d (8: a * 2 + u, u-th direction other than d).
+template <int D>
+__device__ __forceinline__ void load_visc_cell(const Line& PG, const int c0[3], int x, const int n[3], double w[12]) {
+  const LineRef r = wrap_ref(PG, c0, x, D, n);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) w[a] = r[VW_PHI + a];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    int u = 0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      if (t != D) w[4 + a * 2 + u++] = r[VW_G + a * 3 + t];
   }
+}
+
+// Viscous flux (momentum x, y, z and energy) through the d-face between the
+// second and third of four consecutive cells A, B, C, E along d: face values of
+// u, v, w, T and of their index derivatives across d, the compact derivative
+// along d, the physical gradient by the chain rule J sum_t S_t d/dxi_t, the
+// stress and heat flux contracted with the face's area vector sd; m: the
+// face's metrics (six S_t, t != d, then J).
+template <int D>
+__device__ __forceinline__ void visc_face_flux(const double A[12], const double B[12], const double C[12],
+                                               const double E[12], const double m[7], const double sd[3],
+                                               const Gas<double>& gas, double out[4]) {
+  auto fval = [](double a, double b, double c, double e) { return (-a + 9.0 * b + 9.0 * c - e) / 16.0; };
+  double Sf[3][3];
+  {
+    int k = 0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int x = 0; x < 3; ++x) Sf[t][x] = t == D ? sd[x] : m[k++];
+  }
+  const double Jf = m[6];
+  double pf[4], grad[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    pf[a] = fval(A[a], B[a], C[a], E[a]);
+    double dxi[3];
+    int u = 0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (t == D) {
+        dxi[t] = (A[a] - 27.0 * B[a] + 27.0 * C[a] - E[a]) * (1.0 / 24.0);
+      } else {
+        const int f = 4 + a * 2 + u++;
+        dxi[t] = fval(A[f], B[f], C[f], E[f]);
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < 3; ++x) grad[a][x] = Jf * (Sf[0][x] * dxi[0] + Sf[1][x] * dxi[1] + Sf[2][x] * dxi[2]);
+  }
+  const double T = pf[3];
+  const double mu = gas.mu_inf * T * sqrt(T) * (1.0 + gas.s_star) / (T + gas.s_star);
+  const double kc = mu * gas.kfac;
+  const double div = grad[0][0] + grad[1][1] + grad[2][2];
+  double tau[3][3];
+#pragma unroll
+  for (int x = 0; x < 3; ++x)
+#pragma unroll
+    for (int y = 0; y < 3; ++y) tau[x][y] = mu * (grad[x][y] + grad[y][x]);
+#pragma unroll
+  for (int x = 0; x < 3; ++x) tau[x][x] = tau[x][x] - (2.0 / 3.0) * mu * div;
+  double e[3];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) e[x] = pf[0] * tau[x][0] + pf[1] * tau[x][1] + pf[2] * tau[x][2] + kc * grad[3][x];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) out[q] = sd[0] * tau[0][q] + sd[1] * tau[1][q] + sd[2] * tau[2][q];
+  out[3] = sd[0] * e[0] + sd[1] * e[1] + sd[2] * e[2];
+}
+
+template <int D>
+__device__ __forceinline__ void visc_face_at(const Line& FM, const Line& S, const int c0[3], int f, const int n[3],
+                                             const double* A, const double* B, const double* C, const double* E,
+                                             const Gas<double>& gas, double out[4]) {
+  const LineRef mr = wrap_ref(FM, c0, f, D, n), sr = wrap_ref(S, c0, f, D, n);
+  double m[7], sd[3];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) m[k] = mr[D * 7 + k];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) sd[x] = sr[D * 3 + x];
+  visc_face_flux<D>(A, B, C, E, m, sd, gas, out);
+}
+
+// r[1 + v] -= (F_{c-3/2} - 27 F_{c-1/2} + 27 F_{c+1/2} - F_{c+3/2}) / 24 / J^{-1}.
+__device__ __forceinline__ void visc_flux_sub(double* __restrict__ r, const double* __restrict__ jinv, int64_t cells,
+                                              int64_t c, const double* Fm2, const double* Fm1, const double* F0,
+                                              const double* Fp1) {
+  const double ji = jinv[c];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double dF = (Fm2[v] - 27.0 * Fm1[v] + 27.0 * F0[v] - Fp1[v]) * (1.0 / 24.0);
+    r[(1 + v) * cells + c] -= dF / ji;
+  }
+}
+
+// The viscous terms along d = 1 or 2 added into r: each thread marches one
+// line of cells along d (lanes along i, so every load is a coalesced row)
+// over a chunk of `chunk` cells, keeping the four cells around the current
+// face and the last four face fluxes in registers: each cell's inputs are
+// loaded once per chunk instead of once per face stencil, and the face
+// fluxes never leave the chip.
+template <int D>
+__global__ void __launch_bounds__(256) k_c4_visc_march(Line PG, Line FM, Line S, double* __restrict__ r,
+                                                       const double* __restrict__ jinv, Dims3 Dm, int chunk,
+                                                       Gas<double> gas) {
+  constexpr int O = D == 1 ? 2 : 1;
+  const int* n = Dm.n;
+  const int nD = n[D], nO = n[O], n0 = n[0];
+  const int nch = (nD + chunk - 1) / chunk;
+  const int64_t cells = (int64_t)n0 * n[1] * n[2];
+  const int64_t total = (int64_t)n0 * nO * nch;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    int c0[3];
+    c0[0] = (int)(t % n0);
+    const int64_t rest = t / n0;
+    c0[O] = (int)(rest % nO);
+    c0[D] = 0;
+    const int x0 = (int)(rest / nO) * chunk, x1 = min(x0 + chunk, nD);
+    auto cell_index = [&](int x) {
+      int p[3] = {c0[0], c0[1], c0[2]};
+      p[D] = x;
+      return ((int64_t)p[2] * n[1] + p[1]) * n0 + p[0];
+    };
+    double W0[12], W1[12], W2[12], W3[12];
+    double F0[4], F1[4], F2[4], F3[4];
+    load_visc_cell<D>(PG, c0, x0 - 3, n, W0);
+    load_visc_cell<D>(PG, c0, x0 - 2, n, W1);
+    load_visc_cell<D>(PG, c0, x0 - 1, n, W2);
+    // face g (between cells g and g + 1) needs cells g - 1 .. g + 2; cell
+    // g - 1 is finished with face g.  Window and face slots rotate by one per
+    // face: four faces per trip, each with its own register names.
+#define CFD_VSTEP(U, A, B, C, E, FN, FA, FB, FC)                                    \
+  {                                                                               \
+    const int g = f + U;                                                          \
+    if (g <= x1) {                                                                \
+      load_visc_cell<D>(PG, c0, g + 2, n, E);                                     \
+      visc_face_at<D>(FM, S, c0, g, n, A, B, C, E, gas, FN);                      \
+      if (g > x0) visc_flux_sub(r, jinv, cells, cell_index(g - 1), FA, FB, FC, FN); \
+    }                                                                             \
+  }
+    for (int f = x0 - 2; f <= x1; f += 4) {
+      CFD_VSTEP(0, W0, W1, W2, W3, F0, F1, F2, F3)
+      CFD_VSTEP(1, W1, W2, W3, W0, F1, F2, F3, F0)
+      CFD_VSTEP(2, W2, W3, W0, W1, F2, F3, F0, F1)
+      CFD_VSTEP(3, W3, W0, W1, W2, F3, F0, F1, F2)
+    }
+#undef CFD_VSTEP
+  }
+}
+
+// The viscous terms along i added into r: each wave takes 64 cells of one
+// row, stages the inputs of the 70 cells around them in LDS (coalesced along
+// i), computes the 67 face fluxes they need into LDS, then the differences.
+constexpr int VROW_CELLS = 70, VROW_FACES = 67;
+
+__global__ void __launch_bounds__(256) k_c4_visc_rows(Line PG, Line FM, Line S, double* __restrict__ r,
+                                                      const double* __restrict__ jinv, Dims3 Dm, Gas<double> gas) {
+  __shared__ double sw[4][12][VROW_CELLS + 2];
+  __shared__ double sf[4][4][VROW_FACES + 1];
+  const int* n = Dm.n;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nseg = (n[0] + 63) / 64;
+  const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+  const int64_t items = (int64_t)n[1] * n[2] * nseg;
+  for (int64_t base = (int64_t)blockIdx.x * 4; base < items; base += (int64_t)gridDim.x * 4) {
+    const int64_t it = base + w;
+    const bool act = it < items;
+    int c0[3] = {0, 0, 0}, x0 = 0, x1 = 0;
+    if (act) {
+      const int64_t row = it / nseg;
+      x0 = (int)(it % nseg) * 64;
+      x1 = min(x0 + 64, n[0]);
+      c0[1] = (int)(row % n[1]);
+      c0[2] = (int)(row / n[1]);
+      for (int e = lane; e < VROW_CELLS; e += 64) {
+        const int x = x0 - 3 + e;
+        if (x <= x1 + 2) {
+          double v[12];
+          load_visc_cell<0>(PG, c0, x, n, v);
+#pragma unroll
+          for (int f = 0; f < 12; ++f) sw[w][f][e] = v[f];
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+      for (int e = lane; e < VROW_FACES; e += 64) {
+        const int g = x0 - 2 + e;
+        if (g <= x1) {
+          double A[12], B[12], C[12], E[12], out[4];
+#pragma unroll
+          for (int f = 0; f < 12; ++f) {
+            A[f] = sw[w][f][e];
+            B[f] = sw[w][f][e + 1];
+            C[f] = sw[w][f][e + 2];
+            E[f] = sw[w][f][e + 3];
+          }
+          visc_face_at<0>(FM, S, c0, g, n, A, B, C, E, gas, out);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) sf[w][v][e] = out[v];
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+      const int x = x0 + lane;
+      if (x < x1) {
+        double Fm2[4], Fm1[4], F0[4], Fp1[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          Fm2[v] = sf[w][v][lane];
+          Fm1[v] = sf[w][v][lane + 1];
+          F0[v] = sf[w][v][lane + 2];
+          Fp1[v] = sf[w][v][lane + 3];
+        }
+        visc_flux_sub(r, jinv, cells, ((int64_t)c0[2] * n[1] + c0[1]) * n[0] + x, Fm2, Fm1, F0, Fp1);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Chunk of the march kernels: 32 cells, halved (down to 8) while the grid
+// gives fewer than 128 k threads.
+int visc_chunk(const int n[3], int d) {
+  const int o = d == 1 ? 2 : 1;
+  int chunk = 32;
+  while (chunk > 8 && (int64_t)n[0] * n[o] * ((n[d] + chunk - 1) / chunk) < (int64_t)1 << 17) chunk /= 2;
+  return chunk;
+}
+
+// The fused viscous passes of one block (lines built by the caller): i rows,
+// then the j and k marches, each subtracting its differences from r.
+void visc_fused_launch(const Line* PG, const Line* FM, const Line* S, double* r, const double* jinv, const int n[3],
+                       const Gas<double>& gas, hipStream_t stream) {
+  const Dims3 D{{n[0], n[1], n[2]}};
+  const int64_t rows = (int64_t)n[1] * n[2] * ((n[0] + 63) / 64);
+  const int grows = (int)std::min<int64_t>((rows + 3) / 4, 1 << 16);
+  hipLaunchKernelGGL(k_c4_visc_rows, dim3(grows), dim3(256), 0, stream, PG[0], FM[0], S[0], r, jinv, D, gas);
+  const int c1 = visc_chunk(n, 1), c2 = visc_chunk(n, 2);
+  const int64_t t1 = (int64_t)n[0] * n[2] * ((n[1] + c1 - 1) / c1), t2 = (int64_t)n[0] * n[1] * ((n[2] + c2 - 1) / c2);
+  hipLaunchKernelGGL(k_c4_visc_march<1>, dim3(grid_for(t1)), dim3(256), 0, stream, PG[1], FM[1], S[1], r, jinv, D, c1,
+                     gas);
+  hipLaunchKernelGGL(k_c4_visc_march<2>, dim3(grid_for(t2)), dim3(256), 0, stream, PG[2], FM[2], S[2], r, jinv, D, c2,
+                     gas);
+}
+
+// A periodic block's lines: every neighbour the block itself.
+Line self_line(const double* base, int64_t cells, int nd) { return Line{base, base, base, cells, cells, cells, nd, nd}; }
+
+void c4_face_metrics_curv(const double* s_dev, const double* jinv_dev, double* sc_tmp, double* fm, const int32_t n[3],
+                          hipStream_t stream) {
+  const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+  const Cells3 C{{n[0], n[1], n[2]}};
+  const Dims3 D{{n[0], n[1], n[2]}};
+  const int gr = grid_for(cells);
+  hipLaunchKernelGGL(k_c4_cell_metrics, dim3(gr), dim3(256), 0, stream, s_dev, sc_tmp, C);
+  for (int d = 0; d < 3; ++d)
+    hipLaunchKernelGGL(k_c4_face_metrics, dim3(gr), dim3(256), 0, stream, self_line(sc_tmp, cells, n[d]),
+                       self_line(jinv_dev, cells, n[d]), fm, D, d);
+}
+
+// The curvilinear viscous terms of a periodic block added into r (work: phi
+// and gradients, 16 doubles per cell; fm: its face metrics).
+void c4_viscous_curv_core(const double* q_dev, const double* s_dev, const double* jinv_dev, double* r_dev,
+                          double* work, const double* fm, const int32_t n[3], const Gas<double>& gas,
+                          hipStream_t stream) {
+  const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+  double* phi = work;
+  double* g = phi + 4 * cells;
+  const Cells3 C{{n[0], n[1], n[2]}};
+  const int gr = grid_for(cells);
+  hipLaunchKernelGGL(k_c4_phi, dim3(gr), dim3(256), 0, stream, q_dev, phi, cells, gas.gm1);
+  hipLaunchKernelGGL(k_c4_grads, dim3(gr), dim3(256), 0, stream, phi, g, C, 1.0, 1.0, 1.0);
+  Line PG[3], FM[3], S[3];
+  for (int d = 0; d < 3; ++d) {
+    PG[d] = self_line(work, cells, n[d]);
+    FM[d] = self_line(fm, cells, n[d]);
+    S[d] = self_line(s_dev, cells, n[d]);
+  }
+  visc_fused_launch(PG, FM, S, r_dev, jinv_dev, n, gas, stream);
 }
 
 }  // namespace cfd
@@ -1561,57 +1788,76 @@ using cfd::block_cells;
 
 namespace cfd {
 
-// The viscous terms of blocks joined face to face added into r (arguments
-// checked by the caller; W: 29 doubles per cell of every block).
-void c4_viscous_blocks_launch(int32_t nblk, const int32_t* dims, const int32_t* nbr, const double* const* q_dev,
-                              const double* const* s_dev, const double* const* jinv_dev, double* const* r_dev,
-                              double* W, const Gas<double>& gas, hipStream_t stream) {
+// Per-block offsets (in doubles) of `per` fields per cell.
+std::vector<int64_t> field_offsets(int32_t nblk, const int32_t* dims, int per) {
   std::vector<int64_t> off(nblk + 1, 0);
-  for (int b = 0; b < nblk; ++b) off[b + 1] = off[b] + VW_FIELDS * block_cells(dims, b);
-  // the line along d around block b over per-block arrays (bases), or over
-  // the per-block workspaces when bases is NULL
-  auto line = [&](int b, int d, const double* const* bases) {
-    const int lo = nbr[6 * b + 2 * d], hi = nbr[6 * b + 2 * d + 1];
-    Line L{};
-    L.own = bases ? bases[b] : W + off[b];
-    L.lo = bases ? bases[lo] : W + off[lo];
-    L.hi = bases ? bases[hi] : W + off[hi];
-    L.cown = block_cells(dims, b);
-    L.clo = block_cells(dims, lo);
-    L.chi = block_cells(dims, hi);
-    L.nlo = dims[3 * lo + d];
-    L.nhi = dims[3 * hi + d];
-    return L;
-  };
+  for (int b = 0; b < nblk; ++b) off[b + 1] = off[b] + per * block_cells(dims, b);
+  return off;
+}
+
+// The line along d around block b over per-block arrays.
+Line block_line(int b, int d, const int32_t* dims, const int32_t* nbr, const double* const* bases) {
+  const int lo = nbr[6 * b + 2 * d], hi = nbr[6 * b + 2 * d + 1];
+  return Line{bases[b], bases[lo], bases[hi], block_cells(dims, b), block_cells(dims, lo), block_cells(dims, hi),
+              dims[3 * lo + d], dims[3 * hi + d]};
+}
+
+// Face metrics of blocks joined face to face into FM (21 doubles per cell of
+// every block), once per grid; W (16 doubles per cell of every block) holds
+// the cell metrics meanwhile.
+void c4_face_metrics_blocks(int32_t nblk, const int32_t* dims, const int32_t* nbr, const double* const* s_dev,
+                            const double* const* jinv_dev, double* W, double* FM, hipStream_t stream) {
+  const std::vector<int64_t> off = field_offsets(nblk, dims, VW_FIELDS), offm = field_offsets(nblk, dims, FM_FIELDS);
+  std::vector<const double*> sc(nblk);
+  for (int b = 0; b < nblk; ++b) sc[b] = W + off[b];
   for (int b = 0; b < nblk; ++b) {
     const int64_t cb = block_cells(dims, b);
-    hipLaunchKernelGGL(k_c4_phi, dim3(grid_for(cb)), dim3(256), 0, stream, q_dev[b], W + off[b], cb,
-                       gas.gm1);
+    const Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
+    for (int t = 0; t < 3; ++t)
+      hipLaunchKernelGGL(k_c4_cell_metrics_line, dim3(grid_for(cb)), dim3(256), 0, stream,
+                         block_line(b, t, dims, nbr, s_dev), W + off[b], D, t);
   }
   for (int b = 0; b < nblk; ++b) {
     const int64_t cb = block_cells(dims, b);
     const Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
-    for (int t = 0; t < 3; ++t) {
-      hipLaunchKernelGGL(k_c4_grads_line, dim3(grid_for(cb)), dim3(256), 0, stream,
-                         line(b, t, nullptr), W + off[b] + VW_G * cb, D, t);
-      hipLaunchKernelGGL(k_c4_cell_metrics_line, dim3(grid_for(cb)), dim3(256), 0, stream,
-                         line(b, t, s_dev), W + off[b] + VW_SC * cb, D, t);
-    }
+    for (int d = 0; d < 3; ++d)
+      hipLaunchKernelGGL(k_c4_face_metrics, dim3(grid_for(cb)), dim3(256), 0, stream,
+                         block_line(b, d, dims, nbr, sc.data()), block_line(b, d, dims, nbr, jinv_dev), FM + offm[b],
+                         D, d);
   }
-  for (int d = 0; d < 3; ++d) {
-    for (int b = 0; b < nblk; ++b) {
-      const int64_t cb = block_cells(dims, b);
-      const Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
-      hipLaunchKernelGGL(k_c4_visc_faces_line, dim3(grid_for(cb)), dim3(256), 0, stream,
-                         line(b, d, nullptr), line(b, d, jinv_dev), s_dev[b],
-                         W + off[b] + VW_FV * cb, D, d, gas);
+}
+
+// The viscous terms of blocks joined face to face added into r (arguments
+// checked by the caller; W: 16 doubles per cell of every block; FM: their
+// face metrics from c4_face_metrics_blocks).
+void c4_viscous_blocks_launch(int32_t nblk, const int32_t* dims, const int32_t* nbr, const double* const* q_dev,
+                              const double* const* s_dev, const double* const* jinv_dev, double* const* r_dev,
+                              double* W, const double* FM, const Gas<double>& gas, hipStream_t stream) {
+  const std::vector<int64_t> off = field_offsets(nblk, dims, VW_FIELDS), offm = field_offsets(nblk, dims, FM_FIELDS);
+  std::vector<const double*> wb(nblk), fb(nblk);
+  for (int b = 0; b < nblk; ++b) {
+    wb[b] = W + off[b];
+    fb[b] = FM + offm[b];
+  }
+  for (int b = 0; b < nblk; ++b) {
+    const int64_t cb = block_cells(dims, b);
+    hipLaunchKernelGGL(k_c4_phi, dim3(grid_for(cb)), dim3(256), 0, stream, q_dev[b], W + off[b], cb, gas.gm1);
+  }
+  for (int b = 0; b < nblk; ++b) {
+    const int64_t cb = block_cells(dims, b);
+    const Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
+    for (int t = 0; t < 3; ++t)
+      hipLaunchKernelGGL(k_c4_grads_line, dim3(grid_for(cb)), dim3(256), 0, stream,
+                         block_line(b, t, dims, nbr, wb.data()), W + off[b] + VW_G * cb, D, t);
+  }
+  for (int b = 0; b < nblk; ++b) {
+    Line PG[3], FL[3], S[3];
+    for (int d = 0; d < 3; ++d) {
+      PG[d] = block_line(b, d, dims, nbr, wb.data());
+      FL[d] = block_line(b, d, dims, nbr, fb.data());
+      S[d] = block_line(b, d, dims, nbr, s_dev);
     }
-    for (int b = 0; b < nblk; ++b) {
-      const int64_t cb = block_cells(dims, b);
-      const Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
-      hipLaunchKernelGGL(k_c4_flux_sub_line, dim3(grid_for(cb)), dim3(256), 0, stream,
-                         line(b, d, nullptr), r_dev[b], jinv_dev[b], D, d);
-    }
+    visc_fused_launch(PG, FL, S, r_dev[b], jinv_dev[b], dims + 3 * b, gas, stream);
   }
 }
 
@@ -1623,7 +1869,7 @@ extern "C" cfd_status cfd_c4_viscous_blocks_work_bytes(int32_t nblk, const int32
     if (!bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
     check_seams(nblk, dims, nbr);
     size_t total = 0;
-    for (int b = 0; b < nblk; ++b) total += (size_t)8 * cfd::VW_FIELDS * block_cells(dims, b);
+    for (int b = 0; b < nblk; ++b) total += (size_t)8 * (cfd::VW_FIELDS + cfd::FM_FIELDS) * block_cells(dims, b);
     *bytes = total;
   });
 }
@@ -1638,8 +1884,7 @@ extern "C" cfd_status cfd_c4_viscous_add_blocks(int32_t nblk, const int32_t* dim
     if (!q_dev || !s_dev || !jinv_dev || !r_dev || !work_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
     if (!(gamma > 1.0) || !(prandtl > 0.0) || !(mu_inf >= 0.0) || !(s_star > 0.0) || !std::isfinite(mu_inf))
       cfd::host_fail(CFD_EINVAL, "bad gas parameters");
-    std::vector<int64_t> off(nblk + 1, 0);
-    for (int b = 0; b < nblk; ++b) off[b + 1] = off[b] + cfd::VW_FIELDS * block_cells(dims, b);
+    const std::vector<int64_t> off = cfd::field_offsets(nblk, dims, cfd::VW_FIELDS + cfd::FM_FIELDS);
     const size_t need = (size_t)8 * off[nblk];
     if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_c4_viscous_blocks_work_bytes()");
     std::vector<cfd::ArgSpan> spans{cfd::span(work_dev, (int64_t)need, true)};
@@ -1650,7 +1895,10 @@ extern "C" cfd_status cfd_c4_viscous_add_blocks(int32_t nblk, const int32_t* dim
                                  cfd::span(jinv_dev[b], 8 * cb, false), cfd::span(r_dev[b], 40 * cb, true)});
     }
     cfd::check_spans(spans, "a residual or the workspace overlaps an input, another residual or the workspace");
-    cfd::c4_viscous_blocks_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, r_dev, static_cast<double*>(work_dev),
+    double* W = static_cast<double*>(work_dev);
+    double* FM = W + cfd::field_offsets(nblk, dims, cfd::VW_FIELDS)[nblk];
+    cfd::c4_face_metrics_blocks(nblk, dims, nbr, s_dev, jinv_dev, W, FM, stream);
+    cfd::c4_viscous_blocks_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, r_dev, W, FM,
                                   cfd::viscous_gas(gamma, prandtl, mu_inf, s_star), stream);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) cfd::host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -1663,7 +1911,7 @@ extern "C" cfd_status cfd_wcns5_ns_step_work_bytes(const int32_t n[3], size_t* b
     if (!n || !bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
     if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
     const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-    *bytes = std::max(wcns5_residual_work(n), (size_t)8 * 29 * cells) + (size_t)2 * 40 * cells;
+    *bytes = cfd::visc_region(wcns5_residual_work(n), cells) + (size_t)2 * 40 * cells;
   });
 }
 
@@ -1810,8 +2058,9 @@ extern "C" cfd_status cfd_wcns5_implicit_step_work_bytes(const int32_t n[3], siz
     if (!n || !bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
     if (n[0] < 1 || n[1] < 1 || n[2] < 1) cfd::host_fail(CFD_EINVAL, "every extent must be >= 1");
     const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-    // scratch of the residual or the viscous terms, then R, two dQ, lambda (3), viscous lambda (3), D
-    *bytes = std::max(wcns5_residual_work(n), (size_t)8 * 29 * cells) + (size_t)8 * 22 * cells;
+    // scratch of the residual or the viscous terms, the viscous face metrics, then R, two dQ, lambda (3),
+    // viscous lambda (3), D
+    *bytes = cfd::visc_region(wcns5_residual_work(n), cells) + (size_t)8 * 22 * cells;
   });
 }
 
@@ -1831,7 +2080,7 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_curv_periodic(double* q_dev, cons
       cfd::host_fail(CFD_EINVAL, "bad gas parameters");
     const int64_t cells = (int64_t)n[0] * n[1] * n[2];
     const size_t rw0 = wcns5_residual_work(n);
-    const size_t rw = std::max(rw0, (size_t)8 * 29 * cells);
+    const size_t rw = cfd::visc_region(rw0, cells);
     const size_t need = rw + (size_t)8 * 22 * cells;
     if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_implicit_step_work_bytes()");
     if (!cfd::apart(q_dev, 40 * cells, work_dev, (int64_t)work_bytes) ||
@@ -1849,10 +2098,13 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_curv_periodic(double* q_dev, cons
     const cfd::Gas<double> vgas = cfd::viscous_gas(gamma, viscous ? prandtl : 1.0, mu_inf, s_star);
     const cfd::Cells3 C{{n[0], n[1], n[2]}};
     const int gr = cfd::grid_for(cells);
+    double* fm = reinterpret_cast<double*>(static_cast<char*>(work_dev) + cfd::visc_fm_offset(rw0, cells));
+    if (viscous && nsteps > 0)
+      cfd::c4_face_metrics_curv(s_dev, jinv_dev, static_cast<double*>(work_dev), fm, n, stream);
     for (int it = 0; it < nsteps; ++it) {
       cfd::wcns5_residual_core(q_dev, s_dev, jinv_dev, R, work_dev, rw0, n, nullptr, gamma, entropy_fix, eps, stream);
       if (viscous)
-        cfd::c4_viscous_curv_core(q_dev, s_dev, jinv_dev, R, static_cast<double*>(work_dev), n, vgas, stream);
+        cfd::c4_viscous_curv_core(q_dev, s_dev, jinv_dev, R, static_cast<double*>(work_dev), fm, n, vgas, stream);
       hipLaunchKernelGGL(cfd::k_impl_lambda, dim3(gr), dim3(256), 0, stream, q_dev, s_dev, jinv_dev, lam, lamv, C,
                          gamma, vgas, viscous ? 1 : 0);
       hipLaunchKernelGGL(cfd::k_impl_diag, dim3(gr), dim3(256), 0, stream, R, lam, lamv, jinv_dev, diag, dqa, C, dt,
@@ -1988,12 +2240,13 @@ extern "C" cfd_status cfd_wcns5_implicit_blocks_work_bytes(int32_t nblk, const i
   return cfd::host_guarded([&] {
     if (!bytes) cfd::host_fail(CFD_EINVAL, "NULL argument");
     const size_t rscratch = check_seams(nblk, dims, nbr);
-    size_t vscratch = 0, rest = 0;
+    size_t vscratch = 0, fmb = 0, rest = 0;
     for (int b = 0; b < nblk; ++b) {
       vscratch += (size_t)8 * cfd::VW_FIELDS * block_cells(dims, b);   // the viscous terms' scratch
+      fmb += (size_t)8 * cfd::FM_FIELDS * block_cells(dims, b);        // their face metrics
       rest += (size_t)8 * 22 * block_cells(dims, b);                   // R, two dQ, radii (3 + 3), D
     }
-    *bytes = std::max(rscratch, vscratch) + rest;
+    *bytes = std::max(rscratch, vscratch) + fmb + rest;
   });
 }
 
@@ -2007,9 +2260,13 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_
     const size_t rscratch = check_seams(nblk, dims, nbr);
     if (viscous && (!(prandtl > 0.0) || !(mu_inf >= 0.0) || !(s_star > 0.0) || !std::isfinite(mu_inf)))
       cfd::host_fail(CFD_EINVAL, "bad gas parameters");
-    size_t vscratch = 0;
-    for (int b = 0; b < nblk; ++b) vscratch += (size_t)8 * cfd::VW_FIELDS * block_cells(dims, b);
-    const size_t scratch = std::max(rscratch, vscratch);
+    size_t vscratch = 0, fmb = 0;
+    for (int b = 0; b < nblk; ++b) {
+      vscratch += (size_t)8 * cfd::VW_FIELDS * block_cells(dims, b);
+      fmb += (size_t)8 * cfd::FM_FIELDS * block_cells(dims, b);
+    }
+    const size_t shared = std::max(rscratch, vscratch);
+    const size_t scratch = shared + fmb;
     if (!q_dev || !s_dev || !jinv_dev || !work_dev) cfd::host_fail(CFD_EINVAL, "NULL argument");
     if (!(gamma > 1.0) || !std::isfinite(gamma)) cfd::host_fail(CFD_EINVAL, "gamma must exceed 1");
     if (!(entropy_fix >= 0.0) || !std::isfinite(entropy_fix)) cfd::host_fail(CFD_EINVAL, "bad entropy_fix");
@@ -2052,12 +2309,15 @@ extern "C" cfd_status cfd_wcns5_implicit_steps_blocks(int32_t nblk, const int32_
     std::vector<const double*> qv(q_dev, q_dev + nblk), sv(s_dev, s_dev + nblk), jv(jinv_dev, jinv_dev + nblk),
         lamc(lam.begin(), lam.end()), lamvc(lamv.begin(), lamv.end());
     std::vector<double*> rv(R.begin(), R.end());
+    double* FM = reinterpret_cast<double*>(static_cast<char*>(work_dev) + shared);
+    if (viscous && nsteps > 0)
+      cfd::c4_face_metrics_blocks(nblk, dims, nbr, s_dev, jinv_dev, static_cast<double*>(work_dev), FM, stream);
     for (int it = 0; it < nsteps; ++it) {
       cfd::wcns5_blocks_residual_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, rv.data(), work_dev, gamma,
                                         entropy_fix, eps, stream);
       if (viscous)
         cfd::c4_viscous_blocks_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, rv.data(),
-                                      static_cast<double*>(work_dev), vgas, stream);
+                                      static_cast<double*>(work_dev), FM, vgas, stream);
       for (int b = 0; b < nblk; ++b) {
         const int64_t cb = block_cells(dims, b);
         const cfd::Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
@@ -2104,7 +2364,7 @@ extern "C" cfd_status cfd_wcns5_ns_blocks_work_bytes(int32_t nblk, const int32_t
     size_t vscratch = 0, states = 0;
     for (int b = 0; b < nblk; ++b) {
       vscratch += (size_t)8 * cfd::VW_FIELDS * block_cells(dims, b);
-      states += (size_t)8 * 10 * block_cells(dims, b);
+      states += (size_t)8 * (10 + cfd::FM_FIELDS) * block_cells(dims, b);   // Q^n, R, viscous face metrics
     }
     *bytes = std::max(rscratch, vscratch) + states;
   });
@@ -2353,7 +2613,7 @@ cfd_status ns_steps_blocks_impl(int32_t nblk, const int32_t* dims, const int32_t
       vscratch += (size_t)8 * cfd::VW_FIELDS * block_cells(dims, b);
     }
     const size_t scratch = std::max(rscratch, vscratch);
-    const size_t need = scratch + (size_t)8 * off[nblk];
+    const size_t need = scratch + (size_t)8 * off[nblk] + (size_t)8 * cfd::FM_FIELDS * (off[nblk] / 10);
     if (work_bytes < need) cfd::host_fail(CFD_ENOMEM, "workspace smaller than cfd_wcns5_ns_blocks_work_bytes()");
     std::vector<cfd::ArgSpan> spans{cfd::span(work_dev, (int64_t)need, true)};
     for (int b = 0; b < nblk; ++b) {
@@ -2371,6 +2631,9 @@ cfd_status ns_steps_blocks_impl(int32_t nblk, const int32_t* dims, const int32_t
     }
     const cfd::Gas<double> vgas = cfd::viscous_gas(gamma, prandtl, mu_inf, s_star);
     const double a[3] = {0.0, 0.75, 1.0 / 3.0}, bb[3] = {1.0, 0.25, 2.0 / 3.0};
+    double* FM = base + off[nblk];      // the viscous face metrics, once per call
+    if (viscous && nsteps > 0)
+      cfd::c4_face_metrics_blocks(nblk, dims, nbr, s_dev, jinv_dev, static_cast<double*>(work_dev), FM, stream);
     for (int it = 0; it < nsteps; ++it)
       for (int st = 0; st < 3; ++st) {
         for (int c = 0; c < nclosures; ++c) {
@@ -2383,7 +2646,7 @@ cfd_status ns_steps_blocks_impl(int32_t nblk, const int32_t* dims, const int32_t
                                           entropy_fix, eps, stream);
         if (viscous)
           cfd::c4_viscous_blocks_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, R.data(),
-                                        static_cast<double*>(work_dev), vgas, stream);
+                                        static_cast<double*>(work_dev), FM, vgas, stream);
         for (int b = 0; b < nblk; ++b) {
           const int64_t nv = 5 * block_cells(dims, b);
           hipLaunchKernelGGL(cfd::k_rk3_stage, dim3(cfd::grid_for(nv)), dim3(256), 0, stream, q_dev[b], qn[b], R[b],

@@ -259,7 +259,7 @@ def test_curvilinear_viscous_bad_arguments():
     n = (C.c_int32 * 3)(8, 4, 2)
     nb = C.c_size_t()
     assert L.cfd_c4_viscous_curv_work_bytes(n, C.byref(nb)) == 0
-    assert nb.value == 8 * 29 * 64
+    assert nb.value == 8 * (16 + 21) * 64     # phi and gradients, face metrics
     q, s, j, r, w = (C.c_void_p(a) for a in (0x100000, 0x900000, 0x1100000, 0x2100000, 0x3100000))
     ok = dict(q=q, s=s, j=j, r=r, w=w, wb=nb.value, n=n, g=1.4, pr=0.72, mu=1e-3, ss=0.38)
     bad = {-2: [dict(wb=nb.value - 8)],
@@ -332,7 +332,7 @@ def test_viscous_seams_bad_arguments():
     nbr = (C.c_int32 * 12)(1, 1, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1)
     nb = C.c_size_t()
     assert L.cfd_c4_viscous_blocks_work_bytes(2, dims, nbr, C.byref(nb)) == 0
-    assert nb.value == 8 * 29 * 240 * 2
+    assert nb.value == 8 * (16 + 21) * 240 * 2
     bad_nbr = (C.c_int32 * 12)(1, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1)
     assert L.cfd_c4_viscous_blocks_work_bytes(2, dims, bad_nbr, C.byref(nb)) == -1
     assert L.cfd_c4_viscous_blocks_work_bytes(2, dims, nbr, C.byref(nb)) == 0
@@ -357,8 +357,9 @@ def test_ns_steps_bad_arguments():
     n = (C.c_int32 * 3)(8, 4, 2)
     nb = C.c_size_t()
     assert L.cfd_wcns5_ns_step_work_bytes(n, C.byref(nb)) == 0
-    # the larger scratch (29 doubles per cell for the viscous terms vs the residual's) + start state and R
-    assert nb.value == max(8 * (5 * 32 * 12 + 5 * 32 * 7), 8 * 29 * 64) + 2 * 40 * 64
+    # the larger scratch (16 doubles per cell for the viscous terms vs the residual's), the viscous face
+    # metrics (21 per cell), start state and R
+    assert nb.value == max(8 * (5 * 32 * 12 + 5 * 32 * 7), 8 * 16 * 64) + 8 * 21 * 64 + 2 * 40 * 64
     q, s, j, w = C.c_void_p(0x100000), C.c_void_p(0x900000), C.c_void_p(0x1100000), C.c_void_p(0x2100000)
     ok = dict(q=q, s=s, j=j, w=w, wb=nb.value, g=1.4, ef=0.1, eps=1e-6, pr=0.72, mu=1e-3, ss=0.38, dt=0.01, ns=2)
     bad = {-2: [dict(wb=nb.value - 8)],
@@ -377,8 +378,9 @@ def test_implicit_steps_bad_arguments():
     n = (C.c_int32 * 3)(8, 4, 2)
     nb = C.c_size_t()
     assert L.cfd_wcns5_implicit_step_work_bytes(n, C.byref(nb)) == 0
-    # the larger scratch (the viscous terms' 29 doubles per cell here) + 22 doubles per cell
-    assert nb.value == max(8 * (5 * 32 * 12 + 5 * 32 * 7), 8 * 29 * 64) + 8 * 22 * 64
+    # the larger scratch (the viscous terms' 16 doubles per cell, or the residual's) + the face metrics
+    # (21) + 22 doubles per cell
+    assert nb.value == max(8 * (5 * 32 * 12 + 5 * 32 * 7), 8 * 16 * 64) + 8 * 21 * 64 + 8 * 22 * 64
     q, s, j, w = C.c_void_p(0x100000), C.c_void_p(0x900000), C.c_void_p(0x1100000), C.c_void_p(0x2100000)
     ok = dict(q=q, s=s, j=j, w=w, wb=nb.value, g=1.4, ef=0.1, eps=1e-6, v=1, pr=0.72, mu=1e-3, ss=0.38, dt=0.01,
               ns=2, sw=3)
@@ -401,7 +403,7 @@ def test_implicit_blocks_bad_arguments():
     nbr = (C.c_int32 * 12)(1, 1, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1)
     nb = C.c_size_t()
     assert L.cfd_wcns5_implicit_blocks_work_bytes(2, dims, nbr, C.byref(nb)) == 0
-    assert nb.value == max(8 * (5 * 48 * 15 + 5 * 48 * 10), 8 * 29 * 480) + 8 * 22 * 480
+    assert nb.value == max(8 * (5 * 48 * 15 + 5 * 48 * 10), 8 * 16 * 480) + 8 * (21 + 22) * 480
     P = lambda *a: (C.c_void_p * 2)(*[C.c_void_p(v) for v in a])         # noqa: E731
     q, s, j = P(0x100000, 0x200000), P(0x300000, 0x400000), P(0x500000, 0x600000)
     w = C.c_void_p(0x900000)
@@ -426,7 +428,7 @@ def test_ns_blocks_bad_arguments():
     nbr = (C.c_int32 * 12)(1, 1, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1)
     nb = C.c_size_t()
     assert L.cfd_wcns5_ns_blocks_work_bytes(2, dims, nbr, C.byref(nb)) == 0
-    assert nb.value == max(8 * (5 * 48 * 15 + 5 * 48 * 10), 8 * 29 * 480) + 8 * 10 * 480
+    assert nb.value == max(8 * (5 * 48 * 15 + 5 * 48 * 10), 8 * 16 * 480) + 8 * (10 + 21) * 480
     P = lambda *a: (C.c_void_p * 2)(*[C.c_void_p(v) for v in a])         # noqa: E731
     q, s, j = P(0x100000, 0x200000), P(0x300000, 0x400000), P(0x500000, 0x600000)
     w = C.c_void_p(0x900000)
