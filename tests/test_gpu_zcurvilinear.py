@@ -422,6 +422,51 @@ def test_ns_steps_on_split_blocks_match_the_unsplit_block(n, cuts):
         assert np.max(np.abs(g.cpu().numpy() - w)) <= 1e-12 * top
 
 
+def test_marching_passes_match_the_three_pass_path_at_full_size():
+    """At 256 x 128 x 128 the unsplit block's inviscid residual runs its j and
+    k directions as one marching pass each (primitives, WCNS-E-5 face states,
+    Roe's flux and Eq. 2 in registers); its 2 x 2 x 2 split into 128 x 64 x 64
+    blocks has too few lines for the march and runs the padded-primitive, face
+    and Eq. 2 passes.  The residuals, the residuals with the viscous terms and
+    two RK3 Navier-Stokes steps are bitwise the same on both, and a uniform
+    stream keeps R within 1e-10 of its flux scale."""
+    import torch
+    from paper_1710_09995_amd.binding import (c4_viscous_add_blocks, c4_viscous_add_curv_periodic,
+                                              wcns5_euler_residual_blocks, wcns5_euler_residual_curv_periodic,
+                                              wcns5_metrics_periodic, wcns5_ns_steps_blocks,
+                                              wcns5_ns_steps_curv_periodic)
+    from test_oracle_highorder import _split_box
+    n = (256, 128, 128)
+    say("marching passes vs three-pass blocks", n)
+    Xv, P = _curv_grid(n, "wavy")
+    S, J = wcns5_metrics_periodic(torch.from_numpy(Xv).cuda(), P)
+    del Xv
+    qt = torch.from_numpy(_smooth_state(n, seed=23)).cuda()
+    lo, m, nbr = _split_box(n, ([128], [64], [64]))
+    sls = [(slice(o[2], o[2] + e[2]), slice(o[1], o[1] + e[1]), slice(o[0], o[0] + e[0])) for o, e in zip(lo, m)]
+    qs = [qt[(slice(None),) + sl].contiguous() for sl in sls]
+    Ss = [S[(slice(None), slice(None)) + sl].contiguous() for sl in sls]
+    Js = [J[sl].contiguous() for sl in sls]
+    whole = wcns5_euler_residual_curv_periodic(qt, S, J)
+    parts = wcns5_euler_residual_blocks(qs, Ss, Js, nbr)
+    assert all(torch.equal(p, whole[(slice(None),) + sl]) for sl, p in zip(sls, parts))
+    whole = c4_viscous_add_curv_periodic(qt, whole, S, J, 1.4, 0.72, 0.02, 0.38)
+    parts = c4_viscous_add_blocks(qs, parts, Ss, Js, nbr, 1.4, 0.72, 0.02, 0.38)
+    assert all(torch.equal(p, whole[(slice(None),) + sl]) for sl, p in zip(sls, parts))
+    del whole, parts
+    steps_whole = wcns5_ns_steps_curv_periodic(qt.clone(), S, J, 1e-4, 2, 1.4, 0.1, 1e-6, 0.72, 0.02, 0.38)
+    steps_parts = wcns5_ns_steps_blocks([t.clone() for t in qs], Ss, Js, nbr, 1e-4, 2, 1.4, 0.1, 1e-6, 0.72, 0.02,
+                                        0.38)
+    assert all(torch.equal(p, steps_whole[(slice(None),) + sl]) for sl, p in zip(sls, steps_parts))
+    del steps_whole, steps_parts
+    u = torch.empty_like(qt)
+    u[0], u[1], u[2], u[3] = 1.0, 0.5, -0.2, 0.3
+    u[4] = 1.0 / 0.4 + 0.5 * (0.25 + 0.04 + 0.09)
+    R = wcns5_euler_residual_curv_periodic(u, S, J)
+    scale = float(torch.max(torch.abs(S))) * 3.0 / float(torch.min(torch.abs(J)))
+    assert float(torch.max(torch.abs(R))) <= 1e-10 * scale
+
+
 def test_viscous_implicit_steps_on_split_blocks_match_the_unsplit_block():
     """The 12-block split with viscous terms: 2 implicit Navier-Stokes steps
     with 4 sweeps on the blocks are bitwise the unsplit block's on the device,
