@@ -652,7 +652,9 @@ cfd_status cfd_wcns5_ns_steps_blocks(int32_t nblk, const int32_t* dims, const in
  * `bounded`).  Closures are applied in list order; a block may be the ghost
  * block of one closure only, and the owner of a closure may be the ghost
  * block of an earlier one (corners), not of a later one.  The ghost blocks'
- * own states after a call are scratch.  Asynchronous on stream. */
+ * own states after a call are scratch: being refilled before every stage,
+ * they skip their own faces, differences and updates.  Asynchronous on
+ * stream. */
 #define CFD_WCNS5_GHOST 5
 #define CFD_WCNS5_XLAYERS 7
 typedef struct {

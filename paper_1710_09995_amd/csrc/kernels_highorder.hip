@@ -1478,13 +1478,15 @@ namespace cfd {
 // The residual of blocks joined face to face (arguments checked by the caller).
 void wcns5_blocks_residual_launch(int32_t nblk, const int32_t* dims, const int32_t* nbr, const double* const* q_dev,
                                   const double* const* s_dev, const double* const* jinv_dev, double* const* r_dev,
-                                  void* work_dev, double gamma, double entropy_fix, double eps, hipStream_t stream) {
+                                  void* work_dev, double gamma, double entropy_fix, double eps, hipStream_t stream,
+                                  const char* skip = nullptr) {
   Gas<double> gas{};
   gas.gamma = gamma;
   gas.gm1 = gamma - 1.0;
   gas.gg = gamma / (gamma - 1.0);
   gas.eps_h = entropy_fix;
   for (int b = 0; b < nblk; ++b) {
+    if (skip && skip[b]) continue;   // a block whose residual nobody reads (a refilled ghost block)
     const int32_t* n = dims + 3 * b;
     int64_t pmax, fmax;
     wcns5_work(n, pmax, fmax);
@@ -1964,7 +1966,8 @@ void c4_face_metrics_blocks(int32_t nblk, const int32_t* dims, const int32_t* nb
 // face metrics from c4_face_metrics_blocks).
 void c4_viscous_blocks_launch(int32_t nblk, const int32_t* dims, const int32_t* nbr, const double* const* q_dev,
                               const double* const* s_dev, const double* const* jinv_dev, double* const* r_dev,
-                              double* W, const double* FM, const Gas<double>& gas, hipStream_t stream) {
+                              double* W, const double* FM, const Gas<double>& gas, hipStream_t stream,
+                              const char* skip = nullptr) {
   const std::vector<int64_t> off = field_offsets(nblk, dims, VW_FIELDS), offm = field_offsets(nblk, dims, FM_FIELDS);
   std::vector<const double*> wb(nblk), fb(nblk);
   for (int b = 0; b < nblk; ++b) {
@@ -1983,6 +1986,7 @@ void c4_viscous_blocks_launch(int32_t nblk, const int32_t* dims, const int32_t* 
                          block_line(b, t, dims, nbr, wb.data()), W + off[b] + VW_G * cb, D, t);
   }
   for (int b = 0; b < nblk; ++b) {
+    if (skip && skip[b]) continue;   // its u, v, w, T and gradients still serve the neighbours' stencils
     Line PG[3], FL[3], S[3];
     for (int d = 0; d < 3; ++d) {
       PG[d] = block_line(b, d, dims, nbr, wb.data());
@@ -2722,11 +2726,15 @@ cfd_status ns_steps_blocks_impl(int32_t nblk, const int32_t* dims, const int32_t
     if (!(dt > 0.0) || !std::isfinite(dt)) cfd::host_fail(CFD_EINVAL, "dt must be positive and finite");
     if (nsteps < 0) cfd::host_fail(CFD_EINVAL, "nsteps must be >= 0");
     if (nclosures < 0 || (nclosures > 0 && !closures)) cfd::host_fail(CFD_EINVAL, "bad closure list");
+    // ghost blocks: refilled from their owners before every stage, so their
+    // own residual and update are never read (their states after a call are
+    // scratch) and are skipped
+    std::vector<char> ghost(nblk, 0);
     if (nclosures > 0) {
       // a block is the ghost block of at most one closure; an owner may be the
       // ghost block of an earlier closure (corner blocks filled from a face's
       // ghost block), never of a later one (it would be read before written)
-      std::vector<char> ghost(nblk, 0), owner(nblk, 0);
+      std::vector<char> owner(nblk, 0);
       for (int c = 0; c < nclosures; ++c) {
         const cfd_wcns5_closure& cl = closures[c];
         check_closure(nblk, dims, nbr, cl);
@@ -2775,11 +2783,12 @@ cfd_status ns_steps_blocks_impl(int32_t nblk, const int32_t* dims, const int32_t
                                         stream);
         }
         cfd::wcns5_blocks_residual_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, R.data(), work_dev, gamma,
-                                          entropy_fix, eps, stream);
+                                          entropy_fix, eps, stream, ghost.data());
         if (viscous)
           cfd::c4_viscous_blocks_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, R.data(),
-                                        static_cast<double*>(work_dev), FM, vgas, stream);
+                                        static_cast<double*>(work_dev), FM, vgas, stream, ghost.data());
         for (int b = 0; b < nblk; ++b) {
+          if (ghost[b]) continue;
           const int64_t nv = 5 * block_cells(dims, b);
           hipLaunchKernelGGL(cfd::k_rk3_stage, dim3(cfd::grid_for(nv)), dim3(256), 0, stream, q_dev[b], qn[b], R[b],
                              nv, dt, a[st], bb[st], st == 0 ? 1 : 0);
