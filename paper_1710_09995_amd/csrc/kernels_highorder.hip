@@ -1030,9 +1030,22 @@ Gas<double> viscous_gas(double gamma, double prandtl, double mu_inf, double s_st
 constexpr int VW_FIELDS = 16, FM_FIELDS = 21;
 void c4_face_metrics_curv(const double* s_dev, const double* jinv_dev, double* sc_tmp, double* fm, const int32_t n[3],
                           hipStream_t stream);
+// The RK3 stage a Q^n + b (Q^(s-1) - dt R) of Eqs. 4-6 for a pass that
+// applies it (keep: the first stage, which saves Q^n).
+struct RkArgs {
+  double* q;
+  double* qn;
+  double dt, a, b;
+  int keep;
+};
+// Whether a block's last viscous pass applies the RK3 stage itself: only where
+// its k march runs whole 32-cell chunks (on 128 x 64 x 64 blocks, with 8-cell
+// chunks, the fused update measured 3 % slower per step than a separate pass).
+int visc_chunk(const int n[3], int d);
+inline bool rk_fused(const int n[3]) { return visc_chunk(n, 2) >= 32; }
 void c4_viscous_curv_core(const double* q_dev, const double* s_dev, const double* jinv_dev, double* r_dev,
                           double* work, const double* fm, const int32_t n[3], const Gas<double>& gas,
-                          hipStream_t stream);
+                          hipStream_t stream, const RkArgs* rk = nullptr);
 // Bytes of a periodic block's residual-or-viscous scratch followed by its
 // face metrics (the metrics start at visc_fm_offset).
 size_t visc_fm_offset(size_t rw0, int64_t cells) { return std::max(rw0, (size_t)8 * VW_FIELDS * cells); }
@@ -1066,9 +1079,14 @@ void wcns5_steps_core(double* q_dev, const double* s_dev, const double* jinv_dev
   for (int it = 0; it < nsteps; ++it)
     for (int st = 0; st < 3; ++st) {
       wcns5_residual_core(q_dev, s_dev, jinv_dev, r, work_dev, rw0, n, h, gamma, entropy_fix, eps, stream);
-      if (visc) c4_viscous_curv_core(q_dev, s_dev, jinv_dev, r, static_cast<double*>(work_dev), fm, n, *visc, stream);
-      hipLaunchKernelGGL(k_rk3_stage, dim3(g), dim3(256), 0, stream, q_dev, qn, r, nv, dt, a[st], b[st],
-                         st == 0 ? 1 : 0);
+      if (visc && rk_fused(n)) {   // the last viscous pass applies the stage
+        const RkArgs K{q_dev, qn, dt, a[st], b[st], st == 0 ? 1 : 0};
+        c4_viscous_curv_core(q_dev, s_dev, jinv_dev, r, static_cast<double*>(work_dev), fm, n, *visc, stream, &K);
+      } else {
+        if (visc) c4_viscous_curv_core(q_dev, s_dev, jinv_dev, r, static_cast<double*>(work_dev), fm, n, *visc, stream);
+        hipLaunchKernelGGL(k_rk3_stage, dim3(g), dim3(256), 0, stream, q_dev, qn, r, nv, dt, a[st], b[st],
+                           st == 0 ? 1 : 0);
+      }
     }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) host_fail(CFD_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -1724,16 +1742,46 @@ __device__ __forceinline__ void visc_flux_sub(double* __restrict__ r, const doub
   }
 }
 
+// The RK3 stage of Eqs. 4-6 applied by the last viscous pass of a step's
+// stage, cell by cell, once its residual is complete (nothing reads the
+// state after that pass; RkArgs: Q^(s) = a Q^n + b (Q^(s-1) - dt R), Q^n
+// kept from Q by the first stage).  The residual itself is not stored.
+
+__device__ __forceinline__ void visc_flux_sub_rk(const double* __restrict__ r, const double* __restrict__ jinv,
+                                                 int64_t cells, int64_t c, const double* Fm2, const double* Fm1,
+                                                 const double* F0, const double* Fp1, const RkArgs& K) {
+  const double ji = jinv[c];
+  double R[5];
+  R[0] = r[c];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double dF = (Fm2[v] - 27.0 * Fm1[v] + 27.0 * F0[v] - Fp1[v]) * (1.0 / 24.0);
+    R[1 + v] = r[(1 + v) * cells + c] - dF / ji;
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const int64_t t = v * cells + c;
+    const double x = K.q[t], y = R[v];
+    const double s = x - K.dt * y;
+    if (K.keep) {
+      K.qn[t] = x;
+      K.q[t] = s;
+    } else {
+      K.q[t] = K.a * K.qn[t] + K.b * s;
+    }
+  }
+}
+
 // The viscous terms along d = 1 or 2 added into r: each thread marches one
 // line of cells along d (lanes along i, so every load is a coalesced row)
 // over a chunk of `chunk` cells, keeping the four cells around the current
 // face and the last four face fluxes in registers: each cell's inputs are
 // loaded once per chunk instead of once per face stencil, and the face
 // fluxes never leave the chip.
-template <int D>
+template <int D, bool RK>
 __global__ void __launch_bounds__(256) k_c4_visc_march(Line PG, Line FM, Line S, double* __restrict__ r,
                                                        const double* __restrict__ jinv, Dims3 Dm, int chunk,
-                                                       Gas<double> gas) {
+                                                       Gas<double> gas, RkArgs K) {
   constexpr int O = D == 1 ? 2 : 1;
   const int* n = Dm.n;
   const int nD = n[D], nO = n[O], n0 = n[0];
@@ -1766,7 +1814,10 @@ __global__ void __launch_bounds__(256) k_c4_visc_march(Line PG, Line FM, Line S,
     if (g <= x1) {                                                                \
       load_visc_cell<D>(PG, c0, g + 2, n, E);                                     \
       visc_face_at<D>(FM, S, c0, g, n, A, B, C, E, gas, FN);                      \
-      if (g > x0) visc_flux_sub(r, jinv, cells, cell_index(g - 1), FA, FB, FC, FN); \
+      if (g > x0) {                                                               \
+        if constexpr (RK) visc_flux_sub_rk(r, jinv, cells, cell_index(g - 1), FA, FB, FC, FN, K); \
+        else visc_flux_sub(r, jinv, cells, cell_index(g - 1), FA, FB, FC, FN);   \
+      }                                                                           \
     }                                                                             \
   }
     for (int f = x0 - 2; f <= x1; f += 4) {
@@ -1861,19 +1912,26 @@ int visc_chunk(const int n[3], int d) {
 }
 
 // The fused viscous passes of one block (lines built by the caller): i rows,
-// then the j and k marches, each subtracting its differences from r.
+// then the j and k marches, each subtracting its differences from r; with
+// rk (not NULL) the k march applies the RK3 stage to the block's state
+// instead of storing the finished residual.
 void visc_fused_launch(const Line* PG, const Line* FM, const Line* S, double* r, const double* jinv, const int n[3],
-                       const Gas<double>& gas, hipStream_t stream) {
+                       const Gas<double>& gas, hipStream_t stream, const RkArgs* rk = nullptr) {
   const Dims3 D{{n[0], n[1], n[2]}};
   const int64_t rows = (int64_t)n[1] * n[2] * ((n[0] + 63) / 64);
   const int grows = (int)std::min<int64_t>((rows + 3) / 4, 1 << 16);
   hipLaunchKernelGGL(k_c4_visc_rows, dim3(grows), dim3(256), 0, stream, PG[0], FM[0], S[0], r, jinv, D, gas);
   const int c1 = visc_chunk(n, 1), c2 = visc_chunk(n, 2);
   const int64_t t1 = (int64_t)n[0] * n[2] * ((n[1] + c1 - 1) / c1), t2 = (int64_t)n[0] * n[1] * ((n[2] + c2 - 1) / c2);
-  hipLaunchKernelGGL(k_c4_visc_march<1>, dim3(grid_for(t1)), dim3(256), 0, stream, PG[1], FM[1], S[1], r, jinv, D, c1,
-                     gas);
-  hipLaunchKernelGGL(k_c4_visc_march<2>, dim3(grid_for(t2)), dim3(256), 0, stream, PG[2], FM[2], S[2], r, jinv, D, c2,
-                     gas);
+  const RkArgs none{};
+  hipLaunchKernelGGL((k_c4_visc_march<1, false>), dim3(grid_for(t1)), dim3(256), 0, stream, PG[1], FM[1], S[1], r, jinv,
+                     D, c1, gas, none);
+  if (rk)
+    hipLaunchKernelGGL((k_c4_visc_march<2, true>), dim3(grid_for(t2)), dim3(256), 0, stream, PG[2], FM[2], S[2], r,
+                       jinv, D, c2, gas, *rk);
+  else
+    hipLaunchKernelGGL((k_c4_visc_march<2, false>), dim3(grid_for(t2)), dim3(256), 0, stream, PG[2], FM[2], S[2], r,
+                       jinv, D, c2, gas, none);
 }
 
 // A periodic block's lines: every neighbour the block itself.
@@ -1895,7 +1953,7 @@ void c4_face_metrics_curv(const double* s_dev, const double* jinv_dev, double* s
 // and gradients, 16 doubles per cell; fm: its face metrics).
 void c4_viscous_curv_core(const double* q_dev, const double* s_dev, const double* jinv_dev, double* r_dev,
                           double* work, const double* fm, const int32_t n[3], const Gas<double>& gas,
-                          hipStream_t stream) {
+                          hipStream_t stream, const RkArgs* rk) {
   const int64_t cells = (int64_t)n[0] * n[1] * n[2];
   double* phi = work;
   double* g = phi + 4 * cells;
@@ -1909,7 +1967,7 @@ void c4_viscous_curv_core(const double* q_dev, const double* s_dev, const double
     FM[d] = self_line(fm, cells, n[d]);
     S[d] = self_line(s_dev, cells, n[d]);
   }
-  visc_fused_launch(PG, FM, S, r_dev, jinv_dev, n, gas, stream);
+  visc_fused_launch(PG, FM, S, r_dev, jinv_dev, n, gas, stream, rk);
 }
 
 }  // namespace cfd
@@ -1967,7 +2025,7 @@ void c4_face_metrics_blocks(int32_t nblk, const int32_t* dims, const int32_t* nb
 void c4_viscous_blocks_launch(int32_t nblk, const int32_t* dims, const int32_t* nbr, const double* const* q_dev,
                               const double* const* s_dev, const double* const* jinv_dev, double* const* r_dev,
                               double* W, const double* FM, const Gas<double>& gas, hipStream_t stream,
-                              const char* skip = nullptr) {
+                              const char* skip = nullptr, const RkArgs* rk = nullptr) {
   const std::vector<int64_t> off = field_offsets(nblk, dims, VW_FIELDS), offm = field_offsets(nblk, dims, FM_FIELDS);
   std::vector<const double*> wb(nblk), fb(nblk);
   for (int b = 0; b < nblk; ++b) {
@@ -1993,7 +2051,7 @@ void c4_viscous_blocks_launch(int32_t nblk, const int32_t* dims, const int32_t* 
       FL[d] = block_line(b, d, dims, nbr, fb.data());
       S[d] = block_line(b, d, dims, nbr, s_dev);
     }
-    visc_fused_launch(PG, FL, S, r_dev[b], jinv_dev[b], dims + 3 * b, gas, stream);
+    visc_fused_launch(PG, FL, S, r_dev[b], jinv_dev[b], dims + 3 * b, gas, stream, rk && rk[b].q ? rk + b : nullptr);
   }
 }
 
@@ -2784,11 +2842,16 @@ cfd_status ns_steps_blocks_impl(int32_t nblk, const int32_t* dims, const int32_t
         }
         cfd::wcns5_blocks_residual_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, R.data(), work_dev, gamma,
                                           entropy_fix, eps, stream, ghost.data());
+        // the last viscous pass of a large block applies the stage (K[b].q set)
+        std::vector<cfd::RkArgs> K(nblk);
+        for (int b = 0; b < nblk; ++b)
+          if (viscous && cfd::rk_fused(dims + 3 * b))
+            K[b] = cfd::RkArgs{q_dev[b], qn[b], dt, a[st], bb[st], st == 0 ? 1 : 0};
         if (viscous)
           cfd::c4_viscous_blocks_launch(nblk, dims, nbr, q_dev, s_dev, jinv_dev, R.data(),
-                                        static_cast<double*>(work_dev), FM, vgas, stream, ghost.data());
+                                        static_cast<double*>(work_dev), FM, vgas, stream, ghost.data(), K.data());
         for (int b = 0; b < nblk; ++b) {
-          if (ghost[b]) continue;
+          if (ghost[b] || K[b].q) continue;
           const int64_t nv = 5 * block_cells(dims, b);
           hipLaunchKernelGGL(cfd::k_rk3_stage, dim3(cfd::grid_for(nv)), dim3(256), 0, stream, q_dev[b], qn[b], R[b],
                              nv, dt, a[st], bb[st], st == 0 ? 1 : 0);
