@@ -1587,18 +1587,86 @@ extern "C" cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_
 // neighbours along d.  The arithmetic is that of the periodic kernels.
 namespace cfd {
 
-// g[(a * 3 + t) * cells + c] = index derivative of phi_a along t.
-__global__ void __launch_bounds__(256) k_c4_grads_line(Line phi, double* __restrict__ g, Dims3 D, int t) {
+// Index derivatives of u, v, w, T along i (one thread per cell; the four
+// neighbours share its cache lines), g[(a * 3 + 0) * cells + c].
+__global__ void __launch_bounds__(256) k_c4_grads_i(Line phi, double* __restrict__ g, Dims3 D) {
   const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(c % D.n[0]), j = (int)((c / D.n[0]) % D.n[1]), k = (int)(c / ((int64_t)D.n[0] * D.n[1]));
-    const LineRef rm2 = line_ref(phi, i, j, k, -2, t, D.n), rm1 = line_ref(phi, i, j, k, -1, t, D.n),
-                  rp1 = line_ref(phi, i, j, k, 1, t, D.n), rp2 = line_ref(phi, i, j, k, 2, t, D.n);
+    const int p[3] = {(int)(c % D.n[0]), (int)((c / D.n[0]) % D.n[1]), (int)(c / ((int64_t)D.n[0] * D.n[1]))};
+    const LineRef rm2 = wrap_ref(phi, p, p[0] - 2, 0, D.n), rm1 = wrap_ref(phi, p, p[0] - 1, 0, D.n),
+                  rp1 = wrap_ref(phi, p, p[0] + 1, 0, D.n), rp2 = wrap_ref(phi, p, p[0] + 2, 0, D.n);
+#pragma unroll
     for (int a = 0; a < 4; ++a) {
       const double m2 = rm2[a], m1 = rm1[a], p1 = rp1[a], p2 = rp2[a];
-      g[(a * 3 + t) * cells + c] = (m2 - 8.0 * m1 + 8.0 * p1 - p2) * (1.0 / 12.0);
+      g[(a * 3) * cells + c] = (m2 - 8.0 * m1 + 8.0 * p1 - p2) * (1.0 / 12.0);
     }
   }
+}
+
+// The same along j or k: each lane marches a line of cells (lanes along i,
+// coalesced rows) over a chunk, keeping five cells of u, v, w, T in registers,
+// so every cell is read once per chunk instead of four times from other rows
+// or planes.
+template <int D>
+__global__ void __launch_bounds__(256) k_c4_grads_march(Line phi, double* __restrict__ g, Dims3 Dm, int chunk) {
+  constexpr int O = D == 1 ? 2 : 1;
+  const int* n = Dm.n;
+  const int nD = n[D], nO = n[O], n0 = n[0];
+  const int nch = (nD + chunk - 1) / chunk;
+  const int64_t cells = (int64_t)n0 * n[1] * n[2];
+  const int64_t total = (int64_t)n0 * nO * nch;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    int c0[3];
+    c0[0] = (int)(t % n0);
+    const int64_t rest = t / n0;
+    c0[O] = (int)(rest % nO);
+    c0[D] = 0;
+    const int x0 = (int)(rest / nO) * chunk, x1 = min(x0 + chunk, nD);
+    double w[5][4];
+    auto load = [&](int x, double* v) {
+      const LineRef r = wrap_ref(phi, c0, x, D, n);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) v[a] = r[a];
+    };
+#pragma unroll
+    for (int k = 1; k < 5; ++k) load(x0 - 3 + k, w[k]);
+    for (int x = x0; x < x1; ++x) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) w[k][a] = w[k + 1][a];
+      load(x + 2, w[4]);
+      int p[3] = {c0[0], c0[1], c0[2]};
+      p[D] = x;
+      const int64_t c = ((int64_t)p[2] * n[1] + p[1]) * n0 + p[0];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const double m2 = w[0][a], m1 = w[1][a], p1 = w[3][a], p2 = w[4][a];
+        g[(a * 3 + D) * cells + c] = (m2 - 8.0 * m1 + 8.0 * p1 - p2) * (1.0 / 12.0);
+      }
+    }
+  }
+}
+
+// Chunk of the gradient marches: 32 cells, halved (down to 8) while the grid
+// gives fewer than 128 k threads.
+int grads_chunk(const int n[3], int d) {
+  const int o = d == 1 ? 2 : 1;
+  int chunk = 32;
+  while (chunk > 8 && (int64_t)n[0] * n[o] * ((n[d] + chunk - 1) / chunk) < (int64_t)1 << 17) chunk /= 2;
+  return chunk;
+}
+
+// The index derivatives of a block's u, v, w, T (lines P[d] over its phi
+// fields and the neighbours') into g (12 fields).
+void grads_launch(const Line* P, double* g, const int n[3], hipStream_t stream) {
+  const Dims3 D{{n[0], n[1], n[2]}};
+  const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+  hipLaunchKernelGGL(k_c4_grads_i, dim3(grid_for(cells)), dim3(256), 0, stream, P[0], g, D);
+  const int c1 = grads_chunk(n, 1), c2 = grads_chunk(n, 2);
+  const int64_t t1 = (int64_t)n[0] * n[2] * ((n[1] + c1 - 1) / c1), t2 = (int64_t)n[0] * n[1] * ((n[2] + c2 - 1) / c2);
+  hipLaunchKernelGGL(k_c4_grads_march<1>, dim3(grid_for(t1)), dim3(256), 0, stream, P[1], g, D, c1);
+  hipLaunchKernelGGL(k_c4_grads_march<2>, dim3(grid_for(t2)), dim3(256), 0, stream, P[2], g, D, c2);
 }
 
 // sc[(t * 3 + x) * cells + c]: S_t at the cells from its faces along t.
@@ -1957,16 +2025,14 @@ void c4_viscous_curv_core(const double* q_dev, const double* s_dev, const double
   const int64_t cells = (int64_t)n[0] * n[1] * n[2];
   double* phi = work;
   double* g = phi + 4 * cells;
-  const Cells3 C{{n[0], n[1], n[2]}};
-  const int gr = grid_for(cells);
-  hipLaunchKernelGGL(k_c4_phi, dim3(gr), dim3(256), 0, stream, q_dev, phi, cells, gas.gm1);
-  hipLaunchKernelGGL(k_c4_grads, dim3(gr), dim3(256), 0, stream, phi, g, C, 1.0, 1.0, 1.0);
+  hipLaunchKernelGGL(k_c4_phi, dim3(grid_for(cells)), dim3(256), 0, stream, q_dev, phi, cells, gas.gm1);
   Line PG[3], FM[3], S[3];
   for (int d = 0; d < 3; ++d) {
     PG[d] = self_line(work, cells, n[d]);
     FM[d] = self_line(fm, cells, n[d]);
     S[d] = self_line(s_dev, cells, n[d]);
   }
+  grads_launch(PG, g, n, stream);
   visc_fused_launch(PG, FM, S, r_dev, jinv_dev, n, gas, stream, rk);
 }
 
@@ -2038,10 +2104,9 @@ void c4_viscous_blocks_launch(int32_t nblk, const int32_t* dims, const int32_t* 
   }
   for (int b = 0; b < nblk; ++b) {
     const int64_t cb = block_cells(dims, b);
-    const Dims3 D{{dims[3 * b], dims[3 * b + 1], dims[3 * b + 2]}};
-    for (int t = 0; t < 3; ++t)
-      hipLaunchKernelGGL(k_c4_grads_line, dim3(grid_for(cb)), dim3(256), 0, stream,
-                         block_line(b, t, dims, nbr, wb.data()), W + off[b] + VW_G * cb, D, t);
+    const Line P[3] = {block_line(b, 0, dims, nbr, wb.data()), block_line(b, 1, dims, nbr, wb.data()),
+                       block_line(b, 2, dims, nbr, wb.data())};
+    grads_launch(P, W + off[b] + VW_G * cb, dims + 3 * b, stream);
   }
   for (int b = 0; b < nblk; ++b) {
     if (skip && skip[b]) continue;   // its u, v, w, T and gradients still serve the neighbours' stencils
