@@ -828,6 +828,107 @@ void euler_march_launch(const Line& Q, const Line& S, double* r, const double* j
   else hipLaunchKernelGGL((k_wcns5_euler_march<2, 2>), g, b, 0, stream, Q, S, r, jinv, D, ch, eps, c1, c2, c3, gas);
 }
 
+// The inviscid residual along i in one pass: each wave takes a segment of 59
+// cells of a row, converts the 69 cells around it to primitives into LDS
+// (coalesced along i), computes the segment's 64 face fluxes, one per lane,
+// into LDS, then stores Eq. 2 of each cell into R (the first direction).  The
+// arithmetic is that of k_pad_prim_*, k_wcns5_roe_faces and the Eq. 2 pass.
+constexpr int EROW_SEG = 59, EROW_CELLS = EROW_SEG + 10, EROW_FACES = EROW_SEG + 5;
+
+__global__ void __launch_bounds__(256) k_wcns5_euler_rows(Line Q, Line S, double* __restrict__ r, Dims3 Dm,
+                                                          double eps, double c1, double c2, double c3,
+                                                          Gas<double> gas) {
+  __shared__ double sp[4][5][EROW_CELLS + 3];
+  __shared__ double sf[4][5][EROW_FACES];
+  const int* n = Dm.n;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nseg = (n[0] + EROW_SEG - 1) / EROW_SEG;
+  const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+  const int64_t items = (int64_t)n[1] * n[2] * nseg;
+  for (int64_t base = (int64_t)blockIdx.x * 4; base < items; base += (int64_t)gridDim.x * 4) {
+    const int64_t it = base + w;
+    const bool act = it < items;
+    int c0[3] = {0, 0, 0}, x0 = 0, x1 = 0;
+    if (act) {
+      const int64_t row = it / nseg;
+      x0 = (int)(it % nseg) * EROW_SEG;
+      x1 = min(x0 + EROW_SEG, n[0]);
+      c0[1] = (int)(row % n[1]);
+      c0[2] = (int)(row / n[1]);
+      for (int e = lane; e < EROW_CELLS; e += 64) {
+        const int x = x0 - 5 + e;
+        if (x <= x1 + 4) {
+          const LineRef q = wrap_ref(Q, c0, x, 0, n);
+          const Prim<double> p = to_prim<double>(q[0], q[1], q[2], q[3], q[4], gas.gm1);
+          sp[w][0][e] = p.r;
+          sp[w][1][e] = p.u;
+          sp[w][2][e] = p.v;
+          sp[w][3][e] = p.w;
+          sp[w][4][e] = p.p;
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+      const int v = x0 - 3 + lane;   // face between cells v and v + 1: cells v - 2 .. v + 3 at lane .. lane + 5
+      if (v <= x1 + 1) {
+        double L[5], R[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const double* u = &sp[w][q][lane];
+          L[q] = wcns5_left(u[0], u[1], u[2], u[3], u[4], eps);
+          R[q] = wcns5_left(u[5], u[4], u[3], u[2], u[1], eps);
+        }
+        const Prim<double> PL{L[0], L[1], L[2], L[3], L[4]};
+        const Prim<double> PR{R[0], R[1], R[2], R[3], R[4]};
+        double fl[5];
+        if (!S.own) {
+          roe<double>(PL, PR, 1.0, 0.0, 0.0, gas, fl);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) sf[w][q][lane] = fl[q];
+        } else {
+          const LineRef sr = wrap_ref(S, c0, v, 0, n);
+          const double sx = sr[0], sy = sr[1], sz = sr[2];
+          const double area = fsqrt(sx * sx + sy * sy + sz * sz);
+          const double ia = frcp(area);
+          roe<double>(PL, PR, sx * ia, sy * ia, sz * ia, gas, fl);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) sf[w][q][lane] = fl[q] * area;
+        }
+      }
+    }
+    __syncthreads();
+    if (act && lane < EROW_SEG) {
+      const int x = x0 + lane;   // faces x - 3 .. x + 2 at lane .. lane + 5
+      if (x < x1) {
+        const int64_t c = ((int64_t)c0[2] * n[1] + c0[1]) * n[0] + x;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const double* F = &sf[w][q][lane];
+          r[q * cells + c] = c1 * (F[3] - F[2]) + c2 * (F[4] - F[1]) + c3 * (F[5] - F[0]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Rows of n cells leave idle lanes in the last segment's faces; the row pass
+// is used where its face slots stay within 1.25 times the n + 5 faces needed
+// (256- and 512-cell rows: 1.23, 1.11; 128 cells: 1.44).
+bool euler_rows_ok(int n0) {
+  const int64_t nseg = (n0 + EROW_SEG - 1) / EROW_SEG;
+  return nseg * 64 * 4 <= (int64_t)(n0 + 5) * 5;
+}
+
+void euler_rows_launch(const Line& Q, const Line& S, double* r, const int n[3], double eps, double c1, double c2,
+                       double c3, const Gas<double>& gas, hipStream_t stream) {
+  const Dims3 D{{n[0], n[1], n[2]}};
+  const int64_t items = (int64_t)n[1] * n[2] * ((n[0] + EROW_SEG - 1) / EROW_SEG);
+  const int grid = (int)std::min<int64_t>((items + 3) / 4, 1 << 16);
+  hipLaunchKernelGGL(k_wcns5_euler_rows, dim3(grid), dim3(256), 0, stream, Q, S, r, D, eps, c1, c2, c3, gas);
+}
+
 // The periodic WCNS-E-5 residual along the three directions.  Cartesian when
 // s is NULL (face normals e_d, Eq. (2) with the spacings h); else curvilinear:
 // Roe's flux through the face area vectors s, Eq. (2) in index units and a
@@ -860,6 +961,12 @@ void wcns5_residual_core(const double* q_dev, const double* s_dev, const double*
   for (int d = 0; d < 3; ++d) {
     const double hd = s_dev ? 1.0 : h[d];
     const double c1 = 75.0 / (64.0 * hd), c2 = -25.0 / (384.0 * hd), c3 = 3.0 / (640.0 * hd);
+    if (d == 0 && euler_rows_ok(n[0])) {   // i: one row pass
+      const Line Q{q_dev, q_dev, q_dev, cells, cells, cells, n[0], n[0]};
+      const Line S{s_dev, s_dev, s_dev, cells, cells, cells, n[0], n[0]};
+      euler_rows_launch(Q, S, r_dev, n, eps, c1, c2, c3, gas, stream);
+      continue;
+    }
     if (d > 0 && euler_march_ok(n, d)) {   // j and k: one marching pass (the last one divides the sum by J^{-1})
       const Line Q{q_dev, q_dev, q_dev, cells, cells, cells, n[d], n[d]};
       const Line S{s_dev, s_dev, s_dev, cells, cells, cells, n[d], n[d]};
@@ -1513,6 +1620,14 @@ void wcns5_blocks_residual_launch(int32_t nblk, const int32_t* dims, const int32
     for (int d = 0; d < 3; ++d) {
       const int lo = nbr[6 * b + 2 * d], hi = nbr[6 * b + 2 * d + 1];
       const int nlo = dims[3 * lo + d], nhi = dims[3 * hi + d];
+      if (d == 0 && euler_rows_ok(n[0])) {   // i: one row pass across the seams
+        const Line Q{q_dev[b], q_dev[lo], q_dev[hi], block_cells(dims, b), block_cells(dims, lo),
+                     block_cells(dims, hi), nlo, nhi};
+        const Line S{s_dev[b], s_dev[lo], s_dev[hi], block_cells(dims, b), block_cells(dims, lo),
+                     block_cells(dims, hi), nlo, nhi};
+        euler_rows_launch(Q, S, r_dev[b], n, eps, 75.0 / 64.0, -25.0 / 384.0, 3.0 / 640.0, gas, stream);
+        continue;
+      }
       if (d > 0 && euler_march_ok(n, d)) {   // j and k: one marching pass across the seams (the last divides by J^{-1})
         const Line Q{q_dev[b], q_dev[lo], q_dev[hi], block_cells(dims, b), block_cells(dims, lo),
                      block_cells(dims, hi), nlo, nhi};
