@@ -422,6 +422,26 @@ def test_ns_steps_on_split_blocks_match_the_unsplit_block(n, cuts):
         assert np.max(np.abs(g.cpu().numpy() - w)) <= 1e-12 * top
 
 
+@pytest.mark.parametrize("n", [(512, 128, 8), (512, 8, 128)])
+def test_row_and_marching_passes_match_the_oracle(n):
+    """The inviscid residual on blocks whose long rows take the i row pass and
+    whose lines along the thin direction (8 cells, one chunk) take a marching
+    pass, on the oracle's own metrics (at 512 cells per row, the few-ulp
+    differences between the two metric computations alone move R by some
+    1e-11 of max |R|), against the oracle within 1e-12 of max |R|."""
+    import torch
+    from paper_1710_09995_amd.binding import wcns5_euler_residual_curv_periodic
+    Xv, P = _curv_grid(n, "wavy")
+    say("row and marching passes", n)
+    So, Jo = ho.metrics6(ho.periodic_vertices(Xv, P))
+    q = _smooth_state(n, seed=sum(n) + 5)
+    got = wcns5_euler_residual_curv_periodic(torch.from_numpy(q).cuda(), _dev(So), _dev(Jo)).cpu().numpy()
+    want = ho.wcns5_euler_residual_curv_periodic(q, So, Jo, 1.4, 0.1)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    say(f"  max error / max|R| {err:.2e}")
+    assert err <= 1e-12
+
+
 def test_marching_passes_match_the_three_pass_path_at_full_size():
     """At 256 x 128 x 128 the unsplit block's inviscid residual runs its j and
     k directions as one marching pass each (primitives, WCNS-E-5 face states,
