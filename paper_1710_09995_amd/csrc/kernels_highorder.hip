@@ -1702,19 +1702,58 @@ extern "C" cfd_status cfd_wcns5_euler_residual_blocks(int32_t nblk, const int32_
 // neighbours along d.  The arithmetic is that of the periodic kernels.
 namespace cfd {
 
-// Index derivatives of u, v, w, T along i (one thread per cell; the four
-// neighbours share its cache lines), g[(a * 3 + 0) * cells + c].
-__global__ void __launch_bounds__(256) k_c4_grads_i(Line phi, double* __restrict__ g, Dims3 D) {
-  const int64_t cells = (int64_t)D.n[0] * D.n[1] * D.n[2];
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
-    const int p[3] = {(int)(c % D.n[0]), (int)((c / D.n[0]) % D.n[1]), (int)(c / ((int64_t)D.n[0] * D.n[1]))};
-    const LineRef rm2 = wrap_ref(phi, p, p[0] - 2, 0, D.n), rm1 = wrap_ref(phi, p, p[0] - 1, 0, D.n),
-                  rp1 = wrap_ref(phi, p, p[0] + 1, 0, D.n), rp2 = wrap_ref(phi, p, p[0] + 2, 0, D.n);
+// u, v, w, T of a block's cells (phi, 4 fields) and their index derivatives
+// along i (g[(a * 3 + 0) * cells + c]) in one pass: each wave takes 60 cells
+// of a row, converts the 64 cells around them (the neighbours' across the
+// i-faces included) in registers, keeps those in LDS for the derivatives, and
+// writes phi of its own 60 cells.
+constexpr int PGI_SEG = 60;
+
+__global__ void __launch_bounds__(256) k_c4_phi_grads_i(Line Q, double* __restrict__ phi, double* __restrict__ g,
+                                                        Dims3 Dm, double gm1) {
+  __shared__ double sp[4][4][64];
+  const int* n = Dm.n;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nseg = (n[0] + PGI_SEG - 1) / PGI_SEG;
+  const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+  const int64_t items = (int64_t)n[1] * n[2] * nseg;
+  for (int64_t base = (int64_t)blockIdx.x * 4; base < items; base += (int64_t)gridDim.x * 4) {
+    const int64_t it = base + w;
+    const bool act = it < items;
+    int c0[3] = {0, 0, 0}, x0 = 0, x1 = 0;
+    int64_t rb = 0;
+    if (act) {
+      const int64_t row = it / nseg;
+      x0 = (int)(it % nseg) * PGI_SEG;
+      x1 = min(x0 + PGI_SEG, n[0]);
+      c0[1] = (int)(row % n[1]);
+      c0[2] = (int)(row / n[1]);
+      rb = ((int64_t)c0[2] * n[1] + c0[1]) * n[0];
+      const int x = x0 - 2 + lane;   // cells x0 - 2 .. x0 + 61 at lanes 0 .. 63
+      if (x <= x1 + 1) {
+        const LineRef q = wrap_ref(Q, c0, x, 0, n);
+        const Prim<double> p = to_prim<double>(q[0], q[1], q[2], q[3], q[4], gm1);
+        const double f[4] = {p.u, p.v, p.w, p.p / p.r};
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const double m2 = rm2[a], m1 = rm1[a], p1 = rp1[a], p2 = rp2[a];
-      g[(a * 3) * cells + c] = (m2 - 8.0 * m1 + 8.0 * p1 - p2) * (1.0 / 12.0);
+        for (int a = 0; a < 4; ++a) sp[w][a][lane] = f[a];
+        if (x >= x0 && x < x1)
+#pragma unroll
+          for (int a = 0; a < 4; ++a) phi[a * cells + rb + x] = f[a];
+      }
     }
+    __syncthreads();
+    if (act && lane < PGI_SEG) {
+      const int x = x0 + lane;   // cells x - 2 .. x + 2 at lanes lane .. lane + 4
+      if (x < x1) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const double m2 = sp[w][a][lane], m1 = sp[w][a][lane + 1], p1 = sp[w][a][lane + 3],
+                       p2 = sp[w][a][lane + 4];
+          g[(a * 3) * cells + rb + x] = (m2 - 8.0 * m1 + 8.0 * p1 - p2) * (1.0 / 12.0);
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1772,12 +1811,19 @@ int grads_chunk(const int n[3], int d) {
   return chunk;
 }
 
-// The index derivatives of a block's u, v, w, T (lines P[d] over its phi
-// fields and the neighbours') into g (12 fields).
-void grads_launch(const Line* P, double* g, const int n[3], hipStream_t stream) {
+// phi and its index derivatives along i of a block (Qi: its state line along
+// i), into phi (4 fields) and g (12 fields).
+void phi_grads_i_launch(const Line& Qi, double* phi, double* g, const int n[3], double gm1, hipStream_t stream) {
   const Dims3 D{{n[0], n[1], n[2]}};
-  const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-  hipLaunchKernelGGL(k_c4_grads_i, dim3(grid_for(cells)), dim3(256), 0, stream, P[0], g, D);
+  const int64_t items = (int64_t)n[1] * n[2] * ((n[0] + PGI_SEG - 1) / PGI_SEG);
+  const int grid = (int)std::min<int64_t>((items + 3) / 4, 1 << 16);
+  hipLaunchKernelGGL(k_c4_phi_grads_i, dim3(grid), dim3(256), 0, stream, Qi, phi, g, D, gm1);
+}
+
+// The index derivatives along j and k of a block's u, v, w, T (lines P[d]
+// over its phi fields and the neighbours', which must all be written) into g.
+void grads_jk_launch(const Line* P, double* g, const int n[3], hipStream_t stream) {
+  const Dims3 D{{n[0], n[1], n[2]}};
   const int c1 = grads_chunk(n, 1), c2 = grads_chunk(n, 2);
   const int64_t t1 = (int64_t)n[0] * n[2] * ((n[1] + c1 - 1) / c1), t2 = (int64_t)n[0] * n[1] * ((n[2] + c2 - 1) / c2);
   hipLaunchKernelGGL(k_c4_grads_march<1>, dim3(grid_for(t1)), dim3(256), 0, stream, P[1], g, D, c1);
@@ -2140,14 +2186,14 @@ void c4_viscous_curv_core(const double* q_dev, const double* s_dev, const double
   const int64_t cells = (int64_t)n[0] * n[1] * n[2];
   double* phi = work;
   double* g = phi + 4 * cells;
-  hipLaunchKernelGGL(k_c4_phi, dim3(grid_for(cells)), dim3(256), 0, stream, q_dev, phi, cells, gas.gm1);
   Line PG[3], FM[3], S[3];
   for (int d = 0; d < 3; ++d) {
     PG[d] = self_line(work, cells, n[d]);
     FM[d] = self_line(fm, cells, n[d]);
     S[d] = self_line(s_dev, cells, n[d]);
   }
-  grads_launch(PG, g, n, stream);
+  phi_grads_i_launch(self_line(q_dev, cells, n[0]), phi, g, n, gas.gm1, stream);
+  grads_jk_launch(PG, g, n, stream);
   visc_fused_launch(PG, FM, S, r_dev, jinv_dev, n, gas, stream, rk);
 }
 
@@ -2215,13 +2261,14 @@ void c4_viscous_blocks_launch(int32_t nblk, const int32_t* dims, const int32_t* 
   }
   for (int b = 0; b < nblk; ++b) {
     const int64_t cb = block_cells(dims, b);
-    hipLaunchKernelGGL(k_c4_phi, dim3(grid_for(cb)), dim3(256), 0, stream, q_dev[b], W + off[b], cb, gas.gm1);
+    phi_grads_i_launch(block_line(b, 0, dims, nbr, q_dev), W + off[b], W + off[b] + VW_G * cb, dims + 3 * b, gas.gm1,
+                       stream);
   }
   for (int b = 0; b < nblk; ++b) {
     const int64_t cb = block_cells(dims, b);
     const Line P[3] = {block_line(b, 0, dims, nbr, wb.data()), block_line(b, 1, dims, nbr, wb.data()),
                        block_line(b, 2, dims, nbr, wb.data())};
-    grads_launch(P, W + off[b] + VW_G * cb, dims + 3 * b, stream);
+    grads_jk_launch(P, W + off[b] + VW_G * cb, dims + 3 * b, stream);
   }
   for (int b = 0; b < nblk; ++b) {
     if (skip && skip[b]) continue;   // its u, v, w, T and gradients still serve the neighbours' stencils
