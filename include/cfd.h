@@ -167,7 +167,10 @@ cfd_status cfd_residual(cfd_ctx* ctx, const double* q_arena_dev, double* r_arena
 /* Advance q_arena_dev by nsteps third-order Runge-Kutta steps (Eqs. 4-6,
  * lambda = -dt) with a ghost fill before every stage and the CFL time step
  * recomputed from Q^n at every step.  Ghost cells of q_arena_dev are
- * overwritten.  hist_dev (device, nullable) receives one row of 12 doubles
+ * overwritten.  For inviscid flow the fill covers every face's ghost layers
+ * over the face's own cells in one launch: the edge and corner ghost cells,
+ * which no inviscid stencil reads, keep their values (cfd_fill_ghosts fills
+ * them).  hist_dev (device, nullable) receives one row of 12 doubles
  * per step, all about the state at the start of that step:
  *   [dt, L2(R) x5, sum V Q x5, max|R_rho|],  L2(R_c) = sqrt(sum R_c^2 / N).
  * With local_dt, dt is the minimum of the per-cell steps. */

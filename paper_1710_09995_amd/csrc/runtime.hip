@@ -269,9 +269,11 @@ void validate_tables(int nblk, const cfd_dims* dims, int nconn, const cfd_conn* 
 }
 
 // Patch descriptors for sweep d (cells or nodes), with the transverse
-// extension into ghost layers of directions swept earlier.
+// extension into ghost layers of directions swept earlier (extend), or over
+// the face's own cells only.
 void build_patches(int d, bool nodes, const cfd_params* params, const cfd_dims* dims, int nconn,
-                   const cfd_conn* conns, int nbc, const cfd_bc* bcs, std::vector<PatchDesc>& out, int& maxcount) {
+                   const cfd_conn* conns, int nbc, const cfd_bc* bcs, std::vector<PatchDesc>& out, int& maxcount,
+                   bool extend = true) {
   auto make = [&](int blk, int face, int kind, int nbr, const int32_t lo[2], const int32_t hi[2],
                   const int32_t* nbr_lo, const double* shift, double mach) {
     PatchDesc P{};
@@ -293,7 +295,7 @@ void build_patches(int d, bool nodes, const cfd_params* params, const cfd_dims* 
       const int t = ts[a];
       int s = lo[a], e = hi[a];
       if (nodes && hi[a] == n[t]) e = n[t] + 1;
-      if (t < d) {
+      if (extend && t < d) {
         if (lo[a] == 0) s = -NG;
         if (hi[a] == n[t]) e = nodes ? n[t] + 1 + NG : n[t] + NG;
       }
@@ -331,6 +333,10 @@ struct cfd_ctx {
   // per sweep: [node sweeps 0..2][cell sweeps 0..2]
   int poff[6] = {0}, pcount[6] = {0}, pmax[6] = {0};
   int qthreads[3] = {0};   // threads of each state ghost sweep (k_ghost_q)
+  // inviscid flow: every face's ghost layers over its own cells, all three
+  // directions in one launch (no stencil of the inviscid stage reads an edge
+  // or corner ghost cell, the only cells the sweep order exists for)
+  int pm_off = 0, pm_count = 0, pm_threads = 0;
   TileDesc* dtiles = nullptr;
   int ntiles = 0;
   int64_t ncells = 0;
@@ -561,7 +567,15 @@ void timed(cfd_ctx* c, int cls, hipStream_t s, F&& launch) {
   c->ev_used.push_back({a, b, cls});
 }
 
-void ghost_fill(cfd_ctx* c, double* q, hipStream_t s) {
+// full: the i -> j -> k sweeps (edges and corners included) even where one
+// launch over the faces would do.
+void ghost_fill(cfd_ctx* c, double* q, hipStream_t s, bool full = false) {
+  if (!full && c->pm_count > 0) {
+    timed(c, 1, s, [&] {
+      launch_ghost_q(q, c->met(), c->dblocks, c->dpatches + c->pm_off, c->pm_count, c->pm_threads, c->SP, s);
+    });
+    return;
+  }
   for (int d = 0; d < 3; ++d)
     timed(c, 1, s, [&] {
       launch_ghost_q(q, c->met(), c->dblocks, c->dpatches + c->poff[3 + d], c->pcount[3 + d], c->qthreads[d],
@@ -846,7 +860,9 @@ cfd_status cfd_layout(int32_t nblk, const cfd_dims* dims, int32_t ghost_layers, 
   });
 }
 
-static int count_patches(int nconn, int nbc) { return 2 * (nconn + nbc); }
+// node sweeps, cell sweeps and the one-launch face set
+static int count_patches(int nconn, int nbc) { return 3 * (nconn + nbc); }
+constexpr int PATCHES_PER_BLOCK = 3 * 6 * 64;   // reserved: 64 patches per face on average
 
 cfd_status cfd_workspace_size(const cfd_params* params, int32_t nblk, const cfd_dims* dims,
                               size_t* workspace_bytes) {
@@ -857,7 +873,7 @@ cfd_status cfd_workspace_size(const cfd_params* params, int32_t nblk, const cfd_
     Layout L = make_layout(nblk, dims);
     // patch count is bounded by 6 faces x a generous number of patches; the
     // exact count is only known with the tables, so reserve for 64 per face.
-    WsLayout W = make_ws(L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0, params->viscous != 0);
+    WsLayout W = make_ws(L, nblk, dims, PATCHES_PER_BLOCK * nblk, params->local_dt != 0, params->viscous != 0);
     *workspace_bytes = W.total;
   });
 }
@@ -879,7 +895,7 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
     if (!workspace_dev) fail(CFD_EINVAL, "workspace is NULL");
     if ((reinterpret_cast<uintptr_t>(workspace_dev) & 255) != 0) fail(CFD_EINVAL, "workspace must be 256-byte aligned");
     const int npatch = count_patches(nconn, nbc);
-    if (npatch > 2 * 6 * 64 * nblk) fail(CFD_EUNSUPPORTED, "more than 64 patches per face on average");
+    if (npatch > PATCHES_PER_BLOCK * nblk) fail(CFD_EUNSUPPORTED, "more than 64 patches per face on average");
     c = new cfd_ctx();
     c->id = g_ctx_ids++;
     c->params = *params;
@@ -888,11 +904,11 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
     c->L = make_layout(nblk, dims);
     size_t need = 0;
     {
-      WsLayout Wfull = make_ws(c->L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0, params->viscous != 0);
+      WsLayout Wfull = make_ws(c->L, nblk, dims, PATCHES_PER_BLOCK * nblk, params->local_dt != 0, params->viscous != 0);
       need = Wfull.total;
     }
     if (workspace_bytes < need) fail(CFD_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    c->W = make_ws(c->L, nblk, dims, 2 * 6 * 64 * nblk, params->local_dt != 0, params->viscous != 0);
+    c->W = make_ws(c->L, nblk, dims, PATCHES_PER_BLOCK * nblk, params->local_dt != 0, params->viscous != 0);
     c->ws = static_cast<char*>(workspace_dev);
     c->dblocks = reinterpret_cast<BlockDesc*>(c->ws + c->W.blocks);
     c->dpatches = reinterpret_cast<PatchDesc*>(c->ws + c->W.patches);
@@ -931,6 +947,17 @@ cfd_status cfd_create_blocks(const cfd_params* params, int32_t nblk, const cfd_d
       if (!nodes)
         for (int p = c->poff[sweep]; p < (int)all.size(); ++p)
           c->qthreads[d] = std::max(c->qthreads[d], all[p].count * ghost_threads_per_point(all[p].kind, d));
+    }
+    if (!params->viscous) {
+      c->pm_off = (int)all.size();
+      for (int d = 0; d < 3; ++d) {
+        int mx = 0;
+        const int p0 = (int)all.size();
+        build_patches(d, false, params, dims, nconn, conns, nbc, bcs, all, mx, false);
+        for (int p = p0; p < (int)all.size(); ++p)
+          c->pm_threads = std::max(c->pm_threads, all[p].count * ghost_threads_per_point(all[p].kind, d));
+      }
+      c->pm_count = (int)all.size() - c->pm_off;
     }
     HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     {
@@ -1051,7 +1078,7 @@ cfd_status cfd_get_tuning(const cfd_ctx* c, cfd_tuning* t) {
 cfd_status cfd_fill_ghosts(cfd_ctx* c, double* q, hipStream_t s) {
   return guard(c, [&] {
     if (!c || !q) fail(CFD_EINVAL, "NULL argument");
-    ghost_fill(c, q, s);
+    ghost_fill(c, q, s, true);
     check_launch();
   });
 }
