@@ -354,19 +354,17 @@ def bench_wcns5_euler(a) -> int:
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / a.steps
-    nbytes = 0
-    for d in range(3):
-        P = cells // n[d] * (n[d] + 10)
-        F = cells // n[d] * (n[d] + 5)
-        nbytes += 8 * 5 * ((cells + P) + (P + F) + (F + cells * (1 if d == 0 else 2)))
-        if curv:
-            nbytes += 8 * 3 * F                # the faces' area vectors
-    if curv:                                   # J^{-1} read by the last Eq. 2 pass
-        nbytes += 8 * cells
-    if viscous and curv:   # phi (Q in, 4 out), gradients (4 in, 12 out), the cell metrics (9 in, 9 out) and per
-        # direction the face metrics (9 + 1 in, 7 out) that this one-shot call forms each time, then per direction
-        # the fused faces and differences (phi 4 + gradients 8 + face metrics 7 + S_d 3 + J^{-1} 1 in, r 4 in and out)
-        nbytes += 8 * cells * ((5 + 4) + (4 + 12) + (9 + 9) + 3 * (10 + 7) + 3 * (4 + 8 + 7 + 3 + 1 + 4 + 4))
+    # Algorithmic bytes of the passes this block runs (each reading its inputs and writing its outputs once):
+    # inviscid, per direction, the state (5 in) and the face area vectors (3, curvilinear), R written along i and
+    # read and written along j and k, J^{-1} read by the last pass.
+    nbytes = 8 * cells * (3 * 5 + (5 + 2 * 5 + 2 * 5))
+    if curv:
+        nbytes += 8 * cells * (3 * 3 + 1)
+    if viscous and curv:   # phi with the i derivatives (Q in; 4 + 4 out), the j and k derivatives (4 in, 4 out
+        # each), the cell metrics (9 in, 9 out) and per direction the face metrics (9 + 1 in, 7 out) that this
+        # one-shot call forms each time, then per direction the fused faces and differences (phi 4 + gradients 8
+        # + face metrics 7 + S_d 3 + J^{-1} 1 in, r 4 in and out)
+        nbytes += 8 * cells * ((5 + 8) + 2 * (4 + 4) + (9 + 9) + 3 * (10 + 7) + 3 * (4 + 8 + 7 + 3 + 1 + 4 + 4))
     elif viscous:   # phi (Q in, 4 out), gradients (4 in, 12 out), per direction faces (16 in, 4 out) and the sum
         nbytes += 8 * cells * ((5 + 4) + (4 + 12) + 3 * ((4 + 8) + 4) + 3 * (4 + 8))
     achieved = nbytes / (ms / 1e3) / 1e9
@@ -385,10 +383,10 @@ def bench_wcns5_euler(a) -> int:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_rate_gbs": None if traffic is None else round(traffic / (ms / 1e3) / 1e9, 1),
-                     "kernel": "pipeline: k_pad_prim_periodic, k_wcns5_roe_faces, k_window6_*<Eq2OpT>"
+                     "kernel": "pipeline: k_wcns5_euler_rows, k_wcns5_euler_march<1|2>"
                                + (" (the last pass dividing by J^-1)" if curv else "")
-                               + (", k_c4_phi, k_c4_grads, k_c4_cell_metrics, k_c4_face_metrics, k_c4_visc_rows, "
-                                  "k_c4_visc_march<1>, k_c4_visc_march<2>" if viscous and curv else
+                               + (", k_c4_phi_grads_i, k_c4_grads_march<1|2>, k_c4_cell_metrics, k_c4_face_metrics, "
+                                  "k_c4_visc_rows, k_c4_visc_march<1|2>" if viscous and curv else
                                   ", k_c4_phi, k_c4_grads, k_c4_visc_faces, k_c4_flux_sub" if viscous else ""),
                      "mean_ms": round(ms, 4), "pipeline_bytes": nbytes},
         "cpu_baseline": None}), flush=True)
@@ -440,12 +438,9 @@ def bench_implicit(a) -> int:
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / a.steps
-    nbytes = 0
-    for d in range(3):
-        P = cells // n[d] * (n[d] + 10)
-        F = cells // n[d] * (n[d] + 5)
-        nbytes += 8 * 5 * ((cells + P) + (P + F) + (F + cells * (1 if d == 0 else 2))) + 8 * 3 * F
-    nbytes += 8 * cells                                                 # J^{-1} in the last Eq. 2 pass
+    # the residual's row and marching passes (per direction Q and the area vectors in, R written or updated,
+    # J^{-1} in the last), then the implicit passes
+    nbytes = 8 * cells * (3 * 5 + (5 + 2 * 5 + 2 * 5) + 3 * 3 + 1)
     nbytes += 8 * cells * ((5 + 9 + 3) + (5 + 3 + 1 + 1 + 5))           # radii; diagonal and first iterate
     nbytes += sweeps * 8 * cells * (5 + 5 + 5 + 9 + 3 + 1 + 1 + 5)      # one sweep
     nbytes += 8 * cells * 15                                            # q += dQ
@@ -460,7 +455,8 @@ def bench_implicit(a) -> int:
                    "finite": finite},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "pipeline: residual, k_impl_lambda, k_impl_diag, k_impl_sweep x4, k_impl_apply",
+                     "kernel": "pipeline: residual (k_wcns5_euler_rows, k_wcns5_euler_march<1|2>), k_impl_lambda, k_impl_diag, "
+                               "k_impl_sweep x4, k_impl_apply",
                      "mean_ms": round(ms, 4), "pipeline_bytes": nbytes},
         "cpu_baseline": None}), flush=True)
     return 0
