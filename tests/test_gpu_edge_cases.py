@@ -109,3 +109,38 @@ def test_thin_blocks_metrics_and_ghosts():
     for b in range(case.nblk):
         assert np.array_equal(got[b], st.Qs[b]), b
     s.close()
+
+
+@pytest.mark.parametrize("which", ["channel", "chain", "thin"])
+@pytest.mark.parametrize("tuning", list(TUNINGS))
+def test_inviscid_steps_never_read_edge_or_corner_ghosts(which, tuning):
+    """Inviscid steps fill each face's ghost layers over the face's own cells
+    only, so the edge and corner ghost cells keep whatever they held.  Poison
+    test: from a state arena whose every ghost cell is NaN, and from one whose
+    ghosts (edges and corners included) were filled by cfd_fill_ghosts' sweeps,
+    5 steps give bitwise the same history rows and interior states, all
+    finite: no inviscid stencil, time step or norm reads those cells."""
+    import torch
+    from paper_1710_09995_amd.binding import Solver
+    case = {"channel": lambda: cases.channel_case(24, 12, 12, mach=0.6, hb=0.05),
+            "chain": lambda: cases.batched_euler_case(nblk=5, seed=3, lo=8, hi=20, flux_fp32=0),
+            "thin": lambda: cases.split_periodic_box(cases.vortex_case(8, nz=4, seed=7, curvilinear=True),
+                                                     parts=(4, 4, 2))}[which]()
+    assert not case.params.viscous
+    say("edge/corner ghost poison", which, tuning)
+    s = Solver(case)
+    if TUNINGS[tuning]:
+        s.set_tuning(**TUNINGS[tuning])
+    runs = []
+    for prefill in (False, True):
+        a = s.new_arena()                       # every entry NaN
+        s.set_state(case.q0, a)
+        if prefill:
+            s.fill_ghosts(a)
+        h = s.step(5, hist=True, arena=a)
+        q = [v.clone() for v in s.interior_views(a)]
+        runs.append((h, q))
+    (h0, q0), (h1, q1) = runs
+    assert bool(torch.isfinite(h0).all()) and all(bool(torch.isfinite(v).all()) for v in q0)
+    assert torch.equal(h0, h1)
+    assert all(torch.equal(x, y) for x, y in zip(q0, q1))
