@@ -14,6 +14,12 @@
 // its i-column with a register window of 21 entries.  Each input entry is thus
 // loaded about once instead of six times.  With a grid that is a multiple of
 // 8, each XCD (workgroup id mod 8) streams one contiguous eighth of the work.
+// The residuals built from them run, on blocks large enough to fill the chip,
+// as one pass per direction that keeps every intermediate on chip: an LDS row
+// pass along i and register marches along j and k for the inviscid residual
+// (primitives, edge states, Roe's flux, Eq. 2), the index derivatives of the
+// viscous terms and their face fluxes with the staggered difference; smaller
+// blocks take the padded-primitive, face and Eq. 2 passes, with the same bits.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
