@@ -581,6 +581,15 @@ def bench_ns_share(a) -> int:
     ms = e0.elapsed_time(e1) / a.steps
     cells = N[0] * N[1] * N[2]
     finite = bool(all(torch.isfinite(t).all() for t in qs))
+    # Algorithmic bytes per cell and stage of the passes an owner block runs (each reading its inputs and writing
+    # its outputs once; the ghost blocks' fill and the face metrics, formed once per call, left out): inviscid,
+    # per direction Q (5) and S_d (3) in, R written along i and updated along j and k, J^{-1} in the last pass;
+    # phi with its i derivatives (Q in, 4 + 4 out), the j and k derivatives (4 in, 4 out each); per direction
+    # the viscous faces and differences (phi 4 + derivatives 8 + face metrics 7 + S_d 3 + J^{-1} 1 in, r 4 in
+    # and out), the last one applying the RK3 stage (R_rho 1, Q 5 and Q^n 5 in, Q 5 out).
+    per_cell = 8 * ((3 * 5 + 3 * 3 + (5 + 2 * 5 + 2 * 5) + 1) + (5 + 8) + 2 * (4 + 4)
+                    + 3 * (4 + 8 + 7 + 3 + 1 + 4 + 4) - 4 + (1 + 5 + 5 + 5))
+    achieved = per_cell * cells * 3 / (ms / 1e3) / 1e9
     print(json.dumps({
         "metric": "Mcell-stage/s of RK3 Navier-Stokes steps of the paper's operator (WCNS-E-5 + fourth-order "
                   "viscous) on the one-GPU share's geometry closed at the wall and far field",
@@ -590,7 +599,11 @@ def bench_ns_share(a) -> int:
         "config": {"workload": f"ns_wcns5_c4_share_{nb}x{nb}_of_{ni}x{nj}x{nk}", "cells": cells,
                    "blocks": len(tl.owners), "ghost_blocks": 2 * len(tl.owners), "setup_s": round(setup_s, 1),
                    "finite": finite},
-        "roofline": None, "cpu_baseline": None}), flush=True)
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes_per_cell_stage":
+                     per_cell, "kernel": "pipeline: k_wcns5_euler_rows, k_wcns5_euler_march<1|2>, k_c4_phi_grads_i, "
+                     "k_c4_grads_march<1|2>, k_c4_visc_rows, k_c4_visc_march<1, false>, k_c4_visc_march<2, true>"},
+        "cpu_baseline": None}), flush=True)
     return 0
 
 
