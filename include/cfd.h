@@ -112,7 +112,8 @@ typedef struct {
  *   Euler, whose kernels hold two workgroups per CU), use_graph 1, order 1;
  *   tile_k is halved (down to 4) while the grid gives fewer tiles than CUs,
  *   and a grid with fewer tiles than CUs even then gets the tiled kernel
- *   with tile_j halved (down to 2) until it has one tile per CU.
+ *   with tile_j 4 and tile_k halved (down to 1) until it has four tiles per
+ *   CU.
  * use_graph: 1 captures one time step in a hipGraph and replays it.
  * order: tile work-list order.  0 = largest tiles first (balances uneven
  *   blocks); 1 = XCD-aware: the tiles are cut into 8 spatially contiguous

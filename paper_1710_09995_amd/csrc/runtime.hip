@@ -482,10 +482,14 @@ int64_t count_tiles(const std::vector<cfd_dims>& dims, int tj, int tk) {
 // Default tuning for the grid: the plane-ring kernel with 64 x 8 x 32 tiles
 // (deep tiles amortise each tile's three plane fills; measured better than
 // 64 x 8 x 16 even where nk = 144 leaves a half-empty last tile), tile_k
-// halved (down to 4) while there are fewer tiles than CUs, and the tiled
-// kernel with narrower tiles for grids that still leave CUs idle.  Grids of
-// many small uneven blocks run faster with smaller tiles: the autotuner
-// finds them.
+// halved (down to 4) while there are fewer tiles than CUs.  A grid that still
+// leaves CUs idle gets the tiled kernel with 4-row tiles, tile_k halved (down
+// to 1) until there are 4 tiles per CU: on such small grids the launch's
+// latency, not the halo planes each shallow tile reloads, bounds the stage
+// (measured on the 96x48x48 and 48x24x24 levels of a multigrid cycle: 64x4x1
+// tiles took the cycle from 1.45 to 1.26 ms against 64x4x4 and 64x2x4).
+// Grids of many small uneven blocks run faster with smaller tiles: the
+// autotuner finds them.
 // The FP32-flux Euler plane-ring kernels hold two workgroups per CU; tiles of
 // half the depth fill both and shorten the tail of the persistent grid.
 cfd_tuning default_tuning(const std::vector<cfd_dims>& dims, int num_cu, const cfd_params& p) {
@@ -493,7 +497,8 @@ cfd_tuning default_tuning(const std::vector<cfd_dims>& dims, int num_cu, const c
   while (t.tile_k > 4 && count_tiles(dims, t.tile_j, t.tile_k) < (int64_t)num_cu) t.tile_k /= 2;
   if (count_tiles(dims, t.tile_j, t.tile_k) < num_cu) {
     t.kernel = 0;
-    while (t.tile_j > 2 && count_tiles(dims, t.tile_j, t.tile_k) < num_cu) t.tile_j /= 2;
+    t.tile_j = 4;
+    while (t.tile_k > 1 && count_tiles(dims, t.tile_j, t.tile_k) < 4 * (int64_t)num_cu) t.tile_k /= 2;
   }
   return t;
 }

@@ -117,7 +117,8 @@ def test_step_parity_fp32_flux(name, nsteps, tun):
 
 
 TUNINGS = ({"kernel": 0, "use_graph": 1}, {"kernel": 0, "use_graph": 0},
-           {"kernel": 0, "tile_j": 2, "tile_k": 3}, {"kernel": 0, "tile_j": 8, "tile_k": 64},
+           {"kernel": 0, "tile_j": 2, "tile_k": 3}, {"kernel": 0, "tile_j": 4, "tile_k": 1},
+           {"kernel": 0, "tile_j": 8, "tile_k": 64},
            {"kernel": 0, "tile_j": 4, "tile_k": 5, "order": 1},
            {"kernel": 2, "tile_j": 8, "tile_k": 32}, {"kernel": 2, "tile_j": 8, "tile_k": 3, "order": 0},
            {"kernel": 2, "tile_j": 8, "tile_k": 7, "use_graph": 0},
