@@ -42,7 +42,10 @@ Test infrastructure, like the rest of this package.  Two operators:
    flux-split approximate Jacobian relaxed by point-Jacobi sweeps, the
    reading of the sparse linear solve the paper's flowchart names (stated
    below), with the viscous terms and a central diffusion split optional.  Pinned by the explicit Euler limit, a kept uniform stream, the
-   sweeps' fixed point and stability past the explicit limit; its accuracy
+   sweeps' fixed point, stability past the explicit limit, and its linear
+   operator against central differences of an independently written
+   first-order local Lax-Friedrichs residual with frozen dissipation
+   (inviscid and viscous) to O(|dQ|^2); its accuracy
    as a linear solver of the exact Jacobian is not a claim ("parity
    unpinned" for the approximate Jacobian itself).
 
