@@ -643,13 +643,15 @@ void launch_stage(cfd_ctx* c, const StageArgs& A, int mode, hipStream_t s) {
   }
 }
 
-// CFL time step of q: per-cell steps (local stepping) and the minimum into d_dt.
-void time_step_pass(cfd_ctx* c, const double* q, hipStream_t s) {
+// CFL time step of q: per-cell steps (local stepping) and, with min_dt, the
+// minimum into d_dt (read by global-step stages and forcing, and by the
+// history row).
+void time_step_pass(cfd_ctx* c, const double* q, hipStream_t s, bool min_dt = true) {
   const int nwg = dt_nwg(c);
   timed(c, 2, s, [&] {
     launch_dt(q, c->met(), c->scal(), c->part_dt(), c->dblocks, c->nblk, c->nchunks, c->SP, nwg, s);
   });
-  launch_finalize(c->part_dt(), nwg, 0, 0.0, c->d_dt(), nullptr, nullptr, s);
+  if (min_dt) launch_finalize(c->part_dt(), nwg, 0, 0.0, c->d_dt(), nullptr, nullptr, s);
 }
 
 // Whether stage 3 evaluates the next step's time step: the plane-ring kernel
@@ -688,7 +690,9 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history, const doub
   const double inv_n = 1.0 / (double)c->ncells;
   const int nwg_dt = dt_nwg(c);
   ghost_fill(c, q, s);
-  if (!fuse) time_step_pass(c, q, s);
+  // Local steps without a history row read no minimum step: every stage and
+  // the forcing take the per-cell steps.
+  if (!fuse) time_step_pass(c, q, s, history || !c->params.local_dt);
   StageArgs A = stage_args(c);
   A.qs = q;
   A.qn = q;
