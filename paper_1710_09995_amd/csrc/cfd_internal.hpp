@@ -113,6 +113,11 @@ struct StageArgs {
   int32_t ntiles;
   int32_t tile_j, tile_k;
   StepParams sp;      // flow and CFL parameters (mode 3)
+  // A multigrid level's forcing, applied by the tiled and simple kernels in
+  // modes 1-2 (null: none): out = out - (fb dt) F, rounded as the separate
+  // forcing pass rounds it.
+  const double* force;
+  double fb;
 };
 
 

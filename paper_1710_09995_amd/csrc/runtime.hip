@@ -681,9 +681,12 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history, const doub
   const bool ring = c->tun.kernel == 2;
   const bool fuse = fused_dt(c) && !no_fuse && !force;
   const int nwg_f = dt_nwg(c);
-  // a multigrid level's forcing: each stage's output minus b dt F
+  // a multigrid level's forcing: each stage's output minus b dt F, applied
+  // by the tiled and simple stage kernels themselves, after the plane-ring
+  // kernel by a pass of its own (the same rounding either way)
+  const double* force_in_stage = ring ? nullptr : force;
   auto forced = [&](double* out, double b) {
-    if (force)
+    if (force && ring)
       launch_mg_force(out, force, c->params.local_dt ? c->scal() : c->d_dt(), c->params.local_dt, b, c->dblocks,
                       c->nblk, c->nchunks, nwg_f, s);
   };
@@ -697,6 +700,8 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history, const doub
   A.qs = q;
   A.qn = q;
   A.out = c->qa();
+  A.force = force_in_stage;
+  A.fb = 1.0;
   if (ring) {
     const int ntot = history ? nwg_dt : 0;
     if (history)
@@ -725,6 +730,7 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history, const doub
   A.out = c->qb();
   A.a = 0.75;
   A.b = 0.25;
+  A.fb = 0.25;
   launch_stage(c, A, 2, s);
   forced(c->qb(), 0.25);
   ghost_fill(c, c->qb(), s);
@@ -732,6 +738,7 @@ void enqueue_step(cfd_ctx* c, double* q, hipStream_t s, bool history, const doub
   A.out = q;
   A.a = 1.0 / 3.0;
   A.b = 2.0 / 3.0;
+  A.fb = 2.0 / 3.0;
   if (fuse) {
     A.partials = c->part_dt();
     A.dt_out = c->params.local_dt ? c->scal() : nullptr;

@@ -262,12 +262,14 @@ __device__ __forceinline__ void load_cell(const StageArgs& A, const BlockDesc& B
 }
 
 // R = ((Di + Dj) + Dk) / V, then write R (mode 0) or the stage update
-// (modes 1-3; mode 1 also writes R for the norms if A.rout is set).  R is
-// returned in Rc, the written state in Qo (modes 1-3).
+// (modes 1-3; mode 1 also writes R for the norms if A.rout is set), less
+// (A.fb dt) force when a multigrid level's forcing is given.  R is returned
+// in Rc, the written state in Qo (modes 1-3).
 template <int MODE>
 __device__ __forceinline__ void update_cell(const StageArgs& A, const BlockDesc& B, int64_t c, const double Di[5],
                                             const double Dj[5], const double Dk[5], const CellIn& in,
-                                            double Rc[5] = nullptr, double Qo[5] = nullptr) {
+                                            double Rc[5] = nullptr, double Qo[5] = nullptr,
+                                            const double* force = nullptr) {
   double R[5];
   const double ivol = frcp(in.vol);
 #pragma unroll
@@ -278,7 +280,11 @@ __device__ __forceinline__ void update_cell(const StageArgs& A, const BlockDesc&
   } else if (MODE == 1) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      const double o = in.qv[q] - in.dt * R[q];
+      double o = in.qv[q] - in.dt * R[q];
+      if (force) {
+        const double h = A.fb * in.dt;
+        o = o - h * force[B.qoff + q * B.sv + c];
+      }
       A.out[B.qoff + q * B.sv + c] = o;
       if (A.rout) A.rout[B.qoff + q * B.sv + c] = R[q];
       if (Qo) Qo[q] = o;
@@ -286,7 +292,11 @@ __device__ __forceinline__ void update_cell(const StageArgs& A, const BlockDesc&
   } else {
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      const double o = A.a * in.qn[q] + A.b * (in.qv[q] - in.dt * R[q]);
+      double o = A.a * in.qn[q] + A.b * (in.qv[q] - in.dt * R[q]);
+      if (force) {
+        const double h = A.fb * in.dt;
+        o = o - h * force[B.qoff + q * B.sv + c];
+      }
       A.out[B.qoff + q * B.sv + c] = o;
       if (Qo) Qo[q] = o;
     }
@@ -302,7 +312,7 @@ __device__ __forceinline__ void finish_cell(const StageArgs& A, const BlockDesc&
                                             const double Dj[5], const double Dk[5]) {
   CellIn in;
   load_cell<MODE>(A, B, c, in);
-  update_cell<MODE>(A, B, c, Di, Dj, Dk, in);
+  update_cell<MODE>(A, B, c, Di, Dj, Dk, in, nullptr, nullptr, A.force);
 }
 
 // Fixed-order workgroup reduction of NPART partials; thread 0 writes the row.
