@@ -121,6 +121,37 @@ def test_captured_cycles_are_bitwise_the_eager_cycles():
     sb.close()
 
 
+def test_coarse_levels_give_bitwise_the_same_cycles_on_every_stage_kernel():
+    """A coarse level's forcing is applied inside the tiled and simple stage
+    kernels and by a pass of its own after the plane-ring kernel, rounded the
+    same way, and the states do not depend on the stage kernel or its tiles:
+    cycles with the coarse levels on each of the three stage kernels give
+    bitwise the same states and history rows, on the channel (local steps)
+    and on the wall-bump Navier-Stokes block (global step)."""
+    from paper_1710_09995_amd.binding import Multigrid, Solver
+    tunings = ({"kernel": 0, "tile_j": 4, "tile_k": 1}, {"kernel": 1, "tile_j": 4, "tile_k": 8},
+               {"kernel": 2, "tile_j": 8, "tile_k": 4})
+    for name in ("channel", "bump_ns"):
+        case, L, pre, coarse, n = _cases()[name]
+        ref = None
+        for tun in tunings:
+            say("multigrid coarse levels", name, tun)
+            s = Solver(case)
+            mg = Multigrid(s, L, pre, coarse)
+            for lv in mg.levels[1:]:
+                lv.set_tuning(**tun)
+            h = mg.cycles(n).cpu().numpy()
+            q = s.state()
+            mg.close()
+            s.close()
+            if ref is None:
+                ref = (h, q)
+                continue
+            assert np.array_equal(h, ref[0]), (name, tun)
+            for x, y in zip(q, ref[1]):
+                assert np.array_equal(x, y), (name, tun)
+
+
 def test_hierarchy_is_checked():
     """A level that is not the coarsening of the one above (same extents, or
     other flow parameters) is refused before anything runs."""
