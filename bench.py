@@ -613,13 +613,21 @@ def bench_mg_channel(a) -> int:
     a bump at M 0.6 (the warm-start family's grid): K cycles after W warm-up
     ones, one cfd_mg_cycles call, hipEvents on the launch stream, no history
     kept.  The state drifts toward the steady flow while it is timed; the
-    cycle's work does not depend on it."""
+    cycle's work does not depend on it.  --tune picks each level's tiles
+    first (autotune_multigrid, on a scratch copy of the state)."""
     import torch
     from paper_1710_09995_amd import cases
     from paper_1710_09995_amd.binding import Multigrid, Solver
     case = cases.channel_case(192, 96, 96, mach=0.6, hb=0.05)
     s = Solver(case)
     mg = Multigrid(s, 3, 1, 2)
+    tune_info = None
+    if a.tune:
+        from paper_1710_09995_amd.autotune import autotune_multigrid
+        res = autotune_multigrid(mg, log=lambda m: print(m, file=sys.stderr, flush=True))
+        tune_info = {"levels": res["tunings"], "ms_per_cycle_tuning": round(res["ms_per_cycle"], 4),
+                     "candidates": len(res["table"])}
+        print(f"# tuned: {res['tunings']} ({res['ms_per_cycle']:.4f} ms/cycle)", file=sys.stderr, flush=True)
     mg.cycles(a.warmup, hist=False)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -636,6 +644,7 @@ def bench_mg_channel(a) -> int:
         "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (channel with a bump, M 0.6)",
         "config": {"workload": "mg_channel_192x96x96_3levels_pre1_coarse2", "cells": cells,
+                   "tuning": [lv.get_tuning() for lv in mg.levels], "autotune": tune_info,
                    "finite": bool(all(torch.isfinite(v).all() for v in s.interior_views()))},
         "roofline": None, "cpu_baseline": None}), flush=True)
     return 0

@@ -122,3 +122,59 @@ def autotune(solver, candidates: Optional[Iterable[Tuple[int, int, int]]] = None
         db[key] = {"tuning": best[0], "ms_per_step": best[1], "table": table}
         _store(db)
     return {"tuning": best[0], "ms_per_step": best[1], "table": table, "cached": False}
+
+
+MG_CANDIDATES: Tuple[Tuple[int, int, int], ...] = (
+    (2, 8, 8), (2, 8, 16), (2, 4, 4), (2, 8, 4), (0, 4, 4), (0, 4, 2), (0, 4, 1), (0, 8, 4), (0, 2, 2))
+
+
+def autotune_multigrid(mg, candidates: Optional[Iterable[Tuple[int, int, int]]] = None, cycles: int = 100,
+                       log=None) -> dict:
+    """Pick each level's tuning for the V-cycle of a Multigrid ``mg`` by
+    timing whole cycles on a scratch copy of the finest state (the coarse
+    levels' states are rebuilt from it in every cycle, so the solver's state
+    is left untouched).  One level at a time from the finest, the others held
+    at their current tunings; a candidate a level refuses is skipped.  Every
+    tuning gives bitwise the same cycle, so this changes speed only.  Returns
+    {"tunings" (per level), "ms_per_cycle", "table"}."""
+    torch = mg.torch
+    s = mg.solver
+    stream = s.stream if s.stream is not None else torch.cuda.current_stream(s.device)
+    scratch = s.new_arena()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def time_cycles() -> float:
+        scratch.copy_(s.q)
+        mg.cycles(2, hist=False, arena=scratch)       # capture + warm
+        e0.record(stream)
+        mg.cycles(cycles, hist=False, arena=scratch)
+        e1.record(stream)
+        torch.cuda.synchronize(s.device)
+        return e0.elapsed_time(e1) / cycles
+
+    table = []
+    best_ms = None
+    for level, lv in enumerate(mg.levels):
+        cur = lv.get_tuning()
+        best = (cur, time_cycles())
+        table.append(dict(cur, level=level, ms_per_cycle=best[1]))
+        for cand in (candidates or MG_CANDIDATES):
+            kernel, tj, tk = cand[:3]
+            t = {"kernel": kernel, "tile_j": tj, "tile_k": tk, "use_graph": cur["use_graph"], "order": cur["order"]}
+            if all(t[k] == cur[k] for k in t):
+                continue
+            try:
+                lv.set_tuning(**t)
+            except Exception:
+                continue
+            ms = time_cycles()
+            table.append(dict(t, level=level, ms_per_cycle=ms))
+            if log:
+                log(f"# tune level {level} {t}: {ms:.4f} ms/cycle")
+            if ms < best[1]:
+                best = (t, ms)
+        lv.set_tuning(**best[0])
+        best_ms = best[1]
+    del scratch
+    return {"tunings": [lv.get_tuning() for lv in mg.levels], "ms_per_cycle": best_ms, "table": table}
