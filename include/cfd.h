@@ -223,7 +223,9 @@ cfd_status cfd_step_implicit(cfd_ctx* ctx, double* q_arena_dev, int32_t nsteps, 
  * Q_l += Q_{l+1} - Q^0_{l+1} on each coarse cell's 8 children.  With one level
  * a cycle is `coarse` plain RK3 steps.  hist (device, may be NULL):
  * [ncycles][12] rows of cfd_step's layout, each the finest level's first step
- * of the cycle (R without forcing).
+ * of the cycle (R without forcing).  Each level runs its own context's
+ * tuning (cfd_set_tuning on that context); every tuning gives bitwise the
+ * same cycle.
  *
  * cfd_mg_work_size: bytes of work for the hierarchy (three state-layout
  * arenas per level).  cfd_mg_cycles: work_dev 256-byte aligned, disjoint
