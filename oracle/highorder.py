@@ -45,9 +45,9 @@ Test infrastructure, like the rest of this package.  Two operators:
    sweeps' fixed point, stability past the explicit limit, and its linear
    operator against central differences of an independently written
    first-order local Lax-Friedrichs residual with frozen dissipation
-   (inviscid and viscous) to O(|dQ|^2); its accuracy
-   as a linear solver of the exact Jacobian is not a claim ("parity
-   unpinned" for the approximate Jacobian itself).
+   (inviscid and viscous) to O(|dQ|^2); how well that approximate
+   Jacobian solves the exact linear system is not a claim ("parity
+   unpinned" for that accuracy, not for the operator).
 
 Section 2.2, Eq. (2): the cell-centred derivative of a face-centred flux F
 along one index direction with grid size h,
